@@ -1,0 +1,391 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: textbook
+closed forms, the paper's printed Appendix A functions and Table 1, exact
+invariants (symmetry, positive semi-definiteness, independence of the Ewald
+parameter) and brute-force identities.
+"""
+import numpy as np
+import pytest
+
+import appendix_a
+from oracle import brownian, conventions as cv, ewald, integrator, pairfuncs as pf
+from oracle import params
+
+PI = np.pi
+
+
+# ------------------------------------------------------------ conventions --
+
+def test_basis_orthonormal_symmetric_traceless():
+    G = np.einsum('qij,pij->qp', cv.Y, cv.Y)
+    assert np.allclose(G, np.eye(5), atol=1e-15)
+    assert np.allclose(cv.Y, np.transpose(cv.Y, (0, 2, 1)))
+    assert np.allclose(np.trace(cv.Y, axis1=1, axis2=2), 0.0)
+
+
+def test_torque_and_power_pairing():
+    """L = sum y x f for point forces f at y, with C_mn = sum f_m y_n
+    (force index first, Eqs. UC/DC); C:D = L.Omega + S:E."""
+    rng = np.random.default_rng(0)
+    y = rng.normal(size=(7, 3))
+    f = rng.normal(size=(7, 3))
+    f -= f.mean(0)
+    C = np.einsum('km,kn->mn', f, y)
+    C -= np.trace(C) / 3 * np.eye(3)
+    Ltrue = np.cross(y, f).sum(0)
+    S = 0.5 * (C + C.T)
+    s = np.einsum('qij,ij->q', cv.Y, S)
+    assert np.allclose(cv.couplet_from(Ltrue, s), C, atol=1e-13)
+    # rigid rotation u = Omega x x has D_ij = du_i/dx_j and curl/2 = Omega
+    Om = rng.normal(size=3)
+    E = rng.normal(size=(3, 3))
+    E = 0.5 * (E + E.T)
+    E -= np.trace(E) / 3 * np.eye(3)
+    D = np.einsum('ijk,j->ik', cv.EPS, Om) + E
+    om, e = cv.omega_e_from(D)
+    assert np.allclose(om, Om) and np.allclose(e, np.einsum('qij,ij->q', cv.Y, E))
+    assert np.isclose(np.sum(C * D), Ltrue @ om + s @ e)
+
+
+# -------------------------------------------------------------- free space --
+
+def _free(rvec, a=1.0):
+    return ewald.pair_blocks(np.atleast_2d(rvec), 1.0, a, 1.0, 'full')[0]
+
+
+@pytest.mark.parametrize('a', [1.0, 0.7])
+def test_free_space_self(a):
+    B = _free([0.0, 0.0, 0.0], a)
+    assert np.allclose(np.diag(B)[0:3], 1 / (6 * PI * a))
+    assert np.allclose(np.diag(B)[3:6], 1 / (8 * PI * a**3))
+    assert np.allclose(np.diag(B)[6:11], 3 / (20 * PI * a**3))
+    off = B - np.diag(np.diag(B))
+    assert np.abs(off).max() < 1e-15
+
+
+@pytest.mark.parametrize('r', [0.3, 1.1, 1.99, 2.0, 2.7, 5.0])
+def test_free_space_rpy_and_rotlet(r):
+    """Rotne-Prager(-Yamakawa) tensor (overlap and far forms), the
+    rotlet-rotlet coupling and the Stokeslet vorticity."""
+    rng = np.random.default_rng(int(r * 100))
+    e = rng.normal(size=3)
+    e /= np.linalg.norm(e)
+    B = _free(r * e)
+    I, ee = np.eye(3), np.outer(e, e)
+    if r >= 2:
+        uf = ((1 + 2 / (3 * r * r)) * I + (1 - 2 / (r * r)) * ee) / (8 * PI * r)
+        assert np.allclose(B[3:6, 3:6], -(I - 3 * ee) / (16 * PI * r**3), atol=1e-15)
+        assert np.allclose(B[3:6, 0:3], np.einsum('ijk,k->ij', cv.EPS, e) / (8 * PI * r * r),
+                           atol=1e-15)
+    else:
+        uf = ((1 - 9 * r / 32) * I + (3 * r / 32) * ee) / (6 * PI)
+    assert np.allclose(B[0:3, 0:3], uf, atol=1e-15)
+
+
+def test_pair_block_transpose_symmetry():
+    rng = np.random.default_rng(3)
+    rv = rng.normal(size=(6, 3)) * 1.5
+    for part in ('full', 'real'):
+        Bp = ewald.pair_blocks(rv, 0.9, 1.0, 1.0, part)
+        Bm = ewald.pair_blocks(-rv, 0.9, 1.0, 1.0, part)
+        assert np.abs(Bp - np.transpose(Bm, (0, 2, 1))).max() < 1e-15
+
+
+# ----------------------------------------------------- Appendix A functions --
+
+RS = np.array([0.4, 1.0, 1.7, 1.999, 2.001, 2.6, 3.4, 4.5])
+
+
+@pytest.mark.parametrize('xi', [0.5, 0.9, 1.4])
+def test_appendix_a_velocity_force(xi):
+    co = pf.real_coefficients(RS, xi)
+    F1 = 6 * PI * co['a']
+    F2 = 6 * PI * (co['a'] + co['b'])
+    scale = np.abs(appendix_a.F1(RS, xi)).max()
+    assert np.abs(F1 - appendix_a.F1(RS, xi)).max() < 1e-12 * scale
+    assert np.abs(F2 - appendix_a.F2(RS, xi)).max() < 1e-12 * scale
+    self_ = 6 * PI * pf.real_coefficients(np.array([0.0]), xi)['a'][0]
+    assert np.isclose(self_, appendix_a.uf_self(xi), rtol=1e-12)
+
+
+@pytest.mark.parametrize('xi', [0.5, 0.9, 1.4])
+def test_appendix_a_velocity_couplet(xi):
+    """M_UC = 3(c1 + 4c2)(d_im r_n - r r r) - 3 c2 (d_in r_m + d_mn r_i - 4 r r r)
+    equals (1/12 pi eta)(-G1 T1 + G2 T2) at a = 1."""
+    co = pf.real_coefficients(RS, xi)
+    G2 = -36 * PI * co['c2']
+    G1 = -36 * PI * (co['c1'] + 4 * co['c2'])
+    ref2 = appendix_a.G2(RS, xi)
+    assert np.abs(G2 - ref2).max() < 1e-11 * np.abs(ref2).max()
+    far = RS > 2
+    ref1 = appendix_a.G1_far(RS[far], xi)
+    assert np.abs(G1[far] - ref1).max() < 1e-11 * np.abs(ref1).max()
+
+
+@pytest.mark.parametrize('xi', [0.5, 0.9, 1.4])
+def test_appendix_a_gradient_couplet(xi):
+    """Project 6 pi eta M_DC (i, j swapped) on the paper's three basis
+    tensors: the fit is exact and the K3 coefficient equals Appendix A's."""
+    co = pf.real_coefficients(RS, xi)
+    rng = np.random.default_rng(5)
+    e = rng.normal(size=(RS.size, 3))
+    e /= np.linalg.norm(e, axis=1)[:, None]
+    DC = pf.cartesian_tensors(e, co)[3]
+    d = np.eye(3)
+    K3 = []
+    for p in range(RS.size):
+        T = np.transpose(6 * PI * DC[p], (1, 0, 2, 3))
+        rr = np.outer(e[p], e[p])
+        r4 = np.einsum('ij,mn->ijmn', rr, rr)
+        b1 = (np.einsum('ij,mn->ijmn', d, d) + np.einsum('im,jn->ijmn', d, d)
+              - 4 * np.einsum('in,jm->ijmn', d, d))
+        b2 = np.einsum('jm,in->ijmn', d, rr) - r4
+        b3 = (np.einsum('ij,mn->ijmn', d, rr) + np.einsum('im,jn->ijmn', d, rr)
+              + np.einsum('jn,im->ijmn', d, rr) + np.einsum('mn,ij->ijmn', d, rr)
+              + np.einsum('in,jm->ijmn', d, rr) - 6 * r4
+              - np.einsum('in,jm->ijmn', d, d))
+        A = np.stack([b1.ravel(), b2.ravel(), b3.ravel()], 1)
+        c = np.linalg.lstsq(A, T.ravel(), rcond=None)[0]
+        assert np.abs(A @ c - T.ravel()).max() < 1e-13
+        K3.append(c[2])
+    ref = appendix_a.K3(RS, xi)
+    assert np.abs(np.array(K3) - ref).max() < 1e-11 * np.abs(ref).max()
+    # DC self value (a = 1): M_DC = -9 d2(0) (d_ij d_mn + d_in d_jm - 4 d_im d_jn)
+    d2 = pf.real_coefficients(np.array([0.0]), xi)['d2'][0]
+    assert np.isclose(-54 * PI * d2, appendix_a.dc_self_K1(xi), rtol=1e-11)
+
+
+def test_spherical_bessel_series_matches_scipy_branch():
+    from scipy.special import spherical_jn
+    x = np.array([0.5, 1.5, 2.9, 3.1, 7.0])
+    for n in range(5):
+        ref = spherical_jn(n, x) / x**n
+        assert np.allclose(pf.jn_over_xn(n, x), ref, rtol=1e-12, atol=0)
+    assert np.allclose(pf.jn_over_xn(2, np.array([0.0])), 1 / 15)
+
+
+# ---------------------------------------------------------------- periodic --
+
+def _config(L, seed, pairs=((1.3, 0.4, 0.2), (2.2, 0.5, -0.3), (2.0, 0.0, 0.0))):
+    rng = np.random.default_rng(seed)
+    x = [rng.uniform(0, L, 3)]
+    for p in pairs:
+        x.append(x[0] + np.array(p))
+    x.append(rng.uniform(0, L, 3))
+    return np.array(x) % L
+
+
+def test_xi_independence_all_blocks():
+    """M_w(xi) + M_r(xi) does not depend on xi, for overlapping, touching and
+    separated pairs and every 11x11 block."""
+    L = 8.0
+    x = _config(L, 1)
+    Ms = [ewald.wave_dense(x, L, xi) + ewald.real_dense(x, L, xi)
+          for xi in (0.55, 0.85, 1.3)]
+    scale = np.abs(Ms[0]).max()
+    for M in Ms[1:]:
+        assert np.abs(M - Ms[0]).max() < 1e-12 * scale
+
+
+@pytest.mark.parametrize('L', [5.0, 8.0, 12.0])
+def test_periodic_self_mobility(L):
+    """Single sphere in a cubic box: Hasimoto's translational mobility and
+    the traces of the rotational and stresslet blocks (only the k = 0 mode is
+    missing from the lattice sums)."""
+    x = np.array([[0.3, 0.2, 0.1]])
+    M = ewald.wave_dense(x, L, 1.0) + ewald.real_dense(x, L, 1.0)
+    V = L**3
+    mu = 1 - 2.8372975 / L + 4 * PI / (3 * V)
+    assert abs(6 * PI * M[0, 0] - mu) < 2e-7 / L
+    assert np.allclose(np.diag(M)[0:3], M[0, 0], rtol=1e-12)
+    assert np.isclose(np.trace(M[3:6, 3:6]), 3 / (8 * PI) - 1 / (2 * V), rtol=1e-12)
+    assert np.isclose(np.trace(M[6:11, 6:11]), 3 / (4 * PI) * (1 - 4 * PI / (3 * V)),
+                      rtol=1e-12)
+
+
+def test_both_parts_symmetric_positive_semidefinite():
+    """Appendix C: M_r and M_w are each SPSD for any configuration and xi,
+    including overlapping spheres."""
+    L = 7.0
+    x = _config(L, 2, pairs=((0.5, 0.1, 0.0), (1.3, 0.4, 0.2), (2.2, 0.5, -0.3),
+                             (0.0, 1.9, 0.3)))
+    for xi in (0.6, 1.2):
+        for M in (ewald.wave_dense(x, L, xi), ewald.real_dense(x, L, xi)):
+            assert np.abs(M - M.T).max() < 1e-15 * np.abs(M).max()
+            lam = np.linalg.eigvalsh(M)
+            assert lam.min() > -1e-12 * lam.max()
+
+
+def test_matrix_free_products_match_dense():
+    L = 8.0
+    x = _config(L, 4)
+    q = np.random.default_rng(9).normal(size=(x.shape[0], 11))
+    for xi in (0.7, 1.1):
+        Mw = ewald.wave_dense(x, L, xi)
+        Mr = ewald.real_dense(x, L, xi)
+        assert np.allclose(ewald.wave_apply(x, q, L, xi).ravel(), Mw @ q.ravel(),
+                           atol=1e-14)
+        assert np.allclose(ewald.real_apply(x, q, L, xi).ravel(), Mr @ q.ravel(),
+                           atol=1e-14)
+
+
+def test_far_pair_approaches_free_space_in_large_box():
+    """Pair coupling in a box much larger than the separation approaches the
+    free-space tensor; the periodic correction decays like 1/L (the leading
+    backflow term of the Hasimoto sum)."""
+    r = np.array([3.0, 0.0, 0.0])
+    x = np.array([[0.0, 0.0, 0.0], r])
+    free = _free(r)
+    errs = []
+    for L in (40.0, 80.0):
+        M = ewald.wave_dense(x, L, 0.25) + ewald.real_dense(x, L, 0.25)
+        errs.append(np.abs(M[0:11, 11:22] - free.T).max())
+    assert 0.45 < errs[1] / errs[0] < 0.55
+    assert errs[1] < 0.15 * np.abs(free).max()
+
+
+# ----------------------------------------------------------------- sampler --
+
+def test_principal_sqrt():
+    L = 7.0
+    x = _config(L, 6)
+    Mr = ewald.real_dense(x, L, 1.0)
+    Q = np.stack([brownian.principal_sqrt_apply(Mr, v) for v in np.eye(Mr.shape[0])], 1)
+    assert np.allclose(Q, Q.T, atol=1e-14)
+    assert np.allclose(Q @ Q, Mr, atol=1e-14)
+
+
+def test_wave_sampler_covariance_is_grid_wave_mobility():
+    """The wave sampler is linear in the noise; with Re, Im ~ N(0, 1/2) on
+    the canonical half space its exact covariance is M_w summed over the
+    grid's wave vectors."""
+    L, Ng, xi = 6.0, 8, 1.0
+    x = _config(L, 7, pairs=((1.3, 0.4, 0.2),))
+    kap, idx = brownian.grid_half_space(Ng)
+    cols = []
+    for j in range(idx.shape[0]):
+        for c in range(3):
+            for part in (1.0, 1j):
+                psi = np.zeros((3, Ng, Ng, Ng // 2 + 1), complex)
+                psi[c, idx[j, 0], idx[j, 1], idx[j, 2]] = part
+                cols.append(brownian.wave_sample(x, psi, L, Ng, xi).ravel())
+    A = np.array(cols).T
+    cov = 0.5 * A @ A.T
+    ref = brownian.wave_dense_grid(x, L, Ng, xi)
+    assert np.abs(cov - ref).max() < 1e-13 * np.abs(ref).max()
+
+
+def test_sampler_ignores_non_canonical_entries():
+    L, Ng = 6.0, 8
+    x = np.array([[1.0, 2.0, 3.0], [2.5, 2.0, 3.5]])
+    rng = np.random.default_rng(1)
+    psi = rng.normal(size=(3, Ng, Ng, Ng // 2 + 1)) + 0j
+    y0 = brownian.wave_sample(x, psi, L, Ng, 1.0)
+    psi2 = psi.copy()
+    psi2[:, :, Ng // 2 + 1:, 0] = 99.0      # kx = 0, ky < 0: not canonical
+    psi2[:, :, :, Ng // 2] = 77.0           # kx Nyquist: not used
+    assert np.allclose(brownian.wave_sample(x, psi2, L, Ng, 1.0), y0)
+
+
+def test_split_sampler_matches_cholesky_covariance():
+    """Eq. split: covariance of M_r^(1/2) psi1 + M_w^(1/2) psi2 equals that of
+    Cholesky samples L z of M = M_r + M_w(grid) (statistical check)."""
+    L, Ng, xi = 6.0, 8, 1.1
+    x = np.array([[1.0, 1.0, 1.0], [2.6, 1.4, 1.2]])
+    M = brownian.wave_dense_grid(x, L, Ng, xi) + ewald.real_dense(x, L, xi)
+    n = 4000
+    rng = np.random.default_rng(11)
+    Mr = ewald.real_dense(x, L, xi)
+    lam, Q = np.linalg.eigh(Mr)
+    R = Q @ np.diag(np.sqrt(np.clip(lam, 0, None))) @ Q.T
+    kap, idx = brownian.grid_half_space(Ng)
+    cols = []
+    for j in range(idx.shape[0]):
+        for c in range(3):
+            for part in (1.0, 1j):
+                psi = np.zeros((3, Ng, Ng, Ng // 2 + 1), complex)
+                psi[c, idx[j, 0], idx[j, 1], idx[j, 2]] = part
+                cols.append(brownian.wave_sample(x, psi, L, Ng, xi).ravel())
+    A = np.array(cols).T * np.sqrt(0.5)
+    y = R @ rng.normal(size=(22, n)) + A @ rng.normal(size=(A.shape[1], n))
+    z = brownian.cholesky_sample(M, rng.normal(size=(22, n)))
+    cy, cz = y @ y.T / n, z @ z.T / n
+    tol = 6 * np.sqrt(2.0 / n) * np.sqrt(np.outer(np.diag(M), np.diag(M)))
+    assert (np.abs(cy - M) < tol).all()
+    assert (np.abs(cz - M) < tol).all()
+
+
+# -------------------------------------------------------------- constraint --
+
+def test_constraint_solution_and_schur_complement():
+    L = 8.0
+    x = _config(L, 8)
+    M = ewald.grand_dense(x, L, 0.8)
+    N = x.shape[0]
+    FL = np.random.default_rng(2).normal(size=(N, 6))
+    S, Uf = integrator.constrained_solve(M, FL)
+    q = np.concatenate([FL, S], 1)                 # (N, 11) in (F, L, s) order
+    out = (M @ q.ravel()).reshape(N, 11)
+    assert np.abs(out[:, 6:11]).max() < 1e-12 * np.abs(out).max()   # E = 0
+    assert np.allclose(out[:, 0:6], Uf, atol=1e-14)
+    Mc = integrator.constrained_mobility(M)
+    assert np.allclose(Mc @ FL.ravel(), Uf.ravel(), atol=1e-13)
+    # the constraint only removes mobility: M_UF - Mc is SPSD
+    iu, _ = integrator.split_indices(N)
+    lam = np.linalg.eigvalsh(M[np.ix_(iu, iu)] - Mc)
+    assert lam.min() > -1e-13
+    assert np.trace(Mc) < np.trace(M[np.ix_(iu, iu)])
+
+
+def test_midpoint_step_composition():
+    L, Ng, xi, dt = 7.0, 8, 1.1, 1e-3
+    x0 = np.array([[1.0, 1.0, 1.0], [2.6, 1.4, 1.2], [4.0, 5.0, 6.0]])
+    rng = np.random.default_rng(4)
+    FL = rng.normal(size=(3, 6))
+    psi1 = rng.normal(size=(3, 11))
+    psi2 = rng.normal(size=(3, Ng, Ng, Ng // 2 + 1)) * np.sqrt(0.5) * (1 + 1j)
+    out = integrator.midpoint_step(x0, FL, psi1, psi2, dt, L, Ng, xi)
+    y1 = brownian.real_sample(x0, psi1, L, xi)
+    y2 = brownian.wave_sample(x0, psi2, L, Ng, xi)
+    slip = np.sqrt(2 / dt) * (y1 + y2)
+    assert np.allclose(out['slip'], slip)
+    assert np.allclose(out['x_half'], (x0 + 0.5 * dt * slip[:, 0:3]) % L)
+    M = ewald.grand_dense(out['x_half'], L, 0.9)
+    q = np.concatenate([FL, out['S']], 1)
+    res = (M @ q.ravel()).reshape(3, 11)
+    assert np.allclose(res[:, 6:11], -slip[:, 6:11], atol=1e-11)
+    assert np.allclose(out['U'], slip[:, 0:3] + res[:, 0:3], atol=1e-11)
+    assert np.allclose(out['dx'], dt * out['U'])
+
+
+# -------------------------------------------------------------- parameters --
+
+def test_table1_lambda_max_and_support():
+    """Table 1: lambda_max and P at eps_q = 1e-3 for shear and extension."""
+    rows = [(0.0, 1.00, 5, 1.0, 1.00, 5), (0.1, 1.11, 6, 1.1, 1.21, 6),
+            (0.5, 1.64, 7, 1.5, 2.25, 8), (1.0, 2.62, 8, 2.0, 4.00, 10)]
+    for g, ls, ps, e, le, pe in rows:
+        lam_s = params.lambda_max(params.shear_tensor(g))
+        lam_e = params.lambda_max(params.extension_tensor(e))
+        assert np.isclose(lam_s, 1 + g * g / 2 + g * np.sqrt(1 + g * g / 4))
+        assert np.isclose(lam_e, max(e * e, 1 / (e * e)))
+        assert round(lam_s, 2) == ls and round(lam_e, 2) == le
+        assert params.support_deformed(1e-3, lam_s) == ps
+        assert params.support_deformed(1e-3, lam_e) == pe
+    assert params.support_orthorhombic(1e-3) == 5
+    # the orthorhombic rule with m = sqrt(pi P) meets the bound with equality
+    for eps in (1e-2, 1e-3, 1e-4, 1e-5):
+        P = params.support_orthorhombic(eps)
+        assert 2 * np.exp(-PI * P / 2) <= eps < 2 * np.exp(-PI * (P - 1) / 2)
+
+
+def test_deformed_error_estimates():
+    """Sec. II.C: orthorhombic parameters on a deformed grid give an error of
+    about (1e-3)^(1/lambda_max): 0.015 for shear strain 0.5 and 0.046 for
+    planar extension by 0.5 (the Table 1 row epsilon = 1.5, lambda = 2.25;
+    epsilon = 0.5 itself would give lambda = 4 and 0.18)."""
+    ls = params.lambda_max(params.shear_tensor(0.5))
+    le = params.lambda_max(params.extension_tensor(1.5))
+    assert round(1e-3 ** (1 / ls), 3) == 0.015
+    assert round(1e-3 ** (1 / le), 3) == 0.046
