@@ -1,0 +1,220 @@
+/*
+ * pse.h -- C ABI of the MI355X (gfx950) Positively-Split Ewald library for
+ * Brownian dynamics of rigid spheres with stresslet constraints
+ * (Fiore & Swan, arXiv 1709.06946).
+ *
+ * The library evaluates, on one GPU, the FTS grand mobility product
+ * (Sec. II, Eqs. pairsums and WSops2), the split Brownian sampler
+ * (Sec. III, Eq. split with the Lanczos real-space square root and the
+ * analytic wave-space square root of Eq. FFTsqrt) and the stresslet-
+ * constrained mid-point step (Sec. III.D and Appendix B).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Units: any consistent set; radius a, viscosity eta and kT come from the
+ * parameters.  The periodic cell is a cube of side L, V = L^3.
+ *
+ * Positions: double x[N][3], device memory, any real values (they are
+ *   wrapped into [0, L) internally; the caller's array is only written by
+ *   pse_constrained_step).
+ * Generalized force, 11 doubles per particle, particle-major:
+ *   [F_x F_y F_z | L_x L_y L_z | s_1 .. s_5]
+ * Generalized velocity, 11 doubles per particle:
+ *   [U_x U_y U_z | Omega_x Omega_y Omega_z | e_1 .. e_5]
+ *   The couplet is C = sum_q s_q Y_q - 1/2 eps.L (force index first), the
+ *   velocity gradient D_ij = du_i/dx_j gives Omega = -1/2 eps:D and
+ *   e_q = Y_q : D, with the orthonormal symmetric traceless basis
+ *   Y_1 = (xy+yx)/sqrt2, Y_2 = (xz+zx)/sqrt2, Y_3 = (yz+zy)/sqrt2,
+ *   Y_4 = (xx-yy)/sqrt2, Y_5 = (xx+yy-2zz)/sqrt6.  In these coordinates the
+ *   11N x 11N grand mobility is a symmetric matrix.
+ * Particle vectors are always double, whatever the handle's precision.
+ *
+ * Wave noise (optional caller-supplied Brownian noise for the wave-space
+ *   square root): complex double psi[3][Ng][Ng][Ng/2+1] (interleaved re, im),
+ *   device memory.  Index i of the z and y axes maps to wave number i for
+ *   i < Ng/2 and i - Ng otherwise; the x index is kappa_x >= 0.  Only the
+ *   canonical half space (kappa_x > 0; or kappa_x = 0, kappa_y > 0; or
+ *   kappa_x = kappa_y = 0, kappa_z > 0) is read; psi(-k) = conj(psi(k)).
+ *   Modes with a Nyquist index and k = 0 carry no noise.  Real and imaginary
+ *   parts should be independent N(0, 1/2).
+ *
+ * Memory: every pointer argument is caller-owned device memory unless noted;
+ *   the library never frees or keeps it after the call returns.  The handle
+ *   owns all its workspace (grids, spectra, cell lists, Krylov bases).
+ * Streams: all work runs on the stream given at creation (NULL = the
+ *   library's own stream).  Calls return after the work has completed.  A
+ *   handle is not re-entrant: use one handle per host thread.
+ * Status: 0 = success; > 0 = warning with valid outputs; < 0 = error, outputs
+ *   undefined.  No call aborts or throws; pse_last_error gives the message.
+ */
+#ifndef PSE_H
+#define PSE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  PSE_OK = 0,
+  PSE_WARN_NOT_CONVERGED = 1,   /* a Krylov solve stopped at its limit      */
+  PSE_ERR_INVALID = -1,         /* invalid argument or parameter            */
+  PSE_ERR_NOMEM = -2,           /* device allocation failed                 */
+  PSE_ERR_HIP = -3,             /* HIP runtime error                        */
+  PSE_ERR_NONFINITE = -4        /* NaN/Inf detected in an input or result   */
+};
+
+enum { PSE_FP64 = 0, PSE_MIXED = 1 };     /* pse_params.precision */
+enum { PSE_REAL = 1u, PSE_WAVE = 2u };     /* pse_mobility_apply parts */
+
+/* Input parameters.  Fields set to 0 are derived (see pse_derive). */
+typedef struct pse_params {
+  int64_t n;               /* number of particles N > 0                      */
+  double box;              /* cubic cell side L > 4a                         */
+  double radius;           /* sphere radius a > 0                            */
+  double viscosity;        /* eta > 0                                        */
+  double kT;               /* thermal energy > 0                             */
+  double tol;              /* Ewald / quadrature tolerance eps, (0, 0.1]     */
+  int32_t grid;            /* FFT grid points per side Ng (even, 2^j or
+                              3*2^j, 8 <= Ng <= 1024); 0 = from tol         */
+  int32_t support;         /* Gaussian support P (points per side); 0 = auto */
+  double xi;               /* splitting parameter; 0 = from grid and tol     */
+  double rcut;             /* real-space cutoff; 0 = auto                    */
+  int32_t precision;       /* PSE_FP64 or PSE_MIXED                          */
+  int32_t lanczos_maxit;   /* 0 = 100                                        */
+  double lanczos_tol;      /* 0 = 1e-3                                       */
+  int32_t gmres_restart;   /* 0 = 30                                         */
+  int32_t gmres_maxit;     /* total GMRES iterations; 0 = 200                */
+  double gmres_tol;        /* relative residual; 0 = 1e-6                    */
+  int32_t refine_passes;   /* FP64 residual refinement passes (mixed); 0 = 3 */
+  void *stream;            /* hipStream_t to run on, or NULL                 */
+} pse_params;
+
+/* Derived quantities (Sec. II.C, Eq. bound and the Sec. II.C.1 cutoff). */
+typedef struct pse_derived {
+  int32_t grid;            /* Ng                                             */
+  int32_t support;         /* P                                              */
+  double xi;               /* splitting parameter                            */
+  double eta_s;            /* Gaussian shape (h P xi / m)^2, < 1             */
+  double m;                /* Gaussian width in standard deviations          */
+  double h;                /* grid spacing L / Ng                            */
+  double rcut;             /* real-space cutoff                              */
+  int32_t cells;           /* cells per side of the real-space cell list     */
+  int32_t lanczos_maxit, gmres_restart, gmres_maxit, refine_passes;
+  double lanczos_tol, gmres_tol;
+} pse_derived;
+
+/* Krylov statistics of the last call (written by the library, host memory). */
+typedef struct pse_stats {
+  int32_t lanczos_iters;   /* Lanczos iterations of the real-space sqrt      */
+  int32_t gmres_iters;     /* GMRES iterations, all refinement passes        */
+  int32_t refine_passes;   /* FP64 refinement passes (mixed precision)       */
+  int32_t converged;       /* 1 if every Krylov solve met its tolerance      */
+  double lanczos_change;   /* last relative change of the Lanczos iterate    */
+  double gmres_residual;   /* final relative residual of M_ES S = b (in the
+                              precision of the last solve)                   */
+  double fp64_residual;    /* FP64 relative residual after refinement, or -1 */
+} pse_stats;
+
+typedef struct pse_handle pse_handle;
+
+/* Derive Ng, P, xi, eta_s, m, rcut and Krylov defaults from p without any
+ * GPU work.  Rules: P = ceil((2/pi) ln(2/eps)) and m = sqrt(pi P) (Eq. bound
+ * with lambda_max = 1); xi = pi Ng / (2 L sqrt(ln(1/eps))) so that the
+ * Hasimoto factor exp(-k^2/4xi^2) equals eps at the Nyquist wave number;
+ * eta_s = (h P xi / m)^2; rcut = 2a + sqrt(ln(1/eps))/xi, the real-space
+ * functions decaying like exp(-xi^2 (r - 2a)^2) (Appendix A).
+ * Returns PSE_ERR_INVALID for inconsistent parameters (eta_s >= 1,
+ * rcut > L/3, unsupported Ng, ...). */
+int pse_derive(const pse_params *p, pse_derived *out);
+
+/* Device bytes a handle with these parameters would allocate (host only). */
+int pse_footprint_bytes(const pse_params *p, size_t *bytes);
+
+/* Create a handle: validate, derive, allocate the library-owned workspace on
+ * the current device and build the real-space function tables on the GPU. */
+int pse_create(const pse_params *p, pse_handle **out);
+
+/* Free the handle's device memory.  NULL is accepted. */
+int pse_destroy(pse_handle *h);
+
+/* Derived parameters of a live handle. */
+int pse_get_derived(const pse_handle *h, pse_derived *out);
+
+/* Grand mobility product (Eq. pairsums, WSops2):
+ *   out = (M_r + M_w) in     for parts = PSE_REAL | PSE_WAVE,
+ * or either part alone.  x: double[N][3]; in, out: double[N][11] in the
+ * layouts above.  M_r is the neighbour-list sum of the real-space pair
+ * functions (factor 1 - H) within rcut, M_w the Gaussian-gridded NUFFT
+ * evaluation of the wave-space sum (factor H).  in and out must not
+ * overlap. */
+int pse_mobility_apply(pse_handle *h, const double *x, const double *in,
+                       double *out, unsigned parts);
+
+/* Split Brownian sampler (Eq. split): out_real = M_r^(1/2) psi_real by the
+ * Lanczos iteration (relative change tolerance lanczos_tol), and
+ * out_wave = M_w^(1/2) psi_wave by Eq. FFTsqrt (noise scaled, projected,
+ * inverse FFT, interpolated).  Both unscaled (no sqrt(2kT/dt)).
+ * psi_real: double[N][11] or NULL; psi_wave: wave-noise layout or NULL.
+ * A NULL noise pointer draws the noise in-kernel from Philox-4x32-10 keyed by
+ * (seed, counter).  out_real, out_wave: double[N][11], either may be NULL.
+ * stats may be NULL.  Returns PSE_WARN_NOT_CONVERGED if Lanczos hit its
+ * limit. */
+int pse_brownian_sample(pse_handle *h, const double *x,
+                        const double *psi_real, const double *psi_wave,
+                        uint64_t seed, uint64_t counter,
+                        double *out_real, double *out_wave, pse_stats *stats);
+
+/* Optional inputs and outputs of pse_constrained_step (NULL = unused). */
+typedef struct pse_step_io {
+  const double *psi_real;  /* in:  double[N][11] real-space noise           */
+  const double *psi_wave;  /* in:  wave noise (layout above)                */
+  double *slip;            /* out: double[N][11] (U^B, Omega^B, E^B)        */
+  double *stresslet;       /* out: double[N][5]  S at the mid-point         */
+  double *velocity;        /* out: double[N][3]  U at the mid-point         */
+} pse_step_io;
+
+/* One stresslet-constrained mid-point step (Sec. III.D, Appendix B):
+ *   (U^B, E^B) = sqrt(2 kT / dt) (M_r^(1/2) psi1 + M_w^(1/2) psi2)  at x_k
+ *   x_{k+1/2}  = x_k + dt/2 U^B
+ *   M_ES S     = -E^B - M_EF F^P         at x_{k+1/2}  (GMRES)
+ *   U          = U^B + M_UF F^P + M_US S  at x_{k+1/2}
+ *   x_{k+1}    = x_k + dt U      (written to x, wrapped into [0, L))
+ * FL: double[N][6] deterministic force and torque F^P, or NULL for none.
+ * Noise comes from io (if given) or from Philox keyed by (seed, step).
+ * Returns PSE_WARN_NOT_CONVERGED if a Krylov solve hit its limit. */
+int pse_constrained_step(pse_handle *h, double *x, const double *FL,
+                         double dt, uint64_t seed, uint64_t step,
+                         const pse_step_io *io, pse_stats *stats);
+
+/* Diagnostics of individual stages (used by the kernel tests). */
+/* In-place unnormalized 3D FFT of ncomp complex double grids
+ * data[ncomp][Ng][Ng][Ng] (z, y, x; x fastest) with the handle's grid and
+ * precision (mixed handles convert to float and back).  direction -1:
+ * sum f exp(-i k.x); +1: sum f exp(+i k.x).  1 <= ncomp <= 6. */
+int pse_fft3d(pse_handle *h, double *data, int ncomp, int direction);
+
+/* Gaussian spreading of ncomp components of q (double[N][ncomp]) onto
+ * ncomp real grids out[ncomp][Ng][Ng][Ng]: out_c(x_n) = sum_b K(x_n - x_b)
+ * q_bc with K(r) = (2 xi^2 / (pi eta_s))^(3/2) exp(-2 xi^2 r^2 / eta_s)
+ * truncated to the P^3 nearest grid points (Sec. II.C, Eq. quadapprox).
+ * 1 <= ncomp <= 11. */
+int pse_spread(pse_handle *h, const double *x, const double *q, int ncomp,
+               double *grids);
+
+/* Interpolation, the adjoint operation: out_bc = sum_n K(x_n - x_b)
+ * g_c(x_n) for ncomp real grids g[ncomp][Ng][Ng][Ng]; out double[N][ncomp]. */
+int pse_interpolate(pse_handle *h, const double *x, const double *grids,
+                    int ncomp, double *out);
+
+/* Message for the last failure on this handle (or of the last failed create
+ * when h is NULL).  Never NULL. */
+const char *pse_last_error(const pse_handle *h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PSE_H */

@@ -1,0 +1,581 @@
+// C ABI of the PSE library and the orchestration of its stages.
+//
+//  mobility: real part (cell list + pair sum) and wave part
+//    (spread -> FFT -> k-space kernel -> inverse FFT -> interpolate),
+//    Eq. pairsums with M = M_r + M_w (Sec. II.B-C).
+//  sampler:  Eq. split; Lanczos for M_r^(1/2), Eq. FFTsqrt for M_w^(1/2).
+//  step:     the four-step mid-point scheme of Sec. III.D / Appendix B, with
+//            GMRES on the stresslet constraint (Eq. rigidconstraint).
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "pse_internal.h"
+
+struct pse_handle {
+  pse::Handle h;
+};
+
+namespace pse {
+
+static thread_local std::string g_create_error = "no error";
+
+template <typename T> GridSet<T> &grids(Handle &h);
+template <> GridSet<double> &grids<double>(Handle &h) { return h.g64; }
+template <> GridSet<float> &grids<float>(Handle &h) { return h.g32; }
+
+// ------------------------------------------------------- small kernels --
+
+// x_half = wrap(x + c * slip_U)
+__global__ void advance_kernel(const double *__restrict__ x, const double *__restrict__ v,
+                               int vstride, double c, int64_t n, double L,
+                               double *__restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int d = 0; d < 3; ++d) {
+    double y = x[3 * i + d] + c * v[i * vstride + d];
+    y -= L * floor(y / L);
+    if (y >= L) y -= L;
+    if (y < 0) y = 0;
+    out[3 * i + d] = y;
+  }
+}
+
+// slip = c (y1 + y2) on U and E components, Omega from y1 alone is not
+// formed (positions do not need it): those entries are set to 0.
+__global__ void slip_kernel(const double *__restrict__ y1, const double *__restrict__ y2,
+                            double c, int64_t n, double *__restrict__ slip) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int k = 0; k < NC; ++k) {
+    const bool om = k >= 3 && k < 6;
+    slip[i * NC + k] = om ? 0.0 : c * (y1[i * NC + k] + y2[i * NC + k]);
+  }
+}
+
+// b = -(slip_E + m_E) (N x 5); m may be NULL
+__global__ void rhs_kernel(const double *__restrict__ slip, const double *__restrict__ m,
+                           int64_t n, double *__restrict__ b) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int k = 0; k < 5; ++k)
+    b[i * 5 + k] = -(slip[i * NC + 6 + k] + (m ? m[i * NC + 6 + k] : 0.0));
+}
+
+// moments (N x 11) = [FL | S]
+__global__ void moments_kernel(const double *__restrict__ FL, const double *__restrict__ S,
+                               int64_t n, double *__restrict__ q) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int k = 0; k < 6; ++k) q[i * NC + k] = FL ? FL[i * 6 + k] : 0.0;
+  for (int k = 0; k < 5; ++k) q[i * NC + 6 + k] = S ? S[i * 5 + k] : 0.0;
+}
+
+// U = slip_U + m_U (N x 3)
+__global__ void velocity_kernel(const double *__restrict__ slip, const double *__restrict__ m,
+                                int64_t n, double *__restrict__ U) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int k = 0; k < 3; ++k) U[i * 3 + k] = slip[i * NC + k] + m[i * NC + k];
+}
+
+__global__ void twiddle_kernel64(double2 *tw, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s, c;
+  sincospi(-2.0 * i / n, &s, &c);
+  tw[i] = double2{c, s};
+}
+
+__global__ void twiddle_kernel32(float2 *tw, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s, c;
+  sincospi(-2.0 * i / n, &s, &c);
+  tw[i] = float2{(float)c, (float)s};
+}
+
+__global__ void d2f_kernel(const double2 *src, float2 *dst, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = float2{(float)src[i].x, (float)src[i].y};
+}
+
+__global__ void f2d_kernel(const float2 *src, double2 *dst, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = double2{src[i].x, src[i].y};
+}
+
+// ------------------------------------------------------------ operators --
+
+template <typename T>
+static void wave_apply(Handle &h, const double *xw, const double *in, const CompSet &cin,
+                       double *out, const CompSet &cout, bool accumulate) {
+  GridSet<T> &G = grids<T>(h);
+  const int npi = (cin.n + 1) / 2, npo = (cout.n + 1) / 2;
+  zero_grids<T>(h, G.gin, npi);
+  spread<T>(h, xw, in, NC, cin, G.gin);
+  fft3d<T>(h, G.gin, G.twiddle, npi, -1);
+  kspace_mobility<T>(h, G.gin, cin, G.gout, cout);
+  fft3d<T>(h, G.gout, G.twiddle, npo, +1);
+  interpolate<T>(h, xw, G.gout, cout, out, NC, accumulate, 1.0);
+}
+
+// out[cout] = M(cin -> cout) in[cin] at wrapped positions xw whose cell list
+// is current.  fp64 forces the FP64 kernels in a mixed handle.
+static void mobility(Handle &h, const double *xw, bool want_real, bool want_wave,
+                     const double *in, const CompSet &cin, double *out,
+                     const CompSet &cout, bool fp64) {
+  const bool f32 = h.mixed && !fp64;
+  bool acc = false;
+  if (want_real) {
+    if (f32) real_apply<float>(h, xw, in, cin, out, cout, false);
+    else real_apply<double>(h, xw, in, cin, out, cout, false);
+    acc = true;
+  }
+  if (want_wave) {
+    if (f32) wave_apply<float>(h, xw, in, cin, out, cout, acc);
+    else wave_apply<double>(h, xw, in, cin, out, cout, acc);
+  }
+}
+
+template <typename T>
+static void wave_sqrt_t(Handle &h, const double *xw, const double *psi, uint64_t seed,
+                        uint64_t counter, double *out, const CompSet &cout) {
+  GridSet<T> &G = grids<T>(h);
+  const int npo = (cout.n + 1) / 2;
+  kspace_noise<T>(h, psi, seed, counter, G.gout, cout);
+  fft3d<T>(h, G.gout, G.twiddle, npo, +1);
+  interpolate<T>(h, xw, G.gout, cout, out, NC, false, 1.0);
+}
+
+static void wave_sqrt(Handle &h, const double *xw, const double *psi, uint64_t seed,
+                      uint64_t counter, double *out, const CompSet &cout) {
+  if (h.mixed) wave_sqrt_t<float>(h, xw, psi, seed, counter, out, cout);
+  else wave_sqrt_t<double>(h, xw, psi, seed, counter, out, cout);
+}
+
+static KrylovResult real_sqrt(Handle &h, const double *xw, const double *psi, double *out) {
+  const CompSet all = comps_range(0, NC);
+  Op A = [&](const double *in, double *o) {
+    if (h.mixed) real_apply<float>(h, xw, in, all, o, all, false);
+    else real_apply<double>(h, xw, in, all, o, all, false);
+  };
+  return lanczos_sqrt(h, A, psi, (size_t)h.n * NC, out, h.d.lanczos_maxit, h.d.lanczos_tol);
+}
+
+static void prepare_positions(Handle &h, const double *x, double *xw) {
+  wrap_positions(h, x, xw);
+  build_cells(h, xw);
+}
+
+// Solve M_ES S = b at xh (cell list current).  Mixed handles run FP32 GMRES
+// inside FP64 residual refinement: r = b - M_ES^(64) S, correction from the
+// FP32 operator, until the FP64 relative residual meets gmres_tol.
+static void stresslet_solve(Handle &h, const double *xh, const double *b, double *S,
+                            pse_stats &st, bool &converged) {
+  const size_t n5 = (size_t)h.n * 5;
+  const CompSet es = comps_range(6, 11);
+  auto make_op = [&](bool fp64) {
+    return Op([&, fp64](const double *in, double *o) {
+      scatter_comps(h, in, es, h.v0, NC, h.n, false, 1.0);
+      mobility(h, xh, true, true, h.v0, es, h.v1, es, fp64);
+      gather_comps(h, h.v1, NC, es, o, h.n);
+    });
+  };
+  if (!h.mixed) {
+    KrylovResult r = gmres(h, make_op(true), b, n5, S, h.d.gmres_restart, h.d.gmres_maxit,
+                           h.d.gmres_tol);
+    st.gmres_iters += r.iters;
+    st.gmres_residual = r.resid;
+    st.fp64_residual = r.resid;
+    converged = converged && r.converged;
+    return;
+  }
+  Op A32 = make_op(false), A64 = make_op(true);
+  vzero(h, S, n5);
+  vcopy(h, h.es_r, b, n5);
+  double bnorm2 = 0.0;
+  {
+    double *tmp = h.small + h.small_len - 4;
+    multi_dot(h, b, n5, 1, b, n5, tmp);
+    PSE_HIP(hipMemcpyAsync(&bnorm2, tmp, sizeof(double), hipMemcpyDeviceToHost, h.stream));
+    PSE_HIP(hipStreamSynchronize(h.stream));
+  }
+  const double bnorm = std::sqrt(bnorm2);
+  if (!(bnorm > 0)) {
+    st.fp64_residual = 0.0;
+    return;
+  }
+  bool ok = false;
+  for (int pass = 0; pass < h.d.refine_passes; ++pass) {
+    KrylovResult r = gmres(h, A32, h.es_r, n5, h.es_d, h.d.gmres_restart, h.d.gmres_maxit,
+                           h.d.gmres_tol);
+    st.gmres_iters += r.iters;
+    st.gmres_residual = r.resid;
+    st.refine_passes = pass + 1;
+    vaxpby(h, 1.0, h.es_d, 1.0, S, n5);
+    A64(S, h.es_r);
+    vaxpby(h, 1.0, b, -1.0, h.es_r, n5);
+    double rn2 = 0.0;
+    double *tmp = h.small + h.small_len - 4;
+    multi_dot(h, h.es_r, n5, 1, h.es_r, n5, tmp);
+    PSE_HIP(hipMemcpyAsync(&rn2, tmp, sizeof(double), hipMemcpyDeviceToHost, h.stream));
+    PSE_HIP(hipStreamSynchronize(h.stream));
+    st.fp64_residual = std::sqrt(rn2) / bnorm;
+    if (st.fp64_residual < h.d.gmres_tol) {
+      ok = true;
+      break;
+    }
+  }
+  converged = converged && ok;
+}
+
+static void alloc(void **p, size_t bytes) { PSE_HIP(hipMalloc(p, bytes)); }
+
+static void create(const pse_params &p, Handle &h) {
+  derive(p, h.d);
+  h.p = p;
+  h.n = p.n;
+  h.mixed = p.precision == PSE_MIXED;
+  h.ngrid = (size_t)h.d.grid * h.d.grid * h.d.grid;
+  h.ncell = h.d.cells;
+  if (p.stream) {
+    h.stream = (hipStream_t)p.stream;
+    h.own_stream = false;
+  } else {
+    PSE_HIP(hipStreamCreateWithFlags(&h.stream, hipStreamNonBlocking));
+    h.own_stream = true;
+  }
+  const size_t n = (size_t)h.n;
+  const int ng = h.d.grid;
+  alloc((void **)&h.g64.gin, MAX_PACK * h.ngrid * sizeof(double2));
+  alloc((void **)&h.g64.gout, MAX_PACK * h.ngrid * sizeof(double2));
+  alloc((void **)&h.g64.twiddle, ng * sizeof(double2));
+  hipLaunchKernelGGL(twiddle_kernel64, dim3(nblocks(ng, 256)), dim3(256), 0, h.stream,
+                     h.g64.twiddle, ng);
+  PSE_LAUNCH_CHECK();
+  if (h.mixed) {
+    alloc((void **)&h.g32.gin, MAX_PACK * h.ngrid * sizeof(float2));
+    alloc((void **)&h.g32.gout, MAX_PACK * h.ngrid * sizeof(float2));
+    alloc((void **)&h.g32.twiddle, ng * sizeof(float2));
+    hipLaunchKernelGGL(twiddle_kernel32, dim3(nblocks(ng, 256)), dim3(256), 0, h.stream,
+                       h.g32.twiddle, ng);
+    PSE_LAUNCH_CHECK();
+  }
+  build_tables(h);
+  const size_t ncells = (size_t)h.ncell * h.ncell * h.ncell;
+  alloc((void **)&h.cell_start, (ncells + 1) * sizeof(int));
+  alloc((void **)&h.cell_count, ncells * sizeof(int));
+  alloc((void **)&h.scan_tmp, ((ncells + 1023) / 1024 + 8) * sizeof(int));
+  alloc((void **)&h.cell_of, n * sizeof(int));
+  alloc((void **)&h.slot, n * sizeof(int));
+  alloc((void **)&h.perm, n * sizeof(int));
+  alloc((void **)&h.xw, 3 * n * sizeof(double));
+  alloc((void **)&h.xh, 3 * n * sizeof(double));
+  double **vs[6] = {&h.v0, &h.v1, &h.v2, &h.v3, &h.v4, &h.v5};
+  for (double **v : vs) alloc((void **)v, NC * n * sizeof(double));
+  double **es[4] = {&h.es_b, &h.es_x, &h.es_r, &h.es_d};
+  for (double **v : es) alloc((void **)v, 5 * n * sizeof(double));
+  alloc((void **)&h.lz_V, (size_t)(h.d.lanczos_maxit + 1) * NC * n * sizeof(double));
+  alloc((void **)&h.gm_V, (size_t)(h.d.gmres_restart + 1) * 5 * n * sizeof(double));
+  const size_t M = h.d.lanczos_maxit, R = h.d.gmres_restart;
+  h.small_len = std::max((M + 1) * 8 + (M + 3) * (M + 1), (R + 1) * (R + 1) + 8 * (R + 2)) + 64;
+  alloc((void **)&h.small, h.small_len * sizeof(double));
+  h.dots_len = 1024 * (std::max(M, R) + 2);
+  alloc((void **)&h.dots, h.dots_len * sizeof(double));
+  PSE_HIP(hipStreamSynchronize(h.stream));
+}
+
+static void release(Handle &h) {
+  void *ptrs[] = {h.g64.gin, h.g64.gout, h.g64.twiddle, h.g64.table, h.g32.gin, h.g32.gout,
+                  h.g32.twiddle, h.g32.table, h.cell_start, h.cell_count, h.scan_tmp,
+                  h.cell_of, h.slot, h.perm, h.xw, h.xh, h.v0, h.v1, h.v2, h.v3, h.v4,
+                  h.v5, h.es_b, h.es_x, h.es_r, h.es_d, h.lz_V, h.gm_V, h.small, h.dots};
+  for (void *p : ptrs)
+    if (p) (void)hipFree(p);
+  if (h.own_stream && h.stream) (void)hipStreamDestroy(h.stream);
+}
+
+template <typename F> static int guarded(pse_handle *hd, F &&f) {
+  try {
+    f();
+    return PSE_OK;
+  } catch (const Error &e) {
+    if (hd) hd->h.err = e.msg;
+    else g_create_error = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc &) {
+    if (hd) hd->h.err = "host allocation failed";
+    else g_create_error = "host allocation failed";
+    return PSE_ERR_NOMEM;
+  } catch (...) {
+    if (hd) hd->h.err = "unexpected exception";
+    else g_create_error = "unexpected exception";
+    return PSE_ERR_HIP;
+  }
+}
+
+}  // namespace pse
+
+using namespace pse;
+
+extern "C" {
+
+int pse_derive(const pse_params *p, pse_derived *out) {
+  if (!p || !out) return PSE_ERR_INVALID;
+  return guarded(nullptr, [&] { derive(*p, *out); });
+}
+
+int pse_footprint_bytes(const pse_params *p, size_t *bytes) {
+  if (!p || !bytes) return PSE_ERR_INVALID;
+  return guarded(nullptr, [&] {
+    pse_derived d;
+    derive(*p, d);
+    *bytes = footprint(*p, d);
+  });
+}
+
+int pse_create(const pse_params *p, pse_handle **out) {
+  if (!p || !out) {
+    g_create_error = "null argument";
+    return PSE_ERR_INVALID;
+  }
+  *out = nullptr;
+  pse_handle *hd = new (std::nothrow) pse_handle();
+  if (!hd) return PSE_ERR_NOMEM;
+  const int rc = guarded(nullptr, [&] { create(*p, hd->h); });
+  if (rc != PSE_OK) {
+    release(hd->h);
+    delete hd;
+    return rc;
+  }
+  *out = hd;
+  return PSE_OK;
+}
+
+int pse_destroy(pse_handle *hd) {
+  if (!hd) return PSE_OK;
+  (void)hipStreamSynchronize(hd->h.stream);
+  release(hd->h);
+  delete hd;
+  return PSE_OK;
+}
+
+int pse_get_derived(const pse_handle *hd, pse_derived *out) {
+  if (!hd || !out) return PSE_ERR_INVALID;
+  *out = hd->h.d;
+  return PSE_OK;
+}
+
+const char *pse_last_error(const pse_handle *hd) {
+  return hd ? hd->h.err.c_str() : g_create_error.c_str();
+}
+
+int pse_mobility_apply(pse_handle *hd, const double *x, const double *in, double *out,
+                       unsigned parts) {
+  if (!hd) return PSE_ERR_INVALID;
+  if (!x || !in || !out || parts == 0 || (parts & ~3u)) {
+    hd->h.err = "pse_mobility_apply: null pointer or bad parts";
+    return PSE_ERR_INVALID;
+  }
+  return guarded(hd, [&] {
+    Handle &h = hd->h;
+    const CompSet all = comps_range(0, NC);
+    prepare_positions(h, x, h.xw);
+    mobility(h, h.xw, parts & PSE_REAL, parts & PSE_WAVE, in, all, out, all, false);
+    PSE_HIP(hipStreamSynchronize(h.stream));
+  });
+}
+
+int pse_brownian_sample(pse_handle *hd, const double *x, const double *psi_real,
+                        const double *psi_wave, uint64_t seed, uint64_t counter,
+                        double *out_real, double *out_wave, pse_stats *stats) {
+  if (!hd) return PSE_ERR_INVALID;
+  if (!x) {
+    hd->h.err = "pse_brownian_sample: null positions";
+    return PSE_ERR_INVALID;
+  }
+  int warn = PSE_OK;
+  const int rc = guarded(hd, [&] {
+    Handle &h = hd->h;
+    pse_stats st{};
+    st.converged = 1;
+    st.fp64_residual = -1;
+    prepare_positions(h, x, h.xw);
+    if (out_real) {
+      const double *psi = psi_real;
+      if (!psi) {
+        real_noise(h, seed, counter, h.v2);
+        psi = h.v2;
+      }
+      KrylovResult r = real_sqrt(h, h.xw, psi, out_real);
+      st.lanczos_iters = r.iters;
+      st.lanczos_change = r.resid;
+      if (!r.converged) {
+        st.converged = 0;
+        warn = PSE_WARN_NOT_CONVERGED;
+      }
+    }
+    if (out_wave) wave_sqrt(h, h.xw, psi_wave, seed, counter, out_wave, comps_range(0, NC));
+    PSE_HIP(hipStreamSynchronize(h.stream));
+    if (stats) *stats = st;
+  });
+  return rc != PSE_OK ? rc : warn;
+}
+
+int pse_constrained_step(pse_handle *hd, double *x, const double *FL, double dt,
+                         uint64_t seed, uint64_t step, const pse_step_io *io,
+                         pse_stats *stats) {
+  if (!hd) return PSE_ERR_INVALID;
+  if (!x || !(dt > 0)) {
+    hd->h.err = "pse_constrained_step: null positions or dt <= 0";
+    return PSE_ERR_INVALID;
+  }
+  int warn = PSE_OK;
+  const int rc = guarded(hd, [&] {
+    Handle &h = hd->h;
+    const int64_t n = h.n;
+    pse_stats st{};
+    st.fp64_residual = -1;
+    bool converged = true;
+    // 1. slip velocities at x_k
+    prepare_positions(h, x, h.xw);
+    const double *psi = io ? io->psi_real : nullptr;
+    if (!psi) {
+      real_noise(h, seed, step, h.v2);
+      psi = h.v2;
+    }
+    KrylovResult lr = real_sqrt(h, h.xw, psi, h.v0);
+    st.lanczos_iters = lr.iters;
+    st.lanczos_change = lr.resid;
+    converged = converged && lr.converged;
+    CompSet ue{};
+    ue.n = 8;
+    for (int k = 0; k < 3; ++k) ue.idx[k] = k;
+    for (int k = 0; k < 5; ++k) ue.idx[3 + k] = 6 + k;
+    wave_sqrt(h, h.xw, io ? io->psi_wave : nullptr, seed, step, h.v1, ue);
+    double *slip = h.v3;
+    hipLaunchKernelGGL(slip_kernel, dim3(nblocks(n, 256)), dim3(256), 0, h.stream, h.v0,
+                       h.v1, std::sqrt(2.0 * h.p.kT / dt), n, slip);
+    PSE_LAUNCH_CHECK();
+    // 2. mid-point
+    hipLaunchKernelGGL(advance_kernel, dim3(nblocks(n, 256)), dim3(256), 0, h.stream, h.xw,
+                       slip, NC, 0.5 * dt, n, h.p.box, h.xh);
+    PSE_LAUNCH_CHECK();
+    build_cells(h, h.xh);
+    // 3. constraint at the mid-point: M_ES S = -E^B - M_EF F^P
+    const CompSet fl = comps_range(0, 6), es = comps_range(6, 11);
+    if (FL) {
+      hipLaunchKernelGGL(moments_kernel, dim3(nblocks(n, 256)), dim3(256), 0, h.stream, FL,
+                         (const double *)nullptr, n, h.v4);
+      PSE_LAUNCH_CHECK();
+      mobility(h, h.xh, true, true, h.v4, fl, h.v5, es, false);
+    }
+    hipLaunchKernelGGL(rhs_kernel, dim3(nblocks(n, 256)), dim3(256), 0, h.stream, slip,
+                       FL ? (const double *)h.v5 : nullptr, n, h.es_b);
+    PSE_LAUNCH_CHECK();
+    stresslet_solve(h, h.xh, h.es_b, h.es_x, st, converged);
+    // U = U^B + M_UF F^P + M_US S
+    hipLaunchKernelGGL(moments_kernel, dim3(nblocks(n, 256)), dim3(256), 0, h.stream, FL,
+                       (const double *)h.es_x, n, h.v4);
+    PSE_LAUNCH_CHECK();
+    const CompSet u3 = comps_range(0, 3);
+    mobility(h, h.xh, true, true, h.v4, FL ? comps_range(0, 11) : es, h.v5, u3, false);
+    double *U = h.v2;   // N x 3
+    hipLaunchKernelGGL(velocity_kernel, dim3(nblocks(n, 256)), dim3(256), 0, h.stream, slip,
+                       h.v5, n, U);
+    PSE_LAUNCH_CHECK();
+    // 4. x_{k+1} = x_k + dt U
+    hipLaunchKernelGGL(advance_kernel, dim3(nblocks(n, 256)), dim3(256), 0, h.stream, h.xw,
+                       U, 3, dt, n, h.p.box, x);
+    PSE_LAUNCH_CHECK();
+    if (io) {
+      if (io->slip) PSE_HIP(hipMemcpyAsync(io->slip, slip, NC * n * sizeof(double),
+                                           hipMemcpyDeviceToDevice, h.stream));
+      if (io->stresslet) PSE_HIP(hipMemcpyAsync(io->stresslet, h.es_x, 5 * n * sizeof(double),
+                                                hipMemcpyDeviceToDevice, h.stream));
+      if (io->velocity) PSE_HIP(hipMemcpyAsync(io->velocity, U, 3 * n * sizeof(double),
+                                               hipMemcpyDeviceToDevice, h.stream));
+    }
+    PSE_HIP(hipStreamSynchronize(h.stream));
+    st.converged = converged ? 1 : 0;
+    if (!converged) warn = PSE_WARN_NOT_CONVERGED;
+    if (stats) *stats = st;
+  });
+  return rc != PSE_OK ? rc : warn;
+}
+
+int pse_fft3d(pse_handle *hd, double *data, int ncomp, int direction) {
+  if (!hd) return PSE_ERR_INVALID;
+  if (!data || ncomp < 1 || ncomp > MAX_PACK || (direction != 1 && direction != -1)) {
+    hd->h.err = "pse_fft3d: bad arguments";
+    return PSE_ERR_INVALID;
+  }
+  return guarded(hd, [&] {
+    Handle &h = hd->h;
+    if (!h.mixed) {
+      fft3d<double>(h, (double2 *)data, h.g64.twiddle, ncomp, direction);
+    } else {
+      const size_t cnt = (size_t)ncomp * h.ngrid;
+      hipLaunchKernelGGL(d2f_kernel, dim3(nblocks(cnt, 256)), dim3(256), 0, h.stream,
+                         (const double2 *)data, h.g32.gin, cnt);
+      PSE_LAUNCH_CHECK();
+      fft3d<float>(h, h.g32.gin, h.g32.twiddle, ncomp, direction);
+      hipLaunchKernelGGL(f2d_kernel, dim3(nblocks(cnt, 256)), dim3(256), 0, h.stream,
+                         (const float2 *)h.g32.gin, (double2 *)data, cnt);
+      PSE_LAUNCH_CHECK();
+    }
+    PSE_HIP(hipStreamSynchronize(h.stream));
+  });
+}
+
+int pse_spread(pse_handle *hd, const double *x, const double *q, int ncomp, double *out) {
+  if (!hd) return PSE_ERR_INVALID;
+  if (!x || !q || !out || ncomp < 1 || ncomp > NC) {
+    hd->h.err = "pse_spread: bad arguments";
+    return PSE_ERR_INVALID;
+  }
+  return guarded(hd, [&] {
+    Handle &h = hd->h;
+    prepare_positions(h, x, h.xw);
+    const CompSet cs = comps_range(0, ncomp);
+    const int np = (ncomp + 1) / 2;
+    if (h.mixed) {
+      zero_grids<float>(h, h.g32.gin, np);
+      spread<float>(h, h.xw, q, ncomp, cs, h.g32.gin);
+      packed_to_real<float>(h, h.g32.gin, ncomp, out);
+    } else {
+      zero_grids<double>(h, h.g64.gin, np);
+      spread<double>(h, h.xw, q, ncomp, cs, h.g64.gin);
+      packed_to_real<double>(h, h.g64.gin, ncomp, out);
+    }
+    PSE_HIP(hipStreamSynchronize(h.stream));
+  });
+}
+
+int pse_interpolate(pse_handle *hd, const double *x, const double *g, int ncomp,
+                    double *out) {
+  if (!hd) return PSE_ERR_INVALID;
+  if (!x || !g || !out || ncomp < 1 || ncomp > NC) {
+    hd->h.err = "pse_interpolate: bad arguments";
+    return PSE_ERR_INVALID;
+  }
+  return guarded(hd, [&] {
+    Handle &h = hd->h;
+    prepare_positions(h, x, h.xw);
+    const CompSet cs = comps_range(0, ncomp);
+    if (h.mixed) {
+      real_to_packed<float>(h, g, ncomp, h.g32.gout);
+      interpolate<float>(h, h.xw, h.g32.gout, cs, out, ncomp, false, 1.0);
+    } else {
+      real_to_packed<double>(h, g, ncomp, h.g64.gout);
+      interpolate<double>(h, h.xw, h.g64.gout, cs, out, ncomp, false, 1.0);
+    }
+    PSE_HIP(hipStreamSynchronize(h.stream));
+  });
+}
+
+}  // extern "C"

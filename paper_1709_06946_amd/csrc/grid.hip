@@ -1,0 +1,590 @@
+// Wave-space stages of the NUFFT mobility (Sec. II.C, Eq. WSops2) and of the
+// wave-space square root (Sec. III.C, Eq. FFTsqrt).
+//
+// Grids: the G real component grids of one operator application are packed
+// two per complex grid (component 2p in the real part of packed grid p,
+// component 2p+1 in the imaginary part), so every transform is a plain
+// complex FFT and a real grid pair costs one complex transform.  The k-space
+// kernels separate the pair with the Hermitian symmetry of real-grid spectra:
+//   G_2p(k) = (Z(k) + conj Z(-k)) / 2,  G_2p+1(k) = (Z(k) - conj Z(-k)) / 2i.
+//
+// Gaussian kernel (Sec. II.C): K(r) = (2 xi^2/(pi eta_s))^(3/2)
+// exp(-2 xi^2 r^2 / eta_s), truncated to the P^3 nearest grid points, whose
+// Fourier transform is exp(-eta_s k^2 / 8 xi^2).  Spreading and
+// interpolation each contribute that factor once; the k-space scaling
+// divides both out again.
+#include "pse_internal.h"
+
+namespace pse {
+
+// ---------------------------------------------------------------- helpers --
+
+__device__ __forceinline__ int wrapi(int i, int n) {
+  i %= n;
+  return i < 0 ? i + n : i;
+}
+
+// First stencil index and the grid offset of a particle coordinate.
+__device__ __forceinline__ int stencil_start(double xc, double h, int P) {
+  const double f = xc / h;
+  return (P & 1) ? (int)floor(f + 0.5) - (P - 1) / 2 : (int)floor(f) - P / 2 + 1;
+}
+
+template <typename T> __device__ __forceinline__ T &part(cplx<T> &z, int k) {
+  return (k & 1) ? z.y : z.x;
+}
+
+// ------------------------------------------------------------- spreading --
+
+// One wavefront per particle; its lanes cover the P^3 stencil.
+template <typename T>
+__global__ void __launch_bounds__(256)
+spread_kernel(const double *__restrict__ x, const double *__restrict__ q,
+              int qstride, CompSet cs, GridGeom g, const int *__restrict__ order,
+              int64_t n, cplx<T> *__restrict__ grids, size_t ngrid) {
+  const int lane = threadIdx.x & 63;
+  const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (t >= n) return;
+  const int64_t p = order ? order[t] : t;
+  const double px = x[3 * p], py = x[3 * p + 1], pz = x[3 * p + 2];
+  const int P = g.P, P3 = P * P * P;
+  const int ix0 = stencil_start(px, g.h, P);
+  const int iy0 = stencil_start(py, g.h, P);
+  const int iz0 = stencil_start(pz, g.h, P);
+  T qv[NC];
+#pragma unroll
+  for (int k = 0; k < NC; ++k) qv[k] = k < cs.n ? (T)q[p * qstride + cs.idx[k]] : (T)0;
+  const double kn3 = g.knorm * g.knorm * g.knorm;
+  for (int s = lane; s < P3; s += 64) {
+    const int a = s % P, b = (s / P) % P, c = s / (P * P);
+    const double dx = (ix0 + a) * g.h - px;
+    const double dy = (iy0 + b) * g.h - py;
+    const double dz = (iz0 + c) * g.h - pz;
+    const T w = (T)(kn3 * exp(-g.kcoef * (dx * dx + dy * dy + dz * dz)));
+    const size_t gi = ((size_t)wrapi(iz0 + c, g.ng) * g.ng + wrapi(iy0 + b, g.ng)) * g.ng
+                      + wrapi(ix0 + a, g.ng);
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+      if (k < cs.n) {
+        cplx<T> *cell = grids + (size_t)(k >> 1) * ngrid + gi;
+        atomicAdd((k & 1) ? &cell->y : &cell->x, w * qv[k]);
+      }
+    }
+  }
+}
+
+// --------------------------------------------------------- interpolation --
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+interp_kernel(const double *__restrict__ x, const cplx<T> *__restrict__ grids,
+              size_t ngrid, CompSet cs, GridGeom g, const int *__restrict__ order,
+              int64_t n, double *__restrict__ out, int ostride, int accumulate,
+              double scale) {
+  const int lane = threadIdx.x & 63;
+  const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (t >= n) return;
+  const int64_t p = order ? order[t] : t;
+  const double px = x[3 * p], py = x[3 * p + 1], pz = x[3 * p + 2];
+  const int P = g.P, P3 = P * P * P;
+  const int ix0 = stencil_start(px, g.h, P);
+  const int iy0 = stencil_start(py, g.h, P);
+  const int iz0 = stencil_start(pz, g.h, P);
+  T acc[NC];
+#pragma unroll
+  for (int k = 0; k < NC; ++k) acc[k] = (T)0;
+  const double kn3 = g.knorm * g.knorm * g.knorm;
+  for (int s = lane; s < P3; s += 64) {
+    const int a = s % P, b = (s / P) % P, c = s / (P * P);
+    const double dx = (ix0 + a) * g.h - px;
+    const double dy = (iy0 + b) * g.h - py;
+    const double dz = (iz0 + c) * g.h - pz;
+    const T w = (T)(kn3 * exp(-g.kcoef * (dx * dx + dy * dy + dz * dz)));
+    const size_t gi = ((size_t)wrapi(iz0 + c, g.ng) * g.ng + wrapi(iy0 + b, g.ng)) * g.ng
+                      + wrapi(ix0 + a, g.ng);
+#pragma unroll
+    for (int k = 0; k < NC; k += 2) {
+      if (k < cs.n) {
+        const cplx<T> z = grids[(size_t)(k >> 1) * ngrid + gi];
+        acc[k] += w * z.x;
+        if (k + 1 < NC) acc[k + 1] += w * z.y;
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    if (k < cs.n) {
+      T v = acc[k];
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+      acc[k] = v;
+    }
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+      if (k < cs.n) {
+        double *o = out + p * ostride + cs.idx[k];
+        const double v = scale * (double)acc[k];
+        *o = accumulate ? *o + v : v;
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------ k-space kernels --
+
+// Wave vector of grid index i (FFT order).
+__device__ __forceinline__ int kidx(int i, int n) { return i < n / 2 ? i : i - n; }
+
+// Shape factors j0(x) = sin x / x and f1(x) = (sin x - x cos x)/x^3
+// (Eq. WSops); series below x = 0.1 where the closed form cancels.
+__device__ __forceinline__ void shape_factors(double x, double &j0, double &f1) {
+  if (x < 0.1) {
+    const double x2 = x * x;
+    j0 = 1.0 - x2 / 6.0 * (1.0 - x2 / 20.0 * (1.0 - x2 / 42.0));
+    f1 = 1.0 / 3.0 - x2 / 30.0 * (1.0 - x2 / 28.0 * (1.0 - x2 / 54.0));
+  } else {
+    double s, c;
+    sincos(x, &s, &c);
+    j0 = s / x;
+    f1 = (s - x * c) / (x * x * x);
+  }
+}
+
+// The canonical member of each pair {k, -k} handled by one thread, and which
+// modes are zeroed (Nyquist index in any direction, or k = 0).  Threads run
+// over ix in [0, n/2], all iy, iz.  Returns 0 = skip, 1 = zero the mode (and
+// nothing else), 2 = process the pair.
+__device__ __forceinline__ int classify(int ix, int iy, int iz, int n) {
+  const int h = n / 2;
+  if (ix == h || iy == h || iz == h) return 1;
+  if (ix > 0) return 2;
+  // ix == 0: the partner also has ix == 0
+  if (iy > 0 && iy < h) return 2;
+  if (iy == 0 && iz > 0 && iz < h) return 2;
+  if (iy == 0 && iz == 0) return 1;
+  return 0;  // handled by the partner
+}
+
+struct KGeom {
+  int ng;
+  double twopi_L;     // 2 pi / L
+  double a;
+  double inv4xi2;     // 1 / (4 xi^2)
+  double one_m_etas;  // 1 - eta_s
+  double pref;        // mobility: h^6 / (V eta); noise: h^3 / sqrt(V eta)
+};
+
+// P(k) q for one particle-moment component index c (0..10) and value g.
+template <typename C>
+__device__ __forceinline__ void add_P(int c, C gv, const double *kv, double j0,
+                                      double f1, C *rho) {
+  // rho += P_c g: F: j0 e_c; L: (3i/2) f1 (k x e_c); s_q: -3i f1 Y_q k.
+  if (c < 3) {
+    rho[c].x += j0 * gv.x;
+    rho[c].y += j0 * gv.y;
+    return;
+  }
+  double col[3] = {0.0, 0.0, 0.0};
+  double coef;
+  if (c < 6) {
+    const int l = c - 3;          // (k x e_l)_m = eps_mnl k_n
+    const int l1 = (l + 1) % 3, l2 = (l + 2) % 3;
+    col[l1] = kv[l2];
+    col[l2] = -kv[l1];
+    coef = 1.5 * f1;              // times +i
+  } else {
+    const double r2 = 0.70710678118654752440, r6 = 0.40824829046386301637;
+    switch (c - 6) {
+      case 0: col[0] = r2 * kv[1]; col[1] = r2 * kv[0]; break;
+      case 1: col[0] = r2 * kv[2]; col[2] = r2 * kv[0]; break;
+      case 2: col[1] = r2 * kv[2]; col[2] = r2 * kv[1]; break;
+      case 3: col[0] = r2 * kv[0]; col[1] = -r2 * kv[1]; break;
+      default: col[0] = r6 * kv[0]; col[1] = r6 * kv[1]; col[2] = -2.0 * r6 * kv[2]; break;
+    }
+    coef = -3.0 * f1;             // times +i
+  }
+  // rho_m += i coef col_m g  ->  (i g) = (-g.y, g.x)
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    const double s = coef * col[m];
+    rho[m].x += -s * gv.y;
+    rho[m].y += s * gv.x;
+  }
+}
+
+// W_c = P_c^+ u for output component c.
+template <typename C>
+__device__ __forceinline__ C apply_Pdag(int c, const C *u, const double *kv,
+                                        double j0, double f1) {
+  C w;
+  if (c < 3) {
+    w.x = j0 * u[c].x;
+    w.y = j0 * u[c].y;
+    return w;
+  }
+  double re = 0.0, im = 0.0, coef;
+  if (c < 6) {
+    // Omega = (3i/2) f1 (k x u)
+    const int l = c - 3, l1 = (l + 1) % 3, l2 = (l + 2) % 3;
+    re = kv[l1] * u[l2].x - kv[l2] * u[l1].x;
+    im = kv[l1] * u[l2].y - kv[l2] * u[l1].y;
+    coef = 1.5 * f1;
+  } else {
+    // e_q = 3i f1 (Y_q k) . u
+    const double r2 = 0.70710678118654752440, r6 = 0.40824829046386301637;
+    double col[3] = {0.0, 0.0, 0.0};
+    switch (c - 6) {
+      case 0: col[0] = r2 * kv[1]; col[1] = r2 * kv[0]; break;
+      case 1: col[0] = r2 * kv[2]; col[2] = r2 * kv[0]; break;
+      case 2: col[1] = r2 * kv[2]; col[2] = r2 * kv[1]; break;
+      case 3: col[0] = r2 * kv[0]; col[1] = -r2 * kv[1]; break;
+      default: col[0] = r6 * kv[0]; col[1] = r6 * kv[1]; col[2] = -2.0 * r6 * kv[2]; break;
+    }
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      re += col[m] * u[m].x;
+      im += col[m] * u[m].y;
+    }
+    coef = 3.0 * f1;
+  }
+  // i coef (re + i im)
+  w.x = -coef * im;
+  w.y = coef * re;
+  return w;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+kspace_mobility_kernel(const cplx<T> *__restrict__ in, CompSet cin,
+                       cplx<T> *__restrict__ out, CompSet cout, KGeom kg) {
+  using C = cplx<T>;
+  const int n = kg.ng, hx = n / 2 + 1;
+  const size_t total = (size_t)hx * n * n;
+  const size_t tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= total) return;
+  const int ix = (int)(tid % hx);
+  const int iy = (int)((tid / hx) % n);
+  const int iz = (int)(tid / ((size_t)hx * n));
+  const int cls = classify(ix, iy, iz, n);
+  if (cls == 0) return;
+  const size_t ngrid = (size_t)n * n * n;
+  const size_t kp = ((size_t)iz * n + iy) * n + ix;
+  const size_t km = ((size_t)((n - iz) % n) * n + (n - iy) % n) * n + (n - ix) % n;
+  const int npo = (cout.n + 1) / 2;
+  if (cls == 1) {
+    for (int q = 0; q < npo; ++q) {
+      out[q * ngrid + kp] = C{(T)0, (T)0};
+      out[q * ngrid + km] = C{(T)0, (T)0};
+    }
+    return;
+  }
+  const double kv[3] = {kg.twopi_L * kidx(ix, n), kg.twopi_L * kidx(iy, n),
+                        kg.twopi_L * kidx(iz, n)};
+  const double k2 = kv[0] * kv[0] + kv[1] * kv[1] + kv[2] * kv[2];
+  const double kk = sqrt(k2);
+  double j0, f1;
+  shape_factors(kk * kg.a, j0, f1);
+  double2 rho[3] = {{0, 0}, {0, 0}, {0, 0}};
+  const int npi = (cin.n + 1) / 2;
+  for (int p = 0; p < npi; ++p) {
+    const C zp = in[p * ngrid + kp], zm = in[p * ngrid + km];
+    // G_2p = (Z(k) + conj Z(-k)) / 2 ; G_2p+1 = (Z(k) - conj Z(-k)) / 2i
+    double2 ga{0.5 * ((double)zp.x + zm.x), 0.5 * ((double)zp.y - zm.y)};
+    add_P(cin.idx[2 * p], ga, kv, j0, f1, rho);
+    if (2 * p + 1 < cin.n) {
+      const double dre = (double)zp.x - zm.x, dim = (double)zp.y + zm.y;
+      double2 gb{0.5 * dim, -0.5 * dre};
+      add_P(cin.idx[2 * p + 1], gb, kv, j0, f1, rho);
+    }
+  }
+  // u = scale (I - kk) rho
+  const double u = k2 * kg.inv4xi2;
+  const double scale = kg.pref * (1.0 + u) * exp(-kg.one_m_etas * u) / k2;
+  double2 kr{0, 0};
+  for (int m = 0; m < 3; ++m) {
+    kr.x += kv[m] * rho[m].x;
+    kr.y += kv[m] * rho[m].y;
+  }
+  double2 uu[3];
+  for (int m = 0; m < 3; ++m) {
+    uu[m].x = scale * (rho[m].x - kv[m] * kr.x / k2);
+    uu[m].y = scale * (rho[m].y - kv[m] * kr.y / k2);
+  }
+  for (int q = 0; q < npo; ++q) {
+    const double2 wa = apply_Pdag(cout.idx[2 * q], uu, kv, j0, f1);
+    double2 wb{0, 0};
+    if (2 * q + 1 < cout.n) wb = apply_Pdag(cout.idx[2 * q + 1], uu, kv, j0, f1);
+    // Z(k) = Wa + i Wb ; Z(-k) = conj(Wa) + i conj(Wb)
+    out[q * ngrid + kp] = C{(T)(wa.x - wb.y), (T)(wa.y + wb.x)};
+    out[q * ngrid + km] = C{(T)(wa.x + wb.y), (T)(-wa.y + wb.x)};
+  }
+}
+
+// ----------------------------------------------------- Philox4x32-10 RNG --
+// Counter-based generator of Salmon, Moraes, Dror & Shaw (SC'11), written
+// from its published definition.
+
+struct u4 { uint32_t x, y, z, w; };
+
+__device__ __forceinline__ u4 philox4x32_10(u4 c, uint32_t k0, uint32_t k1) {
+  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+  const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = (uint64_t)M0 * c.x, p1 = (uint64_t)M1 * c.z;
+    const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    c = u4{hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
+    k0 += W0;
+    k1 += W1;
+  }
+  return c;
+}
+
+// Four standard normals from one Philox block (Box-Muller).
+__device__ __forceinline__ void normals4(u4 r, double *z) {
+  const double s = 2.3283064365386963e-10;  // 2^-32
+  const double u1 = ((double)r.x + 0.5) * s, u2 = ((double)r.y + 0.5) * s;
+  const double u3 = ((double)r.z + 0.5) * s, u4v = ((double)r.w + 0.5) * s;
+  const double ra = sqrt(-2.0 * log(u1)), rb = sqrt(-2.0 * log(u3));
+  double sa, ca, sb, cb;
+  sincospi(2.0 * u2, &sa, &ca);
+  sincospi(2.0 * u4v, &sb, &cb);
+  z[0] = ra * ca; z[1] = ra * sa; z[2] = rb * cb; z[3] = rb * sb;
+}
+
+__device__ __forceinline__ void philox_normals(uint64_t seed, uint64_t counter,
+                                               uint32_t stream, uint32_t index,
+                                               int nblk, double *z) {
+  for (int b = 0; b < nblk; ++b) {
+    u4 c{index, stream * 16u + (uint32_t)b, (uint32_t)counter, (uint32_t)(counter >> 32)};
+    normals4(philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32)), z + 4 * b);
+  }
+}
+
+enum : uint32_t { STREAM_REAL = 1, STREAM_WAVE = 2 };
+
+// Wave-space square root (Eq. FFTsqrt): for each canonical k,
+//   u(k) = h^3 / sqrt(V eta) sqrt(1 + k^2/4xi^2) exp(-(1 - eta_s) k^2/8xi^2) / k
+//          (I - kk) psi(k),
+//   W_c(k) = P_c^+(k) u(k),  W_c(-k) = conj W_c(k).
+template <typename T>
+__global__ void __launch_bounds__(256)
+kspace_noise_kernel(const double2 *__restrict__ psi, uint64_t seed,
+                    uint64_t counter, cplx<T> *__restrict__ out, CompSet cout,
+                    KGeom kg) {
+  using C = cplx<T>;
+  const int n = kg.ng, hx = n / 2 + 1;
+  const size_t total = (size_t)hx * n * n;
+  const size_t tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= total) return;
+  const int ix = (int)(tid % hx);
+  const int iy = (int)((tid / hx) % n);
+  const int iz = (int)(tid / ((size_t)hx * n));
+  const int cls = classify(ix, iy, iz, n);
+  if (cls == 0) return;
+  const size_t ngrid = (size_t)n * n * n;
+  const size_t kp = ((size_t)iz * n + iy) * n + ix;
+  const size_t km = ((size_t)((n - iz) % n) * n + (n - iy) % n) * n + (n - ix) % n;
+  const int npo = (cout.n + 1) / 2;
+  if (cls == 1) {
+    for (int q = 0; q < npo; ++q) {
+      out[q * ngrid + kp] = C{(T)0, (T)0};
+      out[q * ngrid + km] = C{(T)0, (T)0};
+    }
+    return;
+  }
+  double2 ps[3];
+  if (psi) {
+    const size_t hsz = (size_t)n * n * hx;
+    for (int m = 0; m < 3; ++m) ps[m] = psi[m * hsz + tid];
+  } else {
+    double z[8];
+    philox_normals(seed, counter, STREAM_WAVE, (uint32_t)tid, 2, z);
+    const double s = 0.70710678118654752440;
+    for (int m = 0; m < 3; ++m) ps[m] = double2{s * z[2 * m], s * z[2 * m + 1]};
+  }
+  const double kv[3] = {kg.twopi_L * kidx(ix, n), kg.twopi_L * kidx(iy, n),
+                        kg.twopi_L * kidx(iz, n)};
+  const double k2 = kv[0] * kv[0] + kv[1] * kv[1] + kv[2] * kv[2];
+  const double kk = sqrt(k2);
+  double j0, f1;
+  shape_factors(kk * kg.a, j0, f1);
+  const double u = k2 * kg.inv4xi2;
+  const double amp = kg.pref * sqrt(1.0 + u) * exp(-0.5 * kg.one_m_etas * u) / kk;
+  double2 kr{0, 0};
+  for (int m = 0; m < 3; ++m) {
+    kr.x += kv[m] * ps[m].x;
+    kr.y += kv[m] * ps[m].y;
+  }
+  double2 uu[3];
+  for (int m = 0; m < 3; ++m) {
+    uu[m].x = amp * (ps[m].x - kv[m] * kr.x / k2);
+    uu[m].y = amp * (ps[m].y - kv[m] * kr.y / k2);
+  }
+  for (int q = 0; q < npo; ++q) {
+    const double2 wa = apply_Pdag(cout.idx[2 * q], uu, kv, j0, f1);
+    double2 wb{0, 0};
+    if (2 * q + 1 < cout.n) wb = apply_Pdag(cout.idx[2 * q + 1], uu, kv, j0, f1);
+    out[q * ngrid + kp] = C{(T)(wa.x - wb.y), (T)(wa.y + wb.x)};
+    out[q * ngrid + km] = C{(T)(wa.x + wb.y), (T)(-wa.y + wb.x)};
+  }
+}
+
+// Real-space noise psi1 ~ N(0, I), 11 per particle, from Philox.
+__global__ void real_noise_kernel(uint64_t seed, uint64_t counter, int64_t n,
+                                  double *__restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double z[12];
+  philox_normals(seed, counter, STREAM_REAL, (uint32_t)i, 3, z);
+  for (int c = 0; c < NC; ++c) out[i * NC + c] = z[c];
+}
+
+// --------------------------------------------------------- small kernels --
+
+template <typename T>
+__global__ void zero_kernel(cplx<T> *g, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) g[i] = cplx<T>{(T)0, (T)0};
+}
+
+template <typename T>
+__global__ void real_to_packed_kernel(const double *src, int ncomp, size_t ngrid,
+                                      cplx<T> *dst) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ngrid) return;
+  for (int c = 0; c < ncomp; c += 2) {
+    cplx<T> z;
+    z.x = (T)src[c * ngrid + i];
+    z.y = c + 1 < ncomp ? (T)src[(c + 1) * ngrid + i] : (T)0;
+    dst[(c / 2) * ngrid + i] = z;
+  }
+}
+
+template <typename T>
+__global__ void packed_to_real_kernel(const cplx<T> *src, int ncomp, size_t ngrid,
+                                      double *dst) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ngrid) return;
+  for (int c = 0; c < ncomp; c += 2) {
+    const cplx<T> z = src[(c / 2) * ngrid + i];
+    dst[c * ngrid + i] = z.x;
+    if (c + 1 < ncomp) dst[(c + 1) * ngrid + i] = z.y;
+  }
+}
+
+// ----------------------------------------------------------- host side --
+
+static GridGeom geom(const Handle &h) {
+  GridGeom g;
+  g.ng = h.d.grid;
+  g.P = h.d.support;
+  g.L = h.p.box;
+  g.h = h.d.h;
+  const double xi2 = h.d.xi * h.d.xi;
+  g.kcoef = 2.0 * xi2 / h.d.eta_s;
+  g.knorm = sqrt(2.0 * xi2 / (M_PI * h.d.eta_s));
+  return g;
+}
+
+static KGeom kgeom(const Handle &h, bool noise) {
+  KGeom k;
+  k.ng = h.d.grid;
+  k.twopi_L = 2.0 * M_PI / h.p.box;
+  k.a = h.p.radius;
+  k.inv4xi2 = 1.0 / (4.0 * h.d.xi * h.d.xi);
+  k.one_m_etas = 1.0 - h.d.eta_s;
+  const double V = h.p.box * h.p.box * h.p.box;
+  const double h3 = h.d.h * h.d.h * h.d.h;
+  k.pref = noise ? h3 / sqrt(V * h.p.viscosity) : h3 * h3 / (V * h.p.viscosity);
+  return k;
+}
+
+template <typename T>
+void spread(Handle &h, const double *x, const double *q, int qstride,
+            const CompSet &cs, cplx<T> *grids) {
+  const GridGeom g = geom(h);
+  hipLaunchKernelGGL(spread_kernel<T>, dim3(nblocks(h.n, 4)), dim3(256), 0,
+                     h.stream, x, q, qstride, cs, g, (const int *)h.perm, h.n,
+                     grids, h.ngrid);
+  PSE_LAUNCH_CHECK();
+}
+
+template <typename T>
+void interpolate(Handle &h, const double *x, const cplx<T> *grids,
+                 const CompSet &cs, double *out, int ostride, bool accumulate,
+                 double scale) {
+  const GridGeom g = geom(h);
+  hipLaunchKernelGGL(interp_kernel<T>, dim3(nblocks(h.n, 4)), dim3(256), 0,
+                     h.stream, x, grids, h.ngrid, cs, g, (const int *)h.perm,
+                     h.n, out, ostride, accumulate ? 1 : 0, scale);
+  PSE_LAUNCH_CHECK();
+}
+
+template <typename T>
+void kspace_mobility(Handle &h, const cplx<T> *in, const CompSet &cin,
+                     cplx<T> *out, const CompSet &cout) {
+  const int n = h.d.grid;
+  const size_t total = (size_t)(n / 2 + 1) * n * n;
+  hipLaunchKernelGGL(kspace_mobility_kernel<T>, dim3(nblocks(total, 256)),
+                     dim3(256), 0, h.stream, in, cin, out, cout, kgeom(h, false));
+  PSE_LAUNCH_CHECK();
+}
+
+template <typename T>
+void kspace_noise(Handle &h, const double *psi, uint64_t seed, uint64_t counter,
+                  cplx<T> *out, const CompSet &cout) {
+  const int n = h.d.grid;
+  const size_t total = (size_t)(n / 2 + 1) * n * n;
+  hipLaunchKernelGGL(kspace_noise_kernel<T>, dim3(nblocks(total, 256)), dim3(256),
+                     0, h.stream, (const double2 *)psi, seed, counter, out, cout,
+                     kgeom(h, true));
+  PSE_LAUNCH_CHECK();
+}
+
+void real_noise(Handle &h, uint64_t seed, uint64_t counter, double *out) {
+  hipLaunchKernelGGL(real_noise_kernel, dim3(nblocks(h.n, 256)), dim3(256), 0,
+                     h.stream, seed, counter, h.n, out);
+  PSE_LAUNCH_CHECK();
+}
+
+template <typename T> void zero_grids(Handle &h, cplx<T> *g, int npack) {
+  const size_t n = (size_t)npack * h.ngrid;
+  hipLaunchKernelGGL(zero_kernel<T>, dim3(nblocks(n, 256)), dim3(256), 0, h.stream,
+                     g, n);
+  PSE_LAUNCH_CHECK();
+}
+
+template <typename T>
+void real_to_packed(Handle &h, const double *src, int ncomp, cplx<T> *dst) {
+  hipLaunchKernelGGL(real_to_packed_kernel<T>, dim3(nblocks(h.ngrid, 256)),
+                     dim3(256), 0, h.stream, src, ncomp, h.ngrid, dst);
+  PSE_LAUNCH_CHECK();
+}
+
+template <typename T>
+void packed_to_real(Handle &h, const cplx<T> *src, int ncomp, double *dst) {
+  hipLaunchKernelGGL(packed_to_real_kernel<T>, dim3(nblocks(h.ngrid, 256)),
+                     dim3(256), 0, h.stream, src, ncomp, h.ngrid, dst);
+  PSE_LAUNCH_CHECK();
+}
+
+#define INST(T)                                                                 \
+  template void spread<T>(Handle &, const double *, const double *, int,         \
+                          const CompSet &, cplx<T> *);                           \
+  template void interpolate<T>(Handle &, const double *, const cplx<T> *,        \
+                               const CompSet &, double *, int, bool, double);    \
+  template void kspace_mobility<T>(Handle &, const cplx<T> *, const CompSet &,   \
+                                   cplx<T> *, const CompSet &);                  \
+  template void kspace_noise<T>(Handle &, const double *, uint64_t, uint64_t,    \
+                                cplx<T> *, const CompSet &);                     \
+  template void zero_grids<T>(Handle &, cplx<T> *, int);                         \
+  template void real_to_packed<T>(Handle &, const double *, int, cplx<T> *);     \
+  template void packed_to_real<T>(Handle &, const cplx<T> *, int, double *);
+INST(double)
+INST(float)
+#undef INST
+
+}  // namespace pse

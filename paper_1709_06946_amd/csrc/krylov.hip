@@ -1,0 +1,511 @@
+// FP64 vector kernels and small dense solvers of the Krylov iterations:
+// the Lanczos square root of M_r (Sec. III.B, Chow & Saad) and GMRES on the
+// stresslet constraint M_ES S = b (Eq. rigidconstraint).  All scalars stay
+// on the device; the host only reads a few numbers back per iteration to
+// decide when to stop.
+#include <cmath>
+
+#include "pse_internal.h"
+
+namespace pse {
+
+constexpr int RED_BLOCKS = 1024;   // partial-sum blocks of a reduction
+
+__global__ void zero_kernel_d(double *v, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) v[i] = 0.0;
+}
+
+__global__ void copy_kernel_d(double *dst, const double *src, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
+__global__ void axpby_kernel(double a, const double *x, double b, double *y, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = a * x[i] + b * y[i];
+}
+
+// partial[j * nb + blk] = sum over the block's share of V_j . w
+__global__ void __launch_bounds__(256)
+multi_dot_partial(const double *__restrict__ V, size_t ldv, const double *__restrict__ w,
+                  size_t n, double *__restrict__ partial) {
+  __shared__ double s[256];
+  const int j = blockIdx.y;
+  const double *v = V + (size_t)j * ldv;
+  double acc = 0.0;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
+    acc += v[i] * w[i];
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[(size_t)j * gridDim.x + blockIdx.x] = s[0];
+}
+
+__global__ void __launch_bounds__(256)
+reduce_partial(const double *__restrict__ partial, int nb, double *__restrict__ out) {
+  __shared__ double s[256];
+  const int j = blockIdx.x;
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < nb; b += 256) acc += partial[(size_t)j * nb + b];
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[j] = s[0];
+}
+
+// w -= sum_j coef_j V_j
+__global__ void sub_multi_kernel(double *__restrict__ w, const double *__restrict__ V,
+                                 size_t ldv, int m, const double *__restrict__ coef,
+                                 size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double acc = 0.0;
+  for (int j = 0; j < m; ++j) acc += coef[j] * V[(size_t)j * ldv + i];
+  w[i] -= acc;
+}
+
+// y = (acc ? y : 0) + alpha sum_j coef_j V_j
+__global__ void gemv_small_kernel(const double *__restrict__ V, size_t ldv, int m,
+                                  const double *__restrict__ coef, double *__restrict__ y,
+                                  size_t n, double alpha, int accumulate) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double acc = 0.0;
+  for (int j = 0; j < m; ++j) acc += coef[j] * V[(size_t)j * ldv + i];
+  y[i] = (accumulate ? y[i] : 0.0) + alpha * acc;
+}
+
+// dst = src * s or src / s with s a device scalar (dst may equal src)
+__global__ void scale_dev_kernel(double *dst, const double *src, const double *s,
+                                 int invert, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double f = invert ? (*s != 0.0 ? 1.0 / *s : 0.0) : *s;
+  dst[i] = src[i] * f;
+}
+
+__global__ void gather_kernel(const double *__restrict__ src, int sstride, CompSet cs,
+                              double *__restrict__ dst, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int k = 0; k < cs.n; ++k) dst[i * cs.n + k] = src[i * sstride + cs.idx[k]];
+}
+
+__global__ void scatter_kernel(const double *__restrict__ src, CompSet cs,
+                               double *__restrict__ dst, int dstride, size_t n,
+                               int accumulate, double alpha) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int k = 0; k < cs.n; ++k) {
+    double *o = dst + i * dstride + cs.idx[k];
+    const double v = alpha * src[i * cs.n + k];
+    *o = accumulate ? *o + v : v;
+  }
+}
+
+__global__ void finite_kernel(const double *v, size_t n, int *flag) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && !isfinite(v[i])) atomicOr(flag, 1);
+}
+
+// ------------------------------------------------------------ host glue --
+
+void vzero(Handle &h, double *v, size_t n) {
+  hipLaunchKernelGGL(zero_kernel_d, dim3(nblocks(n, 256)), dim3(256), 0, h.stream, v, n);
+  PSE_LAUNCH_CHECK();
+}
+void vcopy(Handle &h, double *dst, const double *src, size_t n) {
+  hipLaunchKernelGGL(copy_kernel_d, dim3(nblocks(n, 256)), dim3(256), 0, h.stream, dst,
+                     src, n);
+  PSE_LAUNCH_CHECK();
+}
+void vaxpby(Handle &h, double a, const double *x, double b, double *y, size_t n) {
+  hipLaunchKernelGGL(axpby_kernel, dim3(nblocks(n, 256)), dim3(256), 0, h.stream, a, x,
+                     b, y, n);
+  PSE_LAUNCH_CHECK();
+}
+
+void multi_dot(Handle &h, const double *V, size_t ldv, int m, const double *w,
+               size_t n, double *dev_out) {
+  int nb = (int)std::min<size_t>(RED_BLOCKS, (n + 255) / 256);
+  if (nb < 1) nb = 1;
+  if ((size_t)nb * m > h.dots_len) throw Error{PSE_ERR_INVALID, "reduction scratch too small"};
+  hipLaunchKernelGGL(multi_dot_partial, dim3(nb, m), dim3(256), 0, h.stream, V, ldv, w, n,
+                     h.dots);
+  PSE_LAUNCH_CHECK();
+  hipLaunchKernelGGL(reduce_partial, dim3(m), dim3(256), 0, h.stream, h.dots, nb, dev_out);
+  PSE_LAUNCH_CHECK();
+}
+
+void vsub_multi(Handle &h, double *w, const double *V, size_t ldv, int m,
+                const double *coef_dev, size_t n) {
+  hipLaunchKernelGGL(sub_multi_kernel, dim3(nblocks(n, 256)), dim3(256), 0, h.stream, w,
+                     V, ldv, m, coef_dev, n);
+  PSE_LAUNCH_CHECK();
+}
+
+void gemv_small(Handle &h, const double *V, size_t ldv, int m, const double *coef_dev,
+                double *y, size_t n, double alpha, bool accumulate) {
+  hipLaunchKernelGGL(gemv_small_kernel, dim3(nblocks(n, 256)), dim3(256), 0, h.stream, V,
+                     ldv, m, coef_dev, y, n, alpha, accumulate ? 1 : 0);
+  PSE_LAUNCH_CHECK();
+}
+
+void vscale_dev(Handle &h, double *dst, const double *src, const double *s_dev,
+                bool invert, size_t n) {
+  hipLaunchKernelGGL(scale_dev_kernel, dim3(nblocks(n, 256)), dim3(256), 0, h.stream,
+                     dst, src, s_dev, invert ? 1 : 0, n);
+  PSE_LAUNCH_CHECK();
+}
+
+void gather_comps(Handle &h, const double *src, int sstride, const CompSet &cs,
+                  double *dst, size_t n) {
+  hipLaunchKernelGGL(gather_kernel, dim3(nblocks(n, 256)), dim3(256), 0, h.stream, src,
+                     sstride, cs, dst, n);
+  PSE_LAUNCH_CHECK();
+}
+
+void scatter_comps(Handle &h, const double *src, const CompSet &cs, double *dst,
+                   int dstride, size_t n, bool accumulate, double alpha) {
+  hipLaunchKernelGGL(scatter_kernel, dim3(nblocks(n, 256)), dim3(256), 0, h.stream, src,
+                     cs, dst, dstride, n, accumulate ? 1 : 0, alpha);
+  PSE_LAUNCH_CHECK();
+}
+
+int check_finite(Handle &h, const double *v, size_t n) {
+  int *flag = reinterpret_cast<int *>(h.small + h.small_len - 2);
+  PSE_HIP(hipMemsetAsync(flag, 0, sizeof(int), h.stream));
+  hipLaunchKernelGGL(finite_kernel, dim3(nblocks(n, 256)), dim3(256), 0, h.stream, v, n,
+                     flag);
+  PSE_LAUNCH_CHECK();
+  int hv = 0;
+  PSE_HIP(hipMemcpyAsync(&hv, flag, sizeof(int), hipMemcpyDeviceToHost, h.stream));
+  PSE_HIP(hipStreamSynchronize(h.stream));
+  return hv;
+}
+
+// ----------------------------------------------------- small dense work --
+
+// Eigen-decomposition of the symmetric tridiagonal matrix (diag d, off-diag
+// e) by the implicit QL iteration with Wilkinson-type shifts; z accumulates
+// the eigenvectors (column k belongs to eigenvalue d[k]).  m <= ldz.
+__device__ void tridiag_ql(double *d, double *e, double *z, int m, int ldz) {
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < m; ++j) z[i * ldz + j] = (i == j) ? 1.0 : 0.0;
+  if (m == 1) return;
+  e[m - 1] = 0.0;
+  for (int l = 0; l < m; ++l) {
+    for (int iter = 0; iter < 60; ++iter) {
+      int mm = l;
+      for (; mm < m - 1; ++mm) {
+        const double dd = fabs(d[mm]) + fabs(d[mm + 1]);
+        if (fabs(e[mm]) <= 1e-16 * dd) break;
+      }
+      if (mm == l) break;
+      double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+      double r = hypot(g, 1.0);
+      g = d[mm] - d[l] + e[l] / (g + (g >= 0 ? r : -r));
+      double s = 1.0, c = 1.0, p = 0.0;
+      int i = mm - 1;
+      for (; i >= l; --i) {
+        double f = s * e[i], b = c * e[i];
+        r = hypot(f, g);
+        e[i + 1] = r;
+        if (r == 0.0) {
+          d[i + 1] -= p;
+          e[mm] = 0.0;
+          break;
+        }
+        s = f / r;
+        c = g / r;
+        g = d[i + 1] - p;
+        r = (d[i] - g) * s + 2.0 * c * b;
+        p = s * r;
+        d[i + 1] = g + p;
+        g = c * r - b;
+        for (int k = 0; k < m; ++k) {
+          f = z[k * ldz + i + 1];
+          z[k * ldz + i + 1] = s * z[k * ldz + i] + c * f;
+          z[k * ldz + i] = c * z[k * ldz + i] - s * f;
+        }
+      }
+      if (r == 0.0 && i >= l) continue;
+      d[l] -= p;
+      e[l] = g;
+      e[mm] = 0.0;
+    }
+  }
+}
+
+// coef = bnorm * f(T) e_1 with f = sqrt, T = tridiag(alpha, beta) of size m;
+// also the relative change against the previous coefficient vector
+// (zero-padded), written to out_change.
+__global__ void lanczos_sqrt_kernel(const double *alpha, const double *beta, int m,
+                                    double bnorm, double *work, int ldz, double *coef,
+                                    double *coef_prev, double *out_change) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double *d = work, *e = work + ldz, *z = work + 2 * ldz;
+  for (int i = 0; i < m; ++i) {
+    d[i] = alpha[i];
+    e[i] = i + 1 < m ? beta[i] : 0.0;
+  }
+  tridiag_ql(d, e, z, m, ldz);
+  double num = 0.0, den = 0.0;
+  for (int i = 0; i < m; ++i) {
+    double acc = 0.0;
+    for (int k = 0; k < m; ++k) {
+      const double lam = d[k] > 0.0 ? sqrt(d[k]) : 0.0;
+      acc += z[i * ldz + k] * lam * z[0 * ldz + k];
+    }
+    const double c = bnorm * acc;
+    const double prev = i < m - 1 ? coef_prev[i] : 0.0;
+    num += (c - prev) * (c - prev);
+    den += c * c;
+    coef[i] = c;
+  }
+  for (int i = 0; i < m; ++i) coef_prev[i] = coef[i];
+  out_change[0] = den > 0.0 ? sqrt(num / den) : 0.0;
+}
+
+// GMRES: apply the previous Givens rotations to Hessenberg column j, form the
+// new rotation and update g; out[0] = |g_{j+1}|.
+// H is column-major with leading dimension ldh; cs/sn/g have length >= j+2.
+__global__ void givens_kernel(double *H, int ldh, int j, double *cs, double *sn, double *g,
+                              double *out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double *col = H + (size_t)j * ldh;
+  for (int i = 0; i < j; ++i) {
+    const double t = cs[i] * col[i] + sn[i] * col[i + 1];
+    col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
+    col[i] = t;
+  }
+  const double a = col[j], b = col[j + 1];
+  const double r = hypot(a, b);
+  const double c = r > 0 ? a / r : 1.0, s = r > 0 ? b / r : 0.0;
+  cs[j] = c;
+  sn[j] = s;
+  col[j] = r;
+  col[j + 1] = 0.0;
+  g[j + 1] = -s * g[j];
+  g[j] = c * g[j];
+  out[0] = fabs(g[j + 1]);
+}
+
+// y = R^{-1} g for the k x k upper-triangular part of H.
+__global__ void backsub_kernel(const double *H, int ldh, int k, const double *g, double *y) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  for (int i = k - 1; i >= 0; --i) {
+    double s = g[i];
+    for (int j = i + 1; j < k; ++j) s -= H[(size_t)j * ldh + i] * y[j];
+    y[i] = s / H[(size_t)i * ldh + i];
+  }
+}
+
+// Hessenberg column j entries 0..j from h1 + h2 (two Gram-Schmidt passes),
+// entry j+1 = sqrt(norm2).  Also sets g[0] = beta when j == 0 is requested.
+__global__ void hess_fill_kernel(double *H, int ldh, int j, const double *h1,
+                                 const double *h2, const double *norm2, double *vnorm) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double *col = H + (size_t)j * ldh;
+  for (int i = 0; i <= j; ++i) col[i] = h1[i] + h2[i];
+  const double nn = sqrt(fmax(norm2[0], 0.0));
+  col[j + 1] = nn;
+  vnorm[0] = nn;
+}
+
+__global__ void sqrt_kernel(const double *in, double *out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) out[0] = sqrt(fmax(in[0], 0.0));
+}
+
+__global__ void set_g0_kernel(double *g, int len, const double *beta) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    for (int i = 0; i < len; ++i) g[i] = 0.0;
+    g[0] = beta[0];
+  }
+}
+
+// Lanczos tridiagonal entries from the two Gram-Schmidt passes:
+// alpha_j = h1[j] + h2[j], beta_j = sqrt(norm2).
+__global__ void lanczos_fill_kernel(double *alpha, double *beta, int j, const double *h1,
+                                    const double *h2, const double *norm2, double *vnorm) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  alpha[j] = h1[j] + h2[j];
+  const double nn = sqrt(fmax(norm2[0], 0.0));
+  beta[j] = nn;
+  vnorm[0] = nn;
+}
+
+// ---------------------------------------------------- host algorithms --
+
+static void host_read(Handle &h, const double *dev, double *host, int n) {
+  PSE_HIP(hipMemcpyAsync(host, dev, n * sizeof(double), hipMemcpyDeviceToHost, h.stream));
+  PSE_HIP(hipStreamSynchronize(h.stream));
+}
+
+static void norm2_dev(Handle &h, const double *v, size_t n, double *dev_norm2) {
+  multi_dot(h, v, n, 1, v, n, dev_norm2);
+}
+
+// Two-pass classical Gram-Schmidt of w against V[0..m-1] (leading dim n);
+// h1, h2 receive the projection coefficients of the two passes.
+static void cgs2(Handle &h, const double *V, size_t n, int m, double *w, double *h1,
+                 double *h2) {
+  multi_dot(h, V, n, m, w, n, h1);
+  vsub_multi(h, w, V, n, m, h1, n);
+  multi_dot(h, V, n, m, w, n, h2);
+  vsub_multi(h, w, V, n, m, h2, n);
+}
+
+// Lanczos approximation of y = A^(1/2) b (Chow & Saad): full
+// reorthogonalization, stop when the relative change of the iterate falls
+// below tol.  The iterate is y_m = |b| V_m f(T_m) e_1; with V_m orthonormal
+// its change is the change of the small coefficient vector.
+KrylovResult lanczos_sqrt(Handle &h, const Op &A, const double *b, size_t n, double *y,
+                          int maxit, double tol) {
+  const int M = maxit;
+  const int ldz = M + 1;
+  double *s = h.small;
+  double *alpha = s, *beta = alpha + (M + 1), *h1 = beta + (M + 1), *h2 = h1 + (M + 1);
+  double *norm2 = h2 + (M + 1), *vnorm = norm2 + 1, *bn = vnorm + 1, *change = bn + 1;
+  double *coef = change + 1, *coef_prev = coef + (M + 1), *work = coef_prev + (M + 1);
+  if ((size_t)(work - s) + (size_t)(2 + ldz) * ldz + 8 > h.small_len)
+    throw Error{PSE_ERR_INVALID, "Lanczos scratch too small"};
+  double *V = h.lz_V;
+  KrylovResult res{0, 0.0, false};
+  norm2_dev(h, b, n, norm2);
+  hipLaunchKernelGGL(sqrt_kernel, dim3(1), dim3(1), 0, h.stream, norm2, bn);
+  PSE_LAUNCH_CHECK();
+  double hb[2];
+  host_read(h, bn, hb, 1);
+  const double bnorm = hb[0];
+  if (!(bnorm > 0)) {
+    vzero(h, y, n);
+    res.converged = true;
+    return res;
+  }
+  PSE_HIP(hipMemsetAsync(coef_prev, 0, (M + 1) * sizeof(double), h.stream));
+  vscale_dev(h, V, b, bn, true, n);
+  int m = 0;
+  for (int j = 0; j < M; ++j) {
+    double *w = V + (size_t)(j + 1) * n;
+    A(V + (size_t)j * n, w);
+    cgs2(h, V, n, j + 1, w, h1, h2);
+    norm2_dev(h, w, n, norm2);
+    hipLaunchKernelGGL(lanczos_fill_kernel, dim3(1), dim3(1), 0, h.stream, alpha, beta, j,
+                       h1, h2, norm2, vnorm);
+    PSE_LAUNCH_CHECK();
+    hipLaunchKernelGGL(lanczos_sqrt_kernel, dim3(1), dim3(1), 0, h.stream, alpha, beta,
+                       j + 1, bnorm, work, ldz, coef, coef_prev, change);
+    PSE_LAUNCH_CHECK();
+    double hv[2];
+    host_read(h, change, hv, 1);
+    double vn;
+    host_read(h, vnorm, &vn, 1);
+    m = j + 1;
+    res.iters = m;
+    res.resid = hv[0];
+    if ((j > 0 && hv[0] < tol) || vn <= 1e-14 * bnorm) {
+      res.converged = true;
+      break;
+    }
+    vscale_dev(h, w, w, vnorm, true, n);
+  }
+  gemv_small(h, V, n, m, coef, y, n, 1.0, false);
+  return res;
+}
+
+// Restarted GMRES(restart) for A x = b from x = 0, stopping at relative
+// residual tol or after maxit iterations.  Modified to classical
+// Gram-Schmidt with a second pass (CGS2) so that each Arnoldi step costs two
+// fused reductions; Givens rotations on the device.
+KrylovResult gmres(Handle &h, const Op &A, const double *b, size_t n, double *x,
+                   int restart, int maxit, double tol) {
+  const int R = restart;
+  const int ldh = R + 1;
+  double *s = h.small;
+  double *H = s, *cs = H + (size_t)ldh * R, *sn = cs + (R + 1), *g = sn + (R + 1);
+  double *h1 = g + (R + 1), *h2 = h1 + (R + 1), *norm2 = h2 + (R + 1);
+  double *vnorm = norm2 + 1, *bn = vnorm + 1, *resid = bn + 1, *ycoef = resid + 1;
+  if ((size_t)(ycoef - s) + R + 8 > h.small_len)
+    throw Error{PSE_ERR_INVALID, "GMRES scratch too small"};
+  double *V = h.gm_V;
+  KrylovResult res{0, 0.0, false};
+  vzero(h, x, n);
+  norm2_dev(h, b, n, norm2);
+  hipLaunchKernelGGL(sqrt_kernel, dim3(1), dim3(1), 0, h.stream, norm2, bn);
+  PSE_LAUNCH_CHECK();
+  double bnorm;
+  host_read(h, bn, &bnorm, 1);
+  if (!(bnorm > 0)) {
+    res.converged = true;
+    return res;
+  }
+  double rel = 1.0;
+  int total = 0;
+  bool first = true;
+  while (total < maxit) {
+    // r = b - A x (x = 0 on the first cycle)
+    double *r = V;
+    if (first) {
+      vcopy(h, r, b, n);
+    } else {
+      A(x, r);
+      vaxpby(h, 1.0, b, -1.0, r, n);
+    }
+    first = false;
+    norm2_dev(h, r, n, norm2);
+    hipLaunchKernelGGL(sqrt_kernel, dim3(1), dim3(1), 0, h.stream, norm2, vnorm);
+    PSE_LAUNCH_CHECK();
+    double beta;
+    host_read(h, vnorm, &beta, 1);
+    rel = beta / bnorm;
+    if (rel < tol) {
+      res.converged = true;
+      break;
+    }
+    vscale_dev(h, r, r, vnorm, true, n);
+    hipLaunchKernelGGL(set_g0_kernel, dim3(1), dim3(1), 0, h.stream, g, R + 1, vnorm);
+    PSE_LAUNCH_CHECK();
+    int k = 0;
+    for (int j = 0; j < R && total < maxit; ++j) {
+      double *w = V + (size_t)(j + 1) * n;
+      A(V + (size_t)j * n, w);
+      cgs2(h, V, n, j + 1, w, h1, h2);
+      norm2_dev(h, w, n, norm2);
+      hipLaunchKernelGGL(hess_fill_kernel, dim3(1), dim3(1), 0, h.stream, H, ldh, j, h1,
+                         h2, norm2, vnorm);
+      PSE_LAUNCH_CHECK();
+      hipLaunchKernelGGL(givens_kernel, dim3(1), dim3(1), 0, h.stream, H, ldh, j, cs, sn, g,
+                         resid);
+      PSE_LAUNCH_CHECK();
+      double hr[2];
+      host_read(h, resid, hr, 1);
+      double vn;
+      host_read(h, vnorm, &vn, 1);
+      ++total;
+      k = j + 1;
+      rel = hr[0] / bnorm;
+      if (rel < tol || vn <= 1e-15 * bnorm) break;
+      vscale_dev(h, w, w, vnorm, true, n);
+    }
+    hipLaunchKernelGGL(backsub_kernel, dim3(1), dim3(1), 0, h.stream, H, ldh, k, g, ycoef);
+    PSE_LAUNCH_CHECK();
+    gemv_small(h, V, n, k, ycoef, x, n, 1.0, true);
+    if (rel < tol) {
+      res.converged = true;
+      break;
+    }
+  }
+  res.iters = total;
+  res.resid = rel;
+  return res;
+}
+
+}  // namespace pse

@@ -1,0 +1,105 @@
+// Parameter derivation and device footprint (host only, no GPU calls).
+//
+// Rules (Sec. II.C):
+//  * Eq. bound with lambda_max = 1: setting the two error terms equal with
+//    erfc(x) <= exp(-x^2) gives m = sqrt(pi P), each term exp(-pi P / 2);
+//    2 exp(-pi P/2) <= eps gives P = ceil((2/pi) ln(2/eps)).
+//  * eta_s = (h P xi / m)^2 (Gaussian shape, must be < 1 so that the
+//    remaining factor exp(-(1 - eta_s) k^2 / 4 xi^2) still decays).
+//  * xi from the grid: the Hasimoto factor exp(-k^2/4xi^2) equals eps at the
+//    Nyquist wave number pi Ng / L, i.e. xi = pi Ng / (2 L sqrt(ln(1/eps))).
+//  * Real-space cutoff: the real-space functions decay like
+//    exp(-xi^2 (r - 2a)^2) beyond contact (Appendix A), so
+//    rcut = 2a + sqrt(ln(1/eps)) / xi.
+#include <cmath>
+#include <cstdio>
+
+#include "pse_internal.h"
+
+namespace pse {
+
+static bool grid_supported(int ng) {
+  if (ng < 8 || ng > 1024 || (ng & 1)) return false;
+  int m = ng;
+  if (m % 3 == 0) m /= 3;
+  return (m & (m - 1)) == 0;
+}
+
+static int next_supported(int n) {
+  for (int g = std::max(n, 8); g <= 1024; ++g)
+    if (grid_supported(g)) return g;
+  return -1;
+}
+
+static void fail(const char *msg) { throw Error{PSE_ERR_INVALID, msg}; }
+
+void derive(const pse_params &p, pse_derived &d) {
+  if (p.n <= 0) fail("n must be positive");
+  if (!(p.radius > 0)) fail("radius must be positive");
+  if (!(p.viscosity > 0)) fail("viscosity must be positive");
+  if (!(p.kT > 0)) fail("kT must be positive");
+  if (!(p.box > 4 * p.radius)) fail("box must exceed 4 radii");
+  if (!(p.tol > 0 && p.tol <= 0.1)) fail("tol must be in (0, 0.1]");
+  if (p.precision != PSE_FP64 && p.precision != PSE_MIXED)
+    fail("precision must be PSE_FP64 or PSE_MIXED");
+  const double L = p.box, a = p.radius, eps = p.tol;
+  const double lg = std::sqrt(std::log(1.0 / eps));
+  d = pse_derived{};
+  if (p.grid > 0) {
+    if (!grid_supported(p.grid)) fail("grid must be 2^j or 3*2^j in [8, 1024]");
+    d.grid = p.grid;
+    d.xi = p.xi > 0 ? p.xi : M_PI * p.grid / (2.0 * L * lg);
+  } else if (p.xi > 0) {
+    d.xi = p.xi;
+    d.grid = next_supported((int)std::ceil(2.0 * p.xi * L * lg / M_PI));
+    if (d.grid < 0) fail("grid needed for this xi exceeds 1024");
+  } else {
+    fail("set grid or xi");
+  }
+  d.support = p.support > 0 ? p.support
+                            : (int)std::ceil(2.0 / M_PI * std::log(2.0 / eps));
+  if (d.support < 2 || d.support > 16) fail("support must be in [2, 16]");
+  if (d.support > d.grid) fail("support larger than the grid");
+  d.m = std::sqrt(M_PI * d.support);
+  d.h = L / d.grid;
+  d.eta_s = std::pow(d.h * d.support * d.xi / d.m, 2);
+  if (!(d.eta_s < 1.0)) fail("eta_s = (h P xi / m)^2 must be < 1: refine the grid or lower xi");
+  d.rcut = p.rcut > 0 ? p.rcut : 2.0 * a + lg / d.xi;
+  if (d.rcut > L / 3.0) fail("rcut exceeds L/3: raise xi or use a larger box");
+  d.cells = (int)std::floor(L / d.rcut);
+  if (d.cells < 3) fail("fewer than 3 cells per side");
+  if (d.cells > 1024) d.cells = 1024;
+  d.lanczos_maxit = p.lanczos_maxit > 0 ? p.lanczos_maxit : 100;
+  d.lanczos_tol = p.lanczos_tol > 0 ? p.lanczos_tol : 1e-3;
+  d.gmres_restart = p.gmres_restart > 0 ? p.gmres_restart : 30;
+  d.gmres_maxit = p.gmres_maxit > 0 ? p.gmres_maxit : 200;
+  d.gmres_tol = p.gmres_tol > 0 ? p.gmres_tol : 1e-6;
+  d.refine_passes = p.refine_passes > 0 ? p.refine_passes : 3;
+  if (d.lanczos_maxit > 500 || d.gmres_restart > 200)
+    fail("Krylov basis limits too large");
+}
+
+size_t footprint(const pse_params &p, const pse_derived &d) {
+  const size_t ng3 = (size_t)d.grid * d.grid * d.grid;
+  const size_t n = (size_t)p.n;
+  const size_t ncell3 = (size_t)d.cells * d.cells * d.cells;
+  size_t bytes = 0;
+  // FP64 grids are always present (the FP64 path, and the refinement of the
+  // mixed path); FP32 grids only for mixed handles.
+  bytes += 2 * MAX_PACK * ng3 * sizeof(double2) + d.grid * sizeof(double2);
+  if (p.precision == PSE_MIXED)
+    bytes += 2 * MAX_PACK * ng3 * sizeof(float2) + d.grid * sizeof(float2);
+  const size_t ntab = (size_t)(2048.0 * d.rcut / (2 * p.radius)) + 16;
+  bytes += ntab * NCOEF * (sizeof(double) + sizeof(float));
+  bytes += (2 * ncell3 + 2 + ncell3 / 1024 + 8) * sizeof(int) + 3 * n * sizeof(int);
+  bytes += (2 * 3 * n + 6 * NC * n) * sizeof(double);
+  bytes += (size_t)(d.lanczos_maxit + 1) * NC * n * sizeof(double);
+  bytes += (size_t)(d.gmres_restart + 1) * 5 * n * sizeof(double);
+  const size_t small = 4 * (size_t)(d.gmres_restart + 2) * (d.gmres_restart + 2)
+                       + 8 * (size_t)(d.lanczos_maxit + 2) * (d.lanczos_maxit + 2) + 64;
+  bytes += small * sizeof(double);
+  bytes += (size_t)4096 * (std::max(d.lanczos_maxit, d.gmres_restart) + 2) * sizeof(double);
+  return bytes;
+}
+
+}  // namespace pse

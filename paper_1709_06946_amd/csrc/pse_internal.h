@@ -1,0 +1,190 @@
+// Internal declarations of the PSE library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <functional>
+#include <string>
+#include <vector>
+
+#include "../../include/pse.h"
+
+namespace pse {
+
+constexpr int NC = 11;           // generalized force/velocity components
+constexpr int MAX_PACK = 6;      // packed complex grids (two real grids each)
+constexpr int NCOEF = 7;         // real-space coefficient functions
+
+// Error carrying a status code; converted at the ABI boundary.
+struct Error {
+  int code;
+  std::string msg;
+};
+
+#define PSE_HIP(call)                                                        \
+  do {                                                                       \
+    hipError_t e_ = (call);                                                  \
+    if (e_ != hipSuccess)                                                    \
+      throw ::pse::Error{e_ == hipErrorOutOfMemory ? PSE_ERR_NOMEM          \
+                                                   : PSE_ERR_HIP,            \
+                         std::string(#call) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+
+#define PSE_LAUNCH_CHECK() PSE_HIP(hipGetLastError())
+
+template <typename T> struct cplx_t;
+template <> struct cplx_t<double> { using type = double2; };
+template <> struct cplx_t<float> { using type = float2; };
+template <typename T> using cplx = typename cplx_t<T>::type;
+
+// Which 11-vector components an operator reads and writes.
+struct CompSet {
+  int n;          // number of components
+  int idx[NC];    // component indices into the 11-vector
+};
+
+// Geometry and quadrature constants passed by value to kernels.
+struct GridGeom {
+  int ng;          // grid points per side
+  int P;           // support
+  double L, h;     // box, spacing
+  double kcoef;    // Gaussian: K1d(d) = knorm exp(-kcoef d^2)
+  double knorm;
+};
+
+// Device workspace of one precision.
+template <typename T> struct GridSet {
+  cplx<T> *gin = nullptr;    // MAX_PACK packed complex grids
+  cplx<T> *gout = nullptr;   // MAX_PACK packed complex grids
+  cplx<T> *twiddle = nullptr;  // ng entries exp(-2 pi i m / ng)
+  T *table = nullptr;        // real-space coefficient table (ntab x NCOEF)
+};
+
+struct Handle {
+  pse_params p;
+  pse_derived d;
+  int64_t n;
+  size_t ngrid;              // ng^3
+  hipStream_t stream;
+  bool own_stream;
+  std::string err;
+
+  GridSet<double> g64;
+  GridSet<float> g32;
+  bool mixed;
+
+  // real-space table layout: uniform spacing dr, node 0 at r = 0, node
+  // n2a at r = 2a; ntab nodes in total.
+  int ntab, n2a;
+  double dr;
+
+  // cell list
+  int ncell;                 // cells per side
+  int *cell_start = nullptr; // ncell^3 + 1
+  int *cell_count = nullptr; // ncell^3
+  int *cell_of = nullptr;    // N
+  int *slot = nullptr;       // N
+  int *perm = nullptr;       // N: particles sorted by cell
+  int *scan_tmp = nullptr;   // block sums for the scan
+
+  // particle work vectors (double, N x 11 each)
+  double *xw = nullptr;      // wrapped positions N x 3
+  double *xh = nullptr;      // mid-point positions N x 3
+  double *v0 = nullptr, *v1 = nullptr, *v2 = nullptr, *v3 = nullptr;
+  double *v4 = nullptr, *v5 = nullptr;
+  double *es_b = nullptr, *es_x = nullptr, *es_r = nullptr, *es_d = nullptr;  // N x 5
+
+  // Krylov storage
+  double *lz_V = nullptr;    // (lanczos_maxit + 1) x 11N
+  double *gm_V = nullptr;    // (gmres_restart + 1) x 5N
+  double *small = nullptr;   // device scratch for dots / tridiagonal / Hessenberg
+  double *host_small = nullptr;  // pinned mirror
+  size_t small_len;
+  double *dots = nullptr;    // partial sums for reductions
+  size_t dots_len;
+};
+
+// ---- params.cpp
+void derive(const pse_params &p, pse_derived &d);
+size_t footprint(const pse_params &p, const pse_derived &d);
+
+// ---- fft.hip
+template <typename T>
+void fft3d(Handle &h, cplx<T> *data, const cplx<T> *twiddle, int ncomp, int dir);
+
+// ---- grid.hip
+template <typename T>
+void spread(Handle &h, const double *x, const double *q, int qstride,
+            const CompSet &cs, cplx<T> *grids);
+template <typename T>
+void interpolate(Handle &h, const double *x, const cplx<T> *grids,
+                 const CompSet &cs, double *out, int ostride, bool accumulate,
+                 double scale);
+template <typename T>
+void kspace_mobility(Handle &h, const cplx<T> *in, const CompSet &cin,
+                     cplx<T> *out, const CompSet &cout);
+template <typename T>
+void kspace_noise(Handle &h, const double *psi, uint64_t seed, uint64_t counter,
+                  cplx<T> *out, const CompSet &cout);
+template <typename T> void zero_grids(Handle &h, cplx<T> *g, int npack);
+template <typename T>
+void real_to_packed(Handle &h, const double *src, int ncomp, cplx<T> *dst);
+template <typename T>
+void packed_to_real(Handle &h, const cplx<T> *src, int ncomp, double *dst);
+
+// ---- real.hip
+void build_tables(Handle &h);
+void build_cells(Handle &h, const double *x);
+template <typename T>
+void real_apply(Handle &h, const double *x, const double *in,
+                const CompSet &cin, double *out, const CompSet &cout,
+                bool accumulate);
+void wrap_positions(Handle &h, const double *x, double *xw);
+
+// ---- krylov.hip / blas
+void vzero(Handle &h, double *v, size_t n);
+void vcopy(Handle &h, double *dst, const double *src, size_t n);
+void vaxpby(Handle &h, double a, const double *x, double b, double *y, size_t n);
+void multi_dot(Handle &h, const double *V, size_t ldv, int m, const double *w,
+               size_t n, double *dev_out);
+void vsub_multi(Handle &h, double *w, const double *V, size_t ldv, int m,
+                const double *coef_dev, size_t n);
+void gemv_small(Handle &h, const double *V, size_t ldv, int m,
+                const double *coef_dev, double *y, size_t n, double alpha,
+                bool accumulate);
+void vscale_dev(Handle &h, double *dst, const double *src, const double *s_dev,
+                bool invert, size_t n);
+void gather_comps(Handle &h, const double *src, int sstride, const CompSet &cs,
+                  double *dst, size_t n);
+void scatter_comps(Handle &h, const double *src, const CompSet &cs,
+                   double *dst, int dstride, size_t n, bool accumulate,
+                   double alpha);
+int check_finite(Handle &h, const double *v, size_t n);
+
+struct KrylovResult {
+  int iters;
+  double resid;      // Lanczos: last relative change; GMRES: relative residual
+  bool converged;
+};
+using Op = std::function<void(const double *in, double *out)>;
+KrylovResult lanczos_sqrt(Handle &h, const Op &A, const double *b, size_t n,
+                          double *y, int maxit, double tol);
+KrylovResult gmres(Handle &h, const Op &A, const double *b, size_t n, double *x,
+                   int restart, int maxit, double tol);
+
+// ---- grid.hip (noise)
+void real_noise(Handle &h, uint64_t seed, uint64_t counter, double *out);
+
+inline CompSet comps_range(int lo, int hi) {
+  CompSet c{};
+  c.n = hi - lo;
+  for (int i = 0; i < c.n; ++i) c.idx[i] = lo + i;
+  return c;
+}
+
+inline unsigned nblocks(size_t n, unsigned t) {
+  return static_cast<unsigned>((n + t - 1) / t);
+}
+
+}  // namespace pse

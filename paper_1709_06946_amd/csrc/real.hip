@@ -1,0 +1,514 @@
+// Real-space part of the Ewald sum (Sec. II.C.1, Eqs. MUFr-MDCr, pairsums).
+//
+// Pair functions.  Writing T_pq for the inverse transform of
+// f_p f_q (I - kk) / (eta k^2) (f_0 = j0(ka), f_1 = (sin ka - ka cos ka)/(ka)^3,
+// the shape factors of Eqs. MUF-MDC), with k_n <-> -i d_n:
+//   M_UF = T00,  M_UC_imn = -3 d_n T01_im,  M_DF_ijm = 3 d_j T01_im,
+//   M_DC_ijmn = -9 d_j d_n T11_im,   T_pq = (grad grad - I lap) phi_pq,
+// phi_pq the inverse transform of f_p f_q / (eta k^4).  With
+// Phi_n = ((1/r) d/dr)^n phi every block follows from seven radial
+// coefficients (the count of the paper's F1 F2 / G1 G2 / K1 K2 K3):
+//   a = -(r^2 Phi2 + 2 Phi1), b = r^2 Phi2                 (pq = 00)
+//   c1 = r^3 Phi3, c2 = r Phi2                             (pq = 01)
+//   d2 = Phi2, d3 = r^2 Phi3, d4 = r^4 Phi4                (pq = 11)
+// The real-space part (factor 1 - H) is "free space" minus "H part":
+//  * free space: f_0 and f_1 transform to a shell density
+//    delta(r - a)/(4 pi a^2) and a ball density 1/(4 pi a^3), and 1/k^4 to
+//    -r/(8 pi), so phi_pq = -(1/8 pi eta) (shell/ball autocorrelation * r).
+//    Carrying out the radial integrals gives, with A = -1/(8 pi eta),
+//      phi00 = A (4a/3 + r^2/3a - r^3/24a^2),              r < 2a
+//            = A (r + 2a^2/3r),                             r >= 2a
+//      phi01 = A (2a/5 + r^2/9a - r^4/120a^3 + r^5/720a^4), r < 2a
+//            = A (r/3 + 8a^2/45r),                          r >= 2a
+//      phi11 = A (4a/35 + 2r^2/45a - r^4/180a^3 + r^5/720a^4
+//                 - r^7/40320a^6),                          r < 2a
+//            = A (r/9 + 2a^2/45r),                          r >= 2a
+//    whose Phi_n are written out in free_coefficients();
+//  * H part: Phi_n^H(r) = 1/(2 pi^2 eta) int_0^inf H(k) f_p f_q (-1)^n
+//    k^(2n-2) j_n(kr)/(kr)^n dk, by the trapezoidal rule, which converges
+//    geometrically for this even, Gaussian-damped integrand.
+// Both are tabulated once per handle on the GPU (FP64) on a uniform r grid
+// with a node at r = 2a, and interpolated with 4-point Lagrange stencils that
+// never straddle r = 2a.
+#include "pse_internal.h"
+
+namespace pse {
+
+// ------------------------------------------------------------- tables --
+
+__device__ double jn_over_xn(int n, double x) {
+  // j_n(x)/x^n: power series below x = 4, upward recurrence above.
+  if (x < 4.0) {
+    double df = 1.0;
+    for (int k = 3; k <= 2 * n + 1; k += 2) df *= k;
+    double term = 1.0 / df, acc = term;
+    const double t = -0.5 * x * x;
+    for (int k = 1; k < 40; ++k) {
+      term *= t / (k * (2 * n + 2 * k + 1));
+      acc += term;
+    }
+    return acc;
+  }
+  double s, c;
+  sincos(x, &s, &c);
+  double jm = s / x;                   // j0
+  if (n == 0) return jm;
+  double j = s / (x * x) - c / x;      // j1
+  for (int m = 1; m < n; ++m) {
+    const double jp = (2 * m + 1) / x * j - jm;
+    jm = j;
+    j = jp;
+  }
+  double xn = x;
+  for (int m = 1; m < n; ++m) xn *= x;
+  return j / xn;
+}
+
+__device__ void free_coefficients(double r, double a, double eta, double *co) {
+  const double A = -1.0 / (8.0 * M_PI * eta);
+  double v[NCOEF];
+  if (r < 2.0 * a) {
+    const double a2 = a * a, a3 = a2 * a, a4 = a3 * a, a6 = a3 * a3;
+    const double r2 = r * r, r3 = r2 * r;
+    // phi00: Phi1 = 2/3a - r/8a^2, Phi2 = -1/(8 a^2 r)
+    v[0] = -4.0 / (3.0 * a) + 3.0 * r / (8.0 * a2);
+    v[1] = -r / (8.0 * a2);
+    // phi01: Phi2 = -1/15a^3 + r/48a^4, Phi3 = 1/(48 a^4 r)
+    v[2] = r2 / (48.0 * a4);
+    v[3] = -r / (15.0 * a3) + r2 / (48.0 * a4);
+    // phi11: Phi2 = -2/45a^3 + r/48a^4 - r^3/1152a^6,
+    //        Phi3 = 1/(48 a^4 r) - r/384a^6, Phi4 = -1/(48 a^4 r^3) - 1/(384 a^6 r)
+    v[4] = -2.0 / (45.0 * a3) + r / (48.0 * a4) - r3 / (1152.0 * a6);
+    v[5] = r / (48.0 * a4) - r3 / (384.0 * a6);
+    v[6] = -r / (48.0 * a4) - r3 / (384.0 * a6);
+  } else {
+    const double a2 = a * a, r2 = r * r, r3 = r2 * r, r4 = r2 * r2, r5 = r4 * r;
+    // phi00: Phi1 = 1/r - 2a^2/3r^3, Phi2 = -1/r^3 + 2a^2/r^5
+    v[0] = -(1.0 / r + 2.0 * a2 / (3.0 * r3));
+    v[1] = -1.0 / r + 2.0 * a2 / r3;
+    // phi01: Phi2 = -1/3r^3 + 8a^2/15r^5, Phi3 = 1/r^5 - 8a^2/3r^7
+    v[2] = 1.0 / r2 - 8.0 * a2 / (3.0 * r4);
+    v[3] = -1.0 / (3.0 * r2) + 8.0 * a2 / (15.0 * r4);
+    // phi11: Phi2 = -1/9r^3 + 2a^2/15r^5, Phi3 = 1/3r^5 - 2a^2/3r^7,
+    //        Phi4 = -5/3r^7 + 14a^2/3r^9
+    v[4] = -1.0 / (9.0 * r3) + 2.0 * a2 / (15.0 * r5);
+    v[5] = 1.0 / (3.0 * r3) - 2.0 * a2 / (3.0 * r5);
+    v[6] = -5.0 / (3.0 * r3) + 14.0 * a2 / (3.0 * r5);
+  }
+  for (int i = 0; i < NCOEF; ++i) co[i] = A * v[i];
+}
+
+__global__ void table_kernel(double *__restrict__ tab, float *__restrict__ tab32,
+                             int ntab, double dr, double a, double eta, double xi,
+                             double dk, int nk) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ntab) return;
+  const double r = i * dr;
+  double fc[NCOEF];
+  free_coefficients(r, a, eta, fc);
+  // H part: Phi1_00, Phi2_00, Phi2_01, Phi3_01, Phi2_11, Phi3_11, Phi4_11
+  double S[7] = {0, 0, 0, 0, 0, 0, 0};
+  const double inv4xi2 = 1.0 / (4.0 * xi * xi);
+  for (int m = 0; m <= nk; ++m) {
+    const double k = m * dk;
+    const double w = (m == 0) ? 0.5 * dk : dk;
+    const double u = k * k * inv4xi2;
+    const double H = (1.0 + u) * exp(-u);
+    const double f0 = jn_over_xn(0, k * a), f1 = jn_over_xn(1, k * a);
+    const double kr = k * r;
+    const double J1 = jn_over_xn(1, kr), J2 = jn_over_xn(2, kr);
+    const double J3 = jn_over_xn(3, kr), J4 = jn_over_xn(4, kr);
+    const double k2 = k * k, k4 = k2 * k2, k6 = k4 * k2;
+    const double wh = w * H;
+    S[0] += -wh * f0 * f0 * J1;
+    S[1] += wh * f0 * f0 * k2 * J2;
+    S[2] += wh * f0 * f1 * k2 * J2;
+    S[3] += -wh * f0 * f1 * k4 * J3;
+    S[4] += wh * f1 * f1 * k2 * J2;
+    S[5] += -wh * f1 * f1 * k4 * J3;
+    S[6] += wh * f1 * f1 * k6 * J4;
+  }
+  const double c = 1.0 / (2.0 * M_PI * M_PI * eta);
+  for (int j = 0; j < 7; ++j) S[j] *= c;
+  const double r2 = r * r;
+  double hc[NCOEF];
+  hc[0] = -(r2 * S[1] + 2.0 * S[0]);
+  hc[1] = r2 * S[1];
+  hc[2] = r2 * r * S[3];
+  hc[3] = r * S[2];
+  hc[4] = S[4];
+  hc[5] = r2 * S[5];
+  hc[6] = r2 * r2 * S[6];
+  for (int j = 0; j < NCOEF; ++j) {
+    const double v = fc[j] - hc[j];
+    tab[(size_t)i * NCOEF + j] = v;
+    tab32[(size_t)i * NCOEF + j] = (float)v;
+  }
+}
+
+void build_tables(Handle &h) {
+  const double a = h.p.radius, xi = h.d.xi;
+  h.n2a = 2048;
+  h.dr = 2.0 * a / h.n2a;
+  h.ntab = (int)std::ceil(h.d.rcut / h.dr) + 8;
+  PSE_HIP(hipMalloc(&h.g64.table, (size_t)h.ntab * NCOEF * sizeof(double)));
+  PSE_HIP(hipMalloc(&h.g32.table, (size_t)h.ntab * NCOEF * sizeof(float)));
+  const double rmax = h.ntab * h.dr;
+  const double dk = M_PI / (2.0 * a + rmax + 7.0 / xi);
+  const double kmax = 2.0 * xi * std::sqrt(50.0);
+  const int nk = (int)std::ceil(kmax / dk);
+  hipLaunchKernelGGL(table_kernel, dim3(nblocks(h.ntab, 128)), dim3(128), 0,
+                     h.stream, h.g64.table, h.g32.table, h.ntab, h.dr, a,
+                     h.p.viscosity, xi, dk, nk);
+  PSE_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------- positions --
+
+__global__ void wrap_kernel(const double *__restrict__ x, double *__restrict__ xw,
+                            int64_t n3, double L) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n3) return;
+  double v = x[i];
+  v -= L * floor(v / L);
+  if (v >= L) v -= L;
+  if (v < 0) v = 0;
+  xw[i] = v;
+}
+
+void wrap_positions(Handle &h, const double *x, double *xw) {
+  hipLaunchKernelGGL(wrap_kernel, dim3(nblocks(3 * h.n, 256)), dim3(256), 0,
+                     h.stream, x, xw, 3 * h.n, h.p.box);
+  PSE_LAUNCH_CHECK();
+}
+
+// ----------------------------------------------------------- cell list --
+
+__global__ void cell_assign_kernel(const double *__restrict__ xw, int64_t n,
+                                   int nc, double inv_cs, int *__restrict__ cell_of,
+                                   int *__restrict__ slot, int *__restrict__ count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int c[3];
+  for (int d = 0; d < 3; ++d) {
+    int v = (int)(xw[3 * i + d] * inv_cs);
+    c[d] = v < 0 ? 0 : (v >= nc ? nc - 1 : v);
+  }
+  const int cell = (c[2] * nc + c[1]) * nc + c[0];
+  cell_of[i] = cell;
+  slot[i] = atomicAdd(&count[cell], 1);
+}
+
+// Exclusive scan in chunks of 1024 (256 threads x 4).
+__global__ void scan_block_kernel(const int *__restrict__ in, int *__restrict__ out,
+                                  int *__restrict__ block_sums, int n) {
+  __shared__ int s[256];
+  const int base = blockIdx.x * 1024 + threadIdx.x * 4;
+  int v[4], sum = 0;
+  for (int j = 0; j < 4; ++j) {
+    v[j] = base + j < n ? in[base + j] : 0;
+    sum += v[j];
+  }
+  s[threadIdx.x] = sum;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    const int t = threadIdx.x >= off ? s[threadIdx.x - off] : 0;
+    __syncthreads();
+    s[threadIdx.x] += t;
+    __syncthreads();
+  }
+  int run = s[threadIdx.x] - sum;
+  for (int j = 0; j < 4; ++j) {
+    if (base + j < n) out[base + j] = run;
+    run += v[j];
+  }
+  if (threadIdx.x == 255) block_sums[blockIdx.x] = s[255];
+}
+
+__global__ void scan_sums_kernel(int *__restrict__ sums, int nb, int *__restrict__ total) {
+  // single block: exclusive scan of nb block sums with a running carry
+  __shared__ int s[256];
+  __shared__ int carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int b0 = 0; b0 < nb; b0 += 256) {
+    const int i = b0 + threadIdx.x;
+    const int v = i < nb ? sums[i] : 0;
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+      const int t = threadIdx.x >= off ? s[threadIdx.x - off] : 0;
+      __syncthreads();
+      s[threadIdx.x] += t;
+      __syncthreads();
+    }
+    if (i < nb) sums[i] = carry + s[threadIdx.x] - v;
+    __syncthreads();
+    if (threadIdx.x == 255) carry += s[255];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *total = carry;
+}
+
+__global__ void scan_add_kernel(int *__restrict__ out, const int *__restrict__ sums, int n) {
+  const int i = blockIdx.x * 1024 + threadIdx.x * 4;
+  const int add = sums[blockIdx.x];
+  for (int j = 0; j < 4; ++j)
+    if (i + j < n) out[i + j] += add;
+}
+
+__global__ void cell_scatter_kernel(const int *__restrict__ cell_of,
+                                    const int *__restrict__ slot,
+                                    const int *__restrict__ start, int64_t n,
+                                    int *__restrict__ perm) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  perm[start[cell_of[i]] + slot[i]] = (int)i;
+}
+
+void build_cells(Handle &h, const double *xw) {
+  const int nc = h.ncell;
+  const int ncells = nc * nc * nc;
+  PSE_HIP(hipMemsetAsync(h.cell_count, 0, ncells * sizeof(int), h.stream));
+  hipLaunchKernelGGL(cell_assign_kernel, dim3(nblocks(h.n, 256)), dim3(256), 0,
+                     h.stream, xw, h.n, nc, nc / h.p.box, h.cell_of, h.slot,
+                     h.cell_count);
+  PSE_LAUNCH_CHECK();
+  const int nb = (ncells + 1023) / 1024;
+  hipLaunchKernelGGL(scan_block_kernel, dim3(nb), dim3(256), 0, h.stream,
+                     h.cell_count, h.cell_start, h.scan_tmp, ncells);
+  PSE_LAUNCH_CHECK();
+  hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(256), 0, h.stream, h.scan_tmp,
+                     nb, h.cell_start + ncells);
+  PSE_LAUNCH_CHECK();
+  hipLaunchKernelGGL(scan_add_kernel, dim3(nb), dim3(256), 0, h.stream,
+                     h.cell_start, h.scan_tmp, ncells);
+  PSE_LAUNCH_CHECK();
+  hipLaunchKernelGGL(cell_scatter_kernel, dim3(nblocks(h.n, 256)), dim3(256), 0,
+                     h.stream, h.cell_of, h.slot, h.cell_start, h.n, h.perm);
+  PSE_LAUNCH_CHECK();
+}
+
+// ------------------------------------------------------------ pair sum --
+
+struct RealArgs {
+  int64_t n;
+  int nc;
+  double L, rcut2;
+  double inv_dr;
+  int n2a, ntab;
+  int in_mask;    // 1: F, 2: L, 4: S
+  int out_mask;   // 1: U, 2: Omega, 4: E
+  int accumulate;
+};
+
+template <typename T>
+__device__ __forceinline__ void lookup(const T *__restrict__ tab, T r, T inv_dr,
+                                       int n2a, int ntab, T *co) {
+  const T f = r * inv_dr;
+  int i0 = (int)f;
+  int base;
+  if (i0 < n2a) {
+    base = i0 - 1;
+    if (base < 0) base = 0;
+    if (base > n2a - 3) base = n2a - 3;
+  } else {
+    base = i0 - 1;
+    if (base < n2a) base = n2a;
+    if (base > ntab - 4) base = ntab - 4;
+  }
+  const T t = f - (T)base;
+  const T w0 = -(t - 1) * (t - 2) * (t - 3) / (T)6;
+  const T w1 = t * (t - 2) * (t - 3) / (T)2;
+  const T w2 = -t * (t - 1) * (t - 3) / (T)2;
+  const T w3 = t * (t - 1) * (t - 2) / (T)6;
+  const T *p = tab + (size_t)base * NCOEF;
+#pragma unroll
+  for (int j = 0; j < NCOEF; ++j)
+    co[j] = w0 * p[j] + w1 * p[NCOEF + j] + w2 * p[2 * NCOEF + j] + w3 * p[3 * NCOEF + j];
+}
+
+// Acting with the pair block M(r) on (F, C) of the partner; adds to U and D.
+template <typename T>
+__device__ __forceinline__ void pair_action(const T *co, const T *e, const T *F,
+                                            const T (*C)[3], bool useF, bool useC,
+                                            T *U, T (*D)[3]) {
+  const T a = co[0], b = co[1], c1 = co[2], c2 = co[3];
+  const T d2 = co[4], d3 = co[5], d4 = co[6];
+  const T c14 = c1 + (T)4 * c2;
+  if (useF) {
+    const T eF = e[0] * F[0] + e[1] * F[1] + e[2] * F[2];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      U[i] += a * F[i] + b * e[i] * eF;
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        D[i][j] += (T)3 * (c1 * e[i] * e[j] * eF + c2 * ((i == j ? eF : (T)0) + F[j] * e[i])
+                           - c14 * F[i] * e[j]);
+    }
+  }
+  if (useC) {
+    T Ce[3], CTe[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      Ce[i] = C[i][0] * e[0] + C[i][1] * e[1] + C[i][2] * e[2];
+      CTe[i] = C[0][i] * e[0] + C[1][i] * e[1] + C[2][i] * e[2];
+    }
+    const T eCe = e[0] * Ce[0] + e[1] * Ce[1] + e[2] * Ce[2];
+    const T k7 = (T)7 * d3 + d4, k5 = (T)5 * d2 + d3;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      U[i] += (T)(-3) * (c1 * e[i] * eCe + c2 * CTe[i] - c14 * Ce[i]);
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const T s = d4 * e[i] * e[j] * eCe
+                    + d3 * ((i == j ? eCe : (T)0) + e[j] * Ce[i] + e[j] * CTe[i]
+                            + e[i] * Ce[j] + e[i] * CTe[j])
+                    + d2 * (C[i][j] + C[j][i]) - k7 * e[j] * Ce[i] - k5 * C[i][j];
+        D[i][j] += (T)(-9) * s;
+      }
+    }
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void load_moments(const double *__restrict__ v, int mask,
+                                             T *F, T (*C)[3]) {
+  const T r2 = (T)0.70710678118654752440, r6 = (T)0.40824829046386301637;
+  for (int i = 0; i < 3; ++i) {
+    F[i] = (mask & 1) ? (T)v[i] : (T)0;
+    for (int j = 0; j < 3; ++j) C[i][j] = (T)0;
+  }
+  if (mask & 2) {
+    // C^A_mn = -1/2 eps_mnk L_k
+    const T Lx = (T)v[3], Ly = (T)v[4], Lz = (T)v[5];
+    C[0][1] -= (T)0.5 * Lz; C[1][0] += (T)0.5 * Lz;
+    C[0][2] += (T)0.5 * Ly; C[2][0] -= (T)0.5 * Ly;
+    C[1][2] -= (T)0.5 * Lx; C[2][1] += (T)0.5 * Lx;
+  }
+  if (mask & 4) {
+    const T s1 = (T)v[6], s2 = (T)v[7], s3 = (T)v[8], s4 = (T)v[9], s5 = (T)v[10];
+    C[0][1] += r2 * s1; C[1][0] += r2 * s1;
+    C[0][2] += r2 * s2; C[2][0] += r2 * s2;
+    C[1][2] += r2 * s3; C[2][1] += r2 * s3;
+    C[0][0] += r2 * s4 + r6 * s5;
+    C[1][1] += -r2 * s4 + r6 * s5;
+    C[2][2] += (T)(-2) * r6 * s5;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+real_pair_kernel(const double *__restrict__ xw, const double *__restrict__ in,
+                 double *__restrict__ out, const int *__restrict__ perm,
+                 const int *__restrict__ cell_start, const int *__restrict__ cell_of,
+                 const T *__restrict__ tab, RealArgs ra) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ra.n) return;
+  const int i = perm[t];
+  const double xi0 = xw[3 * i], xi1 = xw[3 * i + 1], xi2 = xw[3 * i + 2];
+  const bool useF = ra.in_mask & 1, useC = (ra.in_mask & 6) != 0;
+  T U[3] = {0, 0, 0};
+  T D[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  T F[3], C[3][3];
+  // self term (r = 0: only the isotropic coefficients survive)
+  {
+    T co[NCOEF];
+    for (int j = 0; j < NCOEF; ++j) co[j] = tab[j];
+    const T e0[3] = {0, 0, 0};
+    load_moments<T>(in + (size_t)i * NC, ra.in_mask, F, C);
+    pair_action<T>(co, e0, F, C, useF, useC, U, D);
+  }
+  const int nc = ra.nc;
+  const int ci = cell_of[i];
+  const int cx = ci % nc, cy = (ci / nc) % nc, cz = ci / (nc * nc);
+  const T inv_dr = (T)ra.inv_dr;
+  for (int dz = -1; dz <= 1; ++dz) {
+    const int zz = (cz + dz + nc) % nc;
+    for (int dy = -1; dy <= 1; ++dy) {
+      const int yy = (cy + dy + nc) % nc;
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int xx = (cx + dx + nc) % nc;
+        const int cell = (zz * nc + yy) * nc + xx;
+        const int s0 = cell_start[cell], s1 = cell_start[cell + 1];
+        for (int s = s0; s < s1; ++s) {
+          const int j = perm[s];
+          if (j == i) continue;
+          double d0 = xi0 - xw[3 * j], d1 = xi1 - xw[3 * j + 1], d2 = xi2 - xw[3 * j + 2];
+          d0 -= ra.L * rint(d0 / ra.L);
+          d1 -= ra.L * rint(d1 / ra.L);
+          d2 -= ra.L * rint(d2 / ra.L);
+          const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+          if (r2 >= ra.rcut2) continue;
+          const double r = sqrt(r2);
+          T e[3];
+          if (r > 0) {
+            e[0] = (T)(d0 / r); e[1] = (T)(d1 / r); e[2] = (T)(d2 / r);
+          } else {
+            e[0] = e[1] = e[2] = (T)0;
+          }
+          T co[NCOEF];
+          lookup<T>(tab, (T)r, inv_dr, ra.n2a, ra.ntab, co);
+          load_moments<T>(in + (size_t)j * NC, ra.in_mask, F, C);
+          pair_action<T>(co, e, F, C, useF, useC, U, D);
+        }
+      }
+    }
+  }
+  double *o = out + (size_t)i * NC;
+  const double r2 = 0.70710678118654752440, r6 = 0.40824829046386301637;
+  if (ra.out_mask & 1) {
+    for (int k = 0; k < 3; ++k) o[k] = (ra.accumulate ? o[k] : 0.0) + (double)U[k];
+  }
+  if (ra.out_mask & 2) {
+    // Omega = -1/2 eps : D
+    const double om[3] = {-0.5 * ((double)D[1][2] - D[2][1]),
+                          -0.5 * ((double)D[2][0] - D[0][2]),
+                          -0.5 * ((double)D[0][1] - D[1][0])};
+    for (int k = 0; k < 3; ++k) o[3 + k] = (ra.accumulate ? o[3 + k] : 0.0) + om[k];
+  }
+  if (ra.out_mask & 4) {
+    const double e5[5] = {r2 * ((double)D[0][1] + D[1][0]), r2 * ((double)D[0][2] + D[2][0]),
+                          r2 * ((double)D[1][2] + D[2][1]), r2 * ((double)D[0][0] - D[1][1]),
+                          r6 * ((double)D[0][0] + D[1][1] - 2.0 * D[2][2])};
+    for (int k = 0; k < 5; ++k) o[6 + k] = (ra.accumulate ? o[6 + k] : 0.0) + e5[k];
+  }
+}
+
+static int mask_of(const CompSet &cs, bool input) {
+  int m = 0;
+  for (int k = 0; k < cs.n; ++k) {
+    const int c = cs.idx[k];
+    m |= c < 3 ? 1 : (c < 6 ? 2 : 4);
+  }
+  (void)input;
+  return m;
+}
+
+template <typename T>
+void real_apply(Handle &h, const double *xw, const double *in, const CompSet &cin,
+                double *out, const CompSet &cout, bool accumulate) {
+  RealArgs ra;
+  ra.n = h.n;
+  ra.nc = h.ncell;
+  ra.L = h.p.box;
+  ra.rcut2 = h.d.rcut * h.d.rcut;
+  ra.inv_dr = 1.0 / h.dr;
+  ra.n2a = h.n2a;
+  ra.ntab = h.ntab;
+  ra.in_mask = mask_of(cin, true);
+  ra.out_mask = mask_of(cout, false);
+  ra.accumulate = accumulate ? 1 : 0;
+  const T *tab;
+  if constexpr (sizeof(T) == 8) tab = h.g64.table; else tab = h.g32.table;
+  hipLaunchKernelGGL(real_pair_kernel<T>, dim3(nblocks(h.n, 256)), dim3(256), 0,
+                     h.stream, xw, in, out, h.perm, h.cell_start, h.cell_of, tab, ra);
+  PSE_LAUNCH_CHECK();
+}
+
+template void real_apply<double>(Handle &, const double *, const double *,
+                                 const CompSet &, double *, const CompSet &, bool);
+template void real_apply<float>(Handle &, const double *, const double *,
+                                const CompSet &, double *, const CompSet &, bool);
+
+}  // namespace pse

@@ -1,0 +1,240 @@
+"""Python binding of libpse.so (ctypes): argument marshalling only.
+
+Every computation runs in the HIP library; this module converts torch device
+tensors to raw pointers and checks shapes.  Importing it loads the in-tree
+libpse.so and raises if it is missing -- there is no fallback.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, 'libpse.so')
+
+PSE_OK, PSE_WARN_NOT_CONVERGED = 0, 1
+PSE_FP64, PSE_MIXED = 0, 1
+PSE_REAL, PSE_WAVE = 1, 2
+
+
+class pse_params(ctypes.Structure):
+    _fields_ = [('n', ctypes.c_int64), ('box', ctypes.c_double),
+                ('radius', ctypes.c_double), ('viscosity', ctypes.c_double),
+                ('kT', ctypes.c_double), ('tol', ctypes.c_double),
+                ('grid', ctypes.c_int32), ('support', ctypes.c_int32),
+                ('xi', ctypes.c_double), ('rcut', ctypes.c_double),
+                ('precision', ctypes.c_int32), ('lanczos_maxit', ctypes.c_int32),
+                ('lanczos_tol', ctypes.c_double), ('gmres_restart', ctypes.c_int32),
+                ('gmres_maxit', ctypes.c_int32), ('gmres_tol', ctypes.c_double),
+                ('refine_passes', ctypes.c_int32), ('stream', ctypes.c_void_p)]
+
+
+class pse_derived(ctypes.Structure):
+    _fields_ = [('grid', ctypes.c_int32), ('support', ctypes.c_int32),
+                ('xi', ctypes.c_double), ('eta_s', ctypes.c_double),
+                ('m', ctypes.c_double), ('h', ctypes.c_double),
+                ('rcut', ctypes.c_double), ('cells', ctypes.c_int32),
+                ('lanczos_maxit', ctypes.c_int32), ('gmres_restart', ctypes.c_int32),
+                ('gmres_maxit', ctypes.c_int32), ('refine_passes', ctypes.c_int32),
+                ('lanczos_tol', ctypes.c_double), ('gmres_tol', ctypes.c_double)]
+
+
+class pse_stats(ctypes.Structure):
+    _fields_ = [('lanczos_iters', ctypes.c_int32), ('gmres_iters', ctypes.c_int32),
+                ('refine_passes', ctypes.c_int32), ('converged', ctypes.c_int32),
+                ('lanczos_change', ctypes.c_double), ('gmres_residual', ctypes.c_double),
+                ('fp64_residual', ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class pse_step_io(ctypes.Structure):
+    _fields_ = [('psi_real', ctypes.c_void_p), ('psi_wave', ctypes.c_void_p),
+                ('slip', ctypes.c_void_p), ('stresslet', ctypes.c_void_p),
+                ('velocity', ctypes.c_void_p)]
+
+
+EXPORTS = ('pse_derive', 'pse_footprint_bytes', 'pse_create', 'pse_destroy',
+           'pse_get_derived', 'pse_mobility_apply', 'pse_brownian_sample',
+           'pse_constrained_step', 'pse_fft3d', 'pse_spread', 'pse_interpolate',
+           'pse_last_error')
+
+
+def load_library(path=LIB_PATH):
+    if not os.path.exists(path):
+        raise RuntimeError(f'{path} is missing: run __graft_entry__.build() '
+                           '(python -m paper_1709_06946_amd.build) first')
+    lib = ctypes.CDLL(path)
+    P, V, I = ctypes.POINTER, ctypes.c_void_p, ctypes.c_int
+    lib.pse_derive.argtypes = [P(pse_params), P(pse_derived)]
+    lib.pse_footprint_bytes.argtypes = [P(pse_params), P(ctypes.c_size_t)]
+    lib.pse_create.argtypes = [P(pse_params), P(V)]
+    lib.pse_destroy.argtypes = [V]
+    lib.pse_get_derived.argtypes = [V, P(pse_derived)]
+    lib.pse_mobility_apply.argtypes = [V, V, V, V, ctypes.c_uint]
+    lib.pse_brownian_sample.argtypes = [V, V, V, V, ctypes.c_uint64, ctypes.c_uint64,
+                                        V, V, P(pse_stats)]
+    lib.pse_constrained_step.argtypes = [V, V, V, ctypes.c_double, ctypes.c_uint64,
+                                         ctypes.c_uint64, P(pse_step_io), P(pse_stats)]
+    lib.pse_fft3d.argtypes = [V, V, I, I]
+    lib.pse_spread.argtypes = [V, V, V, I, V]
+    lib.pse_interpolate.argtypes = [V, V, V, I, V]
+    lib.pse_last_error.argtypes = [V]
+    lib.pse_last_error.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        if name != 'pse_last_error':
+            getattr(lib, name).restype = I
+    return lib
+
+
+_LIB = None
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        _LIB = load_library()
+    return _LIB
+
+
+class PSEError(RuntimeError):
+    pass
+
+
+def make_params(n, box, *, radius=1.0, viscosity=1.0, kT=1.0, tol=1e-3, grid=0,
+                support=0, xi=0.0, rcut=0.0, precision=PSE_FP64, lanczos_maxit=0,
+                lanczos_tol=0.0, gmres_restart=0, gmres_maxit=0, gmres_tol=0.0,
+                refine_passes=0, stream=None):
+    return pse_params(int(n), float(box), float(radius), float(viscosity), float(kT),
+                      float(tol), int(grid), int(support), float(xi), float(rcut),
+                      int(precision), int(lanczos_maxit), float(lanczos_tol),
+                      int(gmres_restart), int(gmres_maxit), float(gmres_tol),
+                      int(refine_passes), stream)
+
+
+def derive(params):
+    d = pse_derived()
+    rc = lib().pse_derive(ctypes.byref(params), ctypes.byref(d))
+    if rc != PSE_OK:
+        raise PSEError(f'pse_derive: {rc}: {lib().pse_last_error(None).decode()}')
+    return d
+
+
+def footprint_bytes(params):
+    b = ctypes.c_size_t()
+    rc = lib().pse_footprint_bytes(ctypes.byref(params), ctypes.byref(b))
+    if rc != PSE_OK:
+        raise PSEError(f'pse_footprint_bytes: {rc}: {lib().pse_last_error(None).decode()}')
+    return b.value
+
+
+def _ptr(t, shape=None, name='tensor'):
+    """Raw device pointer of a contiguous float64 CUDA/HIP tensor (or None)."""
+    if t is None:
+        return None
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f'{name} must be a device tensor')
+    if t.dtype not in (torch.float64, torch.complex128):
+        raise TypeError(f'{name} must be float64 or complex128')
+    if not t.is_contiguous():
+        raise ValueError(f'{name} must be contiguous')
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f'{name} has shape {tuple(t.shape)}, expected {tuple(shape)}')
+    return t.data_ptr()
+
+
+def _sync():
+    """Order torch's pending work on the device before a library call (the
+    library runs on its own stream and synchronizes it before returning)."""
+    import torch
+    torch.cuda.synchronize()
+
+
+class PSE:
+    """One library handle (one particle count, box and parameter set)."""
+
+    def __init__(self, n, box, **kw):
+        self.params = make_params(n, box, **kw)
+        self.n = int(n)
+        h = ctypes.c_void_p()
+        rc = lib().pse_create(ctypes.byref(self.params), ctypes.byref(h))
+        if rc != PSE_OK:
+            raise PSEError(f'pse_create: {rc}: {lib().pse_last_error(None).decode()}')
+        self._h = h
+        d = pse_derived()
+        lib().pse_get_derived(self._h, ctypes.byref(d))
+        self.derived = d
+
+    def _check(self, rc, what):
+        if rc < 0:
+            raise PSEError(f'{what}: {rc}: {lib().pse_last_error(self._h).decode()}')
+        return rc
+
+    def close(self):
+        if getattr(self, '_h', None):
+            lib().pse_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def mobility_apply(self, x, q, out, parts=PSE_REAL | PSE_WAVE):
+        n = self.n
+        _sync()
+        return self._check(lib().pse_mobility_apply(
+            self._h, _ptr(x, (n, 3), 'x'), _ptr(q, (n, 11), 'in'),
+            _ptr(out, (n, 11), 'out'), parts), 'pse_mobility_apply')
+
+    def brownian_sample(self, x, psi_real=None, psi_wave=None, seed=0, counter=0,
+                        out_real=None, out_wave=None):
+        n, g = self.n, self.derived.grid
+        _sync()
+        st = pse_stats()
+        rc = self._check(lib().pse_brownian_sample(
+            self._h, _ptr(x, (n, 3), 'x'), _ptr(psi_real, (n, 11), 'psi_real'),
+            _ptr(psi_wave, (3, g, g, g // 2 + 1), 'psi_wave'), seed, counter,
+            _ptr(out_real, (n, 11), 'out_real'), _ptr(out_wave, (n, 11), 'out_wave'),
+            ctypes.byref(st)), 'pse_brownian_sample')
+        return rc, st.as_dict()
+
+    def constrained_step(self, x, FL=None, dt=1e-3, seed=0, step=0, psi_real=None,
+                         psi_wave=None, slip=None, stresslet=None, velocity=None):
+        n, g = self.n, self.derived.grid
+        _sync()
+        io = pse_step_io(_ptr(psi_real, (n, 11), 'psi_real'),
+                         _ptr(psi_wave, (3, g, g, g // 2 + 1), 'psi_wave'),
+                         _ptr(slip, (n, 11), 'slip'), _ptr(stresslet, (n, 5), 'stresslet'),
+                         _ptr(velocity, (n, 3), 'velocity'))
+        st = pse_stats()
+        rc = self._check(lib().pse_constrained_step(
+            self._h, _ptr(x, (n, 3), 'x'), _ptr(FL, (n, 6), 'FL'), float(dt), seed, step,
+            ctypes.byref(io), ctypes.byref(st)), 'pse_constrained_step')
+        return rc, st.as_dict()
+
+    def fft3d(self, data, direction):
+        g = self.derived.grid
+        _sync()
+        nc = data.shape[0]
+        return self._check(lib().pse_fft3d(self._h, _ptr(data, (nc, g, g, g), 'data'), nc,
+                                           direction), 'pse_fft3d')
+
+    def spread(self, x, q, grids):
+        n, g = self.n, self.derived.grid
+        _sync()
+        nc = q.shape[1]
+        return self._check(lib().pse_spread(self._h, _ptr(x, (n, 3), 'x'),
+                                            _ptr(q, (n, nc), 'q'), nc,
+                                            _ptr(grids, (nc, g, g, g), 'grids')),
+                           'pse_spread')
+
+    def interpolate(self, x, grids, out):
+        n, g = self.n, self.derived.grid
+        _sync()
+        nc = grids.shape[0]
+        return self._check(lib().pse_interpolate(self._h, _ptr(x, (n, 3), 'x'),
+                                                 _ptr(grids, (nc, g, g, g), 'grids'), nc,
+                                                 _ptr(out, (n, nc), 'out')),
+                           'pse_interpolate')

@@ -1,0 +1,218 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Inputs are seeded hard-sphere packings (N = 100, phi = 0.1 and 0.01 in a
+32^3 grid, eps = 1e-3) with i.i.d. N(0, 1) moments and noise.  Every result is
+compared block by block (U, Omega, E) by relative 2-norm error; the bar is the
+method tolerance eps = 1e-3 of the configuration.
+"""
+import functools
+
+import numpy as np
+import pytest
+
+from gpu_common import block_errors, dev, host, packing, rel_err
+from oracle import brownian, ewald, integrator
+from paper_1709_06946_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    'phi0.1': dict(N=100, phi=0.1, grid=32, seed=inputs.SEED_BASE),
+    'phi0.01': dict(N=100, phi=0.01, grid=32, seed=inputs.SEED_BASE + 7),
+}
+TOL = 1e-3
+
+
+@functools.lru_cache(maxsize=None)
+def case(name, precision=0, lanczos_tol=1e-3, gmres_tol=1e-6):
+    from paper_1709_06946_amd import pse
+    c = CASES[name]
+    x, L = packing(c['N'], c['phi'], c['seed'])
+    h = pse.PSE(c['N'], L, grid=c['grid'], tol=1e-3, precision=precision,
+                lanczos_tol=lanczos_tol, gmres_tol=gmres_tol)
+    return h, x, L
+
+
+@functools.lru_cache(maxsize=None)
+def moments(name):
+    c = CASES[name]
+    return np.random.default_rng(c['seed'] + 11).normal(size=(c['N'], 11))
+
+
+@functools.lru_cache(maxsize=None)
+def oracle_parts(name):
+    h, x, L = case(name)
+    q = moments(name)
+    xi = h.derived.xi
+    return ewald.real_apply(x, q, L, xi), ewald.wave_apply(x, q, L, xi)
+
+
+def _apply(h, x, q, parts):
+    import torch
+    out = torch.zeros((h.n, 11), dtype=torch.float64, device='cuda:0')
+    h.mobility_apply(dev(x), dev(q), out, parts)
+    return host(out)
+
+
+@pytest.mark.parametrize('name', list(CASES))
+@pytest.mark.parametrize('precision', [0, 1])
+def test_mobility_real_part(name, precision):
+    from paper_1709_06946_amd import pse
+    h, x, L = case(name, precision)
+    ref, _ = oracle_parts(name)
+    errs = block_errors(_apply(h, x, moments(name), pse.PSE_REAL), ref)
+    print(name, precision, 'real', errs)
+    assert max(errs.values()) < TOL, errs
+
+
+@pytest.mark.parametrize('name', list(CASES))
+@pytest.mark.parametrize('precision', [0, 1])
+def test_mobility_wave_part(name, precision):
+    from paper_1709_06946_amd import pse
+    h, x, L = case(name, precision)
+    _, ref = oracle_parts(name)
+    errs = block_errors(_apply(h, x, moments(name), pse.PSE_WAVE), ref)
+    print(name, precision, 'wave', errs)
+    assert max(errs.values()) < TOL, errs
+
+
+@pytest.mark.parametrize('name', list(CASES))
+def test_mobility_total(name):
+    from paper_1709_06946_amd import pse
+    h, x, L = case(name)
+    r, w = oracle_parts(name)
+    y = _apply(h, x, moments(name), pse.PSE_REAL | pse.PSE_WAVE)
+    errs = block_errors(y, r + w)
+    print(name, 'total', errs)
+    assert max(errs.values()) < TOL, errs
+
+
+def test_mobility_is_linear_and_symmetric():
+    """<a, M b> = <M a, b> for the GPU operator (the grand mobility is
+    symmetric in the stored coordinates)."""
+    from paper_1709_06946_amd import pse
+    h, x, L = case('phi0.1')
+    rng = np.random.default_rng(5)
+    a, b = rng.normal(size=(2, h.n, 11))
+    Ma = _apply(h, x, a, pse.PSE_REAL | pse.PSE_WAVE)
+    Mb = _apply(h, x, b, pse.PSE_REAL | pse.PSE_WAVE)
+    assert abs((a * Mb).sum() - (Ma * b).sum()) < 1e-9 * abs((a * Mb).sum())
+    M2a = _apply(h, x, 2.0 * a, pse.PSE_REAL | pse.PSE_WAVE)
+    assert np.abs(M2a - 2.0 * Ma).max() < 1e-12 * np.abs(Ma).max()
+
+
+@pytest.mark.parametrize('name', list(CASES))
+def test_sampler_wave_same_noise(name):
+    import torch
+    h, x, L = case(name)
+    g = h.derived.grid
+    psi = inputs.wave_noise(g, CASES[name]['seed'] + 3)
+    out = torch.zeros((h.n, 11), dtype=torch.float64, device='cuda:0')
+    h.brownian_sample(dev(x), psi_wave=dev(psi), out_wave=out)
+    ref = brownian.wave_sample(x, psi, L, g, h.derived.xi)
+    errs = block_errors(host(out), ref)
+    print(name, 'wave sampler', errs)
+    assert max(errs.values()) < TOL, errs
+
+
+@pytest.mark.parametrize('name', list(CASES))
+def test_sampler_real_same_noise(name):
+    import torch
+    h, x, L = case(name, lanczos_tol=1e-8)
+    psi = inputs.real_noise(h.n, CASES[name]['seed'] + 4)
+    out = torch.zeros((h.n, 11), dtype=torch.float64, device='cuda:0')
+    rc, st = h.brownian_sample(dev(x), psi_real=dev(psi), out_real=out)
+    ref = brownian.real_sample(x, psi, L, h.derived.xi)
+    errs = block_errors(host(out), ref)
+    print(name, 'real sampler', errs, st)
+    assert rc == 0 and st['converged'] == 1
+    assert max(errs.values()) < TOL, errs
+
+
+def test_sampler_real_default_tolerance():
+    """At the Lanczos tolerance 1e-3 the iterate still matches the principal
+    square root to the same order, in a handful of iterations."""
+    import torch
+    h, x, L = case('phi0.1')
+    psi = inputs.real_noise(h.n, 99)
+    out = torch.zeros((h.n, 11), dtype=torch.float64, device='cuda:0')
+    rc, st = h.brownian_sample(dev(x), psi_real=dev(psi), out_real=out)
+    ref = brownian.real_sample(x, psi, L, h.derived.xi)
+    assert rel_err(host(out), ref) < 2e-3
+    assert st['lanczos_iters'] <= 20
+
+
+def test_philox_noise_statistics():
+    """In-kernel Philox noise: the wave-space sample has the covariance of
+    M_w over the grid (checked on the trace, per particle)."""
+    import torch
+    from paper_1709_06946_amd import pse
+    h, x, L = case('phi0.1')
+    out = torch.zeros((h.n, 11), dtype=torch.float64, device='cuda:0')
+    acc = np.zeros((h.n, 11))
+    nrep = 200
+    for s in range(nrep):
+        h.brownian_sample(dev(x), seed=1234, counter=s, out_wave=out)
+        acc += host(out)**2
+    var = acc / nrep
+    Mw = brownian.wave_dense_grid(x, L, h.derived.grid, h.derived.xi)
+    ref = np.diag(Mw).reshape(h.n, 11)
+    ratio = var.sum() / ref.sum()
+    assert abs(ratio - 1) < 0.03, ratio
+    # same (seed, counter) reproduces the same draw
+    h.brownian_sample(dev(x), seed=7, counter=3, out_wave=out)
+    a = host(out)
+    h.brownian_sample(dev(x), seed=7, counter=3, out_wave=out)
+    assert np.array_equal(a, host(out))
+
+
+@functools.lru_cache(maxsize=None)
+def step_case(name, precision=0, with_noise=True):
+    import torch
+    h, x, L = case(name, precision, lanczos_tol=1e-8, gmres_tol=1e-8)
+    c = CASES[name]
+    g = h.derived.grid
+    FL = inputs.forces_torques(h.n, c['seed'] + 1)
+    if with_noise:
+        psi1 = inputs.real_noise(h.n, c['seed'] + 5)
+        psi2 = inputs.wave_noise(g, c['seed'] + 6)
+    else:
+        psi1 = np.zeros((h.n, 11))
+        psi2 = np.zeros((3, g, g, g // 2 + 1), complex)
+    dt = 1e-3
+    xt = dev(x)
+    slip = torch.zeros((h.n, 11), dtype=torch.float64, device='cuda:0')
+    S = torch.zeros((h.n, 5), dtype=torch.float64, device='cuda:0')
+    U = torch.zeros((h.n, 3), dtype=torch.float64, device='cuda:0')
+    rc, st = h.constrained_step(xt, dev(FL), dt, psi_real=dev(psi1), psi_wave=dev(psi2),
+                                slip=slip, stresslet=S, velocity=U)
+    gpu = dict(x1=host(xt), slip=host(slip), S=host(S), U=host(U), rc=rc, st=st)
+    ref = integrator.midpoint_step(x, FL, psi1, psi2, dt, L, g, h.derived.xi,
+                                   xi_total=7.0 / L)
+    return gpu, ref, x, L, dt
+
+
+@pytest.mark.parametrize('name', list(CASES))
+def test_step_deterministic_constrained_velocity(name):
+    """Without noise the step velocity is the stresslet-constrained mobility
+    applied to the forces and torques (Eq. constrained_vel)."""
+    gpu, ref, x, L, dt = step_case(name, with_noise=False)
+    assert gpu['rc'] == 0 and gpu['st']['converged'] == 1
+    eU, eS = rel_err(gpu['U'], ref['U']), rel_err(gpu['S'], ref['S'])
+    print(name, 'deterministic U', eU, 'S', eS, gpu['st'])
+    assert eU < TOL and eS < TOL
+
+
+@pytest.mark.parametrize('name', list(CASES))
+def test_step_same_noise(name):
+    gpu, ref, x, L, dt = step_case(name)
+    assert gpu['rc'] == 0 and gpu['st']['converged'] == 1
+    errs = dict(slipU=rel_err(gpu['slip'][:, 0:3], ref['slip'][:, 0:3]),
+                slipE=rel_err(gpu['slip'][:, 6:11], ref['slip'][:, 6:11]),
+                S=rel_err(gpu['S'], ref['S']), U=rel_err(gpu['U'], ref['U']))
+    dx = gpu['x1'] - x
+    dx -= L * np.rint(dx / L)
+    errs['dx'] = rel_err(dx, ref['dx'])
+    print(name, 'step', errs, gpu['st'])
+    assert max(errs.values()) < TOL, errs
+    assert np.all((gpu['x1'] >= 0) & (gpu['x1'] < L))
