@@ -1,0 +1,151 @@
+"""Benchmark: stresslet-constrained PSE Brownian dynamics steps on one MI355X.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+
+One "step" is one full mid-point step of the method (Sec. III.D): Lanczos
+M_r^(1/2), wave-space M_w^(1/2), half step, GMRES on the stresslet
+constraint, final mobility product and position update.  The default workload
+is N = 10,000 hard spheres (a = 1) at phi = 0.3 in a 128^3 grid, eps = 1e-3,
+dt = 1e-3, with random non-overlapping positions and N(0, 1) forces/torques.
+Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ('particle-steps/s (FTS Brownian, rel.err 1e-3) vs FP64; '
+          'served p50/p99 step latency')
+HBM_PEAK_GBS = 8000.0
+
+
+def run_form(w, precision, steps, warmup, seed):
+    import torch
+
+    from paper_1709_06946_amd import pse
+    N = w['N']
+    h = pse.PSE(N, w['L'], grid=w['grid'], tol=w['eps'], precision=precision,
+                lanczos_tol=w['lanczos_tol'], gmres_tol=w['gmres_tol'])
+    x = torch.tensor(w['x'], device='cuda:0')
+    FL = torch.tensor(w['FL'], device='cuda:0')
+    for k in range(warmup):
+        h.constrained_step(x, FL, w['dt'], seed=seed, step=k)
+    stats = []
+    h.profile(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        rc, st = h.constrained_step(x, FL, w['dt'], seed=seed, step=warmup + k)
+        stats.append(st)
+        print(f'# step {k} rc={rc} lanczos={st["lanczos_iters"]} gmres={st["gmres_iters"]} '
+              f'res={st["fp64_residual"]:.2e}', file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    h.profile(0)
+    prof = h.profile_read()
+    d = h.derived
+    h.close()
+    dt = t1 - t0
+    return dict(value=N * steps / dt, ms_per_step=1e3 * dt / steps, prof=prof, stats=stats,
+                derived=dict(grid=d.grid, support=d.support, xi=d.xi, rcut=d.rcut,
+                             eta_s=d.eta_s), finite=bool(torch.isfinite(x).all()))
+
+
+def roofline(prof):
+    dom = max(prof, key=lambda k: prof[k]['total_ms'])
+    p = prof[dom]
+    per_launch_bytes = p['alg_bytes'] / p['launches']
+    per_launch_s = p['total_ms'] / p['launches'] / 1e3
+    achieved = per_launch_bytes / per_launch_s / 1e9
+    return dom, dict(bound='hbm', achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit='GB/s',
+                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                     kernel=dom, launches=p['launches'],
+                     avg_us=round(1e6 * per_launch_s, 2),
+                     alg_bytes_per_launch=per_launch_bytes)
+
+
+def cpu_baseline():
+    """The FP64 oracle's mid-point step on a bounded sample of the workload:
+    N = 100 spheres at the same phi = 0.3, tolerance and dt (the dense oracle
+    costs O(N^3); its particle-steps/s at N = 100 bounds it from above)."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+
+    from oracle import integrator
+    from paper_1709_06946_amd import inputs, pse
+    N, phi, grid = 100, 0.3, 32
+    x, L = inputs.packing(N, phi, seed=inputs.SEED_BASE + 50)
+    d = pse.derive(pse.make_params(N, L, grid=grid, tol=1e-3))
+    FL = inputs.forces_torques(N, 1)
+    psi1 = inputs.real_noise(N, 2)
+    psi2 = inputs.wave_noise(grid, 3)
+    t0 = time.perf_counter()
+    reps = 0
+    while True:
+        integrator.midpoint_step(x, FL, psi1, psi2, 1e-3, L, grid, d.xi, xi_total=7.0 / L)
+        reps += 1
+        if time.perf_counter() - t0 > 10.0 or reps >= 5:
+            break
+    dt = (time.perf_counter() - t0) / reps
+    cores = max([i.get('num_threads', 1) for i in threadpool_info()] + [1])
+    return dict(value=round(N / dt, 2), unit='particle-steps/s', cores=int(cores),
+                kind='oracle',
+                sample=f'{reps} oracle mid-point step(s) at N=100, phi=0.3, 32^3 k-set, '
+                       f'eps=1e-3, dt=1e-3 ({dt:.2f} s per step)')
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument('--gpus', type=int, default=1)
+    ap.add_argument('--steps', type=int, default=10)
+    ap.add_argument('--warmup', type=int, default=2)
+    ap.add_argument('--workload', default='n10000_phi0.3_g128')
+    ap.add_argument('--no-cpu-baseline', action='store_true')
+    ap.add_argument('--no-mixed', action='store_true')
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f'bench.py runs on one GPU only (--gpus {args.gpus} requested): the method '
+              'here is the single-GPU hot path; see the sharding notes in DESIGN.md.',
+              file=sys.stderr)
+        sys.exit(2)
+
+    from paper_1709_06946_amd import inputs, pse
+    w = inputs.workload(args.workload)
+    seed = w['seed']
+    fp64 = run_form(w, pse.PSE_FP64, args.steps, args.warmup, seed)
+    dom, roof = roofline(fp64['prof'])
+    mixed = None
+    if not args.no_mixed:
+        m = run_form(w, pse.PSE_MIXED, args.steps, args.warmup, seed)
+        mdom, mroof = roofline(m['prof'])
+        mixed = dict(value=round(m['value'], 1), ms_per_step=round(m['ms_per_step'], 3),
+                     speedup_vs_fp64=round(m['value'] / fp64['value'], 3), dtype='f32+f64',
+                     roofline=mroof,
+                     gmres_iters=[s['gmres_iters'] for s in m['stats']],
+                     fp64_residual=[s['fp64_residual'] for s in m['stats']])
+    gm = [s['gmres_iters'] for s in fp64['stats']]
+    lz = [s['lanczos_iters'] for s in fp64['stats']]
+    out = dict(
+        metric=METRIC, value=round(fp64['value'], 1), unit='particle-steps/s', n_gpus=1,
+        steps=args.steps, warmup=args.warmup, ms_per_step=round(fp64['ms_per_step'], 3),
+        higher_is_better=True, scaling='weak', vs_baseline=None, dtype='f64',
+        data='synthetic',
+        config=dict(workload=args.workload, N=w['N'], phi=w['phi'], L=round(w['L'], 4),
+                    grid=w['grid'], tol=w['eps'], dt=w['dt'], gmres_tol=w['gmres_tol'],
+                    lanczos_tol=w['lanczos_tol'], **fp64['derived']),
+        roofline=roof,
+        krylov=dict(lanczos_iters=lz, gmres_iters=gm),
+        stages_ms={k: round(v['total_ms'] / args.steps, 3) for k, v in fp64['prof'].items()},
+        mixed=mixed,
+    )
+    if not args.no_cpu_baseline:
+        out['cpu_baseline'] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == '__main__':
+    main()

@@ -209,6 +209,26 @@ int pse_spread(pse_handle *h, const double *x, const double *q, int ncomp,
 int pse_interpolate(pse_handle *h, const double *x, const double *grids,
                     int ncomp, double *out);
 
+/* Stage timing (instrumentation).  With profiling on, every kernel launch
+ * of the handle is bracketed by HIP events on the handle's stream and its
+ * duration accumulated per stage, together with the stage's algorithmic
+ * bytes (the data a launch must read or write at least once: the grids it
+ * reads and writes, plus particle data).  pse_profile(h, 1) clears the
+ * totals and starts, pse_profile(h, 0) stops.  Stage names: spread, fft,
+ * kspace, interp, zero, real, cells, krylov, noise. */
+typedef struct pse_kernel_stat {
+  const char *name;        /* static string owned by the library            */
+  int64_t launches;
+  double total_ms;
+  double alg_bytes;        /* summed over the launches                      */
+} pse_kernel_stat;
+
+int pse_profile(pse_handle *h, int enable);
+
+/* Copy up to max stage records to out (host memory); *count receives the
+ * number written. */
+int pse_profile_read(pse_handle *h, pse_kernel_stat *out, int max, int *count);
+
 /* Message for the last failure on this handle (or of the last failed create
  * when h is NULL).  Never NULL. */
 const char *pse_last_error(const pse_handle *h);

@@ -83,7 +83,9 @@ def wave_dense(x, L, xi, a=1.0, eta=1.0, kvec=None, chunk=2048):
         A = (amp[:, None, None, None] * ph[:, None, :, None]
              * PP[:, :, None, :])                              # (K,3,N,11)
         A = A.reshape(-1, 11 * N)
-        M += A.real.T @ A.real + A.imag.T @ A.imag
+        Ar = np.ascontiguousarray(A.real)
+        Ai = np.ascontiguousarray(A.imag)
+        M += Ar.T @ Ar + Ai.T @ Ai
     return M
 
 

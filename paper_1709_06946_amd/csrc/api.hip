@@ -233,6 +233,23 @@ static void stresslet_solve(Handle &h, const double *xh, const double *b, double
   converged = converged && ok;
 }
 
+static const char *kPkNames[PK_COUNT] = {"spread", "fft", "kspace", "interp", "zero",
+                                          "real", "cells", "krylov", "noise", "misc"};
+
+void prof_resolve(Handle &h) {
+  Profiler &P = h.prof;
+  for (const ProfRecord &r : P.pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.start, r.stop) == hipSuccess) {
+      P.ms[r.kind] += ms;
+      P.launches[r.kind] += 1;
+      P.bytes[r.kind] += r.bytes;
+    }
+  }
+  P.pending.clear();
+  P.used = 0;
+}
+
 static void alloc(void **p, size_t bytes) { PSE_HIP(hipMalloc(p, bytes)); }
 
 static void create(const pse_params &p, Handle &h) {
@@ -296,12 +313,18 @@ static void release(Handle &h) {
                   h.v5, h.es_b, h.es_x, h.es_r, h.es_d, h.lz_V, h.gm_V, h.small, h.dots};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
+  for (hipEvent_t e : h.prof.pool) (void)hipEventDestroy(e);
+  h.prof.pool.clear();
   if (h.own_stream && h.stream) (void)hipStreamDestroy(h.stream);
 }
 
 template <typename F> static int guarded(pse_handle *hd, F &&f) {
   try {
     f();
+    if (hd && !hd->h.prof.pending.empty()) {
+      PSE_HIP(hipStreamSynchronize(hd->h.stream));
+      prof_resolve(hd->h);
+    }
     return PSE_OK;
   } catch (const Error &e) {
     if (hd) hd->h.err = e.msg;
@@ -576,6 +599,34 @@ int pse_interpolate(pse_handle *hd, const double *x, const double *g, int ncomp,
     }
     PSE_HIP(hipStreamSynchronize(h.stream));
   });
+}
+
+int pse_profile(pse_handle *hd, int enable) {
+  if (!hd) return PSE_ERR_INVALID;
+  Profiler &P = hd->h.prof;
+  if (enable) {
+    for (int k = 0; k < PK_COUNT; ++k) {
+      P.launches[k] = 0;
+      P.ms[k] = 0;
+      P.bytes[k] = 0;
+    }
+    P.pending.clear();
+    P.used = 0;
+  }
+  P.on = enable != 0;
+  return PSE_OK;
+}
+
+int pse_profile_read(pse_handle *hd, pse_kernel_stat *out, int max, int *count) {
+  if (!hd || !out || !count || max < 0) return PSE_ERR_INVALID;
+  Profiler &P = hd->h.prof;
+  int c = 0;
+  for (int k = 0; k < PK_COUNT && c < max; ++k) {
+    if (P.launches[k] == 0) continue;
+    out[c++] = pse_kernel_stat{kPkNames[k], P.launches[k], P.ms[k], P.bytes[k]};
+  }
+  *count = c;
+  return PSE_OK;
 }
 
 }  // extern "C"

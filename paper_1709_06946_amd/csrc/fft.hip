@@ -181,6 +181,7 @@ void fft3d(Handle &h, cplx<T> *data, const cplx<T> *twiddle, int ncomp, int dir)
   const size_t lds = 2 * (size_t)n * plan.tl * sizeof(cplx<T>);
   const unsigned nb = (unsigned)((size_t)ncomp * n * n / plan.tl);
   for (int pass = 0; pass < 3; ++pass) {
+    ProfScope ps(h, PK_FFT, 2.0 * ncomp * h.ngrid * sizeof(cplx<T>));
     hipLaunchKernelGGL(fft_pass<T>, dim3(nb), dim3(256), lds, h.stream, data,
                        twiddle, plan, pass, dir);
     PSE_LAUNCH_CHECK();

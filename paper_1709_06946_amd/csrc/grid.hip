@@ -506,6 +506,7 @@ template <typename T>
 void spread(Handle &h, const double *x, const double *q, int qstride,
             const CompSet &cs, cplx<T> *grids) {
   const GridGeom g = geom(h);
+  ProfScope ps(h, PK_SPREAD, (double)cs.n * h.ngrid * sizeof(T) + (double)h.n * (3 + cs.n) * 8);
   hipLaunchKernelGGL(spread_kernel<T>, dim3(nblocks(h.n, 4)), dim3(256), 0,
                      h.stream, x, q, qstride, cs, g, (const int *)h.perm, h.n,
                      grids, h.ngrid);
@@ -517,6 +518,7 @@ void interpolate(Handle &h, const double *x, const cplx<T> *grids,
                  const CompSet &cs, double *out, int ostride, bool accumulate,
                  double scale) {
   const GridGeom g = geom(h);
+  ProfScope ps(h, PK_INTERP, (double)cs.n * h.ngrid * sizeof(T) + (double)h.n * (3 + cs.n) * 8);
   hipLaunchKernelGGL(interp_kernel<T>, dim3(nblocks(h.n, 4)), dim3(256), 0,
                      h.stream, x, grids, h.ngrid, cs, g, (const int *)h.perm,
                      h.n, out, ostride, accumulate ? 1 : 0, scale);
@@ -528,6 +530,7 @@ void kspace_mobility(Handle &h, const cplx<T> *in, const CompSet &cin,
                      cplx<T> *out, const CompSet &cout) {
   const int n = h.d.grid;
   const size_t total = (size_t)(n / 2 + 1) * n * n;
+  ProfScope ps(h, PK_KSPACE, (double)((cin.n + 1) / 2 + (cout.n + 1) / 2) * h.ngrid * sizeof(cplx<T>));
   hipLaunchKernelGGL(kspace_mobility_kernel<T>, dim3(nblocks(total, 256)),
                      dim3(256), 0, h.stream, in, cin, out, cout, kgeom(h, false));
   PSE_LAUNCH_CHECK();
@@ -538,6 +541,8 @@ void kspace_noise(Handle &h, const double *psi, uint64_t seed, uint64_t counter,
                   cplx<T> *out, const CompSet &cout) {
   const int n = h.d.grid;
   const size_t total = (size_t)(n / 2 + 1) * n * n;
+  ProfScope ps(h, PK_NOISE, (double)((cout.n + 1) / 2) * h.ngrid * sizeof(cplx<T>)
+                             + (psi ? 3.0 * total * 16 : 0.0));
   hipLaunchKernelGGL(kspace_noise_kernel<T>, dim3(nblocks(total, 256)), dim3(256),
                      0, h.stream, (const double2 *)psi, seed, counter, out, cout,
                      kgeom(h, true));
@@ -552,6 +557,7 @@ void real_noise(Handle &h, uint64_t seed, uint64_t counter, double *out) {
 
 template <typename T> void zero_grids(Handle &h, cplx<T> *g, int npack) {
   const size_t n = (size_t)npack * h.ngrid;
+  ProfScope ps(h, PK_ZERO, (double)n * sizeof(cplx<T>));
   hipLaunchKernelGGL(zero_kernel<T>, dim3(nblocks(n, 256)), dim3(256), 0, h.stream,
                      g, n);
   PSE_LAUNCH_CHECK();

@@ -137,6 +137,7 @@ void multi_dot(Handle &h, const double *V, size_t ldv, int m, const double *w,
   int nb = (int)std::min<size_t>(RED_BLOCKS, (n + 255) / 256);
   if (nb < 1) nb = 1;
   if ((size_t)nb * m > h.dots_len) throw Error{PSE_ERR_INVALID, "reduction scratch too small"};
+  ProfScope ps(h, PK_KRYLOV, (double)(m + 1) * n * 8);
   hipLaunchKernelGGL(multi_dot_partial, dim3(nb, m), dim3(256), 0, h.stream, V, ldv, w, n,
                      h.dots);
   PSE_LAUNCH_CHECK();
@@ -146,6 +147,7 @@ void multi_dot(Handle &h, const double *V, size_t ldv, int m, const double *w,
 
 void vsub_multi(Handle &h, double *w, const double *V, size_t ldv, int m,
                 const double *coef_dev, size_t n) {
+  ProfScope ps(h, PK_KRYLOV, (double)(m + 2) * n * 8);
   hipLaunchKernelGGL(sub_multi_kernel, dim3(nblocks(n, 256)), dim3(256), 0, h.stream, w,
                      V, ldv, m, coef_dev, n);
   PSE_LAUNCH_CHECK();
@@ -153,6 +155,7 @@ void vsub_multi(Handle &h, double *w, const double *V, size_t ldv, int m,
 
 void gemv_small(Handle &h, const double *V, size_t ldv, int m, const double *coef_dev,
                 double *y, size_t n, double alpha, bool accumulate) {
+  ProfScope ps(h, PK_KRYLOV, (double)(m + 1 + (accumulate ? 1 : 0)) * n * 8);
   hipLaunchKernelGGL(gemv_small_kernel, dim3(nblocks(n, 256)), dim3(256), 0, h.stream, V,
                      ldv, m, coef_dev, y, n, alpha, accumulate ? 1 : 0);
   PSE_LAUNCH_CHECK();

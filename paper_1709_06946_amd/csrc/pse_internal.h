@@ -61,6 +61,28 @@ template <typename T> struct GridSet {
   T *table = nullptr;        // real-space coefficient table (ntab x NCOEF)
 };
 
+// Kernel classes timed by the optional profiler.
+enum ProfKind {
+  PK_SPREAD = 0, PK_FFT, PK_KSPACE, PK_INTERP, PK_ZERO, PK_REAL, PK_CELLS,
+  PK_KRYLOV, PK_NOISE, PK_MISC, PK_COUNT
+};
+
+struct ProfRecord {
+  int kind;
+  hipEvent_t start, stop;
+  double bytes;
+};
+
+struct Profiler {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  std::vector<ProfRecord> pending;
+  int64_t launches[PK_COUNT] = {};
+  double ms[PK_COUNT] = {};
+  double bytes[PK_COUNT] = {};
+};
+
 struct Handle {
   pse_params p;
   pse_derived d;
@@ -103,7 +125,35 @@ struct Handle {
   size_t small_len;
   double *dots = nullptr;    // partial sums for reductions
   size_t dots_len;
+
+  Profiler prof;
 };
+
+// Brackets the launches of one stage with events when profiling is on.
+struct ProfScope {
+  Handle &h;
+  int idx = -1;
+  ProfScope(Handle &hh, int kind, double bytes) : h(hh) {
+    if (!h.prof.on) return;
+    Profiler &P = h.prof;
+    while (P.pool.size() < P.used + 2) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return;
+      P.pool.push_back(e);
+    }
+    ProfRecord r{kind, P.pool[P.used], P.pool[P.used + 1], bytes};
+    P.used += 2;
+    (void)hipEventRecord(r.start, h.stream);
+    idx = (int)P.pending.size();
+    P.pending.push_back(r);
+  }
+  ~ProfScope() {
+    if (idx >= 0) (void)hipEventRecord(h.prof.pending[idx].stop, h.stream);
+  }
+};
+
+// Accumulate the pending records (the stream must be idle).
+void prof_resolve(Handle &h);
 
 // ---- params.cpp
 void derive(const pse_params &p, pse_derived &d);

@@ -269,6 +269,7 @@ __global__ void cell_scatter_kernel(const int *__restrict__ cell_of,
 void build_cells(Handle &h, const double *xw) {
   const int nc = h.ncell;
   const int ncells = nc * nc * nc;
+  ProfScope ps(h, PK_CELLS, (double)h.n * (24 + 16) + 12.0 * ncells);
   PSE_HIP(hipMemsetAsync(h.cell_count, 0, ncells * sizeof(int), h.stream));
   hipLaunchKernelGGL(cell_assign_kernel, dim3(nblocks(h.n, 256)), dim3(256), 0,
                      h.stream, xw, h.n, nc, nc / h.p.box, h.cell_of, h.slot,
@@ -501,6 +502,7 @@ void real_apply(Handle &h, const double *xw, const double *in, const CompSet &ci
   ra.accumulate = accumulate ? 1 : 0;
   const T *tab;
   if constexpr (sizeof(T) == 8) tab = h.g64.table; else tab = h.g32.table;
+  ProfScope ps(h, PK_REAL, (double)h.n * (2 * NC * 8 + 3 * 8 + 2 * 4));
   hipLaunchKernelGGL(real_pair_kernel<T>, dim3(nblocks(h.n, 256)), dim3(256), 0,
                      h.stream, xw, in, out, h.perm, h.cell_start, h.cell_of, tab, ra);
   PSE_LAUNCH_CHECK();

@@ -53,10 +53,15 @@ class pse_step_io(ctypes.Structure):
                 ('velocity', ctypes.c_void_p)]
 
 
+class pse_kernel_stat(ctypes.Structure):
+    _fields_ = [('name', ctypes.c_char_p), ('launches', ctypes.c_int64),
+                ('total_ms', ctypes.c_double), ('alg_bytes', ctypes.c_double)]
+
+
 EXPORTS = ('pse_derive', 'pse_footprint_bytes', 'pse_create', 'pse_destroy',
            'pse_get_derived', 'pse_mobility_apply', 'pse_brownian_sample',
            'pse_constrained_step', 'pse_fft3d', 'pse_spread', 'pse_interpolate',
-           'pse_last_error')
+           'pse_profile', 'pse_profile_read', 'pse_last_error')
 
 
 def load_library(path=LIB_PATH):
@@ -78,6 +83,8 @@ def load_library(path=LIB_PATH):
     lib.pse_fft3d.argtypes = [V, V, I, I]
     lib.pse_spread.argtypes = [V, V, V, I, V]
     lib.pse_interpolate.argtypes = [V, V, V, I, V]
+    lib.pse_profile.argtypes = [V, I]
+    lib.pse_profile_read.argtypes = [V, P(pse_kernel_stat), I, P(I)]
     lib.pse_last_error.argtypes = [V]
     lib.pse_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
@@ -213,6 +220,18 @@ class PSE:
             self._h, _ptr(x, (n, 3), 'x'), _ptr(FL, (n, 6), 'FL'), float(dt), seed, step,
             ctypes.byref(io), ctypes.byref(st)), 'pse_constrained_step')
         return rc, st.as_dict()
+
+    def profile(self, enable):
+        return self._check(lib().pse_profile(self._h, int(bool(enable))), 'pse_profile')
+
+    def profile_read(self):
+        arr = (pse_kernel_stat * 16)()
+        cnt = ctypes.c_int()
+        self._check(lib().pse_profile_read(self._h, arr, 16, ctypes.byref(cnt)),
+                    'pse_profile_read')
+        return {arr[i].name.decode(): dict(launches=arr[i].launches, total_ms=arr[i].total_ms,
+                                           alg_bytes=arr[i].alg_bytes)
+                for i in range(cnt.value)}
 
     def fft3d(self, data, direction):
         g = self.derived.grid
