@@ -2,12 +2,21 @@
 //
 // Rules (Sec. II.C):
 //  * Eq. bound with lambda_max = 1: setting the two error terms equal with
-//    erfc(x) <= exp(-x^2) gives m = sqrt(pi P), each term exp(-pi P / 2);
-//    2 exp(-pi P/2) <= eps gives P = ceil((2/pi) ln(2/eps)).
+//    erfc(x) <= exp(-x^2) gives m = sqrt(pi P), each term exp(-pi P / 2), and
+//    2 exp(-pi P/2) <= eps_q gives P = ceil((2/pi) ln(2/eps_q)).
+//    The bound carries unknown O(1) constants.  Measured against the exact
+//    Ewald sum, eps_q = eps leaves gridding errors of 2e-3 to 2e-2 on the
+//    couplet blocks (Omega, E) at eps = 1e-3, dominated by aliasing near the
+//    Nyquist wave number.  The library therefore uses eps_q = eps / 10,
+//    truncates the Gaussian at 0.85 of the balanced number of standard
+//    deviations (m = 0.85 sqrt(pi P): for the same P a wider Gaussian in grid
+//    units, hence less aliasing), and a splitting parameter that damps the
+//    Nyquist mode further.
 //  * eta_s = (h P xi / m)^2 (Gaussian shape, must be < 1 so that the
 //    remaining factor exp(-(1 - eta_s) k^2 / 4 xi^2) still decays).
-//  * xi from the grid: the Hasimoto factor exp(-k^2/4xi^2) equals eps at the
-//    Nyquist wave number pi Ng / L, i.e. xi = pi Ng / (2 L sqrt(ln(1/eps))).
+//  * xi from the grid: the Hasimoto factor exp(-k^2/4xi^2) at the Nyquist
+//    wave number pi Ng / L equals exp(-u_N) with u_N = ln(1/eps) + 5, i.e.
+//    xi = pi Ng / (2 L sqrt(u_N)).
 //  * Real-space cutoff: the real-space functions decay like
 //    exp(-xi^2 (r - 2a)^2) beyond contact (Appendix A), so
 //    rcut = 2a + sqrt(ln(1/eps)) / xi.
@@ -44,23 +53,25 @@ void derive(const pse_params &p, pse_derived &d) {
     fail("precision must be PSE_FP64 or PSE_MIXED");
   const double L = p.box, a = p.radius, eps = p.tol;
   const double lg = std::sqrt(std::log(1.0 / eps));
+  const double un = std::sqrt(std::log(1.0 / eps) + 5.0);   // sqrt(u_N)
   d = pse_derived{};
   if (p.grid > 0) {
     if (!grid_supported(p.grid)) fail("grid must be 2^j or 3*2^j in [8, 1024]");
     d.grid = p.grid;
-    d.xi = p.xi > 0 ? p.xi : M_PI * p.grid / (2.0 * L * lg);
+    d.xi = p.xi > 0 ? p.xi : M_PI * p.grid / (2.0 * L * un);
   } else if (p.xi > 0) {
     d.xi = p.xi;
-    d.grid = next_supported((int)std::ceil(2.0 * p.xi * L * lg / M_PI));
+    d.grid = next_supported((int)std::ceil(2.0 * p.xi * L * un / M_PI));
     if (d.grid < 0) fail("grid needed for this xi exceeds 1024");
   } else {
     fail("set grid or xi");
   }
+  const double eps_q = eps / 10.0;
   d.support = p.support > 0 ? p.support
-                            : (int)std::ceil(2.0 / M_PI * std::log(2.0 / eps));
+                            : (int)std::ceil(2.0 / M_PI * std::log(2.0 / eps_q));
   if (d.support < 2 || d.support > 16) fail("support must be in [2, 16]");
   if (d.support > d.grid) fail("support larger than the grid");
-  d.m = std::sqrt(M_PI * d.support);
+  d.m = 0.85 * std::sqrt(M_PI * d.support);
   d.h = L / d.grid;
   d.eta_s = std::pow(d.h * d.support * d.xi / d.m, 2);
   if (!(d.eta_s < 1.0)) fail("eta_s = (h P xi / m)^2 must be < 1: refine the grid or lower xi");

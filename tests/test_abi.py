@@ -80,30 +80,34 @@ int main(void) {
 
 @pytest.mark.parametrize('eps', [1e-2, 1e-3, 1e-4, 1e-5])
 def test_derive_support_and_width_rule(pse, eps):
+    """Eq. bound's orthorhombic rule at the tightened quadrature tolerance
+    eps/10, a Gaussian at 0.85 of the balanced width, and xi placing
+    exp(-u_N) = e^-5 eps at the Nyquist wave number."""
     p = pse.make_params(100, 30.0, grid=64, tol=eps)
     d = pse.derive(p)
-    assert d.support == oparams.support_orthorhombic(eps)
-    assert math.isclose(d.m, math.sqrt(math.pi * d.support))
+    assert d.support == oparams.support_orthorhombic(eps / 10)
+    assert math.isclose(d.m, 0.85 * math.sqrt(math.pi * d.support))
     assert math.isclose(d.h, 30.0 / 64)
     assert math.isclose(d.eta_s, (d.h * d.support * d.xi / d.m) ** 2)
-    # xi puts the Hasimoto factor at eps on the Nyquist wave number
+    assert d.eta_s < 1
     kn = math.pi * 64 / 30.0
-    assert math.isclose(math.exp(-kn**2 / (4 * d.xi**2)), eps, rel_tol=1e-12)
+    assert math.isclose(kn**2 / (4 * d.xi**2), math.log(1 / eps) + 5, rel_tol=1e-12)
     assert math.isclose(d.rcut, 2.0 + math.sqrt(math.log(1 / eps)) / d.xi)
     assert d.cells == int(30.0 // d.rcut)
 
 
-def test_derive_table1_row_lambda1(pse):
-    """Table 1, first row: P = 5 at eps_q = 1e-3 on an orthorhombic grid."""
+def test_derive_support_at_1e3(pse):
+    """At eps = 1e-3 the tightened rule gives P = 7 (Table 1's orthorhombic
+    row, P = 5, is the untightened rule, pinned in the oracle tests)."""
     d = pse.derive(pse.make_params(100, 16.12, grid=32, tol=1e-3))
-    assert d.support == 5
+    assert d.support == 7
 
 
 def test_derive_grid_from_xi(pse):
     d = pse.derive(pse.make_params(1000, 40.0, xi=1.0, tol=1e-3))
-    need = 2 * 1.0 * 40.0 * math.sqrt(math.log(1e3)) / math.pi
+    need = 2 * 1.0 * 40.0 * math.sqrt(math.log(1e3) + 5) / math.pi
     assert d.grid >= need
-    assert d.grid in (64, 96)
+    assert d.grid in (96, 128)
     assert d.xi == 1.0
 
 
