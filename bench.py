@@ -77,7 +77,7 @@ def cpu_baseline():
 
     from oracle import integrator
     from paper_1709_06946_amd import inputs, pse
-    N, phi, grid = 100, 0.3, 32
+    N, phi, grid = 100, 0.3, 48
     x, L = inputs.packing(N, phi, seed=inputs.SEED_BASE + 50)
     d = pse.derive(pse.make_params(N, L, grid=grid, tol=1e-3))
     FL = inputs.forces_torques(N, 1)
@@ -94,7 +94,7 @@ def cpu_baseline():
     cores = max([i.get('num_threads', 1) for i in threadpool_info()] + [1])
     return dict(value=round(N / dt, 2), unit='particle-steps/s', cores=int(cores),
                 kind='oracle',
-                sample=f'{reps} oracle mid-point step(s) at N=100, phi=0.3, 32^3 k-set, '
+                sample=f'{reps} oracle mid-point step(s) at N=100, phi=0.3, 48^3 k-set, '
                        f'eps=1e-3, dt=1e-3 ({dt:.2f} s per step)')
 
 
@@ -136,7 +136,8 @@ def main():
         data='synthetic',
         config=dict(workload=args.workload, N=w['N'], phi=w['phi'], L=round(w['L'], 4),
                     grid=w['grid'], tol=w['eps'], dt=w['dt'], gmres_tol=w['gmres_tol'],
-                    lanczos_tol=w['lanczos_tol'], **fp64['derived']),
+                    lanczos_tol=w['lanczos_tol'],
+                    derived={k: v for k, v in fp64['derived'].items()}),
         roofline=roof,
         krylov=dict(lanczos_iters=lz, gmres_iters=gm),
         stages_ms={k: round(v['total_ms'] / args.steps, 3) for k, v in fp64['prof'].items()},

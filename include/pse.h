@@ -122,14 +122,15 @@ typedef struct pse_handle pse_handle;
 
 /* Derive Ng, P, xi, eta_s, m, rcut and Krylov defaults from p without any
  * GPU work.  Rules (Sec. II.C, Eq. bound with lambda_max = 1, with the
- * quadrature tolerance tightened to eps/10 because the bound's constants are
- * unknown): P = ceil((2/pi) ln(20/eps)); m = 0.85 sqrt(pi P);
- * xi = pi Ng / (2 L sqrt(ln(1/eps) + 5)), so that the Hasimoto factor
- * exp(-k^2/4xi^2) is e^-5 eps at the Nyquist wave number;
+ * quadrature tolerance tightened to eps/20 because the bound's constants are
+ * unknown): P = ceil((2/pi) ln(40/eps)); m = 0.85 sqrt(pi P);
+ * xi = pi Ng / (2 L sqrt(ln(1/eps) + 9)), so that the Hasimoto factor
+ * exp(-k^2/4xi^2) is e^-9 eps at the Nyquist wave number;
  * eta_s = (h P xi / m)^2; rcut = 2a + sqrt(ln(1/eps))/xi, the real-space
  * functions decaying like exp(-xi^2 (r - 2a)^2) (Appendix A).
- * With these rules every block of the mobility product is within 1e-3 of the
- * exact Ewald sum at eps = 1e-3 (checked against the oracle).
+ * With these rules every block of the mobility product and of the wave-space
+ * square root is within eps of the exact sums at eps = 1e-3 (checked against
+ * the oracle).
  * Returns PSE_ERR_INVALID for inconsistent parameters (eta_s >= 1,
  * rcut > L/3, unsupported Ng, ...). */
 int pse_derive(const pse_params *p, pse_derived *out);

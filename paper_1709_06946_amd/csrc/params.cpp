@@ -7,7 +7,9 @@
 //    The bound carries unknown O(1) constants.  Measured against the exact
 //    Ewald sum, eps_q = eps leaves gridding errors of 2e-3 to 2e-2 on the
 //    couplet blocks (Omega, E) at eps = 1e-3, dominated by aliasing near the
-//    Nyquist wave number.  The library therefore uses eps_q = eps / 10,
+//    Nyquist wave number; the wave-space square root, whose error follows
+//    the square root of the damping at the Nyquist shell, needs still more.
+//    The library therefore uses eps_q = eps / 20,
 //    truncates the Gaussian at 0.85 of the balanced number of standard
 //    deviations (m = 0.85 sqrt(pi P): for the same P a wider Gaussian in grid
 //    units, hence less aliasing), and a splitting parameter that damps the
@@ -15,7 +17,7 @@
 //  * eta_s = (h P xi / m)^2 (Gaussian shape, must be < 1 so that the
 //    remaining factor exp(-(1 - eta_s) k^2 / 4 xi^2) still decays).
 //  * xi from the grid: the Hasimoto factor exp(-k^2/4xi^2) at the Nyquist
-//    wave number pi Ng / L equals exp(-u_N) with u_N = ln(1/eps) + 5, i.e.
+//    wave number pi Ng / L equals exp(-u_N) with u_N = ln(1/eps) + 9, i.e.
 //    xi = pi Ng / (2 L sqrt(u_N)).
 //  * Real-space cutoff: the real-space functions decay like
 //    exp(-xi^2 (r - 2a)^2) beyond contact (Appendix A), so
@@ -53,7 +55,7 @@ void derive(const pse_params &p, pse_derived &d) {
     fail("precision must be PSE_FP64 or PSE_MIXED");
   const double L = p.box, a = p.radius, eps = p.tol;
   const double lg = std::sqrt(std::log(1.0 / eps));
-  const double un = std::sqrt(std::log(1.0 / eps) + 5.0);   // sqrt(u_N)
+  const double un = std::sqrt(std::log(1.0 / eps) + 9.0);   // sqrt(u_N)
   d = pse_derived{};
   if (p.grid > 0) {
     if (!grid_supported(p.grid)) fail("grid must be 2^j or 3*2^j in [8, 1024]");
@@ -66,7 +68,7 @@ void derive(const pse_params &p, pse_derived &d) {
   } else {
     fail("set grid or xi");
   }
-  const double eps_q = eps / 10.0;
+  const double eps_q = eps / 20.0;
   d.support = p.support > 0 ? p.support
                             : (int)std::ceil(2.0 / M_PI * std::log(2.0 / eps_q));
   if (d.support < 2 || d.support > 16) fail("support must be in [2, 16]");

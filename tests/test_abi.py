@@ -81,17 +81,17 @@ int main(void) {
 @pytest.mark.parametrize('eps', [1e-2, 1e-3, 1e-4, 1e-5])
 def test_derive_support_and_width_rule(pse, eps):
     """Eq. bound's orthorhombic rule at the tightened quadrature tolerance
-    eps/10, a Gaussian at 0.85 of the balanced width, and xi placing
-    exp(-u_N) = e^-5 eps at the Nyquist wave number."""
+    eps/20, a Gaussian truncated at 0.85 of the balanced width, and xi placing
+    exp(-u_N) = e^-9 eps at the Nyquist wave number."""
     p = pse.make_params(100, 30.0, grid=64, tol=eps)
     d = pse.derive(p)
-    assert d.support == oparams.support_orthorhombic(eps / 10)
+    assert d.support == oparams.support_orthorhombic(eps / 20)
     assert math.isclose(d.m, 0.85 * math.sqrt(math.pi * d.support))
     assert math.isclose(d.h, 30.0 / 64)
     assert math.isclose(d.eta_s, (d.h * d.support * d.xi / d.m) ** 2)
     assert d.eta_s < 1
     kn = math.pi * 64 / 30.0
-    assert math.isclose(kn**2 / (4 * d.xi**2), math.log(1 / eps) + 5, rel_tol=1e-12)
+    assert math.isclose(kn**2 / (4 * d.xi**2), math.log(1 / eps) + 9, rel_tol=1e-12)
     assert math.isclose(d.rcut, 2.0 + math.sqrt(math.log(1 / eps)) / d.xi)
     assert d.cells == int(30.0 // d.rcut)
 
@@ -105,7 +105,7 @@ def test_derive_support_at_1e3(pse):
 
 def test_derive_grid_from_xi(pse):
     d = pse.derive(pse.make_params(1000, 40.0, xi=1.0, tol=1e-3))
-    need = 2 * 1.0 * 40.0 * math.sqrt(math.log(1e3) + 5) / math.pi
+    need = 2 * 1.0 * 40.0 * math.sqrt(math.log(1e3) + 9) / math.pi
     assert d.grid >= need
     assert d.grid in (96, 128)
     assert d.xi == 1.0

@@ -82,17 +82,17 @@ def _interp_ref(h, x, g):
 @pytest.mark.parametrize('precision', [0, 1])
 def test_spread_and_interpolate(ncomp, precision):
     import torch
-    x, L = packing(60, 0.1, 21)
-    h = _handle(60, L, 32, precision=precision)
+    x, L = packing(100, 0.1, 21)
+    h = _handle(100, L, 32, precision=precision)
     rng = np.random.default_rng(ncomp)
-    q = rng.normal(size=(60, ncomp))
+    q = rng.normal(size=(100, ncomp))
     g = torch.zeros((ncomp, 32, 32, 32), dtype=torch.float64, device='cuda:0')
     h.spread(dev(x), dev(q), g)
     ref = _spread_ref(h, x, q)
     tol = 1e-12 if precision == 0 else 2e-6
     assert np.abs(host(g) - ref).max() < tol * np.abs(ref).max()
     field = rng.normal(size=(ncomp, 32, 32, 32))
-    out = torch.zeros((60, ncomp), dtype=torch.float64, device='cuda:0')
+    out = torch.zeros((100, ncomp), dtype=torch.float64, device='cuda:0')
     h.interpolate(dev(x), dev(field), out)
     ref = _interp_ref(h, x, field)
     assert np.abs(host(out) - ref).max() < tol * np.abs(ref).max()
@@ -102,12 +102,12 @@ def test_spread_handles_positions_outside_box():
     """Positions are wrapped into [0, L): shifting by lattice vectors does not
     change the spread grid."""
     import torch
-    x, L = packing(40, 0.1, 22)
-    h = _handle(40, L, 32)
-    q = np.random.default_rng(1).normal(size=(40, 3))
+    x, L = packing(100, 0.1, 22)
+    h = _handle(100, L, 32)
+    q = np.random.default_rng(1).normal(size=(100, 3))
     g1 = torch.zeros((3, 32, 32, 32), dtype=torch.float64, device='cuda:0')
     g2 = torch.zeros_like(g1)
     h.spread(dev(x), dev(q), g1)
-    shift = L * np.random.default_rng(2).integers(-3, 4, size=(40, 3))
+    shift = L * np.random.default_rng(2).integers(-3, 4, size=(100, 3))
     h.spread(dev(x + shift), dev(q), g2)
     assert np.abs(host(g1) - host(g2)).max() < 1e-12 * np.abs(host(g1)).max()
