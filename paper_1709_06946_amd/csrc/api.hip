@@ -114,13 +114,12 @@ template <typename T>
 static void wave_apply(Handle &h, const double *xw, const double *in, const CompSet &cin,
                        double *out, const CompSet &cout, bool accumulate) {
   GridSet<T> &G = grids<T>(h);
-  const int npi = (cin.n + 1) / 2, npo = (cout.n + 1) / 2;
-  zero_grids<T>(h, G.gin, npi);
-  spread<T>(h, xw, in, NC, cin, G.gin);
-  fft3d<T>(h, G.gin, G.twiddle, npi, -1);
+  T *gin = reinterpret_cast<T *>(G.gin), *gout = reinterpret_cast<T *>(G.gout);
+  spread<T>(h, xw, in, NC, cin, gin);
+  rfft3d<T>(h, gin, G.twiddle, cin.n, -1);
   kspace_mobility<T>(h, G.gin, cin, G.gout, cout);
-  fft3d<T>(h, G.gout, G.twiddle, npo, +1);
-  interpolate<T>(h, xw, G.gout, cout, out, NC, accumulate, 1.0);
+  rfft3d<T>(h, gout, G.twiddle, cout.n, +1);
+  interpolate<T>(h, xw, gout, cout, out, NC, accumulate, 1.0);
 }
 
 // out[cout] = M(cin -> cout) in[cin] at wrapped positions xw whose cell list
@@ -145,10 +144,10 @@ template <typename T>
 static void wave_sqrt_t(Handle &h, const double *xw, const double *psi, uint64_t seed,
                         uint64_t counter, double *out, const CompSet &cout) {
   GridSet<T> &G = grids<T>(h);
-  const int npo = (cout.n + 1) / 2;
+  T *gout = reinterpret_cast<T *>(G.gout);
   kspace_noise<T>(h, psi, seed, counter, G.gout, cout);
-  fft3d<T>(h, G.gout, G.twiddle, npo, +1);
-  interpolate<T>(h, xw, G.gout, cout, out, NC, false, 1.0);
+  rfft3d<T>(h, gout, G.twiddle, cout.n, +1);
+  interpolate<T>(h, xw, gout, cout, out, NC, false, 1.0);
 }
 
 static void wave_sqrt(Handle &h, const double *xw, const double *psi, uint64_t seed,
@@ -258,7 +257,13 @@ static void create(const pse_params &p, Handle &h) {
   h.n = p.n;
   h.mixed = p.precision == PSE_MIXED;
   h.ngrid = (size_t)h.d.grid * h.d.grid * h.d.grid;
-  h.ncell = h.d.cells;
+  h.cells.nc = h.d.cells;
+  // spreading tiles of stile^3 grid points gather from the 27 neighbouring
+  // tiles, so a stencil (P points) must not reach beyond one tile.
+  h.stile = 4;
+  while (h.stile < 16 && (h.d.support + 1) / 2 > h.stile) h.stile *= 2;
+  if (h.d.grid % h.stile != 0 || h.d.grid / h.stile < 3) h.stile = 0;
+  h.sbins.nc = h.stile ? h.d.grid / h.stile : 0;
   if (p.stream) {
     h.stream = (hipStream_t)p.stream;
     h.own_stream = false;
@@ -283,13 +288,16 @@ static void create(const pse_params &p, Handle &h) {
     PSE_LAUNCH_CHECK();
   }
   build_tables(h);
-  const size_t ncells = (size_t)h.ncell * h.ncell * h.ncell;
-  alloc((void **)&h.cell_start, (ncells + 1) * sizeof(int));
-  alloc((void **)&h.cell_count, ncells * sizeof(int));
-  alloc((void **)&h.scan_tmp, ((ncells + 1023) / 1024 + 8) * sizeof(int));
-  alloc((void **)&h.cell_of, n * sizeof(int));
-  alloc((void **)&h.slot, n * sizeof(int));
-  alloc((void **)&h.perm, n * sizeof(int));
+  for (Bins *b : {&h.cells, &h.sbins}) {
+    if (b->nc == 0) continue;
+    const size_t ncells = (size_t)b->nc * b->nc * b->nc;
+    alloc((void **)&b->start, (ncells + 1) * sizeof(int));
+    alloc((void **)&b->count, ncells * sizeof(int));
+    alloc((void **)&b->scan_tmp, ((ncells + 1023) / 1024 + 8) * sizeof(int));
+    alloc((void **)&b->of, n * sizeof(int));
+    alloc((void **)&b->slot, n * sizeof(int));
+    alloc((void **)&b->perm, n * sizeof(int));
+  }
   alloc((void **)&h.xw, 3 * n * sizeof(double));
   alloc((void **)&h.xh, 3 * n * sizeof(double));
   double **vs[6] = {&h.v0, &h.v1, &h.v2, &h.v3, &h.v4, &h.v5};
@@ -308,9 +316,11 @@ static void create(const pse_params &p, Handle &h) {
 
 static void release(Handle &h) {
   void *ptrs[] = {h.g64.gin, h.g64.gout, h.g64.twiddle, h.g64.table, h.g32.gin, h.g32.gout,
-                  h.g32.twiddle, h.g32.table, h.cell_start, h.cell_count, h.scan_tmp,
-                  h.cell_of, h.slot, h.perm, h.xw, h.xh, h.v0, h.v1, h.v2, h.v3, h.v4,
-                  h.v5, h.es_b, h.es_x, h.es_r, h.es_d, h.lz_V, h.gm_V, h.small, h.dots};
+                  h.g32.twiddle, h.g32.table, h.cells.start, h.cells.count,
+                  h.cells.scan_tmp, h.cells.of, h.cells.slot, h.cells.perm, h.sbins.start,
+                  h.sbins.count, h.sbins.scan_tmp, h.sbins.of, h.sbins.slot, h.sbins.perm,
+                  h.xw, h.xh, h.v0, h.v1, h.v2, h.v3, h.v4, h.v5, h.es_b, h.es_x, h.es_r,
+                  h.es_d, h.lz_V, h.gm_V, h.small, h.dots};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   for (hipEvent_t e : h.prof.pool) (void)hipEventDestroy(e);
@@ -565,15 +575,15 @@ int pse_spread(pse_handle *hd, const double *x, const double *q, int ncomp, doub
     Handle &h = hd->h;
     prepare_positions(h, x, h.xw);
     const CompSet cs = comps_range(0, ncomp);
-    const int np = (ncomp + 1) / 2;
+    const size_t cnt = (size_t)ncomp * h.ngrid;
     if (h.mixed) {
-      zero_grids<float>(h, h.g32.gin, np);
-      spread<float>(h, h.xw, q, ncomp, cs, h.g32.gin);
-      packed_to_real<float>(h, h.g32.gin, ncomp, out);
+      float *g = reinterpret_cast<float *>(h.g32.gin);
+      spread<float>(h, h.xw, q, ncomp, cs, g);
+      to_double<float>(h, g, cnt, out);
     } else {
-      zero_grids<double>(h, h.g64.gin, np);
-      spread<double>(h, h.xw, q, ncomp, cs, h.g64.gin);
-      packed_to_real<double>(h, h.g64.gin, ncomp, out);
+      double *g = reinterpret_cast<double *>(h.g64.gin);
+      spread<double>(h, h.xw, q, ncomp, cs, g);
+      to_double<double>(h, g, cnt, out);
     }
     PSE_HIP(hipStreamSynchronize(h.stream));
   });
@@ -590,12 +600,15 @@ int pse_interpolate(pse_handle *hd, const double *x, const double *g, int ncomp,
     Handle &h = hd->h;
     prepare_positions(h, x, h.xw);
     const CompSet cs = comps_range(0, ncomp);
+    const size_t cnt = (size_t)ncomp * h.ngrid;
     if (h.mixed) {
-      real_to_packed<float>(h, g, ncomp, h.g32.gout);
-      interpolate<float>(h, h.xw, h.g32.gout, cs, out, ncomp, false, 1.0);
+      float *gg = reinterpret_cast<float *>(h.g32.gout);
+      from_double<float>(h, g, cnt, gg);
+      interpolate<float>(h, h.xw, gg, cs, out, ncomp, false, 1.0);
     } else {
-      real_to_packed<double>(h, g, ncomp, h.g64.gout);
-      interpolate<double>(h, h.xw, h.g64.gout, cs, out, ncomp, false, 1.0);
+      double *gg = reinterpret_cast<double *>(h.g64.gout);
+      from_double<double>(h, g, cnt, gg);
+      interpolate<double>(h, h.xw, gg, cs, out, ncomp, false, 1.0);
     }
     PSE_HIP(hipStreamSynchronize(h.stream));
   });

@@ -1,12 +1,10 @@
 // Wave-space stages of the NUFFT mobility (Sec. II.C, Eq. WSops2) and of the
 // wave-space square root (Sec. III.C, Eq. FFTsqrt).
 //
-// Grids: the G real component grids of one operator application are packed
-// two per complex grid (component 2p in the real part of packed grid p,
-// component 2p+1 in the imaginary part), so every transform is a plain
-// complex FFT and a real grid pair costs one complex transform.  The k-space
-// kernels separate the pair with the Hermitian symmetry of real-grid spectra:
-//   G_2p(k) = (Z(k) + conj Z(-k)) / 2,  G_2p+1(k) = (Z(k) - conj Z(-k)) / 2i.
+// Grids: each of the G real components of one operator application has its
+// own real grid [c][z][y][x]; the real FFT turns it in place into a half
+// spectrum [c][kz][ky][kx < n/2] (fft.hip), so the k-space kernels act on one
+// wave vector at a time and the other half follows by Hermitian symmetry.
 //
 // Gaussian kernel (Sec. II.C): K(r) = (2 xi^2/(pi eta_s))^(3/2)
 // exp(-2 xi^2 r^2 / eta_s), truncated to the P^3 nearest grid points, whose
@@ -41,7 +39,7 @@ template <typename T>
 __global__ void __launch_bounds__(256)
 spread_kernel(const double *__restrict__ x, const double *__restrict__ q,
               int qstride, CompSet cs, GridGeom g, const int *__restrict__ order,
-              int64_t n, cplx<T> *__restrict__ grids, size_t ngrid) {
+              int64_t n, T *__restrict__ grids, size_t ngrid) {
   const int lane = threadIdx.x & 63;
   const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (t >= n) return;
@@ -65,11 +63,113 @@ spread_kernel(const double *__restrict__ x, const double *__restrict__ q,
                       + wrapi(ix0 + a, g.ng);
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
-      if (k < cs.n) {
-        cplx<T> *cell = grids + (size_t)(k >> 1) * ngrid + gi;
-        atomicAdd((k & 1) ? &cell->y : &cell->x, w * qv[k]);
+      if (k < cs.n) atomicAdd(grids + (size_t)k * ngrid + gi, w * qv[k]);
+    }
+  }
+}
+
+// Gather form of the same sum: one workgroup per tile of S^3 grid points.
+// Every particle whose stencil meets the tile lies in the 27 bins around it
+// (the stencil reaches at most (P+1)/2 <= S points past its own bin); their
+// positions, stencil origins and moments are staged in LDS in chunks, and
+// each thread sums the Gaussians over its grid points.  Every grid point is
+// written exactly once: no atomics and no zeroing pass.
+constexpr int GMAXC = 128;
+
+template <typename T, int S>
+__global__ void __launch_bounds__(S * S * S < 256 ? S * S * S : 256)
+spread_gather_kernel(const double *__restrict__ x, const double *__restrict__ q,
+                     int qstride, CompSet cs, GridGeom g, int nb,
+                     const int *__restrict__ bstart, const int *__restrict__ bperm,
+                     T *__restrict__ grids, size_t ngrid) {
+  constexpr int NT = S * S * S < 256 ? S * S * S : 256;
+  constexpr int PPT = S * S * S / NT;
+  __shared__ int pre[28];
+  __shared__ int bfirst[27];
+  __shared__ double cxs[GMAXC], cys[GMAXC], czs[GMAXC];
+  __shared__ int sxs[GMAXC], sys[GMAXC], szs[GMAXC];
+  __shared__ T cq[NC][GMAXC];
+  const int tile = blockIdx.x;
+  const int tx = tile % nb, ty = (tile / nb) % nb, tz = tile / (nb * nb);
+  if (threadIdx.x < 27) {
+    const int o = threadIdx.x;
+    const int bx = (tx + o % 3 - 1 + nb) % nb;
+    const int by = (ty + (o / 3) % 3 - 1 + nb) % nb;
+    const int bz = (tz + o / 9 - 1 + nb) % nb;
+    const int b = (bz * nb + by) * nb + bx;
+    bfirst[o] = bstart[b];
+    pre[o + 1] = bstart[b + 1] - bstart[b];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    pre[0] = 0;
+    for (int o = 0; o < 27; ++o) pre[o + 1] += pre[o];
+  }
+  __syncthreads();
+  const int total = pre[27];
+  const int P = g.P, ng = g.ng;
+  const double kn3 = g.knorm * g.knorm * g.knorm;
+  int gx[PPT], gy[PPT], gz[PPT];
+  T acc[PPT][NC];
+#pragma unroll
+  for (int pt = 0; pt < PPT; ++pt) {
+    const int l = threadIdx.x + pt * NT;
+    gx[pt] = tx * S + l % S;
+    gy[pt] = ty * S + (l / S) % S;
+    gz[pt] = tz * S + l / (S * S);
+#pragma unroll
+    for (int k = 0; k < NC; ++k) acc[pt][k] = (T)0;
+  }
+  for (int c0 = 0; c0 < total; c0 += GMAXC) {
+    __syncthreads();
+    for (int t = threadIdx.x; t < GMAXC; t += NT) {
+      const int idx = c0 + t;
+      if (idx < total) {
+        int o = 0;
+        while (pre[o + 1] <= idx) ++o;
+        const int p = bperm[bfirst[o] + idx - pre[o]];
+        const double px = x[3 * p], py = x[3 * p + 1], pz = x[3 * p + 2];
+        cxs[t] = px;
+        cys[t] = py;
+        czs[t] = pz;
+        sxs[t] = stencil_start(px, g.h, P);
+        sys[t] = stencil_start(py, g.h, P);
+        szs[t] = stencil_start(pz, g.h, P);
+#pragma unroll
+        for (int k = 0; k < NC; ++k)
+          cq[k][t] = k < cs.n ? (T)q[(size_t)p * qstride + cs.idx[k]] : (T)0;
       }
     }
+    __syncthreads();
+    const int nchunk = min(GMAXC, total - c0);
+    for (int j = 0; j < nchunk; ++j) {
+#pragma unroll
+      for (int pt = 0; pt < PPT; ++pt) {
+        int ax = gx[pt] - sxs[j];
+        ax += ax < 0 ? ng : (ax >= ng ? -ng : 0);
+        if (ax >= P) continue;
+        int ay = gy[pt] - sys[j];
+        ay += ay < 0 ? ng : (ay >= ng ? -ng : 0);
+        if (ay >= P) continue;
+        int az = gz[pt] - szs[j];
+        az += az < 0 ? ng : (az >= ng ? -ng : 0);
+        if (az >= P) continue;
+        const double dx = (sxs[j] + ax) * g.h - cxs[j];
+        const double dy = (sys[j] + ay) * g.h - cys[j];
+        const double dz = (szs[j] + az) * g.h - czs[j];
+        const T w = (T)(kn3 * exp(-g.kcoef * (dx * dx + dy * dy + dz * dz)));
+#pragma unroll
+        for (int k = 0; k < NC; ++k)
+          if (k < cs.n) acc[pt][k] += w * cq[k][j];
+      }
+    }
+  }
+#pragma unroll
+  for (int pt = 0; pt < PPT; ++pt) {
+    const size_t gi = ((size_t)gz[pt] * ng + gy[pt]) * ng + gx[pt];
+#pragma unroll
+    for (int k = 0; k < NC; ++k)
+      if (k < cs.n) grids[(size_t)k * ngrid + gi] = acc[pt][k];
   }
 }
 
@@ -77,7 +177,7 @@ spread_kernel(const double *__restrict__ x, const double *__restrict__ q,
 
 template <typename T>
 __global__ void __launch_bounds__(256)
-interp_kernel(const double *__restrict__ x, const cplx<T> *__restrict__ grids,
+interp_kernel(const double *__restrict__ x, const T *__restrict__ grids,
               size_t ngrid, CompSet cs, GridGeom g, const int *__restrict__ order,
               int64_t n, double *__restrict__ out, int ostride, int accumulate,
               double scale) {
@@ -103,13 +203,8 @@ interp_kernel(const double *__restrict__ x, const cplx<T> *__restrict__ grids,
     const size_t gi = ((size_t)wrapi(iz0 + c, g.ng) * g.ng + wrapi(iy0 + b, g.ng)) * g.ng
                       + wrapi(ix0 + a, g.ng);
 #pragma unroll
-    for (int k = 0; k < NC; k += 2) {
-      if (k < cs.n) {
-        const cplx<T> z = grids[(size_t)(k >> 1) * ngrid + gi];
-        acc[k] += w * z.x;
-        if (k + 1 < NC) acc[k + 1] += w * z.y;
-      }
-    }
+    for (int k = 0; k < NC; ++k)
+      if (k < cs.n) acc[k] += w * grids[(size_t)k * ngrid + gi];
   }
 #pragma unroll
   for (int k = 0; k < NC; ++k) {
@@ -149,21 +244,6 @@ __device__ __forceinline__ void shape_factors(double x, double &j0, double &f1) 
     j0 = s / x;
     f1 = (s - x * c) / (x * x * x);
   }
-}
-
-// The canonical member of each pair {k, -k} handled by one thread, and which
-// modes are zeroed (Nyquist index in any direction, or k = 0).  Threads run
-// over ix in [0, n/2], all iy, iz.  Returns 0 = skip, 1 = zero the mode (and
-// nothing else), 2 = process the pair.
-__device__ __forceinline__ int classify(int ix, int iy, int iz, int n) {
-  const int h = n / 2;
-  if (ix == h || iy == h || iz == h) return 1;
-  if (ix > 0) return 2;
-  // ix == 0: the partner also has ix == 0
-  if (iy > 0 && iy < h) return 2;
-  if (iy == 0 && iz > 0 && iz < h) return 2;
-  if (iy == 0 && iz == 0) return 1;
-  return 0;  // handled by the partner
 }
 
 struct KGeom {
@@ -254,49 +334,38 @@ __device__ __forceinline__ C apply_Pdag(int c, const C *u, const double *kv,
   return w;
 }
 
+// Stored half-spectrum mode (ix < n/2, iy, iz): 0 = process, 1 = zero it
+// (a Nyquist index in y or z, or k = 0; the x Nyquist column is not stored).
+__device__ __forceinline__ bool zero_mode(int ix, int iy, int iz, int n) {
+  const int h = n / 2;
+  return iy == h || iz == h || (ix == 0 && iy == 0 && iz == 0);
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256)
 kspace_mobility_kernel(const cplx<T> *__restrict__ in, CompSet cin,
                        cplx<T> *__restrict__ out, CompSet cout, KGeom kg) {
   using C = cplx<T>;
-  const int n = kg.ng, hx = n / 2 + 1;
-  const size_t total = (size_t)hx * n * n;
+  const int n = kg.ng, hx = n / 2;
+  const size_t hsz = (size_t)hx * n * n;            // modes per component
   const size_t tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (tid >= total) return;
+  if (tid >= hsz) return;
   const int ix = (int)(tid % hx);
   const int iy = (int)((tid / hx) % n);
   const int iz = (int)(tid / ((size_t)hx * n));
-  const int cls = classify(ix, iy, iz, n);
-  if (cls == 0) return;
-  const size_t ngrid = (size_t)n * n * n;
-  const size_t kp = ((size_t)iz * n + iy) * n + ix;
-  const size_t km = ((size_t)((n - iz) % n) * n + (n - iy) % n) * n + (n - ix) % n;
-  const int npo = (cout.n + 1) / 2;
-  if (cls == 1) {
-    for (int q = 0; q < npo; ++q) {
-      out[q * ngrid + kp] = C{(T)0, (T)0};
-      out[q * ngrid + km] = C{(T)0, (T)0};
-    }
+  if (zero_mode(ix, iy, iz, n)) {
+    for (int q = 0; q < cout.n; ++q) out[q * hsz + tid] = C{(T)0, (T)0};
     return;
   }
-  const double kv[3] = {kg.twopi_L * kidx(ix, n), kg.twopi_L * kidx(iy, n),
-                        kg.twopi_L * kidx(iz, n)};
+  const double kv[3] = {kg.twopi_L * ix, kg.twopi_L * kidx(iy, n), kg.twopi_L * kidx(iz, n)};
   const double k2 = kv[0] * kv[0] + kv[1] * kv[1] + kv[2] * kv[2];
   const double kk = sqrt(k2);
   double j0, f1;
   shape_factors(kk * kg.a, j0, f1);
   double2 rho[3] = {{0, 0}, {0, 0}, {0, 0}};
-  const int npi = (cin.n + 1) / 2;
-  for (int p = 0; p < npi; ++p) {
-    const C zp = in[p * ngrid + kp], zm = in[p * ngrid + km];
-    // G_2p = (Z(k) + conj Z(-k)) / 2 ; G_2p+1 = (Z(k) - conj Z(-k)) / 2i
-    double2 ga{0.5 * ((double)zp.x + zm.x), 0.5 * ((double)zp.y - zm.y)};
-    add_P(cin.idx[2 * p], ga, kv, j0, f1, rho);
-    if (2 * p + 1 < cin.n) {
-      const double dre = (double)zp.x - zm.x, dim = (double)zp.y + zm.y;
-      double2 gb{0.5 * dim, -0.5 * dre};
-      add_P(cin.idx[2 * p + 1], gb, kv, j0, f1, rho);
-    }
+  for (int p = 0; p < cin.n; ++p) {
+    const C z = in[p * hsz + tid];
+    add_P(cin.idx[p], double2{(double)z.x, (double)z.y}, kv, j0, f1, rho);
   }
   // u = scale (I - kk) rho
   const double u = k2 * kg.inv4xi2;
@@ -311,13 +380,9 @@ kspace_mobility_kernel(const cplx<T> *__restrict__ in, CompSet cin,
     uu[m].x = scale * (rho[m].x - kv[m] * kr.x / k2);
     uu[m].y = scale * (rho[m].y - kv[m] * kr.y / k2);
   }
-  for (int q = 0; q < npo; ++q) {
-    const double2 wa = apply_Pdag(cout.idx[2 * q], uu, kv, j0, f1);
-    double2 wb{0, 0};
-    if (2 * q + 1 < cout.n) wb = apply_Pdag(cout.idx[2 * q + 1], uu, kv, j0, f1);
-    // Z(k) = Wa + i Wb ; Z(-k) = conj(Wa) + i conj(Wb)
-    out[q * ngrid + kp] = C{(T)(wa.x - wb.y), (T)(wa.y + wb.x)};
-    out[q * ngrid + km] = C{(T)(wa.x + wb.y), (T)(-wa.y + wb.x)};
+  for (int q = 0; q < cout.n; ++q) {
+    const double2 w = apply_Pdag(cout.idx[q], uu, kv, j0, f1);
+    out[q * hsz + tid] = C{(T)w.x, (T)w.y};
   }
 }
 
@@ -365,48 +430,46 @@ __device__ __forceinline__ void philox_normals(uint64_t seed, uint64_t counter,
 
 enum : uint32_t { STREAM_REAL = 1, STREAM_WAVE = 2 };
 
-// Wave-space square root (Eq. FFTsqrt): for each canonical k,
+// Wave-space square root (Eq. FFTsqrt): for each stored mode k,
 //   u(k) = h^3 / sqrt(V eta) sqrt(1 + k^2/4xi^2) exp(-(1 - eta_s) k^2/8xi^2) / k
-//          (I - kk) psi(k),
-//   W_c(k) = P_c^+(k) u(k),  W_c(-k) = conj W_c(k).
+//          (I - kk) psi(k),   W_c(k) = P_c^+(k) u(k),
+// with psi read (or drawn) at the canonical member of {k, -k}; the stored
+// modes with kx = 0 outside the canonical half take conj psi(-k), so that the
+// spectrum is Hermitian.
 template <typename T>
 __global__ void __launch_bounds__(256)
 kspace_noise_kernel(const double2 *__restrict__ psi, uint64_t seed,
                     uint64_t counter, cplx<T> *__restrict__ out, CompSet cout,
                     KGeom kg) {
   using C = cplx<T>;
-  const int n = kg.ng, hx = n / 2 + 1;
-  const size_t total = (size_t)hx * n * n;
+  const int n = kg.ng, hx = n / 2, hp = n / 2 + 1;
+  const size_t hsz = (size_t)hx * n * n;
   const size_t tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (tid >= total) return;
+  if (tid >= hsz) return;
   const int ix = (int)(tid % hx);
   const int iy = (int)((tid / hx) % n);
   const int iz = (int)(tid / ((size_t)hx * n));
-  const int cls = classify(ix, iy, iz, n);
-  if (cls == 0) return;
-  const size_t ngrid = (size_t)n * n * n;
-  const size_t kp = ((size_t)iz * n + iy) * n + ix;
-  const size_t km = ((size_t)((n - iz) % n) * n + (n - iy) % n) * n + (n - ix) % n;
-  const int npo = (cout.n + 1) / 2;
-  if (cls == 1) {
-    for (int q = 0; q < npo; ++q) {
-      out[q * ngrid + kp] = C{(T)0, (T)0};
-      out[q * ngrid + km] = C{(T)0, (T)0};
-    }
+  if (zero_mode(ix, iy, iz, n)) {
+    for (int q = 0; q < cout.n; ++q) out[q * hsz + tid] = C{(T)0, (T)0};
     return;
   }
+  // canonical member: kx > 0; or kx = 0 and ky in (0, n/2); or kx = ky = 0, kz in (0, n/2)
+  const bool canon = ix > 0 || (iy > 0 && iy < hx) || (iy == 0 && iz < hx);
+  const int cy = canon ? iy : (n - iy) % n, cz = canon ? iz : (n - iz) % n;
+  const size_t cidx = ((size_t)cz * n + cy) * hp + ix;   // index in the noise layout
   double2 ps[3];
   if (psi) {
-    const size_t hsz = (size_t)n * n * hx;
-    for (int m = 0; m < 3; ++m) ps[m] = psi[m * hsz + tid];
+    const size_t psz = (size_t)n * n * hp;
+    for (int m = 0; m < 3; ++m) ps[m] = psi[m * psz + cidx];
   } else {
     double z[8];
-    philox_normals(seed, counter, STREAM_WAVE, (uint32_t)tid, 2, z);
+    philox_normals(seed, counter, STREAM_WAVE, (uint32_t)cidx, 2, z);
     const double s = 0.70710678118654752440;
     for (int m = 0; m < 3; ++m) ps[m] = double2{s * z[2 * m], s * z[2 * m + 1]};
   }
-  const double kv[3] = {kg.twopi_L * kidx(ix, n), kg.twopi_L * kidx(iy, n),
-                        kg.twopi_L * kidx(iz, n)};
+  if (!canon)
+    for (int m = 0; m < 3; ++m) ps[m].y = -ps[m].y;
+  const double kv[3] = {kg.twopi_L * ix, kg.twopi_L * kidx(iy, n), kg.twopi_L * kidx(iz, n)};
   const double k2 = kv[0] * kv[0] + kv[1] * kv[1] + kv[2] * kv[2];
   const double kk = sqrt(k2);
   double j0, f1;
@@ -423,12 +486,9 @@ kspace_noise_kernel(const double2 *__restrict__ psi, uint64_t seed,
     uu[m].x = amp * (ps[m].x - kv[m] * kr.x / k2);
     uu[m].y = amp * (ps[m].y - kv[m] * kr.y / k2);
   }
-  for (int q = 0; q < npo; ++q) {
-    const double2 wa = apply_Pdag(cout.idx[2 * q], uu, kv, j0, f1);
-    double2 wb{0, 0};
-    if (2 * q + 1 < cout.n) wb = apply_Pdag(cout.idx[2 * q + 1], uu, kv, j0, f1);
-    out[q * ngrid + kp] = C{(T)(wa.x - wb.y), (T)(wa.y + wb.x)};
-    out[q * ngrid + km] = C{(T)(wa.x + wb.y), (T)(-wa.y + wb.x)};
+  for (int q = 0; q < cout.n; ++q) {
+    const double2 w = apply_Pdag(cout.idx[q], uu, kv, j0, f1);
+    out[q * hsz + tid] = C{(T)w.x, (T)w.y};
   }
 }
 
@@ -445,34 +505,21 @@ __global__ void real_noise_kernel(uint64_t seed, uint64_t counter, int64_t n,
 // --------------------------------------------------------- small kernels --
 
 template <typename T>
-__global__ void zero_kernel(cplx<T> *g, size_t n) {
+__global__ void zero_kernel(T *g, size_t n) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) g[i] = cplx<T>{(T)0, (T)0};
+  if (i < n) g[i] = (T)0;
 }
 
 template <typename T>
-__global__ void real_to_packed_kernel(const double *src, int ncomp, size_t ngrid,
-                                      cplx<T> *dst) {
+__global__ void from_double_kernel(const double *src, size_t n, T *dst) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= ngrid) return;
-  for (int c = 0; c < ncomp; c += 2) {
-    cplx<T> z;
-    z.x = (T)src[c * ngrid + i];
-    z.y = c + 1 < ncomp ? (T)src[(c + 1) * ngrid + i] : (T)0;
-    dst[(c / 2) * ngrid + i] = z;
-  }
+  if (i < n) dst[i] = (T)src[i];
 }
 
 template <typename T>
-__global__ void packed_to_real_kernel(const cplx<T> *src, int ncomp, size_t ngrid,
-                                      double *dst) {
+__global__ void to_double_kernel(const T *src, size_t n, double *dst) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= ngrid) return;
-  for (int c = 0; c < ncomp; c += 2) {
-    const cplx<T> z = src[(c / 2) * ngrid + i];
-    dst[c * ngrid + i] = z.x;
-    if (c + 1 < ncomp) dst[(c + 1) * ngrid + i] = z.y;
-  }
+  if (i < n) dst[i] = (double)src[i];
 }
 
 // ----------------------------------------------------------- host side --
@@ -504,23 +551,40 @@ static KGeom kgeom(const Handle &h, bool noise) {
 
 template <typename T>
 void spread(Handle &h, const double *x, const double *q, int qstride,
-            const CompSet &cs, cplx<T> *grids) {
+            const CompSet &cs, T *grids) {
   const GridGeom g = geom(h);
+  if (h.stile) {
+    ProfScope ps(h, PK_SPREAD, (double)cs.n * h.ngrid * sizeof(T) + (double)h.n * (3 + cs.n) * 8);
+    const int nb = h.sbins.nc;
+    const unsigned tiles = (unsigned)nb * nb * nb;
+    if (h.stile == 4)
+      hipLaunchKernelGGL((spread_gather_kernel<T, 4>), dim3(tiles), dim3(64), 0, h.stream, x,
+                         q, qstride, cs, g, nb, (const int *)h.sbins.start,
+                         (const int *)h.sbins.perm, grids, h.ngrid);
+    else if (h.stile == 8)
+      hipLaunchKernelGGL((spread_gather_kernel<T, 8>), dim3(tiles), dim3(256), 0, h.stream, x,
+                         q, qstride, cs, g, nb, (const int *)h.sbins.start,
+                         (const int *)h.sbins.perm, grids, h.ngrid);
+    else
+      throw Error{PSE_ERR_INVALID, "unsupported spreading tile"};
+    PSE_LAUNCH_CHECK();
+    return;
+  }
+  zero_grids<T>(h, grids, cs.n);
   ProfScope ps(h, PK_SPREAD, (double)cs.n * h.ngrid * sizeof(T) + (double)h.n * (3 + cs.n) * 8);
   hipLaunchKernelGGL(spread_kernel<T>, dim3(nblocks(h.n, 4)), dim3(256), 0,
-                     h.stream, x, q, qstride, cs, g, (const int *)h.perm, h.n,
+                     h.stream, x, q, qstride, cs, g, (const int *)h.cells.perm, h.n,
                      grids, h.ngrid);
   PSE_LAUNCH_CHECK();
 }
 
 template <typename T>
-void interpolate(Handle &h, const double *x, const cplx<T> *grids,
-                 const CompSet &cs, double *out, int ostride, bool accumulate,
-                 double scale) {
+void interpolate(Handle &h, const double *x, const T *grids, const CompSet &cs,
+                 double *out, int ostride, bool accumulate, double scale) {
   const GridGeom g = geom(h);
   ProfScope ps(h, PK_INTERP, (double)cs.n * h.ngrid * sizeof(T) + (double)h.n * (3 + cs.n) * 8);
   hipLaunchKernelGGL(interp_kernel<T>, dim3(nblocks(h.n, 4)), dim3(256), 0,
-                     h.stream, x, grids, h.ngrid, cs, g, (const int *)h.perm,
+                     h.stream, x, grids, h.ngrid, cs, g, (const int *)h.cells.perm,
                      h.n, out, ostride, accumulate ? 1 : 0, scale);
   PSE_LAUNCH_CHECK();
 }
@@ -528,10 +592,9 @@ void interpolate(Handle &h, const double *x, const cplx<T> *grids,
 template <typename T>
 void kspace_mobility(Handle &h, const cplx<T> *in, const CompSet &cin,
                      cplx<T> *out, const CompSet &cout) {
-  const int n = h.d.grid;
-  const size_t total = (size_t)(n / 2 + 1) * n * n;
-  ProfScope ps(h, PK_KSPACE, (double)((cin.n + 1) / 2 + (cout.n + 1) / 2) * h.ngrid * sizeof(cplx<T>));
-  hipLaunchKernelGGL(kspace_mobility_kernel<T>, dim3(nblocks(total, 256)),
+  const size_t hsz = h.ngrid / 2;
+  ProfScope ps(h, PK_KSPACE, (double)(cin.n + cout.n) * hsz * sizeof(cplx<T>));
+  hipLaunchKernelGGL(kspace_mobility_kernel<T>, dim3(nblocks(hsz, 256)),
                      dim3(256), 0, h.stream, in, cin, out, cout, kgeom(h, false));
   PSE_LAUNCH_CHECK();
 }
@@ -539,11 +602,9 @@ void kspace_mobility(Handle &h, const cplx<T> *in, const CompSet &cin,
 template <typename T>
 void kspace_noise(Handle &h, const double *psi, uint64_t seed, uint64_t counter,
                   cplx<T> *out, const CompSet &cout) {
-  const int n = h.d.grid;
-  const size_t total = (size_t)(n / 2 + 1) * n * n;
-  ProfScope ps(h, PK_NOISE, (double)((cout.n + 1) / 2) * h.ngrid * sizeof(cplx<T>)
-                             + (psi ? 3.0 * total * 16 : 0.0));
-  hipLaunchKernelGGL(kspace_noise_kernel<T>, dim3(nblocks(total, 256)), dim3(256),
+  const size_t hsz = h.ngrid / 2;
+  ProfScope ps(h, PK_NOISE, (double)cout.n * hsz * sizeof(cplx<T>) + (psi ? 3.0 * hsz * 16 : 0.0));
+  hipLaunchKernelGGL(kspace_noise_kernel<T>, dim3(nblocks(hsz, 256)), dim3(256),
                      0, h.stream, (const double2 *)psi, seed, counter, out, cout,
                      kgeom(h, true));
   PSE_LAUNCH_CHECK();
@@ -555,40 +616,37 @@ void real_noise(Handle &h, uint64_t seed, uint64_t counter, double *out) {
   PSE_LAUNCH_CHECK();
 }
 
-template <typename T> void zero_grids(Handle &h, cplx<T> *g, int npack) {
-  const size_t n = (size_t)npack * h.ngrid;
-  ProfScope ps(h, PK_ZERO, (double)n * sizeof(cplx<T>));
-  hipLaunchKernelGGL(zero_kernel<T>, dim3(nblocks(n, 256)), dim3(256), 0, h.stream,
-                     g, n);
+template <typename T> void zero_grids(Handle &h, T *g, int ncomp) {
+  const size_t n = (size_t)ncomp * h.ngrid;
+  ProfScope ps(h, PK_ZERO, (double)n * sizeof(T));
+  hipLaunchKernelGGL(zero_kernel<T>, dim3(nblocks(n, 256)), dim3(256), 0, h.stream, g, n);
   PSE_LAUNCH_CHECK();
 }
 
-template <typename T>
-void real_to_packed(Handle &h, const double *src, int ncomp, cplx<T> *dst) {
-  hipLaunchKernelGGL(real_to_packed_kernel<T>, dim3(nblocks(h.ngrid, 256)),
-                     dim3(256), 0, h.stream, src, ncomp, h.ngrid, dst);
+template <typename T> void from_double(Handle &h, const double *src, size_t n, T *dst) {
+  hipLaunchKernelGGL(from_double_kernel<T>, dim3(nblocks(n, 256)), dim3(256), 0, h.stream,
+                     src, n, dst);
   PSE_LAUNCH_CHECK();
 }
 
-template <typename T>
-void packed_to_real(Handle &h, const cplx<T> *src, int ncomp, double *dst) {
-  hipLaunchKernelGGL(packed_to_real_kernel<T>, dim3(nblocks(h.ngrid, 256)),
-                     dim3(256), 0, h.stream, src, ncomp, h.ngrid, dst);
+template <typename T> void to_double(Handle &h, const T *src, size_t n, double *dst) {
+  hipLaunchKernelGGL(to_double_kernel<T>, dim3(nblocks(n, 256)), dim3(256), 0, h.stream,
+                     src, n, dst);
   PSE_LAUNCH_CHECK();
 }
 
 #define INST(T)                                                                 \
   template void spread<T>(Handle &, const double *, const double *, int,         \
-                          const CompSet &, cplx<T> *);                           \
-  template void interpolate<T>(Handle &, const double *, const cplx<T> *,        \
+                          const CompSet &, T *);                                 \
+  template void interpolate<T>(Handle &, const double *, const T *,              \
                                const CompSet &, double *, int, bool, double);    \
   template void kspace_mobility<T>(Handle &, const cplx<T> *, const CompSet &,   \
                                    cplx<T> *, const CompSet &);                  \
   template void kspace_noise<T>(Handle &, const double *, uint64_t, uint64_t,    \
                                 cplx<T> *, const CompSet &);                     \
-  template void zero_grids<T>(Handle &, cplx<T> *, int);                         \
-  template void real_to_packed<T>(Handle &, const double *, int, cplx<T> *);     \
-  template void packed_to_real<T>(Handle &, const cplx<T> *, int, double *);
+  template void zero_grids<T>(Handle &, T *, int);                               \
+  template void from_double<T>(Handle &, const double *, size_t, T *);           \
+  template void to_double<T>(Handle &, const T *, size_t, double *);
 INST(double)
 INST(float)
 #undef INST

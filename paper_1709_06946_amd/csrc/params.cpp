@@ -104,7 +104,9 @@ size_t footprint(const pse_params &p, const pse_derived &d) {
     bytes += 2 * MAX_PACK * ng3 * sizeof(float2) + d.grid * sizeof(float2);
   const size_t ntab = (size_t)(2048.0 * d.rcut / (2 * p.radius)) + 16;
   bytes += ntab * NCOEF * (sizeof(double) + sizeof(float));
-  bytes += (2 * ncell3 + 2 + ncell3 / 1024 + 8) * sizeof(int) + 3 * n * sizeof(int);
+  const size_t tiles3 = ng3 / 64;   // spreading tiles (at most 4^3 points each)
+  bytes += (2 * (ncell3 + tiles3) + 4 + (ncell3 + tiles3) / 1024 + 16) * sizeof(int)
+           + 6 * n * sizeof(int);
   bytes += (2 * 3 * n + 6 * NC * n) * sizeof(double);
   bytes += (size_t)(d.lanczos_maxit + 1) * NC * n * sizeof(double);
   bytes += (size_t)(d.gmres_restart + 1) * 5 * n * sizeof(double);

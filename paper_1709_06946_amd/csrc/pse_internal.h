@@ -61,6 +61,17 @@ template <typename T> struct GridSet {
   T *table = nullptr;        // real-space coefficient table (ntab x NCOEF)
 };
 
+// Counting-sort bins of particles on a uniform nc^3 lattice of the box.
+struct Bins {
+  int nc = 0;                // bins per side
+  int *start = nullptr;      // nc^3 + 1: first slot of each bin in perm
+  int *count = nullptr;      // nc^3
+  int *of = nullptr;         // N: bin of each particle
+  int *slot = nullptr;       // N: rank of the particle within its bin
+  int *perm = nullptr;       // N: particles ordered by bin
+  int *scan_tmp = nullptr;   // block sums of the scan
+};
+
 // Kernel classes timed by the optional profiler.
 enum ProfKind {
   PK_SPREAD = 0, PK_FFT, PK_KSPACE, PK_INTERP, PK_ZERO, PK_REAL, PK_CELLS,
@@ -101,14 +112,11 @@ struct Handle {
   int ntab, n2a;
   double dr;
 
-  // cell list
-  int ncell;                 // cells per side
-  int *cell_start = nullptr; // ncell^3 + 1
-  int *cell_count = nullptr; // ncell^3
-  int *cell_of = nullptr;    // N
-  int *slot = nullptr;       // N
-  int *perm = nullptr;       // N: particles sorted by cell
-  int *scan_tmp = nullptr;   // block sums for the scan
+  // particle bins: the real-space cell list (side >= rcut) and the
+  // spreading tiles (stile^3 grid points each)
+  Bins cells;
+  Bins sbins;
+  int stile;                 // grid points per spreading tile side (0: atomics)
 
   // particle work vectors (double, N x 11 each)
   double *xw = nullptr;      // wrapped positions N x 3
@@ -160,32 +168,36 @@ void derive(const pse_params &p, pse_derived &d);
 size_t footprint(const pse_params &p, const pse_derived &d);
 
 // ---- fft.hip
+// complex 3D transform of ncomp full grids [c][z][y][x] (diagnostic)
 template <typename T>
 void fft3d(Handle &h, cplx<T> *data, const cplx<T> *twiddle, int ncomp, int dir);
+// real 3D transform of ncomp real grids [c][z][y][x] in place: dir = -1
+// leaves half spectra [c][kz][ky][kx < n/2], dir = +1 inverts
+template <typename T>
+void rfft3d(Handle &h, T *grids, const cplx<T> *twiddle, int ncomp, int dir);
 
 // ---- grid.hip
+// Real grids [c][z][y][x] (T), half spectra [c][kz][ky][kx < n/2] (cplx<T>)
+// in the same storage; component stride ngrid reals = ngrid/2 complex.
 template <typename T>
 void spread(Handle &h, const double *x, const double *q, int qstride,
-            const CompSet &cs, cplx<T> *grids);
+            const CompSet &cs, T *grids);
 template <typename T>
-void interpolate(Handle &h, const double *x, const cplx<T> *grids,
-                 const CompSet &cs, double *out, int ostride, bool accumulate,
-                 double scale);
+void interpolate(Handle &h, const double *x, const T *grids, const CompSet &cs,
+                 double *out, int ostride, bool accumulate, double scale);
 template <typename T>
 void kspace_mobility(Handle &h, const cplx<T> *in, const CompSet &cin,
                      cplx<T> *out, const CompSet &cout);
 template <typename T>
 void kspace_noise(Handle &h, const double *psi, uint64_t seed, uint64_t counter,
                   cplx<T> *out, const CompSet &cout);
-template <typename T> void zero_grids(Handle &h, cplx<T> *g, int npack);
-template <typename T>
-void real_to_packed(Handle &h, const double *src, int ncomp, cplx<T> *dst);
-template <typename T>
-void packed_to_real(Handle &h, const cplx<T> *src, int ncomp, double *dst);
+template <typename T> void zero_grids(Handle &h, T *g, int ncomp);
+template <typename T> void from_double(Handle &h, const double *src, size_t n, T *dst);
+template <typename T> void to_double(Handle &h, const T *src, size_t n, double *dst);
 
 // ---- real.hip
 void build_tables(Handle &h);
-void build_cells(Handle &h, const double *x);
+void build_cells(Handle &h, const double *xw);   // both bin lists
 template <typename T>
 void real_apply(Handle &h, const double *x, const double *in,
                 const CompSet &cin, double *out, const CompSet &cout,

@@ -266,28 +266,34 @@ __global__ void cell_scatter_kernel(const int *__restrict__ cell_of,
   perm[start[cell_of[i]] + slot[i]] = (int)i;
 }
 
-void build_cells(Handle &h, const double *xw) {
-  const int nc = h.ncell;
+static void build_bins(Handle &h, const double *xw, Bins &b) {
+  const int nc = b.nc;
   const int ncells = nc * nc * nc;
-  ProfScope ps(h, PK_CELLS, (double)h.n * (24 + 16) + 12.0 * ncells);
-  PSE_HIP(hipMemsetAsync(h.cell_count, 0, ncells * sizeof(int), h.stream));
+  PSE_HIP(hipMemsetAsync(b.count, 0, ncells * sizeof(int), h.stream));
   hipLaunchKernelGGL(cell_assign_kernel, dim3(nblocks(h.n, 256)), dim3(256), 0,
-                     h.stream, xw, h.n, nc, nc / h.p.box, h.cell_of, h.slot,
-                     h.cell_count);
+                     h.stream, xw, h.n, nc, nc / h.p.box, b.of, b.slot, b.count);
   PSE_LAUNCH_CHECK();
   const int nb = (ncells + 1023) / 1024;
-  hipLaunchKernelGGL(scan_block_kernel, dim3(nb), dim3(256), 0, h.stream,
-                     h.cell_count, h.cell_start, h.scan_tmp, ncells);
+  hipLaunchKernelGGL(scan_block_kernel, dim3(nb), dim3(256), 0, h.stream, b.count,
+                     b.start, b.scan_tmp, ncells);
   PSE_LAUNCH_CHECK();
-  hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(256), 0, h.stream, h.scan_tmp,
-                     nb, h.cell_start + ncells);
+  hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(256), 0, h.stream, b.scan_tmp, nb,
+                     b.start + ncells);
   PSE_LAUNCH_CHECK();
-  hipLaunchKernelGGL(scan_add_kernel, dim3(nb), dim3(256), 0, h.stream,
-                     h.cell_start, h.scan_tmp, ncells);
+  hipLaunchKernelGGL(scan_add_kernel, dim3(nb), dim3(256), 0, h.stream, b.start,
+                     b.scan_tmp, ncells);
   PSE_LAUNCH_CHECK();
   hipLaunchKernelGGL(cell_scatter_kernel, dim3(nblocks(h.n, 256)), dim3(256), 0,
-                     h.stream, h.cell_of, h.slot, h.cell_start, h.n, h.perm);
+                     h.stream, b.of, b.slot, b.start, h.n, b.perm);
   PSE_LAUNCH_CHECK();
+}
+
+void build_cells(Handle &h, const double *xw) {
+  const double nc3 = (double)h.cells.nc * h.cells.nc * h.cells.nc
+                     + (h.stile ? (double)h.sbins.nc * h.sbins.nc * h.sbins.nc : 0.0);
+  ProfScope ps(h, PK_CELLS, (double)h.n * (24 + 16) * (h.stile ? 2 : 1) + 12.0 * nc3);
+  build_bins(h, xw, h.cells);
+  if (h.stile) build_bins(h, xw, h.sbins);
 }
 
 // ------------------------------------------------------------ pair sum --
@@ -398,13 +404,27 @@ __device__ __forceinline__ void load_moments(const double *__restrict__ v, int m
   }
 }
 
+// A group of GROUP lanes works on one particle: the lanes split the
+// neighbour candidates of the 27 surrounding cells, then reduce U and D with
+// cross-lane shuffles.  One thread per particle would leave most of the chip
+// idle for N ~ 1e4.
+constexpr int GROUP = 16;
+
+template <typename T>
+__device__ __forceinline__ T group_sum(T v) {
+#pragma unroll
+  for (int off = GROUP / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, GROUP);
+  return v;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256)
 real_pair_kernel(const double *__restrict__ xw, const double *__restrict__ in,
                  double *__restrict__ out, const int *__restrict__ perm,
                  const int *__restrict__ cell_start, const int *__restrict__ cell_of,
                  const T *__restrict__ tab, RealArgs ra) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t t = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / GROUP;
+  const int lane = threadIdx.x % GROUP;
   if (t >= ra.n) return;
   const int i = perm[t];
   const double xi0 = xw[3 * i], xi1 = xw[3 * i + 1], xi2 = xw[3 * i + 2];
@@ -412,8 +432,8 @@ real_pair_kernel(const double *__restrict__ xw, const double *__restrict__ in,
   T U[3] = {0, 0, 0};
   T D[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
   T F[3], C[3][3];
-  // self term (r = 0: only the isotropic coefficients survive)
-  {
+  if (lane == 0) {
+    // self term (r = 0: only the isotropic coefficients survive)
     T co[NCOEF];
     for (int j = 0; j < NCOEF; ++j) co[j] = tab[j];
     const T e0[3] = {0, 0, 0};
@@ -432,7 +452,7 @@ real_pair_kernel(const double *__restrict__ xw, const double *__restrict__ in,
         const int xx = (cx + dx + nc) % nc;
         const int cell = (zz * nc + yy) * nc + xx;
         const int s0 = cell_start[cell], s1 = cell_start[cell + 1];
-        for (int s = s0; s < s1; ++s) {
+        for (int s = s0 + lane; s < s1; s += GROUP) {
           const int j = perm[s];
           if (j == i) continue;
           double d0 = xi0 - xw[3 * j], d1 = xi1 - xw[3 * j + 1], d2 = xi2 - xw[3 * j + 2];
@@ -456,6 +476,13 @@ real_pair_kernel(const double *__restrict__ xw, const double *__restrict__ in,
       }
     }
   }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) U[k] = group_sum(U[k]);
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) D[a][b] = group_sum(D[a][b]);
+  if (lane != 0) return;
   double *o = out + (size_t)i * NC;
   const double r2 = 0.70710678118654752440, r6 = 0.40824829046386301637;
   if (ra.out_mask & 1) {
@@ -491,7 +518,7 @@ void real_apply(Handle &h, const double *xw, const double *in, const CompSet &ci
                 double *out, const CompSet &cout, bool accumulate) {
   RealArgs ra;
   ra.n = h.n;
-  ra.nc = h.ncell;
+  ra.nc = h.cells.nc;
   ra.L = h.p.box;
   ra.rcut2 = h.d.rcut * h.d.rcut;
   ra.inv_dr = 1.0 / h.dr;
@@ -503,8 +530,9 @@ void real_apply(Handle &h, const double *xw, const double *in, const CompSet &ci
   const T *tab;
   if constexpr (sizeof(T) == 8) tab = h.g64.table; else tab = h.g32.table;
   ProfScope ps(h, PK_REAL, (double)h.n * (2 * NC * 8 + 3 * 8 + 2 * 4));
-  hipLaunchKernelGGL(real_pair_kernel<T>, dim3(nblocks(h.n, 256)), dim3(256), 0,
-                     h.stream, xw, in, out, h.perm, h.cell_start, h.cell_of, tab, ra);
+  hipLaunchKernelGGL(real_pair_kernel<T>, dim3(nblocks((size_t)h.n * GROUP, 256)), dim3(256), 0,
+                     h.stream, xw, in, out, h.cells.perm, h.cells.start, h.cells.of, tab,
+                     ra);
   PSE_LAUNCH_CHECK();
 }
 
