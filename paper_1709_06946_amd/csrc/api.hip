@@ -116,9 +116,13 @@ static void wave_apply(Handle &h, const double *xw, const double *in, const Comp
   GridSet<T> &G = grids<T>(h);
   T *gin = reinterpret_cast<T *>(G.gin), *gout = reinterpret_cast<T *>(G.gout);
   spread<T>(h, xw, in, NC, cin, gin);
-  rfft3d<T>(h, gin, G.twiddle, cin.n, -1);
-  kspace_mobility<T>(h, G.gin, cin, G.gout, cout);
-  rfft3d<T>(h, gout, G.twiddle, cout.n, +1);
+  rfft_xy<T>(h, gin, G.twiddle, cin.n, -1);
+  if (!kspace_fused<T>(h, G.gin, cin, G.gout, cout, G.twiddle)) {
+    rfft_z<T>(h, gin, G.twiddle, cin.n, -1);
+    kspace_mobility<T>(h, G.gin, cin, G.gout, cout);
+    rfft_z<T>(h, gout, G.twiddle, cout.n, +1);
+  }
+  rfft_xy<T>(h, gout, G.twiddle, cout.n, +1);
   interpolate<T>(h, xw, gout, cout, out, NC, accumulate, 1.0);
 }
 

@@ -3,121 +3,13 @@
 // along each axis, dir = +1 the conjugate sum.
 //
 // One kernel per axis.  A workgroup loads TL whole lines of length N into
-// LDS, runs a Stockham autosort FFT (radix 4, 2, 3 stages; Govindaraju et
-// al., SC'08 formulation) between two LDS buffers, and writes the lines back
-// in place.  LDS is laid out [position][line] so that, along the y and z
+// LDS, runs the Stockham autosort FFT of stockham.h between two LDS buffers,
+// and writes the lines back in place.  LDS is laid out [position][line] so that, along the y and z
 // axes, consecutive threads touch consecutive x addresses both in HBM and in
 // LDS.
-#include "pse_internal.h"
+#include "stockham.h"
 
 namespace pse {
-
-struct FftPlan {
-  int n;        // line length
-  int m;        // stored extent of the x axis (n for full complex grids,
-                // n/2 for half spectra)
-  int tl;       // lines per workgroup
-  int nst;      // number of stages
-  int r[16];    // radix per stage
-};
-
-template <typename C> __device__ __forceinline__ C cmul(C a, C b) {
-  C c;
-  c.x = a.x * b.x - a.y * b.y;
-  c.y = a.x * b.y + a.y * b.x;
-  return c;
-}
-template <typename C> __device__ __forceinline__ C cadd(C a, C b) {
-  C c; c.x = a.x + b.x; c.y = a.y + b.y; return c;
-}
-template <typename C> __device__ __forceinline__ C csub(C a, C b) {
-  C c; c.x = a.x - b.x; c.y = a.y - b.y; return c;
-}
-// multiply by -i*s (s = +1) or +i (s = -1): forward rotation for dir = -1
-template <typename C> __device__ __forceinline__ C rot(C a, int dir) {
-  C c;
-  if (dir < 0) { c.x = a.y; c.y = -a.x; }   // -i a
-  else         { c.x = -a.y; c.y = a.x; }   // +i a
-  return c;
-}
-
-template <typename T, int R>
-__device__ __forceinline__ void dft_small(cplx<T> *v, int dir) {
-  using C = cplx<T>;
-  if constexpr (R == 2) {
-    C a = v[0], b = v[1];
-    v[0] = cadd(a, b);
-    v[1] = csub(a, b);
-  } else if constexpr (R == 4) {
-    C t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
-    C t2 = cadd(v[1], v[3]), t3 = rot(csub(v[1], v[3]), dir);
-    v[0] = cadd(t0, t2);
-    v[2] = csub(t0, t2);
-    v[1] = cadd(t1, t3);
-    v[3] = csub(t1, t3);
-  } else if constexpr (R == 3) {
-    const T s = (T)0.86602540378443864676;  // sqrt(3)/2
-    C a = v[0];
-    C t1 = cadd(v[1], v[2]);
-    C t2; t2.x = a.x - (T)0.5 * t1.x; t2.y = a.y - (T)0.5 * t1.y;
-    C d = csub(v[1], v[2]);
-    C t3 = rot(d, dir);              // -i d (forward) or +i d (inverse)
-    t3.x *= s; t3.y *= s;
-    v[0] = cadd(a, t1);
-    v[1] = cadd(t2, t3);
-    v[2] = csub(t2, t3);
-  }
-}
-
-template <typename T, int R>
-__device__ __forceinline__ void stockham_stage(const cplx<T> *__restrict__ src,
-                                               cplx<T> *__restrict__ dst, int N,
-                                               int TL, int Ns,
-                                               const cplx<T> *__restrict__ tw,
-                                               int dir) {
-  using C = cplx<T>;
-  const int nbf = N / R;
-  const int tstep = N / (Ns * R);
-  for (int w = threadIdx.x; w < nbf * TL; w += blockDim.x) {
-    const int line = w % TL;
-    const int j = w / TL;
-    C v[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) v[r] = src[(j + r * nbf) * TL + line];
-    const int k = j % Ns;
-    if (Ns > 1) {
-#pragma unroll
-      for (int r = 1; r < R; ++r) {
-        C t = tw[k * r * tstep];
-        if (dir > 0) t.y = -t.y;
-        v[r] = cmul(v[r], t);
-      }
-    }
-    dft_small<T, R>(v, dir);
-    const int base = (j / Ns) * Ns * R + k;
-#pragma unroll
-    for (int r = 0; r < R; ++r) dst[(base + r * Ns) * TL + line] = v[r];
-  }
-}
-
-// Runs all stages between the two LDS buffers; returns the buffer holding
-// the result.
-template <typename T>
-__device__ cplx<T> *stockham_all(cplx<T> *src, cplx<T> *dst, const FftPlan &plan,
-                                 const cplx<T> *__restrict__ tw, int dir) {
-  const int N = plan.n, TL = plan.tl;
-  int Ns = 1;
-  for (int s = 0; s < plan.nst; ++s) {
-    const int R = plan.r[s];
-    if (R == 4)      stockham_stage<T, 4>(src, dst, N, TL, Ns, tw, dir);
-    else if (R == 2) stockham_stage<T, 2>(src, dst, N, TL, Ns, tw, dir);
-    else             stockham_stage<T, 3>(src, dst, N, TL, Ns, tw, dir);
-    __syncthreads();
-    cplx<T> *t = src; src = dst; dst = t;
-    Ns *= R;
-  }
-  return src;
-}
 
 // pass 0: lines along x (contiguous); 1: along y; 2: along z.
 template <typename T>
@@ -248,24 +140,6 @@ fft_x_c2r(T *__restrict__ data, const cplx<T> *__restrict__ tw, FftPlan plan) {
   }
 }
 
-static FftPlan make_plan(int n, size_t elem_bytes) {
-  FftPlan p{};
-  p.n = n;
-  int m = n;
-  if (m % 3 == 0) { p.r[p.nst++] = 3; m /= 3; }
-  while (m % 4 == 0) { p.r[p.nst++] = 4; m /= 4; }
-  while (m % 2 == 0) { p.r[p.nst++] = 2; m /= 2; }
-  if (m != 1) throw Error{PSE_ERR_INVALID, "unsupported FFT length"};
-  // two LDS buffers of N * TL elements within 64 KiB
-  int tl = (int)(65536 / (2 * elem_bytes * n));
-  if (tl > n) tl = n;
-  int t = 1;
-  while (t * 2 <= tl && n % (t * 2) == 0) t *= 2;
-  p.tl = t;
-  p.m = n;
-  return p;
-}
-
 template <typename T>
 void fft3d(Handle &h, cplx<T> *data, const cplx<T> *twiddle, int ncomp, int dir) {
   const int n = h.d.grid;
@@ -283,20 +157,17 @@ void fft3d(Handle &h, cplx<T> *data, const cplx<T> *twiddle, int ncomp, int dir)
 // Real 3D transforms of ncomp real grids stored [c][z][y][x], in place.
 // Forward leaves half spectra [c][kz][ky][kx < n/2]; inverse takes them back.
 template <typename T>
-static void half_passes(Handle &h, T *grids, const cplx<T> *tw, int ncomp, int dir) {
+static void half_pass(Handle &h, T *grids, const cplx<T> *tw, int ncomp, int dir, int pass) {
   const int n = h.d.grid;
   FftPlan plan = make_plan(n, sizeof(cplx<T>));
   plan.m = n / 2;
   while (plan.tl > 1 && (n / 2) % plan.tl) plan.tl /= 2;
   const size_t lds = 2 * (size_t)n * plan.tl * sizeof(cplx<T>);
   const unsigned nb = (unsigned)((size_t)ncomp * n * (n / 2) / plan.tl);
-  const int order[2] = {dir < 0 ? 1 : 2, dir < 0 ? 2 : 1};
-  for (int i = 0; i < 2; ++i) {
-    ProfScope ps(h, PK_FFT, 2.0 * ncomp * h.ngrid * sizeof(T));
-    hipLaunchKernelGGL(fft_pass<T>, dim3(nb), dim3(256), lds, h.stream,
-                       reinterpret_cast<cplx<T> *>(grids), tw, plan, order[i], dir);
-    PSE_LAUNCH_CHECK();
-  }
+  ProfScope ps(h, PK_FFT, 2.0 * ncomp * h.ngrid * sizeof(T));
+  hipLaunchKernelGGL(fft_pass<T>, dim3(nb), dim3(256), lds, h.stream,
+                     reinterpret_cast<cplx<T> *>(grids), tw, plan, pass, dir);
+  PSE_LAUNCH_CHECK();
 }
 
 template <typename T>
@@ -316,18 +187,39 @@ static void x_pass(Handle &h, T *grids, const cplx<T> *tw, int ncomp, int dir) {
 }
 
 template <typename T>
-void rfft3d(Handle &h, T *grids, const cplx<T> *twiddle, int ncomp, int dir) {
+void rfft_xy(Handle &h, T *grids, const cplx<T> *twiddle, int ncomp, int dir) {
   if (dir < 0) {
     x_pass<T>(h, grids, twiddle, ncomp, dir);
-    half_passes<T>(h, grids, twiddle, ncomp, dir);
+    half_pass<T>(h, grids, twiddle, ncomp, dir, 1);
   } else {
-    half_passes<T>(h, grids, twiddle, ncomp, dir);
+    half_pass<T>(h, grids, twiddle, ncomp, dir, 1);
     x_pass<T>(h, grids, twiddle, ncomp, dir);
   }
 }
 
-template void rfft3d<double>(Handle &, double *, const double2 *, int, int);
-template void rfft3d<float>(Handle &, float *, const float2 *, int, int);
+template <typename T>
+void rfft_z(Handle &h, T *grids, const cplx<T> *twiddle, int ncomp, int dir) {
+  half_pass<T>(h, grids, twiddle, ncomp, dir, 2);
+}
+
+template <typename T>
+void rfft3d(Handle &h, T *grids, const cplx<T> *twiddle, int ncomp, int dir) {
+  if (dir < 0) {
+    rfft_xy<T>(h, grids, twiddle, ncomp, dir);
+    rfft_z<T>(h, grids, twiddle, ncomp, dir);
+  } else {
+    rfft_z<T>(h, grids, twiddle, ncomp, dir);
+    rfft_xy<T>(h, grids, twiddle, ncomp, dir);
+  }
+}
+
+#define INST(T, C)                                                  \
+  template void rfft3d<T>(Handle &, T *, const C *, int, int);      \
+  template void rfft_xy<T>(Handle &, T *, const C *, int, int);     \
+  template void rfft_z<T>(Handle &, T *, const C *, int, int);
+INST(double, double2)
+INST(float, float2)
+#undef INST
 template void fft3d<double>(Handle &, double2 *, const double2 *, int, int);
 template void fft3d<float>(Handle &, float2 *, const float2 *, int, int);
 

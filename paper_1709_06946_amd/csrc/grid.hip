@@ -11,7 +11,7 @@
 // Fourier transform is exp(-eta_s k^2 / 8 xi^2).  Spreading and
 // interpolation each contribute that factor once; the k-space scaling
 // divides both out again.
-#include "pse_internal.h"
+#include "stockham.h"
 
 namespace pse {
 
@@ -255,82 +255,68 @@ struct KGeom {
   double pref;        // mobility: h^6 / (V eta); noise: h^3 / sqrt(V eta)
 };
 
-// P(k) q for one particle-moment component index c (0..10) and value g.
-template <typename C>
-__device__ __forceinline__ void add_P(int c, C gv, const double *kv, double j0,
-                                      double f1, C *rho) {
-  // rho += P_c g: F: j0 e_c; L: (3i/2) f1 (k x e_c); s_q: -3i f1 Y_q k.
-  if (c < 3) {
-    rho[c].x += j0 * gv.x;
-    rho[c].y += j0 * gv.y;
-    return;
-  }
-  double col[3] = {0.0, 0.0, 0.0};
-  double coef;
-  if (c < 6) {
-    const int l = c - 3;          // (k x e_l)_m = eps_mnl k_n
-    const int l1 = (l + 1) % 3, l2 = (l + 2) % 3;
-    col[l1] = kv[l2];
-    col[l2] = -kv[l1];
-    coef = 1.5 * f1;              // times +i
-  } else {
-    const double r2 = 0.70710678118654752440, r6 = 0.40824829046386301637;
-    switch (c - 6) {
-      case 0: col[0] = r2 * kv[1]; col[1] = r2 * kv[0]; break;
-      case 1: col[0] = r2 * kv[2]; col[2] = r2 * kv[0]; break;
-      case 2: col[1] = r2 * kv[2]; col[2] = r2 * kv[1]; break;
-      case 3: col[0] = r2 * kv[0]; col[1] = -r2 * kv[1]; break;
-      default: col[0] = r6 * kv[0]; col[1] = r6 * kv[1]; col[2] = -2.0 * r6 * kv[2]; break;
-    }
-    coef = -3.0 * f1;             // times +i
-  }
-  // rho_m += i coef col_m g  ->  (i g) = (-g.y, g.x)
-#pragma unroll
-  for (int m = 0; m < 3; ++m) {
-    const double s = coef * col[m];
-    rho[m].x += -s * gv.y;
-    rho[m].y += s * gv.x;
+// Column of P(k) for moment component c (0..10), as (coef, col): the
+// contribution to rho is coef * col * g with coef real for F (j0) and
+// imaginary for L and s:
+//   F_c:  j0 e_c;   L_l: (3i/2) f1 (k x e_l);   s_q: -3i f1 Y_q k.
+__device__ __forceinline__ void p_column(int c, double kx, double ky, double kz,
+                                         double j0, double f1, bool &imag,
+                                         double &cx, double &cy, double &cz) {
+  const double r2 = 0.70710678118654752440, r6 = 0.40824829046386301637;
+  imag = c >= 3;
+  const double a = 1.5 * f1, b = -3.0 * f1;
+  switch (c) {
+    case 0: cx = j0;  cy = 0;   cz = 0;   break;
+    case 1: cx = 0;   cy = j0;  cz = 0;   break;
+    case 2: cx = 0;   cy = 0;   cz = j0;  break;
+    case 3: cx = 0;   cy = a * kz;  cz = -a * ky; break;       // k x e_x
+    case 4: cx = -a * kz; cy = 0;   cz = a * kx;  break;       // k x e_y
+    case 5: cx = a * ky;  cy = -a * kx; cz = 0;   break;       // k x e_z
+    case 6: cx = b * r2 * ky; cy = b * r2 * kx; cz = 0; break;
+    case 7: cx = b * r2 * kz; cy = 0; cz = b * r2 * kx; break;
+    case 8: cx = 0; cy = b * r2 * kz; cz = b * r2 * ky; break;
+    case 9: cx = b * r2 * kx; cy = -b * r2 * ky; cz = 0; break;
+    default: cx = b * r6 * kx; cy = b * r6 * ky; cz = -2.0 * b * r6 * kz; break;
   }
 }
 
-// W_c = P_c^+ u for output component c.
+// rho += P_c(k) g
+template <typename C>
+__device__ __forceinline__ void add_P(int c, C gv, const double *kv, double j0,
+                                      double f1, C *rho) {
+  bool imag;
+  double cx, cy, cz;
+  p_column(c, kv[0], kv[1], kv[2], j0, f1, imag, cx, cy, cz);
+  if (!imag) {
+    rho[0].x += cx * gv.x; rho[0].y += cx * gv.y;
+    rho[1].x += cy * gv.x; rho[1].y += cy * gv.y;
+    rho[2].x += cz * gv.x; rho[2].y += cz * gv.y;
+  } else {
+    // i col g = col (-g.y, g.x)
+    rho[0].x -= cx * gv.y; rho[0].y += cx * gv.x;
+    rho[1].x -= cy * gv.y; rho[1].y += cy * gv.x;
+    rho[2].x -= cz * gv.y; rho[2].y += cz * gv.x;
+  }
+}
+
+// W_c = P_c^+ u = conj(coef) col . u
 template <typename C>
 __device__ __forceinline__ C apply_Pdag(int c, const C *u, const double *kv,
                                         double j0, double f1) {
+  bool imag;
+  double cx, cy, cz;
+  p_column(c, kv[0], kv[1], kv[2], j0, f1, imag, cx, cy, cz);
+  const double re = cx * u[0].x + cy * u[1].x + cz * u[2].x;
+  const double im = cx * u[0].y + cy * u[1].y + cz * u[2].y;
   C w;
-  if (c < 3) {
-    w.x = j0 * u[c].x;
-    w.y = j0 * u[c].y;
-    return w;
-  }
-  double re = 0.0, im = 0.0, coef;
-  if (c < 6) {
-    // Omega = (3i/2) f1 (k x u)
-    const int l = c - 3, l1 = (l + 1) % 3, l2 = (l + 2) % 3;
-    re = kv[l1] * u[l2].x - kv[l2] * u[l1].x;
-    im = kv[l1] * u[l2].y - kv[l2] * u[l1].y;
-    coef = 1.5 * f1;
+  if (!imag) {
+    w.x = re;
+    w.y = im;
   } else {
-    // e_q = 3i f1 (Y_q k) . u
-    const double r2 = 0.70710678118654752440, r6 = 0.40824829046386301637;
-    double col[3] = {0.0, 0.0, 0.0};
-    switch (c - 6) {
-      case 0: col[0] = r2 * kv[1]; col[1] = r2 * kv[0]; break;
-      case 1: col[0] = r2 * kv[2]; col[2] = r2 * kv[0]; break;
-      case 2: col[1] = r2 * kv[2]; col[2] = r2 * kv[1]; break;
-      case 3: col[0] = r2 * kv[0]; col[1] = -r2 * kv[1]; break;
-      default: col[0] = r6 * kv[0]; col[1] = r6 * kv[1]; col[2] = -2.0 * r6 * kv[2]; break;
-    }
-#pragma unroll
-    for (int m = 0; m < 3; ++m) {
-      re += col[m] * u[m].x;
-      im += col[m] * u[m].y;
-    }
-    coef = 3.0 * f1;
+    // conj(i) = -i: -i (re + i im) = im - i re
+    w.x = im;
+    w.y = -re;
   }
-  // i coef (re + i im)
-  w.x = -coef * im;
-  w.y = coef * re;
   return w;
 }
 
@@ -383,6 +369,103 @@ kspace_mobility_kernel(const cplx<T> *__restrict__ in, CompSet cin,
   for (int q = 0; q < cout.n; ++q) {
     const double2 w = apply_Pdag(cout.idx[q], uu, kv, j0, f1);
     out[q * hsz + tid] = C{(T)w.x, (T)w.y};
+  }
+}
+
+// Fused z transform + k-space kernel + inverse z transform.  A workgroup owns
+// TL neighbouring kx columns at one ky, i.e. TL z-lines.  Each input
+// component is loaded, transformed along z in LDS and folded at once into
+// rho(k) = sum_c P_c(k) G_c(k) (three complex numbers per k, kept in LDS), so
+// the inputs stream through one at a time; then rho is scaled and projected,
+// and each output component P_q^+ u is built, inverse-transformed along z and
+// stored.  This replaces three full sweeps over the grids (z pass, k-space,
+// inverse z pass) by one read of the inputs and one write of the outputs.
+template <typename T>
+__global__ void __launch_bounds__(256)
+kspace_fused_kernel(const cplx<T> *__restrict__ in, CompSet cin, cplx<T> *__restrict__ out,
+                    CompSet cout, KGeom kg, FftPlan plan, const cplx<T> *__restrict__ tw) {
+  using C = cplx<T>;
+  extern __shared__ unsigned char smem_raw[];
+  const int N = plan.n, TL = plan.tl, M = N / 2;
+  const int NT = N * TL;
+  C *rho = reinterpret_cast<C *>(smem_raw);     // 3 x NT
+  C *buf0 = rho + 3 * NT, *buf1 = buf0 + NT;
+  const int tiles = M / TL;
+  const int xt = blockIdx.x % tiles, iy = blockIdx.x / tiles;
+  const size_t hsz = (size_t)M * N * N, plane = (size_t)N * M;
+  const size_t base = (size_t)iy * M + (size_t)xt * TL;
+  for (int w = threadIdx.x; w < 3 * NT; w += blockDim.x) rho[w] = C{(T)0, (T)0};
+  for (int p = 0; p < cin.n; ++p) {
+    __syncthreads();
+    for (int w = threadIdx.x; w < NT; w += blockDim.x) {
+      const int line = w % TL, kz = w / TL;
+      buf0[w] = in[p * hsz + base + kz * plane + line];
+    }
+    __syncthreads();
+    const C *res = stockham_all<T>(buf0, buf1, plan, tw, -1);
+    for (int w = threadIdx.x; w < NT; w += blockDim.x) {
+      const int line = w % TL, kz = w / TL;
+      const int ix = xt * TL + line;
+      if (zero_mode(ix, iy, kz, N)) continue;
+      const double kv[3] = {kg.twopi_L * ix, kg.twopi_L * kidx(iy, N), kg.twopi_L * kidx(kz, N)};
+      double j0, f1;
+      shape_factors(sqrt(kv[0] * kv[0] + kv[1] * kv[1] + kv[2] * kv[2]) * kg.a, j0, f1);
+      double2 r3[3] = {{0, 0}, {0, 0}, {0, 0}};
+      const C g = res[w];
+      add_P(cin.idx[p], double2{(double)g.x, (double)g.y}, kv, j0, f1, r3);
+      for (int m = 0; m < 3; ++m) {
+        rho[m * NT + w].x += (T)r3[m].x;
+        rho[m * NT + w].y += (T)r3[m].y;
+      }
+    }
+  }
+  __syncthreads();
+  // u = scale (I - kk) rho, in place
+  for (int w = threadIdx.x; w < NT; w += blockDim.x) {
+    const int line = w % TL, kz = w / TL;
+    const int ix = xt * TL + line;
+    if (zero_mode(ix, iy, kz, N)) {
+      for (int m = 0; m < 3; ++m) rho[m * NT + w] = C{(T)0, (T)0};
+      continue;
+    }
+    const double kv[3] = {kg.twopi_L * ix, kg.twopi_L * kidx(iy, N), kg.twopi_L * kidx(kz, N)};
+    const double k2 = kv[0] * kv[0] + kv[1] * kv[1] + kv[2] * kv[2];
+    const double u = k2 * kg.inv4xi2;
+    const double scale = kg.pref * (1.0 + u) * exp(-kg.one_m_etas * u) / k2;
+    double2 r[3];
+    for (int m = 0; m < 3; ++m) r[m] = double2{(double)rho[m * NT + w].x, (double)rho[m * NT + w].y};
+    double2 kr{0, 0};
+    for (int m = 0; m < 3; ++m) {
+      kr.x += kv[m] * r[m].x;
+      kr.y += kv[m] * r[m].y;
+    }
+    for (int m = 0; m < 3; ++m)
+      rho[m * NT + w] = C{(T)(scale * (r[m].x - kv[m] * kr.x / k2)),
+                          (T)(scale * (r[m].y - kv[m] * kr.y / k2))};
+  }
+  for (int q = 0; q < cout.n; ++q) {
+    __syncthreads();
+    for (int w = threadIdx.x; w < NT; w += blockDim.x) {
+      const int line = w % TL, kz = w / TL;
+      const int ix = xt * TL + line;
+      if (zero_mode(ix, iy, kz, N)) {
+        buf0[w] = C{(T)0, (T)0};
+        continue;
+      }
+      const double kv[3] = {kg.twopi_L * ix, kg.twopi_L * kidx(iy, N), kg.twopi_L * kidx(kz, N)};
+      double j0, f1;
+      shape_factors(sqrt(kv[0] * kv[0] + kv[1] * kv[1] + kv[2] * kv[2]) * kg.a, j0, f1);
+      double2 uu[3];
+      for (int m = 0; m < 3; ++m) uu[m] = double2{(double)rho[m * NT + w].x, (double)rho[m * NT + w].y};
+      const double2 wv = apply_Pdag(cout.idx[q], uu, kv, j0, f1);
+      buf0[w] = C{(T)wv.x, (T)wv.y};
+    }
+    __syncthreads();
+    const C *res = stockham_all<T>(buf0, buf1, plan, tw, +1);
+    for (int w = threadIdx.x; w < NT; w += blockDim.x) {
+      const int line = w % TL, kz = w / TL;
+      out[q * hsz + base + kz * plane + line] = res[w];
+    }
   }
 }
 
@@ -599,6 +682,41 @@ void kspace_mobility(Handle &h, const cplx<T> *in, const CompSet &cin,
   PSE_LAUNCH_CHECK();
 }
 
+// Fused plan: TL z-lines per workgroup, five LDS line sets within 80 KiB;
+// returns tl = 0 when fewer than 4 lines would fit (use the separate passes).
+template <typename T> static FftPlan fused_plan(const Handle &h) {
+  const int n = h.d.grid;
+  FftPlan plan = make_plan(n, sizeof(cplx<T>));
+  int tl = (int)(81920 / (5 * sizeof(cplx<T>) * (size_t)n));
+  int t = 1;
+  while (t * 2 <= tl && (n / 2) % (t * 2) == 0) t *= 2;
+  plan.tl = t >= 4 ? t : 0;
+  plan.m = n / 2;
+  return plan;
+}
+
+template <typename T>
+bool kspace_fused(Handle &h, const cplx<T> *in, const CompSet &cin, cplx<T> *out,
+                  const CompSet &cout, const cplx<T> *tw) {
+  FftPlan plan = fused_plan<T>(h);
+  if (plan.tl == 0) return false;
+  const int n = h.d.grid;
+  const size_t lds = 5 * (size_t)n * plan.tl * sizeof(cplx<T>);
+  static bool attr_set = false;
+  if (!attr_set) {
+    PSE_HIP(hipFuncSetAttribute((const void *)kspace_fused_kernel<T>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 81920));
+    attr_set = true;
+  }
+  const size_t hsz = h.ngrid / 2;
+  ProfScope ps(h, PK_KSPACE, (double)(cin.n + cout.n) * hsz * sizeof(cplx<T>));
+  const unsigned nb = (unsigned)(n * (n / 2 / plan.tl));
+  hipLaunchKernelGGL(kspace_fused_kernel<T>, dim3(nb), dim3(256), lds, h.stream, in, cin, out,
+                     cout, kgeom(h, false), plan, tw);
+  PSE_LAUNCH_CHECK();
+  return true;
+}
+
 template <typename T>
 void kspace_noise(Handle &h, const double *psi, uint64_t seed, uint64_t counter,
                   cplx<T> *out, const CompSet &cout) {
@@ -644,6 +762,8 @@ template <typename T> void to_double(Handle &h, const T *src, size_t n, double *
                                    cplx<T> *, const CompSet &);                  \
   template void kspace_noise<T>(Handle &, const double *, uint64_t, uint64_t,    \
                                 cplx<T> *, const CompSet &);                     \
+  template bool kspace_fused<T>(Handle &, const cplx<T> *, const CompSet &,      \
+                                cplx<T> *, const CompSet &, const cplx<T> *);    \
   template void zero_grids<T>(Handle &, T *, int);                               \
   template void from_double<T>(Handle &, const double *, size_t, T *);           \
   template void to_double<T>(Handle &, const T *, size_t, double *);

@@ -407,14 +407,13 @@ KrylovResult lanczos_sqrt(Handle &h, const Op &A, const double *b, size_t n, dou
     hipLaunchKernelGGL(lanczos_sqrt_kernel, dim3(1), dim3(1), 0, h.stream, alpha, beta,
                        j + 1, bnorm, work, ldz, coef, coef_prev, change);
     PSE_LAUNCH_CHECK();
-    double hv[2];
-    host_read(h, change, hv, 1);
-    double vn;
-    host_read(h, vnorm, &vn, 1);
+    double hv[3];   // vnorm, bn, change are adjacent
+    host_read(h, vnorm, hv, 3);
+    const double vn = hv[0], chg = hv[2];
     m = j + 1;
     res.iters = m;
-    res.resid = hv[0];
-    if ((j > 0 && hv[0] < tol) || vn <= 1e-14 * bnorm) {
+    res.resid = chg;
+    if ((j > 0 && chg < tol) || vn <= 1e-14 * bnorm) {
       res.converged = true;
       break;
     }
@@ -488,13 +487,12 @@ KrylovResult gmres(Handle &h, const Op &A, const double *b, size_t n, double *x,
       hipLaunchKernelGGL(givens_kernel, dim3(1), dim3(1), 0, h.stream, H, ldh, j, cs, sn, g,
                          resid);
       PSE_LAUNCH_CHECK();
-      double hr[2];
-      host_read(h, resid, hr, 1);
-      double vn;
-      host_read(h, vnorm, &vn, 1);
+      double hr[3];   // vnorm, bn, resid are adjacent
+      host_read(h, vnorm, hr, 3);
+      const double vn = hr[0];
       ++total;
       k = j + 1;
-      rel = hr[0] / bnorm;
+      rel = hr[2] / bnorm;
       if (rel < tol || vn <= 1e-15 * bnorm) break;
       vscale_dev(h, w, w, vnorm, true, n);
     }

@@ -175,6 +175,11 @@ void fft3d(Handle &h, cplx<T> *data, const cplx<T> *twiddle, int ncomp, int dir)
 // leaves half spectra [c][kz][ky][kx < n/2], dir = +1 inverts
 template <typename T>
 void rfft3d(Handle &h, T *grids, const cplx<T> *twiddle, int ncomp, int dir);
+// the x and y passes (forward: x then y; inverse: y then x) and the z pass
+template <typename T>
+void rfft_xy(Handle &h, T *grids, const cplx<T> *twiddle, int ncomp, int dir);
+template <typename T>
+void rfft_z(Handle &h, T *grids, const cplx<T> *twiddle, int ncomp, int dir);
 
 // ---- grid.hip
 // Real grids [c][z][y][x] (T), half spectra [c][kz][ky][kx < n/2] (cplx<T>)
@@ -191,6 +196,11 @@ void kspace_mobility(Handle &h, const cplx<T> *in, const CompSet &cin,
 template <typename T>
 void kspace_noise(Handle &h, const double *psi, uint64_t seed, uint64_t counter,
                   cplx<T> *out, const CompSet &cout);
+// z transform + k-space + inverse z transform in one kernel; false if the
+// grid is too long for the LDS budget (caller then runs the separate passes)
+template <typename T>
+bool kspace_fused(Handle &h, const cplx<T> *in, const CompSet &cin, cplx<T> *out,
+                  const CompSet &cout, const cplx<T> *tw);
 template <typename T> void zero_grids(Handle &h, T *g, int ncomp);
 template <typename T> void from_double(Handle &h, const double *src, size_t n, T *dst);
 template <typename T> void to_double(Handle &h, const T *src, size_t n, double *dst);
