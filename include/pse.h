@@ -234,6 +234,71 @@ int pse_profile(pse_handle *h, int enable);
  * number written. */
 int pse_profile_read(pse_handle *h, pse_kernel_stat *out, int max, int *count);
 
+/* ------------------------------------------------------------------------
+ * Serving: continuous admission of independent simulations onto one GPU.
+ * Requests wait in a FIFO queue and are admitted when a worker slot is free
+ * and their device footprint (pse_footprint_bytes plus their particle
+ * arrays) fits in the remaining budget.  An admitted request owns a handle
+ * on its own stream, keeps its state resident and runs all its steps
+ * (pse_constrained_step with Philox noise keyed by (seed, step)); several
+ * admitted requests run at once and their kernels overlap on the device.
+ * The completion time of every step is recorded (per-step latency).  All
+ * server functions are thread-safe.  Host arrays are copied at submission.
+ */
+typedef struct pse_server pse_server;
+
+typedef struct pse_request {
+  int64_t n;               /* particles                                       */
+  double box, radius, viscosity, kT, tol;
+  int32_t grid;            /* FFT grid (see pse_params.grid)                  */
+  int32_t precision;       /* PSE_FP64 or PSE_MIXED                           */
+  double gmres_tol;        /* 0 = library default                             */
+  double lanczos_tol;      /* 0 = library default                             */
+  int32_t steps;           /* mid-point steps to run                          */
+  double dt;
+  uint64_t seed;
+  const double *x0;        /* host double[n][3] initial positions             */
+  const double *FL;        /* host double[n][6] forces/torques, or NULL       */
+} pse_request;
+
+typedef struct pse_request_info {
+  int64_t id;
+  int32_t status;          /* 0 ok, >0 warning, <0 error code                 */
+  int32_t steps_done;
+  size_t bytes;            /* admitted footprint                              */
+  double t_submit, t_admit, t_done;   /* seconds since server creation       */
+} pse_request_info;
+
+typedef struct pse_server_info {
+  size_t budget, used, peak_used;
+  int32_t active, peak_active, queued;
+  int64_t completed, failed;
+  double particle_steps;   /* sum of n * steps over completed requests        */
+  double elapsed;          /* seconds since server creation                   */
+} pse_server_info;
+
+/* budget_bytes = 0: 90 % of the free device memory.  max_active worker
+ * slots (1..64) on the current device. */
+int pse_server_create(size_t budget_bytes, int max_active, pse_server **out);
+
+/* Queue a request (non-blocking).  PSE_ERR_NOMEM if it can never fit. */
+int pse_server_submit(pse_server *s, const pse_request *r, int64_t *id);
+
+/* Block until the request has finished; info may be NULL. */
+int pse_server_wait(pse_server *s, int64_t id, pse_request_info *info);
+
+/* Final positions (host double[n][3]) and per-step latencies in ms (host
+ * double[steps]) of a finished request; either pointer may be NULL. */
+int pse_server_result(pse_server *s, int64_t id, double *x_out, double *step_ms);
+
+/* Forget a finished request. */
+int pse_server_release(pse_server *s, int64_t id);
+
+int pse_server_stats(pse_server *s, pse_server_info *out);
+
+/* Run every queued request to completion, then stop the workers. */
+int pse_server_destroy(pse_server *s);
+
 /* Message for the last failure on this handle (or of the last failed create
  * when h is NULL).  Never NULL. */
 const char *pse_last_error(const pse_handle *h);

@@ -15,7 +15,8 @@ LIB = os.path.join(HERE, 'libpse.so')
 HIPCC = os.environ.get('HIPCC', '/opt/rocm/bin/hipcc')
 ARCH = 'gfx950'
 
-SOURCES = ['params.cpp', 'fft.hip', 'grid.hip', 'real.hip', 'krylov.hip', 'api.hip']
+SOURCES = ['params.cpp', 'serve.cpp', 'fft.hip', 'grid.hip', 'real.hip', 'krylov.hip',
+           'api.hip']
 
 FLAGS = ['-O3', '-std=c++17', '-fPIC', f'--offload-arch={ARCH}',
          '-Xclang', '-target-feature', '-Xclang', '-packed-fp32-ops',
@@ -27,7 +28,7 @@ def _compile(src):
     obj = os.path.join(BUILD, os.path.basename(src) + '.o')
     cmd = [HIPCC] + FLAGS + ['-c', os.path.join(CSRC, src), '-o', obj]
     if src.endswith('.cpp'):
-        cmd = [HIPCC, '-O3', '-std=c++17', '-fPIC', '-Wall', '-c',
+        cmd = [HIPCC, '-O3', '-std=c++17', '-fPIC', '-Wall', '-pthread', '-c',
                os.path.join(CSRC, src), '-o', obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
@@ -46,7 +47,7 @@ def build(verbose=False):
             if err.strip():
                 print(err, file=sys.stderr)
     tmp = LIB + '.tmp'
-    cmd = [HIPCC, '-shared', f'--offload-arch={ARCH}', '-o', tmp] + objs
+    cmd = [HIPCC, '-shared', '-pthread', f'--offload-arch={ARCH}', '-o', tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f'link failed\n{r.stdout}\n{r.stderr}')

@@ -11,6 +11,8 @@
 // Fourier transform is exp(-eta_s k^2 / 8 xi^2).  Spreading and
 // interpolation each contribute that factor once; the k-space scaling
 // divides both out again.
+#include <mutex>
+
 #include "stockham.h"
 
 namespace pse {
@@ -702,12 +704,13 @@ bool kspace_fused(Handle &h, const cplx<T> *in, const CompSet &cin, cplx<T> *out
   if (plan.tl == 0) return false;
   const int n = h.d.grid;
   const size_t lds = 5 * (size_t)n * plan.tl * sizeof(cplx<T>);
-  static bool attr_set = false;
-  if (!attr_set) {
-    PSE_HIP(hipFuncSetAttribute((const void *)kspace_fused_kernel<T>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, 81920));
-    attr_set = true;
-  }
+  static std::once_flag once;
+  hipError_t attr = hipSuccess;
+  std::call_once(once, [&] {
+    attr = hipFuncSetAttribute((const void *)kspace_fused_kernel<T>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, 81920);
+  });
+  PSE_HIP(attr);
   const size_t hsz = h.ngrid / 2;
   ProfScope ps(h, PK_KSPACE, (double)(cin.n + cout.n) * hsz * sizeof(cplx<T>));
   const unsigned nb = (unsigned)(n * (n / 2 / plan.tl));

@@ -1,0 +1,305 @@
+// Serving runtime: continuous admission of independent Brownian-dynamics
+// simulations onto one GPU.
+//
+// Requests (N, box, tolerance, grid, steps, seed, initial positions, forces)
+// wait in a FIFO queue.  A request is admitted as soon as a worker slot is
+// free and its device footprint (pse_footprint_bytes: grids, tables, cell
+// lists, Krylov bases, particle arrays) fits in the remaining budget; it then
+// owns a library handle on its own stream, keeps its state resident, and
+// runs all its steps.  Several admitted requests execute at once, so their
+// kernels overlap on the device; requests arriving meanwhile are admitted
+// as slots and memory free up.  Each step's completion time is recorded for
+// latency percentiles.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/pse.h"
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct Req {
+  int64_t id;
+  pse_request r;
+  std::vector<double> x0, fl, x_out;
+  std::vector<double> lat_ms;     // per-step latency
+  size_t bytes = 0;
+  int status = 0;                 // 0 queued, 1 running, 2 done, <0 failed
+  int rc = 0;
+  std::string err;
+  double t_submit = 0, t_admit = 0, t_done = 0;
+};
+
+}  // namespace
+
+struct pse_server {
+  size_t budget;
+  int max_active;
+  std::mutex mu;
+  std::condition_variable cv_admit;   // wakes workers
+  std::condition_variable cv_done;    // wakes waiters
+  std::deque<std::shared_ptr<Req>> queue;
+  std::map<int64_t, std::shared_ptr<Req>> all;
+  size_t used = 0;
+  int active = 0;
+  bool stopping = false;
+  int64_t next_id = 1;
+  int device = 0;
+  Clock::time_point t0;
+  std::vector<std::thread> workers;
+  // totals
+  int64_t completed = 0, failed = 0;
+  double particle_steps = 0;
+  size_t peak_used = 0;
+  int peak_active = 0;
+
+  double now() const {
+    return std::chrono::duration<double>(Clock::now() - t0).count();
+  }
+};
+
+namespace {
+
+void run_request(pse_server *s, Req &q) {
+  pse_params p{};
+  p.n = q.r.n;
+  p.box = q.r.box;
+  p.radius = q.r.radius;
+  p.viscosity = q.r.viscosity;
+  p.kT = q.r.kT;
+  p.tol = q.r.tol;
+  p.grid = q.r.grid;
+  p.precision = q.r.precision;
+  p.gmres_tol = q.r.gmres_tol;
+  p.lanczos_tol = q.r.lanczos_tol;
+  pse_handle *h = nullptr;
+  int rc = pse_create(&p, &h);
+  if (rc != PSE_OK) {
+    q.rc = rc;
+    q.err = pse_last_error(nullptr);
+    return;
+  }
+  const size_t n = (size_t)q.r.n;
+  double *dx = nullptr, *dfl = nullptr;
+  if (hipMalloc(&dx, 3 * n * sizeof(double)) != hipSuccess ||
+      (q.r.FL && hipMalloc(&dfl, 6 * n * sizeof(double)) != hipSuccess)) {
+    q.rc = PSE_ERR_NOMEM;
+    q.err = "device allocation of request state failed";
+    (void)hipFree(dx);
+    pse_destroy(h);
+    return;
+  }
+  (void)hipMemcpy(dx, q.x0.data(), 3 * n * sizeof(double), hipMemcpyHostToDevice);
+  if (dfl) (void)hipMemcpy(dfl, q.fl.data(), 6 * n * sizeof(double), hipMemcpyHostToDevice);
+  double tprev = s->now();
+  for (int k = 0; k < q.r.steps; ++k) {
+    pse_stats st{};
+    rc = pse_constrained_step(h, dx, dfl, q.r.dt, q.r.seed, (uint64_t)k, nullptr, &st);
+    const double t = s->now();
+    q.lat_ms.push_back(1e3 * (t - tprev));
+    tprev = t;
+    if (rc < 0) {
+      q.rc = rc;
+      q.err = pse_last_error(h);
+      break;
+    }
+    if (rc > 0) q.rc = rc;
+  }
+  q.x_out.resize(3 * n);
+  (void)hipMemcpy(q.x_out.data(), dx, 3 * n * sizeof(double), hipMemcpyDeviceToHost);
+  (void)hipFree(dx);
+  (void)hipFree(dfl);
+  pse_destroy(h);
+}
+
+void worker(pse_server *s) {
+  (void)hipSetDevice(s->device);
+  for (;;) {
+    std::shared_ptr<Req> q;
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      s->cv_admit.wait(lk, [&] {
+        if (s->stopping && s->queue.empty()) return true;
+        if (s->queue.empty()) return false;
+        return s->used + s->queue.front()->bytes <= s->budget || s->active == 0;
+      });
+      if (s->queue.empty()) return;   // stopping
+      q = s->queue.front();
+      s->queue.pop_front();
+      s->used += q->bytes;
+      s->active += 1;
+      s->peak_used = std::max(s->peak_used, s->used);
+      s->peak_active = std::max(s->peak_active, s->active);
+      q->status = 1;
+      q->t_admit = s->now();
+    }
+    run_request(s, *q);
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      s->used -= q->bytes;
+      s->active -= 1;
+      q->t_done = s->now();
+      q->status = q->rc < 0 ? q->rc : 2;
+      if (q->rc < 0) {
+        s->failed += 1;
+      } else {
+        s->completed += 1;
+        s->particle_steps += (double)q->r.n * q->r.steps;
+      }
+    }
+    s->cv_admit.notify_all();
+    s->cv_done.notify_all();
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int pse_server_create(size_t budget_bytes, int max_active, pse_server **out) {
+  if (!out || max_active < 1 || max_active > 64) return PSE_ERR_INVALID;
+  *out = nullptr;
+  pse_server *s = new (std::nothrow) pse_server();
+  if (!s) return PSE_ERR_NOMEM;
+  if (budget_bytes == 0) {
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+      delete s;
+      return PSE_ERR_HIP;
+    }
+    budget_bytes = (size_t)(0.9 * (double)fr);
+  }
+  (void)hipGetDevice(&s->device);
+  s->budget = budget_bytes;
+  s->max_active = max_active;
+  s->t0 = Clock::now();
+  for (int i = 0; i < max_active; ++i) s->workers.emplace_back(worker, s);
+  *out = s;
+  return PSE_OK;
+}
+
+int pse_server_submit(pse_server *s, const pse_request *r, int64_t *id) {
+  if (!s || !r || !id || r->n <= 0 || !r->x0 || r->steps < 0 || !(r->dt > 0))
+    return PSE_ERR_INVALID;
+  pse_params p{};
+  p.n = r->n;
+  p.box = r->box;
+  p.radius = r->radius;
+  p.viscosity = r->viscosity;
+  p.kT = r->kT;
+  p.tol = r->tol;
+  p.grid = r->grid;
+  p.precision = r->precision;
+  p.gmres_tol = r->gmres_tol;
+  p.lanczos_tol = r->lanczos_tol;
+  size_t bytes = 0;
+  const int rc = pse_footprint_bytes(&p, &bytes);
+  if (rc != PSE_OK) return rc;
+  bytes += (size_t)r->n * 9 * sizeof(double);   // request positions and forces
+  if (bytes > s->budget) return PSE_ERR_NOMEM;
+  auto q = std::make_shared<Req>();
+  q->r = *r;
+  q->x0.assign(r->x0, r->x0 + 3 * r->n);
+  if (r->FL) q->fl.assign(r->FL, r->FL + 6 * r->n);
+  q->r.x0 = nullptr;
+  q->r.FL = r->FL ? q->fl.data() : nullptr;
+  q->bytes = bytes;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stopping) return PSE_ERR_INVALID;
+    q->id = s->next_id++;
+    q->t_submit = s->now();
+    s->queue.push_back(q);
+    s->all[q->id] = q;
+    *id = q->id;
+  }
+  s->cv_admit.notify_all();
+  return PSE_OK;
+}
+
+int pse_server_wait(pse_server *s, int64_t id, pse_request_info *info) {
+  if (!s) return PSE_ERR_INVALID;
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto it = s->all.find(id);
+  if (it == s->all.end()) return PSE_ERR_INVALID;
+  auto q = it->second;
+  s->cv_done.wait(lk, [&] { return q->status == 2 || q->status < 0; });
+  if (info) {
+    info->id = q->id;
+    info->status = q->status == 2 ? (q->rc > 0 ? q->rc : PSE_OK) : q->status;
+    info->steps_done = (int32_t)q->lat_ms.size();
+    info->bytes = q->bytes;
+    info->t_submit = q->t_submit;
+    info->t_admit = q->t_admit;
+    info->t_done = q->t_done;
+  }
+  return q->status < 0 ? q->status : PSE_OK;
+}
+
+int pse_server_result(pse_server *s, int64_t id, double *x_out, double *step_ms) {
+  if (!s) return PSE_ERR_INVALID;
+  std::shared_ptr<Req> q;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->all.find(id);
+    if (it == s->all.end()) return PSE_ERR_INVALID;
+    q = it->second;
+    if (q->status != 2 && q->status >= 0) return PSE_ERR_INVALID;
+  }
+  if (x_out && !q->x_out.empty()) std::memcpy(x_out, q->x_out.data(), q->x_out.size() * 8);
+  if (step_ms && !q->lat_ms.empty()) std::memcpy(step_ms, q->lat_ms.data(), q->lat_ms.size() * 8);
+  return PSE_OK;
+}
+
+int pse_server_release(pse_server *s, int64_t id) {
+  if (!s) return PSE_ERR_INVALID;
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->all.find(id);
+  if (it == s->all.end()) return PSE_ERR_INVALID;
+  if (it->second->status == 0 || it->second->status == 1) return PSE_ERR_INVALID;
+  s->all.erase(it);
+  return PSE_OK;
+}
+
+int pse_server_stats(pse_server *s, pse_server_info *out) {
+  if (!s || !out) return PSE_ERR_INVALID;
+  std::lock_guard<std::mutex> lk(s->mu);
+  out->budget = s->budget;
+  out->used = s->used;
+  out->peak_used = s->peak_used;
+  out->active = s->active;
+  out->peak_active = s->peak_active;
+  out->queued = (int32_t)s->queue.size();
+  out->completed = s->completed;
+  out->failed = s->failed;
+  out->particle_steps = s->particle_steps;
+  out->elapsed = s->now();
+  return PSE_OK;
+}
+
+int pse_server_destroy(pse_server *s) {
+  if (!s) return PSE_OK;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stopping = true;
+  }
+  s->cv_admit.notify_all();
+  for (auto &t : s->workers) t.join();
+  delete s;
+  return PSE_OK;
+}
+
+}  // extern "C"

@@ -58,10 +58,43 @@ class pse_kernel_stat(ctypes.Structure):
                 ('total_ms', ctypes.c_double), ('alg_bytes', ctypes.c_double)]
 
 
+class pse_request(ctypes.Structure):
+    _fields_ = [('n', ctypes.c_int64), ('box', ctypes.c_double), ('radius', ctypes.c_double),
+                ('viscosity', ctypes.c_double), ('kT', ctypes.c_double),
+                ('tol', ctypes.c_double), ('grid', ctypes.c_int32),
+                ('precision', ctypes.c_int32), ('gmres_tol', ctypes.c_double),
+                ('lanczos_tol', ctypes.c_double), ('steps', ctypes.c_int32),
+                ('dt', ctypes.c_double), ('seed', ctypes.c_uint64),
+                ('x0', ctypes.c_void_p), ('FL', ctypes.c_void_p)]
+
+
+class pse_request_info(ctypes.Structure):
+    _fields_ = [('id', ctypes.c_int64), ('status', ctypes.c_int32),
+                ('steps_done', ctypes.c_int32), ('bytes', ctypes.c_size_t),
+                ('t_submit', ctypes.c_double), ('t_admit', ctypes.c_double),
+                ('t_done', ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class pse_server_info(ctypes.Structure):
+    _fields_ = [('budget', ctypes.c_size_t), ('used', ctypes.c_size_t),
+                ('peak_used', ctypes.c_size_t), ('active', ctypes.c_int32),
+                ('peak_active', ctypes.c_int32), ('queued', ctypes.c_int32),
+                ('completed', ctypes.c_int64), ('failed', ctypes.c_int64),
+                ('particle_steps', ctypes.c_double), ('elapsed', ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 EXPORTS = ('pse_derive', 'pse_footprint_bytes', 'pse_create', 'pse_destroy',
            'pse_get_derived', 'pse_mobility_apply', 'pse_brownian_sample',
            'pse_constrained_step', 'pse_fft3d', 'pse_spread', 'pse_interpolate',
-           'pse_profile', 'pse_profile_read', 'pse_last_error')
+           'pse_profile', 'pse_profile_read', 'pse_server_create', 'pse_server_submit',
+           'pse_server_wait', 'pse_server_result', 'pse_server_release', 'pse_server_stats',
+           'pse_server_destroy', 'pse_last_error')
 
 
 def load_library(path=LIB_PATH):
@@ -85,6 +118,13 @@ def load_library(path=LIB_PATH):
     lib.pse_interpolate.argtypes = [V, V, V, I, V]
     lib.pse_profile.argtypes = [V, I]
     lib.pse_profile_read.argtypes = [V, P(pse_kernel_stat), I, P(I)]
+    lib.pse_server_create.argtypes = [ctypes.c_size_t, I, P(V)]
+    lib.pse_server_submit.argtypes = [V, P(pse_request), P(ctypes.c_int64)]
+    lib.pse_server_wait.argtypes = [V, ctypes.c_int64, P(pse_request_info)]
+    lib.pse_server_result.argtypes = [V, ctypes.c_int64, V, V]
+    lib.pse_server_release.argtypes = [V, ctypes.c_int64]
+    lib.pse_server_stats.argtypes = [V, P(pse_server_info)]
+    lib.pse_server_destroy.argtypes = [V]
     lib.pse_last_error.argtypes = [V]
     lib.pse_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
@@ -257,3 +297,83 @@ class PSE:
                                                  _ptr(grids, (nc, g, g, g), 'grids'), nc,
                                                  _ptr(out, (n, nc), 'out')),
                            'pse_interpolate')
+
+
+class PSEServer:
+    """Serving runtime: queue of independent simulations admitted onto the GPU
+    by device footprint, several running at once (host numpy arrays in/out)."""
+
+    def __init__(self, budget_bytes=0, max_active=4):
+        h = ctypes.c_void_p()
+        rc = lib().pse_server_create(int(budget_bytes), int(max_active), ctypes.byref(h))
+        if rc != PSE_OK:
+            raise PSEError(f'pse_server_create: {rc}')
+        self._h = h
+        self._meta = {}
+
+    def submit(self, x0, box, *, FL=None, steps=10, dt=1e-3, seed=0, radius=1.0,
+               viscosity=1.0, kT=1.0, tol=1e-3, grid=0, precision=PSE_FP64,
+               gmres_tol=0.0, lanczos_tol=0.0):
+        import numpy as np
+        x0 = np.ascontiguousarray(x0, dtype=np.float64)
+        n = x0.shape[0]
+        fl = None if FL is None else np.ascontiguousarray(FL, dtype=np.float64)
+        req = pse_request(n, float(box), float(radius), float(viscosity), float(kT),
+                          float(tol), int(grid), int(precision), float(gmres_tol),
+                          float(lanczos_tol), int(steps), float(dt), int(seed),
+                          x0.ctypes.data, None if fl is None else fl.ctypes.data)
+        rid = ctypes.c_int64()
+        rc = lib().pse_server_submit(self._h, ctypes.byref(req), ctypes.byref(rid))
+        if rc != PSE_OK:
+            raise PSEError(f'pse_server_submit: {rc}')
+        self._meta[rid.value] = (n, int(steps))
+        return rid.value
+
+    def wait(self, rid):
+        info = pse_request_info()
+        rc = lib().pse_server_wait(self._h, int(rid), ctypes.byref(info))
+        if rc < 0:
+            raise PSEError(f'request {rid} failed: {rc}')
+        return info.as_dict()
+
+    def result(self, rid):
+        import numpy as np
+        n, steps = self._meta[rid]
+        x = np.zeros((n, 3))
+        lat = np.zeros(max(steps, 1))
+        rc = lib().pse_server_result(self._h, int(rid), x.ctypes.data, lat.ctypes.data)
+        if rc != PSE_OK:
+            raise PSEError(f'pse_server_result: {rc}')
+        return x, lat[:steps]
+
+    def release(self, rid):
+        lib().pse_server_release(self._h, int(rid))
+        self._meta.pop(rid, None)
+
+    def stats(self):
+        info = pse_server_info()
+        lib().pse_server_stats(self._h, ctypes.byref(info))
+        return info.as_dict()
+
+    def close(self):
+        if getattr(self, '_h', None):
+            lib().pse_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+SUPPORTED_GRIDS = sorted({2**j for j in range(3, 11)} | {3 * 2**j for j in range(2, 9)})
+
+
+def grid_for(box, h_max=0.5, radius=1.0):
+    """Smallest supported grid with spacing <= h_max * radius."""
+    need = box / (h_max * radius)
+    for g in SUPPORTED_GRIDS:
+        if g >= need:
+            return g
+    raise ValueError(f'box {box} needs a grid above 1024')
