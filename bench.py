@@ -7,6 +7,9 @@ M_r^(1/2), wave-space M_w^(1/2), half step, GMRES on the stresslet
 constraint, final mobility product and position update.  The default workload
 is N = 10,000 hard spheres (a = 1) at phi = 0.3 in a 128^3 grid, eps = 1e-3,
 dt = 1e-3, with random non-overlapping positions and N(0, 1) forces/torques.
+Beside the FP64 headline: the mixed-precision form on the same workload, the
+served form (a Poisson stream of independent simulations of different N and
+phi with p50/p99 per-step latency), and the FP64 oracle on host cores.
 Prints one JSON line.
 """
 import argparse
@@ -98,6 +101,66 @@ def cpu_baseline():
                        f'eps=1e-3, dt=1e-3 ({dt:.2f} s per step)')
 
 
+def served(n_req, steps, max_active, n_max, rate_hz, seed):
+    """Served form: a Poisson stream of independent simulations with N
+    log-uniform in [1e3, n_max] and phi uniform in [0.05, 0.45], each `steps`
+    mixed-precision constrained steps at eps = 1e-3, admitted by device
+    footprint and run concurrently.  The same requests are also run one at a
+    time (no overlap) for comparison."""
+    import numpy as np
+
+    from paper_1709_06946_amd import inputs, pse
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for i in range(n_req):
+        n = int(round(np.exp(rng.uniform(np.log(1e3), np.log(n_max)))))
+        phi = float(rng.uniform(0.05, 0.45))
+        x, L = inputs.packing(n, phi, seed=seed + 10 + i)
+        reqs.append(dict(x=x, L=L, FL=inputs.forces_torques(n, seed + 5000 + i), n=n, phi=phi,
+                         grid=pse.grid_for(L), seed=seed + 9000 + i))
+    gaps = rng.exponential(1.0 / rate_hz, size=n_req)
+
+    def run(active, arrivals):
+        srv = pse.PSEServer(max_active=active)
+        t0 = time.perf_counter()
+        ids = []
+        for r, g in zip(reqs, gaps):
+            if arrivals:
+                time.sleep(g)
+            ids.append(srv.submit(r['x'], r['L'], FL=r['FL'], steps=steps, dt=1e-3,
+                                  seed=r['seed'], grid=r['grid'], precision=pse.PSE_MIXED))
+        lat, waits = [], []
+        for rid in ids:
+            info = srv.wait(rid)
+            _, l = srv.result(rid)
+            lat.extend(l.tolist())
+            waits.append(info['t_admit'] - info['t_submit'])
+            srv.release(rid)
+        wall = time.perf_counter() - t0
+        st = srv.stats()
+        srv.close()
+        lat = np.asarray(lat)
+        return dict(particle_steps_per_s=round(st['particle_steps'] / wall, 1),
+                    wall_s=round(wall, 3), p50_step_ms=round(float(np.percentile(lat, 50)), 3),
+                    p99_step_ms=round(float(np.percentile(lat, 99)), 3),
+                    p50_admit_wait_ms=round(1e3 * float(np.percentile(waits, 50)), 3),
+                    peak_active=st['peak_active'], peak_used_GB=round(st['peak_used'] / 1e9, 3),
+                    completed=st['completed'], failed=st['failed'])
+
+    for r in reqs[:1]:      # warm the library (code objects, tables)
+        srv = pse.PSEServer(max_active=1)
+        srv.wait(srv.submit(r['x'], r['L'], FL=r['FL'], steps=1, grid=r['grid'],
+                            precision=pse.PSE_MIXED))
+        srv.close()
+    conc = run(max_active, True)
+    serial = run(1, False)
+    return dict(requests=n_req, steps_per_request=steps, n_range=[1000, n_max],
+                phi_range=[0.05, 0.45], arrival_rate_hz=rate_hz, max_active=max_active,
+                dtype='f32+f64', tol=1e-3,
+                total_particles=int(sum(r['n'] for r in reqs)),
+                concurrent=conc, one_at_a_time=serial)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument('--gpus', type=int, default=1)
@@ -106,6 +169,12 @@ def main():
     ap.add_argument('--workload', default='n10000_phi0.3_g128')
     ap.add_argument('--no-cpu-baseline', action='store_true')
     ap.add_argument('--no-mixed', action='store_true')
+    ap.add_argument('--no-served', action='store_true')
+    ap.add_argument('--served-requests', type=int, default=16)
+    ap.add_argument('--served-steps', type=int, default=20)
+    ap.add_argument('--served-nmax', type=int, default=20000)
+    ap.add_argument('--served-active', type=int, default=4)
+    ap.add_argument('--served-rate', type=float, default=40.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f'bench.py runs on one GPU only (--gpus {args.gpus} requested): the method '
@@ -143,6 +212,9 @@ def main():
         stages_ms={k: round(v['total_ms'] / args.steps, 3) for k, v in fp64['prof'].items()},
         mixed=mixed,
     )
+    if not args.no_served:
+        out['served'] = served(args.served_requests, args.served_steps, args.served_active,
+                               args.served_nmax, args.served_rate, seed + 777)
     if not args.no_cpu_baseline:
         out['cpu_baseline'] = cpu_baseline()
     print(json.dumps(out), flush=True)
