@@ -117,11 +117,7 @@ static void wave_apply(Handle &h, const double *xw, const double *in, const Comp
   T *gin = reinterpret_cast<T *>(G.gin), *gout = reinterpret_cast<T *>(G.gout);
   spread<T>(h, xw, in, NC, cin, gin);
   rfft_xy<T>(h, gin, G.twiddle, cin.n, -1);
-  if (!kspace_fused<T>(h, G.gin, cin, G.gout, cout, G.twiddle)) {
-    rfft_z<T>(h, gin, G.twiddle, cin.n, -1);
-    kspace_mobility<T>(h, G.gin, cin, G.gout, cout);
-    rfft_z<T>(h, gout, G.twiddle, cout.n, +1);
-  }
+  kspace_fused<T>(h, G.gin, cin, G.gout, cout, G.twiddle);
   rfft_xy<T>(h, gout, G.twiddle, cout.n, +1);
   interpolate<T>(h, xw, gout, cout, out, NC, accumulate, 1.0);
 }
@@ -292,6 +288,8 @@ static void create(const pse_params &p, Handle &h) {
     PSE_LAUNCH_CHECK();
   }
   build_tables(h);
+  alloc((void **)&h.ktab, (size_t)ktable_len(ng) * 4 * sizeof(double));
+  build_ktable(h);
   for (Bins *b : {&h.cells, &h.sbins}) {
     if (b->nc == 0) continue;
     const size_t ncells = (size_t)b->nc * b->nc * b->nc;
@@ -324,7 +322,7 @@ static void release(Handle &h) {
                   h.cells.scan_tmp, h.cells.of, h.cells.slot, h.cells.perm, h.sbins.start,
                   h.sbins.count, h.sbins.scan_tmp, h.sbins.of, h.sbins.slot, h.sbins.perm,
                   h.xw, h.xh, h.v0, h.v1, h.v2, h.v3, h.v4, h.v5, h.es_b, h.es_x, h.es_r,
-                  h.es_d, h.lz_V, h.gm_V, h.small, h.dots};
+                  h.es_d, h.lz_V, h.gm_V, h.small, h.dots, h.ktab};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   for (hipEvent_t e : h.prof.pool) (void)hipEventDestroy(e);

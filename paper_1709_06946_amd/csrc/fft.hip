@@ -1,226 +1,327 @@
-// Batched 3D complex FFT for the wave-space NUFFT (Sec. II.C: the F of
-// Eq. WSops2).  Unnormalized: dir = -1 computes sum_n f_n exp(-2 pi i k n / N)
-// along each axis, dir = +1 the conjugate sum.
+// Batched 3D FFTs of the wave-space NUFFT (Sec. II.C: the F of Eq. WSops2),
+// unnormalised: dir = -1 computes sum_n f_n exp(-2 pi i k n / N) along each
+// axis, dir = +1 the conjugate sum.
 //
-// One kernel per axis.  A workgroup loads TL whole lines of length N into
-// LDS, runs the Stockham autosort FFT of stockham.h between two LDS buffers,
-// and writes the lines back in place.  LDS is laid out [position][line] so that, along the y and z
-// axes, consecutive threads touch consecutive x addresses both in HBM and in
-// LDS.
-#include "stockham.h"
+// One kernel per axis, built on the register-resident line FFT of fftreg.h.
+// Grids of real components R[c][z][y][x] are transformed in place into half
+// spectra H[c][kz][ky][kx < N/2] (a row of N reals holds N/2 complex); the
+// Nyquist column kx = N/2 is not stored, and every Nyquist mode is zero in
+// the spectra the k-space kernels produce.
+#include "fftreg.h"
 
 namespace pse {
 
-// pass 0: lines along x (contiguous); 1: along y; 2: along z.
-template <typename T>
-__global__ void __launch_bounds__(256)
-fft_pass(cplx<T> *__restrict__ data, const cplx<T> *__restrict__ tw,
-         FftPlan plan, int pass, int dir) {
-  using C = cplx<T>;
-  extern __shared__ unsigned char smem_raw[];
-  C *buf0 = reinterpret_cast<C *>(smem_raw);
-  const int N = plan.n, M = plan.m, TL = plan.tl;
-  C *buf1 = buf0 + N * TL;
-  // stored array per component: [z][y][x] with extents N, N, M
-  const size_t row = M, plane = (size_t)N * M, vol = plane * N;
-  size_t base, ls, es;
-  const size_t b = blockIdx.x;
-  if (pass == 0) {
-    base = b * TL * (size_t)N;
-    ls = N;
-    es = 1;
-  } else {
-    const int tiles = M / TL;
-    const size_t xt = b % tiles;
-    const size_t rest = b / tiles;       // (c, z) for pass 1, (c, y) for pass 2
-    const size_t c = rest / N, o = rest % N;
-    if (pass == 1) {
-      base = c * vol + o * plane + xt * TL;
-      ls = 1;
-      es = row;
-    } else {
-      base = c * vol + o * row + xt * TL;
-      ls = 1;
-      es = plane;
-    }
-  }
-  const int total = N * TL;
-  for (int w = threadIdx.x; w < total; w += blockDim.x) {
-    int line, pos;
-    if (pass == 0) { pos = w % N; line = w / N; }
-    else           { line = w % TL; pos = w / TL; }
-    buf0[pos * TL + line] = data[base + line * ls + pos * es];
-  }
-  __syncthreads();
-  C *src = stockham_all<T>(buf0, buf1, plan, tw, dir);
-  for (int w = threadIdx.x; w < total; w += blockDim.x) {
-    int line, pos;
-    if (pass == 0) { pos = w % N; line = w / N; }
-    else           { line = w % TL; pos = w / TL; }
-    data[base + line * ls + pos * es] = src[pos * TL + line];
-  }
-}
+// ------------------------------------------------------------- x passes --
 
-// x pass of the real transforms.  Real grids R[c][z][y][x] and half spectra
-// H[c][z][y][kx], kx in [0, n/2), share the same memory (a row of n reals
-// holds n/2 complex).  The Nyquist column kx = n/2 is not stored: the
-// k-space kernels zero every Nyquist mode.  Rows y and y+1 travel together
-// as one complex line z = a + i b; after the complex FFT the two spectra are
-// A(k) = (Z(k) + conj Z(-k))/2 and B(k) = (Z(k) - conj Z(-k))/2i.
-template <typename T>
+// Rows y and y+1 travel as one complex line z = a + i b.  After the forward
+// transform the two half spectra are A(k) = (Z(k) + conj Z(-k))/2 and
+// B(k) = (Z(k) - conj Z(-k))/2i, separated from LDS and written over the rows.
+template <typename T, int N>
 __global__ void __launch_bounds__(256)
-fft_x_r2c(T *__restrict__ data, const cplx<T> *__restrict__ tw, FftPlan plan) {
+fft_x_r2c_kernel(T *__restrict__ data, const cplx<T> *__restrict__ tw, int TL) {
   using C = cplx<T>;
+  constexpr int E = line_e(N), TPL = N / E, H = N / 2;
+  using S = Shape<N, E>;
   extern __shared__ unsigned char smem_raw[];
-  C *buf0 = reinterpret_cast<C *>(smem_raw);
-  const int N = plan.n, TL = plan.tl, H = N / 2;
-  C *buf1 = buf0 + N * TL;
-  const size_t row0 = (size_t)blockIdx.x * TL * 2;   // first real row of the block
-  for (int w = threadIdx.x; w < N * TL; w += blockDim.x) {
-    const int pos = w % N, line = w / N;
-    const T *r = data + (row0 + 2 * line) * N;
-    C z;
-    z.x = r[pos];
-    z.y = r[N + pos];
-    buf0[pos * TL + line] = z;
-  }
+  C *lds = reinterpret_cast<C *>(smem_raw);
+  const int line = threadIdx.x / TPL, t = threadIdx.x % TPL;
+  const size_t pair = (size_t)blockIdx.x * TL + line;
+  T *row = data + 2 * pair * N;
+  constexpr int R0 = S::first(false);
+  C v[E];
+#pragma unroll
+  for (int b = 0; b < E / R0; ++b)
+#pragma unroll
+    for (int r = 0; r < R0; ++r) {
+      const int pos = reg_pos<N, E, R0>(t, b, r);
+      v[b * R0 + r] = C{row[pos], row[N + pos]};
+    }
+  const int off = line * (N + 1);
+  reg_fft_forward<T, N, E>(v, t, lds, 1, off, tw);
+  constexpr int RL = S::last(false);
   __syncthreads();
-  C *Z = stockham_all<T>(buf0, buf1, plan, tw, -1);
-  for (int w = threadIdx.x; w < H * TL; w += blockDim.x) {
-    const int k = w % H, line = w / H;
-    const C zp = Z[k * TL + line], zm = Z[((N - k) % N) * TL + line];
+#pragma unroll
+  for (int b = 0; b < E / RL; ++b)
+#pragma unroll
+    for (int r = 0; r < RL; ++r) lds[off + reg_pos<N, E, RL>(t, b, r)] = v[b * RL + r];
+  __syncthreads();
+  const C *Z = lds;
+  for (int w = threadIdx.x; w < TL * H; w += blockDim.x) {
+    const int ln = w / H, k = w % H;
+    const C zp = Z[ln * (N + 1) + k], zm = Z[ln * (N + 1) + (N - k) % N];
     C a, bb;
     a.x = (T)0.5 * (zp.x + zm.x);
     a.y = (T)0.5 * (zp.y - zm.y);
     bb.x = (T)0.5 * (zp.y + zm.y);
     bb.y = (T)0.5 * (zm.x - zp.x);
-    C *out = reinterpret_cast<C *>(data + (row0 + 2 * line) * N);
+    C *out = reinterpret_cast<C *>(data + 2 * ((size_t)blockIdx.x * TL + ln) * N);
     out[k] = a;
-    out[H + k] = bb;        // the next row starts n/2 complex further on
+    out[H + k] = bb;
   }
 }
 
-// Inverse: Z(k) = A(k) + i B(k) with A(-k) = conj A(k) (Nyquist zero), the
-// complex inverse FFT gives rows y (real part) and y+1 (imaginary part).
-template <typename T>
+// Inverse: Z(k) = A(k) + i B(k), with A(-k) = conj A(k) and B likewise and
+// the Nyquist term zero; the complex inverse transform returns rows y (real
+// part) and y+1 (imaginary part).
+template <typename T, int N>
 __global__ void __launch_bounds__(256)
-fft_x_c2r(T *__restrict__ data, const cplx<T> *__restrict__ tw, FftPlan plan) {
+fft_x_c2r_kernel(T *__restrict__ data, const cplx<T> *__restrict__ tw, int TL) {
   using C = cplx<T>;
+  constexpr int E = line_e(N), TPL = N / E, H = N / 2;
+  using S = Shape<N, E>;
   extern __shared__ unsigned char smem_raw[];
-  C *buf0 = reinterpret_cast<C *>(smem_raw);
-  const int N = plan.n, TL = plan.tl, H = N / 2;
-  C *buf1 = buf0 + N * TL;
-  const size_t row0 = (size_t)blockIdx.x * TL * 2;
-  for (int w = threadIdx.x; w < N * TL; w += blockDim.x) {
-    const int k = w % N, line = w / N;
-    const C *in = reinterpret_cast<const C *>(data + (row0 + 2 * line) * N);
-    C z;
-    if (k < H) {
-      const C a = in[k], bb = in[H + k];
-      z.x = a.x - bb.y;
-      z.y = a.y + bb.x;
-    } else if (k == H) {
-      z.x = (T)0;
-      z.y = (T)0;
-    } else {
-      const C a = in[N - k], bb = in[H + N - k];   // conj A(N-k) + i conj B(N-k)
-      z.x = a.x + bb.y;
-      z.y = -a.y + bb.x;
-    }
-    buf0[k * TL + line] = z;
+  C *lds = reinterpret_cast<C *>(smem_raw);
+  for (int w = threadIdx.x; w < TL * H; w += blockDim.x) {
+    const int ln = w / H, k = w % H;
+    const C *in = reinterpret_cast<const C *>(data + 2 * ((size_t)blockIdx.x * TL + ln) * N);
+    const C a = in[k], bb = in[H + k];
+    C *Z = lds + ln * (N + 1);
+    Z[k] = C{a.x - bb.y, a.y + bb.x};
+    if (k > 0) Z[N - k] = C{a.x + bb.y, bb.x - a.y};
+    else Z[H] = C{(T)0, (T)0};
   }
   __syncthreads();
-  C *Z = stockham_all<T>(buf0, buf1, plan, tw, +1);
-  for (int w = threadIdx.x; w < N * TL; w += blockDim.x) {
-    const int pos = w % N, line = w / N;
-    T *r = data + (row0 + 2 * line) * N;
-    const C z = Z[pos * TL + line];
-    r[pos] = z.x;
-    r[N + pos] = z.y;
+  const int line = threadIdx.x / TPL, t = threadIdx.x % TPL;
+  const int off = line * (N + 1);
+  constexpr int R0 = S::first(true);
+  C v[E];
+#pragma unroll
+  for (int b = 0; b < E / R0; ++b)
+#pragma unroll
+    for (int r = 0; r < R0; ++r) v[b * R0 + r] = lds[off + reg_pos<N, E, R0>(t, b, r)];
+  reg_fft_inverse<T, N, E>(v, t, lds, 1, off, tw);
+  constexpr int RL = S::last(true);
+  T *row = data + 2 * ((size_t)blockIdx.x * TL + line) * N;
+#pragma unroll
+  for (int b = 0; b < E / RL; ++b)
+#pragma unroll
+    for (int r = 0; r < RL; ++r) {
+      const int pos = reg_pos<N, E, RL>(t, b, r);
+      row[pos] = v[b * RL + r].x;
+      row[N + pos] = v[b * RL + r].y;
+    }
+}
+
+// Complex lines along x (contiguous), for the full complex transform.
+template <typename T, int N>
+__global__ void __launch_bounds__(256)
+fft_xc_kernel(cplx<T> *__restrict__ data, const cplx<T> *__restrict__ tw, int dir, int TL) {
+  using C = cplx<T>;
+  constexpr int E = line_e(N), TPL = N / E;
+  using S = Shape<N, E>;
+  extern __shared__ unsigned char smem_raw[];
+  C *lds = reinterpret_cast<C *>(smem_raw);
+  const int line = threadIdx.x / TPL, t = threadIdx.x % TPL;
+  C *ln = data + ((size_t)blockIdx.x * TL + line) * N;
+  const int off = line * (N + 1);
+  C v[E];
+  if (dir < 0) {
+    constexpr int R0 = S::first(false), RL = S::last(false);
+#pragma unroll
+    for (int b = 0; b < E / R0; ++b)
+#pragma unroll
+      for (int r = 0; r < R0; ++r) v[b * R0 + r] = ln[reg_pos<N, E, R0>(t, b, r)];
+    reg_fft_forward<T, N, E>(v, t, lds, 1, off, tw);
+#pragma unroll
+    for (int b = 0; b < E / RL; ++b)
+#pragma unroll
+      for (int r = 0; r < RL; ++r) ln[reg_pos<N, E, RL>(t, b, r)] = v[b * RL + r];
+  } else {
+    constexpr int R0 = S::first(true), RL = S::last(true);
+#pragma unroll
+    for (int b = 0; b < E / R0; ++b)
+#pragma unroll
+      for (int r = 0; r < R0; ++r) v[b * R0 + r] = ln[reg_pos<N, E, R0>(t, b, r)];
+    reg_fft_inverse<T, N, E>(v, t, lds, 1, off, tw);
+#pragma unroll
+    for (int b = 0; b < E / RL; ++b)
+#pragma unroll
+      for (int r = 0; r < RL; ++r) ln[reg_pos<N, E, RL>(t, b, r)] = v[b * RL + r];
   }
 }
 
-template <typename T>
-void fft3d(Handle &h, cplx<T> *data, const cplx<T> *twiddle, int ncomp, int dir) {
-  const int n = h.d.grid;
-  FftPlan plan = make_plan(n, sizeof(cplx<T>));
-  const size_t lds = 2 * (size_t)n * plan.tl * sizeof(cplx<T>);
-  const unsigned nb = (unsigned)((size_t)ncomp * n * n / plan.tl);
-  for (int pass = 0; pass < 3; ++pass) {
-    ProfScope ps(h, PK_FFT, 2.0 * ncomp * h.ngrid * sizeof(cplx<T>));
-    hipLaunchKernelGGL(fft_pass<T>, dim3(nb), dim3(256), lds, h.stream, data,
-                       twiddle, plan, pass, dir);
-    PSE_LAUNCH_CHECK();
+// ------------------------------------------------------- y and z passes --
+
+// Lines along y (axis 1) or z (axis 2) of complex arrays [c][z][y][x] with
+// extents N, N, M.  A workgroup owns TL neighbouring x positions; thread
+// (t, line) = (tid / TL, tid % TL), so every global access of a wavefront
+// covers TL consecutive x addresses.
+template <typename T, int N>
+__global__ void __launch_bounds__(256)
+fft_lines_kernel(cplx<T> *__restrict__ data, const cplx<T> *__restrict__ tw, int M, int axis,
+                 int dir, int TL) {
+  using C = cplx<T>;
+  constexpr int E = line_e(N);
+  using S = Shape<N, E>;
+  extern __shared__ unsigned char smem_raw[];
+  C *lds = reinterpret_cast<C *>(smem_raw);
+  const int tiles = M / TL;
+  const size_t xt = blockIdx.x % tiles, rest = blockIdx.x / tiles;
+  const size_t c = rest / N, o = rest % N;
+  const size_t plane = (size_t)N * M, vol = plane * N;
+  const int line = threadIdx.x % TL, t = threadIdx.x / TL;
+  size_t base, es;
+  if (axis == 1) {
+    base = c * vol + o * plane + xt * TL + line;
+    es = M;
+  } else {
+    base = c * vol + o * M + xt * TL + line;
+    es = plane;
+  }
+  C v[E];
+  if (dir < 0) {
+    constexpr int R0 = S::first(false), RL = S::last(false);
+#pragma unroll
+    for (int b = 0; b < E / R0; ++b)
+#pragma unroll
+      for (int r = 0; r < R0; ++r) v[b * R0 + r] = data[base + reg_pos<N, E, R0>(t, b, r) * es];
+    reg_fft_forward<T, N, E>(v, t, lds, TL, line, tw);
+#pragma unroll
+    for (int b = 0; b < E / RL; ++b)
+#pragma unroll
+      for (int r = 0; r < RL; ++r) data[base + reg_pos<N, E, RL>(t, b, r) * es] = v[b * RL + r];
+  } else {
+    constexpr int R0 = S::first(true), RL = S::last(true);
+#pragma unroll
+    for (int b = 0; b < E / R0; ++b)
+#pragma unroll
+      for (int r = 0; r < R0; ++r) v[b * R0 + r] = data[base + reg_pos<N, E, R0>(t, b, r) * es];
+    reg_fft_inverse<T, N, E>(v, t, lds, TL, line, tw);
+#pragma unroll
+    for (int b = 0; b < E / RL; ++b)
+#pragma unroll
+      for (int r = 0; r < RL; ++r) data[base + reg_pos<N, E, RL>(t, b, r) * es] = v[b * RL + r];
   }
 }
 
-// Real 3D transforms of ncomp real grids stored [c][z][y][x], in place.
-// Forward leaves half spectra [c][kz][ky][kx < n/2]; inverse takes them back.
-template <typename T>
-static void half_pass(Handle &h, T *grids, const cplx<T> *tw, int ncomp, int dir, int pass) {
-  const int n = h.d.grid;
-  FftPlan plan = make_plan(n, sizeof(cplx<T>));
-  plan.m = n / 2;
-  while (plan.tl > 1 && (n / 2) % plan.tl) plan.tl /= 2;
-  const size_t lds = 2 * (size_t)n * plan.tl * sizeof(cplx<T>);
-  const unsigned nb = (unsigned)((size_t)ncomp * n * (n / 2) / plan.tl);
-  ProfScope ps(h, PK_FFT, 2.0 * ncomp * h.ngrid * sizeof(T));
-  hipLaunchKernelGGL(fft_pass<T>, dim3(nb), dim3(256), lds, h.stream,
-                     reinterpret_cast<cplx<T> *>(grids), tw, plan, pass, dir);
+// -------------------------------------------------------------- host side --
+
+// Lines per workgroup: a power of two dividing `count`, about 256 threads,
+// LDS within 64 KiB.
+int lines_per_block(int n, int tpl, size_t line_bytes, size_t count) {
+  int tl = 1;
+  while (tl * 2 * tpl <= 256 && count % (size_t)(tl * 2) == 0 &&
+         (size_t)(tl * 2) * line_bytes <= 65536)
+    tl *= 2;
+  return tl;
+}
+
+namespace {
+
+template <typename T, int N>
+void launch_x(Handle &h, T *grids, const cplx<T> *tw, int ncomp, int dir) {
+  constexpr int TPL = N / line_e(N);
+  const size_t pairs = (size_t)ncomp * N * N / 2;
+  const int tl = lines_per_block(N, TPL, (N + 1) * sizeof(cplx<T>), pairs);
+  const size_t lds = (size_t)tl * (N + 1) * sizeof(cplx<T>);
+  const unsigned nb = (unsigned)(pairs / tl);
+  if (dir < 0)
+    hipLaunchKernelGGL((fft_x_r2c_kernel<T, N>), dim3(nb), dim3(tl * TPL), lds, h.stream, grids,
+                       tw, tl);
+  else
+    hipLaunchKernelGGL((fft_x_c2r_kernel<T, N>), dim3(nb), dim3(tl * TPL), lds, h.stream, grids,
+                       tw, tl);
   PSE_LAUNCH_CHECK();
 }
+
+template <typename T, int N>
+void launch_xc(Handle &h, cplx<T> *data, const cplx<T> *tw, int ncomp, int dir) {
+  constexpr int TPL = N / line_e(N);
+  const size_t lines = (size_t)ncomp * N * N;
+  const int tl = lines_per_block(N, TPL, (N + 1) * sizeof(cplx<T>), lines);
+  const size_t lds = (size_t)tl * (N + 1) * sizeof(cplx<T>);
+  hipLaunchKernelGGL((fft_xc_kernel<T, N>), dim3((unsigned)(lines / tl)), dim3(tl * TPL), lds,
+                     h.stream, data, tw, dir, tl);
+  PSE_LAUNCH_CHECK();
+}
+
+template <typename T, int N>
+void launch_lines(Handle &h, cplx<T> *data, const cplx<T> *tw, int ncomp, int M, int axis,
+                  int dir) {
+  constexpr int TPL = N / line_e(N);
+  const int tl = lines_per_block(N, TPL, N * sizeof(cplx<T>), (size_t)M);
+  const size_t lds = (size_t)tl * N * sizeof(cplx<T>);
+  const unsigned nb = (unsigned)((size_t)ncomp * N * (M / tl));
+  hipLaunchKernelGGL((fft_lines_kernel<T, N>), dim3(nb), dim3(tl * TPL), lds, h.stream, data,
+                     tw, M, axis, dir, tl);
+  PSE_LAUNCH_CHECK();
+}
+
+}  // namespace
+
+#define PSE_CASE_X(NN) case NN: launch_x<T, NN>(h, grids, tw, ncomp, dir); break;
+#define PSE_CASE_XC(NN) case NN: launch_xc<T, NN>(h, data, tw, ncomp, dir); break;
+#define PSE_CASE_L(NN) case NN: launch_lines<T, NN>(h, data, tw, ncomp, M, axis, dir); break;
 
 template <typename T>
 static void x_pass(Handle &h, T *grids, const cplx<T> *tw, int ncomp, int dir) {
-  const int n = h.d.grid;
-  FftPlan plan = make_plan(n, sizeof(cplx<T>));
-  // plan.tl counts row pairs here; rows per component n^2 (even)
-  while (plan.tl > 1 && ((size_t)n * n / 2) % plan.tl) plan.tl /= 2;
-  const size_t lds = 2 * (size_t)n * plan.tl * sizeof(cplx<T>);
-  const unsigned nb = (unsigned)((size_t)ncomp * n * n / 2 / plan.tl);
   ProfScope ps(h, PK_FFT, 2.0 * ncomp * h.ngrid * sizeof(T));
-  if (dir < 0)
-    hipLaunchKernelGGL(fft_x_r2c<T>, dim3(nb), dim3(256), lds, h.stream, grids, tw, plan);
-  else
-    hipLaunchKernelGGL(fft_x_c2r<T>, dim3(nb), dim3(256), lds, h.stream, grids, tw, plan);
-  PSE_LAUNCH_CHECK();
-}
-
-template <typename T>
-void rfft_xy(Handle &h, T *grids, const cplx<T> *twiddle, int ncomp, int dir) {
-  if (dir < 0) {
-    x_pass<T>(h, grids, twiddle, ncomp, dir);
-    half_pass<T>(h, grids, twiddle, ncomp, dir, 1);
-  } else {
-    half_pass<T>(h, grids, twiddle, ncomp, dir, 1);
-    x_pass<T>(h, grids, twiddle, ncomp, dir);
+  switch (h.d.grid) {
+    PSE_FOR_EACH_N(PSE_CASE_X)
+    default: throw Error{PSE_ERR_INVALID, "unsupported FFT length"};
   }
 }
 
 template <typename T>
-void rfft_z(Handle &h, T *grids, const cplx<T> *twiddle, int ncomp, int dir) {
-  half_pass<T>(h, grids, twiddle, ncomp, dir, 2);
+static void line_pass(Handle &h, cplx<T> *data, const cplx<T> *tw, int ncomp, int M, int axis,
+                      int dir) {
+  ProfScope ps(h, PK_FFT, 2.0 * ncomp * (double)h.d.grid * h.d.grid * M * sizeof(cplx<T>));
+  switch (h.d.grid) {
+    PSE_FOR_EACH_N(PSE_CASE_L)
+    default: throw Error{PSE_ERR_INVALID, "unsupported FFT length"};
+  }
 }
 
 template <typename T>
-void rfft3d(Handle &h, T *grids, const cplx<T> *twiddle, int ncomp, int dir) {
+void fft3d(Handle &h, cplx<T> *data, const cplx<T> *tw, int ncomp, int dir) {
+  const int n = h.d.grid;
+  {
+    ProfScope ps(h, PK_FFT, 2.0 * ncomp * h.ngrid * sizeof(cplx<T>));
+    switch (n) {
+      PSE_FOR_EACH_N(PSE_CASE_XC)
+      default: throw Error{PSE_ERR_INVALID, "unsupported FFT length"};
+    }
+  }
+  line_pass<T>(h, data, tw, ncomp, n, 1, dir);
+  line_pass<T>(h, data, tw, ncomp, n, 2, dir);
+}
+
+template <typename T>
+void rfft_xy(Handle &h, T *grids, const cplx<T> *tw, int ncomp, int dir) {
+  const int n = h.d.grid;
+  cplx<T> *spec = reinterpret_cast<cplx<T> *>(grids);
   if (dir < 0) {
-    rfft_xy<T>(h, grids, twiddle, ncomp, dir);
-    rfft_z<T>(h, grids, twiddle, ncomp, dir);
+    x_pass<T>(h, grids, tw, ncomp, dir);
+    line_pass<T>(h, spec, tw, ncomp, n / 2, 1, dir);
   } else {
-    rfft_z<T>(h, grids, twiddle, ncomp, dir);
-    rfft_xy<T>(h, grids, twiddle, ncomp, dir);
+    line_pass<T>(h, spec, tw, ncomp, n / 2, 1, dir);
+    x_pass<T>(h, grids, tw, ncomp, dir);
+  }
+}
+
+template <typename T>
+void rfft_z(Handle &h, T *grids, const cplx<T> *tw, int ncomp, int dir) {
+  line_pass<T>(h, reinterpret_cast<cplx<T> *>(grids), tw, ncomp, h.d.grid / 2, 2, dir);
+}
+
+template <typename T>
+void rfft3d(Handle &h, T *grids, const cplx<T> *tw, int ncomp, int dir) {
+  if (dir < 0) {
+    rfft_xy<T>(h, grids, tw, ncomp, dir);
+    rfft_z<T>(h, grids, tw, ncomp, dir);
+  } else {
+    rfft_z<T>(h, grids, tw, ncomp, dir);
+    rfft_xy<T>(h, grids, tw, ncomp, dir);
   }
 }
 
 #define INST(T, C)                                                  \
   template void rfft3d<T>(Handle &, T *, const C *, int, int);      \
   template void rfft_xy<T>(Handle &, T *, const C *, int, int);     \
-  template void rfft_z<T>(Handle &, T *, const C *, int, int);
+  template void rfft_z<T>(Handle &, T *, const C *, int, int);      \
+  template void fft3d<T>(Handle &, C *, const C *, int, int);
 INST(double, double2)
 INST(float, float2)
 #undef INST
-template void fft3d<double>(Handle &, double2 *, const double2 *, int, int);
-template void fft3d<float>(Handle &, float2 *, const float2 *, int, int);
 
 }  // namespace pse

@@ -13,7 +13,7 @@
 // divides both out again.
 #include <mutex>
 
-#include "stockham.h"
+#include "fftreg.h"
 
 namespace pse {
 
@@ -254,8 +254,34 @@ struct KGeom {
   double a;
   double inv4xi2;     // 1 / (4 xi^2)
   double one_m_etas;  // 1 - eta_s
-  double pref;        // mobility: h^6 / (V eta); noise: h^3 / sqrt(V eta)
+  double pref_m;      // mobility: h^6 / (V eta)
+  double pref_n;      // noise: h^3 / sqrt(V eta)
 };
+
+// Every stored wave vector is k = (2 pi / L) (i, j, l) with integers, so all
+// radial factors depend on |k|^2 only through the integer n2 = i^2 + j^2 + l^2
+// <= 3 (N/2)^2.  The table holds, per n2:
+//   x = j0(ka), y = f1(ka), z = h^6/(V eta) (1 + u) e^{-(1 - eta_s) u} / k^2,
+//   w = h^3/sqrt(V eta) sqrt(1 + u) e^{-(1 - eta_s) u / 2} / k,  u = k^2 / 4 xi^2
+// (the mobility scaling of Eq. WSops2 with both Gaussian factors divided out,
+// and the amplitude of Eq. FFTsqrt).  Entry 0 (k = 0) is zero.
+__global__ void __launch_bounds__(256)
+ktable_kernel(KGeom kg, int len, double4 *__restrict__ tab) {
+  const int n2 = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n2 >= len) return;
+  if (n2 == 0) {
+    tab[0] = double4{0, 0, 0, 0};
+    return;
+  }
+  const double k2 = kg.twopi_L * kg.twopi_L * (double)n2;
+  const double k = sqrt(k2);
+  double j0, f1;
+  shape_factors(k * kg.a, j0, f1);
+  const double u = k2 * kg.inv4xi2;
+  const double mob = kg.pref_m * (1.0 + u) * exp(-kg.one_m_etas * u) / k2;
+  const double amp = kg.pref_n * sqrt(1.0 + u) * exp(-0.5 * kg.one_m_etas * u) / k;
+  tab[n2] = double4{j0, f1, mob, amp};
+}
 
 // Column of P(k) for moment component c (0..10), as (coef, col): the
 // contribution to rho is coef * col * g with coef real for F (j0) and
@@ -284,27 +310,28 @@ __device__ __forceinline__ void p_column(int c, double kx, double ky, double kz,
 
 // rho += P_c(k) g
 template <typename C>
-__device__ __forceinline__ void add_P(int c, C gv, const double *kv, double j0,
-                                      double f1, C *rho) {
+__device__ __forceinline__ void add_P(int c, C gv, const double *kv, double j0, double f1,
+                                      C *rho) {
   bool imag;
   double cx, cy, cz;
   p_column(c, kv[0], kv[1], kv[2], j0, f1, imag, cx, cy, cz);
+  const double gx = gv.x, gy = gv.y;
   if (!imag) {
-    rho[0].x += cx * gv.x; rho[0].y += cx * gv.y;
-    rho[1].x += cy * gv.x; rho[1].y += cy * gv.y;
-    rho[2].x += cz * gv.x; rho[2].y += cz * gv.y;
+    rho[0].x += cx * gx; rho[0].y += cx * gy;
+    rho[1].x += cy * gx; rho[1].y += cy * gy;
+    rho[2].x += cz * gx; rho[2].y += cz * gy;
   } else {
     // i col g = col (-g.y, g.x)
-    rho[0].x -= cx * gv.y; rho[0].y += cx * gv.x;
-    rho[1].x -= cy * gv.y; rho[1].y += cy * gv.x;
-    rho[2].x -= cz * gv.y; rho[2].y += cz * gv.x;
+    rho[0].x -= cx * gy; rho[0].y += cx * gx;
+    rho[1].x -= cy * gy; rho[1].y += cy * gx;
+    rho[2].x -= cz * gy; rho[2].y += cz * gx;
   }
 }
 
 // W_c = P_c^+ u = conj(coef) col . u
 template <typename C>
-__device__ __forceinline__ C apply_Pdag(int c, const C *u, const double *kv,
-                                        double j0, double f1) {
+__device__ __forceinline__ C apply_Pdag(int c, const C *u, const double *kv, double j0,
+                                        double f1) {
   bool imag;
   double cx, cy, cz;
   p_column(c, kv[0], kv[1], kv[2], j0, f1, imag, cx, cy, cz);
@@ -322,152 +349,120 @@ __device__ __forceinline__ C apply_Pdag(int c, const C *u, const double *kv,
   return w;
 }
 
-// Stored half-spectrum mode (ix < n/2, iy, iz): 0 = process, 1 = zero it
-// (a Nyquist index in y or z, or k = 0; the x Nyquist column is not stored).
+// Stored half-spectrum mode (ix < n/2, iy, iz) that is zeroed: a Nyquist
+// index in y or z, or k = 0 (the x Nyquist column is not stored).
 __device__ __forceinline__ bool zero_mode(int ix, int iy, int iz, int n) {
   const int h = n / 2;
   return iy == h || iz == h || (ix == 0 && iy == 0 && iz == 0);
 }
 
-template <typename T>
-__global__ void __launch_bounds__(256)
-kspace_mobility_kernel(const cplx<T> *__restrict__ in, CompSet cin,
-                       cplx<T> *__restrict__ out, CompSet cout, KGeom kg) {
-  using C = cplx<T>;
-  const int n = kg.ng, hx = n / 2;
-  const size_t hsz = (size_t)hx * n * n;            // modes per component
-  const size_t tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (tid >= hsz) return;
-  const int ix = (int)(tid % hx);
-  const int iy = (int)((tid / hx) % n);
-  const int iz = (int)(tid / ((size_t)hx * n));
-  if (zero_mode(ix, iy, iz, n)) {
-    for (int q = 0; q < cout.n; ++q) out[q * hsz + tid] = C{(T)0, (T)0};
-    return;
-  }
-  const double kv[3] = {kg.twopi_L * ix, kg.twopi_L * kidx(iy, n), kg.twopi_L * kidx(iz, n)};
-  const double k2 = kv[0] * kv[0] + kv[1] * kv[1] + kv[2] * kv[2];
-  const double kk = sqrt(k2);
-  double j0, f1;
-  shape_factors(kk * kg.a, j0, f1);
-  double2 rho[3] = {{0, 0}, {0, 0}, {0, 0}};
-  for (int p = 0; p < cin.n; ++p) {
-    const C z = in[p * hsz + tid];
-    add_P(cin.idx[p], double2{(double)z.x, (double)z.y}, kv, j0, f1, rho);
-  }
-  // u = scale (I - kk) rho
-  const double u = k2 * kg.inv4xi2;
-  const double scale = kg.pref * (1.0 + u) * exp(-kg.one_m_etas * u) / k2;
-  double2 kr{0, 0};
-  for (int m = 0; m < 3; ++m) {
-    kr.x += kv[m] * rho[m].x;
-    kr.y += kv[m] * rho[m].y;
-  }
-  double2 uu[3];
-  for (int m = 0; m < 3; ++m) {
-    uu[m].x = scale * (rho[m].x - kv[m] * kr.x / k2);
-    uu[m].y = scale * (rho[m].y - kv[m] * kr.y / k2);
-  }
-  for (int q = 0; q < cout.n; ++q) {
-    const double2 w = apply_Pdag(cout.idx[q], uu, kv, j0, f1);
-    out[q * hsz + tid] = C{(T)w.x, (T)w.y};
-  }
-}
-
-// Fused z transform + k-space kernel + inverse z transform.  A workgroup owns
-// TL neighbouring kx columns at one ky, i.e. TL z-lines.  Each input
-// component is loaded, transformed along z in LDS and folded at once into
-// rho(k) = sum_c P_c(k) G_c(k) (three complex numbers per k, kept in LDS), so
-// the inputs stream through one at a time; then rho is scaled and projected,
-// and each output component P_q^+ u is built, inverse-transformed along z and
-// stored.  This replaces three full sweeps over the grids (z pass, k-space,
-// inverse z pass) by one read of the inputs and one write of the outputs.
-template <typename T>
+// Fused z transform + k-space kernel + inverse z transform (Eq. WSops2 from
+// the half spectra after the x and y transforms back to them).  A workgroup
+// owns TL neighbouring kx columns at one ky, i.e. TL z-lines, each
+// transformed by TPL threads that hold E modes in registers.  For every input
+// component the z transform runs in registers and the mode is folded at
+// once into rho(k) = sum_c P_c(k) G_c(k) (three complex numbers per mode,
+// kept in registers), so the inputs stream through one at a time.  Then
+// u = scale (I - k^k^) rho, and for every output component P_q^+ u is formed
+// in the same registers -- the inverse transform runs the passes in reverse
+// order, so its input layout is the forward output layout -- transformed back
+// along z and stored.  One read of the inputs and one write of the outputs.
+template <typename T, int N>
 __global__ void __launch_bounds__(256)
 kspace_fused_kernel(const cplx<T> *__restrict__ in, CompSet cin, cplx<T> *__restrict__ out,
-                    CompSet cout, KGeom kg, FftPlan plan, const cplx<T> *__restrict__ tw) {
+                    CompSet cout, KGeom kg, const double4 *__restrict__ ktab,
+                    const cplx<T> *__restrict__ tw, int TL) {
   using C = cplx<T>;
+  constexpr int E = fused_e(N), M = N / 2;
+  using S = Shape<N, E>;
+  constexpr int R0 = S::first(false), RL = S::last(false);
   extern __shared__ unsigned char smem_raw[];
-  const int N = plan.n, TL = plan.tl, M = N / 2;
-  const int NT = N * TL;
-  C *rho = reinterpret_cast<C *>(smem_raw);     // 3 x NT
-  C *buf0 = rho + 3 * NT, *buf1 = buf0 + NT;
+  C *lds = reinterpret_cast<C *>(smem_raw);
   const int tiles = M / TL;
   const int xt = blockIdx.x % tiles, iy = blockIdx.x / tiles;
+  const int line = threadIdx.x % TL, t = threadIdx.x / TL;
+  const int ix = xt * TL + line;
+  const int ky = kidx(iy, N);
   const size_t hsz = (size_t)M * N * N, plane = (size_t)N * M;
-  const size_t base = (size_t)iy * M + (size_t)xt * TL;
-  for (int w = threadIdx.x; w < 3 * NT; w += blockDim.x) rho[w] = C{(T)0, (T)0};
+  const size_t base = (size_t)iy * M + ix;
+  C rho[E][3];
+#pragma unroll
+  for (int e = 0; e < E; ++e)
+#pragma unroll
+    for (int m = 0; m < 3; ++m) rho[e][m] = C{(T)0, (T)0};
+  C v[E];
   for (int p = 0; p < cin.n; ++p) {
-    __syncthreads();
-    for (int w = threadIdx.x; w < NT; w += blockDim.x) {
-      const int line = w % TL, kz = w / TL;
-      buf0[w] = in[p * hsz + base + kz * plane + line];
-    }
-    __syncthreads();
-    const C *res = stockham_all<T>(buf0, buf1, plan, tw, -1);
-    for (int w = threadIdx.x; w < NT; w += blockDim.x) {
-      const int line = w % TL, kz = w / TL;
-      const int ix = xt * TL + line;
-      if (zero_mode(ix, iy, kz, N)) continue;
-      const double kv[3] = {kg.twopi_L * ix, kg.twopi_L * kidx(iy, N), kg.twopi_L * kidx(kz, N)};
-      double j0, f1;
-      shape_factors(sqrt(kv[0] * kv[0] + kv[1] * kv[1] + kv[2] * kv[2]) * kg.a, j0, f1);
-      double2 r3[3] = {{0, 0}, {0, 0}, {0, 0}};
-      const C g = res[w];
-      add_P(cin.idx[p], double2{(double)g.x, (double)g.y}, kv, j0, f1, r3);
-      for (int m = 0; m < 3; ++m) {
-        rho[m * NT + w].x += (T)r3[m].x;
-        rho[m * NT + w].y += (T)r3[m].y;
+    const C *src = in + (size_t)p * hsz + base;
+#pragma unroll
+    for (int b = 0; b < E / R0; ++b)
+#pragma unroll
+      for (int r = 0; r < R0; ++r) v[b * R0 + r] = src[reg_pos<N, E, R0>(t, b, r) * plane];
+    reg_fft_forward<T, N, E>(v, t, lds, TL, line, tw);
+    const int c = cin.idx[p];
+#pragma unroll
+    for (int b = 0; b < E / RL; ++b)
+#pragma unroll
+      for (int r = 0; r < RL; ++r) {
+        const int iz = reg_pos<N, E, RL>(t, b, r);
+        if (zero_mode(ix, iy, iz, N)) continue;
+        const int kz = kidx(iz, N);
+        const double4 tb = ktab[ix * ix + ky * ky + kz * kz];
+        const double kv[3] = {kg.twopi_L * ix, kg.twopi_L * ky, kg.twopi_L * kz};
+        add_P(c, v[b * RL + r], kv, tb.x, tb.y, rho[b * RL + r]);
       }
-    }
   }
-  __syncthreads();
-  // u = scale (I - kk) rho, in place
-  for (int w = threadIdx.x; w < NT; w += blockDim.x) {
-    const int line = w % TL, kz = w / TL;
-    const int ix = xt * TL + line;
-    if (zero_mode(ix, iy, kz, N)) {
-      for (int m = 0; m < 3; ++m) rho[m * NT + w] = C{(T)0, (T)0};
-      continue;
-    }
-    const double kv[3] = {kg.twopi_L * ix, kg.twopi_L * kidx(iy, N), kg.twopi_L * kidx(kz, N)};
-    const double k2 = kv[0] * kv[0] + kv[1] * kv[1] + kv[2] * kv[2];
-    const double u = k2 * kg.inv4xi2;
-    const double scale = kg.pref * (1.0 + u) * exp(-kg.one_m_etas * u) / k2;
-    double2 r[3];
-    for (int m = 0; m < 3; ++m) r[m] = double2{(double)rho[m * NT + w].x, (double)rho[m * NT + w].y};
-    double2 kr{0, 0};
-    for (int m = 0; m < 3; ++m) {
-      kr.x += kv[m] * r[m].x;
-      kr.y += kv[m] * r[m].y;
-    }
-    for (int m = 0; m < 3; ++m)
-      rho[m * NT + w] = C{(T)(scale * (r[m].x - kv[m] * kr.x / k2)),
-                          (T)(scale * (r[m].y - kv[m] * kr.y / k2))};
-  }
-  for (int q = 0; q < cout.n; ++q) {
-    __syncthreads();
-    for (int w = threadIdx.x; w < NT; w += blockDim.x) {
-      const int line = w % TL, kz = w / TL;
-      const int ix = xt * TL + line;
-      if (zero_mode(ix, iy, kz, N)) {
-        buf0[w] = C{(T)0, (T)0};
+  // u = scale (I - k^k^) rho
+#pragma unroll
+  for (int b = 0; b < E / RL; ++b)
+#pragma unroll
+    for (int r = 0; r < RL; ++r) {
+      const int e = b * RL + r;
+      const int iz = reg_pos<N, E, RL>(t, b, r);
+      const int kz = kidx(iz, N);
+      const int n2 = ix * ix + ky * ky + kz * kz;
+      if (zero_mode(ix, iy, iz, N)) {
+#pragma unroll
+        for (int m = 0; m < 3; ++m) rho[e][m] = C{(T)0, (T)0};
         continue;
       }
-      const double kv[3] = {kg.twopi_L * ix, kg.twopi_L * kidx(iy, N), kg.twopi_L * kidx(kz, N)};
-      double j0, f1;
-      shape_factors(sqrt(kv[0] * kv[0] + kv[1] * kv[1] + kv[2] * kv[2]) * kg.a, j0, f1);
-      double2 uu[3];
-      for (int m = 0; m < 3; ++m) uu[m] = double2{(double)rho[m * NT + w].x, (double)rho[m * NT + w].y};
-      const double2 wv = apply_Pdag(cout.idx[q], uu, kv, j0, f1);
-      buf0[w] = C{(T)wv.x, (T)wv.y};
+      const double scale = ktab[n2].z;
+      const double kv[3] = {(double)ix, (double)ky, (double)kz};
+      const double inv = 1.0 / (double)n2;
+      double krx = 0, kry = 0;
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        krx += kv[m] * (double)rho[e][m].x;
+        kry += kv[m] * (double)rho[e][m].y;
+      }
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        rho[e][m].x = (T)(scale * ((double)rho[e][m].x - kv[m] * krx * inv));
+        rho[e][m].y = (T)(scale * ((double)rho[e][m].y - kv[m] * kry * inv));
+      }
     }
-    __syncthreads();
-    const C *res = stockham_all<T>(buf0, buf1, plan, tw, +1);
-    for (int w = threadIdx.x; w < NT; w += blockDim.x) {
-      const int line = w % TL, kz = w / TL;
-      out[q * hsz + base + kz * plane + line] = res[w];
-    }
+  for (int q = 0; q < cout.n; ++q) {
+    const int c = cout.idx[q];
+#pragma unroll
+    for (int b = 0; b < E / RL; ++b)
+#pragma unroll
+      for (int r = 0; r < RL; ++r) {
+        const int e = b * RL + r;
+        const int iz = reg_pos<N, E, RL>(t, b, r);
+        if (zero_mode(ix, iy, iz, N)) {
+          v[e] = C{(T)0, (T)0};
+          continue;
+        }
+        const int kz = kidx(iz, N);
+        const double4 tb = ktab[ix * ix + ky * ky + kz * kz];
+        const double kv[3] = {kg.twopi_L * ix, kg.twopi_L * ky, kg.twopi_L * kz};
+        v[e] = apply_Pdag(c, rho[e], kv, tb.x, tb.y);
+      }
+    reg_fft_inverse<T, N, E>(v, t, lds, TL, line, tw);
+    C *dst = out + (size_t)q * hsz + base;
+#pragma unroll
+    for (int b = 0; b < E / R0; ++b)
+#pragma unroll
+      for (int r = 0; r < R0; ++r) dst[reg_pos<N, E, R0>(t, b, r) * plane] = v[b * R0 + r];
   }
 }
 
@@ -523,9 +518,9 @@ enum : uint32_t { STREAM_REAL = 1, STREAM_WAVE = 2 };
 // spectrum is Hermitian.
 template <typename T>
 __global__ void __launch_bounds__(256)
-kspace_noise_kernel(const double2 *__restrict__ psi, uint64_t seed,
-                    uint64_t counter, cplx<T> *__restrict__ out, CompSet cout,
-                    KGeom kg) {
+kspace_noise_kernel(const double2 *__restrict__ psi, uint64_t seed, uint64_t counter,
+                    cplx<T> *__restrict__ out, CompSet cout, KGeom kg,
+                    const double4 *__restrict__ ktab) {
   using C = cplx<T>;
   const int n = kg.ng, hx = n / 2, hp = n / 2 + 1;
   const size_t hsz = (size_t)hx * n * n;
@@ -554,25 +549,24 @@ kspace_noise_kernel(const double2 *__restrict__ psi, uint64_t seed,
   }
   if (!canon)
     for (int m = 0; m < 3; ++m) ps[m].y = -ps[m].y;
-  const double kv[3] = {kg.twopi_L * ix, kg.twopi_L * kidx(iy, n), kg.twopi_L * kidx(iz, n)};
-  const double k2 = kv[0] * kv[0] + kv[1] * kv[1] + kv[2] * kv[2];
-  const double kk = sqrt(k2);
-  double j0, f1;
-  shape_factors(kk * kg.a, j0, f1);
-  const double u = k2 * kg.inv4xi2;
-  const double amp = kg.pref * sqrt(1.0 + u) * exp(-0.5 * kg.one_m_etas * u) / kk;
+  const int ky = kidx(iy, n), kz = kidx(iz, n);
+  const int n2 = ix * ix + ky * ky + kz * kz;
+  const double4 tb = ktab[n2];
+  const double kv[3] = {kg.twopi_L * ix, kg.twopi_L * ky, kg.twopi_L * kz};
+  const double iv[3] = {(double)ix, (double)ky, (double)kz};
+  const double inv = 1.0 / (double)n2;
   double2 kr{0, 0};
   for (int m = 0; m < 3; ++m) {
-    kr.x += kv[m] * ps[m].x;
-    kr.y += kv[m] * ps[m].y;
+    kr.x += iv[m] * ps[m].x;
+    kr.y += iv[m] * ps[m].y;
   }
   double2 uu[3];
   for (int m = 0; m < 3; ++m) {
-    uu[m].x = amp * (ps[m].x - kv[m] * kr.x / k2);
-    uu[m].y = amp * (ps[m].y - kv[m] * kr.y / k2);
+    uu[m].x = tb.w * (ps[m].x - iv[m] * kr.x * inv);
+    uu[m].y = tb.w * (ps[m].y - iv[m] * kr.y * inv);
   }
   for (int q = 0; q < cout.n; ++q) {
-    const double2 w = apply_Pdag(cout.idx[q], uu, kv, j0, f1);
+    const double2 w = apply_Pdag(cout.idx[q], uu, kv, tb.x, tb.y);
     out[q * hsz + tid] = C{(T)w.x, (T)w.y};
   }
 }
@@ -621,7 +615,7 @@ static GridGeom geom(const Handle &h) {
   return g;
 }
 
-static KGeom kgeom(const Handle &h, bool noise) {
+static KGeom kgeom(const Handle &h) {
   KGeom k;
   k.ng = h.d.grid;
   k.twopi_L = 2.0 * M_PI / h.p.box;
@@ -630,8 +624,18 @@ static KGeom kgeom(const Handle &h, bool noise) {
   k.one_m_etas = 1.0 - h.d.eta_s;
   const double V = h.p.box * h.p.box * h.p.box;
   const double h3 = h.d.h * h.d.h * h.d.h;
-  k.pref = noise ? h3 / sqrt(V * h.p.viscosity) : h3 * h3 / (V * h.p.viscosity);
+  k.pref_n = h3 / sqrt(V * h.p.viscosity);
+  k.pref_m = h3 * h3 / (V * h.p.viscosity);
   return k;
+}
+
+int ktable_len(int grid) { return 3 * (grid / 2) * (grid / 2) + 1; }
+
+void build_ktable(Handle &h) {
+  const int len = ktable_len(h.d.grid);
+  hipLaunchKernelGGL(ktable_kernel, dim3(nblocks(len, 256)), dim3(256), 0, h.stream, kgeom(h),
+                     len, (double4 *)h.ktab);
+  PSE_LAUNCH_CHECK();
 }
 
 template <typename T>
@@ -674,50 +678,33 @@ void interpolate(Handle &h, const double *x, const T *grids, const CompSet &cs,
   PSE_LAUNCH_CHECK();
 }
 
-template <typename T>
-void kspace_mobility(Handle &h, const cplx<T> *in, const CompSet &cin,
-                     cplx<T> *out, const CompSet &cout) {
-  const size_t hsz = h.ngrid / 2;
-  ProfScope ps(h, PK_KSPACE, (double)(cin.n + cout.n) * hsz * sizeof(cplx<T>));
-  hipLaunchKernelGGL(kspace_mobility_kernel<T>, dim3(nblocks(hsz, 256)),
-                     dim3(256), 0, h.stream, in, cin, out, cout, kgeom(h, false));
-  PSE_LAUNCH_CHECK();
-}
+namespace {
 
-// Fused plan: TL z-lines per workgroup, five LDS line sets within 80 KiB;
-// returns tl = 0 when fewer than 4 lines would fit (use the separate passes).
-template <typename T> static FftPlan fused_plan(const Handle &h) {
-  const int n = h.d.grid;
-  FftPlan plan = make_plan(n, sizeof(cplx<T>));
-  int tl = (int)(81920 / (5 * sizeof(cplx<T>) * (size_t)n));
-  int t = 1;
-  while (t * 2 <= tl && (n / 2) % (t * 2) == 0) t *= 2;
-  plan.tl = t >= 4 ? t : 0;
-  plan.m = n / 2;
-  return plan;
-}
-
-template <typename T>
-bool kspace_fused(Handle &h, const cplx<T> *in, const CompSet &cin, cplx<T> *out,
+template <typename T, int N>
+void launch_fused(Handle &h, const cplx<T> *in, const CompSet &cin, cplx<T> *out,
                   const CompSet &cout, const cplx<T> *tw) {
-  FftPlan plan = fused_plan<T>(h);
-  if (plan.tl == 0) return false;
-  const int n = h.d.grid;
-  const size_t lds = 5 * (size_t)n * plan.tl * sizeof(cplx<T>);
-  static std::once_flag once;
-  hipError_t attr = hipSuccess;
-  std::call_once(once, [&] {
-    attr = hipFuncSetAttribute((const void *)kspace_fused_kernel<T>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, 81920);
-  });
-  PSE_HIP(attr);
+  constexpr int TPL = N / fused_e(N);
+  const int tl = lines_per_block(N, TPL, N * sizeof(cplx<T>), (size_t)N / 2);
+  const size_t lds = (size_t)tl * N * sizeof(cplx<T>);
+  const unsigned nb = (unsigned)(N * (N / 2 / tl));
+  hipLaunchKernelGGL((kspace_fused_kernel<T, N>), dim3(nb), dim3(tl * TPL), lds, h.stream, in,
+                     cin, out, cout, kgeom(h), (const double4 *)h.ktab, tw, tl);
+  PSE_LAUNCH_CHECK();
+}
+
+}  // namespace
+
+#define PSE_CASE_F(NN) case NN: launch_fused<T, NN>(h, in, cin, out, cout, tw); break;
+
+template <typename T>
+void kspace_fused(Handle &h, const cplx<T> *in, const CompSet &cin, cplx<T> *out,
+                  const CompSet &cout, const cplx<T> *tw) {
   const size_t hsz = h.ngrid / 2;
   ProfScope ps(h, PK_KSPACE, (double)(cin.n + cout.n) * hsz * sizeof(cplx<T>));
-  const unsigned nb = (unsigned)(n * (n / 2 / plan.tl));
-  hipLaunchKernelGGL(kspace_fused_kernel<T>, dim3(nb), dim3(256), lds, h.stream, in, cin, out,
-                     cout, kgeom(h, false), plan, tw);
-  PSE_LAUNCH_CHECK();
-  return true;
+  switch (h.d.grid) {
+    PSE_FOR_EACH_N(PSE_CASE_F)
+    default: throw Error{PSE_ERR_INVALID, "unsupported FFT length"};
+  }
 }
 
 template <typename T>
@@ -727,7 +714,7 @@ void kspace_noise(Handle &h, const double *psi, uint64_t seed, uint64_t counter,
   ProfScope ps(h, PK_NOISE, (double)cout.n * hsz * sizeof(cplx<T>) + (psi ? 3.0 * hsz * 16 : 0.0));
   hipLaunchKernelGGL(kspace_noise_kernel<T>, dim3(nblocks(hsz, 256)), dim3(256),
                      0, h.stream, (const double2 *)psi, seed, counter, out, cout,
-                     kgeom(h, true));
+                     kgeom(h), (const double4 *)h.ktab);
   PSE_LAUNCH_CHECK();
 }
 
@@ -761,11 +748,9 @@ template <typename T> void to_double(Handle &h, const T *src, size_t n, double *
                           const CompSet &, T *);                                 \
   template void interpolate<T>(Handle &, const double *, const T *,              \
                                const CompSet &, double *, int, bool, double);    \
-  template void kspace_mobility<T>(Handle &, const cplx<T> *, const CompSet &,   \
-                                   cplx<T> *, const CompSet &);                  \
   template void kspace_noise<T>(Handle &, const double *, uint64_t, uint64_t,    \
                                 cplx<T> *, const CompSet &);                     \
-  template bool kspace_fused<T>(Handle &, const cplx<T> *, const CompSet &,      \
+  template void kspace_fused<T>(Handle &, const cplx<T> *, const CompSet &,      \
                                 cplx<T> *, const CompSet &, const cplx<T> *);    \
   template void zero_grids<T>(Handle &, T *, int);                               \
   template void from_double<T>(Handle &, const double *, size_t, T *);           \

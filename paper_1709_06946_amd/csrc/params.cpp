@@ -102,6 +102,7 @@ size_t footprint(const pse_params &p, const pse_derived &d) {
   bytes += 2 * MAX_PACK * ng3 * sizeof(double2) + d.grid * sizeof(double2);
   if (p.precision == PSE_MIXED)
     bytes += 2 * MAX_PACK * ng3 * sizeof(float2) + d.grid * sizeof(float2);
+  bytes += (size_t)(3 * (d.grid / 2) * (d.grid / 2) + 1) * 4 * sizeof(double);
   const size_t ntab = (size_t)(2048.0 * d.rcut / (2 * p.radius)) + 16;
   bytes += ntab * NCOEF * (sizeof(double) + sizeof(float));
   const size_t tiles3 = ng3 / 64;   // spreading tiles (at most 4^3 points each)

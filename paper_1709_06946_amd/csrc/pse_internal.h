@@ -125,6 +125,8 @@ struct Handle {
   double *v4 = nullptr, *v5 = nullptr;
   double *es_b = nullptr, *es_x = nullptr, *es_r = nullptr, *es_d = nullptr;  // N x 5
 
+  double *ktab = nullptr;    // per-|k|^2 radial factors (4 doubles per entry)
+
   // Krylov storage
   double *lz_V = nullptr;    // (lanczos_maxit + 1) x 11N
   double *gm_V = nullptr;    // (gmres_restart + 1) x 5N
@@ -191,17 +193,15 @@ template <typename T>
 void interpolate(Handle &h, const double *x, const T *grids, const CompSet &cs,
                  double *out, int ostride, bool accumulate, double scale);
 template <typename T>
-void kspace_mobility(Handle &h, const cplx<T> *in, const CompSet &cin,
-                     cplx<T> *out, const CompSet &cout);
-template <typename T>
 void kspace_noise(Handle &h, const double *psi, uint64_t seed, uint64_t counter,
                   cplx<T> *out, const CompSet &cout);
-// z transform + k-space + inverse z transform in one kernel; false if the
-// grid is too long for the LDS budget (caller then runs the separate passes)
+// z transform + k-space + inverse z transform in one kernel
 template <typename T>
-bool kspace_fused(Handle &h, const cplx<T> *in, const CompSet &cin, cplx<T> *out,
+void kspace_fused(Handle &h, const cplx<T> *in, const CompSet &cin, cplx<T> *out,
                   const CompSet &cout, const cplx<T> *tw);
 template <typename T> void zero_grids(Handle &h, T *g, int ncomp);
+int ktable_len(int grid);                         // entries of the |k|^2 table
+void build_ktable(Handle &h);
 template <typename T> void from_double(Handle &h, const double *src, size_t n, T *dst);
 template <typename T> void to_double(Handle &h, const T *src, size_t n, double *dst);
 
