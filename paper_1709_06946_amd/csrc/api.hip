@@ -260,9 +260,7 @@ static void create(const pse_params &p, Handle &h) {
   h.cells.nc = h.d.cells;
   // spreading tiles of stile^3 grid points gather from the 27 neighbouring
   // tiles, so a stencil (P points) must not reach beyond one tile.
-  h.stile = 4;
-  while (h.stile < 16 && (h.d.support + 1) / 2 > h.stile) h.stile *= 2;
-  if (h.d.grid % h.stile != 0 || h.d.grid / h.stile < 3) h.stile = 0;
+  h.stile = spread_tile(h.d.grid, h.d.support);
   h.sbins.nc = h.stile ? h.d.grid / h.stile : 0;
   if (p.stream) {
     h.stream = (hipStream_t)p.stream;
@@ -290,6 +288,19 @@ static void create(const pse_params &p, Handle &h) {
   build_tables(h);
   alloc((void **)&h.ktab, (size_t)ktable_len(ng) * 4 * sizeof(double));
   build_ktable(h);
+  if (h.stile) {
+    const size_t ntile = (size_t)h.sbins.nc * h.sbins.nc * h.sbins.nc;
+    alloc((void **)&h.tl_cnt, ntile * sizeof(int));
+    alloc((void **)&h.tl_start, (ntile + 1) * sizeof(int));
+    alloc((void **)&h.tl_scan, ((ntile + 1023) / 1024 + 8) * sizeof(int));
+    alloc((void **)&h.tl_list, n * tiles_per_particle(h.d.support, h.stile) * sizeof(int));
+  }
+  alloc((void **)&h.pl_cnt, n * sizeof(int));
+  alloc((void **)&h.pl_start, (n + 1) * sizeof(int));
+  alloc((void **)&h.pl_scan, ((n + 1023) / 1024 + 8) * sizeof(int));
+  h.pl_cap = pair_capacity(h.p, h.d);
+  alloc((void **)&h.pl_nbr, h.pl_cap * sizeof(int));
+  alloc((void **)&h.pl_rec, h.pl_cap * 10 * sizeof(double));
   for (Bins *b : {&h.cells, &h.sbins}) {
     if (b->nc == 0) continue;
     const size_t ncells = (size_t)b->nc * b->nc * b->nc;
@@ -322,7 +333,9 @@ static void release(Handle &h) {
                   h.cells.scan_tmp, h.cells.of, h.cells.slot, h.cells.perm, h.sbins.start,
                   h.sbins.count, h.sbins.scan_tmp, h.sbins.of, h.sbins.slot, h.sbins.perm,
                   h.xw, h.xh, h.v0, h.v1, h.v2, h.v3, h.v4, h.v5, h.es_b, h.es_x, h.es_r,
-                  h.es_d, h.lz_V, h.gm_V, h.small, h.dots, h.ktab};
+                  h.es_d, h.lz_V, h.gm_V, h.small, h.dots, h.ktab, h.pl_cnt,
+                  h.pl_start, h.pl_scan, h.pl_nbr, h.pl_rec, h.tl_cnt, h.tl_start,
+                  h.tl_scan, h.tl_list};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   for (hipEvent_t e : h.prof.pool) (void)hipEventDestroy(e);

@@ -70,45 +70,85 @@ spread_kernel(const double *__restrict__ x, const double *__restrict__ q,
   }
 }
 
-// Gather form of the same sum: one workgroup per tile of S^3 grid points.
-// Every particle whose stencil meets the tile lies in the 27 bins around it
-// (the stencil reaches at most (P+1)/2 <= S points past its own bin); their
-// positions, stencil origins and moments are staged in LDS in chunks, and
-// each thread sums the Gaussians over its grid points.  Every grid point is
-// written exactly once: no atomics and no zeroing pass.
+// Gather form of the same sum: one workgroup per tile of S^3 grid points,
+// reading the tile's candidate list (the particles whose stencil meets the
+// tile, built once per position update by tile_list_kernel).  The
+// candidates' positions, stencil origins and moments are staged in LDS in
+// chunks and each thread sums the Gaussians over its grid points.  Every
+// grid point is written exactly once: no atomics and no zeroing pass.
 constexpr int GMAXC = 128;
+
+// Whether a stencil starting at grid index st (P points) meets the tile
+// starting at t0 (S points) on a periodic axis of ng points.
+__device__ __forceinline__ bool stencil_meets(int st, int t0, int P, int S, int ng) {
+  int a = (t0 - st) % ng;
+  a += a < 0 ? ng : 0;
+  return a < P || a > ng - S;
+}
+
+// FILL = false: count each tile's candidates; true: write them from
+// start[tile] on, in bin order and ranked with a ballot.  One wavefront per
+// tile scans the particles of the 27 bins around it (bins are tiles; a
+// stencil reaches at most one tile beyond its particle's).
+template <bool FILL>
+__global__ void __launch_bounds__(256)
+tile_list_kernel(const double *__restrict__ x, GridGeom g, int S, int nb,
+                 const int *__restrict__ bstart, const int *__restrict__ bperm,
+                 int *__restrict__ cnt, const int *__restrict__ start, int *__restrict__ list) {
+  const int tile = blockIdx.x * 4 + threadIdx.x / 64;
+  const int lane = threadIdx.x % 64;
+  if (tile >= nb * nb * nb) return;
+  const int tx = tile % nb, ty = (tile / nb) % nb, tz = tile / (nb * nb);
+  const int P = g.P, ng = g.ng;
+  int pos = FILL ? start[tile] : 0;
+  int count = 0;
+  for (int o = 0; o < 27; ++o) {
+    const int bx = (tx + o % 3 - 1 + nb) % nb;
+    const int by = (ty + (o / 3) % 3 - 1 + nb) % nb;
+    const int bz = (tz + o / 9 - 1 + nb) % nb;
+    const int b = (bz * nb + by) * nb + bx;
+    const int b0 = bstart[b], b1 = bstart[b + 1];
+    for (int base = b0; base < b1; base += 64) {
+      const int s = base + lane;
+      bool ok = false;
+      int p = 0;
+      if (s < b1) {
+        p = bperm[s];
+        ok = stencil_meets(stencil_start(x[3 * p], g.h, P), tx * S, P, S, ng) &&
+             stencil_meets(stencil_start(x[3 * p + 1], g.h, P), ty * S, P, S, ng) &&
+             stencil_meets(stencil_start(x[3 * p + 2], g.h, P), tz * S, P, S, ng);
+      }
+      if (!FILL) {
+        count += ok ? 1 : 0;
+      } else {
+        const unsigned long long m = __ballot(ok);
+        if (ok) list[pos + __popcll(m & ((1ull << lane) - 1ull))] = p;
+        pos += __popcll(m);
+      }
+    }
+  }
+  if (!FILL) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) count += __shfl_xor(count, off, 64);
+    if (lane == 0) cnt[tile] = count;
+  }
+}
 
 template <typename T, int S>
 __global__ void __launch_bounds__(S * S * S < 256 ? S * S * S : 256)
-spread_gather_kernel(const double *__restrict__ x, const double *__restrict__ q,
-                     int qstride, CompSet cs, GridGeom g, int nb,
-                     const int *__restrict__ bstart, const int *__restrict__ bperm,
-                     T *__restrict__ grids, size_t ngrid) {
+spread_list_kernel(const double *__restrict__ x, const double *__restrict__ q,
+                   int qstride, CompSet cs, GridGeom g, int nb,
+                   const int *__restrict__ tstart, const int *__restrict__ tlist,
+                   T *__restrict__ grids, size_t ngrid) {
   constexpr int NT = S * S * S < 256 ? S * S * S : 256;
   constexpr int PPT = S * S * S / NT;
-  __shared__ int pre[28];
-  __shared__ int bfirst[27];
   __shared__ double cxs[GMAXC], cys[GMAXC], czs[GMAXC];
   __shared__ int sxs[GMAXC], sys[GMAXC], szs[GMAXC];
   __shared__ T cq[NC][GMAXC];
   const int tile = blockIdx.x;
   const int tx = tile % nb, ty = (tile / nb) % nb, tz = tile / (nb * nb);
-  if (threadIdx.x < 27) {
-    const int o = threadIdx.x;
-    const int bx = (tx + o % 3 - 1 + nb) % nb;
-    const int by = (ty + (o / 3) % 3 - 1 + nb) % nb;
-    const int bz = (tz + o / 9 - 1 + nb) % nb;
-    const int b = (bz * nb + by) * nb + bx;
-    bfirst[o] = bstart[b];
-    pre[o + 1] = bstart[b + 1] - bstart[b];
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    pre[0] = 0;
-    for (int o = 0; o < 27; ++o) pre[o + 1] += pre[o];
-  }
-  __syncthreads();
-  const int total = pre[27];
+  const int lo = tstart[tile];
+  const int total = tstart[tile + 1] - lo;
   const int P = g.P, ng = g.ng;
   const double kn3 = g.knorm * g.knorm * g.knorm;
   int gx[PPT], gy[PPT], gz[PPT];
@@ -125,11 +165,8 @@ spread_gather_kernel(const double *__restrict__ x, const double *__restrict__ q,
   for (int c0 = 0; c0 < total; c0 += GMAXC) {
     __syncthreads();
     for (int t = threadIdx.x; t < GMAXC; t += NT) {
-      const int idx = c0 + t;
-      if (idx < total) {
-        int o = 0;
-        while (pre[o + 1] <= idx) ++o;
-        const int p = bperm[bfirst[o] + idx - pre[o]];
+      if (c0 + t < total) {
+        const int p = tlist[lo + c0 + t];
         const double px = x[3 * p], py = x[3 * p + 1], pz = x[3 * p + 2];
         cxs[t] = px;
         cys[t] = py;
@@ -139,7 +176,7 @@ spread_gather_kernel(const double *__restrict__ x, const double *__restrict__ q,
         szs[t] = stencil_start(pz, g.h, P);
 #pragma unroll
         for (int k = 0; k < NC; ++k)
-          cq[k][t] = k < cs.n ? (T)q[(size_t)p * qstride + cs.idx[k]] : (T)0;
+          if (k < cs.n) cq[k][t] = (T)q[(size_t)p * qstride + cs.idx[k]];
       }
     }
     __syncthreads();
@@ -638,6 +675,26 @@ void build_ktable(Handle &h) {
   PSE_LAUNCH_CHECK();
 }
 
+// Candidate lists of the spreading tiles for wrapped positions xw (after the
+// spreading bins are current).  The capacity N * (ceil((P-1)/S) + 1)^3 is
+// the most tiles a stencil can meet, so the lists never overflow.
+void build_tile_lists(Handle &h, const double *xw) {
+  if (!h.stile) return;
+  const GridGeom g = geom(h);
+  const int nb = h.sbins.nc;
+  const int ntile = nb * nb * nb;
+  const unsigned blocks = (unsigned)((ntile + 3) / 4);
+  hipLaunchKernelGGL((tile_list_kernel<false>), dim3(blocks), dim3(256), 0, h.stream, xw, g,
+                     h.stile, nb, (const int *)h.sbins.start, (const int *)h.sbins.perm,
+                     h.tl_cnt, nullptr, nullptr);
+  PSE_LAUNCH_CHECK();
+  exclusive_scan(h, h.tl_cnt, h.tl_start, h.tl_scan, ntile);
+  hipLaunchKernelGGL((tile_list_kernel<true>), dim3(blocks), dim3(256), 0, h.stream, xw, g,
+                     h.stile, nb, (const int *)h.sbins.start, (const int *)h.sbins.perm, nullptr,
+                     (const int *)h.tl_start, h.tl_list);
+  PSE_LAUNCH_CHECK();
+}
+
 template <typename T>
 void spread(Handle &h, const double *x, const double *q, int qstride,
             const CompSet &cs, T *grids) {
@@ -647,13 +704,13 @@ void spread(Handle &h, const double *x, const double *q, int qstride,
     const int nb = h.sbins.nc;
     const unsigned tiles = (unsigned)nb * nb * nb;
     if (h.stile == 4)
-      hipLaunchKernelGGL((spread_gather_kernel<T, 4>), dim3(tiles), dim3(64), 0, h.stream, x,
-                         q, qstride, cs, g, nb, (const int *)h.sbins.start,
-                         (const int *)h.sbins.perm, grids, h.ngrid);
+      hipLaunchKernelGGL((spread_list_kernel<T, 4>), dim3(tiles), dim3(64), 0, h.stream, x, q,
+                         qstride, cs, g, nb, (const int *)h.tl_start, (const int *)h.tl_list,
+                         grids, h.ngrid);
     else if (h.stile == 8)
-      hipLaunchKernelGGL((spread_gather_kernel<T, 8>), dim3(tiles), dim3(256), 0, h.stream, x,
-                         q, qstride, cs, g, nb, (const int *)h.sbins.start,
-                         (const int *)h.sbins.perm, grids, h.ngrid);
+      hipLaunchKernelGGL((spread_list_kernel<T, 8>), dim3(tiles), dim3(256), 0, h.stream, x, q,
+                         qstride, cs, g, nb, (const int *)h.tl_start, (const int *)h.tl_list,
+                         grids, h.ngrid);
     else
       throw Error{PSE_ERR_INVALID, "unsupported spreading tile"};
     PSE_LAUNCH_CHECK();

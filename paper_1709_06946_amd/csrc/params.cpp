@@ -103,9 +103,14 @@ size_t footprint(const pse_params &p, const pse_derived &d) {
   if (p.precision == PSE_MIXED)
     bytes += 2 * MAX_PACK * ng3 * sizeof(float2) + d.grid * sizeof(float2);
   bytes += (size_t)(3 * (d.grid / 2) * (d.grid / 2) + 1) * 4 * sizeof(double);
+  bytes += pair_capacity(p, d) * (sizeof(int) + 10 * sizeof(double))
+           + (2 * n + n / 1024 + 16) * sizeof(int);
   const size_t ntab = (size_t)(2048.0 * d.rcut / (2 * p.radius)) + 16;
   bytes += ntab * NCOEF * (sizeof(double) + sizeof(float));
-  const size_t tiles3 = ng3 / 64;   // spreading tiles (at most 4^3 points each)
+  const int S = spread_tile(d.grid, d.support);
+  const size_t tiles3 = S ? ng3 / ((size_t)S * S * S) : 0;
+  if (S) bytes += (2 * tiles3 + tiles3 / 1024 + 16) * sizeof(int)
+                  + n * tiles_per_particle(d.support, S) * sizeof(int);
   bytes += (2 * (ncell3 + tiles3) + 4 + (ncell3 + tiles3) / 1024 + 16) * sizeof(int)
            + 6 * n * sizeof(int);
   bytes += (2 * 3 * n + 6 * NC * n) * sizeof(double);

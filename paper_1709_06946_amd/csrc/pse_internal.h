@@ -125,7 +125,14 @@ struct Handle {
   double *v4 = nullptr, *v5 = nullptr;
   double *es_b = nullptr, *es_x = nullptr, *es_r = nullptr, *es_d = nullptr;  // N x 5
 
-  double *ktab = nullptr;    // per-|k|^2 radial factors (4 doubles per entry)
+  double *ktab = nullptr;
+  // real-space pair list (CSR in cell order): start[N+1], neighbour index and
+  // 10 doubles of pair data per entry; counts and scan scratch
+  int *pl_cnt = nullptr, *pl_start = nullptr, *pl_scan = nullptr, *pl_nbr = nullptr;
+  double *pl_rec = nullptr;
+  size_t pl_cap = 0, pl_pairs = 0;
+  // spreading-tile candidate lists (CSR over tiles)
+  int *tl_cnt = nullptr, *tl_start = nullptr, *tl_scan = nullptr, *tl_list = nullptr;    // per-|k|^2 radial factors (4 doubles per entry)
 
   // Krylov storage
   double *lz_V = nullptr;    // (lanczos_maxit + 1) x 11N
@@ -200,13 +207,38 @@ template <typename T>
 void kspace_fused(Handle &h, const cplx<T> *in, const CompSet &cin, cplx<T> *out,
                   const CompSet &cout, const cplx<T> *tw);
 template <typename T> void zero_grids(Handle &h, T *g, int ncomp);
+void build_tile_lists(Handle &h, const double *xw);
 int ktable_len(int grid);                         // entries of the |k|^2 table
 void build_ktable(Handle &h);
 template <typename T> void from_double(Handle &h, const double *src, size_t n, T *dst);
 template <typename T> void to_double(Handle &h, const T *src, size_t n, double *dst);
 
+// Initial capacity of the real-space pair list: twice the pair count of a
+// uniform suspension (neighbours within rcut), plus slack.
+inline size_t pair_capacity(const pse_params &p, const pse_derived &d) {
+  const double dens = (double)p.n / (p.box * p.box * p.box);
+  const double nb = 4.18879020478639098 * d.rcut * d.rcut * d.rcut * dens;
+  return (size_t)(2.0 * nb * (double)p.n) + 1024;
+}
+
+// Most spreading tiles (S^3 points) one P-point stencil can meet.
+inline size_t tiles_per_particle(int P, int S) {
+  const size_t k = (size_t)((P - 1 + S - 1) / S + 1);
+  return k * k * k;
+}
+// Spreading tile side: the stencil may reach one tile beyond its particle's
+// bin, with one grid point of slack for rounding in the bin assignment.
+inline int spread_tile(int grid, int P) {
+  for (int S : {8, 4, 16}) {
+    const int need = (P & 1) ? P + 1 : P + 2;
+    if (grid % S == 0 && grid / S >= 3 && need <= 2 * S) return S;
+  }
+  return 0;
+}
+
 // ---- real.hip
 void build_tables(Handle &h);
+void exclusive_scan(Handle &h, const int *in, int *out, int *tmp, int n);
 void build_cells(Handle &h, const double *xw);   // both bin lists
 template <typename T>
 void real_apply(Handle &h, const double *x, const double *in,

@@ -266,6 +266,18 @@ __global__ void cell_scatter_kernel(const int *__restrict__ cell_of,
   perm[start[cell_of[i]] + slot[i]] = (int)i;
 }
 
+// out[0..n] = exclusive prefix sums of in[0..n) (out[n] = total); tmp holds
+// n/1024 + 8 ints.
+void exclusive_scan(Handle &h, const int *in, int *out, int *tmp, int n) {
+  const int sb = (n + 1023) / 1024;
+  hipLaunchKernelGGL(scan_block_kernel, dim3(sb), dim3(256), 0, h.stream, in, out, tmp, n);
+  PSE_LAUNCH_CHECK();
+  hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(256), 0, h.stream, tmp, sb, out + n);
+  PSE_LAUNCH_CHECK();
+  hipLaunchKernelGGL(scan_add_kernel, dim3(sb), dim3(256), 0, h.stream, out, tmp, n);
+  PSE_LAUNCH_CHECK();
+}
+
 static void build_bins(Handle &h, const double *xw, Bins &b) {
   const int nc = b.nc;
   const int ncells = nc * nc * nc;
@@ -288,26 +300,7 @@ static void build_bins(Handle &h, const double *xw, Bins &b) {
   PSE_LAUNCH_CHECK();
 }
 
-void build_cells(Handle &h, const double *xw) {
-  const double nc3 = (double)h.cells.nc * h.cells.nc * h.cells.nc
-                     + (h.stile ? (double)h.sbins.nc * h.sbins.nc * h.sbins.nc : 0.0);
-  ProfScope ps(h, PK_CELLS, (double)h.n * (24 + 16) * (h.stile ? 2 : 1) + 12.0 * nc3);
-  build_bins(h, xw, h.cells);
-  if (h.stile) build_bins(h, xw, h.sbins);
-}
-
 // ------------------------------------------------------------ pair sum --
-
-struct RealArgs {
-  int64_t n;
-  int nc;
-  double L, rcut2;
-  double inv_dr;
-  int n2a, ntab;
-  int in_mask;    // 1: F, 2: L, 4: S
-  int out_mask;   // 1: U, 2: Omega, 4: E
-  int accumulate;
-};
 
 template <typename T>
 __device__ __forceinline__ void lookup(const T *__restrict__ tab, T r, T inv_dr,
@@ -404,10 +397,8 @@ __device__ __forceinline__ void load_moments(const double *__restrict__ v, int m
   }
 }
 
-// A group of GROUP lanes works on one particle: the lanes split the
-// neighbour candidates of the 27 surrounding cells, then reduce U and D with
-// cross-lane shuffles.  One thread per particle would leave most of the chip
-// idle for N ~ 1e4.
+// A group of GROUP lanes works on one particle.  One thread per particle
+// would leave most of the chip idle for N ~ 1e4.
 constexpr int GROUP = 16;
 
 template <typename T>
@@ -417,33 +408,56 @@ __device__ __forceinline__ T group_sum(T v) {
   return v;
 }
 
-template <typename T>
+// ------------------------------------------------------------ pair list --
+// The positions stay fixed over all the operator applications of a Krylov
+// solve, so the neighbours within rcut and their pair data (the seven
+// interpolated radial coefficients and the unit vector) are found once per
+// position update and stored as a CSR list in cell order: row t holds the
+// neighbours of particle perm[t].  Rows are filled in a fixed order
+// (cells, then candidates, ranked with a ballot inside the group).
+
+struct PairArgs {
+  int64_t n;
+  int nc;
+  double L, rcut2;
+  double inv_dr;
+  int n2a, ntab;
+};
+
+constexpr int PAIR_REC = 10;   // co[7], e[3]
+
+__device__ __forceinline__ bool near_pair(const double *__restrict__ xw, double xi0, double xi1,
+                                          double xi2, int j, const PairArgs &pa, double *d) {
+  d[0] = xi0 - xw[3 * j];
+  d[1] = xi1 - xw[3 * j + 1];
+  d[2] = xi2 - xw[3 * j + 2];
+  // positions are wrapped into [0, L): one image shift per axis suffices
+  const double hL = 0.5 * pa.L;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) d[k] += d[k] > hL ? -pa.L : (d[k] < -hL ? pa.L : 0.0);
+  return d[0] * d[0] + d[1] * d[1] + d[2] * d[2] < pa.rcut2;
+}
+
+// fill = false: count the neighbours of each row into cnt[t];
+// fill = true: write them from start[t] on.
+template <bool FILL>
 __global__ void __launch_bounds__(256)
-real_pair_kernel(const double *__restrict__ xw, const double *__restrict__ in,
-                 double *__restrict__ out, const int *__restrict__ perm,
+pair_list_kernel(const double *__restrict__ xw, const int *__restrict__ perm,
                  const int *__restrict__ cell_start, const int *__restrict__ cell_of,
-                 const T *__restrict__ tab, RealArgs ra) {
+                 PairArgs pa, int *__restrict__ cnt, const int *__restrict__ start,
+                 const double *__restrict__ tab, int *__restrict__ nbr,
+                 double *__restrict__ rec) {
   const int64_t t = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / GROUP;
   const int lane = threadIdx.x % GROUP;
-  if (t >= ra.n) return;
+  if (t >= pa.n) return;
+  const int gshift = (threadIdx.x % 64) / GROUP * GROUP;
   const int i = perm[t];
   const double xi0 = xw[3 * i], xi1 = xw[3 * i + 1], xi2 = xw[3 * i + 2];
-  const bool useF = ra.in_mask & 1, useC = (ra.in_mask & 6) != 0;
-  T U[3] = {0, 0, 0};
-  T D[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-  T F[3], C[3][3];
-  if (lane == 0) {
-    // self term (r = 0: only the isotropic coefficients survive)
-    T co[NCOEF];
-    for (int j = 0; j < NCOEF; ++j) co[j] = tab[j];
-    const T e0[3] = {0, 0, 0};
-    load_moments<T>(in + (size_t)i * NC, ra.in_mask, F, C);
-    pair_action<T>(co, e0, F, C, useF, useC, U, D);
-  }
-  const int nc = ra.nc;
+  const int nc = pa.nc;
   const int ci = cell_of[i];
   const int cx = ci % nc, cy = (ci / nc) % nc, cz = ci / (nc * nc);
-  const T inv_dr = (T)ra.inv_dr;
+  int pos = FILL ? start[t] : 0;
+  int count = 0;
   for (int dz = -1; dz <= 1; ++dz) {
     const int zz = (cz + dz + nc) % nc;
     for (int dy = -1; dy <= 1; ++dy) {
@@ -452,29 +466,86 @@ real_pair_kernel(const double *__restrict__ xw, const double *__restrict__ in,
         const int xx = (cx + dx + nc) % nc;
         const int cell = (zz * nc + yy) * nc + xx;
         const int s0 = cell_start[cell], s1 = cell_start[cell + 1];
-        for (int s = s0 + lane; s < s1; s += GROUP) {
-          const int j = perm[s];
-          if (j == i) continue;
-          double d0 = xi0 - xw[3 * j], d1 = xi1 - xw[3 * j + 1], d2 = xi2 - xw[3 * j + 2];
-          d0 -= ra.L * rint(d0 / ra.L);
-          d1 -= ra.L * rint(d1 / ra.L);
-          d2 -= ra.L * rint(d2 / ra.L);
-          const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
-          if (r2 >= ra.rcut2) continue;
-          const double r = sqrt(r2);
-          T e[3];
-          if (r > 0) {
-            e[0] = (T)(d0 / r); e[1] = (T)(d1 / r); e[2] = (T)(d2 / r);
-          } else {
-            e[0] = e[1] = e[2] = (T)0;
+        for (int base = s0; base < s1; base += GROUP) {
+          const int s = base + lane;
+          double d[3];
+          int j = -1;
+          bool ok = false;
+          if (s < s1) {
+            j = perm[s];
+            ok = j != i && near_pair(xw, xi0, xi1, xi2, j, pa, d);
           }
-          T co[NCOEF];
-          lookup<T>(tab, (T)r, inv_dr, ra.n2a, ra.ntab, co);
-          load_moments<T>(in + (size_t)j * NC, ra.in_mask, F, C);
-          pair_action<T>(co, e, F, C, useF, useC, U, D);
+          if (!FILL) {
+            count += ok ? 1 : 0;
+          } else {
+            const unsigned long long m = __ballot(ok);
+            const unsigned g = (unsigned)(m >> gshift) & ((1u << GROUP) - 1u);
+            if (ok) {
+              const int slot = pos + __popc(g & ((1u << lane) - 1u));
+              nbr[slot] = j;
+              const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+              double co[NCOEF];
+              lookup<double>(tab, r, pa.inv_dr, pa.n2a, pa.ntab, co);
+              double *o = rec + (size_t)slot * PAIR_REC;
+#pragma unroll
+              for (int k = 0; k < NCOEF; ++k) o[k] = co[k];
+              const double inv = r > 0 ? 1.0 / r : 0.0;
+#pragma unroll
+              for (int k = 0; k < 3; ++k) o[NCOEF + k] = d[k] * inv;
+            }
+            pos += __popc(g);
+          }
         }
       }
     }
+  }
+  if (!FILL) {
+    count = group_sum(count);
+    if (lane == 0) cnt[t] = count;
+  }
+}
+
+struct RealArgs {
+  int64_t n;
+  int in_mask;    // 1: F, 2: L, 4: S
+  int out_mask;   // 1: U, 2: Omega, 4: E
+  int accumulate;
+};
+
+// M_r applied from the pair list: the self block (r = 0: only the isotropic
+// coefficients, table row 0) plus one pair block per stored neighbour.
+template <typename T>
+__global__ void __launch_bounds__(256)
+real_pair_kernel(const double *__restrict__ in, double *__restrict__ out,
+                 const int *__restrict__ perm, const int *__restrict__ start,
+                 const int *__restrict__ nbr, const double *__restrict__ rec,
+                 const T *__restrict__ tab, RealArgs ra) {
+  const int64_t t = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / GROUP;
+  const int lane = threadIdx.x % GROUP;
+  if (t >= ra.n) return;
+  const int i = perm[t];
+  const bool useF = ra.in_mask & 1, useC = (ra.in_mask & 6) != 0;
+  T U[3] = {0, 0, 0};
+  T D[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  T F[3], C[3][3];
+  if (lane == 0) {
+    T co[NCOEF];
+    for (int j = 0; j < NCOEF; ++j) co[j] = tab[j];
+    const T e0[3] = {0, 0, 0};
+    load_moments<T>(in + (size_t)i * NC, ra.in_mask, F, C);
+    pair_action<T>(co, e0, F, C, useF, useC, U, D);
+  }
+  const int s1 = start[t + 1];
+  for (int s = start[t] + lane; s < s1; s += GROUP) {
+    const int j = nbr[s];
+    const double *r = rec + (size_t)s * PAIR_REC;
+    T co[NCOEF], e[3];
+#pragma unroll
+    for (int k = 0; k < NCOEF; ++k) co[k] = (T)r[k];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) e[k] = (T)r[NCOEF + k];
+    load_moments<T>(in + (size_t)j * NC, ra.in_mask, F, C);
+    pair_action<T>(co, e, F, C, useF, useC, U, D);
   }
 #pragma unroll
   for (int k = 0; k < 3; ++k) U[k] = group_sum(U[k]);
@@ -503,6 +574,59 @@ real_pair_kernel(const double *__restrict__ xw, const double *__restrict__ in,
   }
 }
 
+// Builds the pair list for the current cell list; grows its storage when
+// the count exceeds the capacity (one host read of the total per update).
+static void build_pair_list(Handle &h, const double *xw) {
+  PairArgs pa;
+  pa.n = h.n;
+  pa.nc = h.cells.nc;
+  pa.L = h.p.box;
+  pa.rcut2 = h.d.rcut * h.d.rcut;
+  pa.inv_dr = 1.0 / h.dr;
+  pa.n2a = h.n2a;
+  pa.ntab = h.ntab;
+  const unsigned nb = nblocks((size_t)h.n * GROUP, 256);
+  hipLaunchKernelGGL((pair_list_kernel<false>), dim3(nb), dim3(256), 0, h.stream, xw,
+                     h.cells.perm, h.cells.start, h.cells.of, pa, h.pl_cnt, nullptr, nullptr,
+                     nullptr, nullptr);
+  PSE_LAUNCH_CHECK();
+  const int n = (int)h.n;
+  exclusive_scan(h, h.pl_cnt, h.pl_start, h.pl_scan, n);
+  int total = 0;
+  PSE_HIP(hipMemcpyAsync(&total, h.pl_start + n, sizeof(int), hipMemcpyDeviceToHost,
+                         h.stream));
+  PSE_HIP(hipStreamSynchronize(h.stream));
+  if ((size_t)total > h.pl_cap) {
+    const size_t cap = (size_t)total + total / 4 + 1024;
+    PSE_HIP(hipFree(h.pl_nbr));
+    PSE_HIP(hipFree(h.pl_rec));
+    h.pl_nbr = nullptr;
+    h.pl_rec = nullptr;
+    h.pl_cap = 0;
+    PSE_HIP(hipMalloc((void **)&h.pl_nbr, cap * sizeof(int)));
+    PSE_HIP(hipMalloc((void **)&h.pl_rec, cap * PAIR_REC * sizeof(double)));
+    h.pl_cap = cap;
+  }
+  h.pl_pairs = (size_t)total;
+  hipLaunchKernelGGL((pair_list_kernel<true>), dim3(nb), dim3(256), 0, h.stream, xw,
+                     h.cells.perm, h.cells.start, h.cells.of, pa, nullptr, h.pl_start,
+                     h.g64.table, h.pl_nbr, h.pl_rec);
+  PSE_LAUNCH_CHECK();
+}
+
+// Cell list, spreading bins and pair list for wrapped positions xw.
+void build_cells(Handle &h, const double *xw) {
+  const double nc3 = (double)h.cells.nc * h.cells.nc * h.cells.nc
+                     + (h.stile ? (double)h.sbins.nc * h.sbins.nc * h.sbins.nc : 0.0);
+  ProfScope ps(h, PK_CELLS, (double)h.n * (24 + 16) * (h.stile ? 2 : 1) + 12.0 * nc3);
+  build_bins(h, xw, h.cells);
+  if (h.stile) {
+    build_bins(h, xw, h.sbins);
+    build_tile_lists(h, xw);
+  }
+  build_pair_list(h, xw);
+}
+
 static int mask_of(const CompSet &cs, bool input) {
   int m = 0;
   for (int k = 0; k < cs.n; ++k) {
@@ -516,23 +640,18 @@ static int mask_of(const CompSet &cs, bool input) {
 template <typename T>
 void real_apply(Handle &h, const double *xw, const double *in, const CompSet &cin,
                 double *out, const CompSet &cout, bool accumulate) {
+  (void)xw;
   RealArgs ra;
   ra.n = h.n;
-  ra.nc = h.cells.nc;
-  ra.L = h.p.box;
-  ra.rcut2 = h.d.rcut * h.d.rcut;
-  ra.inv_dr = 1.0 / h.dr;
-  ra.n2a = h.n2a;
-  ra.ntab = h.ntab;
   ra.in_mask = mask_of(cin, true);
   ra.out_mask = mask_of(cout, false);
   ra.accumulate = accumulate ? 1 : 0;
   const T *tab;
   if constexpr (sizeof(T) == 8) tab = h.g64.table; else tab = h.g32.table;
-  ProfScope ps(h, PK_REAL, (double)h.n * (2 * NC * 8 + 3 * 8 + 2 * 4));
+  ProfScope ps(h, PK_REAL, (double)h.pl_pairs * (PAIR_REC * 8 + 4 + NC * 8) +
+                               (double)h.n * (NC * 8 * 2 + 8));
   hipLaunchKernelGGL(real_pair_kernel<T>, dim3(nblocks((size_t)h.n * GROUP, 256)), dim3(256), 0,
-                     h.stream, xw, in, out, h.cells.perm, h.cells.start, h.cells.of, tab,
-                     ra);
+                     h.stream, in, out, h.cells.perm, h.pl_start, h.pl_nbr, h.pl_rec, tab, ra);
   PSE_LAUNCH_CHECK();
 }
 

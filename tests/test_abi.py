@@ -137,10 +137,12 @@ def test_null_arguments_rejected(pse):
 
 
 def test_footprint_grows_with_grid_and_precision(pse):
-    f = [pse.footprint_bytes(pse.make_params(10000, 52.0, grid=g, tol=1e-3))
+    # same cutoff for both grids, so that the pair list is the same size
+    f = [pse.footprint_bytes(pse.make_params(10000, 52.0, grid=g, tol=1e-3, rcut=6.0))
          for g in (64, 128)]
     assert f[1] - f[0] >= 0.99 * 2 * 6 * (128**3 - 64**3) * 16
-    fm = pse.footprint_bytes(pse.make_params(10000, 52.0, grid=128, tol=1e-3, precision=1))
+    fm = pse.footprint_bytes(pse.make_params(10000, 52.0, grid=128, tol=1e-3, rcut=6.0,
+                                             precision=1))
     assert fm > f[1]
     # FP64 grids dominate: 2 sets x 6 packed complex grids x 16 B
     assert f[1] > 2 * 6 * 128**3 * 16
