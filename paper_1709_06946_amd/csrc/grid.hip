@@ -214,7 +214,12 @@ spread_list_kernel(const double *__restrict__ x, const double *__restrict__ q,
 
 // --------------------------------------------------------- interpolation --
 
-template <typename T>
+// One wavefront per particle; lane s covers stencil points s, s + 64, ...
+// With MAXIT = ceil(P^3 / 64) fixed at compile time, a lane first forms all
+// its grid indices and weights and then issues every grid load at once, so
+// that the loads of all stencil points and components are in flight
+// together (MAXIT = 0: generic loop for large supports).
+template <typename T, int MAXIT>
 __global__ void __launch_bounds__(256)
 interp_kernel(const double *__restrict__ x, const T *__restrict__ grids,
               size_t ngrid, CompSet cs, GridGeom g, const int *__restrict__ order,
@@ -233,17 +238,46 @@ interp_kernel(const double *__restrict__ x, const T *__restrict__ grids,
 #pragma unroll
   for (int k = 0; k < NC; ++k) acc[k] = (T)0;
   const double kn3 = g.knorm * g.knorm * g.knorm;
-  for (int s = lane; s < P3; s += 64) {
-    const int a = s % P, b = (s / P) % P, c = s / (P * P);
-    const double dx = (ix0 + a) * g.h - px;
-    const double dy = (iy0 + b) * g.h - py;
-    const double dz = (iz0 + c) * g.h - pz;
-    const T w = (T)(kn3 * exp(-g.kcoef * (dx * dx + dy * dy + dz * dz)));
-    const size_t gi = ((size_t)wrapi(iz0 + c, g.ng) * g.ng + wrapi(iy0 + b, g.ng)) * g.ng
-                      + wrapi(ix0 + a, g.ng);
+  if constexpr (MAXIT > 0) {
+    size_t gi[MAXIT];
+    T w[MAXIT];
 #pragma unroll
-    for (int k = 0; k < NC; ++k)
-      if (k < cs.n) acc[k] += w * grids[(size_t)k * ngrid + gi];
+    for (int it = 0; it < MAXIT; ++it) {
+      const int s = lane + 64 * it;
+      const int a = s % P, b = (s / P) % P, c = s / (P * P);
+      const double dx = (ix0 + a) * g.h - px;
+      const double dy = (iy0 + b) * g.h - py;
+      const double dz = (iz0 + c) * g.h - pz;
+      const bool in = s < P3;
+      w[it] = in ? (T)(kn3 * exp(-g.kcoef * (dx * dx + dy * dy + dz * dz))) : (T)0;
+      gi[it] = in ? ((size_t)wrapi(iz0 + c, g.ng) * g.ng + wrapi(iy0 + b, g.ng)) * g.ng
+                        + wrapi(ix0 + a, g.ng)
+                  : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+      if (k < cs.n) {
+        const T *gk = grids + (size_t)k * ngrid;
+        T v[MAXIT];
+#pragma unroll
+        for (int it = 0; it < MAXIT; ++it) v[it] = gk[gi[it]];
+#pragma unroll
+        for (int it = 0; it < MAXIT; ++it) acc[k] += w[it] * v[it];
+      }
+    }
+  } else {
+    for (int s = lane; s < P3; s += 64) {
+      const int a = s % P, b = (s / P) % P, c = s / (P * P);
+      const double dx = (ix0 + a) * g.h - px;
+      const double dy = (iy0 + b) * g.h - py;
+      const double dz = (iz0 + c) * g.h - pz;
+      const T w = (T)(kn3 * exp(-g.kcoef * (dx * dx + dy * dy + dz * dz)));
+      const size_t gi = ((size_t)wrapi(iz0 + c, g.ng) * g.ng + wrapi(iy0 + b, g.ng)) * g.ng
+                        + wrapi(ix0 + a, g.ng);
+#pragma unroll
+      for (int k = 0; k < NC; ++k)
+        if (k < cs.n) acc[k] += w * grids[(size_t)k * ngrid + gi];
+    }
   }
 #pragma unroll
   for (int k = 0; k < NC; ++k) {
@@ -427,13 +461,23 @@ kspace_fused_kernel(const cplx<T> *__restrict__ in, CompSet cin, cplx<T> *__rest
   for (int e = 0; e < E; ++e)
 #pragma unroll
     for (int m = 0; m < 3; ++m) rho[e][m] = C{(T)0, (T)0};
-  C v[E];
+  // the next component's z-line is loaded while the current one is
+  // transformed (the barriers of the exchanges wait on LDS traffic only)
+  C v[E], vn[E];
+#pragma unroll
+  for (int b = 0; b < E / R0; ++b)
+#pragma unroll
+    for (int r = 0; r < R0; ++r) vn[b * R0 + r] = in[base + reg_pos<N, E, R0>(t, b, r) * plane];
   for (int p = 0; p < cin.n; ++p) {
-    const C *src = in + (size_t)p * hsz + base;
 #pragma unroll
-    for (int b = 0; b < E / R0; ++b)
+    for (int e = 0; e < E; ++e) v[e] = vn[e];
+    if (p + 1 < cin.n) {
+      const C *src = in + (size_t)(p + 1) * hsz + base;
 #pragma unroll
-      for (int r = 0; r < R0; ++r) v[b * R0 + r] = src[reg_pos<N, E, R0>(t, b, r) * plane];
+      for (int b = 0; b < E / R0; ++b)
+#pragma unroll
+        for (int r = 0; r < R0; ++r) vn[b * R0 + r] = src[reg_pos<N, E, R0>(t, b, r) * plane];
+    }
     reg_fft_forward<T, N, E>(v, t, lds, TL, line, tw);
     const int c = cin.idx[p];
 #pragma unroll
@@ -729,9 +773,25 @@ void interpolate(Handle &h, const double *x, const T *grids, const CompSet &cs,
                  double *out, int ostride, bool accumulate, double scale) {
   const GridGeom g = geom(h);
   ProfScope ps(h, PK_INTERP, (double)cs.n * h.ngrid * sizeof(T) + (double)h.n * (3 + cs.n) * 8);
-  hipLaunchKernelGGL(interp_kernel<T>, dim3(nblocks(h.n, 4)), dim3(256), 0,
-                     h.stream, x, grids, h.ngrid, cs, g, (const int *)h.cells.perm,
-                     h.n, out, ostride, accumulate ? 1 : 0, scale);
+  const int P3 = g.P * g.P * g.P;
+  const dim3 grid(nblocks(h.n, 4)), block(256);
+  const int acc = accumulate ? 1 : 0;
+  const int *order = (const int *)h.cells.perm;
+  if (P3 <= 128)
+    hipLaunchKernelGGL((interp_kernel<T, 2>), grid, block, 0, h.stream, x, grids, h.ngrid, cs, g,
+                       order, h.n, out, ostride, acc, scale);
+  else if (P3 <= 256)
+    hipLaunchKernelGGL((interp_kernel<T, 4>), grid, block, 0, h.stream, x, grids, h.ngrid, cs, g,
+                       order, h.n, out, ostride, acc, scale);
+  else if (P3 <= 384)
+    hipLaunchKernelGGL((interp_kernel<T, 6>), grid, block, 0, h.stream, x, grids, h.ngrid, cs, g,
+                       order, h.n, out, ostride, acc, scale);
+  else if (P3 <= 512)
+    hipLaunchKernelGGL((interp_kernel<T, 8>), grid, block, 0, h.stream, x, grids, h.ngrid, cs, g,
+                       order, h.n, out, ostride, acc, scale);
+  else
+    hipLaunchKernelGGL((interp_kernel<T, 0>), grid, block, 0, h.stream, x, grids, h.ngrid, cs, g,
+                       order, h.n, out, ostride, acc, scale);
   PSE_LAUNCH_CHECK();
 }
 
