@@ -26,7 +26,9 @@ METRIC = ('particle-steps/s (FTS Brownian, rel.err 1e-3) vs FP64; '
 HBM_PEAK_GBS = 8000.0
 
 
-def run_form(w, precision, steps, warmup, seed):
+def run_form(w, precision, steps, warmup, seed, prof_steps=2):
+    """Times `steps` steps with the stage profiler off (the throughput), then
+    runs `prof_steps` more with it on (stage times, launch durations)."""
     import torch
 
     from paper_1709_06946_amd import pse
@@ -38,22 +40,27 @@ def run_form(w, precision, steps, warmup, seed):
     for k in range(warmup):
         h.constrained_step(x, FL, w['dt'], seed=seed, step=k)
     stats = []
-    h.profile(1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(steps):
         rc, st = h.constrained_step(x, FL, w['dt'], seed=seed, step=warmup + k)
         stats.append(st)
-        print(f'# step {k} rc={rc} lanczos={st["lanczos_iters"]} gmres={st["gmres_iters"]} '
-              f'res={st["fp64_residual"]:.2e}', file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    for k, st in enumerate(stats):
+        print(f'# step {k} lanczos={st["lanczos_iters"]} gmres={st["gmres_iters"]} '
+              f'res={st["fp64_residual"]:.2e}', file=sys.stderr, flush=True)
+    h.profile(1)
+    for k in range(prof_steps):
+        h.constrained_step(x, FL, w['dt'], seed=seed, step=warmup + steps + k)
+    torch.cuda.synchronize()
     h.profile(0)
     prof = h.profile_read()
     d = h.derived
     h.close()
     dt = t1 - t0
     return dict(value=N * steps / dt, ms_per_step=1e3 * dt / steps, prof=prof, stats=stats,
+                prof_steps=prof_steps,
                 derived=dict(grid=d.grid, support=d.support, xi=d.xi, rcut=d.rcut,
                              eta_s=d.eta_s), finite=bool(torch.isfinite(x).all()))
 
@@ -209,7 +216,8 @@ def main():
                     derived={k: v for k, v in fp64['derived'].items()}),
         roofline=roof,
         krylov=dict(lanczos_iters=lz, gmres_iters=gm),
-        stages_ms={k: round(v['total_ms'] / args.steps, 3) for k, v in fp64['prof'].items()},
+        stages_ms={k: round(v['total_ms'] / fp64['prof_steps'], 3)
+                   for k, v in fp64['prof'].items()},
         mixed=mixed,
     )
     if not args.no_served:

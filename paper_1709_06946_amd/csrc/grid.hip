@@ -88,8 +88,8 @@ __device__ __forceinline__ bool stencil_meets(int st, int t0, int P, int S, int 
 
 // FILL = false: count each tile's candidates; true: write them from
 // start[tile] on, in bin order and ranked with a ballot.  One wavefront per
-// tile scans the particles of the 27 bins around it (bins are tiles; a
-// stencil reaches at most one tile beyond its particle's).
+// tile enumerates the particles of the 27 bins around it 64 at a time (bins
+// are tiles; a stencil reaches at most one tile beyond its particle's).
 template <bool FILL>
 __global__ void __launch_bounds__(256)
 tile_list_kernel(const double *__restrict__ x, GridGeom g, int S, int nb,
@@ -100,31 +100,27 @@ tile_list_kernel(const double *__restrict__ x, GridGeom g, int S, int nb,
   if (tile >= nb * nb * nb) return;
   const int tx = tile % nb, ty = (tile / nb) % nb, tz = tile / (nb * nb);
   const int P = g.P, ng = g.ng;
+  int first, pre, total;
+  nbr27_setup(lane, tx, ty, tz, nb, bstart, first, pre, total);
   int pos = FILL ? start[tile] : 0;
   int count = 0;
-  for (int o = 0; o < 27; ++o) {
-    const int bx = (tx + o % 3 - 1 + nb) % nb;
-    const int by = (ty + (o / 3) % 3 - 1 + nb) % nb;
-    const int bz = (tz + o / 9 - 1 + nb) % nb;
-    const int b = (bz * nb + by) * nb + bx;
-    const int b0 = bstart[b], b1 = bstart[b + 1];
-    for (int base = b0; base < b1; base += 64) {
-      const int s = base + lane;
-      bool ok = false;
-      int p = 0;
-      if (s < b1) {
-        p = bperm[s];
-        ok = stencil_meets(stencil_start(x[3 * p], g.h, P), tx * S, P, S, ng) &&
-             stencil_meets(stencil_start(x[3 * p + 1], g.h, P), ty * S, P, S, ng) &&
-             stencil_meets(stencil_start(x[3 * p + 2], g.h, P), tz * S, P, S, ng);
-      }
-      if (!FILL) {
-        count += ok ? 1 : 0;
-      } else {
-        const unsigned long long m = __ballot(ok);
-        if (ok) list[pos + __popcll(m & ((1ull << lane) - 1ull))] = p;
-        pos += __popcll(m);
-      }
+  for (int base = 0; base < total; base += 64) {
+    const int idx = base + lane;
+    const int s = nbr27_slot(idx, first, pre);
+    bool ok = false;
+    int p = 0;
+    if (idx < total) {
+      p = bperm[s];
+      ok = stencil_meets(stencil_start(x[3 * p], g.h, P), tx * S, P, S, ng) &&
+           stencil_meets(stencil_start(x[3 * p + 1], g.h, P), ty * S, P, S, ng) &&
+           stencil_meets(stencil_start(x[3 * p + 2], g.h, P), tz * S, P, S, ng);
+    }
+    if (!FILL) {
+      count += ok ? 1 : 0;
+    } else {
+      const unsigned long long m = __ballot(ok);
+      if (ok) list[pos + __popcll(m & ((1ull << lane) - 1ull))] = p;
+      pos += __popcll(m);
     }
   }
   if (!FILL) {

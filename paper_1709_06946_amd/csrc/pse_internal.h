@@ -236,6 +236,48 @@ inline int spread_tile(int grid, int P) {
   return 0;
 }
 
+// ---- neighbour-bin enumeration (device helpers shared by the list builders)
+
+// Lanes 0..26 of a wavefront take the 27 bins around (cx, cy, cz) of a
+// periodic nc^3 lattice (bin offsets in x fastest) and load their first slot
+// and length; an inclusive scan over the wavefront gives each bin's offset
+// `pre` in the concatenated candidate sequence of length `total`.
+__device__ __forceinline__ void nbr27_setup(int lane, int cx, int cy, int cz, int nc,
+                                            const int *__restrict__ start, int &first,
+                                            int &pre, int &total) {
+  int len = 0;
+  first = 0;
+  if (lane < 27) {
+    const int bx = (cx + lane % 3 - 1 + nc) % nc;
+    const int by = (cy + (lane / 3) % 3 - 1 + nc) % nc;
+    const int bz = (cz + lane / 9 - 1 + nc) % nc;
+    const int b = (bz * nc + by) * nc + bx;
+    first = start[b];
+    len = start[b + 1] - first;
+  }
+  int incl = len;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int v = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += v;
+  }
+  pre = incl - len;
+  total = __shfl(incl, 63, 64);
+}
+
+// Slot (in the bins' permutation) of candidate idx < total; every lane of
+// the wavefront must call it (binary search over the lanes' offsets).
+__device__ __forceinline__ int nbr27_slot(int idx, int first, int pre) {
+  int lo = 0;
+#pragma unroll
+  for (int step = 16; step > 0; step >>= 1) {
+    const int c = lo + step;
+    const int pc = __shfl(pre, c < 27 ? c : 26, 64);
+    if (c < 27 && pc <= idx) lo = c;
+  }
+  return __shfl(first, lo, 64) + idx - __shfl(pre, lo, 64);
+}
+
 // ---- real.hip
 void build_tables(Handle &h);
 void exclusive_scan(Handle &h, const int *in, int *out, int *tmp, int n);

@@ -438,8 +438,9 @@ __device__ __forceinline__ bool near_pair(const double *__restrict__ xw, double 
   return d[0] * d[0] + d[1] * d[1] + d[2] * d[2] < pa.rcut2;
 }
 
-// fill = false: count the neighbours of each row into cnt[t];
-// fill = true: write them from start[t] on.
+// FILL = false: count the neighbours of each row into cnt[t]; FILL = true:
+// write them from start[t] on.  One wavefront per row enumerates the
+// candidates of the 27 cells around the particle 64 at a time.
 template <bool FILL>
 __global__ void __launch_bounds__(256)
 pair_list_kernel(const double *__restrict__ xw, const int *__restrict__ perm,
@@ -447,60 +448,50 @@ pair_list_kernel(const double *__restrict__ xw, const int *__restrict__ perm,
                  PairArgs pa, int *__restrict__ cnt, const int *__restrict__ start,
                  const double *__restrict__ tab, int *__restrict__ nbr,
                  double *__restrict__ rec) {
-  const int64_t t = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / GROUP;
-  const int lane = threadIdx.x % GROUP;
+  const int64_t t = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
+  const int lane = threadIdx.x % 64;
   if (t >= pa.n) return;
-  const int gshift = (threadIdx.x % 64) / GROUP * GROUP;
   const int i = perm[t];
   const double xi0 = xw[3 * i], xi1 = xw[3 * i + 1], xi2 = xw[3 * i + 2];
   const int nc = pa.nc;
   const int ci = cell_of[i];
-  const int cx = ci % nc, cy = (ci / nc) % nc, cz = ci / (nc * nc);
+  int first, pre, total;
+  nbr27_setup(lane, ci % nc, (ci / nc) % nc, ci / (nc * nc), nc, cell_start, first, pre, total);
   int pos = FILL ? start[t] : 0;
   int count = 0;
-  for (int dz = -1; dz <= 1; ++dz) {
-    const int zz = (cz + dz + nc) % nc;
-    for (int dy = -1; dy <= 1; ++dy) {
-      const int yy = (cy + dy + nc) % nc;
-      for (int dx = -1; dx <= 1; ++dx) {
-        const int xx = (cx + dx + nc) % nc;
-        const int cell = (zz * nc + yy) * nc + xx;
-        const int s0 = cell_start[cell], s1 = cell_start[cell + 1];
-        for (int base = s0; base < s1; base += GROUP) {
-          const int s = base + lane;
-          double d[3];
-          int j = -1;
-          bool ok = false;
-          if (s < s1) {
-            j = perm[s];
-            ok = j != i && near_pair(xw, xi0, xi1, xi2, j, pa, d);
-          }
-          if (!FILL) {
-            count += ok ? 1 : 0;
-          } else {
-            const unsigned long long m = __ballot(ok);
-            const unsigned g = (unsigned)(m >> gshift) & ((1u << GROUP) - 1u);
-            if (ok) {
-              const int slot = pos + __popc(g & ((1u << lane) - 1u));
-              nbr[slot] = j;
-              const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-              double co[NCOEF];
-              lookup<double>(tab, r, pa.inv_dr, pa.n2a, pa.ntab, co);
-              double *o = rec + (size_t)slot * PAIR_REC;
+  for (int base = 0; base < total; base += 64) {
+    const int idx = base + lane;
+    const int s = nbr27_slot(idx, first, pre);
+    double d[3];
+    int j = -1;
+    bool ok = false;
+    if (idx < total) {
+      j = perm[s];
+      ok = j != i && near_pair(xw, xi0, xi1, xi2, j, pa, d);
+    }
+    if (!FILL) {
+      count += ok ? 1 : 0;
+    } else {
+      const unsigned long long m = __ballot(ok);
+      if (ok) {
+        const int slot = pos + __popcll(m & ((1ull << lane) - 1ull));
+        nbr[slot] = j;
+        const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        double co[NCOEF];
+        lookup<double>(tab, r, pa.inv_dr, pa.n2a, pa.ntab, co);
+        double *o = rec + (size_t)slot * PAIR_REC;
 #pragma unroll
-              for (int k = 0; k < NCOEF; ++k) o[k] = co[k];
-              const double inv = r > 0 ? 1.0 / r : 0.0;
+        for (int k = 0; k < NCOEF; ++k) o[k] = co[k];
+        const double inv = r > 0 ? 1.0 / r : 0.0;
 #pragma unroll
-              for (int k = 0; k < 3; ++k) o[NCOEF + k] = d[k] * inv;
-            }
-            pos += __popc(g);
-          }
-        }
+        for (int k = 0; k < 3; ++k) o[NCOEF + k] = d[k] * inv;
       }
+      pos += __popcll(m);
     }
   }
   if (!FILL) {
-    count = group_sum(count);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) count += __shfl_xor(count, off, 64);
     if (lane == 0) cnt[t] = count;
   }
 }
@@ -585,7 +576,7 @@ static void build_pair_list(Handle &h, const double *xw) {
   pa.inv_dr = 1.0 / h.dr;
   pa.n2a = h.n2a;
   pa.ntab = h.ntab;
-  const unsigned nb = nblocks((size_t)h.n * GROUP, 256);
+  const unsigned nb = nblocks((size_t)h.n * 64, 256);
   hipLaunchKernelGGL((pair_list_kernel<false>), dim3(nb), dim3(256), 0, h.stream, xw,
                      h.cells.perm, h.cells.start, h.cells.of, pa, h.pl_cnt, nullptr, nullptr,
                      nullptr, nullptr);
