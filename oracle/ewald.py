@@ -191,6 +191,32 @@ def real_apply(x, q, L, xi, a=1.0, eta=1.0, rcut=None):
     return out
 
 
+def real_apply_rows(x, q, L, xi, rows, a=1.0, eta=1.0, rcut=None):
+    """Rows `rows` of M_r q (Eq. pairsums for chosen output particles):
+    out[alpha] = sum over partners beta and lattice vectors n with
+    |x_alpha - x_beta + n L| < rcut of M^{alpha beta}(x_alpha - x_beta + n L) q_beta,
+    the self block (beta = alpha, n = 0) included.  Each block is evaluated
+    at its own separation (no transpose relation is used), so the cost is
+    O(N) per row and full-size systems can be sampled."""
+    x = np.asarray(x, np.float64)
+    q = np.asarray(q, np.float64)
+    if rcut is None:
+        rcut = real_cutoff(xi, a)
+    nimg = int(np.ceil(rcut / L)) + 1
+    g = np.arange(-nimg, nimg + 1)
+    shifts = L * np.stack(np.meshgrid(g, g, g, indexing='ij'), -1).reshape(-1, 3)
+    out = np.zeros((len(rows), q.shape[1]))
+    for k, al in enumerate(rows):
+        d = x[al] - x
+        d -= L * np.rint(d / L)
+        rr = (d[:, None, :] + shifts[None, :, :]).reshape(-1, 3)
+        beta = np.repeat(np.arange(x.shape[0]), shifts.shape[0])
+        m = np.sqrt((rr**2).sum(1)) < rcut
+        B = pair_blocks(rr[m], xi, a, eta, 'real')
+        out[k] = np.einsum('pij,pj->i', B, q[beta[m]])
+    return out
+
+
 def grand_dense(x, L, xi, a=1.0, eta=1.0):
     """Full grand mobility M = M_w + M_r (independent of xi)."""
     return wave_dense(x, L, xi, a, eta) + real_dense(x, L, xi, a, eta)

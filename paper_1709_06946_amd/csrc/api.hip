@@ -269,6 +269,12 @@ static void create(const pse_params &p, Handle &h) {
     PSE_HIP(hipStreamCreateWithFlags(&h.stream, hipStreamNonBlocking));
     h.own_stream = true;
   }
+  {
+    int dev = 0, lds = 0;
+    PSE_HIP(hipGetDevice(&dev));
+    PSE_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    h.max_lds = lds;
+  }
   const size_t n = (size_t)h.n;
   const int ng = h.d.grid;
   alloc((void **)&h.g64.gin, MAX_PACK * h.ngrid * sizeof(double2));

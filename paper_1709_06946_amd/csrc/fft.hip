@@ -7,6 +7,8 @@
 // spectra H[c][kz][ky][kx < N/2] (a row of N reals holds N/2 complex); the
 // Nyquist column kx = N/2 is not stored, and every Nyquist mode is zero in
 // the spectra the k-space kernels produce.
+#include <mutex>
+
 #include "fftreg.h"
 
 namespace pse {
@@ -140,6 +142,125 @@ fft_xc_kernel(cplx<T> *__restrict__ data, const cplx<T> *__restrict__ tw, int di
   }
 }
 
+// ------------------------------------------------- x and y in one kernel --
+
+// Forward (INV = false): one workgroup transforms one z-plane of one real
+// component: x transforms of the N/2 row pairs (registers + LDS exchanges in
+// a padded [pair][N+1] layout), separation of the two half spectra into a
+// [y][kx < N/2] layout in the same LDS buffer, then y transforms of the N/2
+// columns, written to the plane's half spectrum.  Inverse (INV = true): the
+// same steps in reverse order.  The plane travels through HBM once each way
+// instead of twice.  Thread (line, t) is (tid / TPL, tid % TPL) in the x
+// steps and (tid % H, tid / H) in the y steps.
+// Elements per thread in the plane kernel: 8 for power-of-two planes (up to
+// 1024 threads, 16 wavefronts per workgroup), 12 for 3 * 2^j.
+constexpr int plane_e(int n) { return n % 3 == 0 ? 12 : 8; }
+
+template <typename T, int N, bool INV>
+__global__ void __launch_bounds__(1024)
+fft_xy_plane_kernel(T *__restrict__ data, const cplx<T> *__restrict__ tw) {
+  using C = cplx<T>;
+  constexpr int E = plane_e(N), TPL = N / E, H = N / 2, NT = H * TPL;
+  using S = Shape<N, E>;
+  extern __shared__ unsigned char smem_raw[];
+  C *lds = reinterpret_cast<C *>(smem_raw);
+  T *plane = data + (size_t)blockIdx.x * N * N;      // reals [y][x]; complex [ky][kx < H]
+  C *spec = reinterpret_cast<C *>(plane);
+  const int tid = threadIdx.x;
+  const int xl = tid / TPL, xt = tid % TPL;          // x steps: pair xl, thread xt
+  const int yl = tid % H, yt = tid / H;              // y steps: column yl, thread yt
+  const int xoff = xl * (N + 1);
+  constexpr int NTASK = H * H / NT;                  // separation tasks per thread
+  C v[E];
+  if (!INV) {
+    constexpr int R0 = S::first(false), RL = S::last(false);
+#pragma unroll
+    for (int b = 0; b < E / R0; ++b)
+#pragma unroll
+      for (int r = 0; r < R0; ++r) {
+        const int pos = reg_pos<N, E, R0>(xt, b, r);
+        v[b * R0 + r] = C{plane[(2 * xl) * N + pos], plane[(2 * xl + 1) * N + pos]};
+      }
+    reg_fft_forward<T, N, E>(v, xt, lds, 1, xoff, tw);
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < E / RL; ++b)
+#pragma unroll
+      for (int r = 0; r < RL; ++r) lds[xoff + reg_pos<N, E, RL>(xt, b, r)] = v[b * RL + r];
+    __syncthreads();
+    // A(k) = (Z(k) + conj Z(-k))/2 (row 2p), B(k) = (Z(k) - conj Z(-k))/2i (row 2p+1)
+    C A[NTASK], B[NTASK];
+#pragma unroll
+    for (int j = 0; j < NTASK; ++j) {
+      const int w = tid + j * NT, ln = w / H, k = w % H;
+      const C zp = lds[ln * (N + 1) + k], zm = lds[ln * (N + 1) + (N - k) % N];
+      A[j] = C{(T)0.5 * (zp.x + zm.x), (T)0.5 * (zp.y - zm.y)};
+      B[j] = C{(T)0.5 * (zp.y + zm.y), (T)0.5 * (zm.x - zp.x)};
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < NTASK; ++j) {
+      const int w = tid + j * NT, ln = w / H, k = w % H;
+      lds[(2 * ln) * H + k] = A[j];
+      lds[(2 * ln + 1) * H + k] = B[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < E / R0; ++b)
+#pragma unroll
+      for (int r = 0; r < R0; ++r) v[b * R0 + r] = lds[reg_pos<N, E, R0>(yt, b, r) * H + yl];
+    reg_fft_forward<T, N, E>(v, yt, lds, H, yl, tw);
+#pragma unroll
+    for (int b = 0; b < E / RL; ++b)
+#pragma unroll
+      for (int r = 0; r < RL; ++r) spec[reg_pos<N, E, RL>(yt, b, r) * H + yl] = v[b * RL + r];
+  } else {
+    constexpr int R0 = S::first(true), RL = S::last(true);
+#pragma unroll
+    for (int b = 0; b < E / R0; ++b)
+#pragma unroll
+      for (int r = 0; r < R0; ++r) v[b * R0 + r] = spec[reg_pos<N, E, R0>(yt, b, r) * H + yl];
+    reg_fft_inverse<T, N, E>(v, yt, lds, H, yl, tw);
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < E / RL; ++b)
+#pragma unroll
+      for (int r = 0; r < RL; ++r) lds[reg_pos<N, E, RL>(yt, b, r) * H + yl] = v[b * RL + r];
+    __syncthreads();
+    // Z(k) = A(k) + i B(k); Z(N-k) = conj A(k) + i conj B(k); Z(N/2) = 0
+    C Zp[NTASK], Zm[NTASK];
+#pragma unroll
+    for (int j = 0; j < NTASK; ++j) {
+      const int w = tid + j * NT, ln = w / H, k = w % H;
+      const C a = lds[(2 * ln) * H + k], bb = lds[(2 * ln + 1) * H + k];
+      Zp[j] = C{a.x - bb.y, a.y + bb.x};
+      Zm[j] = C{a.x + bb.y, bb.x - a.y};
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < NTASK; ++j) {
+      const int w = tid + j * NT, ln = w / H, k = w % H;
+      lds[ln * (N + 1) + k] = Zp[j];
+      if (k > 0) lds[ln * (N + 1) + N - k] = Zm[j];
+      else lds[ln * (N + 1) + H] = C{(T)0, (T)0};
+    }
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < E / R0; ++b)
+#pragma unroll
+      for (int r = 0; r < R0; ++r) v[b * R0 + r] = lds[xoff + reg_pos<N, E, R0>(xt, b, r)];
+    reg_fft_inverse<T, N, E>(v, xt, lds, 1, xoff, tw);
+#pragma unroll
+    for (int b = 0; b < E / RL; ++b)
+#pragma unroll
+      for (int r = 0; r < RL; ++r) {
+        const int pos = reg_pos<N, E, RL>(xt, b, r);
+        plane[(2 * xl) * N + pos] = v[b * RL + r].x;
+        plane[(2 * xl + 1) * N + pos] = v[b * RL + r].y;
+      }
+  }
+}
+
 // ------------------------------------------------------- y and z passes --
 
 // Lines along y (axis 1) or z (axis 2) of complex arrays [c][z][y][x] with
@@ -247,6 +368,34 @@ void launch_lines(Handle &h, cplx<T> *data, const cplx<T> *tw, int ncomp, int M,
   PSE_LAUNCH_CHECK();
 }
 
+// Plane kernel: N/2 * TPL threads and H (N + 1) complex of LDS, when these
+// fit (returns false otherwise).
+template <typename T, int N>
+bool launch_xy_plane(Handle &h, T *grids, const cplx<T> *tw, int ncomp, int dir) {
+  constexpr int TPL = N / plane_e(N), H = N / 2;
+  constexpr int threads = H * TPL;
+  const size_t lds = (size_t)H * (N + 1) * sizeof(cplx<T>);
+  if (threads > 1024 || threads < 64 || lds > (size_t)h.max_lds) return false;
+  static std::once_flag once[2];
+  hipError_t attr = hipSuccess;
+  std::call_once(once[dir < 0 ? 0 : 1], [&] {
+    attr = dir < 0 ? hipFuncSetAttribute((const void *)fft_xy_plane_kernel<T, N, false>,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)
+                   : hipFuncSetAttribute((const void *)fft_xy_plane_kernel<T, N, true>,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  });
+  PSE_HIP(attr);
+  const unsigned nb = (unsigned)((size_t)ncomp * N);
+  if (dir < 0)
+    hipLaunchKernelGGL((fft_xy_plane_kernel<T, N, false>), dim3(nb), dim3(threads), lds,
+                       h.stream, grids, tw);
+  else
+    hipLaunchKernelGGL((fft_xy_plane_kernel<T, N, true>), dim3(nb), dim3(threads), lds,
+                       h.stream, grids, tw);
+  PSE_LAUNCH_CHECK();
+  return true;
+}
+
 }  // namespace
 
 #define PSE_CASE_X(NN) case NN: launch_x<T, NN>(h, grids, tw, ncomp, dir); break;
@@ -286,9 +435,22 @@ void fft3d(Handle &h, cplx<T> *data, const cplx<T> *tw, int ncomp, int dir) {
   line_pass<T>(h, data, tw, ncomp, n, 2, dir);
 }
 
+#define PSE_CASE_P(NN) case NN: done = launch_xy_plane<T, NN>(h, grids, tw, ncomp, dir); break;
+
 template <typename T>
 void rfft_xy(Handle &h, T *grids, const cplx<T> *tw, int ncomp, int dir) {
   const int n = h.d.grid;
+  if (n <= 128) {
+    bool done = false;
+    {
+      ProfScope ps(h, PK_FFT, 2.0 * ncomp * h.ngrid * sizeof(T));
+      switch (n) {
+        PSE_FOR_EACH_SMALL_N(PSE_CASE_P)
+        default: break;
+      }
+    }
+    if (done) return;
+  }
   cplx<T> *spec = reinterpret_cast<cplx<T> *>(grids);
   if (dir < 0) {
     x_pass<T>(h, grids, tw, ncomp, dir);

@@ -304,6 +304,9 @@ constexpr int fused_e(int n) { return n % 3 == 0 ? 12 : (n <= 256 ? 4 : 8); }
 // LDS of tl * line_bytes within 64 KiB.
 int lines_per_block(int n, int tpl, size_t line_bytes, size_t count);
 
+// Line lengths whose x-y plane fits one workgroup's LDS.
+#define PSE_FOR_EACH_SMALL_N(X) X(32) X(48) X(64) X(96) X(128)
+
 // Supported line lengths (the grid sizes accepted by the parameter rule).
 #define PSE_FOR_EACH_N(X) \
   X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024)
