@@ -101,6 +101,14 @@ def load_library(path=LIB_PATH):
     if not os.path.exists(path):
         raise RuntimeError(f'{path} is missing: run __graft_entry__.build() '
                            '(python -m paper_1709_06946_amd.build) first')
+    # torch ships its own HIP runtime under the soname libamdhip64.so.7.  Loading
+    # torch first makes the library bind to that same runtime; loading the
+    # library first would map the system runtime, and torch would then start
+    # a second one in the process, which finds no device.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     P, V, I = ctypes.POINTER, ctypes.c_void_p, ctypes.c_int
     lib.pse_derive.argtypes = [P(pse_params), P(pse_derived)]

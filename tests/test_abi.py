@@ -6,6 +6,7 @@ import math
 import os
 import re
 import subprocess
+import sys
 
 import numpy as np
 import pytest
@@ -146,3 +147,15 @@ def test_footprint_grows_with_grid_and_precision(pse):
     assert fm > f[1]
     # FP64 grids dominate: 2 sets x 6 packed complex grids x 16 B
     assert f[1] > 2 * 6 * 128**3 * 16
+
+
+def test_library_binds_to_torchs_hip_runtime():
+    """One HIP runtime per process: after loading the binding in a fresh
+    interpreter, only torch's copy of libamdhip64 is mapped."""
+    code = ("from paper_1709_06946_amd import pse; pse.lib(); "
+            "m = open('/proc/self/maps').read().splitlines(); "
+            "print(sorted({l.split()[-1] for l in m if 'libamdhip64' in l}))")
+    out = subprocess.run([sys.executable, '-c', code], capture_output=True, text=True,
+                         cwd=ROOT, check=True).stdout
+    paths = eval(out.strip())
+    assert len(paths) == 1 and 'torch' in paths[0], paths
