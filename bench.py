@@ -168,6 +168,19 @@ def served(n_req, steps, max_active, n_max, rate_hz, seed):
                 concurrent=conc, one_at_a_time=serial)
 
 
+def copy_calibration(mib=1024, reps=3):
+    """A plain device copy of known size, for scaling HBM byte counters
+    (FETCH_SIZE / WRITE_SIZE under rocprofv3 --pmc): each copy reads and
+    writes `mib` MiB."""
+    import torch
+    a = torch.ones(mib * 2**20 // 8, dtype=torch.float64, device='cuda:0')
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps(dict(copy_mib=mib, reps=reps, bytes_each_way=mib * 2**20)), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument('--gpus', type=int, default=1)
@@ -177,6 +190,8 @@ def main():
     ap.add_argument('--no-cpu-baseline', action='store_true')
     ap.add_argument('--no-mixed', action='store_true')
     ap.add_argument('--no-served', action='store_true')
+    ap.add_argument('--copy-calibration', action='store_true',
+                    help='only run a 1 GiB device copy (counter calibration)')
     ap.add_argument('--served-requests', type=int, default=16)
     ap.add_argument('--served-steps', type=int, default=20)
     ap.add_argument('--served-nmax', type=int, default=20000)
@@ -189,6 +204,9 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    if args.copy_calibration:
+        copy_calibration()
+        return
     from paper_1709_06946_amd import inputs, pse
     w = inputs.workload(args.workload)
     seed = w['seed']

@@ -152,9 +152,9 @@ fft_xc_kernel(cplx<T> *__restrict__ data, const cplx<T> *__restrict__ tw, int di
 // same steps in reverse order.  The plane travels through HBM once each way
 // instead of twice.  Thread (line, t) is (tid / TPL, tid % TPL) in the x
 // steps and (tid % H, tid / H) in the y steps.
-// Elements per thread in the plane kernel: 8 for power-of-two planes (up to
-// 1024 threads, 16 wavefronts per workgroup), 12 for 3 * 2^j.
-constexpr int plane_e(int n) { return n % 3 == 0 ? 12 : 8; }
+// Elements per thread in the plane kernel (as the line passes: fewer
+// exchanges; eight per thread measured slower at 128^2).
+constexpr int plane_e(int n) { return line_e(n); }
 
 template <typename T, int N, bool INV>
 __global__ void __launch_bounds__(1024)

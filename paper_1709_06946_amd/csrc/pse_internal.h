@@ -126,14 +126,20 @@ struct Handle {
   double *v4 = nullptr, *v5 = nullptr;
   double *es_b = nullptr, *es_x = nullptr, *es_r = nullptr, *es_d = nullptr;  // N x 5
 
-  double *ktab = nullptr;
+  double *ktab = nullptr;    // per-|k|^2 radial factors (4 doubles per entry)
   // real-space pair list (CSR in cell order): start[N+1], neighbour index and
   // 10 doubles of pair data per entry; counts and scan scratch
   int *pl_cnt = nullptr, *pl_start = nullptr, *pl_scan = nullptr, *pl_nbr = nullptr;
   double *pl_rec = nullptr;
   size_t pl_cap = 0, pl_pairs = 0;
-  // spreading-tile candidate lists (CSR over tiles)
-  int *tl_cnt = nullptr, *tl_start = nullptr, *tl_scan = nullptr, *tl_list = nullptr;    // per-|k|^2 radial factors (4 doubles per entry)
+  // spreading-tile candidate lists (CSR over tiles): one record per (tile,
+  // particle) pair; the particle side lists each particle's entries
+  // (p_start[N+1], p_slot) for the second pass of the interpolation, whose
+  // per-entry partial sums live in tl_part (cs.n doubles per entry)
+  int *tl_cnt = nullptr, *tl_start = nullptr, *tl_scan = nullptr;
+  void *tl_rec = nullptr;
+  int *p_cnt = nullptr, *p_start = nullptr, *p_scan = nullptr, *p_slot = nullptr;
+  double *tl_part = nullptr;
 
   // Krylov storage
   double *lz_V = nullptr;    // (lanczos_maxit + 1) x 11N
@@ -209,6 +215,7 @@ void kspace_fused(Handle &h, const cplx<T> *in, const CompSet &cin, cplx<T> *out
                   const CompSet &cout, const cplx<T> *tw);
 template <typename T> void zero_grids(Handle &h, T *g, int ncomp);
 void build_tile_lists(Handle &h, const double *xw);
+size_t tile_record_bytes();                       // one (tile, particle) record
 int ktable_len(int grid);                         // entries of the |k|^2 table
 void build_ktable(Handle &h);
 template <typename T> void from_double(Handle &h, const double *src, size_t n, T *dst);
