@@ -301,11 +301,6 @@ static void create(const pse_params &p, Handle &h) {
     alloc((void **)&h.tl_scan, ((ntile + 1023) / 1024 + 8) * sizeof(int));
     const size_t cap = n * tiles_per_particle(h.d.support, h.stile);
     alloc((void **)&h.tl_rec, cap * tile_record_bytes());
-    alloc((void **)&h.tl_part, cap * NC * sizeof(double));
-    alloc((void **)&h.p_cnt, n * sizeof(int));
-    alloc((void **)&h.p_start, (n + 1) * sizeof(int));
-    alloc((void **)&h.p_scan, ((n + 1023) / 1024 + 8) * sizeof(int));
-    alloc((void **)&h.p_slot, cap * sizeof(int));
   }
   alloc((void **)&h.pl_cnt, n * sizeof(int));
   alloc((void **)&h.pl_start, (n + 1) * sizeof(int));
@@ -347,7 +342,7 @@ static void release(Handle &h) {
                   h.xw, h.xh, h.v0, h.v1, h.v2, h.v3, h.v4, h.v5, h.es_b, h.es_x, h.es_r,
                   h.es_d, h.lz_V, h.gm_V, h.small, h.dots, h.ktab, h.pl_cnt,
                   h.pl_start, h.pl_scan, h.pl_nbr, h.pl_rec, h.tl_cnt, h.tl_start,
-                  h.tl_scan, h.tl_rec, h.tl_part, h.p_cnt, h.p_start, h.p_scan, h.p_slot};
+                  h.tl_scan, h.tl_rec};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   for (hipEvent_t e : h.prof.pool) (void)hipEventDestroy(e);

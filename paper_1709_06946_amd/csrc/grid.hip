@@ -79,10 +79,6 @@ struct TileRec {
   double x[3];
 };
 
-__device__ __forceinline__ int floor_div(int a, int b) {
-  return a >= 0 ? a / b : -((-a + b - 1) / b);
-}
-
 // Whether a stencil starting at grid index st (P points) meets the tile
 // starting at t0 (S points) on a periodic axis of ng points.
 __device__ __forceinline__ bool stencil_meets(int st, int t0, int P, int S, int ng) {
@@ -91,26 +87,8 @@ __device__ __forceinline__ bool stencil_meets(int st, int t0, int P, int S, int 
   return a < P || a > ng - S;
 }
 
-// Tiles met by each particle's stencil: the product over the axes of the
-// tile range floor(st/S) .. floor((st + P - 1)/S).
-__global__ void __launch_bounds__(256)
-particle_tiles_kernel(const double *__restrict__ x, GridGeom g, int S, int64_t n,
-                      int *__restrict__ cnt) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n) return;
-  int c = 1;
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    const int st = stencil_start(x[3 * p + d], g.h, g.P);
-    c *= floor_div(st + g.P - 1, S) - floor_div(st, S) + 1;
-  }
-  cnt[p] = c;
-}
-
 // FILL = false: count each tile's candidates; true: write their records from
-// start[tile] on, in bin order and ranked with a ballot, and enter each
-// record's slot in its particle's list at the position of the tile within
-// the particle's tile range.  One wavefront per tile enumerates the
+// start[tile] on, in bin order and ranked with a ballot.  One wavefront per tile enumerates the
 // particles of the 27 bins around it 64 at a time (bins are tiles; a
 // stencil reaches at most one tile beyond its particle's).
 template <bool FILL>
@@ -118,8 +96,7 @@ __global__ void __launch_bounds__(256)
 tile_list_kernel(const double *__restrict__ x, GridGeom g, int S, int nb,
                  const int *__restrict__ bstart, const int *__restrict__ bperm,
                  int *__restrict__ cnt, const int *__restrict__ start,
-                 TileRec *__restrict__ rec, const int *__restrict__ pstart,
-                 int *__restrict__ pslot) {
+                 TileRec *__restrict__ rec) {
   const int tile = blockIdx.x * 4 + threadIdx.x / 64;
   const int lane = threadIdx.x % 64;
   if (tile >= nb * nb * nb) return;
@@ -151,20 +128,12 @@ tile_list_kernel(const double *__restrict__ x, GridGeom g, int S, int nb,
         const int e = pos + __popcll(m & ((1ull << lane) - 1ull));
         TileRec r;
         r.p = p;
-        int ord = 0, mul = 1;
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
           r.st[d] = st[d];
           r.x[d] = x[3 * p + d];
-          const int f = floor_div(st[d], S);
-          const int c = floor_div(st[d] + P - 1, S) - f + 1;
-          int o = (tc[d] - f) % nb;
-          o += o < 0 ? nb : 0;
-          ord += o * mul;
-          mul *= c;
         }
         rec[e] = r;
-        pslot[pstart[p] + ord] = e;
       }
       pos += __popcll(m);
     }
@@ -259,119 +228,11 @@ spread_list_kernel(const double *__restrict__ q, int qstride, CompSet cs, GridGe
   }
 }
 
-// Interpolation by tiles, first pass: one workgroup per tile loads the
-// tile's grid values (every component) into LDS with coalesced reads, then
-// each wavefront takes candidates in turn and sums the Gaussian weights
-// times the grid over the part of the candidate's stencil inside the tile,
-// writing that partial sum to the candidate's record slot.  The grids are
-// read from HBM once.
-template <typename T, int S, int NCM>
-__global__ void __launch_bounds__(256)
-interp_tile_kernel(const T *__restrict__ grids, size_t ngrid, CompSet cs, GridGeom g, int nb,
-                   const int *__restrict__ tstart, const TileRec *__restrict__ rec,
-                   double *__restrict__ part) {
-  constexpr int S3 = S * S * S;
-  __shared__ T tb[NCM][S3];
-  const int tile = blockIdx.x;
-  const int tx = tile % nb, ty = (tile / nb) % nb, tz = tile / (nb * nb);
-  const int ng = g.ng, P = g.P;
-  for (int l = threadIdx.x; l < S3; l += blockDim.x) {
-    const size_t gi = ((size_t)(tz * S + l / (S * S)) * ng + ty * S + (l / S) % S) * ng
-                      + tx * S + l % S;
-#pragma unroll
-    for (int k = 0; k < NCM; ++k)
-      if (k < cs.n) tb[k][l] = grids[(size_t)k * ngrid + gi];
-  }
-  __syncthreads();
-  const int lo = tstart[tile], hi = tstart[tile + 1];
-  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64, nwave = blockDim.x / 64;
-  const double kn3 = g.knorm * g.knorm * g.knorm;
-  const int t0[3] = {tx * S, ty * S, tz * S};
-  for (int e = lo + wave; e < hi; e += nwave) {
-    const TileRec r = rec[e];
-    // overlap of stencil and tile per axis: tile-local start, extent and the
-    // stencil index of the first overlapping point
-    int tl[3], ext[3], s0[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      int a = (t0[d] - r.st[d]) % ng;
-      a += a < 0 ? ng : 0;
-      if (a < P) {             // tile starts inside the stencil
-        tl[d] = 0;
-        s0[d] = a;
-        ext[d] = min(S, P - a);
-      } else {                 // stencil starts inside the tile
-        tl[d] = ng - a;
-        s0[d] = 0;
-        ext[d] = min(S - tl[d], P);
-      }
-    }
-    const int nbox = ext[0] * ext[1] * ext[2];
-    T acc[NCM];
-#pragma unroll
-    for (int k = 0; k < NCM; ++k) acc[k] = (T)0;
-    for (int i = lane; i < nbox; i += 64) {
-      const int a = i % ext[0], b = (i / ext[0]) % ext[1], c = i / (ext[0] * ext[1]);
-      const double dx = (r.st[0] + s0[0] + a) * g.h - r.x[0];
-      const double dy = (r.st[1] + s0[1] + b) * g.h - r.x[1];
-      const double dz = (r.st[2] + s0[2] + c) * g.h - r.x[2];
-      const T w = (T)(kn3 * exp(-g.kcoef * (dx * dx + dy * dy + dz * dz)));
-      const int l = ((tl[2] + c) * S + tl[1] + b) * S + tl[0] + a;
-#pragma unroll
-      for (int k = 0; k < NCM; ++k)
-        if (k < cs.n) acc[k] += w * tb[k][l];
-    }
-#pragma unroll
-    for (int k = 0; k < NCM; ++k) {
-      if (k < cs.n) {
-        T v = acc[k];
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-        if (lane == 0) part[(size_t)e * NCM + k] = (double)v;
-      }
-    }
-  }
-}
-
-__global__ void __launch_bounds__(256) fill_i32_kernel(int *__restrict__ a, size_t n, int v) {
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) a[i] = v;
-}
-
-// Second pass: each particle sums the partial results of its tiles in a
-// fixed order (its tile range, x fastest).  Slots are reset to -1 before the
-// lists are filled, and any slot outside [0, cap) is skipped.
-template <int NCM>
-__global__ void __launch_bounds__(256)
-interp_sum_kernel(const double *__restrict__ part, const int *__restrict__ pstart,
-                  const int *__restrict__ pslot, int cap, CompSet cs, int64_t n,
-                  double *__restrict__ out, int ostride, int accumulate, double scale) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n) return;
-  double acc[NCM];
-#pragma unroll
-  for (int k = 0; k < NCM; ++k) acc[k] = 0.0;
-  const int s1 = pstart[p + 1];
-  for (int s = pstart[p]; s < s1; ++s) {
-    const int e = pslot[s];
-    if (e < 0 || e >= cap) continue;
-    const double *pp = part + (size_t)e * NCM;
-#pragma unroll
-    for (int k = 0; k < NCM; ++k)
-      if (k < cs.n) acc[k] += pp[k];
-  }
-#pragma unroll
-  for (int k = 0; k < NCM; ++k) {
-    if (k < cs.n) {
-      double *o = out + p * ostride + cs.idx[k];
-      const double v = scale * acc[k];
-      *o = accumulate ? *o + v : v;
-    }
-  }
-}
-
 // --------------------------------------------------------- interpolation --
 
-// One wavefront per particle; lane s covers stencil points s, s + 64, ...
+// One wavefront per particle (particles in cell order, each XCD taking a
+// contiguous range of them so that neighbouring stencils share its L2);
+// lane s covers stencil points s, s + 64, ...
 // With MAXIT = ceil(P^3 / 64) fixed at compile time, a lane first forms all
 // its grid indices and weights and then issues every grid load at once, so
 // that the loads of all stencil points and components are in flight
@@ -383,7 +244,7 @@ interp_kernel(const double *__restrict__ x, const T *__restrict__ grids,
               int64_t n, double *__restrict__ out, int ostride, int accumulate,
               double scale) {
   const int lane = threadIdx.x & 63;
-  const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t t = (int64_t)xcd_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
   if (t >= n) return;
   const int64_t p = order ? order[t] : t;
   const double px = x[3 * p], py = x[3 * p + 1], pz = x[3 * p + 2];
@@ -877,7 +738,7 @@ void build_ktable(Handle &h) {
 }
 
 // Candidate lists of the spreading tiles for wrapped positions xw (after the
-// spreading bins are current), with each particle's list of its entries.
+// spreading bins are current).
 // The capacity N * (ceil((P-1)/S) + 1)^3 is the most tiles a stencil can
 // meet, so the lists never overflow.
 void build_tile_lists(Handle &h, const double *xw) {
@@ -885,24 +746,15 @@ void build_tile_lists(Handle &h, const double *xw) {
   const GridGeom g = geom(h);
   const int nb = h.sbins.nc;
   const int ntile = nb * nb * nb;
-  hipLaunchKernelGGL(particle_tiles_kernel, dim3(nblocks(h.n, 256)), dim3(256), 0, h.stream, xw,
-                     g, h.stile, h.n, h.p_cnt);
-  PSE_LAUNCH_CHECK();
-  exclusive_scan(h, h.p_cnt, h.p_start, h.p_scan, (int)h.n);
-  const size_t cap = (size_t)h.n * tiles_per_particle(h.d.support, h.stile);
-  hipLaunchKernelGGL(fill_i32_kernel, dim3(nblocks(cap, 256)), dim3(256), 0, h.stream, h.p_slot,
-                     cap, -1);
-  PSE_LAUNCH_CHECK();
   const unsigned blocks = (unsigned)((ntile + 3) / 4);
   hipLaunchKernelGGL((tile_list_kernel<false>), dim3(blocks), dim3(256), 0, h.stream, xw, g,
                      h.stile, nb, (const int *)h.sbins.start, (const int *)h.sbins.perm,
-                     h.tl_cnt, nullptr, nullptr, nullptr, nullptr);
+                     h.tl_cnt, nullptr, nullptr);
   PSE_LAUNCH_CHECK();
   exclusive_scan(h, h.tl_cnt, h.tl_start, h.tl_scan, ntile);
   hipLaunchKernelGGL((tile_list_kernel<true>), dim3(blocks), dim3(256), 0, h.stream, xw, g,
                      h.stile, nb, (const int *)h.sbins.start, (const int *)h.sbins.perm, nullptr,
-                     (const int *)h.tl_start, (TileRec *)h.tl_rec, (const int *)h.p_start,
-                     h.p_slot);
+                     (const int *)h.tl_start, (TileRec *)h.tl_rec);
   PSE_LAUNCH_CHECK();
 }
 
@@ -957,37 +809,6 @@ void interpolate(Handle &h, const double *x, const T *grids, const CompSet &cs,
                  double *out, int ostride, bool accumulate, double scale) {
   const GridGeom g = geom(h);
   const int acc = accumulate ? 1 : 0;
-  if (h.stile) {
-    const int nb = h.sbins.nc;
-    const unsigned tiles = (unsigned)nb * nb * nb;
-    const TileRec *rec = (const TileRec *)h.tl_rec;
-    const int *ts = (const int *)h.tl_start;
-    {
-      ProfScope ps(h, PK_INTERP, (double)cs.n * h.ngrid * sizeof(T));
-      with_ncm(cs.n, [&](auto ncm) {
-        constexpr int M = decltype(ncm)::value;
-        if (h.stile == 4)
-          hipLaunchKernelGGL((interp_tile_kernel<T, 4, M>), dim3(tiles), dim3(64), 0, h.stream,
-                             grids, h.ngrid, cs, g, nb, ts, rec, h.tl_part);
-        else if (h.stile == 8)
-          hipLaunchKernelGGL((interp_tile_kernel<T, 8, M>), dim3(tiles), dim3(256), 0, h.stream,
-                             grids, h.ngrid, cs, g, nb, ts, rec, h.tl_part);
-        else
-          throw Error{PSE_ERR_INVALID, "unsupported spreading tile"};
-      });
-      PSE_LAUNCH_CHECK();
-    }
-    ProfScope ps(h, PK_MISC, (double)h.n * cs.n * 8 * 2);
-    with_ncm(cs.n, [&](auto ncm) {
-      constexpr int M = decltype(ncm)::value;
-      hipLaunchKernelGGL((interp_sum_kernel<M>), dim3(nblocks(h.n, 256)), dim3(256), 0,
-                         h.stream, h.tl_part, (const int *)h.p_start, (const int *)h.p_slot,
-                         (int)((size_t)h.n * tiles_per_particle(h.d.support, h.stile)), cs, h.n,
-                         out, ostride, acc, scale);
-    });
-    PSE_LAUNCH_CHECK();
-    return;
-  }
   ProfScope ps(h, PK_INTERP, (double)cs.n * h.ngrid * sizeof(T) + (double)h.n * (3 + cs.n) * 8);
   const int P3 = g.P * g.P * g.P;
   const dim3 grid(nblocks(h.n, 4)), block(256);

@@ -110,10 +110,9 @@ size_t footprint(const pse_params &p, const pse_derived &d) {
   const int S = spread_tile(d.grid, d.support);
   const size_t tiles3 = S ? ng3 / ((size_t)S * S * S) : 0;
   if (S) {
-    // tile CSR, particle CSR, and per entry: record (40 B), slot, partial sums
+    // tile CSR and one 40-byte record per (tile, particle) pair
     const size_t cap = n * tiles_per_particle(d.support, S);
-    bytes += (2 * tiles3 + tiles3 / 1024 + 2 * n + n / 1024 + 32) * sizeof(int)
-             + cap * (40 + sizeof(int) + NC * sizeof(double));
+    bytes += (2 * tiles3 + tiles3 / 1024 + 16) * sizeof(int) + cap * 40;
   }
   bytes += (2 * (ncell3 + tiles3) + 4 + (ncell3 + tiles3) / 1024 + 16) * sizeof(int)
            + 6 * n * sizeof(int);

@@ -133,13 +133,9 @@ struct Handle {
   double *pl_rec = nullptr;
   size_t pl_cap = 0, pl_pairs = 0;
   // spreading-tile candidate lists (CSR over tiles): one record per (tile,
-  // particle) pair; the particle side lists each particle's entries
-  // (p_start[N+1], p_slot) for the second pass of the interpolation, whose
-  // per-entry partial sums live in tl_part (cs.n doubles per entry)
+  // particle) pair
   int *tl_cnt = nullptr, *tl_start = nullptr, *tl_scan = nullptr;
   void *tl_rec = nullptr;
-  int *p_cnt = nullptr, *p_start = nullptr, *p_scan = nullptr, *p_slot = nullptr;
-  double *tl_part = nullptr;
 
   // Krylov storage
   double *lz_V = nullptr;    // (lanczos_maxit + 1) x 11N
@@ -242,6 +238,15 @@ inline int spread_tile(int grid, int P) {
     if (grid % S == 0 && grid / S >= 3 && need <= 2 * S) return S;
   }
   return 0;
+}
+
+// Workgroups are dispatched to the 8 XCDs in turn; this maps the dispatch
+// index to a logical block so that each XCD takes a contiguous range of
+// logical blocks (and its L2 sees neighbouring work).  A bijection of
+// [0, nb).
+__device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nb) {
+  const unsigned x = b % 8, i = b / 8, per = nb / 8, rem = nb % 8;
+  return x * per + (x < rem ? x : rem) + i;
 }
 
 // ---- neighbour-bin enumeration (device helpers shared by the list builders)

@@ -511,7 +511,8 @@ real_pair_kernel(const double *__restrict__ in, double *__restrict__ out,
                  const int *__restrict__ perm, const int *__restrict__ start,
                  const int *__restrict__ nbr, const double *__restrict__ rec,
                  const T *__restrict__ tab, RealArgs ra) {
-  const int64_t t = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / GROUP;
+  const int64_t t =
+      ((int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x) / GROUP;
   const int lane = threadIdx.x % GROUP;
   if (t >= ra.n) return;
   const int i = perm[t];
