@@ -45,6 +45,51 @@ multi_dot_partial(const double *__restrict__ V, size_t ldv, const double *__rest
   if (threadIdx.x == 0) partial[(size_t)j * gridDim.x + blockIdx.x] = s[0];
 }
 
+// Same partial sums, and the last workgroup to finish vector j (counted in
+// done[j], which it resets to zero) adds the partials of j in block order:
+// one launch, deterministic result.
+__global__ void __launch_bounds__(256)
+multi_dot_fused(const double *__restrict__ V, size_t ldv, const double *__restrict__ w,
+                size_t n, double *__restrict__ partial, unsigned *__restrict__ done,
+                double *__restrict__ out) {
+  __shared__ double s[256];
+  __shared__ bool last;
+  const int j = blockIdx.y;
+  const double *v = V + (size_t)j * ldv;
+  double acc = 0.0;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
+    acc += v[i] * w[i];
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    partial[(size_t)j * gridDim.x + blockIdx.x] = s[0];
+    __threadfence();
+    last = atomicAdd(done + j, 1u) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  const int nb = gridDim.x;
+  double a = 0.0;
+  for (int b = threadIdx.x; b < nb; b += 256)
+    a += __hip_atomic_load(partial + (size_t)j * nb + b, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+  s[threadIdx.x] = a;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[j] = s[0];
+    done[j] = 0u;
+  }
+}
+
 __global__ void __launch_bounds__(256)
 reduce_partial(const double *__restrict__ partial, int nb, double *__restrict__ out) {
   __shared__ double s[256];
@@ -137,11 +182,10 @@ void multi_dot(Handle &h, const double *V, size_t ldv, int m, const double *w,
   int nb = (int)std::min<size_t>(RED_BLOCKS, (n + 255) / 256);
   if (nb < 1) nb = 1;
   if ((size_t)nb * m > h.dots_len) throw Error{PSE_ERR_INVALID, "reduction scratch too small"};
+  if (m > MAX_DOT_VECTORS) throw Error{PSE_ERR_INVALID, "too many vectors in one reduction"};
   ProfScope ps(h, PK_KRYLOV, (double)(m + 1) * n * 8);
-  hipLaunchKernelGGL(multi_dot_partial, dim3(nb, m), dim3(256), 0, h.stream, V, ldv, w, n,
-                     h.dots);
-  PSE_LAUNCH_CHECK();
-  hipLaunchKernelGGL(reduce_partial, dim3(m), dim3(256), 0, h.stream, h.dots, nb, dev_out);
+  hipLaunchKernelGGL(multi_dot_fused, dim3(nb, m), dim3(256), 0, h.stream, V, ldv, w, n,
+                     h.dots, h.dot_done, dev_out);
   PSE_LAUNCH_CHECK();
 }
 
@@ -253,8 +297,13 @@ __device__ void tridiag_ql(double *d, double *e, double *z, int m, int ldz) {
 __global__ void lanczos_sqrt_kernel(const double *alpha, const double *beta, int m,
                                     double bnorm, double *work, int ldz, double *coef,
                                     double *coef_prev, double *out_change) {
+  // the eigenproblem runs on one thread; its arrays live in LDS when they fit
+  // (dynamic shared memory sized by the host), else in the global work area
+  extern __shared__ double lds_work[];
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  double *d = work, *e = work + ldz, *z = work + 2 * ldz;
+  const bool in_lds = ldz == m;
+  double *base = in_lds ? lds_work : work;
+  double *d = base, *e = base + ldz, *z = base + 2 * ldz;
   for (int i = 0; i < m; ++i) {
     d[i] = alpha[i];
     e[i] = i + 1 < m ? beta[i] : 0.0;
@@ -404,8 +453,15 @@ KrylovResult lanczos_sqrt(Handle &h, const Op &A, const double *b, size_t n, dou
     hipLaunchKernelGGL(lanczos_fill_kernel, dim3(1), dim3(1), 0, h.stream, alpha, beta, j,
                        h1, h2, norm2, vnorm);
     PSE_LAUNCH_CHECK();
-    hipLaunchKernelGGL(lanczos_sqrt_kernel, dim3(1), dim3(1), 0, h.stream, alpha, beta,
-                       j + 1, bnorm, work, ldz, coef, coef_prev, change);
+    {
+      // LDS holds d, e and the (j+1)^2 eigenvectors when they fit in 48 KiB
+      const int mm = j + 1;
+      const size_t lds = (size_t)(2 * mm + mm * mm) * sizeof(double);
+      const bool fits = lds <= 49152;
+      hipLaunchKernelGGL(lanczos_sqrt_kernel, dim3(1), dim3(64), fits ? lds : 0, h.stream,
+                         alpha, beta, mm, bnorm, work, fits ? mm : ldz, coef, coef_prev,
+                         change);
+    }
     PSE_LAUNCH_CHECK();
     double hv[3];   // vnorm, bn, change are adjacent
     host_read(h, vnorm, hv, 3);
