@@ -331,8 +331,6 @@ static void create(const pse_params &p, Handle &h) {
   alloc((void **)&h.small, h.small_len * sizeof(double));
   h.dots_len = 1024 * (std::max(M, R) + 2);
   alloc((void **)&h.dots, h.dots_len * sizeof(double));
-  alloc((void **)&h.dot_done, MAX_DOT_VECTORS * sizeof(unsigned));
-  PSE_HIP(hipMemsetAsync(h.dot_done, 0, MAX_DOT_VECTORS * sizeof(unsigned), h.stream));
   PSE_HIP(hipStreamSynchronize(h.stream));
 }
 
@@ -344,7 +342,7 @@ static void release(Handle &h) {
                   h.xw, h.xh, h.v0, h.v1, h.v2, h.v3, h.v4, h.v5, h.es_b, h.es_x, h.es_r,
                   h.es_d, h.lz_V, h.gm_V, h.small, h.dots, h.ktab, h.pl_cnt,
                   h.pl_start, h.pl_scan, h.pl_nbr, h.pl_rec, h.tl_cnt, h.tl_start,
-                  h.tl_scan, h.tl_rec, h.dot_done};
+                  h.tl_scan, h.tl_rec};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   for (hipEvent_t e : h.prof.pool) (void)hipEventDestroy(e);

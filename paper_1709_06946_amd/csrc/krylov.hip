@@ -45,51 +45,6 @@ multi_dot_partial(const double *__restrict__ V, size_t ldv, const double *__rest
   if (threadIdx.x == 0) partial[(size_t)j * gridDim.x + blockIdx.x] = s[0];
 }
 
-// Same partial sums, and the last workgroup to finish vector j (counted in
-// done[j], which it resets to zero) adds the partials of j in block order:
-// one launch, deterministic result.
-__global__ void __launch_bounds__(256)
-multi_dot_fused(const double *__restrict__ V, size_t ldv, const double *__restrict__ w,
-                size_t n, double *__restrict__ partial, unsigned *__restrict__ done,
-                double *__restrict__ out) {
-  __shared__ double s[256];
-  __shared__ bool last;
-  const int j = blockIdx.y;
-  const double *v = V + (size_t)j * ldv;
-  double acc = 0.0;
-  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
-    acc += v[i] * w[i];
-  s[threadIdx.x] = acc;
-  __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
-    if (threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    partial[(size_t)j * gridDim.x + blockIdx.x] = s[0];
-    __threadfence();
-    last = atomicAdd(done + j, 1u) == gridDim.x - 1;
-  }
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  const int nb = gridDim.x;
-  double a = 0.0;
-  for (int b = threadIdx.x; b < nb; b += 256)
-    a += __hip_atomic_load(partial + (size_t)j * nb + b, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-  s[threadIdx.x] = a;
-  __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
-    if (threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    out[j] = s[0];
-    done[j] = 0u;
-  }
-}
-
 __global__ void __launch_bounds__(256)
 reduce_partial(const double *__restrict__ partial, int nb, double *__restrict__ out) {
   __shared__ double s[256];
@@ -182,10 +137,11 @@ void multi_dot(Handle &h, const double *V, size_t ldv, int m, const double *w,
   int nb = (int)std::min<size_t>(RED_BLOCKS, (n + 255) / 256);
   if (nb < 1) nb = 1;
   if ((size_t)nb * m > h.dots_len) throw Error{PSE_ERR_INVALID, "reduction scratch too small"};
-  if (m > MAX_DOT_VECTORS) throw Error{PSE_ERR_INVALID, "too many vectors in one reduction"};
   ProfScope ps(h, PK_KRYLOV, (double)(m + 1) * n * 8);
-  hipLaunchKernelGGL(multi_dot_fused, dim3(nb, m), dim3(256), 0, h.stream, V, ldv, w, n,
-                     h.dots, h.dot_done, dev_out);
+  hipLaunchKernelGGL(multi_dot_partial, dim3(nb, m), dim3(256), 0, h.stream, V, ldv, w, n,
+                     h.dots);
+  PSE_LAUNCH_CHECK();
+  hipLaunchKernelGGL(reduce_partial, dim3(m), dim3(256), 0, h.stream, h.dots, nb, dev_out);
   PSE_LAUNCH_CHECK();
 }
 

@@ -14,7 +14,6 @@ namespace pse {
 
 constexpr int NC = 11;           // generalized force/velocity components
 constexpr int MAX_PACK = 6;      // packed complex grids (two real grids each)
-constexpr int MAX_DOT_VECTORS = 512;   // vectors in one multi-dot reduction
 constexpr int NCOEF = 7;         // real-space coefficient functions
 
 // Error carrying a status code; converted at the ABI boundary.
@@ -146,7 +145,6 @@ struct Handle {
   size_t small_len;
   double *dots = nullptr;    // partial sums for reductions
   size_t dots_len;
-  unsigned *dot_done = nullptr;  // per-vector completion counters of the reductions
 
   Profiler prof;
 };
