@@ -15,6 +15,16 @@ namespace pse {
 
 // ------------------------------------------------------------- x passes --
 
+// Contiguous-line LDS layout of the x steps: one pad element after every PAD
+// positions, PAD = the first radix of the direction (see padpos), and a line
+// stride of N + N/PAD + 1 elements.
+constexpr int xstride(int n, int pad) { return n + n / pad + 1; }
+template <int N, int E> constexpr int xstride_max() {
+  return xstride(N, Shape<N, E>::first(false)) > xstride(N, Shape<N, E>::first(true))
+             ? xstride(N, Shape<N, E>::first(false))
+             : xstride(N, Shape<N, E>::first(true));
+}
+
 // Rows y and y+1 travel as one complex line z = a + i b.  After the forward
 // transform the two half spectra are A(k) = (Z(k) + conj Z(-k))/2 and
 // B(k) = (Z(k) - conj Z(-k))/2i, separated from LDS and written over the rows.
@@ -38,19 +48,20 @@ fft_x_r2c_kernel(T *__restrict__ data, const cplx<T> *__restrict__ tw, int TL) {
       const int pos = reg_pos<N, E, R0>(t, b, r);
       v[b * R0 + r] = C{row[pos], row[N + pos]};
     }
-  const int off = line * (N + 1);
-  reg_fft_forward<T, N, E>(v, t, lds, 1, off, tw);
+  constexpr int PAD = S::first(false), LS = xstride(N, PAD);
+  const int off = line * LS;
+  reg_fft_forward<T, N, E, PAD>(v, t, lds, 1, off, tw);
   constexpr int RL = S::last(false);
   __syncthreads();
 #pragma unroll
   for (int b = 0; b < E / RL; ++b)
 #pragma unroll
-    for (int r = 0; r < RL; ++r) lds[off + reg_pos<N, E, RL>(t, b, r)] = v[b * RL + r];
+    for (int r = 0; r < RL; ++r) lds[off + padpos<PAD>(reg_pos<N, E, RL>(t, b, r))] = v[b * RL + r];
   __syncthreads();
   const C *Z = lds;
   for (int w = threadIdx.x; w < TL * H; w += blockDim.x) {
     const int ln = w / H, k = w % H;
-    const C zp = Z[ln * (N + 1) + k], zm = Z[ln * (N + 1) + (N - k) % N];
+    const C zp = Z[ln * LS + padpos<PAD>(k)], zm = Z[ln * LS + padpos<PAD>((N - k) % N)];
     C a, bb;
     a.x = (T)0.5 * (zp.x + zm.x);
     a.y = (T)0.5 * (zp.y - zm.y);
@@ -73,25 +84,26 @@ fft_x_c2r_kernel(T *__restrict__ data, const cplx<T> *__restrict__ tw, int TL) {
   using S = Shape<N, E>;
   extern __shared__ unsigned char smem_raw[];
   C *lds = reinterpret_cast<C *>(smem_raw);
+  constexpr int PAD = S::first(true), LS = xstride(N, PAD);
   for (int w = threadIdx.x; w < TL * H; w += blockDim.x) {
     const int ln = w / H, k = w % H;
     const C *in = reinterpret_cast<const C *>(data + 2 * ((size_t)blockIdx.x * TL + ln) * N);
     const C a = in[k], bb = in[H + k];
-    C *Z = lds + ln * (N + 1);
-    Z[k] = C{a.x - bb.y, a.y + bb.x};
-    if (k > 0) Z[N - k] = C{a.x + bb.y, bb.x - a.y};
-    else Z[H] = C{(T)0, (T)0};
+    C *Z = lds + ln * LS;
+    Z[padpos<PAD>(k)] = C{a.x - bb.y, a.y + bb.x};
+    if (k > 0) Z[padpos<PAD>(N - k)] = C{a.x + bb.y, bb.x - a.y};
+    else Z[padpos<PAD>(H)] = C{(T)0, (T)0};
   }
   __syncthreads();
   const int line = threadIdx.x / TPL, t = threadIdx.x % TPL;
-  const int off = line * (N + 1);
+  const int off = line * LS;
   constexpr int R0 = S::first(true);
   C v[E];
 #pragma unroll
   for (int b = 0; b < E / R0; ++b)
 #pragma unroll
-    for (int r = 0; r < R0; ++r) v[b * R0 + r] = lds[off + reg_pos<N, E, R0>(t, b, r)];
-  reg_fft_inverse<T, N, E>(v, t, lds, 1, off, tw);
+    for (int r = 0; r < R0; ++r) v[b * R0 + r] = lds[off + padpos<PAD>(reg_pos<N, E, R0>(t, b, r))];
+  reg_fft_inverse<T, N, E, PAD>(v, t, lds, 1, off, tw);
   constexpr int RL = S::last(true);
   T *row = data + 2 * ((size_t)blockIdx.x * TL + line) * N;
 #pragma unroll
@@ -115,7 +127,7 @@ fft_xc_kernel(cplx<T> *__restrict__ data, const cplx<T> *__restrict__ tw, int di
   C *lds = reinterpret_cast<C *>(smem_raw);
   const int line = threadIdx.x / TPL, t = threadIdx.x % TPL;
   C *ln = data + ((size_t)blockIdx.x * TL + line) * N;
-  const int off = line * (N + 1);
+  const int off = line * xstride_max<N, E>();
   C v[E];
   if (dir < 0) {
     constexpr int R0 = S::first(false), RL = S::last(false);
@@ -123,7 +135,7 @@ fft_xc_kernel(cplx<T> *__restrict__ data, const cplx<T> *__restrict__ tw, int di
     for (int b = 0; b < E / R0; ++b)
 #pragma unroll
       for (int r = 0; r < R0; ++r) v[b * R0 + r] = ln[reg_pos<N, E, R0>(t, b, r)];
-    reg_fft_forward<T, N, E>(v, t, lds, 1, off, tw);
+    reg_fft_forward<T, N, E, S::first(false)>(v, t, lds, 1, off, tw);
 #pragma unroll
     for (int b = 0; b < E / RL; ++b)
 #pragma unroll
@@ -134,7 +146,7 @@ fft_xc_kernel(cplx<T> *__restrict__ data, const cplx<T> *__restrict__ tw, int di
     for (int b = 0; b < E / R0; ++b)
 #pragma unroll
       for (int r = 0; r < R0; ++r) v[b * R0 + r] = ln[reg_pos<N, E, R0>(t, b, r)];
-    reg_fft_inverse<T, N, E>(v, t, lds, 1, off, tw);
+    reg_fft_inverse<T, N, E, S::first(true)>(v, t, lds, 1, off, tw);
 #pragma unroll
     for (int b = 0; b < E / RL; ++b)
 #pragma unroll
@@ -169,11 +181,12 @@ fft_xy_plane_kernel(T *__restrict__ data, const cplx<T> *__restrict__ tw) {
   const int tid = threadIdx.x;
   const int xl = tid / TPL, xt = tid % TPL;          // x steps: pair xl, thread xt
   const int yl = tid % H, yt = tid / H;              // y steps: column yl, thread yt
-  const int xoff = xl * (N + 1);
   constexpr int NTASK = H * H / NT;                  // separation tasks per thread
   C v[E];
   if (!INV) {
     constexpr int R0 = S::first(false), RL = S::last(false);
+    constexpr int PAD = R0, LS = xstride(N, PAD);
+    const int xoff = xl * LS;
 #pragma unroll
     for (int b = 0; b < E / R0; ++b)
 #pragma unroll
@@ -181,19 +194,20 @@ fft_xy_plane_kernel(T *__restrict__ data, const cplx<T> *__restrict__ tw) {
         const int pos = reg_pos<N, E, R0>(xt, b, r);
         v[b * R0 + r] = C{plane[(2 * xl) * N + pos], plane[(2 * xl + 1) * N + pos]};
       }
-    reg_fft_forward<T, N, E>(v, xt, lds, 1, xoff, tw);
+    reg_fft_forward<T, N, E, PAD>(v, xt, lds, 1, xoff, tw);
     __syncthreads();
 #pragma unroll
     for (int b = 0; b < E / RL; ++b)
 #pragma unroll
-      for (int r = 0; r < RL; ++r) lds[xoff + reg_pos<N, E, RL>(xt, b, r)] = v[b * RL + r];
+      for (int r = 0; r < RL; ++r)
+        lds[xoff + padpos<PAD>(reg_pos<N, E, RL>(xt, b, r))] = v[b * RL + r];
     __syncthreads();
     // A(k) = (Z(k) + conj Z(-k))/2 (row 2p), B(k) = (Z(k) - conj Z(-k))/2i (row 2p+1)
     C A[NTASK], B[NTASK];
 #pragma unroll
     for (int j = 0; j < NTASK; ++j) {
       const int w = tid + j * NT, ln = w / H, k = w % H;
-      const C zp = lds[ln * (N + 1) + k], zm = lds[ln * (N + 1) + (N - k) % N];
+      const C zp = lds[ln * LS + padpos<PAD>(k)], zm = lds[ln * LS + padpos<PAD>((N - k) % N)];
       A[j] = C{(T)0.5 * (zp.x + zm.x), (T)0.5 * (zp.y - zm.y)};
       B[j] = C{(T)0.5 * (zp.y + zm.y), (T)0.5 * (zm.x - zp.x)};
     }
@@ -216,6 +230,8 @@ fft_xy_plane_kernel(T *__restrict__ data, const cplx<T> *__restrict__ tw) {
       for (int r = 0; r < RL; ++r) spec[reg_pos<N, E, RL>(yt, b, r) * H + yl] = v[b * RL + r];
   } else {
     constexpr int R0 = S::first(true), RL = S::last(true);
+    constexpr int PAD = R0, LS = xstride(N, PAD);
+    const int xoff = xl * LS;
 #pragma unroll
     for (int b = 0; b < E / R0; ++b)
 #pragma unroll
@@ -240,16 +256,16 @@ fft_xy_plane_kernel(T *__restrict__ data, const cplx<T> *__restrict__ tw) {
 #pragma unroll
     for (int j = 0; j < NTASK; ++j) {
       const int w = tid + j * NT, ln = w / H, k = w % H;
-      lds[ln * (N + 1) + k] = Zp[j];
-      if (k > 0) lds[ln * (N + 1) + N - k] = Zm[j];
-      else lds[ln * (N + 1) + H] = C{(T)0, (T)0};
+      lds[ln * LS + padpos<PAD>(k)] = Zp[j];
+      if (k > 0) lds[ln * LS + padpos<PAD>(N - k)] = Zm[j];
+      else lds[ln * LS + padpos<PAD>(H)] = C{(T)0, (T)0};
     }
     __syncthreads();
 #pragma unroll
     for (int b = 0; b < E / R0; ++b)
 #pragma unroll
-      for (int r = 0; r < R0; ++r) v[b * R0 + r] = lds[xoff + reg_pos<N, E, R0>(xt, b, r)];
-    reg_fft_inverse<T, N, E>(v, xt, lds, 1, xoff, tw);
+      for (int r = 0; r < R0; ++r) v[b * R0 + r] = lds[xoff + padpos<PAD>(reg_pos<N, E, R0>(xt, b, r))];
+    reg_fft_inverse<T, N, E, PAD>(v, xt, lds, 1, xoff, tw);
 #pragma unroll
     for (int b = 0; b < E / RL; ++b)
 #pragma unroll
@@ -333,8 +349,9 @@ template <typename T, int N>
 void launch_x(Handle &h, T *grids, const cplx<T> *tw, int ncomp, int dir) {
   constexpr int TPL = N / line_e(N);
   const size_t pairs = (size_t)ncomp * N * N / 2;
-  const int tl = lines_per_block(N, TPL, (N + 1) * sizeof(cplx<T>), pairs);
-  const size_t lds = (size_t)tl * (N + 1) * sizeof(cplx<T>);
+  constexpr int LS = xstride_max<N, line_e(N)>();
+  const int tl = lines_per_block(N, TPL, LS * sizeof(cplx<T>), pairs);
+  const size_t lds = (size_t)tl * LS * sizeof(cplx<T>);
   const unsigned nb = (unsigned)(pairs / tl);
   if (dir < 0)
     hipLaunchKernelGGL((fft_x_r2c_kernel<T, N>), dim3(nb), dim3(tl * TPL), lds, h.stream, grids,
@@ -349,8 +366,9 @@ template <typename T, int N>
 void launch_xc(Handle &h, cplx<T> *data, const cplx<T> *tw, int ncomp, int dir) {
   constexpr int TPL = N / line_e(N);
   const size_t lines = (size_t)ncomp * N * N;
-  const int tl = lines_per_block(N, TPL, (N + 1) * sizeof(cplx<T>), lines);
-  const size_t lds = (size_t)tl * (N + 1) * sizeof(cplx<T>);
+  constexpr int LS = xstride_max<N, line_e(N)>();
+  const int tl = lines_per_block(N, TPL, LS * sizeof(cplx<T>), lines);
+  const size_t lds = (size_t)tl * LS * sizeof(cplx<T>);
   hipLaunchKernelGGL((fft_xc_kernel<T, N>), dim3((unsigned)(lines / tl)), dim3(tl * TPL), lds,
                      h.stream, data, tw, dir, tl);
   PSE_LAUNCH_CHECK();
@@ -368,13 +386,15 @@ void launch_lines(Handle &h, cplx<T> *data, const cplx<T> *tw, int ncomp, int M,
   PSE_LAUNCH_CHECK();
 }
 
-// Plane kernel: N/2 * TPL threads and H (N + 1) complex of LDS, when these
-// fit (returns false otherwise).
+// Plane kernel: N/2 * TPL threads and max(H * LS, N * H) complex of LDS
+// (the padded x layout and the [y][kx] layout), when these fit (returns
+// false otherwise).
 template <typename T, int N>
 bool launch_xy_plane(Handle &h, T *grids, const cplx<T> *tw, int ncomp, int dir) {
   constexpr int TPL = N / plane_e(N), H = N / 2;
   constexpr int threads = H * TPL;
-  const size_t lds = (size_t)H * (N + 1) * sizeof(cplx<T>);
+  constexpr int LS = xstride_max<N, plane_e(N)>();
+  const size_t lds = (size_t)(H * LS > N * H ? H * LS : N * H) * sizeof(cplx<T>);
   if (threads > 1024 || threads < 64 || lds > (size_t)h.max_lds) return false;
   static std::once_flag once[2];
   hipError_t attr = hipSuccess;

@@ -246,10 +246,20 @@ __device__ __forceinline__ void reg_pass(cplx<T> (&v)[E], int t, const cplx<T> *
   }
 }
 
+// LDS position with one pad element after every PADP positions (PADP = 0:
+// none).  In the contiguous-line layouts (ps = 1) the first pass of radix R
+// writes positions j R + r, a stride of R elements across the threads of a
+// line; padding with PADP = R makes that stride R + 1 and spreads the
+// accesses over the banks.
+template <int PADP> __device__ __forceinline__ int padpos(int pos) {
+  if constexpr (PADP > 0) return pos + pos / PADP;
+  else return pos;
+}
+
 // Exchange through LDS after a pass of radix R (span Ns) into the input
 // layout of a pass of radix R2.  Element at position pos lives at
-// lds[pos * ps + off].
-template <typename T, int N, int E, int R, int Ns, int R2>
+// lds[padpos(pos) * ps + off].
+template <typename T, int N, int E, int R, int Ns, int R2, int PADP>
 __device__ __forceinline__ void reg_exchange(cplx<T> (&v)[E], int t, cplx<T> *lds, int ps,
                                              int off) {
   constexpr int TPL = N / E;
@@ -259,16 +269,17 @@ __device__ __forceinline__ void reg_exchange(cplx<T> (&v)[E], int t, cplx<T> *ld
     const int j = t + b * TPL;
     const int base = (j / Ns) * Ns * R + (j % Ns);
 #pragma unroll
-    for (int r = 0; r < R; ++r) lds[(base + r * Ns) * ps + off] = v[b * R + r];
+    for (int r = 0; r < R; ++r) lds[padpos<PADP>(base + r * Ns) * ps + off] = v[b * R + r];
   }
   __syncthreads();
 #pragma unroll
   for (int b = 0; b < E / R2; ++b)
 #pragma unroll
-    for (int r = 0; r < R2; ++r) v[b * R2 + r] = lds[reg_pos<N, E, R2>(t, b, r) * ps + off];
+    for (int r = 0; r < R2; ++r)
+      v[b * R2 + r] = lds[padpos<PADP>(reg_pos<N, E, R2>(t, b, r)) * ps + off];
 }
 
-template <typename T, int N, int E, bool REV, int P, int Ns>
+template <typename T, int N, int E, bool REV, int P, int Ns, int PADP>
 __device__ __forceinline__ void reg_run(cplx<T> (&v)[E], int t, cplx<T> *lds, int ps, int off,
                                         const cplx<T> *__restrict__ tw, int dir) {
   using S = Shape<N, E>;
@@ -276,23 +287,23 @@ __device__ __forceinline__ void reg_run(cplx<T> (&v)[E], int t, cplx<T> *lds, in
   reg_pass<T, N, E, R, Ns>(v, t, tw, dir);
   if constexpr (P + 1 < S::NP) {
     constexpr int R2 = S::radix(P + 1, REV);
-    reg_exchange<T, N, E, R, Ns, R2>(v, t, lds, ps, off);
-    reg_run<T, N, E, REV, P + 1, Ns * R>(v, t, lds, ps, off, tw, dir);
+    reg_exchange<T, N, E, R, Ns, R2, PADP>(v, t, lds, ps, off);
+    reg_run<T, N, E, REV, P + 1, Ns * R, PADP>(v, t, lds, ps, off, tw, dir);
   }
 }
 
 // Forward transform (exp(-2 pi i k n / N)) with the passes in factor order.
-template <typename T, int N, int E>
+template <typename T, int N, int E, int PADP = 0>
 __device__ __forceinline__ void reg_fft_forward(cplx<T> (&v)[E], int t, cplx<T> *lds, int ps,
                                                 int off, const cplx<T> *__restrict__ tw) {
-  reg_run<T, N, E, false, 0, 1>(v, t, lds, ps, off, tw, -1);
+  reg_run<T, N, E, false, 0, 1, PADP>(v, t, lds, ps, off, tw, -1);
 }
 
 // Inverse (unnormalised, exp(+2 pi i k n / N)) with the passes reversed.
-template <typename T, int N, int E>
+template <typename T, int N, int E, int PADP = 0>
 __device__ __forceinline__ void reg_fft_inverse(cplx<T> (&v)[E], int t, cplx<T> *lds, int ps,
                                                 int off, const cplx<T> *__restrict__ tw) {
-  reg_run<T, N, E, true, 0, 1>(v, t, lds, ps, off, tw, +1);
+  reg_run<T, N, E, true, 0, 1, PADP>(v, t, lds, ps, off, tw, +1);
 }
 
 // Element counts per thread: line passes and the fused k-space kernel (which
