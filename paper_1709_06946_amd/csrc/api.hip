@@ -274,6 +274,9 @@ static void create(const pse_params &p, Handle &h) {
     PSE_HIP(hipGetDevice(&dev));
     PSE_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
     h.max_lds = lds;
+    int cus = 0;
+    PSE_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    h.num_cu = cus > 0 ? cus : 1;
   }
   const size_t n = (size_t)h.n;
   const int ng = h.d.grid;

@@ -7,6 +7,7 @@
 // spectra H[c][kz][ky][kx < N/2] (a row of N reals holds N/2 complex); the
 // Nyquist column kx = N/2 is not stored, and every Nyquist mode is zero in
 // the spectra the k-space kernels produce.
+#include <algorithm>
 #include <mutex>
 
 #include "fftreg.h"
@@ -156,124 +157,170 @@ fft_xc_kernel(cplx<T> *__restrict__ data, const cplx<T> *__restrict__ tw, int di
 
 // ------------------------------------------------- x and y in one kernel --
 
-// Forward (INV = false): one workgroup transforms one z-plane of one real
-// component: x transforms of the N/2 row pairs (registers + LDS exchanges in
-// a padded [pair][N+1] layout), separation of the two half spectra into a
-// [y][kx < N/2] layout in the same LDS buffer, then y transforms of the N/2
-// columns, written to the plane's half spectrum.  Inverse (INV = true): the
-// same steps in reverse order.  The plane travels through HBM once each way
-// instead of twice.  Thread (line, t) is (tid / TPL, tid % TPL) in the x
-// steps and (tid % H, tid / H) in the y steps.
 // Elements per thread in the plane kernel (as the line passes: fewer
 // exchanges; eight per thread measured slower at 128^2).
 constexpr int plane_e(int n) { return line_e(n); }
 
+// Forward (INV = false): a workgroup transforms z-planes of the real
+// components, one at a time: x transforms of the N/2 row pairs (registers +
+// LDS exchanges in a padded [pair][LS] layout), separation of the two half
+// spectra into a [y][kx < N/2] layout in the same LDS buffer, then y
+// transforms of the N/2 columns, written to the plane's half spectrum.
+// Inverse (INV = true): the same steps in reverse order.  Each plane travels
+// through HBM once each way instead of twice.  The kernel is persistent: a
+// workgroup takes planes blockIdx.x, blockIdx.x + gridDim.x, ... and loads
+// the next plane into registers while it transforms the current one (the
+// plane's LDS footprint allows one or two workgroups per CU, which leaves
+// registers to spare).  Thread (line, t) is (tid / TPL, tid % TPL) in the x
+// steps and (tid % H, tid / H) in the y steps.
 template <typename T, int N, bool INV>
-__global__ void __launch_bounds__(1024)
-fft_xy_plane_kernel(T *__restrict__ data, const cplx<T> *__restrict__ tw) {
+__global__ void __launch_bounds__(512)
+fft_xy_plane_kernel(T *__restrict__ data, const cplx<T> *__restrict__ tw, int nplanes) {
   using C = cplx<T>;
   constexpr int E = plane_e(N), TPL = N / E, H = N / 2, NT = H * TPL;
   using S = Shape<N, E>;
   extern __shared__ unsigned char smem_raw[];
   C *lds = reinterpret_cast<C *>(smem_raw);
-  T *plane = data + (size_t)blockIdx.x * N * N;      // reals [y][x]; complex [ky][kx < H]
-  C *spec = reinterpret_cast<C *>(plane);
   const int tid = threadIdx.x;
   const int xl = tid / TPL, xt = tid % TPL;          // x steps: pair xl, thread xt
   const int yl = tid % H, yt = tid / H;              // y steps: column yl, thread yt
   constexpr int NTASK = H * H / NT;                  // separation tasks per thread
-  C v[E];
+  const int step = gridDim.x;
+  int pl = blockIdx.x;
+  if (pl >= nplanes) return;
+  C v[E], vn[E];
   if (!INV) {
     constexpr int R0 = S::first(false), RL = S::last(false);
     constexpr int PAD = R0, LS = xstride(N, PAD);
     const int xoff = xl * LS;
+    {
+      const T *pr = data + (size_t)pl * N * N;
 #pragma unroll
-    for (int b = 0; b < E / R0; ++b)
+      for (int b = 0; b < E / R0; ++b)
 #pragma unroll
-      for (int r = 0; r < R0; ++r) {
-        const int pos = reg_pos<N, E, R0>(xt, b, r);
-        v[b * R0 + r] = C{plane[(2 * xl) * N + pos], plane[(2 * xl + 1) * N + pos]};
+        for (int r = 0; r < R0; ++r) {
+          const int pos = reg_pos<N, E, R0>(xt, b, r);
+          vn[b * R0 + r] = C{pr[(2 * xl) * N + pos], pr[(2 * xl + 1) * N + pos]};
+        }
+    }
+    for (; pl < nplanes; pl += step) {
+      // the thread coordinates are made opaque in each iteration so that the
+      // transforms' twiddle loads stay inside the loop instead of holding
+      // registers across it
+      int xt_ = xt, yt_ = yt;
+      asm volatile("" : "+v"(xt_), "+v"(yt_));
+#pragma unroll
+      for (int e = 0; e < E; ++e) v[e] = vn[e];
+      if (pl + step < nplanes) {
+        const T *pr = data + (size_t)(pl + step) * N * N;
+#pragma unroll
+        for (int b = 0; b < E / R0; ++b)
+#pragma unroll
+          for (int r = 0; r < R0; ++r) {
+            const int pos = reg_pos<N, E, R0>(xt, b, r);
+            vn[b * R0 + r] = C{pr[(2 * xl) * N + pos], pr[(2 * xl + 1) * N + pos]};
+          }
       }
-    reg_fft_forward<T, N, E, PAD>(v, xt, lds, 1, xoff, tw);
-    __syncthreads();
+      reg_fft_forward<T, N, E, PAD>(v, xt_, lds, 1, xoff, tw);
+      __syncthreads();
 #pragma unroll
-    for (int b = 0; b < E / RL; ++b)
+      for (int b = 0; b < E / RL; ++b)
 #pragma unroll
-      for (int r = 0; r < RL; ++r)
-        lds[xoff + padpos<PAD>(reg_pos<N, E, RL>(xt, b, r))] = v[b * RL + r];
-    __syncthreads();
-    // A(k) = (Z(k) + conj Z(-k))/2 (row 2p), B(k) = (Z(k) - conj Z(-k))/2i (row 2p+1)
-    C A[NTASK], B[NTASK];
+        for (int r = 0; r < RL; ++r)
+          lds[xoff + padpos<PAD>(reg_pos<N, E, RL>(xt_, b, r))] = v[b * RL + r];
+      __syncthreads();
+      // A(k) = (Z(k) + conj Z(-k))/2 (row 2p), B(k) = (Z(k) - conj Z(-k))/2i (row 2p+1)
+      C A[NTASK], B[NTASK];
 #pragma unroll
-    for (int j = 0; j < NTASK; ++j) {
-      const int w = tid + j * NT, ln = w / H, k = w % H;
-      const C zp = lds[ln * LS + padpos<PAD>(k)], zm = lds[ln * LS + padpos<PAD>((N - k) % N)];
-      A[j] = C{(T)0.5 * (zp.x + zm.x), (T)0.5 * (zp.y - zm.y)};
-      B[j] = C{(T)0.5 * (zp.y + zm.y), (T)0.5 * (zm.x - zp.x)};
+      for (int j = 0; j < NTASK; ++j) {
+        const int w = tid + j * NT, ln = w / H, k = w % H;
+        const C zp = lds[ln * LS + padpos<PAD>(k)], zm = lds[ln * LS + padpos<PAD>((N - k) % N)];
+        A[j] = C{(T)0.5 * (zp.x + zm.x), (T)0.5 * (zp.y - zm.y)};
+        B[j] = C{(T)0.5 * (zp.y + zm.y), (T)0.5 * (zm.x - zp.x)};
+      }
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < NTASK; ++j) {
+        const int w = tid + j * NT, ln = w / H, k = w % H;
+        lds[(2 * ln) * H + k] = A[j];
+        lds[(2 * ln + 1) * H + k] = B[j];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int b = 0; b < E / R0; ++b)
+#pragma unroll
+        for (int r = 0; r < R0; ++r) v[b * R0 + r] = lds[reg_pos<N, E, R0>(yt_, b, r) * H + yl];
+      reg_fft_forward<T, N, E>(v, yt_, lds, H, yl, tw);
+      C *spec = reinterpret_cast<C *>(data + (size_t)pl * N * N);
+#pragma unroll
+      for (int b = 0; b < E / RL; ++b)
+#pragma unroll
+        for (int r = 0; r < RL; ++r) spec[reg_pos<N, E, RL>(yt_, b, r) * H + yl] = v[b * RL + r];
     }
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < NTASK; ++j) {
-      const int w = tid + j * NT, ln = w / H, k = w % H;
-      lds[(2 * ln) * H + k] = A[j];
-      lds[(2 * ln + 1) * H + k] = B[j];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int b = 0; b < E / R0; ++b)
-#pragma unroll
-      for (int r = 0; r < R0; ++r) v[b * R0 + r] = lds[reg_pos<N, E, R0>(yt, b, r) * H + yl];
-    reg_fft_forward<T, N, E>(v, yt, lds, H, yl, tw);
-#pragma unroll
-    for (int b = 0; b < E / RL; ++b)
-#pragma unroll
-      for (int r = 0; r < RL; ++r) spec[reg_pos<N, E, RL>(yt, b, r) * H + yl] = v[b * RL + r];
   } else {
     constexpr int R0 = S::first(true), RL = S::last(true);
     constexpr int PAD = R0, LS = xstride(N, PAD);
     const int xoff = xl * LS;
+    {
+      const C *sp = reinterpret_cast<const C *>(data + (size_t)pl * N * N);
 #pragma unroll
-    for (int b = 0; b < E / R0; ++b)
+      for (int b = 0; b < E / R0; ++b)
 #pragma unroll
-      for (int r = 0; r < R0; ++r) v[b * R0 + r] = spec[reg_pos<N, E, R0>(yt, b, r) * H + yl];
-    reg_fft_inverse<T, N, E>(v, yt, lds, H, yl, tw);
-    __syncthreads();
-#pragma unroll
-    for (int b = 0; b < E / RL; ++b)
-#pragma unroll
-      for (int r = 0; r < RL; ++r) lds[reg_pos<N, E, RL>(yt, b, r) * H + yl] = v[b * RL + r];
-    __syncthreads();
-    // Z(k) = A(k) + i B(k); Z(N-k) = conj A(k) + i conj B(k); Z(N/2) = 0
-    C Zp[NTASK], Zm[NTASK];
-#pragma unroll
-    for (int j = 0; j < NTASK; ++j) {
-      const int w = tid + j * NT, ln = w / H, k = w % H;
-      const C a = lds[(2 * ln) * H + k], bb = lds[(2 * ln + 1) * H + k];
-      Zp[j] = C{a.x - bb.y, a.y + bb.x};
-      Zm[j] = C{a.x + bb.y, bb.x - a.y};
+        for (int r = 0; r < R0; ++r) vn[b * R0 + r] = sp[reg_pos<N, E, R0>(yt, b, r) * H + yl];
     }
-    __syncthreads();
+    for (; pl < nplanes; pl += step) {
+      int xt_ = xt, yt_ = yt;
+      asm volatile("" : "+v"(xt_), "+v"(yt_));
 #pragma unroll
-    for (int j = 0; j < NTASK; ++j) {
-      const int w = tid + j * NT, ln = w / H, k = w % H;
-      lds[ln * LS + padpos<PAD>(k)] = Zp[j];
-      if (k > 0) lds[ln * LS + padpos<PAD>(N - k)] = Zm[j];
-      else lds[ln * LS + padpos<PAD>(H)] = C{(T)0, (T)0};
-    }
-    __syncthreads();
+      for (int e = 0; e < E; ++e) v[e] = vn[e];
+      if (pl + step < nplanes) {
+        const C *sp = reinterpret_cast<const C *>(data + (size_t)(pl + step) * N * N);
 #pragma unroll
-    for (int b = 0; b < E / R0; ++b)
+        for (int b = 0; b < E / R0; ++b)
 #pragma unroll
-      for (int r = 0; r < R0; ++r) v[b * R0 + r] = lds[xoff + padpos<PAD>(reg_pos<N, E, R0>(xt, b, r))];
-    reg_fft_inverse<T, N, E, PAD>(v, xt, lds, 1, xoff, tw);
-#pragma unroll
-    for (int b = 0; b < E / RL; ++b)
-#pragma unroll
-      for (int r = 0; r < RL; ++r) {
-        const int pos = reg_pos<N, E, RL>(xt, b, r);
-        plane[(2 * xl) * N + pos] = v[b * RL + r].x;
-        plane[(2 * xl + 1) * N + pos] = v[b * RL + r].y;
+          for (int r = 0; r < R0; ++r) vn[b * R0 + r] = sp[reg_pos<N, E, R0>(yt, b, r) * H + yl];
       }
+      reg_fft_inverse<T, N, E>(v, yt_, lds, H, yl, tw);
+      __syncthreads();
+#pragma unroll
+      for (int b = 0; b < E / RL; ++b)
+#pragma unroll
+        for (int r = 0; r < RL; ++r) lds[reg_pos<N, E, RL>(yt_, b, r) * H + yl] = v[b * RL + r];
+      __syncthreads();
+      // Z(k) = A(k) + i B(k); Z(N-k) = conj A(k) + i conj B(k); Z(N/2) = 0
+      C Zp[NTASK], Zm[NTASK];
+#pragma unroll
+      for (int j = 0; j < NTASK; ++j) {
+        const int w = tid + j * NT, ln = w / H, k = w % H;
+        const C a = lds[(2 * ln) * H + k], bb = lds[(2 * ln + 1) * H + k];
+        Zp[j] = C{a.x - bb.y, a.y + bb.x};
+        Zm[j] = C{a.x + bb.y, bb.x - a.y};
+      }
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < NTASK; ++j) {
+        const int w = tid + j * NT, ln = w / H, k = w % H;
+        lds[ln * LS + padpos<PAD>(k)] = Zp[j];
+        if (k > 0) lds[ln * LS + padpos<PAD>(N - k)] = Zm[j];
+        else lds[ln * LS + padpos<PAD>(H)] = C{(T)0, (T)0};
+      }
+      __syncthreads();
+#pragma unroll
+      for (int b = 0; b < E / R0; ++b)
+#pragma unroll
+        for (int r = 0; r < R0; ++r)
+          v[b * R0 + r] = lds[xoff + padpos<PAD>(reg_pos<N, E, R0>(xt_, b, r))];
+      reg_fft_inverse<T, N, E, PAD>(v, xt_, lds, 1, xoff, tw);
+      T *pr = data + (size_t)pl * N * N;
+#pragma unroll
+      for (int b = 0; b < E / RL; ++b)
+#pragma unroll
+        for (int r = 0; r < RL; ++r) {
+          const int pos = reg_pos<N, E, RL>(xt_, b, r);
+          pr[(2 * xl) * N + pos] = v[b * RL + r].x;
+          pr[(2 * xl + 1) * N + pos] = v[b * RL + r].y;
+        }
+    }
   }
 }
 
@@ -395,7 +442,7 @@ bool launch_xy_plane(Handle &h, T *grids, const cplx<T> *tw, int ncomp, int dir)
   constexpr int threads = H * TPL;
   constexpr int LS = xstride_max<N, plane_e(N)>();
   const size_t lds = (size_t)(H * LS > N * H ? H * LS : N * H) * sizeof(cplx<T>);
-  if (threads > 1024 || threads < 64 || lds > (size_t)h.max_lds) return false;
+  if (threads > 512 || threads < 64 || lds > (size_t)h.max_lds) return false;
   static std::once_flag once[2];
   hipError_t attr = hipSuccess;
   std::call_once(once[dir < 0 ? 0 : 1], [&] {
@@ -405,13 +452,18 @@ bool launch_xy_plane(Handle &h, T *grids, const cplx<T> *tw, int ncomp, int dir)
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   });
   PSE_HIP(attr);
-  const unsigned nb = (unsigned)((size_t)ncomp * N);
+  // forward: persistent, as many workgroups as fit at once (LDS bound);
+  // inverse: one workgroup per plane (measured faster without the prefetch)
+  const int nplanes = ncomp * N;
+  const int per_cu = std::max(1, (int)(163840 / lds));
+  const unsigned nb =
+      dir < 0 ? (unsigned)std::min(nplanes, h.num_cu * per_cu) : (unsigned)nplanes;
   if (dir < 0)
     hipLaunchKernelGGL((fft_xy_plane_kernel<T, N, false>), dim3(nb), dim3(threads), lds,
-                       h.stream, grids, tw);
+                       h.stream, grids, tw, nplanes);
   else
     hipLaunchKernelGGL((fft_xy_plane_kernel<T, N, true>), dim3(nb), dim3(threads), lds,
-                       h.stream, grids, tw);
+                       h.stream, grids, tw, nplanes);
   PSE_LAUNCH_CHECK();
   return true;
 }

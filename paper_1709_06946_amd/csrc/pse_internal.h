@@ -118,6 +118,7 @@ struct Handle {
   Bins sbins;
   int stile;                 // grid points per spreading tile side (0: atomics)
   int max_lds = 65536;       // dynamic LDS a workgroup may use on this device
+  int num_cu = 256;          // compute units of the device
 
   // particle work vectors (double, N x 11 each)
   double *xw = nullptr;      // wrapped positions N x 3
