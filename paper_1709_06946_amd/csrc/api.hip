@@ -111,32 +111,34 @@ __global__ void f2d_kernel(const float2 *src, double2 *dst, size_t n) {
 // ------------------------------------------------------------ operators --
 
 template <typename T>
-static void wave_apply(Handle &h, const double *xw, const double *in, const CompSet &cin,
-                       double *out, const CompSet &cout, bool accumulate) {
+static void wave_apply(Handle &h, const double *xw, const double *in, Layout lin,
+                       const CompSet &cin, double *out, Layout lout, const CompSet &cout,
+                       bool accumulate) {
   GridSet<T> &G = grids<T>(h);
   T *gin = reinterpret_cast<T *>(G.gin), *gout = reinterpret_cast<T *>(G.gout);
-  spread<T>(h, xw, in, NC, cin, gin);
+  spread<T>(h, xw, in, lin, cin, gin);
   rfft_xy<T>(h, gin, G.twiddle, cin.n, -1);
   kspace_fused<T>(h, G.gin, cin, G.gout, cout, G.twiddle);
   rfft_xy<T>(h, gout, G.twiddle, cout.n, +1);
-  interpolate<T>(h, xw, gout, cout, out, NC, accumulate, 1.0);
+  interpolate<T>(h, xw, gout, cout, out, lout, accumulate, 1.0);
 }
 
 // out[cout] = M(cin -> cout) in[cin] at wrapped positions xw whose cell list
-// is current.  fp64 forces the FP64 kernels in a mixed handle.
+// is current; in and out are particle vectors in layouts lin and lout.  fp64
+// forces the FP64 kernels in a mixed handle.
 static void mobility(Handle &h, const double *xw, bool want_real, bool want_wave,
-                     const double *in, const CompSet &cin, double *out,
-                     const CompSet &cout, bool fp64) {
+                     const double *in, Layout lin, const CompSet &cin, double *out,
+                     Layout lout, const CompSet &cout, bool fp64) {
   const bool f32 = h.mixed && !fp64;
   bool acc = false;
   if (want_real) {
-    if (f32) real_apply<float>(h, xw, in, cin, out, cout, false);
-    else real_apply<double>(h, xw, in, cin, out, cout, false);
+    if (f32) real_apply<float>(h, xw, in, lin, cin, out, lout, cout, false);
+    else real_apply<double>(h, xw, in, lin, cin, out, lout, cout, false);
     acc = true;
   }
   if (want_wave) {
-    if (f32) wave_apply<float>(h, xw, in, cin, out, cout, acc);
-    else wave_apply<double>(h, xw, in, cin, out, cout, acc);
+    if (f32) wave_apply<float>(h, xw, in, lin, cin, out, lout, cout, acc);
+    else wave_apply<double>(h, xw, in, lin, cin, out, lout, cout, acc);
   }
 }
 
@@ -147,7 +149,7 @@ static void wave_sqrt_t(Handle &h, const double *xw, const double *psi, uint64_t
   T *gout = reinterpret_cast<T *>(G.gout);
   kspace_noise<T>(h, psi, seed, counter, G.gout, cout);
   rfft3d<T>(h, gout, G.twiddle, cout.n, +1);
-  interpolate<T>(h, xw, gout, cout, out, NC, false, 1.0);
+  interpolate<T>(h, xw, gout, cout, out, FULL_LAYOUT, false, 1.0);
 }
 
 static void wave_sqrt(Handle &h, const double *xw, const double *psi, uint64_t seed,
@@ -159,8 +161,8 @@ static void wave_sqrt(Handle &h, const double *xw, const double *psi, uint64_t s
 static KrylovResult real_sqrt(Handle &h, const double *xw, const double *psi, double *out) {
   const CompSet all = comps_range(0, NC);
   Op A = [&](const double *in, double *o) {
-    if (h.mixed) real_apply<float>(h, xw, in, all, o, all, false);
-    else real_apply<double>(h, xw, in, all, o, all, false);
+    if (h.mixed) real_apply<float>(h, xw, in, FULL_LAYOUT, all, o, FULL_LAYOUT, all, false);
+    else real_apply<double>(h, xw, in, FULL_LAYOUT, all, o, FULL_LAYOUT, all, false);
   };
   return lanczos_sqrt(h, A, psi, (size_t)h.n * NC, out, h.d.lanczos_maxit, h.d.lanczos_tol);
 }
@@ -177,11 +179,11 @@ static void stresslet_solve(Handle &h, const double *xh, const double *b, double
                             pse_stats &st, bool &converged) {
   const size_t n5 = (size_t)h.n * 5;
   const CompSet es = comps_range(6, 11);
-  auto make_op = [&](bool fp64) {
-    return Op([&, fp64](const double *in, double *o) {
-      scatter_comps(h, in, es, h.v0, NC, h.n, false, 1.0);
-      mobility(h, xh, true, true, h.v0, es, h.v1, es, fp64);
-      gather_comps(h, h.v1, NC, es, o, h.n);
+  // the operator reads and writes the 5-component vectors directly
+  const Layout l5{5, 6};
+  auto make_op = [&, l5](bool fp64) {
+    return Op([&, fp64, l5](const double *in, double *o) {
+      mobility(h, xh, true, true, in, l5, es, o, l5, es, fp64);
     });
   };
   if (!h.mixed) {
@@ -296,6 +298,7 @@ static void create(const pse_params &p, Handle &h) {
   }
   build_tables(h);
   alloc((void **)&h.ktab, (size_t)ktable_len(ng) * 4 * sizeof(double));
+  alloc((void **)&h.bad_pos, 64);
   build_ktable(h);
   if (h.stile) {
     const size_t ntile = (size_t)h.sbins.nc * h.sbins.nc * h.sbins.nc;
@@ -345,7 +348,7 @@ static void release(Handle &h) {
                   h.xw, h.xh, h.v0, h.v1, h.v2, h.v3, h.v4, h.v5, h.es_b, h.es_x, h.es_r,
                   h.es_d, h.lz_V, h.gm_V, h.small, h.dots, h.ktab, h.pl_cnt,
                   h.pl_start, h.pl_scan, h.pl_nbr, h.pl_rec, h.tl_cnt, h.tl_start,
-                  h.tl_scan, h.tl_rec};
+                  h.tl_scan, h.tl_rec, h.bad_pos};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   for (hipEvent_t e : h.prof.pool) (void)hipEventDestroy(e);
@@ -443,8 +446,10 @@ int pse_mobility_apply(pse_handle *hd, const double *x, const double *in, double
     Handle &h = hd->h;
     const CompSet all = comps_range(0, NC);
     prepare_positions(h, x, h.xw);
-    mobility(h, h.xw, parts & PSE_REAL, parts & PSE_WAVE, in, all, out, all, false);
-    PSE_HIP(hipStreamSynchronize(h.stream));
+    mobility(h, h.xw, parts & PSE_REAL, parts & PSE_WAVE, in, FULL_LAYOUT, all, out,
+             FULL_LAYOUT, all, false);
+    if (check_finite(h, out, (size_t)h.n * NC))
+      throw Error{PSE_ERR_NONFINITE, "non-finite mobility product (non-finite input?)"};
   });
 }
 
@@ -530,7 +535,7 @@ int pse_constrained_step(pse_handle *hd, double *x, const double *FL, double dt,
       hipLaunchKernelGGL(moments_kernel, dim3(nblocks(n, 256)), dim3(256), 0, h.stream, FL,
                          (const double *)nullptr, n, h.v4);
       PSE_LAUNCH_CHECK();
-      mobility(h, h.xh, true, true, h.v4, fl, h.v5, es, false);
+      mobility(h, h.xh, true, true, h.v4, FULL_LAYOUT, fl, h.v5, FULL_LAYOUT, es, false);
     }
     hipLaunchKernelGGL(rhs_kernel, dim3(nblocks(n, 256)), dim3(256), 0, h.stream, slip,
                        FL ? (const double *)h.v5 : nullptr, n, h.es_b);
@@ -541,7 +546,8 @@ int pse_constrained_step(pse_handle *hd, double *x, const double *FL, double dt,
                        (const double *)h.es_x, n, h.v4);
     PSE_LAUNCH_CHECK();
     const CompSet u3 = comps_range(0, 3);
-    mobility(h, h.xh, true, true, h.v4, FL ? comps_range(0, 11) : es, h.v5, u3, false);
+    mobility(h, h.xh, true, true, h.v4, FULL_LAYOUT, FL ? comps_range(0, 11) : es, h.v5,
+             FULL_LAYOUT, u3, false);
     double *U = h.v2;   // N x 3
     hipLaunchKernelGGL(velocity_kernel, dim3(nblocks(n, 256)), dim3(256), 0, h.stream, slip,
                        h.v5, n, U);
@@ -603,11 +609,11 @@ int pse_spread(pse_handle *hd, const double *x, const double *q, int ncomp, doub
     const size_t cnt = (size_t)ncomp * h.ngrid;
     if (h.mixed) {
       float *g = reinterpret_cast<float *>(h.g32.gin);
-      spread<float>(h, h.xw, q, ncomp, cs, g);
+      spread<float>(h, h.xw, q, Layout{ncomp, 0}, cs, g);
       to_double<float>(h, g, cnt, out);
     } else {
       double *g = reinterpret_cast<double *>(h.g64.gin);
-      spread<double>(h, h.xw, q, ncomp, cs, g);
+      spread<double>(h, h.xw, q, Layout{ncomp, 0}, cs, g);
       to_double<double>(h, g, cnt, out);
     }
     PSE_HIP(hipStreamSynchronize(h.stream));
@@ -629,11 +635,11 @@ int pse_interpolate(pse_handle *hd, const double *x, const double *g, int ncomp,
     if (h.mixed) {
       float *gg = reinterpret_cast<float *>(h.g32.gout);
       from_double<float>(h, g, cnt, gg);
-      interpolate<float>(h, h.xw, gg, cs, out, ncomp, false, 1.0);
+      interpolate<float>(h, h.xw, gg, cs, out, Layout{ncomp, 0}, false, 1.0);
     } else {
       double *gg = reinterpret_cast<double *>(h.g64.gout);
       from_double<double>(h, g, cnt, gg);
-      interpolate<double>(h, h.xw, gg, cs, out, ncomp, false, 1.0);
+      interpolate<double>(h, h.xw, gg, cs, out, Layout{ncomp, 0}, false, 1.0);
     }
     PSE_HIP(hipStreamSynchronize(h.stream));
   });

@@ -171,7 +171,7 @@ constexpr int plane_e(int n) { return line_e(n); }
 // workgroup takes planes blockIdx.x, blockIdx.x + gridDim.x, ... and loads
 // the next plane into registers while it transforms the current one (the
 // plane's LDS footprint allows one or two workgroups per CU, which leaves
-// registers to spare).  Thread (line, t) is (tid / TPL, tid % TPL) in the x
+// registers to spare); the inverse takes one plane per workgroup.  Thread (line, t) is (tid / TPL, tid % TPL) in the x
 // steps and (tid % H, tid / H) in the y steps.
 template <typename T, int N, bool INV>
 __global__ void __launch_bounds__(512)
@@ -188,8 +188,9 @@ fft_xy_plane_kernel(T *__restrict__ data, const cplx<T> *__restrict__ tw, int np
   const int step = gridDim.x;
   int pl = blockIdx.x;
   if (pl >= nplanes) return;
-  C v[E], vn[E];
+  C v[E];
   if (!INV) {
+    C vn[E];
     constexpr int R0 = S::first(false), RL = S::last(false);
     constexpr int PAD = R0, LS = xstride(N, PAD);
     const int xoff = xl * LS;
@@ -258,69 +259,55 @@ fft_xy_plane_kernel(T *__restrict__ data, const cplx<T> *__restrict__ tw, int np
         for (int r = 0; r < RL; ++r) spec[reg_pos<N, E, RL>(yt_, b, r) * H + yl] = v[b * RL + r];
     }
   } else {
+    // one plane per workgroup (the prefetching loop measured slower here)
     constexpr int R0 = S::first(true), RL = S::last(true);
     constexpr int PAD = R0, LS = xstride(N, PAD);
     const int xoff = xl * LS;
-    {
-      const C *sp = reinterpret_cast<const C *>(data + (size_t)pl * N * N);
+    const C *sp = reinterpret_cast<const C *>(data + (size_t)pl * N * N);
 #pragma unroll
-      for (int b = 0; b < E / R0; ++b)
+    for (int b = 0; b < E / R0; ++b)
 #pragma unroll
-        for (int r = 0; r < R0; ++r) vn[b * R0 + r] = sp[reg_pos<N, E, R0>(yt, b, r) * H + yl];
+      for (int r = 0; r < R0; ++r) v[b * R0 + r] = sp[reg_pos<N, E, R0>(yt, b, r) * H + yl];
+    reg_fft_inverse<T, N, E>(v, yt, lds, H, yl, tw);
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < E / RL; ++b)
+#pragma unroll
+      for (int r = 0; r < RL; ++r) lds[reg_pos<N, E, RL>(yt, b, r) * H + yl] = v[b * RL + r];
+    __syncthreads();
+    // Z(k) = A(k) + i B(k); Z(N-k) = conj A(k) + i conj B(k); Z(N/2) = 0
+    C Zp[NTASK], Zm[NTASK];
+#pragma unroll
+    for (int j = 0; j < NTASK; ++j) {
+      const int w = tid + j * NT, ln = w / H, k = w % H;
+      const C a = lds[(2 * ln) * H + k], bb = lds[(2 * ln + 1) * H + k];
+      Zp[j] = C{a.x - bb.y, a.y + bb.x};
+      Zm[j] = C{a.x + bb.y, bb.x - a.y};
     }
-    for (; pl < nplanes; pl += step) {
-      int xt_ = xt, yt_ = yt;
-      asm volatile("" : "+v"(xt_), "+v"(yt_));
+    __syncthreads();
 #pragma unroll
-      for (int e = 0; e < E; ++e) v[e] = vn[e];
-      if (pl + step < nplanes) {
-        const C *sp = reinterpret_cast<const C *>(data + (size_t)(pl + step) * N * N);
-#pragma unroll
-        for (int b = 0; b < E / R0; ++b)
-#pragma unroll
-          for (int r = 0; r < R0; ++r) vn[b * R0 + r] = sp[reg_pos<N, E, R0>(yt, b, r) * H + yl];
-      }
-      reg_fft_inverse<T, N, E>(v, yt_, lds, H, yl, tw);
-      __syncthreads();
-#pragma unroll
-      for (int b = 0; b < E / RL; ++b)
-#pragma unroll
-        for (int r = 0; r < RL; ++r) lds[reg_pos<N, E, RL>(yt_, b, r) * H + yl] = v[b * RL + r];
-      __syncthreads();
-      // Z(k) = A(k) + i B(k); Z(N-k) = conj A(k) + i conj B(k); Z(N/2) = 0
-      C Zp[NTASK], Zm[NTASK];
-#pragma unroll
-      for (int j = 0; j < NTASK; ++j) {
-        const int w = tid + j * NT, ln = w / H, k = w % H;
-        const C a = lds[(2 * ln) * H + k], bb = lds[(2 * ln + 1) * H + k];
-        Zp[j] = C{a.x - bb.y, a.y + bb.x};
-        Zm[j] = C{a.x + bb.y, bb.x - a.y};
-      }
-      __syncthreads();
-#pragma unroll
-      for (int j = 0; j < NTASK; ++j) {
-        const int w = tid + j * NT, ln = w / H, k = w % H;
-        lds[ln * LS + padpos<PAD>(k)] = Zp[j];
-        if (k > 0) lds[ln * LS + padpos<PAD>(N - k)] = Zm[j];
-        else lds[ln * LS + padpos<PAD>(H)] = C{(T)0, (T)0};
-      }
-      __syncthreads();
-#pragma unroll
-      for (int b = 0; b < E / R0; ++b)
-#pragma unroll
-        for (int r = 0; r < R0; ++r)
-          v[b * R0 + r] = lds[xoff + padpos<PAD>(reg_pos<N, E, R0>(xt_, b, r))];
-      reg_fft_inverse<T, N, E, PAD>(v, xt_, lds, 1, xoff, tw);
-      T *pr = data + (size_t)pl * N * N;
-#pragma unroll
-      for (int b = 0; b < E / RL; ++b)
-#pragma unroll
-        for (int r = 0; r < RL; ++r) {
-          const int pos = reg_pos<N, E, RL>(xt_, b, r);
-          pr[(2 * xl) * N + pos] = v[b * RL + r].x;
-          pr[(2 * xl + 1) * N + pos] = v[b * RL + r].y;
-        }
+    for (int j = 0; j < NTASK; ++j) {
+      const int w = tid + j * NT, ln = w / H, k = w % H;
+      lds[ln * LS + padpos<PAD>(k)] = Zp[j];
+      if (k > 0) lds[ln * LS + padpos<PAD>(N - k)] = Zm[j];
+      else lds[ln * LS + padpos<PAD>(H)] = C{(T)0, (T)0};
     }
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < E / R0; ++b)
+#pragma unroll
+      for (int r = 0; r < R0; ++r)
+        v[b * R0 + r] = lds[xoff + padpos<PAD>(reg_pos<N, E, R0>(xt, b, r))];
+    reg_fft_inverse<T, N, E, PAD>(v, xt, lds, 1, xoff, tw);
+    T *pr = data + (size_t)pl * N * N;
+#pragma unroll
+    for (int b = 0; b < E / RL; ++b)
+#pragma unroll
+      for (int r = 0; r < RL; ++r) {
+        const int pos = reg_pos<N, E, RL>(xt, b, r);
+        pr[(2 * xl) * N + pos] = v[b * RL + r].x;
+        pr[(2 * xl + 1) * N + pos] = v[b * RL + r].y;
+      }
   }
 }
 

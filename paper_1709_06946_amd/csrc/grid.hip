@@ -41,7 +41,7 @@ template <typename T> __device__ __forceinline__ T &part(cplx<T> &z, int k) {
 template <typename T>
 __global__ void __launch_bounds__(256)
 spread_kernel(const double *__restrict__ x, const double *__restrict__ q,
-              int qstride, CompSet cs, GridGeom g, const int *__restrict__ order,
+              Layout lq, CompSet cs, GridGeom g, const int *__restrict__ order,
               int64_t n, T *__restrict__ grids, size_t ngrid) {
   const int lane = threadIdx.x & 63;
   const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -54,7 +54,8 @@ spread_kernel(const double *__restrict__ x, const double *__restrict__ q,
   const int iz0 = stencil_start(pz, g.h, P);
   T qv[NC];
 #pragma unroll
-  for (int k = 0; k < NC; ++k) qv[k] = k < cs.n ? (T)q[p * qstride + cs.idx[k]] : (T)0;
+  for (int k = 0; k < NC; ++k)
+    qv[k] = k < cs.n ? (T)q[p * lq.stride + cs.idx[k] - lq.off] : (T)0;
   const double kn3 = g.knorm * g.knorm * g.knorm;
   for (int s = lane; s < P3; s += 64) {
     const int a = s % P, b = (s / P) % P, c = s / (P * P);
@@ -154,7 +155,7 @@ constexpr int GMAXC = 128;
 
 template <typename T, int S, int NCM>
 __global__ void __launch_bounds__(S * S * S < 256 ? S * S * S : 256)
-spread_list_kernel(const double *__restrict__ q, int qstride, CompSet cs, GridGeom g, int nb,
+spread_list_kernel(const double *__restrict__ q, Layout lq, CompSet cs, GridGeom g, int nb,
                    const int *__restrict__ tstart, const TileRec *__restrict__ rec,
                    T *__restrict__ grids, size_t ngrid) {
   constexpr int NT = S * S * S < 256 ? S * S * S : 256;
@@ -192,7 +193,7 @@ spread_list_kernel(const double *__restrict__ q, int qstride, CompSet cs, GridGe
         szs[t] = r.st[2];
 #pragma unroll
         for (int k = 0; k < NCM; ++k)
-          if (k < cs.n) cq[k][t] = (T)q[(size_t)r.p * qstride + cs.idx[k]];
+          if (k < cs.n) cq[k][t] = (T)q[(size_t)r.p * lq.stride + cs.idx[k] - lq.off];
       }
     }
     __syncthreads();
@@ -241,7 +242,7 @@ template <typename T, int MAXIT>
 __global__ void __launch_bounds__(256)
 interp_kernel(const double *__restrict__ x, const T *__restrict__ grids,
               size_t ngrid, CompSet cs, GridGeom g, const int *__restrict__ order,
-              int64_t n, double *__restrict__ out, int ostride, int accumulate,
+              int64_t n, double *__restrict__ out, Layout lo, int accumulate,
               double scale) {
   const int lane = threadIdx.x & 63;
   const int64_t t = (int64_t)xcd_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
@@ -309,7 +310,7 @@ interp_kernel(const double *__restrict__ x, const T *__restrict__ grids,
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
       if (k < cs.n) {
-        double *o = out + p * ostride + cs.idx[k];
+        double *o = out + p * lo.stride + cs.idx[k] - lo.off;
         const double v = scale * (double)acc[k];
         *o = accumulate ? *o + v : v;
       }
@@ -773,8 +774,8 @@ template <typename F> void with_ncm(int n, F f) {
 }  // namespace
 
 template <typename T>
-void spread(Handle &h, const double *x, const double *q, int qstride,
-            const CompSet &cs, T *grids) {
+void spread(Handle &h, const double *x, const double *q, Layout lq, const CompSet &cs,
+            T *grids) {
   const GridGeom g = geom(h);
   if (h.stile) {
     ProfScope ps(h, PK_SPREAD, (double)cs.n * h.ngrid * sizeof(T) + (double)h.n * (3 + cs.n) * 8);
@@ -786,10 +787,10 @@ void spread(Handle &h, const double *x, const double *q, int qstride,
       constexpr int M = decltype(ncm)::value;
       if (h.stile == 4)
         hipLaunchKernelGGL((spread_list_kernel<T, 4, M>), dim3(tiles), dim3(64), 0, h.stream,
-                           q, qstride, cs, g, nb, ts, rec, grids, h.ngrid);
+                           q, lq, cs, g, nb, ts, rec, grids, h.ngrid);
       else if (h.stile == 8)
         hipLaunchKernelGGL((spread_list_kernel<T, 8, M>), dim3(tiles), dim3(256), 0, h.stream,
-                           q, qstride, cs, g, nb, ts, rec, grids, h.ngrid);
+                           q, lq, cs, g, nb, ts, rec, grids, h.ngrid);
       else
         throw Error{PSE_ERR_INVALID, "unsupported spreading tile"};
     });
@@ -799,14 +800,14 @@ void spread(Handle &h, const double *x, const double *q, int qstride,
   zero_grids<T>(h, grids, cs.n);
   ProfScope ps(h, PK_SPREAD, (double)cs.n * h.ngrid * sizeof(T) + (double)h.n * (3 + cs.n) * 8);
   hipLaunchKernelGGL(spread_kernel<T>, dim3(nblocks(h.n, 4)), dim3(256), 0,
-                     h.stream, x, q, qstride, cs, g, (const int *)h.cells.perm, h.n,
+                     h.stream, x, q, lq, cs, g, (const int *)h.cells.perm, h.n,
                      grids, h.ngrid);
   PSE_LAUNCH_CHECK();
 }
 
 template <typename T>
-void interpolate(Handle &h, const double *x, const T *grids, const CompSet &cs,
-                 double *out, int ostride, bool accumulate, double scale) {
+void interpolate(Handle &h, const double *x, const T *grids, const CompSet &cs, double *out,
+                 Layout lo, bool accumulate, double scale) {
   const GridGeom g = geom(h);
   const int acc = accumulate ? 1 : 0;
   ProfScope ps(h, PK_INTERP, (double)cs.n * h.ngrid * sizeof(T) + (double)h.n * (3 + cs.n) * 8);
@@ -815,19 +816,19 @@ void interpolate(Handle &h, const double *x, const T *grids, const CompSet &cs,
   const int *order = (const int *)h.cells.perm;
   if (P3 <= 128)
     hipLaunchKernelGGL((interp_kernel<T, 2>), grid, block, 0, h.stream, x, grids, h.ngrid, cs, g,
-                       order, h.n, out, ostride, acc, scale);
+                       order, h.n, out, lo, acc, scale);
   else if (P3 <= 256)
     hipLaunchKernelGGL((interp_kernel<T, 4>), grid, block, 0, h.stream, x, grids, h.ngrid, cs, g,
-                       order, h.n, out, ostride, acc, scale);
+                       order, h.n, out, lo, acc, scale);
   else if (P3 <= 384)
     hipLaunchKernelGGL((interp_kernel<T, 6>), grid, block, 0, h.stream, x, grids, h.ngrid, cs, g,
-                       order, h.n, out, ostride, acc, scale);
+                       order, h.n, out, lo, acc, scale);
   else if (P3 <= 512)
     hipLaunchKernelGGL((interp_kernel<T, 8>), grid, block, 0, h.stream, x, grids, h.ngrid, cs, g,
-                       order, h.n, out, ostride, acc, scale);
+                       order, h.n, out, lo, acc, scale);
   else
     hipLaunchKernelGGL((interp_kernel<T, 0>), grid, block, 0, h.stream, x, grids, h.ngrid, cs, g,
-                       order, h.n, out, ostride, acc, scale);
+                       order, h.n, out, lo, acc, scale);
   PSE_LAUNCH_CHECK();
 }
 
@@ -897,10 +898,10 @@ template <typename T> void to_double(Handle &h, const T *src, size_t n, double *
 }
 
 #define INST(T)                                                                 \
-  template void spread<T>(Handle &, const double *, const double *, int,         \
+  template void spread<T>(Handle &, const double *, const double *, Layout,      \
                           const CompSet &, T *);                                 \
   template void interpolate<T>(Handle &, const double *, const T *,              \
-                               const CompSet &, double *, int, bool, double);    \
+                               const CompSet &, double *, Layout, bool, double); \
   template void kspace_noise<T>(Handle &, const double *, uint64_t, uint64_t,    \
                                 cplx<T> *, const CompSet &);                     \
   template void kspace_fused<T>(Handle &, const cplx<T> *, const CompSet &,      \

@@ -71,6 +71,18 @@ __global__ void sub_multi_kernel(double *__restrict__ w, const double *__restric
   w[i] -= acc;
 }
 
+// w = (w - sum_{j<m} coef_j V_j) / s with s a device scalar (0 if s <= 0)
+__global__ void sub_scale_kernel(double *__restrict__ w, const double *__restrict__ V,
+                                 size_t ldv, int m, const double *__restrict__ coef,
+                                 const double *__restrict__ s, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double acc = 0.0;
+  for (int j = 0; j < m; ++j) acc += coef[j] * V[(size_t)j * ldv + i];
+  const double f = s[0] > 0.0 ? 1.0 / s[0] : 0.0;
+  w[i] = (w[i] - acc) * f;
+}
+
 // y = (acc ? y : 0) + alpha sum_j coef_j V_j
 __global__ void gemv_small_kernel(const double *__restrict__ V, size_t ldv, int m,
                                   const double *__restrict__ coef, double *__restrict__ y,
@@ -282,13 +294,36 @@ __global__ void lanczos_sqrt_kernel(const double *alpha, const double *beta, int
   out_change[0] = den > 0.0 ? sqrt(num / den) : 0.0;
 }
 
-// GMRES: apply the previous Givens rotations to Hessenberg column j, form the
-// new rotation and update g; out[0] = |g_{j+1}|.
-// H is column-major with leading dimension ldh; cs/sn/g have length >= j+2.
-__global__ void givens_kernel(double *H, int ldh, int j, double *cs, double *sn, double *g,
-                              double *out) {
+// y = R^{-1} g for the k x k upper-triangular part of H.
+__global__ void backsub_kernel(const double *H, int ldh, int k, const double *g, double *y) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  for (int i = k - 1; i >= 0; --i) {
+    double s = g[i];
+    for (int j = i + 1; j < k; ++j) s -= H[(size_t)j * ldh + i] * y[j];
+    y[i] = s / H[(size_t)i * ldh + i];
+  }
+}
+
+// Hessenberg column j entries 0..j from h1 + h2 (two Gram-Schmidt passes),
+// entry j+1 = sqrt(norm2).  Also sets g[0] = beta when j == 0 is requested.
+// GMRES column j from the two Gram-Schmidt passes: H[i][j] = h1[i] + h2[i]
+// (i <= j); h2[j+1] holds w.w after the first pass, so the norm of the
+// twice-orthogonalised w is sqrt(w.w - |h2|^2) (V orthonormal).  Then the
+// previous Givens rotations are applied to the column, the new one is
+// formed and g updated; vnorm = H[j+1][j], resid = |g_{j+1}|.
+__global__ void hess_givens_kernel(double *H, int ldh, int j, const double *h1,
+                                   const double *h2, double *cs, double *sn, double *g,
+                                   double *vnorm, double *resid) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   double *col = H + (size_t)j * ldh;
+  double p2 = 0.0;
+  for (int i = 0; i <= j; ++i) {
+    col[i] = h1[i] + h2[i];
+    p2 += h2[i] * h2[i];
+  }
+  const double nn = sqrt(fmax(h2[j + 1] - p2, 0.0));
+  col[j + 1] = nn;
+  vnorm[0] = nn;
   for (int i = 0; i < j; ++i) {
     const double t = cs[i] * col[i] + sn[i] * col[i + 1];
     col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
@@ -303,29 +338,7 @@ __global__ void givens_kernel(double *H, int ldh, int j, double *cs, double *sn,
   col[j + 1] = 0.0;
   g[j + 1] = -s * g[j];
   g[j] = c * g[j];
-  out[0] = fabs(g[j + 1]);
-}
-
-// y = R^{-1} g for the k x k upper-triangular part of H.
-__global__ void backsub_kernel(const double *H, int ldh, int k, const double *g, double *y) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  for (int i = k - 1; i >= 0; --i) {
-    double s = g[i];
-    for (int j = i + 1; j < k; ++j) s -= H[(size_t)j * ldh + i] * y[j];
-    y[i] = s / H[(size_t)i * ldh + i];
-  }
-}
-
-// Hessenberg column j entries 0..j from h1 + h2 (two Gram-Schmidt passes),
-// entry j+1 = sqrt(norm2).  Also sets g[0] = beta when j == 0 is requested.
-__global__ void hess_fill_kernel(double *H, int ldh, int j, const double *h1,
-                                 const double *h2, const double *norm2, double *vnorm) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  double *col = H + (size_t)j * ldh;
-  for (int i = 0; i <= j; ++i) col[i] = h1[i] + h2[i];
-  const double nn = sqrt(fmax(norm2[0], 0.0));
-  col[j + 1] = nn;
-  vnorm[0] = nn;
+  resid[0] = fabs(g[j + 1]);
 }
 
 __global__ void sqrt_kernel(const double *in, double *out) {
@@ -340,35 +353,51 @@ __global__ void set_g0_kernel(double *g, int len, const double *beta) {
 }
 
 // Lanczos tridiagonal entries from the two Gram-Schmidt passes:
-// alpha_j = h1[j] + h2[j], beta_j = sqrt(norm2).
+// alpha_j = h1[j] + h2[j]; h2[j+1] holds w.w after the first pass, so
+// beta_j = sqrt(w.w - |h2|^2) is the norm of the twice-orthogonalised w.
 __global__ void lanczos_fill_kernel(double *alpha, double *beta, int j, const double *h1,
-                                    const double *h2, const double *norm2, double *vnorm) {
+                                    const double *h2, double *vnorm) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   alpha[j] = h1[j] + h2[j];
-  const double nn = sqrt(fmax(norm2[0], 0.0));
+  double p2 = 0.0;
+  for (int i = 0; i <= j; ++i) p2 += h2[i] * h2[i];
+  const double nn = sqrt(fmax(h2[j + 1] - p2, 0.0));
   beta[j] = nn;
   vnorm[0] = nn;
 }
 
 // ---------------------------------------------------- host algorithms --
 
+// Reads n Krylov scalars; any non-finite one is reported as an error (a
+// non-finite input vector or operator result).
 static void host_read(Handle &h, const double *dev, double *host, int n) {
   PSE_HIP(hipMemcpyAsync(host, dev, n * sizeof(double), hipMemcpyDeviceToHost, h.stream));
   PSE_HIP(hipStreamSynchronize(h.stream));
+  for (int i = 0; i < n; ++i)
+    if (!std::isfinite(host[i])) throw Error{PSE_ERR_NONFINITE, "non-finite Krylov scalar"};
 }
 
 static void norm2_dev(Handle &h, const double *v, size_t n, double *dev_norm2) {
   multi_dot(h, v, n, 1, v, n, dev_norm2);
 }
 
-// Two-pass classical Gram-Schmidt of w against V[0..m-1] (leading dim n);
-// h1, h2 receive the projection coefficients of the two passes.
-static void cgs2(Handle &h, const double *V, size_t n, int m, double *w, double *h1,
-                 double *h2) {
+// Two-pass classical Gram-Schmidt of w = V[m] against V[0..m-1] (leading dim
+// n): h1 = V^T w, w -= V h1; then h2[0..m] = [V, w]^T w (h2[m] = w.w).  The
+// second subtraction is fused with the normalisation (sub_scale) once the
+// norm is known on the device.
+static void cgs2_pass(Handle &h, const double *V, size_t n, int m, double *w, double *h1,
+                      double *h2) {
   multi_dot(h, V, n, m, w, n, h1);
   vsub_multi(h, w, V, n, m, h1, n);
-  multi_dot(h, V, n, m, w, n, h2);
-  vsub_multi(h, w, V, n, m, h2, n);
+  multi_dot(h, V, n, m + 1, w, n, h2);
+}
+
+static void sub_scale(Handle &h, double *w, const double *V, size_t n, int m,
+                      const double *coef, const double *s) {
+  ProfScope ps(h, PK_KRYLOV, (double)(m + 2) * n * 8);
+  hipLaunchKernelGGL(sub_scale_kernel, dim3(nblocks(n, 256)), dim3(256), 0, h.stream, w, V, n,
+                     m, coef, s, n);
+  PSE_LAUNCH_CHECK();
 }
 
 // Lanczos approximation of y = A^(1/2) b (Chow & Saad): full
@@ -404,11 +433,11 @@ KrylovResult lanczos_sqrt(Handle &h, const Op &A, const double *b, size_t n, dou
   for (int j = 0; j < M; ++j) {
     double *w = V + (size_t)(j + 1) * n;
     A(V + (size_t)j * n, w);
-    cgs2(h, V, n, j + 1, w, h1, h2);
-    norm2_dev(h, w, n, norm2);
+    cgs2_pass(h, V, n, j + 1, w, h1, h2);
     hipLaunchKernelGGL(lanczos_fill_kernel, dim3(1), dim3(1), 0, h.stream, alpha, beta, j,
-                       h1, h2, norm2, vnorm);
+                       h1, h2, vnorm);
     PSE_LAUNCH_CHECK();
+    sub_scale(h, w, V, n, j + 1, h2, vnorm);
     {
       // LDS holds d, e and the (j+1)^2 eigenvectors when they fit in 48 KiB
       const int mm = j + 1;
@@ -429,7 +458,6 @@ KrylovResult lanczos_sqrt(Handle &h, const Op &A, const double *b, size_t n, dou
       res.converged = true;
       break;
     }
-    vscale_dev(h, w, w, vnorm, true, n);
   }
   gemv_small(h, V, n, m, coef, y, n, 1.0, false);
   return res;
@@ -491,14 +519,11 @@ KrylovResult gmres(Handle &h, const Op &A, const double *b, size_t n, double *x,
     for (int j = 0; j < R && total < maxit; ++j) {
       double *w = V + (size_t)(j + 1) * n;
       A(V + (size_t)j * n, w);
-      cgs2(h, V, n, j + 1, w, h1, h2);
-      norm2_dev(h, w, n, norm2);
-      hipLaunchKernelGGL(hess_fill_kernel, dim3(1), dim3(1), 0, h.stream, H, ldh, j, h1,
-                         h2, norm2, vnorm);
+      cgs2_pass(h, V, n, j + 1, w, h1, h2);
+      hipLaunchKernelGGL(hess_givens_kernel, dim3(1), dim3(1), 0, h.stream, H, ldh, j, h1, h2,
+                         cs, sn, g, vnorm, resid);
       PSE_LAUNCH_CHECK();
-      hipLaunchKernelGGL(givens_kernel, dim3(1), dim3(1), 0, h.stream, H, ldh, j, cs, sn, g,
-                         resid);
-      PSE_LAUNCH_CHECK();
+      sub_scale(h, w, V, n, j + 1, h2, vnorm);
       double hr[3];   // vnorm, bn, resid are adjacent
       host_read(h, vnorm, hr, 3);
       const double vn = hr[0];
@@ -506,7 +531,6 @@ KrylovResult gmres(Handle &h, const Op &A, const double *b, size_t n, double *x,
       k = j + 1;
       rel = hr[2] / bnorm;
       if (rel < tol || vn <= 1e-15 * bnorm) break;
-      vscale_dev(h, w, w, vnorm, true, n);
     }
     hipLaunchKernelGGL(backsub_kernel, dim3(1), dim3(1), 0, h.stream, H, ldh, k, g, ycoef);
     PSE_LAUNCH_CHECK();

@@ -39,6 +39,15 @@ template <> struct cplx_t<float> { using type = float2; };
 template <typename T> using cplx = typename cplx_t<T>::type;
 
 // Which 11-vector components an operator reads and writes.
+// Where particle vector components live: component c of particle p is at
+// ptr[p * stride + c - off] (the full 11-component layout is {NC, 0}; the
+// 5-component stresslet / strain vectors of the constraint solve are {5, 6}).
+struct Layout {
+  int stride;
+  int off;
+};
+constexpr Layout FULL_LAYOUT{NC, 0};
+
 struct CompSet {
   int n;          // number of components
   int idx[NC];    // component indices into the 11-vector
@@ -128,6 +137,7 @@ struct Handle {
   double *es_b = nullptr, *es_x = nullptr, *es_r = nullptr, *es_d = nullptr;  // N x 5
 
   double *ktab = nullptr;    // per-|k|^2 radial factors (4 doubles per entry)
+  int *bad_pos = nullptr;    // set by the wrap kernel on a non-finite coordinate
   // real-space pair list (CSR in cell order): start[N+1], neighbour index and
   // 10 doubles of pair data per entry; counts and scan scratch
   int *pl_cnt = nullptr, *pl_start = nullptr, *pl_scan = nullptr, *pl_nbr = nullptr;
@@ -198,11 +208,11 @@ void rfft_z(Handle &h, T *grids, const cplx<T> *twiddle, int ncomp, int dir);
 // Real grids [c][z][y][x] (T), half spectra [c][kz][ky][kx < n/2] (cplx<T>)
 // in the same storage; component stride ngrid reals = ngrid/2 complex.
 template <typename T>
-void spread(Handle &h, const double *x, const double *q, int qstride,
-            const CompSet &cs, T *grids);
+void spread(Handle &h, const double *x, const double *q, Layout lq, const CompSet &cs,
+            T *grids);
 template <typename T>
-void interpolate(Handle &h, const double *x, const T *grids, const CompSet &cs,
-                 double *out, int ostride, bool accumulate, double scale);
+void interpolate(Handle &h, const double *x, const T *grids, const CompSet &cs, double *out,
+                 Layout lo, bool accumulate, double scale);
 template <typename T>
 void kspace_noise(Handle &h, const double *psi, uint64_t seed, uint64_t counter,
                   cplx<T> *out, const CompSet &cout);
@@ -297,8 +307,8 @@ void build_tables(Handle &h);
 void exclusive_scan(Handle &h, const int *in, int *out, int *tmp, int n);
 void build_cells(Handle &h, const double *xw);   // both bin lists
 template <typename T>
-void real_apply(Handle &h, const double *x, const double *in,
-                const CompSet &cin, double *out, const CompSet &cout,
+void real_apply(Handle &h, const double *x, const double *in, Layout lin,
+                const CompSet &cin, double *out, Layout lout, const CompSet &cout,
                 bool accumulate);
 void wrap_positions(Handle &h, const double *x, double *xw);
 

@@ -165,11 +165,17 @@ void build_tables(Handle &h) {
 
 // ---------------------------------------------------------- positions --
 
+// Non-finite coordinates raise *bad and are replaced by 0, so that every
+// later kernel stays in bounds until the host reports the error.
 __global__ void wrap_kernel(const double *__restrict__ x, double *__restrict__ xw,
-                            int64_t n3, double L) {
+                            int64_t n3, double L, int *__restrict__ bad) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n3) return;
   double v = x[i];
+  if (!isfinite(v)) {
+    *bad = 1;
+    v = 0.0;
+  }
   v -= L * floor(v / L);
   if (v >= L) v -= L;
   if (v < 0) v = 0;
@@ -177,8 +183,9 @@ __global__ void wrap_kernel(const double *__restrict__ x, double *__restrict__ x
 }
 
 void wrap_positions(Handle &h, const double *x, double *xw) {
+  PSE_HIP(hipMemsetAsync(h.bad_pos, 0, sizeof(int), h.stream));
   hipLaunchKernelGGL(wrap_kernel, dim3(nblocks(3 * h.n, 256)), dim3(256), 0,
-                     h.stream, x, xw, 3 * h.n, h.p.box);
+                     h.stream, x, xw, 3 * h.n, h.p.box, h.bad_pos);
   PSE_LAUNCH_CHECK();
 }
 
@@ -371,23 +378,28 @@ __device__ __forceinline__ void pair_action(const T *co, const T *e, const T *F,
   }
 }
 
+// Moments of one particle; v points at its vector in layout lo (component c
+// at v[c - lo.off]), only the components selected by mask are read.
 template <typename T>
-__device__ __forceinline__ void load_moments(const double *__restrict__ v, int mask,
+__device__ __forceinline__ void load_moments(const double *__restrict__ v0, int off, int mask,
                                              T *F, T (*C)[3]) {
+  auto v = [&](int c) { return v0[c - off]; };
   const T r2 = (T)0.70710678118654752440, r6 = (T)0.40824829046386301637;
   for (int i = 0; i < 3; ++i) {
-    F[i] = (mask & 1) ? (T)v[i] : (T)0;
+    F[i] = (T)0;
     for (int j = 0; j < 3; ++j) C[i][j] = (T)0;
   }
+  if (mask & 1)
+    for (int i = 0; i < 3; ++i) F[i] = (T)v(i);
   if (mask & 2) {
     // C^A_mn = -1/2 eps_mnk L_k
-    const T Lx = (T)v[3], Ly = (T)v[4], Lz = (T)v[5];
+    const T Lx = (T)v(3), Ly = (T)v(4), Lz = (T)v(5);
     C[0][1] -= (T)0.5 * Lz; C[1][0] += (T)0.5 * Lz;
     C[0][2] += (T)0.5 * Ly; C[2][0] -= (T)0.5 * Ly;
     C[1][2] -= (T)0.5 * Lx; C[2][1] += (T)0.5 * Lx;
   }
   if (mask & 4) {
-    const T s1 = (T)v[6], s2 = (T)v[7], s3 = (T)v[8], s4 = (T)v[9], s5 = (T)v[10];
+    const T s1 = (T)v(6), s2 = (T)v(7), s3 = (T)v(8), s4 = (T)v(9), s5 = (T)v(10);
     C[0][1] += r2 * s1; C[1][0] += r2 * s1;
     C[0][2] += r2 * s2; C[2][0] += r2 * s2;
     C[1][2] += r2 * s3; C[2][1] += r2 * s3;
@@ -501,6 +513,7 @@ struct RealArgs {
   int in_mask;    // 1: F, 2: L, 4: S
   int out_mask;   // 1: U, 2: Omega, 4: E
   int accumulate;
+  Layout lin, lout;
 };
 
 // M_r applied from the pair list: the self block (r = 0: only the isotropic
@@ -524,7 +537,7 @@ real_pair_kernel(const double *__restrict__ in, double *__restrict__ out,
     T co[NCOEF];
     for (int j = 0; j < NCOEF; ++j) co[j] = tab[j];
     const T e0[3] = {0, 0, 0};
-    load_moments<T>(in + (size_t)i * NC, ra.in_mask, F, C);
+    load_moments<T>(in + (size_t)i * ra.lin.stride, ra.lin.off, ra.in_mask, F, C);
     pair_action<T>(co, e0, F, C, useF, useC, U, D);
   }
   const int s1 = start[t + 1];
@@ -536,7 +549,7 @@ real_pair_kernel(const double *__restrict__ in, double *__restrict__ out,
     for (int k = 0; k < NCOEF; ++k) co[k] = (T)r[k];
 #pragma unroll
     for (int k = 0; k < 3; ++k) e[k] = (T)r[NCOEF + k];
-    load_moments<T>(in + (size_t)j * NC, ra.in_mask, F, C);
+    load_moments<T>(in + (size_t)j * ra.lin.stride, ra.lin.off, ra.in_mask, F, C);
     pair_action<T>(co, e, F, C, useF, useC, U, D);
   }
 #pragma unroll
@@ -546,23 +559,25 @@ real_pair_kernel(const double *__restrict__ in, double *__restrict__ out,
 #pragma unroll
     for (int b = 0; b < 3; ++b) D[a][b] = group_sum(D[a][b]);
   if (lane != 0) return;
-  double *o = out + (size_t)i * NC;
+  // component c of the output at out[row + c - off]
+  const size_t row = (size_t)i * ra.lout.stride;
+  auto O = [&](int c) -> double & { return out[row + c - ra.lout.off]; };
   const double r2 = 0.70710678118654752440, r6 = 0.40824829046386301637;
   if (ra.out_mask & 1) {
-    for (int k = 0; k < 3; ++k) o[k] = (ra.accumulate ? o[k] : 0.0) + (double)U[k];
+    for (int k = 0; k < 3; ++k) O(k) = (ra.accumulate ? O(k) : 0.0) + (double)U[k];
   }
   if (ra.out_mask & 2) {
     // Omega = -1/2 eps : D
     const double om[3] = {-0.5 * ((double)D[1][2] - D[2][1]),
                           -0.5 * ((double)D[2][0] - D[0][2]),
                           -0.5 * ((double)D[0][1] - D[1][0])};
-    for (int k = 0; k < 3; ++k) o[3 + k] = (ra.accumulate ? o[3 + k] : 0.0) + om[k];
+    for (int k = 0; k < 3; ++k) O(3 + k) = (ra.accumulate ? O(3 + k) : 0.0) + om[k];
   }
   if (ra.out_mask & 4) {
     const double e5[5] = {r2 * ((double)D[0][1] + D[1][0]), r2 * ((double)D[0][2] + D[2][0]),
                           r2 * ((double)D[1][2] + D[2][1]), r2 * ((double)D[0][0] - D[1][1]),
                           r6 * ((double)D[0][0] + D[1][1] - 2.0 * D[2][2])};
-    for (int k = 0; k < 5; ++k) o[6 + k] = (ra.accumulate ? o[6 + k] : 0.0) + e5[k];
+    for (int k = 0; k < 5; ++k) O(6 + k) = (ra.accumulate ? O(6 + k) : 0.0) + e5[k];
   }
 }
 
@@ -584,10 +599,12 @@ static void build_pair_list(Handle &h, const double *xw) {
   PSE_LAUNCH_CHECK();
   const int n = (int)h.n;
   exclusive_scan(h, h.pl_cnt, h.pl_start, h.pl_scan, n);
-  int total = 0;
+  int total = 0, bad = 0;
   PSE_HIP(hipMemcpyAsync(&total, h.pl_start + n, sizeof(int), hipMemcpyDeviceToHost,
                          h.stream));
+  PSE_HIP(hipMemcpyAsync(&bad, h.bad_pos, sizeof(int), hipMemcpyDeviceToHost, h.stream));
   PSE_HIP(hipStreamSynchronize(h.stream));
+  if (bad) throw Error{PSE_ERR_NONFINITE, "non-finite particle position"};
   if ((size_t)total > h.pl_cap) {
     const size_t cap = (size_t)total + total / 4 + 1024;
     PSE_HIP(hipFree(h.pl_nbr));
@@ -630,11 +647,13 @@ static int mask_of(const CompSet &cs, bool input) {
 }
 
 template <typename T>
-void real_apply(Handle &h, const double *xw, const double *in, const CompSet &cin,
-                double *out, const CompSet &cout, bool accumulate) {
+void real_apply(Handle &h, const double *xw, const double *in, Layout lin, const CompSet &cin,
+                double *out, Layout lout, const CompSet &cout, bool accumulate) {
   (void)xw;
   RealArgs ra;
   ra.n = h.n;
+  ra.lin = lin;
+  ra.lout = lout;
   ra.in_mask = mask_of(cin, true);
   ra.out_mask = mask_of(cout, false);
   ra.accumulate = accumulate ? 1 : 0;
@@ -647,9 +666,9 @@ void real_apply(Handle &h, const double *xw, const double *in, const CompSet &ci
   PSE_LAUNCH_CHECK();
 }
 
-template void real_apply<double>(Handle &, const double *, const double *,
-                                 const CompSet &, double *, const CompSet &, bool);
-template void real_apply<float>(Handle &, const double *, const double *,
-                                const CompSet &, double *, const CompSet &, bool);
+template void real_apply<double>(Handle &, const double *, const double *, Layout,
+                                 const CompSet &, double *, Layout, const CompSet &, bool);
+template void real_apply<float>(Handle &, const double *, const double *, Layout,
+                                const CompSet &, double *, Layout, const CompSet &, bool);
 
 }  // namespace pse
