@@ -65,17 +65,31 @@ def run_form(w, precision, steps, warmup, seed, prof_steps=2):
                              eta_s=d.eta_s), finite=bool(torch.isfinite(x).all()))
 
 
-def roofline(prof):
+STAGE_KERNELS = {
+    'fft': 'fft_xy_plane_kernel (x-y transform of one z-plane, both directions)',
+    'kspace': 'kspace_fused_kernel (z transform, k-space kernel, inverse z transform)',
+    'spread': 'spread_list_kernel', 'interp': 'interp_kernel', 'real': 'real_pair_kernel',
+}
+
+
+def roofline(prof, traffic_file=None):
+    """The stage with the largest total time: algorithmic bytes per launch over
+    the average event-timed launch duration, against the HBM peak; traffic is
+    the HBM bytes per launch from the committed counter summary, if it was
+    taken on the current sources (else null)."""
+    from paper_1709_06946_amd import profsum
     dom = max(prof, key=lambda k: prof[k]['total_ms'])
     p = prof[dom]
     per_launch_bytes = p['alg_bytes'] / p['launches']
     per_launch_s = p['total_ms'] / p['launches'] / 1e3
     achieved = per_launch_bytes / per_launch_s / 1e9
+    traffic = profsum.recorded_traffic(dom, traffic_file) if traffic_file else None
     return dom, dict(bound='hbm', achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit='GB/s',
-                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
-                     kernel=dom, launches=p['launches'],
+                     frac=round(achieved / HBM_PEAK_GBS, 4),
+                     traffic=None if traffic is None else round(traffic),
+                     kernel=STAGE_KERNELS.get(dom, dom), stage=dom, launches=p['launches'],
                      avg_us=round(1e6 * per_launch_s, 2),
-                     alg_bytes_per_launch=per_launch_bytes)
+                     alg_bytes_per_launch=round(per_launch_bytes))
 
 
 def cpu_baseline():
@@ -211,7 +225,8 @@ def main():
     w = inputs.workload(args.workload)
     seed = w['seed']
     fp64 = run_form(w, pse.PSE_FP64, args.steps, args.warmup, seed)
-    dom, roof = roofline(fp64['prof'])
+    traffic_file = os.path.join(ROOT, 'profiles', f'hbm_traffic_{args.workload}_fp64.md')
+    dom, roof = roofline(fp64['prof'], traffic_file)
     mixed = None
     if not args.no_mixed:
         m = run_form(w, pse.PSE_MIXED, args.steps, args.warmup, seed)

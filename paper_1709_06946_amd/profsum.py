@@ -64,6 +64,31 @@ def counters(d):
     return {k: {c: (e[0], e[1] / e[0]) for c, e in cs.items()} for k, cs in acc.items()}
 
 
+_TRAFFIC = re.compile(r'<!-- traffic stage=(\w+) bytes_per_launch=(\d+) sources=([^ ]+) -->')
+
+
+def recorded_traffic(stage, profile_file):
+    """HBM bytes per launch of `stage` recorded in a committed traffic summary,
+    or None when the file is missing or any kernel source it names has changed
+    since the counters were taken (sources are hashed with sha256)."""
+    import hashlib
+    if not os.path.exists(profile_file):
+        return None
+    csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), 'csrc')
+    for m in _TRAFFIC.finditer(open(profile_file).read()):
+        if m.group(1) != stage:
+            continue
+        for item in m.group(3).split(','):
+            name, digest = item.split(':')
+            path = os.path.join(csrc, name)
+            if not os.path.exists(path):
+                return None
+            if hashlib.sha256(open(path, 'rb').read()).hexdigest()[:len(digest)] != digest:
+                return None
+        return float(m.group(2))
+    return None
+
+
 def main(argv):
     if len(argv) != 3 or argv[1] not in ('stats', 'pmc'):
         print(__doc__)
