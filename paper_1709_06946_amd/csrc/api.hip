@@ -298,6 +298,7 @@ static void create(const pse_params &p, Handle &h) {
   }
   build_tables(h);
   alloc((void **)&h.ktab, (size_t)ktable_len(ng) * 4 * sizeof(double));
+  if (h.mixed) alloc((void **)&h.ktab32, (size_t)ktable_len(ng) * 4 * sizeof(float));
   alloc((void **)&h.bad_pos, 64);
   build_ktable(h);
   if (h.stile) {
@@ -348,7 +349,7 @@ static void release(Handle &h) {
                   h.xw, h.xh, h.v0, h.v1, h.v2, h.v3, h.v4, h.v5, h.es_b, h.es_x, h.es_r,
                   h.es_d, h.lz_V, h.gm_V, h.small, h.dots, h.ktab, h.pl_cnt,
                   h.pl_start, h.pl_scan, h.pl_nbr, h.pl_rec, h.tl_cnt, h.tl_start,
-                  h.tl_scan, h.tl_rec, h.bad_pos};
+                  h.tl_scan, h.tl_rec, h.bad_pos, h.ktab32};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   for (hipEvent_t e : h.prof.pool) (void)hipEventDestroy(e);

@@ -338,6 +338,12 @@ __device__ __forceinline__ void shape_factors(double x, double &j0, double &f1) 
   }
 }
 
+// k-table entry type per precision: double4 for the FP64 kernels, float4
+// (the same values rounded) for the FP32 ones.
+template <typename T> struct TabT;
+template <> struct TabT<double> { using type = double4; };
+template <> struct TabT<float> { using type = float4; };
+
 struct KGeom {
   int ng;
   double twopi_L;     // 2 pi / L
@@ -377,12 +383,13 @@ ktable_kernel(KGeom kg, int len, double4 *__restrict__ tab) {
 // contribution to rho is coef * col * g with coef real for F (j0) and
 // imaginary for L and s:
 //   F_c:  j0 e_c;   L_l: (3i/2) f1 (k x e_l);   s_q: -3i f1 Y_q k.
-__device__ __forceinline__ void p_column(int c, double kx, double ky, double kz,
-                                         double j0, double f1, bool &imag,
-                                         double &cx, double &cy, double &cz) {
-  const double r2 = 0.70710678118654752440, r6 = 0.40824829046386301637;
+// R is the arithmetic type (double, or float in the FP32 kernels).
+template <typename R>
+__device__ __forceinline__ void p_column(int c, R kx, R ky, R kz, R j0, R f1, bool &imag,
+                                         R &cx, R &cy, R &cz) {
+  const R r2 = (R)0.70710678118654752440, r6 = (R)0.40824829046386301637;
   imag = c >= 3;
-  const double a = 1.5 * f1, b = -3.0 * f1;
+  const R a = (R)1.5 * f1, b = (R)-3.0 * f1;
   switch (c) {
     case 0: cx = j0;  cy = 0;   cz = 0;   break;
     case 1: cx = 0;   cy = j0;  cz = 0;   break;
@@ -394,18 +401,17 @@ __device__ __forceinline__ void p_column(int c, double kx, double ky, double kz,
     case 7: cx = b * r2 * kz; cy = 0; cz = b * r2 * kx; break;
     case 8: cx = 0; cy = b * r2 * kz; cz = b * r2 * ky; break;
     case 9: cx = b * r2 * kx; cy = -b * r2 * ky; cz = 0; break;
-    default: cx = b * r6 * kx; cy = b * r6 * ky; cz = -2.0 * b * r6 * kz; break;
+    default: cx = b * r6 * kx; cy = b * r6 * ky; cz = (R)-2.0 * b * r6 * kz; break;
   }
 }
 
 // rho += P_c(k) g
-template <typename C>
-__device__ __forceinline__ void add_P(int c, C gv, const double *kv, double j0, double f1,
-                                      C *rho) {
+template <typename C, typename R>
+__device__ __forceinline__ void add_P(int c, C gv, const R *kv, R j0, R f1, C *rho) {
   bool imag;
-  double cx, cy, cz;
-  p_column(c, kv[0], kv[1], kv[2], j0, f1, imag, cx, cy, cz);
-  const double gx = gv.x, gy = gv.y;
+  R cx, cy, cz;
+  p_column<R>(c, kv[0], kv[1], kv[2], j0, f1, imag, cx, cy, cz);
+  const R gx = (R)gv.x, gy = (R)gv.y;
   if (!imag) {
     rho[0].x += cx * gx; rho[0].y += cx * gy;
     rho[1].x += cy * gx; rho[1].y += cy * gy;
@@ -419,14 +425,13 @@ __device__ __forceinline__ void add_P(int c, C gv, const double *kv, double j0, 
 }
 
 // W_c = P_c^+ u = conj(coef) col . u
-template <typename C>
-__device__ __forceinline__ C apply_Pdag(int c, const C *u, const double *kv, double j0,
-                                        double f1) {
+template <typename C, typename R>
+__device__ __forceinline__ C apply_Pdag(int c, const C *u, const R *kv, R j0, R f1) {
   bool imag;
-  double cx, cy, cz;
-  p_column(c, kv[0], kv[1], kv[2], j0, f1, imag, cx, cy, cz);
-  const double re = cx * u[0].x + cy * u[1].x + cz * u[2].x;
-  const double im = cx * u[0].y + cy * u[1].y + cz * u[2].y;
+  R cx, cy, cz;
+  p_column<R>(c, kv[0], kv[1], kv[2], j0, f1, imag, cx, cy, cz);
+  const R re = cx * (R)u[0].x + cy * (R)u[1].x + cz * (R)u[2].x;
+  const R im = cx * (R)u[0].y + cy * (R)u[1].y + cz * (R)u[2].y;
   C w;
   if (!imag) {
     w.x = re;
@@ -460,7 +465,7 @@ __device__ __forceinline__ bool zero_mode(int ix, int iy, int iz, int n) {
 template <typename T, int N>
 __global__ void __launch_bounds__(256)
 kspace_fused_kernel(const cplx<T> *__restrict__ in, CompSet cin, cplx<T> *__restrict__ out,
-                    CompSet cout, KGeom kg, const double4 *__restrict__ ktab,
+                    CompSet cout, KGeom kg, const typename TabT<T>::type *__restrict__ ktab,
                     const cplx<T> *__restrict__ tw, int TL) {
   using C = cplx<T>;
   constexpr int E = fused_e(N), M = N / 2;
@@ -475,6 +480,7 @@ kspace_fused_kernel(const cplx<T> *__restrict__ in, CompSet cin, cplx<T> *__rest
   const int ky = kidx(iy, N);
   const size_t hsz = (size_t)M * N * N, plane = (size_t)N * M;
   const size_t base = (size_t)iy * M + ix;
+  const T tp = (T)kg.twopi_L;
   C rho[E][3];
 #pragma unroll
   for (int e = 0; e < E; ++e)
@@ -506,9 +512,9 @@ kspace_fused_kernel(const cplx<T> *__restrict__ in, CompSet cin, cplx<T> *__rest
         const int iz = reg_pos<N, E, RL>(t, b, r);
         if (zero_mode(ix, iy, iz, N)) continue;
         const int kz = kidx(iz, N);
-        const double4 tb = ktab[ix * ix + ky * ky + kz * kz];
-        const double kv[3] = {kg.twopi_L * ix, kg.twopi_L * ky, kg.twopi_L * kz};
-        add_P(c, v[b * RL + r], kv, tb.x, tb.y, rho[b * RL + r]);
+        const auto tb = ktab[ix * ix + ky * ky + kz * kz];
+        const T kv[3] = {tp * ix, tp * ky, tp * kz};
+        add_P<C, T>(c, v[b * RL + r], kv, tb.x, tb.y, rho[b * RL + r]);
       }
   }
   // u = scale (I - k^k^) rho
@@ -525,19 +531,19 @@ kspace_fused_kernel(const cplx<T> *__restrict__ in, CompSet cin, cplx<T> *__rest
         for (int m = 0; m < 3; ++m) rho[e][m] = C{(T)0, (T)0};
         continue;
       }
-      const double scale = ktab[n2].z;
-      const double kv[3] = {(double)ix, (double)ky, (double)kz};
-      const double inv = 1.0 / (double)n2;
-      double krx = 0, kry = 0;
+      const T scale = ktab[n2].z;
+      const T kv[3] = {(T)ix, (T)ky, (T)kz};
+      const T inv = (T)1 / (T)n2;
+      T krx = 0, kry = 0;
 #pragma unroll
       for (int m = 0; m < 3; ++m) {
-        krx += kv[m] * (double)rho[e][m].x;
-        kry += kv[m] * (double)rho[e][m].y;
+        krx += kv[m] * rho[e][m].x;
+        kry += kv[m] * rho[e][m].y;
       }
 #pragma unroll
       for (int m = 0; m < 3; ++m) {
-        rho[e][m].x = (T)(scale * ((double)rho[e][m].x - kv[m] * krx * inv));
-        rho[e][m].y = (T)(scale * ((double)rho[e][m].y - kv[m] * kry * inv));
+        rho[e][m].x = scale * (rho[e][m].x - kv[m] * krx * inv);
+        rho[e][m].y = scale * (rho[e][m].y - kv[m] * kry * inv);
       }
     }
   for (int q = 0; q < cout.n; ++q) {
@@ -553,9 +559,9 @@ kspace_fused_kernel(const cplx<T> *__restrict__ in, CompSet cin, cplx<T> *__rest
           continue;
         }
         const int kz = kidx(iz, N);
-        const double4 tb = ktab[ix * ix + ky * ky + kz * kz];
-        const double kv[3] = {kg.twopi_L * ix, kg.twopi_L * ky, kg.twopi_L * kz};
-        v[e] = apply_Pdag(c, rho[e], kv, tb.x, tb.y);
+        const auto tb = ktab[ix * ix + ky * ky + kz * kz];
+        const T kv[3] = {tp * ix, tp * ky, tp * kz};
+        v[e] = apply_Pdag<C, T>(c, rho[e], kv, tb.x, tb.y);
       }
     reg_fft_inverse<T, N, E>(v, t, lds, TL, line, tw);
     C *dst = out + (size_t)q * hsz + base;
@@ -666,7 +672,7 @@ kspace_noise_kernel(const double2 *__restrict__ psi, uint64_t seed, uint64_t cou
     uu[m].y = tb.w * (ps[m].y - iv[m] * kr.y * inv);
   }
   for (int q = 0; q < cout.n; ++q) {
-    const double2 w = apply_Pdag(cout.idx[q], uu, kv, tb.x, tb.y);
+    const double2 w = apply_Pdag<double2, double>(cout.idx[q], uu, kv, tb.x, tb.y);
     out[q * hsz + tid] = C{(T)w.x, (T)w.y};
   }
 }
@@ -731,11 +737,22 @@ static KGeom kgeom(const Handle &h) {
 
 int ktable_len(int grid) { return 3 * (grid / 2) * (grid / 2) + 1; }
 
+__global__ void __launch_bounds__(256)
+ktable_to_float_kernel(const double4 *__restrict__ src, int len, float4 *__restrict__ dst) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < len) dst[i] = float4{(float)src[i].x, (float)src[i].y, (float)src[i].z, (float)src[i].w};
+}
+
 void build_ktable(Handle &h) {
   const int len = ktable_len(h.d.grid);
   hipLaunchKernelGGL(ktable_kernel, dim3(nblocks(len, 256)), dim3(256), 0, h.stream, kgeom(h),
                      len, (double4 *)h.ktab);
   PSE_LAUNCH_CHECK();
+  if (h.ktab32) {
+    hipLaunchKernelGGL(ktable_to_float_kernel, dim3(nblocks(len, 256)), dim3(256), 0, h.stream,
+                       (const double4 *)h.ktab, len, (float4 *)h.ktab32);
+    PSE_LAUNCH_CHECK();
+  }
 }
 
 // Candidate lists of the spreading tiles for wrapped positions xw (after the
@@ -841,8 +858,10 @@ void launch_fused(Handle &h, const cplx<T> *in, const CompSet &cin, cplx<T> *out
   const int tl = lines_per_block(N, TPL, N * sizeof(cplx<T>), (size_t)N / 2);
   const size_t lds = (size_t)tl * N * sizeof(cplx<T>);
   const unsigned nb = (unsigned)(N * (N / 2 / tl));
+  using Tab = typename TabT<T>::type;
+  const Tab *tab = sizeof(T) == 8 ? (const Tab *)h.ktab : (const Tab *)h.ktab32;
   hipLaunchKernelGGL((kspace_fused_kernel<T, N>), dim3(nb), dim3(tl * TPL), lds, h.stream, in,
-                     cin, out, cout, kgeom(h), (const double4 *)h.ktab, tw, tl);
+                     cin, out, cout, kgeom(h), tab, tw, tl);
   PSE_LAUNCH_CHECK();
 }
 

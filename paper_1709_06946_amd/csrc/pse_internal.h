@@ -137,6 +137,7 @@ struct Handle {
   double *es_b = nullptr, *es_x = nullptr, *es_r = nullptr, *es_d = nullptr;  // N x 5
 
   double *ktab = nullptr;    // per-|k|^2 radial factors (4 doubles per entry)
+  float *ktab32 = nullptr;   // the same rounded to float (mixed handles)
   int *bad_pos = nullptr;    // set by the wrap kernel on a non-finite coordinate
   // real-space pair list (CSR in cell order): start[N+1], neighbour index and
   // 10 doubles of pair data per entry; counts and scan scratch
