@@ -147,11 +147,14 @@ tile_list_kernel(const double *__restrict__ x, GridGeom g, int S, int nb,
 }
 
 // Gather form of the spreading sum: one workgroup per tile of S^3 grid
-// points reads the tile's candidate records; their positions, stencil
-// origins and moments are staged in LDS in chunks and each thread sums the
-// Gaussians over its grid points.  Every grid point is written exactly once:
-// no atomics and no zeroing pass.
-constexpr int GMAXC = 128;
+// points reads the tile's candidate records.  The Gaussian factorises over
+// the axes, K = prod_d knorm exp(-kcoef dx_d^2), so for each staged candidate
+// the 1D weights at the tile's S positions per axis are computed once (zero
+// outside the stencil) and kept in LDS with the candidate's moments; each
+// thread then sums w_x w_y w_z q over the candidates for its grid points,
+// without range tests or exponentials.  Every grid point is written exactly
+// once: no atomics and no zeroing pass.
+constexpr int GMAXC = 64;
 
 template <typename T, int S, int NCM>
 __global__ void __launch_bounds__(S * S * S < 256 ? S * S * S : 256)
@@ -160,60 +163,53 @@ spread_list_kernel(const double *__restrict__ q, Layout lq, CompSet cs, GridGeom
                    T *__restrict__ grids, size_t ngrid) {
   constexpr int NT = S * S * S < 256 ? S * S * S : 256;
   constexpr int PPT = S * S * S / NT;
-  __shared__ double cxs[GMAXC], cys[GMAXC], czs[GMAXC];
-  __shared__ int sxs[GMAXC], sys[GMAXC], szs[GMAXC];
+  __shared__ T wts[3][GMAXC][S];
   __shared__ T cq[NCM][GMAXC];
   const int tile = blockIdx.x;
-  const int tx = tile % nb, ty = (tile / nb) % nb, tz = tile / (nb * nb);
+  const int tc[3] = {tile % nb, (tile / nb) % nb, tile / (nb * nb)};
   const int lo = tstart[tile];
   const int total = tstart[tile + 1] - lo;
   const int P = g.P, ng = g.ng;
-  const double kn3 = g.knorm * g.knorm * g.knorm;
-  int gx[PPT], gy[PPT], gz[PPT];
+  int lx[PPT], ly[PPT], lz[PPT];
   T acc[PPT][NCM];
 #pragma unroll
   for (int pt = 0; pt < PPT; ++pt) {
     const int l = threadIdx.x + pt * NT;
-    gx[pt] = tx * S + l % S;
-    gy[pt] = ty * S + (l / S) % S;
-    gz[pt] = tz * S + l / (S * S);
+    lx[pt] = l % S;
+    ly[pt] = (l / S) % S;
+    lz[pt] = l / (S * S);
 #pragma unroll
     for (int k = 0; k < NCM; ++k) acc[pt][k] = (T)0;
   }
   for (int c0 = 0; c0 < total; c0 += GMAXC) {
+    const int nchunk = min(GMAXC, total - c0);
     __syncthreads();
-    for (int t = threadIdx.x; t < GMAXC; t += NT) {
-      if (c0 + t < total) {
-        const TileRec r = rec[lo + c0 + t];
-        cxs[t] = r.x[0];
-        cys[t] = r.x[1];
-        czs[t] = r.x[2];
-        sxs[t] = r.st[0];
-        sys[t] = r.st[1];
-        szs[t] = r.st[2];
-#pragma unroll
-        for (int k = 0; k < NCM; ++k)
-          if (k < cs.n) cq[k][t] = (T)q[(size_t)r.p * lq.stride + cs.idx[k] - lq.off];
+    // moments of the chunk's candidates
+    for (int t = threadIdx.x; t < nchunk * NCM; t += NT) {
+      const int j = t / NCM, k = t % NCM;
+      if (k < cs.n) {
+        const int p = rec[lo + c0 + j].p;
+        cq[k][j] = (T)q[(size_t)p * lq.stride + cs.idx[k] - lq.off];
       }
     }
+    // 1D weights: candidate j, axis d, tile position i
+    for (int t = threadIdx.x; t < nchunk * 3 * S; t += NT) {
+      const int j = t / (3 * S), d = (t / S) % 3, i = t % S;
+      const TileRec &r = rec[lo + c0 + j];
+      int a = (tc[d] * S + i - r.st[d]) % ng;
+      a += a < 0 ? ng : 0;
+      T w = (T)0;
+      if (a < P) {
+        const double dx = (r.st[d] + a) * g.h - r.x[d];
+        w = (T)(g.knorm * exp(-g.kcoef * dx * dx));
+      }
+      wts[d][j][i] = w;
+    }
     __syncthreads();
-    const int nchunk = min(GMAXC, total - c0);
     for (int j = 0; j < nchunk; ++j) {
 #pragma unroll
       for (int pt = 0; pt < PPT; ++pt) {
-        int ax = gx[pt] - sxs[j];
-        ax += ax < 0 ? ng : (ax >= ng ? -ng : 0);
-        if (ax >= P) continue;
-        int ay = gy[pt] - sys[j];
-        ay += ay < 0 ? ng : (ay >= ng ? -ng : 0);
-        if (ay >= P) continue;
-        int az = gz[pt] - szs[j];
-        az += az < 0 ? ng : (az >= ng ? -ng : 0);
-        if (az >= P) continue;
-        const double dx = (sxs[j] + ax) * g.h - cxs[j];
-        const double dy = (sys[j] + ay) * g.h - cys[j];
-        const double dz = (szs[j] + az) * g.h - czs[j];
-        const T w = (T)(kn3 * exp(-g.kcoef * (dx * dx + dy * dy + dz * dz)));
+        const T w = wts[0][j][lx[pt]] * wts[1][j][ly[pt]] * wts[2][j][lz[pt]];
 #pragma unroll
         for (int k = 0; k < NCM; ++k)
           if (k < cs.n) acc[pt][k] += w * cq[k][j];
@@ -222,7 +218,8 @@ spread_list_kernel(const double *__restrict__ q, Layout lq, CompSet cs, GridGeom
   }
 #pragma unroll
   for (int pt = 0; pt < PPT; ++pt) {
-    const size_t gi = ((size_t)gz[pt] * ng + gy[pt]) * ng + gx[pt];
+    const size_t gi = ((size_t)(tc[2] * S + lz[pt]) * ng + tc[1] * S + ly[pt]) * ng
+                      + tc[0] * S + lx[pt];
 #pragma unroll
     for (int k = 0; k < NCM; ++k)
       if (k < cs.n) grids[(size_t)k * ngrid + gi] = acc[pt][k];
