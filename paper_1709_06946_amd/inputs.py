@@ -150,9 +150,34 @@ def relaxed_packing(N, phi, a=1.0, seed=SEED_BASE, margin=1e-3,
     raise RuntimeError('overlap relaxation did not converge')
 
 
+LATTICE_N = 200_000   # from this size on, packings are jittered lattices
+
+
+def jittered_lattice(N, phi, a=1.0, seed=SEED_BASE):
+    """Non-overlapping spheres for very large N: N distinct random sites of
+    the m^3 cubic lattice (m = ceil(N^(1/3))) of the box, each displaced
+    uniformly by at most half the gap (spacing - 2a) per axis, so that no
+    two spheres overlap; the volume fraction is exactly phi.  Needs a lattice
+    spacing above 2a (phi below about 0.47)."""
+    L = box_length(N, phi, a)
+    m = int(np.ceil(N ** (1.0 / 3.0) - 1e-9))
+    s = L / m
+    if s <= 2.0 * a:
+        raise ValueError('volume fraction too high for a jittered lattice')
+    rng = np.random.default_rng(seed)
+    sites = rng.choice(m**3, size=N, replace=False)
+    ijk = np.stack([sites % m, (sites // m) % m, sites // (m * m)], axis=1)
+    half_gap = 0.5 * (s - 2.0 * a) * (1.0 - 1e-9)
+    x = (ijk + 0.5) * s + rng.uniform(-half_gap, half_gap, size=(N, 3))
+    return np.mod(x, L), L
+
+
 def packing(N, phi, a=1.0, seed=SEED_BASE):
     """Random non-overlapping packing: sequential addition for dilute
-    suspensions, overlap relaxation for dense ones."""
+    suspensions, overlap relaxation for dense ones, a jittered lattice from
+    LATTICE_N spheres on (sequential addition is too slow there)."""
+    if N >= LATTICE_N:
+        return jittered_lattice(N, phi, a, seed)
     if phi <= 0.2:
         return rsa_packing(N, phi, a, seed)
     return relaxed_packing(N, phi, a, seed)
