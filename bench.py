@@ -67,12 +67,13 @@ def run_form(w, precision, steps, warmup, seed, prof_steps=2):
 
 STAGE_KERNELS = {
     'fft': 'fft_xy_plane_kernel (x-y transform of one z-plane, both directions)',
+    'fft_large': 'fft_x_r2c/c2r_kernel and fft_lines_kernel (x and y passes)',
     'kspace': 'kspace_fused_kernel (z transform, k-space kernel, inverse z transform)',
     'spread': 'spread_list_kernel', 'interp': 'interp_kernel', 'real': 'real_pair_kernel',
 }
 
 
-def roofline(prof, traffic_file=None):
+def roofline(prof, traffic_file=None, grid=128):
     """The stage with the largest total time: algorithmic bytes per launch over
     the average event-timed launch duration, against the HBM peak; traffic is
     the HBM bytes per launch from the committed counter summary, if it was
@@ -87,7 +88,9 @@ def roofline(prof, traffic_file=None):
     return dom, dict(bound='hbm', achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit='GB/s',
                      frac=round(achieved / HBM_PEAK_GBS, 4),
                      traffic=None if traffic is None else round(traffic),
-                     kernel=STAGE_KERNELS.get(dom, dom), stage=dom, launches=p['launches'],
+                     kernel=STAGE_KERNELS.get('fft_large' if dom == 'fft' and grid > 128
+                                              else dom, dom),
+                     stage=dom, launches=p['launches'],
                      avg_us=round(1e6 * per_launch_s, 2),
                      alg_bytes_per_launch=round(per_launch_bytes))
 
@@ -226,11 +229,11 @@ def main():
     seed = w['seed']
     fp64 = run_form(w, pse.PSE_FP64, args.steps, args.warmup, seed)
     traffic_file = os.path.join(ROOT, 'profiles', f'hbm_traffic_{args.workload}_fp64.md')
-    dom, roof = roofline(fp64['prof'], traffic_file)
+    dom, roof = roofline(fp64['prof'], traffic_file, w['grid'])
     mixed = None
     if not args.no_mixed:
         m = run_form(w, pse.PSE_MIXED, args.steps, args.warmup, seed)
-        mdom, mroof = roofline(m['prof'])
+        mdom, mroof = roofline(m['prof'], None, w['grid'])
         mixed = dict(value=round(m['value'], 1), ms_per_step=round(m['ms_per_step'], 3),
                      speedup_vs_fp64=round(m['value'] / fp64['value'], 3), dtype='f32+f64',
                      roofline=mroof,

@@ -369,9 +369,9 @@ fft_lines_kernel(cplx<T> *__restrict__ data, const cplx<T> *__restrict__ tw, int
 
 // Lines per workgroup: a power of two dividing `count`, about 256 threads,
 // LDS within 64 KiB.
-int lines_per_block(int n, int tpl, size_t line_bytes, size_t count) {
+int lines_per_block(int n, int tpl, size_t line_bytes, size_t count, int max_threads) {
   int tl = 1;
-  while (tl * 2 * tpl <= 256 && count % (size_t)(tl * 2) == 0 &&
+  while (tl * 2 * tpl <= max_threads && count % (size_t)(tl * 2) == 0 &&
          (size_t)(tl * 2) * line_bytes <= 65536)
     tl *= 2;
   return tl;

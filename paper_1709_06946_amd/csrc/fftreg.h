@@ -309,11 +309,11 @@ __device__ __forceinline__ void reg_fft_inverse(cplx<T> (&v)[E], int t, cplx<T> 
 // Element counts per thread: line passes and the fused k-space kernel (which
 // also keeps three complex numbers per element in registers).
 constexpr int line_e(int n) { return n % 3 == 0 ? 12 : (n >= 128 ? 16 : 8); }
-constexpr int fused_e(int n) { return n % 3 == 0 ? 12 : (n <= 256 ? 4 : 8); }
+constexpr int fused_e(int n) { return n % 3 == 0 ? 12 : 4; }
 
-// Lines per workgroup: a power of two dividing `count`, about 256 threads,
-// LDS of tl * line_bytes within 64 KiB.
-int lines_per_block(int n, int tpl, size_t line_bytes, size_t count);
+// Lines per workgroup: a power of two dividing `count`, at most max_threads
+// threads (about 256 by default), LDS of tl * line_bytes within 64 KiB.
+int lines_per_block(int n, int tpl, size_t line_bytes, size_t count, int max_threads = 256);
 
 // Line lengths whose x-y plane fits one workgroup's LDS.
 #define PSE_FOR_EACH_SMALL_N(X) X(32) X(48) X(64) X(96) X(128)

@@ -460,7 +460,7 @@ __device__ __forceinline__ bool zero_mode(int ix, int iy, int iz, int n) {
 // order, so its input layout is the forward output layout -- transformed back
 // along z and stored.  One read of the inputs and one write of the outputs.
 template <typename T, int N>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(512)
 kspace_fused_kernel(const cplx<T> *__restrict__ in, CompSet cin, cplx<T> *__restrict__ out,
                     CompSet cout, KGeom kg, const typename TabT<T>::type *__restrict__ ktab,
                     const cplx<T> *__restrict__ tw, int TL) {
@@ -852,7 +852,9 @@ template <typename T, int N>
 void launch_fused(Handle &h, const cplx<T> *in, const CompSet &cin, cplx<T> *out,
                   const CompSet &cout, const cplx<T> *tw) {
   constexpr int TPL = N / fused_e(N);
-  const int tl = lines_per_block(N, TPL, N * sizeof(cplx<T>), (size_t)N / 2);
+  // at least four z-lines (64-byte row segments) per workgroup on long lines
+  const int tl = lines_per_block(N, TPL, N * sizeof(cplx<T>), (size_t)N / 2,
+                                 TPL >= 128 ? 512 : 256);
   const size_t lds = (size_t)tl * N * sizeof(cplx<T>);
   const unsigned nb = (unsigned)(N * (N / 2 / tl));
   using Tab = typename TabT<T>::type;
