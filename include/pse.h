@@ -89,6 +89,9 @@ typedef struct pse_params {
   int32_t gmres_maxit;     /* total GMRES iterations; 0 = 200                */
   double gmres_tol;        /* relative residual; 0 = 1e-6                    */
   int32_t refine_passes;   /* FP64 residual refinement passes (mixed); 0 = 3 */
+  int32_t graphs;          /* 0: replay each constraint-operator application
+                              from a captured hipGraph (captured on first use
+                              per input/output pair); -1: launch eagerly     */
   void *stream;            /* hipStream_t to run on, or NULL                 */
 } pse_params;
 

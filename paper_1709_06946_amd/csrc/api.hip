@@ -172,6 +172,48 @@ static void prepare_positions(Handle &h, const double *x, double *xw) {
   build_cells(h, xw);
 }
 
+void clear_graphs(Handle &h) {
+  for (auto &kv : h.graphs) (void)hipGraphExecDestroy(kv.second);
+  h.graphs.clear();
+}
+
+// Runs fn, an operator application on the handle's stream, from a captured
+// graph: on the first call for (in, out, kind) the launches are captured
+// (thread-local capture mode, so other threads' handles are unaffected) and
+// instantiated, and every call replays the graph.  The launches read all
+// per-step data (positions, lists, moments) from device memory at fixed
+// addresses, so one capture serves every later step.  Eager when graphs are
+// off, while the stage profiler runs, on the legacy null stream, and for the
+// handle's very first application (lazy kernel attributes are set then).
+template <typename F>
+static void run_graphed(Handle &h, const void *in, const void *out, int kind, F &&fn) {
+  if (!h.use_graphs || h.prof.on || h.stream == nullptr || !h.graph_warm) {
+    fn();
+    h.graph_warm = true;
+    return;
+  }
+  const auto key = std::make_tuple(in, (const void *)out, kind);
+  auto it = h.graphs.find(key);
+  if (it == h.graphs.end()) {
+    hipGraph_t g = nullptr;
+    PSE_HIP(hipStreamBeginCapture(h.stream, hipStreamCaptureModeThreadLocal));
+    try {
+      fn();
+    } catch (...) {
+      (void)hipStreamEndCapture(h.stream, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    PSE_HIP(hipStreamEndCapture(h.stream, &g));
+    hipGraphExec_t ex = nullptr;
+    const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    PSE_HIP(e);
+    it = h.graphs.emplace(key, ex).first;
+  }
+  PSE_HIP(hipGraphLaunch(it->second, h.stream));
+}
+
 // Solve M_ES S = b at xh (cell list current).  Mixed handles run FP32 GMRES
 // inside FP64 residual refinement: r = b - M_ES^(64) S, correction from the
 // FP32 operator, until the FP64 relative residual meets gmres_tol.
@@ -183,7 +225,8 @@ static void stresslet_solve(Handle &h, const double *xh, const double *b, double
   const Layout l5{5, 6};
   auto make_op = [&, l5](bool fp64) {
     return Op([&, fp64, l5](const double *in, double *o) {
-      mobility(h, xh, true, true, in, l5, es, o, l5, es, fp64);
+      run_graphed(h, in, o, fp64 ? 1 : 2,
+                  [&] { mobility(h, xh, true, true, in, l5, es, o, l5, es, fp64); });
     });
   };
   if (!h.mixed) {
@@ -258,6 +301,7 @@ static void create(const pse_params &p, Handle &h) {
   h.p = p;
   h.n = p.n;
   h.mixed = p.precision == PSE_MIXED;
+  h.use_graphs = p.graphs >= 0;
   h.ngrid = (size_t)h.d.grid * h.d.grid * h.d.grid;
   h.cells.nc = h.d.cells;
   // spreading tiles of stile^3 grid points gather from the 27 neighbouring
@@ -352,6 +396,7 @@ static void release(Handle &h) {
                   h.tl_scan, h.tl_rec, h.bad_pos, h.ktab32};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
+  clear_graphs(h);
   for (hipEvent_t e : h.prof.pool) (void)hipEventDestroy(e);
   h.prof.pool.clear();
   if (h.own_stream && h.stream) (void)hipStreamDestroy(h.stream);

@@ -5,7 +5,9 @@
 
 #include <cstdint>
 #include <functional>
+#include <map>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/pse.h"
@@ -159,7 +161,16 @@ struct Handle {
   size_t dots_len;
 
   Profiler prof;
+
+  // captured constraint-operator applications, keyed by (input, output,
+  // kind); cleared when a buffer baked into them is reallocated
+  bool use_graphs = true;
+  bool graph_warm = false;   // one eager application before the first capture
+  std::map<std::tuple<const void *, const void *, int>, hipGraphExec_t> graphs;
 };
+
+// Destroys every captured graph of the handle.
+void clear_graphs(Handle &h);
 
 // Brackets the launches of one stage with events when profiling is on.
 struct ProfScope {

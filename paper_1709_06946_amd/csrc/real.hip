@@ -606,6 +606,7 @@ static void build_pair_list(Handle &h, const double *xw) {
   PSE_HIP(hipStreamSynchronize(h.stream));
   if (bad) throw Error{PSE_ERR_NONFINITE, "non-finite particle position"};
   if ((size_t)total > h.pl_cap) {
+    clear_graphs(h);   // captured real-space launches hold the old buffers
     const size_t cap = (size_t)total + total / 4 + 1024;
     PSE_HIP(hipFree(h.pl_nbr));
     PSE_HIP(hipFree(h.pl_rec));

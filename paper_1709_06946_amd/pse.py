@@ -24,7 +24,8 @@ class pse_params(ctypes.Structure):
                 ('precision', ctypes.c_int32), ('lanczos_maxit', ctypes.c_int32),
                 ('lanczos_tol', ctypes.c_double), ('gmres_restart', ctypes.c_int32),
                 ('gmres_maxit', ctypes.c_int32), ('gmres_tol', ctypes.c_double),
-                ('refine_passes', ctypes.c_int32), ('stream', ctypes.c_void_p)]
+                ('refine_passes', ctypes.c_int32), ('graphs', ctypes.c_int32),
+                ('stream', ctypes.c_void_p)]
 
 
 class pse_derived(ctypes.Structure):
@@ -158,12 +159,12 @@ class PSEError(RuntimeError):
 def make_params(n, box, *, radius=1.0, viscosity=1.0, kT=1.0, tol=1e-3, grid=0,
                 support=0, xi=0.0, rcut=0.0, precision=PSE_FP64, lanczos_maxit=0,
                 lanczos_tol=0.0, gmres_restart=0, gmres_maxit=0, gmres_tol=0.0,
-                refine_passes=0, stream=None):
+                refine_passes=0, graphs=0, stream=None):
     return pse_params(int(n), float(box), float(radius), float(viscosity), float(kT),
                       float(tol), int(grid), int(support), float(xi), float(rcut),
                       int(precision), int(lanczos_maxit), float(lanczos_tol),
                       int(gmres_restart), int(gmres_maxit), float(gmres_tol),
-                      int(refine_passes), stream)
+                      int(refine_passes), int(graphs), stream)
 
 
 def derive(params):

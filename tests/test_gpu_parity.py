@@ -216,3 +216,32 @@ def test_step_same_noise(name):
     print(name, 'step', errs, gpu['st'])
     assert max(errs.values()) < TOL, errs
     assert np.all((gpu['x1'] >= 0) & (gpu['x1'] < L))
+
+
+@pytest.mark.parametrize('precision', [0, 1])
+def test_graph_replays_match_eager_launches(precision):
+    """Constrained steps with the operator replayed from captured graphs
+    (default) and launched eagerly agree, over several steps in a row (each
+    replay after the library's own eager work and synchronisations)."""
+    import torch
+
+    from paper_1709_06946_amd import pse
+    c = CASES['phi0.1']
+    x0, L = packing(c['N'], c['phi'], c['seed'])
+    FL = np.random.default_rng(5).normal(size=(c['N'], 6))
+    res = []
+    for graphs in (0, -1):
+        h = pse.PSE(c['N'], L, grid=c['grid'], tol=1e-3, precision=precision, graphs=graphs)
+        x = dev(x0)
+        stats = []
+        for k in range(3):
+            rc, st = h.constrained_step(x, dev(FL), 1e-3, seed=77, step=k)
+            assert rc >= 0
+            stats.append(st['gmres_iters'])
+        res.append((host(x), stats))
+        h.close()
+    (xa, sa), (xb, sb) = res
+    d = xa - xb
+    d -= L * np.rint(d / L)
+    assert sa == sb
+    assert np.abs(d).max() <= 1e-10 * L
