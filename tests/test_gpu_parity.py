@@ -243,5 +243,10 @@ def test_graph_replays_match_eager_launches(precision):
     (xa, sa), (xb, sb) = res
     d = xa - xb
     d -= L * np.rint(d / L)
+    disp = xa - x0
+    disp -= L * np.rint(disp / L)
     assert sa == sb
-    assert np.abs(d).max() <= 1e-10 * L
+    # FP64: rounding-level agreement; mixed: FP32 sums whose order follows the
+    # cell slots (taken by atomics) differ from run to run at the 1e-7 level
+    bound = 1e-10 * L if precision == 0 else 1e-5 * np.abs(disp).max()
+    assert np.abs(d).max() <= bound
