@@ -164,7 +164,8 @@ static KrylovResult real_sqrt(Handle &h, const double *xw, const double *psi, do
     if (h.mixed) real_apply<float>(h, xw, in, FULL_LAYOUT, all, o, FULL_LAYOUT, all, false);
     else real_apply<double>(h, xw, in, FULL_LAYOUT, all, o, FULL_LAYOUT, all, false);
   };
-  return lanczos_sqrt(h, A, psi, (size_t)h.n * NC, out, h.d.lanczos_maxit, h.d.lanczos_tol);
+  return lanczos_sqrt(h, A, psi, (size_t)h.n * NC, out, h.d.lanczos_maxit, h.d.lanczos_tol,
+                      &h.lz_prev);
 }
 
 static void prepare_positions(Handle &h, const double *x, double *xw) {
@@ -231,7 +232,7 @@ static void stresslet_solve(Handle &h, const double *xh, const double *b, double
   };
   if (!h.mixed) {
     KrylovResult r = gmres(h, make_op(true), b, n5, S, h.d.gmres_restart, h.d.gmres_maxit,
-                           h.d.gmres_tol);
+                           h.d.gmres_tol, &h.gm_prev[0]);
     st.gmres_iters += r.iters;
     st.gmres_residual = r.resid;
     st.fp64_residual = r.resid;
@@ -256,7 +257,7 @@ static void stresslet_solve(Handle &h, const double *xh, const double *b, double
   bool ok = false;
   for (int pass = 0; pass < h.d.refine_passes; ++pass) {
     KrylovResult r = gmres(h, A32, h.es_r, n5, h.es_d, h.d.gmres_restart, h.d.gmres_maxit,
-                           h.d.gmres_tol);
+                           h.d.gmres_tol, pass == 0 ? &h.gm_prev[1] : nullptr);
     st.gmres_iters += r.iters;
     st.gmres_residual = r.resid;
     st.refine_passes = pass + 1;

@@ -4,6 +4,7 @@
 // on the device; the host only reads a few numbers back per iteration to
 // decide when to stop.
 #include <cmath>
+#include <vector>
 
 #include "pse_internal.h"
 
@@ -264,7 +265,8 @@ __device__ void tridiag_ql(double *d, double *e, double *z, int m, int ldz) {
 // (zero-padded), written to out_change.
 __global__ void lanczos_sqrt_kernel(const double *alpha, const double *beta, int m,
                                     double bnorm, double *work, int ldz, double *coef,
-                                    double *coef_prev, double *out_change) {
+                                    double *coef_prev, double *out_change,
+                                    double *chg_hist) {
   // the eigenproblem runs on one thread; its arrays live in LDS when they fit
   // (dynamic shared memory sized by the host), else in the global work area
   extern __shared__ double lds_work[];
@@ -292,6 +294,7 @@ __global__ void lanczos_sqrt_kernel(const double *alpha, const double *beta, int
   }
   for (int i = 0; i < m; ++i) coef_prev[i] = coef[i];
   out_change[0] = den > 0.0 ? sqrt(num / den) : 0.0;
+  chg_hist[m - 1] = out_change[0];
 }
 
 // y = R^{-1} g for the k x k upper-triangular part of H.
@@ -313,7 +316,8 @@ __global__ void backsub_kernel(const double *H, int ldh, int k, const double *g,
 // formed and g updated; vnorm = H[j+1][j], resid = |g_{j+1}|.
 __global__ void hess_givens_kernel(double *H, int ldh, int j, const double *h1,
                                    const double *h2, double *cs, double *sn, double *g,
-                                   double *vnorm, double *resid) {
+                                   double *vnorm, double *resid, double *vn_hist,
+                                   double *res_hist) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   double *col = H + (size_t)j * ldh;
   double p2 = 0.0;
@@ -339,6 +343,8 @@ __global__ void hess_givens_kernel(double *H, int ldh, int j, const double *h1,
   g[j + 1] = -s * g[j];
   g[j] = c * g[j];
   resid[0] = fabs(g[j + 1]);
+  vn_hist[j] = nn;
+  res_hist[j] = resid[0];
 }
 
 __global__ void sqrt_kernel(const double *in, double *out) {
@@ -356,7 +362,7 @@ __global__ void set_g0_kernel(double *g, int len, const double *beta) {
 // alpha_j = h1[j] + h2[j]; h2[j+1] holds w.w after the first pass, so
 // beta_j = sqrt(w.w - |h2|^2) is the norm of the twice-orthogonalised w.
 __global__ void lanczos_fill_kernel(double *alpha, double *beta, int j, const double *h1,
-                                    const double *h2, double *vnorm) {
+                                    const double *h2, double *vnorm, double *vn_hist) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   alpha[j] = h1[j] + h2[j];
   double p2 = 0.0;
@@ -364,6 +370,7 @@ __global__ void lanczos_fill_kernel(double *alpha, double *beta, int j, const do
   const double nn = sqrt(fmax(h2[j + 1] - p2, 0.0));
   beta[j] = nn;
   vnorm[0] = nn;
+  vn_hist[j] = nn;
 }
 
 // ---------------------------------------------------- host algorithms --
@@ -375,6 +382,17 @@ static void host_read(Handle &h, const double *dev, double *host, int n) {
   PSE_HIP(hipStreamSynchronize(h.stream));
   for (int i = 0; i < n; ++i)
     if (!std::isfinite(host[i])) throw Error{PSE_ERR_NONFINITE, "non-finite Krylov scalar"};
+}
+
+// Reads n values from each of two device arrays with one synchronisation.
+static void host_read2(Handle &h, const double *a, double *ha, const double *b, double *hb,
+                       int n) {
+  PSE_HIP(hipMemcpyAsync(ha, a, n * sizeof(double), hipMemcpyDeviceToHost, h.stream));
+  PSE_HIP(hipMemcpyAsync(hb, b, n * sizeof(double), hipMemcpyDeviceToHost, h.stream));
+  PSE_HIP(hipStreamSynchronize(h.stream));
+  for (int i = 0; i < n; ++i)
+    if (!std::isfinite(ha[i]) || !std::isfinite(hb[i]))
+      throw Error{PSE_ERR_NONFINITE, "non-finite Krylov scalar"};
 }
 
 static void norm2_dev(Handle &h, const double *v, size_t n, double *dev_norm2) {
@@ -404,14 +422,23 @@ static void sub_scale(Handle &h, double *w, const double *V, size_t n, int m,
 // reorthogonalization, stop when the relative change of the iterate falls
 // below tol.  The iterate is y_m = |b| V_m f(T_m) e_1; with V_m orthonormal
 // its change is the change of the small coefficient vector.
+// Convergence checks read per-iteration scalars on the host, each a stall of
+// the stream.  The iteration counts of successive solves on a handle barely
+// change, so a solve reads them from two iterations before the previous
+// solve's count on (every iteration on the first solve); per-iteration
+// values are kept on the device, so the first converged iteration (or a
+// breakdown) is still found exactly and later iterations are discarded.
+
 KrylovResult lanczos_sqrt(Handle &h, const Op &A, const double *b, size_t n, double *y,
-                          int maxit, double tol) {
+                          int maxit, double tol, int *prev_iters) {
   const int M = maxit;
   const int ldz = M + 1;
   double *s = h.small;
   double *alpha = s, *beta = alpha + (M + 1), *h1 = beta + (M + 1), *h2 = h1 + (M + 1);
   double *norm2 = h2 + (M + 1), *vnorm = norm2 + 1, *bn = vnorm + 1, *change = bn + 1;
-  double *coef = change + 1, *coef_prev = coef + (M + 1), *work = coef_prev + (M + 1);
+  double *coef = change + 1, *coef_prev = coef + (M + 1);
+  double *vn_hist = coef_prev + (M + 1), *chg_hist = vn_hist + (M + 1);
+  double *work = chg_hist + (M + 1);
   if ((size_t)(work - s) + (size_t)(2 + ldz) * ldz + 8 > h.small_len)
     throw Error{PSE_ERR_INVALID, "Lanczos scratch too small"};
   double *V = h.lz_V;
@@ -429,36 +456,53 @@ KrylovResult lanczos_sqrt(Handle &h, const Op &A, const double *b, size_t n, dou
   }
   PSE_HIP(hipMemsetAsync(coef_prev, 0, (M + 1) * sizeof(double), h.stream));
   vscale_dev(h, V, b, bn, true, n);
+  auto sqrt_coef = [&](int mm) {
+    // LDS holds d, e and the mm^2 eigenvectors when they fit in 48 KiB
+    const size_t lds = (size_t)(2 * mm + mm * mm) * sizeof(double);
+    const bool fits = lds <= 49152;
+    hipLaunchKernelGGL(lanczos_sqrt_kernel, dim3(1), dim3(64), fits ? lds : 0, h.stream, alpha,
+                       beta, mm, bnorm, work, fits ? mm : ldz, coef, coef_prev, change,
+                       chg_hist);
+    PSE_LAUNCH_CHECK();
+  };
+  const int check_from = (prev_iters && *prev_iters > 3) ? *prev_iters - 2 : 0;
+  std::vector<double> hist(2 * (M + 1));
   int m = 0;
   for (int j = 0; j < M; ++j) {
     double *w = V + (size_t)(j + 1) * n;
     A(V + (size_t)j * n, w);
     cgs2_pass(h, V, n, j + 1, w, h1, h2);
     hipLaunchKernelGGL(lanczos_fill_kernel, dim3(1), dim3(1), 0, h.stream, alpha, beta, j,
-                       h1, h2, vnorm);
+                       h1, h2, vnorm, vn_hist);
     PSE_LAUNCH_CHECK();
     sub_scale(h, w, V, n, j + 1, h2, vnorm);
-    {
-      // LDS holds d, e and the (j+1)^2 eigenvectors when they fit in 48 KiB
-      const int mm = j + 1;
-      const size_t lds = (size_t)(2 * mm + mm * mm) * sizeof(double);
-      const bool fits = lds <= 49152;
-      hipLaunchKernelGGL(lanczos_sqrt_kernel, dim3(1), dim3(64), fits ? lds : 0, h.stream,
-                         alpha, beta, mm, bnorm, work, fits ? mm : ldz, coef, coef_prev,
-                         change);
-    }
-    PSE_LAUNCH_CHECK();
-    double hv[3];   // vnorm, bn, change are adjacent
-    host_read(h, vnorm, hv, 3);
-    const double vn = hv[0], chg = hv[2];
+    sqrt_coef(j + 1);
     m = j + 1;
     res.iters = m;
-    res.resid = chg;
-    if ((j > 0 && chg < tol) || vn <= 1e-14 * bnorm) {
+    if (m < check_from && m < M) continue;
+    host_read2(h, vn_hist, hist.data(), chg_hist, hist.data() + (M + 1), j + 1);
+    const double *vh = hist.data(), *ch = vh + (M + 1);
+    int brk = -1;
+    for (int i = 0; i <= j; ++i)
+      if (vh[i] <= 1e-14 * bnorm) {
+        brk = i;
+        break;
+      }
+    if (brk >= 0) {
+      // breakdown: the Krylov space is exhausted after brk + 1 vectors
+      if (brk < j) sqrt_coef(brk + 1);
+      m = brk + 1;
+      res.resid = ch[brk];
+      res.converged = true;
+      break;
+    }
+    res.resid = ch[j];
+    if (j > 0 && ch[j] < tol) {
       res.converged = true;
       break;
     }
   }
+  if (prev_iters) *prev_iters = res.iters;
   gemv_small(h, V, n, m, coef, y, n, 1.0, false);
   return res;
 }
@@ -468,14 +512,15 @@ KrylovResult lanczos_sqrt(Handle &h, const Op &A, const double *b, size_t n, dou
 // Gram-Schmidt with a second pass (CGS2) so that each Arnoldi step costs two
 // fused reductions; Givens rotations on the device.
 KrylovResult gmres(Handle &h, const Op &A, const double *b, size_t n, double *x,
-                   int restart, int maxit, double tol) {
+                   int restart, int maxit, double tol, int *prev_iters) {
   const int R = restart;
   const int ldh = R + 1;
   double *s = h.small;
   double *H = s, *cs = H + (size_t)ldh * R, *sn = cs + (R + 1), *g = sn + (R + 1);
   double *h1 = g + (R + 1), *h2 = h1 + (R + 1), *norm2 = h2 + (R + 1);
   double *vnorm = norm2 + 1, *bn = vnorm + 1, *resid = bn + 1, *ycoef = resid + 1;
-  if ((size_t)(ycoef - s) + R + 8 > h.small_len)
+  double *vn_hist = ycoef + (R + 1), *res_hist = vn_hist + (R + 1);
+  if ((size_t)(res_hist - s) + R + 8 > h.small_len)
     throw Error{PSE_ERR_INVALID, "GMRES scratch too small"};
   double *V = h.gm_V;
   KrylovResult res{0, 0.0, false};
@@ -487,11 +532,15 @@ KrylovResult gmres(Handle &h, const Op &A, const double *b, size_t n, double *x,
   host_read(h, bn, &bnorm, 1);
   if (!(bnorm > 0)) {
     res.converged = true;
+    if (prev_iters) *prev_iters = 0;
     return res;
   }
   double rel = 1.0;
   int total = 0;
   bool first = true;
+  // only the first cycle reads late (see above); restarts check every step
+  int check_from = (prev_iters && *prev_iters > 3) ? *prev_iters - 2 : 0;
+  std::vector<double> hist(2 * (R + 1));
   while (total < maxit) {
     // r = b - A x (x = 0 on the first cycle)
     double *r = V;
@@ -500,6 +549,7 @@ KrylovResult gmres(Handle &h, const Op &A, const double *b, size_t n, double *x,
     } else {
       A(x, r);
       vaxpby(h, 1.0, b, -1.0, r, n);
+      check_from = 0;
     }
     first = false;
     norm2_dev(h, r, n, norm2);
@@ -521,16 +571,28 @@ KrylovResult gmres(Handle &h, const Op &A, const double *b, size_t n, double *x,
       A(V + (size_t)j * n, w);
       cgs2_pass(h, V, n, j + 1, w, h1, h2);
       hipLaunchKernelGGL(hess_givens_kernel, dim3(1), dim3(1), 0, h.stream, H, ldh, j, h1, h2,
-                         cs, sn, g, vnorm, resid);
+                         cs, sn, g, vnorm, resid, vn_hist, res_hist);
       PSE_LAUNCH_CHECK();
       sub_scale(h, w, V, n, j + 1, h2, vnorm);
-      double hr[3];   // vnorm, bn, resid are adjacent
-      host_read(h, vnorm, hr, 3);
-      const double vn = hr[0];
       ++total;
       k = j + 1;
-      rel = hr[2] / bnorm;
-      if (rel < tol || vn <= 1e-15 * bnorm) break;
+      if (k < check_from && j + 1 < R && total < maxit) continue;
+      host_read2(h, vn_hist, hist.data(), res_hist, hist.data() + (R + 1), j + 1);
+      const double *vh = hist.data(), *rh = vh + (R + 1);
+      // first column at which the residual met tol or the space was exhausted;
+      // later columns (and Givens entries) are not used by the update
+      int stop = -1;
+      for (int i = 0; i <= j; ++i)
+        if (rh[i] / bnorm < tol || vh[i] <= 1e-15 * bnorm) {
+          stop = i;
+          break;
+        }
+      if (stop >= 0) {
+        k = stop + 1;
+        rel = rh[stop] / bnorm;
+        break;
+      }
+      rel = rh[j] / bnorm;
     }
     hipLaunchKernelGGL(backsub_kernel, dim3(1), dim3(1), 0, h.stream, H, ldh, k, g, ycoef);
     PSE_LAUNCH_CHECK();
@@ -542,6 +604,7 @@ KrylovResult gmres(Handle &h, const Op &A, const double *b, size_t n, double *x,
   }
   res.iters = total;
   res.resid = rel;
+  if (prev_iters) *prev_iters = total;
   return res;
 }
 

@@ -165,6 +165,9 @@ struct Handle {
   // captured constraint-operator applications, keyed by (input, output,
   // kind); cleared when a buffer baked into them is reallocated
   bool use_graphs = true;
+  // iteration counts of the previous Lanczos and GMRES (FP64, FP32) solves
+  int lz_prev = 0;
+  int gm_prev[2] = {0, 0};
   bool graph_warm = false;   // one eager application before the first capture
   std::map<std::tuple<const void *, const void *, int>, hipGraphExec_t> graphs;
 };
@@ -350,10 +353,12 @@ struct KrylovResult {
   bool converged;
 };
 using Op = std::function<void(const double *in, double *out)>;
+// prev_iters (may be null): the previous solve's iteration count, read and
+// updated; the convergence checks start two iterations before it.
 KrylovResult lanczos_sqrt(Handle &h, const Op &A, const double *b, size_t n,
-                          double *y, int maxit, double tol);
+                          double *y, int maxit, double tol, int *prev_iters);
 KrylovResult gmres(Handle &h, const Op &A, const double *b, size_t n, double *x,
-                   int restart, int maxit, double tol);
+                   int restart, int maxit, double tol, int *prev_iters);
 
 // ---- grid.hip (noise)
 void real_noise(Handle &h, uint64_t seed, uint64_t counter, double *out);
