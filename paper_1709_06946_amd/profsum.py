@@ -2,6 +2,8 @@
 
 python -m paper_1709_06946_amd.profsum stats DIR      per-kernel time table
 python -m paper_1709_06946_amd.profsum pmc DIR         per-kernel mean counters
+python -m paper_1709_06946_amd.profsum traffic FETCH WRITE COPY_FETCH COPY_WRITE STAGE
+                                                      HBM bytes per launch of one stage
 
 DIR is the `-d` directory of a `rocprofv3 --kernel-trace --stats` run (files
 `*_kernel_stats.csv`) or of a `rocprofv3 --pmc ...` run (files
@@ -89,7 +91,56 @@ def recorded_traffic(stage, profile_file):
     return None
 
 
+# Kernels whose launches make up one stage of the wave-space product.
+STAGE_PREFIX = {'fft': ('fft_',), 'kspace': ('kspace_fused',), 'spread': ('spread_list',),
+                'interp': ('interp_kernel',), 'real': ('real_pair',)}
+STAGE_SOURCES = {'fft': ('fft.hip', 'fftreg.h'), 'kspace': ('grid.hip', 'fftreg.h'),
+                 'spread': ('grid.hip',), 'interp': ('grid.hip',), 'real': ('real.hip',)}
+COPY_BYTES = 2**30
+
+
+def _copy_counter(d, counter):
+    """Mean per dispatch of one counter for the copy kernel of a calibration
+    run (the kernel with the largest mean; each dispatch copies 1 GiB)."""
+    return max(cs[counter][1] for cs in counters(d).values() if counter in cs)
+
+
+def traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, stage):
+    """Markdown rows of fetched/written MB per launch, scaled by what the same
+    counters read for a 1 GiB device copy, and the stamped total for `stage`
+    (bytes per launch, with the sha256 of the sources its kernels come from)."""
+    import hashlib
+    fscale = COPY_BYTES / (1024 * _copy_counter(copy_fetch_dir, 'FETCH_SIZE'))
+    wscale = COPY_BYTES / (1024 * _copy_counter(copy_write_dir, 'WRITE_SIZE'))
+    fc, wc = counters(fetch_dir), counters(write_dir)
+    rows = []
+    for k in set(fc) | set(wc):
+        n = max(fc.get(k, {}).get('FETCH_SIZE', (0, 0))[0],
+                wc.get(k, {}).get('WRITE_SIZE', (0, 0))[0])
+        fb = 1024 * fscale * fc.get(k, {}).get('FETCH_SIZE', (0, 0.0))[1]
+        wb = 1024 * wscale * wc.get(k, {}).get('WRITE_SIZE', (0, 0.0))[1]
+        rows.append((k, n, fb, wb))
+    rows.sort(key=lambda r: -(r[2] + r[3]) * r[1])
+    out = [f'Calibration: fetched bytes = {fscale:.3f} x FETCH_SIZE KiB x 1024, '
+           f'written bytes = {wscale:.3f} x WRITE_SIZE KiB x 1024 (1 GiB device copy).', '',
+           '| kernel | launches | fetched MB | written MB |', '|---|---:|---:|---:|']
+    out += [f'| `{k}` | {n} | {fb / 1e6:.1f} | {wb / 1e6:.1f} |' for k, n, fb, wb in rows]
+    sel = [r for r in rows if r[0].startswith(STAGE_PREFIX[stage])]
+    launches = sum(r[1] for r in sel)
+    total = sum((r[2] + r[3]) * r[1] for r in sel) / max(launches, 1)
+    csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), 'csrc')
+    srcs = ','.join(f'{f}:' + hashlib.sha256(open(os.path.join(csrc, f), 'rb').read())
+                    .hexdigest()[:16] for f in STAGE_SOURCES[stage])
+    out += ['', f'Stage `{stage}` (all {", ".join(STAGE_PREFIX[stage])}* launches): '
+            f'{total / 1e6:.1f} MB per launch over {launches} launches.', '',
+            f'<!-- traffic stage={stage} bytes_per_launch={round(total)} sources={srcs} -->']
+    return '\n'.join(out)
+
+
 def main(argv):
+    if len(argv) == 7 and argv[1] == 'traffic':
+        print(traffic(*argv[2:7]))
+        return 0
     if len(argv) != 3 or argv[1] not in ('stats', 'pmc'):
         print(__doc__)
         return 2
