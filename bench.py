@@ -153,9 +153,14 @@ def served(n_req, steps, max_active, n_max, rate_hz, seed):
                 time.sleep(g)
             ids.append(srv.submit(r['x'], r['L'], FL=r['FL'], steps=steps, dt=1e-3,
                                   seed=r['seed'], grid=r['grid'], precision=pse.PSE_MIXED))
-        lat, waits = [], []
+        lat, waits, errors = [], [], []
         for rid in ids:
-            info = srv.wait(rid)
+            try:
+                info = srv.wait(rid)
+            except pse.PSEError as e:       # reported below, not fatal to the bench
+                errors.append(str(e))
+                srv.release(rid)
+                continue
             _, l = srv.result(rid)
             lat.extend(l.tolist())
             waits.append(info['t_admit'] - info['t_submit'])
@@ -163,13 +168,14 @@ def served(n_req, steps, max_active, n_max, rate_hz, seed):
         wall = time.perf_counter() - t0
         st = srv.stats()
         srv.close()
-        lat = np.asarray(lat)
+        lat = np.asarray(lat) if lat else np.full(1, np.nan)
+        waits = np.asarray(waits) if waits else np.full(1, np.nan)
         return dict(particle_steps_per_s=round(st['particle_steps'] / wall, 1),
                     wall_s=round(wall, 3), p50_step_ms=round(float(np.percentile(lat, 50)), 3),
                     p99_step_ms=round(float(np.percentile(lat, 99)), 3),
                     p50_admit_wait_ms=round(1e3 * float(np.percentile(waits, 50)), 3),
                     peak_active=st['peak_active'], peak_used_GB=round(st['peak_used'] / 1e9, 3),
-                    completed=st['completed'], failed=st['failed'])
+                    completed=st['completed'], failed=st['failed'], errors=errors[:3])
 
     for r in reqs[:1]:      # warm the library (code objects, tables)
         srv = pse.PSEServer(max_active=1)

@@ -294,6 +294,11 @@ int pse_server_wait(pse_server *s, int64_t id, pse_request_info *info);
  * double[steps]) of a finished request; either pointer may be NULL. */
 int pse_server_result(pse_server *s, int64_t id, double *x_out, double *step_ms);
 
+/* Message of a failed request: the library's error text (the failing HIP
+ * call or check and where it was made).  "" while the request has not
+ * failed or for an unknown id; valid until the request is released. */
+const char *pse_server_error(pse_server *s, int64_t id);
+
 /* Forget a finished request. */
 int pse_server_release(pse_server *s, int64_t id);
 

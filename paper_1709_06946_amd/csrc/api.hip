@@ -186,6 +186,10 @@ void clear_graphs(Handle &h) {
 // addresses, so one capture serves every later step.  Eager when graphs are
 // off, while the stage profiler runs, on the legacy null stream, and for the
 // handle's very first application (lazy kernel attributes are set then).
+// A capture that fails (begin, a launch into it, end or instantiation) is
+// discarded, graphs are switched off for the handle (graph_error keeps the
+// reason) and the application runs eagerly; a launch error that is not a
+// capture error then reappears in the eager run and is reported as usual.
 template <typename F>
 static void run_graphed(Handle &h, const void *in, const void *out, int kind, F &&fn) {
   if (!h.use_graphs || h.prof.on || h.stream == nullptr || !h.graph_warm) {
@@ -197,19 +201,36 @@ static void run_graphed(Handle &h, const void *in, const void *out, int kind, F 
   auto it = h.graphs.find(key);
   if (it == h.graphs.end()) {
     hipGraph_t g = nullptr;
-    PSE_HIP(hipStreamBeginCapture(h.stream, hipStreamCaptureModeThreadLocal));
-    try {
-      fn();
-    } catch (...) {
-      (void)hipStreamEndCapture(h.stream, &g);
-      if (g) (void)hipGraphDestroy(g);
-      throw;
-    }
-    PSE_HIP(hipStreamEndCapture(h.stream, &g));
     hipGraphExec_t ex = nullptr;
-    const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    PSE_HIP(e);
+    std::string why;
+    hipError_t e = hipStreamBeginCapture(h.stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+      why = std::string("hipStreamBeginCapture: ") + hipGetErrorString(e);
+    } else {
+      try {
+        fn();
+      } catch (const Error &err) {
+        why = "launch during capture: " + err.msg;
+      }
+      e = hipStreamEndCapture(h.stream, &g);
+      if (why.empty() && e != hipSuccess)
+        why = std::string("hipStreamEndCapture: ") + hipGetErrorString(e);
+      if (why.empty()) {
+        e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+          why = std::string("hipGraphInstantiate: ") + hipGetErrorString(e);
+          ex = nullptr;
+        }
+      }
+      if (g) (void)hipGraphDestroy(g);
+    }
+    if (!why.empty()) {
+      (void)hipGetLastError();
+      h.use_graphs = false;
+      h.graph_error = why;
+      fn();
+      return;
+    }
     it = h.graphs.emplace(key, ex).first;
   }
   PSE_HIP(hipGraphLaunch(it->second, h.stream));
@@ -351,8 +372,8 @@ static void create(const pse_params &p, Handle &h) {
     alloc((void **)&h.tl_cnt, ntile * sizeof(int));
     alloc((void **)&h.tl_start, (ntile + 1) * sizeof(int));
     alloc((void **)&h.tl_scan, ((ntile + 1023) / 1024 + 8) * sizeof(int));
-    const size_t cap = n * tiles_per_particle(h.d.support, h.stile);
-    alloc((void **)&h.tl_rec, cap * tile_record_bytes());
+    h.tl_cap = n * tiles_per_particle(h.d.support, h.stile);
+    alloc((void **)&h.tl_rec, h.tl_cap * tile_record_bytes(h.stile) + 256);
   }
   alloc((void **)&h.pl_cnt, n * sizeof(int));
   alloc((void **)&h.pl_start, (n + 1) * sizeof(int));
@@ -404,6 +425,7 @@ static void release(Handle &h) {
 }
 
 template <typename F> static int guarded(pse_handle *hd, F &&f) {
+  RelaxedCaptureScope relaxed;
   try {
     f();
     if (hd && !hd->h.prof.pending.empty()) {
@@ -466,6 +488,7 @@ int pse_create(const pse_params *p, pse_handle **out) {
 
 int pse_destroy(pse_handle *hd) {
   if (!hd) return PSE_OK;
+  RelaxedCaptureScope relaxed;
   (void)hipStreamSynchronize(hd->h.stream);
   release(hd->h);
   delete hd;

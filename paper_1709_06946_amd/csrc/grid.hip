@@ -72,14 +72,6 @@ spread_kernel(const double *__restrict__ x, const double *__restrict__ q,
   }
 }
 
-// One (tile, particle) pair of the candidate lists: the particle, its
-// stencil origin and its position (fixed until the positions move).
-struct TileRec {
-  int p;
-  int st[3];
-  double x[3];
-};
-
 // Whether a stencil starting at grid index st (P points) meets the tile
 // starting at t0 (S points) on a periodic axis of ng points.
 __device__ __forceinline__ bool stencil_meets(int st, int t0, int P, int S, int ng) {
@@ -88,16 +80,25 @@ __device__ __forceinline__ bool stencil_meets(int st, int t0, int P, int S, int 
   return a < P || a > ng - S;
 }
 
+// The candidate lists hold one record per (tile, particle) pair: the
+// particle index (rp) and the record's one-dimensional Gaussian weights at
+// the tile's S grid positions along x, y and z (rw, 3 S doubles, zero outside
+// the stencil).  The weights depend on the positions only, so they are formed
+// once per position update, when the lists are built.
+struct TileRecs {
+  int *p;
+  double *w;
+};
+
 // FILL = false: count each tile's candidates; true: write their records from
-// start[tile] on, in bin order and ranked with a ballot.  One wavefront per tile enumerates the
-// particles of the 27 bins around it 64 at a time (bins are tiles; a
-// stencil reaches at most one tile beyond its particle's).
+// start[tile] on, in bin order and ranked with a ballot.  One wavefront per
+// tile enumerates the particles of the 27 bins around it 64 at a time (bins
+// are tiles; a stencil reaches at most one tile beyond its particle's).
 template <bool FILL>
 __global__ void __launch_bounds__(256)
 tile_list_kernel(const double *__restrict__ x, GridGeom g, int S, int nb,
                  const int *__restrict__ bstart, const int *__restrict__ bperm,
-                 int *__restrict__ cnt, const int *__restrict__ start,
-                 TileRec *__restrict__ rec) {
+                 int *__restrict__ cnt, const int *__restrict__ start, TileRecs rec) {
   const int tile = blockIdx.x * 4 + threadIdx.x / 64;
   const int lane = threadIdx.x % 64;
   if (tile >= nb * nb * nb) return;
@@ -127,14 +128,21 @@ tile_list_kernel(const double *__restrict__ x, GridGeom g, int S, int nb,
       const unsigned long long m = __ballot(ok);
       if (ok) {
         const int e = pos + __popcll(m & ((1ull << lane) - 1ull));
-        TileRec r;
-        r.p = p;
-#pragma unroll
+        rec.p[e] = p;
+        double *w = rec.w + (size_t)e * (3 * S);
         for (int d = 0; d < 3; ++d) {
-          r.st[d] = st[d];
-          r.x[d] = x[3 * p + d];
+          const double xd = x[3 * p + d];
+          for (int i = 0; i < S; ++i) {
+            int a = (tc[d] * S + i - st[d]) % ng;
+            a += a < 0 ? ng : 0;
+            double wi = 0.0;
+            if (a < P) {
+              const double dx = (st[d] + a) * g.h - xd;
+              wi = g.knorm * exp(-g.kcoef * dx * dx);
+            }
+            w[d * S + i] = wi;
+          }
         }
-        rec[e] = r;
       }
       pos += __popcll(m);
     }
@@ -148,81 +156,83 @@ tile_list_kernel(const double *__restrict__ x, GridGeom g, int S, int nb,
 
 // Gather form of the spreading sum: one workgroup per tile of S^3 grid
 // points reads the tile's candidate records.  The Gaussian factorises over
-// the axes, K = prod_d knorm exp(-kcoef dx_d^2), so for each staged candidate
-// the 1D weights at the tile's S positions per axis are computed once (zero
-// outside the stencil) and kept in LDS with the candidate's moments; each
-// thread then sums w_x w_y w_z q over the candidates for its grid points,
-// without range tests or exponentials.  Every grid point is written exactly
-// once: no atomics and no zeroing pass.
-constexpr int GMAXC = 64;
+// the axes, K = w_x w_y w_z, and the records carry the 1D weights, so a chunk
+// of candidates is staged in LDS with one coalesced read of its weights and
+// one gather of its moments.  Each thread owns ZPT points of one z-column of
+// the tile and, per candidate, forms w_x w_y once and reads the moments once
+// for all of them.  Every grid point is written exactly once: no atomics and
+// no zeroing pass.
+constexpr int GMAXC = 32;
 
-template <typename T, int S, int NCM>
-__global__ void __launch_bounds__(S * S * S < 256 ? S * S * S : 256)
+template <typename T, int S, int NCM, int ZPT>
+__global__ void __launch_bounds__(S * S * S / ZPT)
 spread_list_kernel(const double *__restrict__ q, Layout lq, CompSet cs, GridGeom g, int nb,
-                   const int *__restrict__ tstart, const TileRec *__restrict__ rec,
-                   T *__restrict__ grids, size_t ngrid) {
-  constexpr int NT = S * S * S < 256 ? S * S * S : 256;
-  constexpr int PPT = S * S * S / NT;
-  __shared__ T wts[3][GMAXC][S];
-  __shared__ T cq[NCM][GMAXC];
+                   const int *__restrict__ tstart, TileRecs rec, T *__restrict__ grids,
+                   size_t ngrid) {
+  constexpr int NT = S * S * S / ZPT;
+  constexpr int RW = 3 * S;
+  constexpr int WPT = (GMAXC * RW + NT - 1) / NT;
+  constexpr int NCMP = NCM + (NCM & 1);
+  static_assert(GMAXC <= NT, "one candidate per thread in the moment gather");
+  __shared__ T wts[GMAXC * RW];
+  __shared__ T cq[GMAXC * NCMP];
   const int tile = blockIdx.x;
   const int tc[3] = {tile % nb, (tile / nb) % nb, tile / (nb * nb)};
   const int lo = tstart[tile];
   const int total = tstart[tile + 1] - lo;
-  const int P = g.P, ng = g.ng;
-  int lx[PPT], ly[PPT], lz[PPT];
-  T acc[PPT][NCM];
+  const int ng = g.ng;
+  const int tid = threadIdx.x;
+  const int lx = tid % S, ly = (tid / S) % S, z0 = (tid / (S * S)) * ZPT;
+  T acc[ZPT][NCM];
 #pragma unroll
-  for (int pt = 0; pt < PPT; ++pt) {
-    const int l = threadIdx.x + pt * NT;
-    lx[pt] = l % S;
-    ly[pt] = (l / S) % S;
-    lz[pt] = l / (S * S);
+  for (int z = 0; z < ZPT; ++z)
 #pragma unroll
-    for (int k = 0; k < NCM; ++k) acc[pt][k] = (T)0;
-  }
+    for (int k = 0; k < NCM; ++k) acc[z][k] = (T)0;
   for (int c0 = 0; c0 < total; c0 += GMAXC) {
     const int nchunk = min(GMAXC, total - c0);
+    const int nw = nchunk * RW;
     __syncthreads();
-    // moments of the chunk's candidates
-    for (int t = threadIdx.x; t < nchunk * NCM; t += NT) {
-      const int j = t / NCM, k = t % NCM;
-      if (k < cs.n) {
-        const int p = rec[lo + c0 + j].p;
-        cq[k][j] = (T)q[(size_t)p * lq.stride + cs.idx[k] - lq.off];
-      }
+    const int pj = tid < nchunk ? rec.p[lo + c0 + tid] : 0;
+    const double *wsrc = rec.w + (size_t)(lo + c0) * RW;
+    double wv[WPT];
+#pragma unroll
+    for (int i = 0; i < WPT; ++i) {
+      const int t = tid + i * NT;
+      wv[i] = t < nw ? wsrc[t] : 0.0;
     }
-    // 1D weights: candidate j, axis d, tile position i
-    for (int t = threadIdx.x; t < nchunk * 3 * S; t += NT) {
-      const int j = t / (3 * S), d = (t / S) % 3, i = t % S;
-      const TileRec &r = rec[lo + c0 + j];
-      int a = (tc[d] * S + i - r.st[d]) % ng;
-      a += a < 0 ? ng : 0;
-      T w = (T)0;
-      if (a < P) {
-        const double dx = (r.st[d] + a) * g.h - r.x[d];
-        w = (T)(g.knorm * exp(-g.kcoef * dx * dx));
-      }
-      wts[d][j][i] = w;
+    if (tid < nchunk) {
+#pragma unroll
+      for (int k = 0; k < NCM; ++k)
+        if (k < cs.n) cq[tid * NCMP + k] = (T)q[(size_t)pj * lq.stride + cs.idx[k] - lq.off];
+    }
+#pragma unroll
+    for (int i = 0; i < WPT; ++i) {
+      const int t = tid + i * NT;
+      if (t < nw) wts[t] = (T)wv[i];
     }
     __syncthreads();
     for (int j = 0; j < nchunk; ++j) {
+      const T *wj = wts + j * RW;
+      const T wxy = wj[lx] * wj[S + ly];
+      T qk[NCM];
 #pragma unroll
-      for (int pt = 0; pt < PPT; ++pt) {
-        const T w = wts[0][j][lx[pt]] * wts[1][j][ly[pt]] * wts[2][j][lz[pt]];
+      for (int k = 0; k < NCM; ++k) qk[k] = cq[j * NCMP + k];
+#pragma unroll
+      for (int z = 0; z < ZPT; ++z) {
+        const T w = wxy * wj[2 * S + z0 + z];
 #pragma unroll
         for (int k = 0; k < NCM; ++k)
-          if (k < cs.n) acc[pt][k] += w * cq[k][j];
+          if (k < cs.n) acc[z][k] += w * qk[k];
       }
     }
   }
 #pragma unroll
-  for (int pt = 0; pt < PPT; ++pt) {
-    const size_t gi = ((size_t)(tc[2] * S + lz[pt]) * ng + tc[1] * S + ly[pt]) * ng
-                      + tc[0] * S + lx[pt];
+  for (int z = 0; z < ZPT; ++z) {
+    const size_t gi = ((size_t)(tc[2] * S + z0 + z) * ng + tc[1] * S + ly) * ng
+                      + tc[0] * S + lx;
 #pragma unroll
     for (int k = 0; k < NCM; ++k)
-      if (k < cs.n) grids[(size_t)k * ngrid + gi] = acc[pt][k];
+      if (k < cs.n) grids[(size_t)k * ngrid + gi] = acc[z][k];
   }
 }
 
@@ -752,6 +762,17 @@ void build_ktable(Handle &h) {
   }
 }
 
+namespace {
+
+// The record arrays inside the handle's tile-record allocation: tl_cap
+// particle indices, then (from a 256-byte boundary) tl_cap x 3 S weights.
+TileRecs tile_recs(const Handle &h) {
+  const size_t off = (h.tl_cap * sizeof(int) + 255) / 256 * 256;
+  return TileRecs{(int *)h.tl_rec, (double *)((char *)h.tl_rec + off)};
+}
+
+}  // namespace
+
 // Candidate lists of the spreading tiles for wrapped positions xw (after the
 // spreading bins are current).
 // The capacity N * (ceil((P-1)/S) + 1)^3 is the most tiles a stencil can
@@ -764,16 +785,16 @@ void build_tile_lists(Handle &h, const double *xw) {
   const unsigned blocks = (unsigned)((ntile + 3) / 4);
   hipLaunchKernelGGL((tile_list_kernel<false>), dim3(blocks), dim3(256), 0, h.stream, xw, g,
                      h.stile, nb, (const int *)h.sbins.start, (const int *)h.sbins.perm,
-                     h.tl_cnt, nullptr, nullptr);
+                     h.tl_cnt, nullptr, TileRecs{nullptr, nullptr});
   PSE_LAUNCH_CHECK();
   exclusive_scan(h, h.tl_cnt, h.tl_start, h.tl_scan, ntile);
   hipLaunchKernelGGL((tile_list_kernel<true>), dim3(blocks), dim3(256), 0, h.stream, xw, g,
                      h.stile, nb, (const int *)h.sbins.start, (const int *)h.sbins.perm, nullptr,
-                     (const int *)h.tl_start, (TileRec *)h.tl_rec);
+                     (const int *)h.tl_start, tile_recs(h));
   PSE_LAUNCH_CHECK();
 }
 
-size_t tile_record_bytes() { return sizeof(TileRec); }
+size_t tile_record_bytes(int S) { return sizeof(int) + 3 * (size_t)S * sizeof(double); }
 
 namespace {
 
@@ -795,16 +816,19 @@ void spread(Handle &h, const double *x, const double *q, Layout lq, const CompSe
     ProfScope ps(h, PK_SPREAD, (double)cs.n * h.ngrid * sizeof(T) + (double)h.n * (3 + cs.n) * 8);
     const int nb = h.sbins.nc;
     const unsigned tiles = (unsigned)nb * nb * nb;
-    const TileRec *rec = (const TileRec *)h.tl_rec;
+    const TileRecs rec = tile_recs(h);
     const int *ts = (const int *)h.tl_start;
     with_ncm(cs.n, [&](auto ncm) {
       constexpr int M = decltype(ncm)::value;
+      // z points per thread: a whole column of the tile while the
+      // accumulators fit, half of it for the 11-component product
+      constexpr int Z8 = M <= 6 ? 8 : 4;
       if (h.stile == 4)
-        hipLaunchKernelGGL((spread_list_kernel<T, 4, M>), dim3(tiles), dim3(64), 0, h.stream,
-                           q, lq, cs, g, nb, ts, rec, grids, h.ngrid);
+        hipLaunchKernelGGL((spread_list_kernel<T, 4, M, 1>), dim3(tiles), dim3(64), 0,
+                           h.stream, q, lq, cs, g, nb, ts, rec, grids, h.ngrid);
       else if (h.stile == 8)
-        hipLaunchKernelGGL((spread_list_kernel<T, 8, M>), dim3(tiles), dim3(256), 0, h.stream,
-                           q, lq, cs, g, nb, ts, rec, grids, h.ngrid);
+        hipLaunchKernelGGL((spread_list_kernel<T, 8, M, Z8>), dim3(tiles), dim3(512 / Z8), 0,
+                           h.stream, q, lq, cs, g, nb, ts, rec, grids, h.ngrid);
       else
         throw Error{PSE_ERR_INVALID, "unsupported spreading tile"};
     });

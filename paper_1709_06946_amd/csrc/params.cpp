@@ -110,9 +110,11 @@ size_t footprint(const pse_params &p, const pse_derived &d) {
   const int S = spread_tile(d.grid, d.support);
   const size_t tiles3 = S ? ng3 / ((size_t)S * S * S) : 0;
   if (S) {
-    // tile CSR and one 40-byte record per (tile, particle) pair
+    // tile CSR and one record per (tile, particle) pair: the particle index
+    // and 3 S one-dimensional weights
     const size_t cap = n * tiles_per_particle(d.support, S);
-    bytes += (2 * tiles3 + tiles3 / 1024 + 16) * sizeof(int) + cap * 40;
+    bytes += (2 * tiles3 + tiles3 / 1024 + 16) * sizeof(int)
+             + cap * (sizeof(int) + 3 * (size_t)S * sizeof(double)) + 256;
   }
   bytes += (2 * (ncell3 + tiles3) + 4 + (ncell3 + tiles3) / 1024 + 16) * sizeof(int)
            + 6 * n * sizeof(int);

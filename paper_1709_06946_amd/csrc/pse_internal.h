@@ -30,7 +30,9 @@ struct Error {
     if (e_ != hipSuccess)                                                    \
       throw ::pse::Error{e_ == hipErrorOutOfMemory ? PSE_ERR_NOMEM          \
                                                    : PSE_ERR_HIP,            \
-                         std::string(#call) + ": " + hipGetErrorString(e_)}; \
+                         std::string(#call) + " (" + __FILE__ + ":" +       \
+                             std::to_string(__LINE__) + "): " +                \
+                             hipGetErrorString(e_)};                           \
   } while (0)
 
 #define PSE_LAUNCH_CHECK() PSE_HIP(hipGetLastError())
@@ -147,9 +149,10 @@ struct Handle {
   double *pl_rec = nullptr;
   size_t pl_cap = 0, pl_pairs = 0;
   // spreading-tile candidate lists (CSR over tiles): one record per (tile,
-  // particle) pair
+  // particle) pair, tl_cap records at most
   int *tl_cnt = nullptr, *tl_start = nullptr, *tl_scan = nullptr;
   void *tl_rec = nullptr;
+  size_t tl_cap = 0;
 
   // Krylov storage
   double *lz_V = nullptr;    // (lanczos_maxit + 1) x 11N
@@ -169,11 +172,26 @@ struct Handle {
   int lz_prev = 0;
   int gm_prev[2] = {0, 0};
   bool graph_warm = false;   // one eager application before the first capture
+  std::string graph_error;   // why graphs were switched off after a failed capture
   std::map<std::tuple<const void *, const void *, int>, hipGraphExec_t> graphs;
 };
 
 // Destroys every captured graph of the handle.
 void clear_graphs(Handle &h);
+
+// Sets the calling thread's stream-capture interaction mode to relaxed for
+// the scope (restoring the previous mode after).  Allocations, frees and
+// synchronous copies made by this thread while another thread captures a
+// graph on its own stream are then not refused; the library's captures hold
+// kernel launches on the capturing handle's stream only, which such calls do
+// not touch.
+struct RelaxedCaptureScope {
+  hipStreamCaptureMode prev = hipStreamCaptureModeRelaxed;
+  RelaxedCaptureScope() { (void)hipThreadExchangeStreamCaptureMode(&prev); }
+  ~RelaxedCaptureScope() { (void)hipThreadExchangeStreamCaptureMode(&prev); }
+  RelaxedCaptureScope(const RelaxedCaptureScope &) = delete;
+  RelaxedCaptureScope &operator=(const RelaxedCaptureScope &) = delete;
+};
 
 // Brackets the launches of one stage with events when profiling is on.
 struct ProfScope {
@@ -237,7 +255,7 @@ void kspace_fused(Handle &h, const cplx<T> *in, const CompSet &cin, cplx<T> *out
                   const CompSet &cout, const cplx<T> *tw);
 template <typename T> void zero_grids(Handle &h, T *g, int ncomp);
 void build_tile_lists(Handle &h, const double *xw);
-size_t tile_record_bytes();                       // one (tile, particle) record
+size_t tile_record_bytes(int S);                  // one (tile, particle) record
 int ktable_len(int grid);                         // entries of the |k|^2 table
 void build_ktable(Handle &h);
 template <typename T> void from_double(Handle &h, const double *src, size_t n, T *dst);

@@ -127,6 +127,11 @@ void run_request(pse_server *s, Req &q) {
 
 void worker(pse_server *s) {
   (void)hipSetDevice(s->device);
+  // requests are created, copied and freed here while other workers'
+  // handles capture their operator graphs: relaxed capture interaction for
+  // this thread (it ends with the server)
+  hipStreamCaptureMode mode = hipStreamCaptureModeRelaxed;
+  (void)hipThreadExchangeStreamCaptureMode(&mode);
   for (;;) {
     std::shared_ptr<Req> q;
     {
@@ -262,6 +267,14 @@ int pse_server_result(pse_server *s, int64_t id, double *x_out, double *step_ms)
   if (x_out && !q->x_out.empty()) std::memcpy(x_out, q->x_out.data(), q->x_out.size() * 8);
   if (step_ms && !q->lat_ms.empty()) std::memcpy(step_ms, q->lat_ms.data(), q->lat_ms.size() * 8);
   return PSE_OK;
+}
+
+const char *pse_server_error(pse_server *s, int64_t id) {
+  if (!s) return "";
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->all.find(id);
+  if (it == s->all.end() || it->second->status >= 0) return "";
+  return it->second->err.c_str();
 }
 
 int pse_server_release(pse_server *s, int64_t id) {

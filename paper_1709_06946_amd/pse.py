@@ -95,7 +95,7 @@ EXPORTS = ('pse_derive', 'pse_footprint_bytes', 'pse_create', 'pse_destroy',
            'pse_constrained_step', 'pse_fft3d', 'pse_spread', 'pse_interpolate',
            'pse_profile', 'pse_profile_read', 'pse_server_create', 'pse_server_submit',
            'pse_server_wait', 'pse_server_result', 'pse_server_release', 'pse_server_stats',
-           'pse_server_destroy', 'pse_last_error')
+           'pse_server_destroy', 'pse_server_error', 'pse_last_error')
 
 
 def load_library(path=LIB_PATH):
@@ -134,10 +134,12 @@ def load_library(path=LIB_PATH):
     lib.pse_server_release.argtypes = [V, ctypes.c_int64]
     lib.pse_server_stats.argtypes = [V, P(pse_server_info)]
     lib.pse_server_destroy.argtypes = [V]
+    lib.pse_server_error.argtypes = [V, ctypes.c_int64]
+    lib.pse_server_error.restype = ctypes.c_char_p
     lib.pse_last_error.argtypes = [V]
     lib.pse_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
-        if name != 'pse_last_error':
+        if name not in ('pse_last_error', 'pse_server_error'):
             getattr(lib, name).restype = I
     return lib
 
@@ -342,7 +344,8 @@ class PSEServer:
         info = pse_request_info()
         rc = lib().pse_server_wait(self._h, int(rid), ctypes.byref(info))
         if rc < 0:
-            raise PSEError(f'request {rid} failed: {rc}')
+            msg = lib().pse_server_error(self._h, int(rid)).decode()
+            raise PSEError(f'request {rid} failed: {rc}: {msg}')
         return info.as_dict()
 
     def result(self, rid):

@@ -159,3 +159,10 @@ def test_library_binds_to_torchs_hip_runtime():
                          cwd=ROOT, check=True).stdout
     paths = eval(out.strip())
     assert len(paths) == 1 and 'torch' in paths[0], paths
+
+
+def test_server_error_without_server_is_empty(pse):
+    """pse_server_error never returns NULL: "" for a null server or an
+    unknown request (no device needed)."""
+    lib = pse.load_library()
+    assert lib.pse_server_error(None, 1) == b''
