@@ -174,6 +174,8 @@ static void prepare_positions(Handle &h, const double *x, double *xw) {
 }
 
 void clear_graphs(Handle &h) {
+  if (h.graphs.empty()) return;
+  std::unique_lock<std::shared_mutex> lk(capture_gate());
   for (auto &kv : h.graphs) (void)hipGraphExecDestroy(kv.second);
   h.graphs.clear();
 }
@@ -203,6 +205,7 @@ static void run_graphed(Handle &h, const void *in, const void *out, int kind, F 
     hipGraph_t g = nullptr;
     hipGraphExec_t ex = nullptr;
     std::string why;
+    std::shared_lock<std::shared_mutex> gate(capture_gate());
     hipError_t e = hipStreamBeginCapture(h.stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) {
       why = std::string("hipStreamBeginCapture: ") + hipGetErrorString(e);
@@ -211,6 +214,8 @@ static void run_graphed(Handle &h, const void *in, const void *out, int kind, F 
         fn();
       } catch (const Error &err) {
         why = "launch during capture: " + err.msg;
+      } catch (...) {
+        why = "exception during capture";
       }
       e = hipStreamEndCapture(h.stream, &g);
       if (why.empty() && e != hipSuccess)
@@ -224,6 +229,7 @@ static void run_graphed(Handle &h, const void *in, const void *out, int kind, F 
       }
       if (g) (void)hipGraphDestroy(g);
     }
+    gate.unlock();
     if (!why.empty()) {
       (void)hipGetLastError();
       h.use_graphs = false;
@@ -316,7 +322,28 @@ void prof_resolve(Handle &h) {
   P.used = 0;
 }
 
-static void alloc(void **p, size_t bytes) { PSE_HIP(hipMalloc(p, bytes)); }
+std::shared_mutex &capture_gate() {
+  static std::shared_mutex m;
+  return m;
+}
+
+void dev_alloc(void **p, size_t bytes) {
+  std::unique_lock<std::shared_mutex> lk(capture_gate());
+  PSE_HIP(hipMalloc(p, bytes));
+}
+
+void dev_free(void *p) {
+  if (!p) return;
+  std::unique_lock<std::shared_mutex> lk(capture_gate());
+  (void)hipFree(p);
+}
+
+hipError_t dev_copy(void *dst, const void *src, size_t bytes, hipMemcpyKind kind) {
+  std::unique_lock<std::shared_mutex> lk(capture_gate());
+  return hipMemcpy(dst, src, bytes, kind);
+}
+
+static void alloc(void **p, size_t bytes) { dev_alloc(p, bytes); }
 
 static void create(const pse_params &p, Handle &h) {
   derive(p, h.d);
@@ -334,6 +361,7 @@ static void create(const pse_params &p, Handle &h) {
     h.stream = (hipStream_t)p.stream;
     h.own_stream = false;
   } else {
+    std::unique_lock<std::shared_mutex> lk(capture_gate());
     PSE_HIP(hipStreamCreateWithFlags(&h.stream, hipStreamNonBlocking));
     h.own_stream = true;
   }
@@ -417,15 +445,20 @@ static void release(Handle &h) {
                   h.pl_start, h.pl_scan, h.pl_nbr, h.pl_rec, h.tl_cnt, h.tl_start,
                   h.tl_scan, h.tl_rec, h.bad_pos, h.ktab32};
   for (void *p : ptrs)
-    if (p) (void)hipFree(p);
+    dev_free(p);
   clear_graphs(h);
   for (hipEvent_t e : h.prof.pool) (void)hipEventDestroy(e);
   h.prof.pool.clear();
-  if (h.own_stream && h.stream) (void)hipStreamDestroy(h.stream);
+  if (h.own_stream && h.stream) {
+    std::unique_lock<std::shared_mutex> lk(capture_gate());
+    (void)hipStreamDestroy(h.stream);
+  }
 }
 
 template <typename F> static int guarded(pse_handle *hd, F &&f) {
   RelaxedCaptureScope relaxed;
+  // an error left by the caller's own runtime calls is not this call's
+  (void)hipGetLastError();
   try {
     f();
     if (hd && !hd->h.prof.pending.empty()) {

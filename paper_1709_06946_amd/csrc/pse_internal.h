@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <functional>
 #include <map>
+#include <shared_mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -158,7 +159,6 @@ struct Handle {
   double *lz_V = nullptr;    // (lanczos_maxit + 1) x 11N
   double *gm_V = nullptr;    // (gmres_restart + 1) x 5N
   double *small = nullptr;   // device scratch for dots / tridiagonal / Hessenberg
-  double *host_small = nullptr;  // pinned mirror
   size_t small_len;
   double *dots = nullptr;    // partial sums for reductions
   size_t dots_len;
@@ -178,6 +178,17 @@ struct Handle {
 
 // Destroys every captured graph of the handle.
 void clear_graphs(Handle &h);
+
+// The runtime refuses allocations, frees and legacy-stream copies while any
+// stream of the process captures a graph (and such a call invalidates the
+// capture), even when the capturing stream is non-blocking and owned by
+// another thread.  The library's captures hold this gate shared; its
+// allocations, frees and synchronous copies (dev_alloc, dev_free, dev_copy)
+// hold it exclusively, so the two never overlap across threads.
+std::shared_mutex &capture_gate();
+void dev_alloc(void **p, size_t bytes);          // hipMalloc; throws on failure
+void dev_free(void *p);                          // hipFree of a non-null pointer
+hipError_t dev_copy(void *dst, const void *src, size_t bytes, hipMemcpyKind kind);
 
 // Sets the calling thread's stream-capture interaction mode to relaxed for
 // the scope (restoring the previous mode after).  Allocations, frees and

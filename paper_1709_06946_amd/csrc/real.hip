@@ -151,8 +151,8 @@ void build_tables(Handle &h) {
   h.n2a = 2048;
   h.dr = 2.0 * a / h.n2a;
   h.ntab = (int)std::ceil(h.d.rcut / h.dr) + 8;
-  PSE_HIP(hipMalloc(&h.g64.table, (size_t)h.ntab * NCOEF * sizeof(double)));
-  PSE_HIP(hipMalloc(&h.g32.table, (size_t)h.ntab * NCOEF * sizeof(float)));
+  dev_alloc((void **)&h.g64.table, (size_t)h.ntab * NCOEF * sizeof(double));
+  dev_alloc((void **)&h.g32.table, (size_t)h.ntab * NCOEF * sizeof(float));
   const double rmax = h.ntab * h.dr;
   const double dk = M_PI / (2.0 * a + rmax + 7.0 / xi);
   const double kmax = 2.0 * xi * std::sqrt(50.0);
@@ -608,13 +608,13 @@ static void build_pair_list(Handle &h, const double *xw) {
   if ((size_t)total > h.pl_cap) {
     clear_graphs(h);   // captured real-space launches hold the old buffers
     const size_t cap = (size_t)total + total / 4 + 1024;
-    PSE_HIP(hipFree(h.pl_nbr));
-    PSE_HIP(hipFree(h.pl_rec));
+    dev_free(h.pl_nbr);
+    dev_free(h.pl_rec);
     h.pl_nbr = nullptr;
     h.pl_rec = nullptr;
     h.pl_cap = 0;
-    PSE_HIP(hipMalloc((void **)&h.pl_nbr, cap * sizeof(int)));
-    PSE_HIP(hipMalloc((void **)&h.pl_rec, cap * PAIR_REC * sizeof(double)));
+    dev_alloc((void **)&h.pl_nbr, cap * sizeof(int));
+    dev_alloc((void **)&h.pl_rec, cap * PAIR_REC * sizeof(double));
     h.pl_cap = cap;
   }
   h.pl_pairs = (size_t)total;

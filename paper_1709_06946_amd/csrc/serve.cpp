@@ -26,6 +26,7 @@
 #include <vector>
 
 #include "../../include/pse.h"
+#include "pse_internal.h"
 
 namespace {
 
@@ -94,16 +95,28 @@ void run_request(pse_server *s, Req &q) {
   }
   const size_t n = (size_t)q.r.n;
   double *dx = nullptr, *dfl = nullptr;
-  if (hipMalloc(&dx, 3 * n * sizeof(double)) != hipSuccess ||
-      (q.r.FL && hipMalloc(&dfl, 6 * n * sizeof(double)) != hipSuccess)) {
+  try {
+    pse::dev_alloc((void **)&dx, 3 * n * sizeof(double));
+    if (q.r.FL) pse::dev_alloc((void **)&dfl, 6 * n * sizeof(double));
+  } catch (const pse::Error &e) {
     q.rc = PSE_ERR_NOMEM;
-    q.err = "device allocation of request state failed";
-    (void)hipFree(dx);
+    q.err = "device allocation of request state failed: " + e.msg;
+    pse::dev_free(dx);
     pse_destroy(h);
     return;
   }
-  (void)hipMemcpy(dx, q.x0.data(), 3 * n * sizeof(double), hipMemcpyHostToDevice);
-  if (dfl) (void)hipMemcpy(dfl, q.fl.data(), 6 * n * sizeof(double), hipMemcpyHostToDevice);
+  hipError_t ce = pse::dev_copy(dx, q.x0.data(), 3 * n * sizeof(double),
+                                hipMemcpyHostToDevice);
+  if (ce == hipSuccess && dfl)
+    ce = pse::dev_copy(dfl, q.fl.data(), 6 * n * sizeof(double), hipMemcpyHostToDevice);
+  if (ce != hipSuccess) {
+    q.rc = PSE_ERR_HIP;
+    q.err = std::string("copy of request inputs: ") + hipGetErrorString(ce);
+    pse::dev_free(dx);
+    pse::dev_free(dfl);
+    pse_destroy(h);
+    return;
+  }
   double tprev = s->now();
   for (int k = 0; k < q.r.steps; ++k) {
     pse_stats st{};
@@ -119,9 +132,13 @@ void run_request(pse_server *s, Req &q) {
     if (rc > 0) q.rc = rc;
   }
   q.x_out.resize(3 * n);
-  (void)hipMemcpy(q.x_out.data(), dx, 3 * n * sizeof(double), hipMemcpyDeviceToHost);
-  (void)hipFree(dx);
-  (void)hipFree(dfl);
+  ce = pse::dev_copy(q.x_out.data(), dx, 3 * n * sizeof(double), hipMemcpyDeviceToHost);
+  if (ce != hipSuccess && q.rc >= 0) {
+    q.rc = PSE_ERR_HIP;
+    q.err = std::string("copy of request results: ") + hipGetErrorString(ce);
+  }
+  pse::dev_free(dx);
+  pse::dev_free(dfl);
   pse_destroy(h);
 }
 

@@ -63,3 +63,28 @@ def test_alone_equals_mix_and_budget_respected():
     # requests overlapped in time on the device
     spans = sorted((i['t_admit'], i['t_done']) for i, _, _ in mix)
     assert any(spans[k + 1][0] < spans[k][1] for k in range(len(spans) - 1))
+
+
+def test_creates_and_copies_overlapping_captures_do_not_fail():
+    """Many short requests, six at a time, in both precisions: handles are
+    created, filled and freed by some workers while others capture their
+    constraint-operator graphs.  Those calls and the captures are kept apart
+    by the library, so no request fails and every result is finite."""
+    from paper_1709_06946_amd import pse
+    srv = pse.PSEServer(max_active=6)
+    ids = []
+    for i in range(18):
+        n = 400 + 150 * (i % 7)
+        x, L = inputs.packing(n, 0.1 + 0.05 * (i % 5), seed=inputs.SEED_BASE + 400 + i)
+        FL = inputs.forces_torques(n, inputs.SEED_BASE + 500 + i)
+        ids.append(srv.submit(x, L, FL=FL, steps=3, seed=2000 + i, grid=pse.grid_for(L),
+                              precision=pse.PSE_MIXED if i % 2 else pse.PSE_FP64))
+    for rid in ids:
+        info = srv.wait(rid)
+        x, lat = srv.result(rid)
+        assert info['status'] >= 0 and np.isfinite(x).all() and len(lat) == 3
+    st = srv.stats()
+    srv.close()
+    print('peak active', st['peak_active'], 'completed', st['completed'])
+    assert st['failed'] == 0 and st['completed'] == 18
+    assert st['peak_active'] >= 2
