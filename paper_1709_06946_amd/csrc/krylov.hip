@@ -35,7 +35,6 @@ multi_dot_partial(const double *__restrict__ V, size_t ldv, const double *__rest
   const int j = blockIdx.y;
   const double *v = V + (size_t)j * ldv;
   double acc = 0.0;
-#pragma unroll 4
   for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
     acc += v[i] * w[i];
   s[threadIdx.x] = acc;
@@ -65,45 +64,33 @@ reduce_partial(const double *__restrict__ partial, int nb, double *__restrict__ 
 // ---- fused classical Gram-Schmidt with a second pass (CGS2) ----
 //
 // One Arnoldi / Lanczos step orthogonalises w = A v_m against V = [v_0 ..
-// v_{m-1}] twice.  Five launches do it: the partial dot products of the
-// first pass (multi_dot_partial, nb blocks per coefficient); sub_coef_kernel,
-// whose blocks each sum those partials and subtract V h1 from their share of
-// w; the partial dot products of the second pass ([V, w]^T w); the
-// small-matrix kernel of the method (Hessenberg column and Givens rotation,
-// or Lanczos tridiagonal entries and square root), which sums the second
-// partials itself; and sub_scale_fused_kernel, which sums them again,
-// subtracts V h2 and divides by the norm.  Every sum of partials runs in one
-// fixed order, so all blocks and kernels that need a coefficient get the
-// same bits.
+// v_{m-1}] twice.  Four launches do it: the partial dot products of the first
+// pass (multi_dot_partial, nb blocks); sub_dot_kernel, whose blocks each sum
+// those partials, subtract V h1 from their share of w and form the partial
+// dot products of the second pass (V^T w and w.w); the small-matrix kernel of
+// the method (Hessenberg column and Givens rotation, or Lanczos tridiagonal
+// entries and square root), which sums the second partials itself; and
+// sub_scale_fused_kernel, which sums them again, subtracts V h2 and divides
+// by the norm.  Every sum of partials runs in one fixed order, so all blocks
+// and kernels that need a coefficient get the same bits.
 
-constexpr int MAXC = 512;      // most coefficients of one reduction (m + 1)
-constexpr int STAGE = 1024;    // partials staged in LDS at a time (>= RED_BLOCKS)
+constexpr int MAXC = 512;   // most coefficients of one reduction (m + 1)
 
-// out[j] = sum over b < nb of part[j * nb + b] for j < cnt (nb <= STAGE).
-// The partials of as many coefficients as fit are staged in LDS with all
-// loads in flight; then one wavefront per coefficient sums them, lane l
-// taking b = l, l + 64, ... in order, and a butterfly over the lanes (every
-// lane ends with the same bits), so the result does not depend on the
-// caller's block size.  Ends with a barrier.
-__device__ void reduce_partials(const double *__restrict__ part, int cnt, int nb, double *out,
-                                double *stage) {
+// out[j] = sum over b < nb of part[j * nb + b] for j < cnt: one wavefront per
+// coefficient, lane l summing b = l, l + 64, ... and a butterfly over the
+// lanes (every lane ends with the same bits), so the result does not depend
+// on the caller's block size.  Ends with a barrier.
+__device__ void reduce_partials(const double *__restrict__ part, int cnt, int nb,
+                                double *out) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  const int per = STAGE / nb;
-  for (int c0 = 0; c0 < cnt; c0 += per) {
-    const int cc = min(per, cnt - c0);
-    const double *src = part + (size_t)c0 * nb;
-#pragma unroll 8
-    for (int t = threadIdx.x; t < cc * nb; t += blockDim.x) stage[t] = src[t];
-    __syncthreads();
-    for (int j = wv; j < cc; j += nw) {
-      double a = 0.0;
-      for (int b = lane; b < nb; b += 64) a += stage[j * nb + b];
+  for (int j = wv; j < cnt; j += nw) {
+    double a = 0.0;
+    for (int b = lane; b < nb; b += 64) a += part[(size_t)j * nb + b];
 #pragma unroll
-      for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
-      if (lane == 0) out[c0 + j] = a;
-    }
-    __syncthreads();
+    for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
+    if (lane == 0) out[j] = a;
   }
+  __syncthreads();
 }
 
 // Norm of the twice-orthogonalised vector: h2[0..m-1] = V^T w and h2[m] =
@@ -115,22 +102,40 @@ __device__ __forceinline__ double cgs2_norm(const double *h2, int m) {
   return sqrt(fmax(h2[m] - p2, 0.0));
 }
 
-// Grid-stride over n with nb blocks of 256 threads: h1 = the sum of part1
-// (m rows of nb partials; written to h1 by block 0), then w -= V h1.
+// Grid-stride over n with gridDim.x == nb blocks of 256 threads: h1 = sum of
+// part1 (written to h1 by block 0), w -= V h1, then the partial sums of
+// V_j . w (j < m) and w . w into part2[j * nb + block] (j <= m).
 __global__ void __launch_bounds__(256)
-sub_coef_kernel(double *__restrict__ w, const double *__restrict__ V, size_t ldv, int m,
-                const double *__restrict__ part1, int nb, double *__restrict__ h1, size_t n) {
+sub_dot_kernel(double *__restrict__ w, const double *__restrict__ V, size_t ldv, int m,
+               const double *__restrict__ part1, double *__restrict__ h1,
+               double *__restrict__ part2, size_t n) {
   __shared__ double coef[MAXC];
-  __shared__ double stage[STAGE];
-  reduce_partials(part1, m, nb, coef, stage);
+  __shared__ double red[4][MAXC];
+  const int nb = gridDim.x;
+  reduce_partials(part1, m, nb, coef);
   if (blockIdx.x == 0)
     for (int j = threadIdx.x; j < m; j += blockDim.x) h1[j] = coef[j];
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (size_t)gridDim.x * blockDim.x) {
+  const size_t i0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t stride = (size_t)nb * blockDim.x;
+  for (size_t i = i0; i < n; i += stride) {
     double acc = 0.0;
     for (int j = 0; j < m; ++j) acc += coef[j] * V[(size_t)j * ldv + i];
     w[i] -= acc;
   }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int j = 0; j <= m; ++j) {
+    double a = 0.0;
+    for (size_t i = i0; i < n; i += stride) {
+      const double wi = w[i];
+      a += (j < m ? V[(size_t)j * ldv + i] : wi) * wi;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
+    if (lane == 0) red[wv][j] = a;
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j <= m; j += blockDim.x)
+    part2[(size_t)j * nb + blockIdx.x] = red[0][j] + red[1][j] + red[2][j] + red[3][j];
 }
 
 // w = (w - V h2) / |.| with h2 and the norm summed from part2 (nb blocks'
@@ -139,8 +144,7 @@ __global__ void __launch_bounds__(256)
 sub_scale_fused_kernel(double *__restrict__ w, const double *__restrict__ V, size_t ldv,
                        int m, const double *__restrict__ part2, int nb, size_t n) {
   __shared__ double h2[MAXC];
-  __shared__ double stage[STAGE];
-  reduce_partials(part2, m + 1, nb, h2, stage);
+  reduce_partials(part2, m + 1, nb, h2);
   const double nn = cgs2_norm(h2, m);
   const double f = nn > 0.0 ? 1.0 / nn : 0.0;
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -375,8 +379,7 @@ lanczos_step_kernel(double *alpha, double *beta, int j, const double *h1,
                     double *out_change, double *chg_hist) {
   extern __shared__ double lds_work[];
   __shared__ double h2[MAXC];
-  __shared__ double stage[STAGE];
-  reduce_partials(part2, j + 2, nb, h2, stage);
+  reduce_partials(part2, j + 2, nb, h2);
   if (threadIdx.x != 0) return;
   alpha[j] = h1[j] + h2[j];
   const double nn = cgs2_norm(h2, j + 1);
@@ -406,8 +409,7 @@ hess_givens_kernel(double *H, int ldh, int j, const double *h1, const double *pa
                    double *cs, double *sn, double *g, double *resid, double *vn_hist,
                    double *res_hist) {
   __shared__ double h2[MAXC];
-  __shared__ double stage[STAGE];
-  reduce_partials(part2, j + 2, nb, h2, stage);
+  reduce_partials(part2, j + 2, nb, h2);
   if (threadIdx.x != 0) return;
   double *col = H + (size_t)j * ldh;
   for (int i = 0; i <= j; ++i) col[i] = h1[i] + h2[i];
@@ -489,11 +491,8 @@ static double *cgs2_first(Handle &h, const double *V, size_t n, int m, double *w
   hipLaunchKernelGGL(multi_dot_partial, dim3(nb, m), dim3(256), 0, h.stream, V, n, w, n,
                      part1);
   PSE_LAUNCH_CHECK();
-  hipLaunchKernelGGL(sub_coef_kernel, dim3(nb), dim3(256), 0, h.stream, w, V, n, m, part1, nb,
-                     h1, n);
-  PSE_LAUNCH_CHECK();
-  hipLaunchKernelGGL(multi_dot_partial, dim3(nb, m + 1), dim3(256), 0, h.stream, V, n, w, n,
-                     part2);
+  hipLaunchKernelGGL(sub_dot_kernel, dim3(nb), dim3(256), 0, h.stream, w, V, n, m, part1, h1,
+                     part2, n);
   PSE_LAUNCH_CHECK();
   return part2;
 }
