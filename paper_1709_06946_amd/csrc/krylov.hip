@@ -61,98 +61,27 @@ reduce_partial(const double *__restrict__ partial, int nb, double *__restrict__ 
   if (threadIdx.x == 0) out[j] = s[0];
 }
 
-// ---- fused classical Gram-Schmidt with a second pass (CGS2) ----
-//
-// One Arnoldi / Lanczos step orthogonalises w = A v_m against V = [v_0 ..
-// v_{m-1}] twice.  Four launches do it: the partial dot products of the first
-// pass (multi_dot_partial, nb blocks); sub_dot_kernel, whose blocks each sum
-// those partials, subtract V h1 from their share of w and form the partial
-// dot products of the second pass (V^T w and w.w); the small-matrix kernel of
-// the method (Hessenberg column and Givens rotation, or Lanczos tridiagonal
-// entries and square root), which sums the second partials itself; and
-// sub_scale_fused_kernel, which sums them again, subtracts V h2 and divides
-// by the norm.  Every sum of partials runs in one fixed order, so all blocks
-// and kernels that need a coefficient get the same bits.
-
-constexpr int MAXC = 512;   // most coefficients of one reduction (m + 1)
-
-// out[j] = sum over b < nb of part[j * nb + b] for j < cnt: one wavefront per
-// coefficient, lane l summing b = l, l + 64, ... and a butterfly over the
-// lanes (every lane ends with the same bits), so the result does not depend
-// on the caller's block size.  Ends with a barrier.
-__device__ void reduce_partials(const double *__restrict__ part, int cnt, int nb,
-                                double *out) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  for (int j = wv; j < cnt; j += nw) {
-    double a = 0.0;
-    for (int b = lane; b < nb; b += 64) a += part[(size_t)j * nb + b];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
-    if (lane == 0) out[j] = a;
-  }
-  __syncthreads();
+// w -= sum_j coef_j V_j
+__global__ void sub_multi_kernel(double *__restrict__ w, const double *__restrict__ V,
+                                 size_t ldv, int m, const double *__restrict__ coef,
+                                 size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double acc = 0.0;
+  for (int j = 0; j < m; ++j) acc += coef[j] * V[(size_t)j * ldv + i];
+  w[i] -= acc;
 }
 
-// Norm of the twice-orthogonalised vector: h2[0..m-1] = V^T w and h2[m] =
-// w.w after the first pass, so |w - V h2| = sqrt(w.w - |h2|^2) (V
-// orthonormal).
-__device__ __forceinline__ double cgs2_norm(const double *h2, int m) {
-  double p2 = 0.0;
-  for (int i = 0; i < m; ++i) p2 += h2[i] * h2[i];
-  return sqrt(fmax(h2[m] - p2, 0.0));
-}
-
-// Grid-stride over n with gridDim.x == nb blocks of 256 threads: h1 = sum of
-// part1 (written to h1 by block 0), w -= V h1, then the partial sums of
-// V_j . w (j < m) and w . w into part2[j * nb + block] (j <= m).
-__global__ void __launch_bounds__(256)
-sub_dot_kernel(double *__restrict__ w, const double *__restrict__ V, size_t ldv, int m,
-               const double *__restrict__ part1, double *__restrict__ h1,
-               double *__restrict__ part2, size_t n) {
-  __shared__ double coef[MAXC];
-  __shared__ double red[4][MAXC];
-  const int nb = gridDim.x;
-  reduce_partials(part1, m, nb, coef);
-  if (blockIdx.x == 0)
-    for (int j = threadIdx.x; j < m; j += blockDim.x) h1[j] = coef[j];
-  const size_t i0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const size_t stride = (size_t)nb * blockDim.x;
-  for (size_t i = i0; i < n; i += stride) {
-    double acc = 0.0;
-    for (int j = 0; j < m; ++j) acc += coef[j] * V[(size_t)j * ldv + i];
-    w[i] -= acc;
-  }
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int j = 0; j <= m; ++j) {
-    double a = 0.0;
-    for (size_t i = i0; i < n; i += stride) {
-      const double wi = w[i];
-      a += (j < m ? V[(size_t)j * ldv + i] : wi) * wi;
-    }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
-    if (lane == 0) red[wv][j] = a;
-  }
-  __syncthreads();
-  for (int j = threadIdx.x; j <= m; j += blockDim.x)
-    part2[(size_t)j * nb + blockIdx.x] = red[0][j] + red[1][j] + red[2][j] + red[3][j];
-}
-
-// w = (w - V h2) / |.| with h2 and the norm summed from part2 (nb blocks'
-// partials, m + 1 rows); grid-stride over n.
-__global__ void __launch_bounds__(256)
-sub_scale_fused_kernel(double *__restrict__ w, const double *__restrict__ V, size_t ldv,
-                       int m, const double *__restrict__ part2, int nb, size_t n) {
-  __shared__ double h2[MAXC];
-  reduce_partials(part2, m + 1, nb, h2);
-  const double nn = cgs2_norm(h2, m);
-  const double f = nn > 0.0 ? 1.0 / nn : 0.0;
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (size_t)gridDim.x * blockDim.x) {
-    double acc = 0.0;
-    for (int j = 0; j < m; ++j) acc += h2[j] * V[(size_t)j * ldv + i];
-    w[i] = (w[i] - acc) * f;
-  }
+// w = (w - sum_{j<m} coef_j V_j) / s with s a device scalar (0 if s <= 0)
+__global__ void sub_scale_kernel(double *__restrict__ w, const double *__restrict__ V,
+                                 size_t ldv, int m, const double *__restrict__ coef,
+                                 const double *__restrict__ s, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double acc = 0.0;
+  for (int j = 0; j < m; ++j) acc += coef[j] * V[(size_t)j * ldv + i];
+  const double f = s[0] > 0.0 ? 1.0 / s[0] : 0.0;
+  w[i] = (w[i] - acc) * f;
 }
 
 // y = (acc ? y : 0) + alpha sum_j coef_j V_j
@@ -226,6 +155,14 @@ void multi_dot(Handle &h, const double *V, size_t ldv, int m, const double *w,
                      h.dots);
   PSE_LAUNCH_CHECK();
   hipLaunchKernelGGL(reduce_partial, dim3(m), dim3(256), 0, h.stream, h.dots, nb, dev_out);
+  PSE_LAUNCH_CHECK();
+}
+
+void vsub_multi(Handle &h, double *w, const double *V, size_t ldv, int m,
+                const double *coef_dev, size_t n) {
+  ProfScope ps(h, PK_KRYLOV, (double)(m + 2) * n * 8);
+  hipLaunchKernelGGL(sub_multi_kernel, dim3(nblocks(n, 256)), dim3(256), 0, h.stream, w,
+                     V, ldv, m, coef_dev, n);
   PSE_LAUNCH_CHECK();
 }
 
@@ -325,12 +262,15 @@ __device__ void tridiag_ql(double *d, double *e, double *z, int m, int ldz) {
 
 // coef = bnorm * f(T) e_1 with f = sqrt, T = tridiag(alpha, beta) of size m;
 // also the relative change against the previous coefficient vector
-// (zero-padded), written to out_change.  One thread; the eigenproblem's
-// arrays live in LDS (lds_work) when ldz == m, else in the global work area.
-__device__ void lanczos_sqrt_body(const double *alpha, const double *beta, int m,
-                                  double bnorm, double *work, int ldz, double *coef,
-                                  double *coef_prev, double *out_change, double *chg_hist,
-                                  double *lds_work) {
+// (zero-padded), written to out_change.
+__global__ void lanczos_sqrt_kernel(const double *alpha, const double *beta, int m,
+                                    double bnorm, double *work, int ldz, double *coef,
+                                    double *coef_prev, double *out_change,
+                                    double *chg_hist) {
+  // the eigenproblem runs on one thread; its arrays live in LDS when they fit
+  // (dynamic shared memory sized by the host), else in the global work area
+  extern __shared__ double lds_work[];
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
   const bool in_lds = ldz == m;
   double *base = in_lds ? lds_work : work;
   double *d = base, *e = base + ldz, *z = base + 2 * ldz;
@@ -357,38 +297,6 @@ __device__ void lanczos_sqrt_body(const double *alpha, const double *beta, int m
   chg_hist[m - 1] = out_change[0];
 }
 
-// f(T) e_1 for the leading m x m block (used after a breakdown).
-__global__ void lanczos_sqrt_kernel(const double *alpha, const double *beta, int m,
-                                    double bnorm, double *work, int ldz, double *coef,
-                                    double *coef_prev, double *out_change,
-                                    double *chg_hist) {
-  extern __shared__ double lds_work[];
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  lanczos_sqrt_body(alpha, beta, m, bnorm, work, ldz, coef, coef_prev, out_change, chg_hist,
-                    lds_work);
-}
-
-// Lanczos step j: the tridiagonal entries from the two Gram-Schmidt passes,
-// alpha_j = h1[j] + h2[j] and beta_j = the norm of the twice-orthogonalised
-// vector (h2 summed from the second pass's partials, m = j + 1 rows plus
-// w.w), then f(T) e_1 for the (j + 1) x (j + 1) matrix.  64 threads.
-__global__ void __launch_bounds__(64)
-lanczos_step_kernel(double *alpha, double *beta, int j, const double *h1,
-                    const double *part2, int nb, double *vn_hist, double bnorm,
-                    double *work, int ldz, double *coef, double *coef_prev,
-                    double *out_change, double *chg_hist) {
-  extern __shared__ double lds_work[];
-  __shared__ double h2[MAXC];
-  reduce_partials(part2, j + 2, nb, h2);
-  if (threadIdx.x != 0) return;
-  alpha[j] = h1[j] + h2[j];
-  const double nn = cgs2_norm(h2, j + 1);
-  beta[j] = nn;
-  vn_hist[j] = nn;
-  lanczos_sqrt_body(alpha, beta, j + 1, bnorm, work, ldz, coef, coef_prev, out_change,
-                    chg_hist, lds_work);
-}
-
 // y = R^{-1} g for the k x k upper-triangular part of H.
 __global__ void backsub_kernel(const double *H, int ldh, int k, const double *g, double *y) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
@@ -399,22 +307,27 @@ __global__ void backsub_kernel(const double *H, int ldh, int k, const double *g,
   }
 }
 
+// Hessenberg column j entries 0..j from h1 + h2 (two Gram-Schmidt passes),
+// entry j+1 = sqrt(norm2).  Also sets g[0] = beta when j == 0 is requested.
 // GMRES column j from the two Gram-Schmidt passes: H[i][j] = h1[i] + h2[i]
-// (i <= j) with h2 summed from the second pass's partials, H[j+1][j] the
-// norm of the twice-orthogonalised w.  Then the previous Givens rotations
-// are applied to the column, the new one is formed and g updated;
-// resid = |g_{j+1}|.  64 threads.
-__global__ void __launch_bounds__(64)
-hess_givens_kernel(double *H, int ldh, int j, const double *h1, const double *part2, int nb,
-                   double *cs, double *sn, double *g, double *resid, double *vn_hist,
-                   double *res_hist) {
-  __shared__ double h2[MAXC];
-  reduce_partials(part2, j + 2, nb, h2);
-  if (threadIdx.x != 0) return;
+// (i <= j); h2[j+1] holds w.w after the first pass, so the norm of the
+// twice-orthogonalised w is sqrt(w.w - |h2|^2) (V orthonormal).  Then the
+// previous Givens rotations are applied to the column, the new one is
+// formed and g updated; vnorm = H[j+1][j], resid = |g_{j+1}|.
+__global__ void hess_givens_kernel(double *H, int ldh, int j, const double *h1,
+                                   const double *h2, double *cs, double *sn, double *g,
+                                   double *vnorm, double *resid, double *vn_hist,
+                                   double *res_hist) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
   double *col = H + (size_t)j * ldh;
-  for (int i = 0; i <= j; ++i) col[i] = h1[i] + h2[i];
-  const double nn = cgs2_norm(h2, j + 1);
+  double p2 = 0.0;
+  for (int i = 0; i <= j; ++i) {
+    col[i] = h1[i] + h2[i];
+    p2 += h2[i] * h2[i];
+  }
+  const double nn = sqrt(fmax(h2[j + 1] - p2, 0.0));
   col[j + 1] = nn;
+  vnorm[0] = nn;
   for (int i = 0; i < j; ++i) {
     const double t = cs[i] * col[i] + sn[i] * col[i + 1];
     col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
@@ -445,6 +358,21 @@ __global__ void set_g0_kernel(double *g, int len, const double *beta) {
   }
 }
 
+// Lanczos tridiagonal entries from the two Gram-Schmidt passes:
+// alpha_j = h1[j] + h2[j]; h2[j+1] holds w.w after the first pass, so
+// beta_j = sqrt(w.w - |h2|^2) is the norm of the twice-orthogonalised w.
+__global__ void lanczos_fill_kernel(double *alpha, double *beta, int j, const double *h1,
+                                    const double *h2, double *vnorm, double *vn_hist) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  alpha[j] = h1[j] + h2[j];
+  double p2 = 0.0;
+  for (int i = 0; i <= j; ++i) p2 += h2[i] * h2[i];
+  const double nn = sqrt(fmax(h2[j + 1] - p2, 0.0));
+  beta[j] = nn;
+  vnorm[0] = nn;
+  vn_hist[j] = nn;
+}
+
 // ---------------------------------------------------- host algorithms --
 
 // Reads n Krylov scalars; any non-finite one is reported as an error (a
@@ -471,38 +399,22 @@ static void norm2_dev(Handle &h, const double *v, size_t n, double *dev_norm2) {
   multi_dot(h, v, n, 1, v, n, dev_norm2);
 }
 
-// Blocks of the fused Gram-Schmidt kernels: about 1024 elements per block,
-// at most RED_BLOCKS.
-static int cgs2_blocks(size_t n) {
-  return (int)std::max<size_t>(1, std::min<size_t>(RED_BLOCKS, n / 1024));
+// Two-pass classical Gram-Schmidt of w = V[m] against V[0..m-1] (leading dim
+// n): h1 = V^T w, w -= V h1; then h2[0..m] = [V, w]^T w (h2[m] = w.w).  The
+// second subtraction is fused with the normalisation (sub_scale) once the
+// norm is known on the device.
+static void cgs2_pass(Handle &h, const double *V, size_t n, int m, double *w, double *h1,
+                      double *h2) {
+  multi_dot(h, V, n, m, w, n, h1);
+  vsub_multi(h, w, V, n, m, h1, n);
+  multi_dot(h, V, n, m + 1, w, n, h2);
 }
 
-// The first pass of CGS2 for w = V[m] against V[0..m-1] (leading dim n) and
-// the second pass's partial dot products: h1 = V^T w, w -= V h1, part2 =
-// partials of [V, w]^T w over nb blocks.  The small-matrix kernel and
-// sub_scale_fused finish the step from part2.
-static double *cgs2_first(Handle &h, const double *V, size_t n, int m, double *w, double *h1,
-                          int nb) {
-  if (m + 1 > MAXC) throw Error{PSE_ERR_INVALID, "Krylov basis larger than supported"};
-  if ((size_t)nb * (2 * m + 1) > h.dots_len)
-    throw Error{PSE_ERR_INVALID, "reduction scratch too small"};
-  double *part1 = h.dots, *part2 = h.dots + (size_t)nb * m;
-  ProfScope ps(h, PK_KRYLOV, (double)(3 * m + 3) * n * 8);
-  hipLaunchKernelGGL(multi_dot_partial, dim3(nb, m), dim3(256), 0, h.stream, V, n, w, n,
-                     part1);
-  PSE_LAUNCH_CHECK();
-  hipLaunchKernelGGL(sub_dot_kernel, dim3(nb), dim3(256), 0, h.stream, w, V, n, m, part1, h1,
-                     part2, n);
-  PSE_LAUNCH_CHECK();
-  return part2;
-}
-
-// w = (w - V h2) / |w - V h2| from the second pass's partials.
 static void sub_scale(Handle &h, double *w, const double *V, size_t n, int m,
-                      const double *part2, int nb) {
+                      const double *coef, const double *s) {
   ProfScope ps(h, PK_KRYLOV, (double)(m + 2) * n * 8);
-  hipLaunchKernelGGL(sub_scale_fused_kernel, dim3(nb), dim3(256), 0, h.stream, w, V, n, m,
-                     part2, nb, n);
+  hipLaunchKernelGGL(sub_scale_kernel, dim3(nblocks(n, 256)), dim3(256), 0, h.stream, w, V, n,
+                     m, coef, s, n);
   PSE_LAUNCH_CHECK();
 }
 
@@ -555,22 +467,16 @@ KrylovResult lanczos_sqrt(Handle &h, const Op &A, const double *b, size_t n, dou
   };
   const int check_from = (prev_iters && *prev_iters > 3) ? *prev_iters - 2 : 0;
   std::vector<double> hist(2 * (M + 1));
-  const int nb = cgs2_blocks(n);
   int m = 0;
   for (int j = 0; j < M; ++j) {
     double *w = V + (size_t)(j + 1) * n;
     A(V + (size_t)j * n, w);
-    const double *part2 = cgs2_first(h, V, n, j + 1, w, h1, nb);
-    {
-      const int mm = j + 1;
-      const size_t lds = (size_t)(2 * mm + mm * mm) * sizeof(double);
-      const bool fits = lds <= 32768;
-      hipLaunchKernelGGL(lanczos_step_kernel, dim3(1), dim3(64), fits ? lds : 0, h.stream,
-                         alpha, beta, j, h1, part2, nb, vn_hist, bnorm, work, fits ? mm : ldz,
-                         coef, coef_prev, change, chg_hist);
-      PSE_LAUNCH_CHECK();
-    }
-    sub_scale(h, w, V, n, j + 1, part2, nb);
+    cgs2_pass(h, V, n, j + 1, w, h1, h2);
+    hipLaunchKernelGGL(lanczos_fill_kernel, dim3(1), dim3(1), 0, h.stream, alpha, beta, j,
+                       h1, h2, vnorm, vn_hist);
+    PSE_LAUNCH_CHECK();
+    sub_scale(h, w, V, n, j + 1, h2, vnorm);
+    sqrt_coef(j + 1);
     m = j + 1;
     res.iters = m;
     if (m < check_from && m < M) continue;
@@ -631,7 +537,6 @@ KrylovResult gmres(Handle &h, const Op &A, const double *b, size_t n, double *x,
   }
   double rel = 1.0;
   int total = 0;
-  const int nb = cgs2_blocks(n);
   bool first = true;
   // only the first cycle reads late (see above); restarts check every step
   int check_from = (prev_iters && *prev_iters > 3) ? *prev_iters - 2 : 0;
@@ -664,11 +569,11 @@ KrylovResult gmres(Handle &h, const Op &A, const double *b, size_t n, double *x,
     for (int j = 0; j < R && total < maxit; ++j) {
       double *w = V + (size_t)(j + 1) * n;
       A(V + (size_t)j * n, w);
-      const double *part2 = cgs2_first(h, V, n, j + 1, w, h1, nb);
-      hipLaunchKernelGGL(hess_givens_kernel, dim3(1), dim3(64), 0, h.stream, H, ldh, j, h1,
-                         part2, nb, cs, sn, g, resid, vn_hist, res_hist);
+      cgs2_pass(h, V, n, j + 1, w, h1, h2);
+      hipLaunchKernelGGL(hess_givens_kernel, dim3(1), dim3(1), 0, h.stream, H, ldh, j, h1, h2,
+                         cs, sn, g, vnorm, resid, vn_hist, res_hist);
       PSE_LAUNCH_CHECK();
-      sub_scale(h, w, V, n, j + 1, part2, nb);
+      sub_scale(h, w, V, n, j + 1, h2, vnorm);
       ++total;
       k = j + 1;
       if (k < check_from && j + 1 < R && total < maxit) continue;

@@ -362,6 +362,8 @@ void vcopy(Handle &h, double *dst, const double *src, size_t n);
 void vaxpby(Handle &h, double a, const double *x, double b, double *y, size_t n);
 void multi_dot(Handle &h, const double *V, size_t ldv, int m, const double *w,
                size_t n, double *dev_out);
+void vsub_multi(Handle &h, double *w, const double *V, size_t ldv, int m,
+                const double *coef_dev, size_t n);
 void gemv_small(Handle &h, const double *V, size_t ldv, int m,
                 const double *coef_dev, double *y, size_t n, double alpha,
                 bool accumulate);
