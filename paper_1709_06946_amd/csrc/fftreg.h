@@ -170,6 +170,8 @@ template <typename T, int R> __device__ __forceinline__ void dft(cplx<T> *v, int
     v[2] = csub(t0, t2);
     v[1] = cadd(t1, t3);
     v[3] = csub(t1, t3);
+  } else if constexpr (R == 6) {
+    dft_compose<T, 3, 2>(v, dir);
   } else if constexpr (R == 8) {
     dft_compose<T, 2, 4>(v, dir);
   } else if constexpr (R == 12) {
@@ -188,14 +190,15 @@ struct Radices {
   int r[8];
 };
 
-// Greedy factorisation of n into radices that divide e (largest first).
+// Greedy factorisation of n into radices that divide e (largest first);
+// np = -1 when n has no such factorisation in at most 8 passes.
 constexpr Radices factor(int n, int e) {
   Radices out{};
-  const int cand[6] = {16, 12, 8, 4, 3, 2};
+  const int cand[7] = {16, 12, 8, 6, 4, 3, 2};
   int m = n;
   while (m > 1 && out.np < 8) {
     int pick = 0;
-    for (int i = 0; i < 6; ++i) {
+    for (int i = 0; i < 7; ++i) {
       if (e % cand[i] == 0 && m % cand[i] == 0) {
         pick = cand[i];
         break;
@@ -205,6 +208,7 @@ constexpr Radices factor(int n, int e) {
     out.r[out.np++] = pick;
     m /= pick;
   }
+  if (m > 1) return Radices{-1, {}};
   return out;
 }
 
@@ -307,9 +311,10 @@ __device__ __forceinline__ void reg_fft_inverse(cplx<T> (&v)[E], int t, cplx<T> 
 }
 
 // Element counts per thread: line passes and the fused k-space kernel (which
-// also keeps three complex numbers per element in registers).
+// also keeps three complex numbers per element in registers, so it takes few
+// elements: 4 for powers of two, 6 (radices 6, 3, 2) for 3 * 2^k lengths).
 constexpr int line_e(int n) { return n % 3 == 0 ? 12 : (n >= 128 ? 16 : 8); }
-constexpr int fused_e(int n) { return n % 3 == 0 ? 12 : 4; }
+constexpr int fused_e(int n) { return n % 3 == 0 ? 6 : 4; }
 
 // Lines per workgroup: a power of two dividing `count`, at most max_threads
 // threads (about 256 by default), LDS of tl * line_bytes within 64 KiB.
