@@ -71,14 +71,15 @@ def test_creates_and_copies_overlapping_captures_do_not_fail():
     constraint-operator graphs.  Those calls and the captures are kept apart
     by the library, so no request fails and every result is finite."""
     from paper_1709_06946_amd import pse
-    srv = pse.PSEServer(max_active=6)
-    ids = []
+    reqs = []
     for i in range(18):
         n = 400 + 150 * (i % 7)
         x, L = inputs.packing(n, 0.1 + 0.05 * (i % 5), seed=inputs.SEED_BASE + 400 + i)
-        FL = inputs.forces_torques(n, inputs.SEED_BASE + 500 + i)
-        ids.append(srv.submit(x, L, FL=FL, steps=3, seed=2000 + i, grid=pse.grid_for(L),
-                              precision=pse.PSE_MIXED if i % 2 else pse.PSE_FP64))
+        reqs.append((x, L, inputs.forces_torques(n, inputs.SEED_BASE + 500 + i)))
+    srv = pse.PSEServer(max_active=6)
+    ids = [srv.submit(x, L, FL=FL, steps=3, seed=2000 + i, grid=pse.grid_for(L),
+                      precision=pse.PSE_MIXED if i % 2 else pse.PSE_FP64)
+           for i, (x, L, FL) in enumerate(reqs)]
     for rid in ids:
         info = srv.wait(rid)
         x, lat = srv.result(rid)
