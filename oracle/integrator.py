@@ -84,3 +84,44 @@ def midpoint_step(x0, FL, psi1, psi2, dt, L, Ng, xi, a=1.0, eta=1.0, kT=1.0,
     dx = dt * U
     return dict(y_real=y1, y_wave=y2, slip=slip, x_half=x_half, S=S,
                 U=U, Ufrak=Uf, dx=dx, x1=wrap(x0 + dx, L))
+
+
+# ------------------------------------------------- RPY-level comparison --
+#
+# The unconstrained PSE of the performance comparison (Sec. IV): forces
+# only, so the mobility reduces to its force-velocity block M_UF (the
+# periodic RPY tensor as split by the positively split Ewald sum).  The
+# split sampler restricted to that block gives the Brownian velocity
+#   U^B = sqrt(2 kT / dt) ((M_r)_UF^(1/2) psi1 + (M_w)_UF^(1/2) psi2),
+# with (M_r)_UF^(1/2) the principal root of the real-space UF block and the
+# wave part the velocity rows of the wave sampler (whose covariance is the
+# wave-space UF block).  M_UF is divergence-free, so an Euler-Maruyama step
+#   x_{k+1} = x_k + dt (M_UF F + U^B)
+# carries no drift term.
+
+def rpy_mobility(x, L, xi, a=1.0, eta=1.0):
+    """M_UF (3N x 3N): the force-velocity block of the full mobility."""
+    N = np.asarray(x).shape[0]
+    iu = cv.block_indices(N, cv.IDX_U)
+    return ewald.grand_dense(x, L, xi, a, eta)[np.ix_(iu, iu)]
+
+
+def rpy_step(x0, F, psi1, psi2, dt, L, Ng, xi, a=1.0, eta=1.0, kT=1.0, xi_total=None):
+    """One unconstrained RPY-level step.
+
+    F: (N, 3) or None; psi1: (N, 3) real noise; psi2: wave noise in the grid
+    layout of brownian.py; Ng, xi: the sampler's grid and splitting.
+    Returns a dict of every intermediate result."""
+    x0 = np.asarray(x0, np.float64)
+    N = x0.shape[0]
+    iu = cv.block_indices(N, cv.IDX_U)
+    Mr = ewald.real_dense(x0, L, xi, a, eta)[np.ix_(iu, iu)]
+    y1 = brownian.principal_sqrt_apply(Mr, np.asarray(psi1, np.float64).ravel()).reshape(N, 3)
+    y2 = brownian.wave_sample(x0, psi2, L, Ng, xi, a, eta)[:, cv.IDX_U]
+    slip = np.sqrt(2.0 * kT / dt) * (y1 + y2)
+    U = slip.copy()
+    if F is not None:
+        M = rpy_mobility(x0, L, xi if xi_total is None else xi_total, a, eta)
+        U += (M @ np.asarray(F, np.float64).ravel()).reshape(N, 3)
+    dx = dt * U
+    return dict(y_real=y1, y_wave=y2, slip=slip, U=U, dx=dx, x1=wrap(x0 + dx, L))

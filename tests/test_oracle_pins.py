@@ -404,3 +404,40 @@ def test_real_apply_rows_equals_full_sum():
     rows = [0, 7, 31, 59]
     part = ewald.real_apply_rows(x, q, L, xi, rows)
     assert np.abs(part - full[rows]).max() <= 1e-13 * np.abs(full).max()
+
+
+# ------------------------------------------------------------ RPY level --
+
+@pytest.mark.parametrize('L', [8.0, 20.0])
+def test_rpy_step_single_particle_moves_with_hasimoto_mobility(L):
+    """Noise-free RPY-level step of one sphere: x moves by dt mu F with
+    Hasimoto's periodic translational mobility."""
+    x = np.array([[0.3, 0.2, 0.1]])
+    F = np.array([[1.0, -2.0, 0.5]])
+    dt = 1e-2
+    r = integrator.rpy_step(x, F, np.zeros((1, 3)), np.zeros((3, 16, 16, 9)), dt, L, 16, 1.0)
+    mu = (1 - 2.8372975 / L + 4 * PI / (3 * L**3)) / (6 * PI)
+    assert np.allclose(r['dx'], dt * mu * F, rtol=0, atol=2e-7 / L * dt * np.abs(F).max())
+
+
+def test_rpy_real_sampler_is_principal_root_of_real_uf_block():
+    """The real-space part of the RPY sampler maps psi1 by a symmetric PSD
+    matrix whose square is the real-space force-velocity block (built here
+    column by column from unit noise vectors)."""
+    L = 9.0
+    x = _config(L, 3, pairs=((0.0, 0.0, 0.0), (2.3, 0.4, 0.1), (1.1, 2.5, -0.4)))
+    N = x.shape[0]
+    zero_wave = np.zeros((3, 8, 8, 5))
+    cols = []
+    for j in range(3 * N):
+        e = np.zeros(3 * N)
+        e[j] = 1.0
+        # dt = 2 kT makes the noise prefactor sqrt(2 kT / dt) one
+        cols.append(integrator.rpy_step(x, None, e.reshape(N, 3), zero_wave, 2.0, L, 8,
+                                        1.2)['slip'].ravel())
+    R = np.array(cols).T
+    iu = cv.block_indices(N, cv.IDX_U)
+    Mr = ewald.real_dense(x, L, 1.2)[np.ix_(iu, iu)]
+    assert np.allclose(R, R.T, atol=1e-12)
+    assert np.linalg.eigvalsh(R).min() > -1e-12
+    assert np.allclose(R @ R, Mr, atol=1e-12 * np.abs(Mr).max())
