@@ -197,6 +197,31 @@ int pse_constrained_step(pse_handle *h, double *x, const double *FL,
                          double dt, uint64_t seed, uint64_t step,
                          const pse_step_io *io, pse_stats *stats);
 
+/* ---- Unconstrained (RPY-level) PSE: forces only ----
+ * The comparison system of the performance study (Sec. IV): the mobility
+ * reduced to its force-velocity block M_UF (the periodic RPY tensor of the
+ * positively split Ewald sum), three gridded components per product and no
+ * constraint.  Same handle, kernels and precision as the FTS calls. */
+
+/* U = M_UF F (parts as for pse_mobility_apply).  x: double[N][3];
+ * F, U: double[N][3] device arrays (U overwritten). */
+int pse_rpy_apply(pse_handle *h, const double *x, const double *F, double *U,
+                  unsigned parts);
+
+/* One Euler-Maruyama step with the split sampler restricted to the UF block
+ * (the RPY tensor is divergence-free, so there is no drift term):
+ *   U^B     = sqrt(2 kT / dt) ((M_r)_UF^(1/2) psi1 + (M_w)_UF^(1/2) psi2)  at x_k
+ *   x_{k+1} = x_k + dt (M_UF F + U^B)   (written to x, wrapped into [0, L))
+ * (M_r)_UF^(1/2) is the principal root of the real-space UF block (Lanczos);
+ * the wave part maps the same three-component wave noise as the FTS sampler
+ * through the velocity rows only.  F: double[N][3] or NULL.  io as for
+ * pse_constrained_step, with psi_real double[N][3] (the first three of each
+ * particle's Philox normals when NULL), slip double[N][3] = U^B and velocity
+ * double[N][3] = M_UF F + U^B; stresslet is not used.  Returns
+ * PSE_WARN_NOT_CONVERGED if Lanczos hit its limit. */
+int pse_rpy_step(pse_handle *h, double *x, const double *F, double dt, uint64_t seed,
+                 uint64_t step, const pse_step_io *io, pse_stats *stats);
+
 /* Diagnostics of individual stages (used by the kernel tests). */
 /* In-place unnormalized 3D FFT of ncomp complex double grids
  * data[ncomp][Ng][Ng][Ng] (z, y, x; x fastest) with the handle's grid and

@@ -74,6 +74,17 @@ __global__ void moments_kernel(const double *__restrict__ FL, const double *__re
   for (int k = 0; k < 5; ++k) q[i * NC + 6 + k] = S ? S[i * 5 + k] : 0.0;
 }
 
+// RPY step: slip = c (y1 + y2), U = slip + m (all N x 3, flat; m may be NULL)
+__global__ void rpy_velocity_kernel(const double *__restrict__ y1, const double *__restrict__ y2,
+                                    const double *__restrict__ m, double c, int64_t n3,
+                                    double *__restrict__ slip, double *__restrict__ U) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n3) return;
+  const double s = c * (y1[i] + y2[i]);
+  slip[i] = s;
+  U[i] = s + (m ? m[i] : 0.0);
+}
+
 // U = slip_U + m_U (N x 3)
 __global__ void velocity_kernel(const double *__restrict__ slip, const double *__restrict__ m,
                                 int64_t n, double *__restrict__ U) {
@@ -144,18 +155,19 @@ static void mobility(Handle &h, const double *xw, bool want_real, bool want_wave
 
 template <typename T>
 static void wave_sqrt_t(Handle &h, const double *xw, const double *psi, uint64_t seed,
-                        uint64_t counter, double *out, const CompSet &cout) {
+                        uint64_t counter, double *out, const CompSet &cout, Layout lout) {
   GridSet<T> &G = grids<T>(h);
   T *gout = reinterpret_cast<T *>(G.gout);
   kspace_noise<T>(h, psi, seed, counter, G.gout, cout);
   rfft3d<T>(h, gout, G.twiddle, cout.n, +1);
-  interpolate<T>(h, xw, gout, cout, out, FULL_LAYOUT, false, 1.0);
+  interpolate<T>(h, xw, gout, cout, out, lout, false, 1.0);
 }
 
 static void wave_sqrt(Handle &h, const double *xw, const double *psi, uint64_t seed,
-                      uint64_t counter, double *out, const CompSet &cout) {
-  if (h.mixed) wave_sqrt_t<float>(h, xw, psi, seed, counter, out, cout);
-  else wave_sqrt_t<double>(h, xw, psi, seed, counter, out, cout);
+                      uint64_t counter, double *out, const CompSet &cout,
+                      Layout lout = FULL_LAYOUT) {
+  if (h.mixed) wave_sqrt_t<float>(h, xw, psi, seed, counter, out, cout, lout);
+  else wave_sqrt_t<double>(h, xw, psi, seed, counter, out, cout, lout);
 }
 
 static KrylovResult real_sqrt(Handle &h, const double *xw, const double *psi, double *out) {
@@ -670,6 +682,84 @@ int pse_constrained_step(pse_handle *hd, double *x, const double *FL, double dt,
     PSE_HIP(hipStreamSynchronize(h.stream));
     st.converged = converged ? 1 : 0;
     if (!converged) warn = PSE_WARN_NOT_CONVERGED;
+    if (stats) *stats = st;
+  });
+  return rc != PSE_OK ? rc : warn;
+}
+
+// ---- RPY-level (unconstrained) PSE ----
+
+// Particle vectors of the force-velocity block: N x 3, components 0..2.
+static const Layout RPY_LAYOUT{3, 0};
+
+int pse_rpy_apply(pse_handle *hd, const double *x, const double *F, double *U,
+                  unsigned parts) {
+  if (!hd) return PSE_ERR_INVALID;
+  if (!x || !F || !U || parts == 0 || (parts & ~3u)) {
+    hd->h.err = "pse_rpy_apply: null pointer or bad parts";
+    return PSE_ERR_INVALID;
+  }
+  return guarded(hd, [&] {
+    Handle &h = hd->h;
+    const CompSet u3 = comps_range(0, 3);
+    prepare_positions(h, x, h.xw);
+    mobility(h, h.xw, parts & PSE_REAL, parts & PSE_WAVE, F, RPY_LAYOUT, u3, U, RPY_LAYOUT, u3,
+             false);
+    if (check_finite(h, U, (size_t)h.n * 3))
+      throw Error{PSE_ERR_NONFINITE, "non-finite mobility product (non-finite input?)"};
+  });
+}
+
+int pse_rpy_step(pse_handle *hd, double *x, const double *F, double dt, uint64_t seed,
+                 uint64_t step, const pse_step_io *io, pse_stats *stats) {
+  if (!hd) return PSE_ERR_INVALID;
+  if (!x || !(dt > 0)) {
+    hd->h.err = "pse_rpy_step: null positions or dt <= 0";
+    return PSE_ERR_INVALID;
+  }
+  int warn = PSE_OK;
+  const int rc = guarded(hd, [&] {
+    Handle &h = hd->h;
+    const int64_t n = h.n;
+    const CompSet u3 = comps_range(0, 3);
+    pse_stats st{};
+    st.fp64_residual = -1;
+    prepare_positions(h, x, h.xw);
+    // (M_r)_UF^(1/2) psi1 by Lanczos on the UF block of the pair sum
+    const double *psi = io ? io->psi_real : nullptr;
+    if (!psi) {
+      real_noise(h, seed, step, h.v2, 3);
+      psi = h.v2;
+    }
+    Op A = [&](const double *in, double *o) {
+      if (h.mixed) real_apply<float>(h, h.xw, in, RPY_LAYOUT, u3, o, RPY_LAYOUT, u3, false);
+      else real_apply<double>(h, h.xw, in, RPY_LAYOUT, u3, o, RPY_LAYOUT, u3, false);
+    };
+    KrylovResult lr = lanczos_sqrt(h, A, psi, (size_t)n * 3, h.v0, h.d.lanczos_maxit,
+                                   h.d.lanczos_tol, &h.lz_prev_rpy);
+    st.lanczos_iters = lr.iters;
+    st.lanczos_change = lr.resid;
+    // (M_w)_UF^(1/2) psi2: the wave sampler's velocity rows
+    wave_sqrt(h, h.xw, io ? io->psi_wave : nullptr, seed, step, h.v1, u3, RPY_LAYOUT);
+    // M_UF F at x_k
+    if (F) mobility(h, h.xw, true, true, F, RPY_LAYOUT, u3, h.v4, RPY_LAYOUT, u3, false);
+    double *slip = h.v3, *U = h.v5;
+    hipLaunchKernelGGL(rpy_velocity_kernel, dim3(nblocks(3 * n, 256)), dim3(256), 0, h.stream,
+                       h.v0, h.v1, F ? (const double *)h.v4 : nullptr,
+                       std::sqrt(2.0 * h.p.kT / dt), 3 * n, slip, U);
+    PSE_LAUNCH_CHECK();
+    hipLaunchKernelGGL(advance_kernel, dim3(nblocks(n, 256)), dim3(256), 0, h.stream, h.xw,
+                       U, 3, dt, n, h.p.box, x);
+    PSE_LAUNCH_CHECK();
+    if (io) {
+      if (io->slip) PSE_HIP(hipMemcpyAsync(io->slip, slip, 3 * n * sizeof(double),
+                                           hipMemcpyDeviceToDevice, h.stream));
+      if (io->velocity) PSE_HIP(hipMemcpyAsync(io->velocity, U, 3 * n * sizeof(double),
+                                               hipMemcpyDeviceToDevice, h.stream));
+    }
+    PSE_HIP(hipStreamSynchronize(h.stream));
+    st.converged = lr.converged ? 1 : 0;
+    if (!lr.converged) warn = PSE_WARN_NOT_CONVERGED;
     if (stats) *stats = st;
   });
   return rc != PSE_OK ? rc : warn;

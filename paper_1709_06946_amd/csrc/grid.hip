@@ -685,13 +685,13 @@ kspace_noise_kernel(const double2 *__restrict__ psi, uint64_t seed, uint64_t cou
 }
 
 // Real-space noise psi1 ~ N(0, I), 11 per particle, from Philox.
-__global__ void real_noise_kernel(uint64_t seed, uint64_t counter, int64_t n,
+__global__ void real_noise_kernel(uint64_t seed, uint64_t counter, int64_t n, int ncomp,
                                   double *__restrict__ out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   double z[12];
   philox_normals(seed, counter, STREAM_REAL, (uint32_t)i, 3, z);
-  for (int c = 0; c < NC; ++c) out[i * NC + c] = z[c];
+  for (int c = 0; c < ncomp; ++c) out[i * ncomp + c] = z[c];
 }
 
 // --------------------------------------------------------- small kernels --
@@ -914,9 +914,9 @@ void kspace_noise(Handle &h, const double *psi, uint64_t seed, uint64_t counter,
   PSE_LAUNCH_CHECK();
 }
 
-void real_noise(Handle &h, uint64_t seed, uint64_t counter, double *out) {
+void real_noise(Handle &h, uint64_t seed, uint64_t counter, double *out, int ncomp) {
   hipLaunchKernelGGL(real_noise_kernel, dim3(nblocks(h.n, 256)), dim3(256), 0,
-                     h.stream, seed, counter, h.n, out);
+                     h.stream, seed, counter, h.n, ncomp, out);
   PSE_LAUNCH_CHECK();
 }
 

@@ -170,6 +170,7 @@ struct Handle {
   bool use_graphs = true;
   // iteration counts of the previous Lanczos and GMRES (FP64, FP32) solves
   int lz_prev = 0;
+  int lz_prev_rpy = 0;       // the same for the RPY sampler's UF-block Lanczos
   int gm_prev[2] = {0, 0};
   bool graph_warm = false;   // one eager application before the first capture
   std::string graph_error;   // why graphs were switched off after a failed capture
@@ -390,7 +391,9 @@ KrylovResult gmres(Handle &h, const Op &A, const double *b, size_t n, double *x,
                    int restart, int maxit, double tol, int *prev_iters);
 
 // ---- grid.hip (noise)
-void real_noise(Handle &h, uint64_t seed, uint64_t counter, double *out);
+// N x ncomp standard normals (the first ncomp of each particle's Philox
+// draws, so the F components agree for every ncomp).
+void real_noise(Handle &h, uint64_t seed, uint64_t counter, double *out, int ncomp = NC);
 
 inline CompSet comps_range(int lo, int hi) {
   CompSet c{};

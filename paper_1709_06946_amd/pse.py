@@ -92,7 +92,7 @@ class pse_server_info(ctypes.Structure):
 
 EXPORTS = ('pse_derive', 'pse_footprint_bytes', 'pse_create', 'pse_destroy',
            'pse_get_derived', 'pse_mobility_apply', 'pse_brownian_sample',
-           'pse_constrained_step', 'pse_fft3d', 'pse_spread', 'pse_interpolate',
+           'pse_constrained_step', 'pse_rpy_apply', 'pse_rpy_step', 'pse_fft3d', 'pse_spread', 'pse_interpolate',
            'pse_profile', 'pse_profile_read', 'pse_server_create', 'pse_server_submit',
            'pse_server_wait', 'pse_server_result', 'pse_server_release', 'pse_server_stats',
            'pse_server_destroy', 'pse_server_error', 'pse_last_error')
@@ -122,6 +122,9 @@ def load_library(path=LIB_PATH):
                                         V, V, P(pse_stats)]
     lib.pse_constrained_step.argtypes = [V, V, V, ctypes.c_double, ctypes.c_uint64,
                                          ctypes.c_uint64, P(pse_step_io), P(pse_stats)]
+    lib.pse_rpy_apply.argtypes = [V, V, V, V, ctypes.c_uint]
+    lib.pse_rpy_step.argtypes = [V, V, V, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64,
+                                 P(pse_step_io), P(pse_stats)]
     lib.pse_fft3d.argtypes = [V, V, I, I]
     lib.pse_spread.argtypes = [V, V, V, I, V]
     lib.pse_interpolate.argtypes = [V, V, V, I, V]
@@ -270,6 +273,28 @@ class PSE:
         rc = self._check(lib().pse_constrained_step(
             self._h, _ptr(x, (n, 3), 'x'), _ptr(FL, (n, 6), 'FL'), float(dt), seed, step,
             ctypes.byref(io), ctypes.byref(st)), 'pse_constrained_step')
+        return rc, st.as_dict()
+
+    def rpy_apply(self, x, F, out, parts=PSE_REAL | PSE_WAVE):
+        """out = M_UF F (the RPY-level product; F, out of shape (N, 3))."""
+        n = self.n
+        _sync()
+        return self._check(lib().pse_rpy_apply(
+            self._h, _ptr(x, (n, 3), 'x'), _ptr(F, (n, 3), 'F'), _ptr(out, (n, 3), 'out'),
+            parts), 'pse_rpy_apply')
+
+    def rpy_step(self, x, F=None, dt=1e-3, seed=0, step=0, psi_real=None, psi_wave=None,
+                 slip=None, velocity=None):
+        """One unconstrained RPY-level Euler-Maruyama step (x updated in place)."""
+        n, g = self.n, self.derived.grid
+        _sync()
+        io = pse_step_io(_ptr(psi_real, (n, 3), 'psi_real'),
+                         _ptr(psi_wave, (3, g, g, g // 2 + 1), 'psi_wave'),
+                         _ptr(slip, (n, 3), 'slip'), None, _ptr(velocity, (n, 3), 'velocity'))
+        st = pse_stats()
+        rc = self._check(lib().pse_rpy_step(
+            self._h, _ptr(x, (n, 3), 'x'), _ptr(F, (n, 3), 'F'), float(dt), seed, step,
+            ctypes.byref(io), ctypes.byref(st)), 'pse_rpy_step')
         return rc, st.as_dict()
 
     def profile(self, enable):
