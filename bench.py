@@ -8,8 +8,9 @@ constraint, final mobility product and position update.  The default workload
 is N = 10,000 hard spheres (a = 1) at phi = 0.3 in a 128^3 grid, eps = 1e-3,
 dt = 1e-3, with random non-overlapping positions and N(0, 1) forces/torques.
 Beside the FP64 headline: the mixed-precision form on the same workload, the
-served form (a Poisson stream of independent simulations of different N and
-phi with p50/p99 per-step latency), and the FP64 oracle on host cores.
+RPY-level comparison system (forces only, no constraint) and its cost ratio,
+the served form (a Poisson stream of independent simulations of different N
+and phi with p50/p99 per-step latency), and the FP64 oracle on host cores.
 Prints one JSON line.
 """
 import argparse
@@ -63,6 +64,33 @@ def run_form(w, precision, steps, warmup, seed, prof_steps=2):
                 prof_steps=prof_steps,
                 derived=dict(grid=d.grid, support=d.support, xi=d.xi, rcut=d.rcut,
                              eta_s=d.eta_s), finite=bool(torch.isfinite(x).all()))
+
+
+def run_rpy(w, steps, warmup, seed):
+    """The RPY-level comparison system (forces only, Sec. IV) on the same
+    workload in FP64: Euler-Maruyama steps with the split sampler on the
+    force-velocity block and the same forces' translational part."""
+    import torch
+
+    from paper_1709_06946_amd import pse
+    N = w['N']
+    h = pse.PSE(N, w['L'], grid=w['grid'], tol=w['eps'], precision=pse.PSE_FP64,
+                lanczos_tol=w['lanczos_tol'])
+    x = torch.tensor(w['x'], device='cuda:0')
+    F = torch.tensor(w['FL'][:, 0:3].copy(), device='cuda:0')
+    for k in range(warmup):
+        h.rpy_step(x, F, w['dt'], seed=seed, step=k)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lz = []
+    for k in range(steps):
+        _, st = h.rpy_step(x, F, w['dt'], seed=seed, step=warmup + k)
+        lz.append(st['lanczos_iters'])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    h.close()
+    return dict(value=round(N * steps / dt, 1), ms_per_step=round(1e3 * dt / steps, 3),
+                lanczos_iters=lz)
 
 
 STAGE_KERNELS = {
@@ -213,6 +241,7 @@ def main():
     ap.add_argument('--no-cpu-baseline', action='store_true')
     ap.add_argument('--no-mixed', action='store_true')
     ap.add_argument('--no-served', action='store_true')
+    ap.add_argument('--no-rpy', action='store_true')
     ap.add_argument('--copy-calibration', action='store_true',
                     help='only run a 1 GiB device copy (counter calibration)')
     ap.add_argument('--served-requests', type=int, default=16)
@@ -262,6 +291,10 @@ def main():
                    for k, v in fp64['prof'].items()},
         mixed=mixed,
     )
+    if not args.no_rpy:
+        r = run_rpy(w, args.steps, args.warmup, seed)
+        r['fts_over_rpy'] = round(r['value'] / fp64['value'], 2)
+        out['rpy'] = r
     if not args.no_served:
         out['served'] = served(args.served_requests, args.served_steps, args.served_active,
                                args.served_nmax, args.served_rate, seed + 777)
