@@ -429,6 +429,7 @@ static void create(const pse_params &p, Handle &h) {
     alloc((void **)&b->scan_tmp, ((ncells + 1023) / 1024 + 8) * sizeof(int));
     alloc((void **)&b->of, n * sizeof(int));
     alloc((void **)&b->slot, n * sizeof(int));
+    alloc((void **)&b->scat, n * sizeof(int));
     alloc((void **)&b->perm, n * sizeof(int));
   }
   alloc((void **)&h.xw, 3 * n * sizeof(double));
@@ -450,8 +451,9 @@ static void create(const pse_params &p, Handle &h) {
 static void release(Handle &h) {
   void *ptrs[] = {h.g64.gin, h.g64.gout, h.g64.twiddle, h.g64.table, h.g32.gin, h.g32.gout,
                   h.g32.twiddle, h.g32.table, h.cells.start, h.cells.count,
-                  h.cells.scan_tmp, h.cells.of, h.cells.slot, h.cells.perm, h.sbins.start,
-                  h.sbins.count, h.sbins.scan_tmp, h.sbins.of, h.sbins.slot, h.sbins.perm,
+                  h.cells.scan_tmp, h.cells.of, h.cells.slot, h.cells.scat, h.cells.perm,
+                  h.sbins.start, h.sbins.count, h.sbins.scan_tmp, h.sbins.of, h.sbins.slot,
+                  h.sbins.scat, h.sbins.perm,
                   h.xw, h.xh, h.v0, h.v1, h.v2, h.v3, h.v4, h.v5, h.es_b, h.es_x, h.es_r,
                   h.es_d, h.lz_V, h.gm_V, h.small, h.dots, h.ktab, h.pl_cnt,
                   h.pl_start, h.pl_scan, h.pl_nbr, h.pl_rec, h.tl_cnt, h.tl_start,

@@ -81,8 +81,9 @@ struct Bins {
   int *start = nullptr;      // nc^3 + 1: first slot of each bin in perm
   int *count = nullptr;      // nc^3
   int *of = nullptr;         // N: bin of each particle
-  int *slot = nullptr;       // N: rank of the particle within its bin
-  int *perm = nullptr;       // N: particles ordered by bin
+  int *slot = nullptr;       // N: arrival slot of the particle within its bin
+  int *scat = nullptr;       // N: particles by bin, in arrival order
+  int *perm = nullptr;       // N: particles ordered by bin, by index within a bin
   int *scan_tmp = nullptr;   // block sums of the scan
 };
 

@@ -267,10 +267,30 @@ __global__ void scan_add_kernel(int *__restrict__ out, const int *__restrict__ s
 __global__ void cell_scatter_kernel(const int *__restrict__ cell_of,
                                     const int *__restrict__ slot,
                                     const int *__restrict__ start, int64_t n,
-                                    int *__restrict__ perm) {
+                                    int *__restrict__ scat) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  perm[start[cell_of[i]] + slot[i]] = (int)i;
+  scat[start[cell_of[i]] + slot[i]] = (int)i;
+}
+
+// The arrival order within a bin (atomic slots) varies from run to run; every
+// later sum runs in bin order, so each bin's members are put in increasing
+// particle index: one wavefront per bin, member p going to the position of
+// its rank among the bin's indices.  Results are then reproducible bit for
+// bit.
+__global__ void __launch_bounds__(256)
+cell_order_kernel(const int *__restrict__ start, const int *__restrict__ scat, int nbins,
+                  int *__restrict__ perm) {
+  const int bin = blockIdx.x * 4 + threadIdx.x / 64;
+  const int lane = threadIdx.x % 64;
+  if (bin >= nbins) return;
+  const int lo = start[bin], k = start[bin + 1] - lo;
+  for (int p = lane; p < k; p += 64) {
+    const int v = scat[lo + p];
+    int rank = 0;
+    for (int q = 0; q < k; ++q) rank += scat[lo + q] < v ? 1 : 0;
+    perm[lo + rank] = v;
+  }
 }
 
 // out[0..n] = exclusive prefix sums of in[0..n) (out[n] = total); tmp holds
@@ -303,7 +323,10 @@ static void build_bins(Handle &h, const double *xw, Bins &b) {
                      b.scan_tmp, ncells);
   PSE_LAUNCH_CHECK();
   hipLaunchKernelGGL(cell_scatter_kernel, dim3(nblocks(h.n, 256)), dim3(256), 0,
-                     h.stream, b.of, b.slot, b.start, h.n, b.perm);
+                     h.stream, b.of, b.slot, b.start, h.n, b.scat);
+  PSE_LAUNCH_CHECK();
+  hipLaunchKernelGGL(cell_order_kernel, dim3((unsigned)((ncells + 3) / 4)), dim3(256), 0,
+                     h.stream, b.start, b.scat, ncells, b.perm);
   PSE_LAUNCH_CHECK();
 }
 
