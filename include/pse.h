@@ -67,7 +67,11 @@ enum {
 };
 
 enum { PSE_FP64 = 0, PSE_MIXED = 1 };     /* pse_params.precision */
-enum { PSE_REAL = 1u, PSE_WAVE = 2u };     /* pse_mobility_apply parts */
+/* pse_mobility_apply parts; PSE_ES_BLOCK with either or both parts applies
+ * only the stresslet-strain block M_ES (in's s components to out's e
+ * components, the other components of out untouched) through the operator
+ * the constrained step solves with (moment or derivative gridding). */
+enum { PSE_REAL = 1u, PSE_WAVE = 2u, PSE_ES_BLOCK = 4u };
 
 /* Input parameters.  Fields set to 0 are derived (see pse_derive). */
 typedef struct pse_params {
@@ -92,6 +96,12 @@ typedef struct pse_params {
   int32_t graphs;          /* 0: replay each constraint-operator application
                               from a captured hipGraph (captured on first use
                               per input/output pair); -1: launch eagerly     */
+  int32_t deriv_gridding;  /* wave-space part of the constraint operator
+                              M_ES: 1 = the five stresslet moments gridded
+                              and transformed each way; 2 = three grids each
+                              way (stresslets spread with the Gaussian's
+                              gradient, strain interpolated with it);
+                              0 = library default (1)                       */
   void *stream;            /* hipStream_t to run on, or NULL                 */
 } pse_params;
 

@@ -153,6 +153,47 @@ static void mobility(Handle &h, const double *xw, bool want_real, bool want_wave
   }
 }
 
+// Wave-space part of M_ES with derivative gridding: the stresslets spread
+// with the Gaussian's gradient onto three grids, the derivative k-space
+// factors, and the strain interpolated with the gradient (three grids each
+// way instead of five).
+template <typename T>
+static void wave_apply_dg(Handle &h, const double *xw, const double *in, Layout lin,
+                          const CompSet &cin, double *out, Layout lout, const CompSet &cout,
+                          bool accumulate) {
+  GridSet<T> &G = grids<T>(h);
+  T *gin = reinterpret_cast<T *>(G.gin), *gout = reinterpret_cast<T *>(G.gout);
+  const CompSet c3 = comps_range(0, 3);
+  spread_deriv<T>(h, in, lin, cin, gin);
+  rfft_xy<T>(h, gin, G.twiddle, 3, -1);
+  kspace_fused<T>(h, G.gin, c3, G.gout, c3, G.twiddle, true);
+  rfft_xy<T>(h, gout, G.twiddle, 3, +1);
+  interp_deriv<T>(h, xw, gout, cout, out, lout, accumulate, 1.0);
+}
+
+// out[E] = M_ES in[S] (layouts lin, lout), the operator of the stresslet
+// constraint: derivative gridding for the wave part when the handle uses
+// it, else the moment product.
+static void es_apply(Handle &h, const double *xw, bool want_real, bool want_wave,
+                     const double *in, Layout lin, double *out, Layout lout, bool fp64) {
+  const CompSet es = comps_range(6, 11);
+  if (!h.deriv) {
+    mobility(h, xw, want_real, want_wave, in, lin, es, out, lout, es, fp64);
+    return;
+  }
+  const bool f32 = h.mixed && !fp64;
+  bool acc = false;
+  if (want_real) {
+    if (f32) real_apply<float>(h, xw, in, lin, es, out, lout, es, false);
+    else real_apply<double>(h, xw, in, lin, es, out, lout, es, false);
+    acc = true;
+  }
+  if (want_wave) {
+    if (f32) wave_apply_dg<float>(h, xw, in, lin, es, out, lout, es, acc);
+    else wave_apply_dg<double>(h, xw, in, lin, es, out, lout, es, acc);
+  }
+}
+
 template <typename T>
 static void wave_sqrt_t(Handle &h, const double *xw, const double *psi, uint64_t seed,
                         uint64_t counter, double *out, const CompSet &cout, Layout lout) {
@@ -266,7 +307,7 @@ static void stresslet_solve(Handle &h, const double *xh, const double *b, double
   auto make_op = [&, l5](bool fp64) {
     return Op([&, fp64, l5](const double *in, double *o) {
       run_graphed(h, in, o, fp64 ? 1 : 2,
-                  [&] { mobility(h, xh, true, true, in, l5, es, o, l5, es, fp64); });
+                  [&] { es_apply(h, xh, true, true, in, l5, o, l5, fp64); });
     });
   };
   if (!h.mixed) {
@@ -369,6 +410,8 @@ static void create(const pse_params &p, Handle &h) {
   // tiles, so a stencil (P points) must not reach beyond one tile.
   h.stile = spread_tile(h.d.grid, h.d.support);
   h.sbins.nc = h.stile ? h.d.grid / h.stile : 0;
+  // derivative gridding needs the tile lists and at most 10^3 stencil points
+  h.deriv = p.deriv_gridding == 2 && h.stile != 0 && h.d.support <= 10;
   if (p.stream) {
     h.stream = (hipStream_t)p.stream;
     h.own_stream = false;
@@ -555,7 +598,7 @@ const char *pse_last_error(const pse_handle *hd) {
 int pse_mobility_apply(pse_handle *hd, const double *x, const double *in, double *out,
                        unsigned parts) {
   if (!hd) return PSE_ERR_INVALID;
-  if (!x || !in || !out || parts == 0 || (parts & ~3u)) {
+  if (!x || !in || !out || (parts & 3u) == 0 || (parts & ~7u)) {
     hd->h.err = "pse_mobility_apply: null pointer or bad parts";
     return PSE_ERR_INVALID;
   }
@@ -563,8 +606,12 @@ int pse_mobility_apply(pse_handle *hd, const double *x, const double *in, double
     Handle &h = hd->h;
     const CompSet all = comps_range(0, NC);
     prepare_positions(h, x, h.xw);
-    mobility(h, h.xw, parts & PSE_REAL, parts & PSE_WAVE, in, FULL_LAYOUT, all, out,
-             FULL_LAYOUT, all, false);
+    if (parts & PSE_ES_BLOCK)
+      es_apply(h, h.xw, parts & PSE_REAL, parts & PSE_WAVE, in, FULL_LAYOUT, out, FULL_LAYOUT,
+               false);
+    else
+      mobility(h, h.xw, parts & PSE_REAL, parts & PSE_WAVE, in, FULL_LAYOUT, all, out,
+               FULL_LAYOUT, all, false);
     if (check_finite(h, out, (size_t)h.n * NC))
       throw Error{PSE_ERR_NONFINITE, "non-finite mobility product (non-finite input?)"};
   });

@@ -81,10 +81,13 @@ __device__ __forceinline__ bool stencil_meets(int st, int t0, int P, int S, int 
 }
 
 // The candidate lists hold one record per (tile, particle) pair: the
-// particle index (rp) and the record's one-dimensional Gaussian weights at
-// the tile's S grid positions along x, y and z (rw, 3 S doubles, zero outside
-// the stencil).  The weights depend on the positions only, so they are formed
-// once per position update, when the lists are built.
+// particle index (rp) and REC_W(S) doubles (rw): the one-dimensional Gaussian
+// weights at the tile's S grid positions along x, y and z (zero outside the
+// stencil), then per axis the offset d0 such that d0 + i h is the distance
+// from the particle to tile position i wherever the weight is nonzero (the
+// gradient weights of derivative gridding are -2 kcoef (d0 + i h) w_i).  They
+// depend on the positions only, so they are formed once per position update,
+// when the lists are built.
 struct TileRecs {
   int *p;
   double *w;
@@ -129,9 +132,10 @@ tile_list_kernel(const double *__restrict__ x, GridGeom g, int S, int nb,
       if (ok) {
         const int e = pos + __popcll(m & ((1ull << lane) - 1ull));
         rec.p[e] = p;
-        double *w = rec.w + (size_t)e * (3 * S);
+        double *w = rec.w + (size_t)e * (3 * S + 3);
         for (int d = 0; d < 3; ++d) {
           const double xd = x[3 * p + d];
+          double d0 = 0.0;
           for (int i = 0; i < S; ++i) {
             int a = (tc[d] * S + i - st[d]) % ng;
             a += a < 0 ? ng : 0;
@@ -139,9 +143,11 @@ tile_list_kernel(const double *__restrict__ x, GridGeom g, int S, int nb,
             if (a < P) {
               const double dx = (st[d] + a) * g.h - xd;
               wi = g.knorm * exp(-g.kcoef * dx * dx);
+              d0 = dx - i * g.h;
             }
             w[d * S + i] = wi;
           }
+          w[3 * S + d] = d0;
         }
       }
       pos += __popcll(m);
@@ -170,7 +176,7 @@ spread_list_kernel(const double *__restrict__ q, Layout lq, CompSet cs, GridGeom
                    const int *__restrict__ tstart, TileRecs rec, T *__restrict__ grids,
                    size_t ngrid) {
   constexpr int NT = S * S * S / ZPT;
-  constexpr int RW = 3 * S;
+  constexpr int RW = 3 * S + 3;
   constexpr int WPT = (GMAXC * RW + NT - 1) / NT;
   constexpr int NCMP = NCM + (NCM & 1);
   static_assert(GMAXC <= NT, "one candidate per thread in the moment gather");
@@ -233,6 +239,101 @@ spread_list_kernel(const double *__restrict__ q, Layout lq, CompSet cs, GridGeom
 #pragma unroll
     for (int k = 0; k < NCM; ++k)
       if (k < cs.n) grids[(size_t)k * ngrid + gi] = acc[z][k];
+  }
+}
+
+// Derivative gridding of the stresslets (input of the constraint operator):
+// three grids D_i(x_n) = sum_b sum_j S_b,ij dK/dx_j (x_n - x_b), with S_b the
+// symmetric traceless tensor of the particle's five components in the Y_q
+// basis.  Their transform is i k . S^ K^, so the k-space factor of the
+// stresslet column, -3 i f1(ka) Y_q k, becomes -3 f1(ka) on D^ (Eq. WSops
+// with the gradient moved onto the Gaussian).  Tiles, records and staging as
+// spread_list_kernel; per candidate the gradient weights along each axis are
+// g_i = -2 kcoef (d0 + i h) w_i, and per point dK/dx = g_x w_y w_z, etc.
+template <typename T, int S, int ZPT>
+__global__ void __launch_bounds__(S * S * S / ZPT)
+spread_deriv_kernel(const double *__restrict__ q, Layout lq, CompSet cs, GridGeom g, int nb,
+                    const int *__restrict__ tstart, TileRecs rec, T *__restrict__ grids,
+                    size_t ngrid) {
+  constexpr int NT = S * S * S / ZPT;
+  constexpr int RW = 3 * S + 3;
+  constexpr int WPT = (GMAXC * RW + NT - 1) / NT;
+  static_assert(GMAXC <= NT, "one candidate per thread in the moment gather");
+  __shared__ double raw[GMAXC * RW];
+  __shared__ T wg[GMAXC * 6 * S];      // per candidate: w (3 S), then g (3 S)
+  __shared__ T st6[GMAXC * 6];         // per candidate: Sxx Syy Szz Sxy Sxz Syz
+  const int tile = blockIdx.x;
+  const int tc[3] = {tile % nb, (tile / nb) % nb, tile / (nb * nb)};
+  const int lo = tstart[tile];
+  const int total = tstart[tile + 1] - lo;
+  const int ng = g.ng;
+  const int tid = threadIdx.x;
+  const int lx = tid % S, ly = (tid / S) % S, z0 = (tid / (S * S)) * ZPT;
+  const T r2 = (T)0.70710678118654752440, r6 = (T)0.40824829046386301637;
+  T acc[ZPT][3];
+#pragma unroll
+  for (int z = 0; z < ZPT; ++z)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) acc[z][k] = (T)0;
+  for (int c0 = 0; c0 < total; c0 += GMAXC) {
+    const int nchunk = min(GMAXC, total - c0);
+    const int nw = nchunk * RW;
+    __syncthreads();
+    const int pj = tid < nchunk ? rec.p[lo + c0 + tid] : 0;
+    const double *wsrc = rec.w + (size_t)(lo + c0) * RW;
+    double wv[WPT];
+#pragma unroll
+    for (int i = 0; i < WPT; ++i) {
+      const int t = tid + i * NT;
+      wv[i] = t < nw ? wsrc[t] : 0.0;
+    }
+    if (tid < nchunk) {
+      T sq[5];
+#pragma unroll
+      for (int k = 0; k < 5; ++k)
+        sq[k] = (T)q[(size_t)pj * lq.stride + cs.idx[k] - lq.off];
+      T *o = st6 + tid * 6;
+      o[0] = r2 * sq[3] + r6 * sq[4];
+      o[1] = -r2 * sq[3] + r6 * sq[4];
+      o[2] = (T)-2 * r6 * sq[4];
+      o[3] = r2 * sq[0];
+      o[4] = r2 * sq[1];
+      o[5] = r2 * sq[2];
+    }
+#pragma unroll
+    for (int i = 0; i < WPT; ++i) {
+      const int t = tid + i * NT;
+      if (t < nw) raw[t] = wv[i];
+    }
+    __syncthreads();
+    for (int t = tid; t < nchunk * 3 * S; t += NT) {
+      const int j = t / (3 * S), r = t % (3 * S), d = r / S, i = r % S;
+      const double w = raw[j * RW + r];
+      const double dx = raw[j * RW + 3 * S + d] + i * g.h;
+      wg[j * 6 * S + r] = (T)w;
+      wg[j * 6 * S + 3 * S + r] = (T)(-2.0 * g.kcoef * dx * w);
+    }
+    __syncthreads();
+    for (int j = 0; j < nchunk; ++j) {
+      const T *wj = wg + j * 6 * S, *gj = wj + 3 * S, *sj = st6 + j * 6;
+      const T gxwy = gj[lx] * wj[S + ly], wxgy = wj[lx] * gj[S + ly], wxwy = wj[lx] * wj[S + ly];
+      const T sxx = sj[0], syy = sj[1], szz = sj[2], sxy = sj[3], sxz = sj[4], syz = sj[5];
+#pragma unroll
+      for (int z = 0; z < ZPT; ++z) {
+        const T wz = wj[2 * S + z0 + z], gz = gj[2 * S + z0 + z];
+        const T a = gxwy * wz, b = wxgy * wz, c = wxwy * gz;
+        acc[z][0] += sxx * a + sxy * b + sxz * c;
+        acc[z][1] += sxy * a + syy * b + syz * c;
+        acc[z][2] += sxz * a + syz * b + szz * c;
+      }
+    }
+  }
+#pragma unroll
+  for (int z = 0; z < ZPT; ++z) {
+    const size_t gi = ((size_t)(tc[2] * S + z0 + z) * ng + tc[1] * S + ly) * ng
+                      + tc[0] * S + lx;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) grids[(size_t)k * ngrid + gi] = acc[z][k];
   }
 }
 
@@ -469,7 +570,11 @@ __device__ __forceinline__ bool zero_mode(int ix, int iy, int iz, int n) {
 // in the same registers -- the inverse transform runs the passes in reverse
 // order, so its input layout is the forward output layout -- transformed back
 // along z and stored.  One read of the inputs and one write of the outputs.
-template <typename T, int N>
+// DG (derivative gridding of the constraint operator): the inputs are the
+// three grids D^ of the stresslets spread with the Gaussian's gradient, so
+// rho = -3 f1(ka) D^, and the outputs are the three grids v^ = 3 f1(ka) u^
+// whose gradient the interpolation takes.
+template <typename T, int N, bool DG>
 __global__ void __launch_bounds__(512)
 kspace_fused_kernel(const cplx<T> *__restrict__ in, CompSet cin, cplx<T> *__restrict__ out,
                     CompSet cout, KGeom kg, const typename TabT<T>::type *__restrict__ ktab,
@@ -520,8 +625,19 @@ kspace_fused_kernel(const cplx<T> *__restrict__ in, CompSet cin, cplx<T> *__rest
         if (zero_mode(ix, iy, iz, N)) continue;
         const int kz = kidx(iz, N);
         const auto tb = ktab[ix * ix + ky * ky + kz * kz];
-        const T kv[3] = {tp * ix, tp * ky, tp * kz};
-        add_P<C, T>(c, v[b * RL + r], kv, tb.x, tb.y, rho[b * RL + r]);
+        if constexpr (DG) {
+          const T f = (T)-3 * (T)tb.y;
+          const C vv = v[b * RL + r];
+#pragma unroll
+          for (int m = 0; m < 3; ++m)
+            if (m == c) {
+              rho[b * RL + r][m].x += f * vv.x;
+              rho[b * RL + r][m].y += f * vv.y;
+            }
+        } else {
+          const T kv[3] = {tp * ix, tp * ky, tp * kz};
+          add_P<C, T>(c, v[b * RL + r], kv, tb.x, tb.y, rho[b * RL + r]);
+        }
       }
   }
   // u = scale (I - k^k^) rho
@@ -567,8 +683,16 @@ kspace_fused_kernel(const cplx<T> *__restrict__ in, CompSet cin, cplx<T> *__rest
         }
         const int kz = kidx(iz, N);
         const auto tb = ktab[ix * ix + ky * ky + kz * kz];
-        const T kv[3] = {tp * ix, tp * ky, tp * kz};
-        v[e] = apply_Pdag<C, T>(c, rho[e], kv, tb.x, tb.y);
+        if constexpr (DG) {
+          const T f = (T)3 * (T)tb.y;
+          v[e] = C{(T)0, (T)0};
+#pragma unroll
+          for (int m = 0; m < 3; ++m)
+            if (m == c) v[e] = C{f * rho[e][m].x, f * rho[e][m].y};
+        } else {
+          const T kv[3] = {tp * ix, tp * ky, tp * kz};
+          v[e] = apply_Pdag<C, T>(c, rho[e], kv, tb.x, tb.y);
+        }
       }
     reg_fft_inverse<T, N, E>(v, t, lds, TL, line, tw);
     C *dst = out + (size_t)q * hsz + base;
@@ -794,7 +918,7 @@ void build_tile_lists(Handle &h, const double *xw) {
   PSE_LAUNCH_CHECK();
 }
 
-size_t tile_record_bytes(int S) { return sizeof(int) + 3 * (size_t)S * sizeof(double); }
+size_t tile_record_bytes(int S) { return sizeof(int) + (3 * (size_t)S + 3) * sizeof(double); }
 
 namespace {
 
@@ -807,6 +931,85 @@ template <typename F> void with_ncm(int n, F f) {
 }
 
 }  // namespace
+
+// Strain from derivative gridding (output of the constraint operator): with
+// v = the three velocity grids of the k-space factor 3 f1(ka) u^, the strain
+// is e_q = -Y_q : sum_n v(x_n) (x) grad K(x_n - x_p) (the interpolation of
+// Y_q : grad v with the gradient moved onto the Gaussian).  One wavefront per
+// particle as interp_kernel; per stencil point the gradient weight is
+// -2 kcoef d K(d), d = x_n - x_p; the sums T_ij = v_i dK/dx_j enter only
+// through their symmetric traceless part.
+template <typename T, int MAXIT>
+__global__ void __launch_bounds__(256)
+interp_deriv_kernel(const double *__restrict__ x, const T *__restrict__ grids, size_t ngrid,
+                    CompSet cs, GridGeom g, const int *__restrict__ order, int64_t n,
+                    double *__restrict__ out, Layout lo, int accumulate, double scale) {
+  const int lane = threadIdx.x & 63;
+  const int64_t t = (int64_t)xcd_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
+  if (t >= n) return;
+  const int64_t p = order ? order[t] : t;
+  const double px = x[3 * p], py = x[3 * p + 1], pz = x[3 * p + 2];
+  const int P = g.P, P3 = P * P * P;
+  const int ix0 = stencil_start(px, g.h, P);
+  const int iy0 = stencil_start(py, g.h, P);
+  const int iz0 = stencil_start(pz, g.h, P);
+  const double kn3 = g.knorm * g.knorm * g.knorm;
+  // Txx, Tyy, Tzz, Txy + Tyx, Txz + Tzx, Tyz + Tzy
+  T acc[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) acc[k] = (T)0;
+  size_t gi[MAXIT];
+  T gw[MAXIT][3];
+#pragma unroll
+  for (int it = 0; it < MAXIT; ++it) {
+    const int s = lane + 64 * it;
+    const int a = s % P, b = (s / P) % P, c = s / (P * P);
+    const double dx = (ix0 + a) * g.h - px;
+    const double dy = (iy0 + b) * g.h - py;
+    const double dz = (iz0 + c) * g.h - pz;
+    const bool in = s < P3;
+    const double f = in ? -2.0 * g.kcoef * kn3 * exp(-g.kcoef * (dx * dx + dy * dy + dz * dz))
+                        : 0.0;
+    gw[it][0] = (T)(f * dx);
+    gw[it][1] = (T)(f * dy);
+    gw[it][2] = (T)(f * dz);
+    gi[it] = in ? ((size_t)wrapi(iz0 + c, g.ng) * g.ng + wrapi(iy0 + b, g.ng)) * g.ng
+                      + wrapi(ix0 + a, g.ng)
+                : 0;
+  }
+  T v[3][MAXIT];
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int it = 0; it < MAXIT; ++it) v[k][it] = grids[(size_t)k * ngrid + gi[it]];
+#pragma unroll
+  for (int it = 0; it < MAXIT; ++it) {
+    acc[0] += v[0][it] * gw[it][0];
+    acc[1] += v[1][it] * gw[it][1];
+    acc[2] += v[2][it] * gw[it][2];
+    acc[3] += v[0][it] * gw[it][1] + v[1][it] * gw[it][0];
+    acc[4] += v[0][it] * gw[it][2] + v[2][it] * gw[it][0];
+    acc[5] += v[1][it] * gw[it][2] + v[2][it] * gw[it][1];
+  }
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    T w = acc[k];
+    for (int off = 32; off > 0; off >>= 1) w += __shfl_xor(w, off, 64);
+    acc[k] = w;
+  }
+  if (lane == 0) {
+    const double r2 = 0.70710678118654752440, r6 = 0.40824829046386301637;
+    const double txx = acc[0], tyy = acc[1], tzz = acc[2];
+    const double e[5] = {-r2 * (double)acc[3], -r2 * (double)acc[4], -r2 * (double)acc[5],
+                         -r2 * (txx - tyy), -r6 * (txx + tyy - 2.0 * tzz)};
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      double *o = out + p * lo.stride + cs.idx[k] - lo.off;
+      const double val = scale * e[k];
+      *o = accumulate ? *o + val : val;
+    }
+  }
+}
 
 template <typename T>
 void spread(Handle &h, const double *x, const double *q, Layout lq, const CompSet &cs,
@@ -870,11 +1073,63 @@ void interpolate(Handle &h, const double *x, const T *grids, const CompSet &cs, 
   PSE_LAUNCH_CHECK();
 }
 
+// Derivative gridding of the constraint operator (tile lists required): the
+// stresslet components cs (five, in the Y_q basis) of q in layout lq spread
+// onto three grids with the Gaussian's gradient.
+template <typename T>
+void spread_deriv(Handle &h, const double *q, Layout lq, const CompSet &cs, T *grids) {
+  if (!h.stile || cs.n != 5) throw Error{PSE_ERR_INVALID, "derivative gridding unavailable"};
+  const GridGeom g = geom(h);
+  ProfScope ps(h, PK_SPREAD, 3.0 * h.ngrid * sizeof(T) + (double)h.n * (3 + 5) * 8);
+  const int nb = h.sbins.nc;
+  const unsigned tiles = (unsigned)nb * nb * nb;
+  const TileRecs rec = tile_recs(h);
+  const int *ts = (const int *)h.tl_start;
+  if (h.stile == 4)
+    hipLaunchKernelGGL((spread_deriv_kernel<T, 4, 1>), dim3(tiles), dim3(64), 0, h.stream, q,
+                       lq, cs, g, nb, ts, rec, grids, h.ngrid);
+  else if (h.stile == 8)
+    hipLaunchKernelGGL((spread_deriv_kernel<T, 8, 8>), dim3(tiles), dim3(64), 0, h.stream, q,
+                       lq, cs, g, nb, ts, rec, grids, h.ngrid);
+  else
+    throw Error{PSE_ERR_INVALID, "unsupported spreading tile"};
+  PSE_LAUNCH_CHECK();
+}
+
+// The strain components cs (five) of out in layout lo from the three
+// velocity grids of derivative gridding (see interp_deriv_kernel).
+template <typename T>
+void interp_deriv(Handle &h, const double *x, const T *grids, const CompSet &cs, double *out,
+                  Layout lo, bool accumulate, double scale) {
+  if (cs.n != 5) throw Error{PSE_ERR_INVALID, "derivative gridding unavailable"};
+  const GridGeom g = geom(h);
+  const int acc = accumulate ? 1 : 0;
+  ProfScope ps(h, PK_INTERP, 3.0 * h.ngrid * sizeof(T) + (double)h.n * (3 + 5) * 8);
+  const int P3 = g.P * g.P * g.P;
+  const dim3 grid(nblocks(h.n, 4)), block(256);
+  const int *order = (const int *)h.cells.perm;
+  if (P3 <= 256)
+    hipLaunchKernelGGL((interp_deriv_kernel<T, 4>), grid, block, 0, h.stream, x, grids,
+                       h.ngrid, cs, g, order, h.n, out, lo, acc, scale);
+  else if (P3 <= 384)
+    hipLaunchKernelGGL((interp_deriv_kernel<T, 6>), grid, block, 0, h.stream, x, grids,
+                       h.ngrid, cs, g, order, h.n, out, lo, acc, scale);
+  else if (P3 <= 512)
+    hipLaunchKernelGGL((interp_deriv_kernel<T, 8>), grid, block, 0, h.stream, x, grids,
+                       h.ngrid, cs, g, order, h.n, out, lo, acc, scale);
+  else if (P3 <= 1024)
+    hipLaunchKernelGGL((interp_deriv_kernel<T, 16>), grid, block, 0, h.stream, x, grids,
+                       h.ngrid, cs, g, order, h.n, out, lo, acc, scale);
+  else
+    throw Error{PSE_ERR_INVALID, "derivative gridding supports P <= 10"};
+  PSE_LAUNCH_CHECK();
+}
+
 namespace {
 
 template <typename T, int N>
 void launch_fused(Handle &h, const cplx<T> *in, const CompSet &cin, cplx<T> *out,
-                  const CompSet &cout, const cplx<T> *tw) {
+                  const CompSet &cout, const cplx<T> *tw, bool dg) {
   constexpr int TPL = N / fused_e(N);
   // at least four z-lines (64-byte row segments) per workgroup on long lines
   const int tl = lines_per_block(N, TPL, N * sizeof(cplx<T>), (size_t)N / 2,
@@ -883,18 +1138,22 @@ void launch_fused(Handle &h, const cplx<T> *in, const CompSet &cin, cplx<T> *out
   const unsigned nb = (unsigned)(N * (N / 2 / tl));
   using Tab = typename TabT<T>::type;
   const Tab *tab = sizeof(T) == 8 ? (const Tab *)h.ktab : (const Tab *)h.ktab32;
-  hipLaunchKernelGGL((kspace_fused_kernel<T, N>), dim3(nb), dim3(tl * TPL), lds, h.stream, in,
-                     cin, out, cout, kgeom(h), tab, tw, tl);
+  if (dg)
+    hipLaunchKernelGGL((kspace_fused_kernel<T, N, true>), dim3(nb), dim3(tl * TPL), lds,
+                       h.stream, in, cin, out, cout, kgeom(h), tab, tw, tl);
+  else
+    hipLaunchKernelGGL((kspace_fused_kernel<T, N, false>), dim3(nb), dim3(tl * TPL), lds,
+                       h.stream, in, cin, out, cout, kgeom(h), tab, tw, tl);
   PSE_LAUNCH_CHECK();
 }
 
 }  // namespace
 
-#define PSE_CASE_F(NN) case NN: launch_fused<T, NN>(h, in, cin, out, cout, tw); break;
+#define PSE_CASE_F(NN) case NN: launch_fused<T, NN>(h, in, cin, out, cout, tw, dg); break;
 
 template <typename T>
 void kspace_fused(Handle &h, const cplx<T> *in, const CompSet &cin, cplx<T> *out,
-                  const CompSet &cout, const cplx<T> *tw) {
+                  const CompSet &cout, const cplx<T> *tw, bool dg) {
   const size_t hsz = h.ngrid / 2;
   ProfScope ps(h, PK_KSPACE, (double)(cin.n + cout.n) * hsz * sizeof(cplx<T>));
   switch (h.d.grid) {
@@ -947,7 +1206,12 @@ template <typename T> void to_double(Handle &h, const T *src, size_t n, double *
   template void kspace_noise<T>(Handle &, const double *, uint64_t, uint64_t,    \
                                 cplx<T> *, const CompSet &);                     \
   template void kspace_fused<T>(Handle &, const cplx<T> *, const CompSet &,      \
-                                cplx<T> *, const CompSet &, const cplx<T> *);    \
+                                cplx<T> *, const CompSet &, const cplx<T> *,     \
+                                bool);                                           \
+  template void spread_deriv<T>(Handle &, const double *, Layout, const CompSet &, \
+                                T *);                                            \
+  template void interp_deriv<T>(Handle &, const double *, const T *,             \
+                                const CompSet &, double *, Layout, bool, double); \
   template void zero_grids<T>(Handle &, T *, int);                               \
   template void from_double<T>(Handle &, const double *, size_t, T *);           \
   template void to_double<T>(Handle &, const T *, size_t, double *);

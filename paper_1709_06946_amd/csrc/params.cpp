@@ -90,6 +90,7 @@ void derive(const pse_params &p, pse_derived &d) {
   d.refine_passes = p.refine_passes > 0 ? p.refine_passes : 3;
   if (d.lanczos_maxit > 500 || d.gmres_restart > 200)
     fail("Krylov basis limits too large");
+  if (p.deriv_gridding < 0 || p.deriv_gridding > 2) fail("deriv_gridding must be 0, 1 or 2");
 }
 
 size_t footprint(const pse_params &p, const pse_derived &d) {
@@ -110,11 +111,11 @@ size_t footprint(const pse_params &p, const pse_derived &d) {
   const int S = spread_tile(d.grid, d.support);
   const size_t tiles3 = S ? ng3 / ((size_t)S * S * S) : 0;
   if (S) {
-    // tile CSR and one record per (tile, particle) pair: the particle index
-    // and 3 S one-dimensional weights
+    // tile CSR and one record per (tile, particle) pair: the particle index,
+    // 3 S one-dimensional weights and 3 offsets
     const size_t cap = n * tiles_per_particle(d.support, S);
     bytes += (2 * tiles3 + tiles3 / 1024 + 16) * sizeof(int)
-             + cap * (sizeof(int) + 3 * (size_t)S * sizeof(double)) + 256;
+             + cap * (sizeof(int) + (3 * (size_t)S + 3) * sizeof(double)) + 256;
   }
   bytes += (2 * (ncell3 + tiles3) + 4 + (ncell3 + tiles3) / 1024 + 16) * sizeof(int)
            + 8 * n * sizeof(int);

@@ -169,6 +169,7 @@ struct Handle {
   // captured constraint-operator applications, keyed by (input, output,
   // kind); cleared when a buffer baked into them is reallocated
   bool use_graphs = true;
+  bool deriv = false;        // derivative gridding in the constraint operator
   // iteration counts of the previous Lanczos and GMRES (FP64, FP32) solves
   int lz_prev = 0;
   int lz_prev_rpy = 0;       // the same for the RPY sampler's UF-block Lanczos
@@ -262,10 +263,17 @@ void interpolate(Handle &h, const double *x, const T *grids, const CompSet &cs, 
 template <typename T>
 void kspace_noise(Handle &h, const double *psi, uint64_t seed, uint64_t counter,
                   cplx<T> *out, const CompSet &cout);
-// z transform + k-space + inverse z transform in one kernel
+// z transform + k-space + inverse z transform in one kernel; dg: the
+// derivative-gridding factors (three grids in, three out)
 template <typename T>
 void kspace_fused(Handle &h, const cplx<T> *in, const CompSet &cin, cplx<T> *out,
-                  const CompSet &cout, const cplx<T> *tw);
+                  const CompSet &cout, const cplx<T> *tw, bool dg = false);
+// derivative gridding of the constraint operator (three grids each way)
+template <typename T>
+void spread_deriv(Handle &h, const double *q, Layout lq, const CompSet &cs, T *grids);
+template <typename T>
+void interp_deriv(Handle &h, const double *x, const T *grids, const CompSet &cs, double *out,
+                  Layout lo, bool accumulate, double scale);
 template <typename T> void zero_grids(Handle &h, T *g, int ncomp);
 void build_tile_lists(Handle &h, const double *xw);
 size_t tile_record_bytes(int S);                  // one (tile, particle) record

@@ -12,7 +12,7 @@ LIB_PATH = os.path.join(HERE, 'libpse.so')
 
 PSE_OK, PSE_WARN_NOT_CONVERGED = 0, 1
 PSE_FP64, PSE_MIXED = 0, 1
-PSE_REAL, PSE_WAVE = 1, 2
+PSE_REAL, PSE_WAVE, PSE_ES_BLOCK = 1, 2, 4
 
 
 class pse_params(ctypes.Structure):
@@ -25,7 +25,7 @@ class pse_params(ctypes.Structure):
                 ('lanczos_tol', ctypes.c_double), ('gmres_restart', ctypes.c_int32),
                 ('gmres_maxit', ctypes.c_int32), ('gmres_tol', ctypes.c_double),
                 ('refine_passes', ctypes.c_int32), ('graphs', ctypes.c_int32),
-                ('stream', ctypes.c_void_p)]
+                ('deriv_gridding', ctypes.c_int32), ('stream', ctypes.c_void_p)]
 
 
 class pse_derived(ctypes.Structure):
@@ -164,12 +164,12 @@ class PSEError(RuntimeError):
 def make_params(n, box, *, radius=1.0, viscosity=1.0, kT=1.0, tol=1e-3, grid=0,
                 support=0, xi=0.0, rcut=0.0, precision=PSE_FP64, lanczos_maxit=0,
                 lanczos_tol=0.0, gmres_restart=0, gmres_maxit=0, gmres_tol=0.0,
-                refine_passes=0, graphs=0, stream=None):
+                refine_passes=0, graphs=0, deriv_gridding=0, stream=None):
     return pse_params(int(n), float(box), float(radius), float(viscosity), float(kT),
                       float(tol), int(grid), int(support), float(xi), float(rcut),
                       int(precision), int(lanczos_maxit), float(lanczos_tol),
                       int(gmres_restart), int(gmres_maxit), float(gmres_tol),
-                      int(refine_passes), int(graphs), stream)
+                      int(refine_passes), int(graphs), int(deriv_gridding), stream)
 
 
 def derive(params):
