@@ -27,7 +27,7 @@ METRIC = ('particle-steps/s (FTS Brownian, rel.err 1e-3) vs FP64; '
 HBM_PEAK_GBS = 8000.0
 
 
-def run_form(w, precision, steps, warmup, seed, prof_steps=2):
+def run_form(w, precision, steps, warmup, seed, prof_steps=2, deriv_gridding=0):
     """Times `steps` steps with the stage profiler off (the throughput), then
     runs `prof_steps` more with it on (stage times, launch durations)."""
     import torch
@@ -35,7 +35,8 @@ def run_form(w, precision, steps, warmup, seed, prof_steps=2):
     from paper_1709_06946_amd import pse
     N = w['N']
     h = pse.PSE(N, w['L'], grid=w['grid'], tol=w['eps'], precision=precision,
-                lanczos_tol=w['lanczos_tol'], gmres_tol=w['gmres_tol'])
+                lanczos_tol=w['lanczos_tol'], gmres_tol=w['gmres_tol'],
+                deriv_gridding=deriv_gridding)
     x = torch.tensor(w['x'], device='cuda:0')
     FL = torch.tensor(w['FL'], device='cuda:0')
     for k in range(warmup):
@@ -63,6 +64,7 @@ def run_form(w, precision, steps, warmup, seed, prof_steps=2):
     return dict(value=N * steps / dt, ms_per_step=1e3 * dt / steps, prof=prof, stats=stats,
                 prof_steps=prof_steps,
                 derived=dict(grid=d.grid, support=d.support, xi=d.xi, rcut=d.rcut,
+                             deriv_gridding=d.deriv_gridding,
                              eta_s=d.eta_s), finite=bool(torch.isfinite(x).all()))
 
 
@@ -242,6 +244,9 @@ def main():
     ap.add_argument('--no-mixed', action='store_true')
     ap.add_argument('--no-served', action='store_true')
     ap.add_argument('--no-rpy', action='store_true')
+    ap.add_argument('--deriv-gridding', type=int, default=0,
+                    help='gridding of the constraint operator: 0 library default, '
+                         '1 moments, 2 derivative')
     ap.add_argument('--copy-calibration', action='store_true',
                     help='only run a 1 GiB device copy (counter calibration)')
     ap.add_argument('--served-requests', type=int, default=16)
@@ -262,12 +267,14 @@ def main():
     from paper_1709_06946_amd import inputs, pse
     w = inputs.workload(args.workload)
     seed = w['seed']
-    fp64 = run_form(w, pse.PSE_FP64, args.steps, args.warmup, seed)
+    fp64 = run_form(w, pse.PSE_FP64, args.steps, args.warmup, seed,
+                    deriv_gridding=args.deriv_gridding)
     traffic_file = os.path.join(ROOT, 'profiles', f'hbm_traffic_{args.workload}_fp64.md')
     dom, roof = roofline(fp64['prof'], traffic_file, w['grid'])
     mixed = None
     if not args.no_mixed:
-        m = run_form(w, pse.PSE_MIXED, args.steps, args.warmup, seed)
+        m = run_form(w, pse.PSE_MIXED, args.steps, args.warmup, seed,
+                     deriv_gridding=args.deriv_gridding)
         mdom, mroof = roofline(m['prof'], None, w['grid'])
         mixed = dict(value=round(m['value'], 1), ms_per_step=round(m['ms_per_step'], 3),
                      speedup_vs_fp64=round(m['value'] / fp64['value'], 3), dtype='f32+f64',

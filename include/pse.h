@@ -117,6 +117,9 @@ typedef struct pse_derived {
   int32_t cells;           /* cells per side of the real-space cell list     */
   int32_t lanczos_maxit, gmres_restart, gmres_maxit, refine_passes;
   double lanczos_tol, gmres_tol;
+  int32_t deriv_gridding;  /* gridding of M_ES in effect: 1 moments, 2
+                              derivative (2 needs the spreading tiles and
+                              P <= 10, else 1 is used)                      */
 } pse_derived;
 
 /* Krylov statistics of the last call (written by the library, host memory). */

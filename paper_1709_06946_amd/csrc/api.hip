@@ -410,8 +410,7 @@ static void create(const pse_params &p, Handle &h) {
   // tiles, so a stencil (P points) must not reach beyond one tile.
   h.stile = spread_tile(h.d.grid, h.d.support);
   h.sbins.nc = h.stile ? h.d.grid / h.stile : 0;
-  // derivative gridding needs the tile lists and at most 10^3 stencil points
-  h.deriv = p.deriv_gridding == 2 && h.stile != 0 && h.d.support <= 10;
+  h.deriv = h.d.deriv_gridding == 2;
   if (p.stream) {
     h.stream = (hipStream_t)p.stream;
     h.own_stream = false;

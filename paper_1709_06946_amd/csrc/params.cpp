@@ -91,6 +91,8 @@ void derive(const pse_params &p, pse_derived &d) {
   if (d.lanczos_maxit > 500 || d.gmres_restart > 200)
     fail("Krylov basis limits too large");
   if (p.deriv_gridding < 0 || p.deriv_gridding > 2) fail("deriv_gridding must be 0, 1 or 2");
+  d.deriv_gridding =
+      (p.deriv_gridding == 2 && spread_tile(d.grid, d.support) != 0 && d.support <= 10) ? 2 : 1;
 }
 
 size_t footprint(const pse_params &p, const pse_derived &d) {

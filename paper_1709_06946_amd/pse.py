@@ -35,7 +35,8 @@ class pse_derived(ctypes.Structure):
                 ('rcut', ctypes.c_double), ('cells', ctypes.c_int32),
                 ('lanczos_maxit', ctypes.c_int32), ('gmres_restart', ctypes.c_int32),
                 ('gmres_maxit', ctypes.c_int32), ('refine_passes', ctypes.c_int32),
-                ('lanczos_tol', ctypes.c_double), ('gmres_tol', ctypes.c_double)]
+                ('lanczos_tol', ctypes.c_double), ('gmres_tol', ctypes.c_double),
+                ('deriv_gridding', ctypes.c_int32)]
 
 
 class pse_stats(ctypes.Structure):
