@@ -100,7 +100,11 @@ typedef struct pse_params {
                               M_ES: 1 = the five stresslet moments gridded
                               and transformed each way; 2 = three grids each
                               way (stresslets spread with the Gaussian's
-                              gradient, strain interpolated with it);
+                              gradient, strain interpolated with it), with
+                              one more support point when support = 0 (the
+                              gradient's quadrature error is about ten times
+                              the Gaussian's at equal support); falls back
+                              to 1 when that support exceeds 10;
                               0 = library default (1)                       */
   void *stream;            /* hipStream_t to run on, or NULL                 */
 } pse_params;
@@ -118,8 +122,7 @@ typedef struct pse_derived {
   int32_t lanczos_maxit, gmres_restart, gmres_maxit, refine_passes;
   double lanczos_tol, gmres_tol;
   int32_t deriv_gridding;  /* gridding of M_ES in effect: 1 moments, 2
-                              derivative (2 needs the spreading tiles and
-                              P <= 10, else 1 is used)                      */
+                              derivative                                     */
 } pse_derived;
 
 /* Krylov statistics of the last call (written by the library, host memory). */

@@ -68,9 +68,23 @@ void derive(const pse_params &p, pse_derived &d) {
   } else {
     fail("set grid or xi");
   }
+  if (p.deriv_gridding < 0 || p.deriv_gridding > 2) fail("deriv_gridding must be 0, 1 or 2");
   const double eps_q = eps / 20.0;
   d.support = p.support > 0 ? p.support
                             : (int)std::ceil(2.0 / M_PI * std::log(2.0 / eps_q));
+  // Derivative gridding of M_ES: the gradient of the truncated Gaussian
+  // carries about ten times the Gaussian's quadrature error at equal support
+  // (each further point divides both by about 3.5), so with an automatic
+  // support it takes one more point; it needs the spreading tiles and at
+  // most 10 points, else the moment gridding is used.
+  d.deriv_gridding = 1;
+  if (p.deriv_gridding == 2) {
+    const int pd = p.support > 0 ? d.support : d.support + 1;
+    if (pd <= 10 && spread_tile(d.grid, pd) != 0) {
+      d.support = pd;
+      d.deriv_gridding = 2;
+    }
+  }
   if (d.support < 2 || d.support > 16) fail("support must be in [2, 16]");
   if (d.support > d.grid) fail("support larger than the grid");
   d.m = 0.85 * std::sqrt(M_PI * d.support);
@@ -90,9 +104,6 @@ void derive(const pse_params &p, pse_derived &d) {
   d.refine_passes = p.refine_passes > 0 ? p.refine_passes : 3;
   if (d.lanczos_maxit > 500 || d.gmres_restart > 200)
     fail("Krylov basis limits too large");
-  if (p.deriv_gridding < 0 || p.deriv_gridding > 2) fail("deriv_gridding must be 0, 1 or 2");
-  d.deriv_gridding =
-      (p.deriv_gridding == 2 && spread_tile(d.grid, d.support) != 0 && d.support <= 10) ? 2 : 1;
 }
 
 size_t footprint(const pse_params &p, const pse_derived &d) {

@@ -44,7 +44,9 @@ def test_es_block_within_tolerance(eps, mode):
     x, L = packing(100, 0.1, inputs.SEED_BASE)
     h = pse.PSE(100, L, tol=eps, xi=_min_xi(L, eps), deriv_gridding=mode)
     d = h.derived
-    assert d.deriv_gridding == mode
+    # derivative gridding takes one more support point; at eps = 1e-5 that
+    # exceeds 10 and the moment gridding is used
+    assert d.deriv_gridding == (mode if eps >= 1e-4 else 1)
     q = _stresslets(100, 21)
     ref = (ewald.real_apply(x, q, L, d.xi) + ewald.wave_apply(x, q, L, d.xi))[:, 6:11]
     err = rel_err(_es(h, x, q, pse.PSE_REAL | pse.PSE_WAVE), ref)
@@ -68,11 +70,11 @@ def test_es_wave_part_derivative(phi, precision):
 
 def test_derivative_and_moment_gridding_agree_at_tight_tolerance():
     """Both quadratures of the same operator converge to the same sums: at
-    eps = 1e-5 (P = 10, the largest derivative-gridding support) they agree
-    to within twice the tolerance."""
+    eps = 1e-4 (derivative gridding at P = 10, its largest support) they
+    agree to within twice the tolerance."""
     from paper_1709_06946_amd import pse
     x, L = packing(100, 0.1, inputs.SEED_BASE + 5)
-    eps = 1e-5
+    eps = 1e-4
     q = _stresslets(100, 23)
     out = {}
     for mode in (1, 2):
@@ -80,8 +82,8 @@ def test_derivative_and_moment_gridding_agree_at_tight_tolerance():
         assert h.derived.deriv_gridding == mode
         out[mode] = _es(h, x, q, pse.PSE_WAVE)
     err = rel_err(out[2], out[1])
-    print('derivative vs moment gridding at eps=1e-5', err)
-    assert err < 2e-5
+    print('derivative vs moment gridding at eps=1e-4', err)
+    assert err < 2e-4
 
 
 @pytest.mark.parametrize('phi', [0.1, 0.01])
