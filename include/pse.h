@@ -105,7 +105,7 @@ typedef struct pse_params {
                               gradient's quadrature error is about ten times
                               the Gaussian's at equal support); falls back
                               to 1 when that support exceeds 10;
-                              0 = library default (1)                       */
+                              0 = library default (2)                       */
   void *stream;            /* hipStream_t to run on, or NULL                 */
 } pse_params;
 

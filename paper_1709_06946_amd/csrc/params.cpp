@@ -78,7 +78,7 @@ void derive(const pse_params &p, pse_derived &d) {
   // support it takes one more point; it needs the spreading tiles and at
   // most 10 points, else the moment gridding is used.
   d.deriv_gridding = 1;
-  if (p.deriv_gridding == 2) {
+  if (p.deriv_gridding != 1) {   // 0 (default) or 2
     const int pd = p.support > 0 ? d.support : d.support + 1;
     if (pd <= 10 && spread_tile(d.grid, pd) != 0) {
       d.support = pd;

@@ -83,9 +83,10 @@ int main(void) {
 def test_derive_support_and_width_rule(pse, eps):
     """Eq. bound's orthorhombic rule at the tightened quadrature tolerance
     eps/20, a Gaussian truncated at 0.85 of the balanced width, and xi placing
-    exp(-u_N) = e^-9 eps at the Nyquist wave number."""
-    p = pse.make_params(100, 30.0, grid=64, tol=eps)
+    exp(-u_N) = e^-9 eps at the Nyquist wave number (moment gridding)."""
+    p = pse.make_params(100, 30.0, grid=64, tol=eps, deriv_gridding=1)
     d = pse.derive(p)
+    assert d.deriv_gridding == 1
     assert d.support == oparams.support_orthorhombic(eps / 20)
     assert math.isclose(d.m, 0.85 * math.sqrt(math.pi * d.support))
     assert math.isclose(d.h, 30.0 / 64)
@@ -97,11 +98,29 @@ def test_derive_support_and_width_rule(pse, eps):
     assert d.cells == int(30.0 // d.rcut)
 
 
+@pytest.mark.parametrize('eps', [1e-2, 1e-3, 1e-4, 1e-5])
+def test_derivative_gridding_takes_one_more_support_point(pse, eps):
+    """The default gridding of M_ES is the derivative one with one support
+    point more than the moment rule, while that stays within 10 points (else
+    the moment gridding and its support are used)."""
+    base = oparams.support_orthorhombic(eps / 20)
+    for mode in (0, 2):
+        d = pse.derive(pse.make_params(100, 30.0, grid=64, tol=eps, deriv_gridding=mode))
+        if base + 1 <= 10:
+            assert (d.deriv_gridding, d.support) == (2, base + 1)
+        else:
+            assert (d.deriv_gridding, d.support) == (1, base)
+        assert math.isclose(d.m, 0.85 * math.sqrt(math.pi * d.support))
+    with pytest.raises(pse.PSEError):
+        pse.derive(pse.make_params(100, 30.0, grid=64, tol=eps, deriv_gridding=3))
+
+
 def test_derive_support_at_1e3(pse):
     """At eps = 1e-3 the tightened rule gives P = 7 (Table 1's orthorhombic
     row, P = 5, is the untightened rule, pinned in the oracle tests)."""
-    d = pse.derive(pse.make_params(100, 16.12, grid=32, tol=1e-3))
+    d = pse.derive(pse.make_params(100, 16.12, grid=32, tol=1e-3, deriv_gridding=1))
     assert d.support == 7
+    assert pse.derive(pse.make_params(100, 16.12, grid=32, tol=1e-3)).support == 8
 
 
 def test_derive_grid_from_xi(pse):
