@@ -1089,7 +1089,7 @@ void spread_deriv(Handle &h, const double *q, Layout lq, const CompSet &cs, T *g
     hipLaunchKernelGGL((spread_deriv_kernel<T, 4, 1>), dim3(tiles), dim3(64), 0, h.stream, q,
                        lq, cs, g, nb, ts, rec, grids, h.ngrid);
   else if (h.stile == 8)
-    hipLaunchKernelGGL((spread_deriv_kernel<T, 8, 8>), dim3(tiles), dim3(64), 0, h.stream, q,
+    hipLaunchKernelGGL((spread_deriv_kernel<T, 8, 4>), dim3(tiles), dim3(128), 0, h.stream, q,
                        lq, cs, g, nb, ts, rec, grids, h.ngrid);
   else
     throw Error{PSE_ERR_INVALID, "unsupported spreading tile"};
