@@ -157,12 +157,10 @@ static void mobility(Handle &h, const double *xw, bool want_real, bool want_wave
 // with the Gaussian's gradient onto three grids, the derivative k-space
 // factors, and the strain interpolated with the gradient (three grids each
 // way instead of five).
-// wait_before_interp: an event the interpolation's stream waits for first
-// (the pair sum on the side stream, which writes the same outputs).
 template <typename T>
 static void wave_apply_dg(Handle &h, const double *xw, const double *in, Layout lin,
                           const CompSet &cin, double *out, Layout lout, const CompSet &cout,
-                          bool accumulate, hipEvent_t wait_before_interp = nullptr) {
+                          bool accumulate) {
   GridSet<T> &G = grids<T>(h);
   T *gin = reinterpret_cast<T *>(G.gin), *gout = reinterpret_cast<T *>(G.gout);
   const CompSet c3 = comps_range(0, 3);
@@ -170,19 +168,8 @@ static void wave_apply_dg(Handle &h, const double *xw, const double *in, Layout 
   rfft_xy<T>(h, gin, G.twiddle, 3, -1);
   kspace_fused<T>(h, G.gin, c3, G.gout, c3, G.twiddle, true);
   rfft_xy<T>(h, gout, G.twiddle, 3, +1);
-  if (wait_before_interp) PSE_HIP(hipStreamWaitEvent(h.stream, wait_before_interp, 0));
   interp_deriv<T>(h, xw, gout, cout, out, lout, accumulate, 1.0);
 }
-
-// Runs the enclosed launches on another stream of the handle.
-struct OnStream {
-  Handle &h;
-  hipStream_t saved;
-  OnStream(Handle &hh, hipStream_t s) : h(hh), saved(hh.stream) { h.stream = s; }
-  ~OnStream() { h.stream = saved; }
-  OnStream(const OnStream &) = delete;
-  OnStream &operator=(const OnStream &) = delete;
-};
 
 // out[E] = M_ES in[S] (layouts lin, lout), the operator of the stresslet
 // constraint: derivative gridding for the wave part when the handle uses
@@ -195,21 +182,6 @@ static void es_apply(Handle &h, const double *xw, bool want_real, bool want_wave
     return;
   }
   const bool f32 = h.mixed && !fp64;
-  if (want_real && want_wave && h.side && !h.prof.on) {
-    // the pair sum (which writes out) runs beside the wave-space chain, and
-    // the interpolation (which adds to out) waits for it
-    PSE_HIP(hipEventRecord(h.ev_fork, h.stream));
-    PSE_HIP(hipStreamWaitEvent(h.side, h.ev_fork, 0));
-    {
-      OnStream on(h, h.side);
-      if (f32) real_apply<float>(h, xw, in, lin, es, out, lout, es, false);
-      else real_apply<double>(h, xw, in, lin, es, out, lout, es, false);
-      PSE_HIP(hipEventRecord(h.ev_join, h.side));
-    }
-    if (f32) wave_apply_dg<float>(h, xw, in, lin, es, out, lout, es, true, h.ev_join);
-    else wave_apply_dg<double>(h, xw, in, lin, es, out, lout, es, true, h.ev_join);
-    return;
-  }
   bool acc = false;
   if (want_real) {
     if (f32) real_apply<float>(h, xw, in, lin, es, out, lout, es, false);
@@ -295,10 +267,6 @@ static void run_graphed(Handle &h, const void *in, const void *out, int kind, F 
         fn();
       } catch (const Error &err) {
         why = "launch during capture: " + err.msg;
-        // a fork left open by the failure would keep the side stream in the
-        // capture: join it before ending
-        (void)hipEventRecord(h.ev_join, h.side);
-        (void)hipStreamWaitEvent(h.stream, h.ev_join, 0);
       } catch (...) {
         why = "exception during capture";
       }
@@ -452,12 +420,6 @@ static void create(const pse_params &p, Handle &h) {
     h.own_stream = true;
   }
   {
-    std::unique_lock<std::shared_mutex> lk(capture_gate());
-    PSE_HIP(hipStreamCreateWithFlags(&h.side, hipStreamNonBlocking));
-    PSE_HIP(hipEventCreateWithFlags(&h.ev_fork, hipEventDisableTiming));
-    PSE_HIP(hipEventCreateWithFlags(&h.ev_join, hipEventDisableTiming));
-  }
-  {
     int dev = 0, lds = 0;
     PSE_HIP(hipGetDevice(&dev));
     PSE_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
@@ -543,12 +505,9 @@ static void release(Handle &h) {
   clear_graphs(h);
   for (hipEvent_t e : h.prof.pool) (void)hipEventDestroy(e);
   h.prof.pool.clear();
-  {
+  if (h.own_stream && h.stream) {
     std::unique_lock<std::shared_mutex> lk(capture_gate());
-    if (h.ev_fork) (void)hipEventDestroy(h.ev_fork);
-    if (h.ev_join) (void)hipEventDestroy(h.ev_join);
-    if (h.side) (void)hipStreamDestroy(h.side);
-    if (h.own_stream && h.stream) (void)hipStreamDestroy(h.stream);
+    (void)hipStreamDestroy(h.stream);
   }
 }
 

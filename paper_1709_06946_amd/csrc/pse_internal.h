@@ -116,11 +116,6 @@ struct Handle {
   size_t ngrid;              // ng^3
   hipStream_t stream;
   bool own_stream;
-  // second stream of the handle: the real-space pair sum of a constraint-
-  // operator application runs on it beside the wave-space chain (forked and
-  // joined with the two events, so a captured graph holds both branches)
-  hipStream_t side = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   std::string err;
 
   GridSet<double> g64;
