@@ -455,6 +455,9 @@ KrylovResult lanczos_sqrt(Handle &h, const Op &A, const double *b, size_t n, dou
     return res;
   }
   PSE_HIP(hipMemsetAsync(coef_prev, 0, (M + 1) * sizeof(double), h.stream));
+  // iterations before the first read leave their change unset: zero, so that
+  // the history read back is finite
+  PSE_HIP(hipMemsetAsync(chg_hist, 0, (M + 1) * sizeof(double), h.stream));
   vscale_dev(h, V, b, bn, true, n);
   auto sqrt_coef = [&](int mm) {
     // LDS holds d, e and the mm^2 eigenvectors when they fit in 48 KiB
@@ -476,7 +479,9 @@ KrylovResult lanczos_sqrt(Handle &h, const Op &A, const double *b, size_t n, dou
                        h1, h2, vnorm, vn_hist);
     PSE_LAUNCH_CHECK();
     sub_scale(h, w, V, n, j + 1, h2, vnorm);
-    sqrt_coef(j + 1);
+    // f(T) e_1 is needed from one iteration before the first read on (the
+    // change there is taken against it); a breakdown recomputes its own
+    if (j + 2 >= check_from || j + 1 >= M) sqrt_coef(j + 1);
     m = j + 1;
     res.iters = m;
     if (m < check_from && m < M) continue;
