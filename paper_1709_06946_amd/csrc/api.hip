@@ -301,7 +301,6 @@ static void run_graphed(Handle &h, const void *in, const void *out, int kind, F 
 static void stresslet_solve(Handle &h, const double *xh, const double *b, double *S,
                             pse_stats &st, bool &converged) {
   const size_t n5 = (size_t)h.n * 5;
-  const CompSet es = comps_range(6, 11);
   // the operator reads and writes the 5-component vectors directly
   const Layout l5{5, 6};
   auto make_op = [&, l5](bool fp64) {
