@@ -26,6 +26,11 @@ WORKLOADS = {
                                  dt=1e-3, gmres_tol=1e-4, lanczos_tol=1e-3,
                                  index=2),
 }
+# the dense suspension over its tolerance sweep (eps, grid)
+for _eps, _g in ((1e-2, 128), (1e-3, 192), (1e-4, 256), (1e-5, 384)):
+    WORKLOADS[f'n200000_phi0.45_g{_g}'] = dict(N=200_000, phi=0.45, grid=_g, eps=_eps,
+                                               dt=1e-3, gmres_tol=1e-4, lanczos_tol=1e-3,
+                                               index=3)
 
 
 def box_length(N, phi, a=1.0):
