@@ -547,28 +547,30 @@ KrylovResult gmres(Handle &h, const Op &A, const double *b, size_t n, double *x,
   int check_from = (prev_iters && *prev_iters > 3) ? *prev_iters - 2 : 0;
   std::vector<double> hist(2 * (R + 1));
   while (total < maxit) {
-    // r = b - A x (x = 0 on the first cycle)
+    // r = b - A x; on the first cycle x = 0, so r = b and its norm is the
+    // |b| already on the device and the host
     double *r = V;
-    if (first) {
-      vcopy(h, r, b, n);
-    } else {
+    const double *beta_dev = bn;
+    double beta = bnorm;
+    if (!first) {
       A(x, r);
       vaxpby(h, 1.0, b, -1.0, r, n);
       check_from = 0;
+      norm2_dev(h, r, n, norm2);
+      hipLaunchKernelGGL(sqrt_kernel, dim3(1), dim3(1), 0, h.stream, norm2, vnorm);
+      PSE_LAUNCH_CHECK();
+      host_read(h, vnorm, &beta, 1);
+      beta_dev = vnorm;
     }
-    first = false;
-    norm2_dev(h, r, n, norm2);
-    hipLaunchKernelGGL(sqrt_kernel, dim3(1), dim3(1), 0, h.stream, norm2, vnorm);
-    PSE_LAUNCH_CHECK();
-    double beta;
-    host_read(h, vnorm, &beta, 1);
     rel = beta / bnorm;
     if (rel < tol) {
       res.converged = true;
       break;
     }
-    vscale_dev(h, r, r, vnorm, true, n);
-    hipLaunchKernelGGL(set_g0_kernel, dim3(1), dim3(1), 0, h.stream, g, R + 1, vnorm);
+    // v_0 = r / beta
+    vscale_dev(h, r, first ? b : r, beta_dev, true, n);
+    first = false;
+    hipLaunchKernelGGL(set_g0_kernel, dim3(1), dim3(1), 0, h.stream, g, R + 1, beta_dev);
     PSE_LAUNCH_CHECK();
     int k = 0;
     for (int j = 0; j < R && total < maxit; ++j) {
