@@ -105,7 +105,9 @@ typedef struct pse_params {
                               gradient's quadrature error is about ten times
                               the Gaussian's at equal support); falls back
                               to 1 when that support exceeds 10;
-                              0 = library default (2)                       */
+                              0 = library default: 2 while the stencil
+                              points per grid point N (P+1)^3 / Ng^3 stay
+                              at most 20, else 1                            */
   void *stream;            /* hipStream_t to run on, or NULL                 */
 } pse_params;
 

@@ -1067,6 +1067,9 @@ void interpolate(Handle &h, const double *x, const T *grids, const CompSet &cs, 
   else if (P3 <= 512)
     hipLaunchKernelGGL((interp_kernel<T, 8>), grid, block, 0, h.stream, x, grids, h.ngrid, cs, g,
                        order, h.n, out, lo, acc, scale);
+  else if (P3 <= 1024)
+    hipLaunchKernelGGL((interp_kernel<T, 16>), grid, block, 0, h.stream, x, grids, h.ngrid, cs,
+                       g, order, h.n, out, lo, acc, scale);
   else
     hipLaunchKernelGGL((interp_kernel<T, 0>), grid, block, 0, h.stream, x, grids, h.ngrid, cs, g,
                        order, h.n, out, lo, acc, scale);
