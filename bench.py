@@ -58,11 +58,12 @@ def run_form(w, precision, steps, warmup, seed, prof_steps=2, deriv_gridding=0):
     torch.cuda.synchronize()
     h.profile(0)
     prof = h.profile_read()
+    bracket = prof.pop('bracket', {'total_ms': 0.0})['total_ms']
     d = h.derived
     h.close()
     dt = t1 - t0
     return dict(value=N * steps / dt, ms_per_step=1e3 * dt / steps, prof=prof, stats=stats,
-                prof_steps=prof_steps,
+                prof_steps=prof_steps, bracket_us=1e3 * bracket,
                 derived=dict(grid=d.grid, support=d.support, xi=d.xi, rcut=d.rcut,
                              deriv_gridding=d.deriv_gridding,
                              eta_s=d.eta_s), finite=bool(torch.isfinite(x).all()))
@@ -103,11 +104,12 @@ STAGE_KERNELS = {
 }
 
 
-def roofline(prof, traffic_file=None, grid=128):
+def roofline(prof, traffic_file=None, grid=128, bracket_us=0.0):
     """The stage with the largest total time: algorithmic bytes per launch over
     the average event-timed launch duration, against the HBM peak; traffic is
     the HBM bytes per launch from the committed counter summary, if it was
-    taken on the current sources (else null)."""
+    taken on the current sources (else null).  The durations have the event
+    time of a bracket around an empty kernel (bracket_us) subtracted."""
     from paper_1709_06946_amd import profsum
     dom = max(prof, key=lambda k: prof[k]['total_ms'])
     p = prof[dom]
@@ -122,6 +124,7 @@ def roofline(prof, traffic_file=None, grid=128):
                                               else dom, dom),
                      stage=dom, launches=p['launches'],
                      avg_us=round(1e6 * per_launch_s, 2),
+                     event_bracket_us=round(bracket_us, 2),
                      alg_bytes_per_launch=round(per_launch_bytes))
 
 
@@ -270,12 +273,12 @@ def main():
     fp64 = run_form(w, pse.PSE_FP64, args.steps, args.warmup, seed,
                     deriv_gridding=args.deriv_gridding)
     traffic_file = os.path.join(ROOT, 'profiles', f'hbm_traffic_{args.workload}_fp64.md')
-    dom, roof = roofline(fp64['prof'], traffic_file, w['grid'])
+    dom, roof = roofline(fp64['prof'], traffic_file, w['grid'], fp64['bracket_us'])
     mixed = None
     if not args.no_mixed:
         m = run_form(w, pse.PSE_MIXED, args.steps, args.warmup, seed,
                      deriv_gridding=args.deriv_gridding)
-        mdom, mroof = roofline(m['prof'], None, w['grid'])
+        mdom, mroof = roofline(m['prof'], None, w['grid'], m['bracket_us'])
         mixed = dict(value=round(m['value'], 1), ms_per_step=round(m['ms_per_step'], 3),
                      speedup_vs_fp64=round(m['value'] / fp64['value'], 3), dtype='f32+f64',
                      roofline=mroof,

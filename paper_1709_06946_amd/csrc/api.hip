@@ -6,6 +6,7 @@
 //  sampler:  Eq. split; Lanczos for M_r^(1/2), Eq. FFTsqrt for M_w^(1/2).
 //  step:     the four-step mid-point scheme of Sec. III.D / Appendix B, with
 //            GMRES on the stresslet constraint (Eq. rigidconstraint).
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -360,12 +361,37 @@ static void stresslet_solve(Handle &h, const double *xh, const double *b, double
 static const char *kPkNames[PK_COUNT] = {"spread", "fft", "kspace", "interp", "zero",
                                           "real", "cells", "krylov", "noise", "misc"};
 
+__global__ void noop_kernel() {}
+
+// Median event time of a bracket around an empty one-thread kernel.
+static double bracket_overhead(Handle &h) {
+  constexpr int REPS = 16;
+  hipEvent_t a, b;
+  PSE_HIP(hipEventCreate(&a));
+  PSE_HIP(hipEventCreate(&b));
+  std::vector<double> t;
+  for (int i = 0; i < REPS; ++i) {
+    PSE_HIP(hipEventRecord(a, h.stream));
+    hipLaunchKernelGGL(noop_kernel, dim3(1), dim3(1), 0, h.stream);
+    PSE_LAUNCH_CHECK();
+    PSE_HIP(hipEventRecord(b, h.stream));
+    PSE_HIP(hipEventSynchronize(b));
+    float ms = 0.f;
+    PSE_HIP(hipEventElapsedTime(&ms, a, b));
+    t.push_back(ms);
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  std::sort(t.begin(), t.end());
+  return t[REPS / 2];
+}
+
 void prof_resolve(Handle &h) {
   Profiler &P = h.prof;
   for (const ProfRecord &r : P.pending) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, r.start, r.stop) == hipSuccess) {
-      P.ms[r.kind] += ms;
+      P.ms[r.kind] += std::max(0.0, (double)ms - P.bracket_ms);
       P.launches[r.kind] += 1;
       P.bytes[r.kind] += r.bytes;
     }
@@ -896,6 +922,8 @@ int pse_profile(pse_handle *hd, int enable) {
     }
     P.pending.clear();
     P.used = 0;
+    const int rc = guarded(hd, [&] { P.bracket_ms = bracket_overhead(hd->h); });
+    if (rc != PSE_OK) return rc;
   }
   P.on = enable != 0;
   return PSE_OK;
@@ -909,6 +937,7 @@ int pse_profile_read(pse_handle *hd, pse_kernel_stat *out, int max, int *count) 
     if (P.launches[k] == 0) continue;
     out[c++] = pse_kernel_stat{kPkNames[k], P.launches[k], P.ms[k], P.bytes[k]};
   }
+  if (c < max) out[c++] = pse_kernel_stat{"bracket", 1, P.bracket_ms, 0.0};
   *count = c;
   return PSE_OK;
 }
