@@ -59,11 +59,12 @@ def run_form(w, precision, steps, warmup, seed, prof_steps=2, deriv_gridding=0):
     h.profile(0)
     prof = h.profile_read()
     bracket = prof.pop('bracket', {'total_ms': 0.0})['total_ms']
+    noop = prof.pop('bracket_noop', {'total_ms': 0.0})['total_ms']
     d = h.derived
     h.close()
     dt = t1 - t0
     return dict(value=N * steps / dt, ms_per_step=1e3 * dt / steps, prof=prof, stats=stats,
-                prof_steps=prof_steps, bracket_us=1e3 * bracket,
+                prof_steps=prof_steps, bracket_us=(1e3 * bracket, 1e3 * noop),
                 derived=dict(grid=d.grid, support=d.support, xi=d.xi, rcut=d.rcut,
                              deriv_gridding=d.deriv_gridding,
                              eta_s=d.eta_s), finite=bool(torch.isfinite(x).all()))
@@ -104,12 +105,13 @@ STAGE_KERNELS = {
 }
 
 
-def roofline(prof, traffic_file=None, grid=128, bracket_us=0.0):
+def roofline(prof, traffic_file=None, grid=128, bracket_us=(0.0, 0.0)):
     """The stage with the largest total time: algorithmic bytes per launch over
     the average event-timed launch duration, against the HBM peak; traffic is
     the HBM bytes per launch from the committed counter summary, if it was
     taken on the current sources (else null).  The durations have the event
-    time of a bracket around an empty kernel (bracket_us) subtracted."""
+    time of an empty bracket (bracket_us[0]) subtracted; bracket_us[1], the
+    time of a bracket around an empty kernel, is reported beside it."""
     from paper_1709_06946_amd import profsum
     dom = max(prof, key=lambda k: prof[k]['total_ms'])
     p = prof[dom]
@@ -124,7 +126,8 @@ def roofline(prof, traffic_file=None, grid=128, bracket_us=0.0):
                                               else dom, dom),
                      stage=dom, launches=p['launches'],
                      avg_us=round(1e6 * per_launch_s, 2),
-                     event_bracket_us=round(bracket_us, 2),
+                     event_bracket_us=round(bracket_us[0], 2),
+                     event_noop_bracket_us=round(bracket_us[1], 2),
                      alg_bytes_per_launch=round(per_launch_bytes))
 
 

@@ -265,11 +265,13 @@ int pse_interpolate(pse_handle *h, const double *x, const double *grids,
  * duration accumulated per stage, together with the stage's algorithmic
  * bytes (the data a launch must read or write at least once: the grids it
  * reads and writes, plus particle data).  pse_profile(h, 1) clears the
- * totals, times a bracket around an empty one-thread kernel (the time the
- * events and a dispatch add; subtracted once from every bracket) and starts;
- * pse_profile(h, 0) stops.  Stage names: spread, fft, kspace, interp, zero,
- * real, cells, krylov, noise; a last record "bracket" holds the subtracted
- * bracket time (launches = 1). */
+ * totals, times an empty bracket (two event records back to back: the time
+ * the timestamps add, subtracted once from every bracket) and a bracket
+ * around an empty one-thread kernel, and starts; pse_profile(h, 0) stops.
+ * Stage names: spread, fft, kspace, interp, zero, real, cells, krylov,
+ * noise; two last records (launches = 1) hold the empty bracket time
+ * ("bracket", the subtracted one) and the empty-kernel bracket time
+ * ("bracket_noop"). */
 typedef struct pse_kernel_stat {
   const char *name;        /* static string owned by the library            */
   int64_t launches;

@@ -363,27 +363,32 @@ static const char *kPkNames[PK_COUNT] = {"spread", "fft", "kspace", "interp", "z
 
 __global__ void noop_kernel() {}
 
-// Median event time of a bracket around an empty one-thread kernel.
-static double bracket_overhead(Handle &h) {
+// Median event times of an empty bracket (two records back to back) and of
+// a bracket around an empty one-thread kernel.
+static void bracket_overhead(Handle &h, double &empty_ms, double &noop_ms) {
   constexpr int REPS = 16;
   hipEvent_t a, b;
   PSE_HIP(hipEventCreate(&a));
   PSE_HIP(hipEventCreate(&b));
-  std::vector<double> t;
-  for (int i = 0; i < REPS; ++i) {
+  std::vector<double> t[2];
+  for (int i = 0; i < 2 * REPS; ++i) {
+    const bool with_kernel = i & 1;
     PSE_HIP(hipEventRecord(a, h.stream));
-    hipLaunchKernelGGL(noop_kernel, dim3(1), dim3(1), 0, h.stream);
-    PSE_LAUNCH_CHECK();
+    if (with_kernel) {
+      hipLaunchKernelGGL(noop_kernel, dim3(1), dim3(1), 0, h.stream);
+      PSE_LAUNCH_CHECK();
+    }
     PSE_HIP(hipEventRecord(b, h.stream));
     PSE_HIP(hipEventSynchronize(b));
     float ms = 0.f;
     PSE_HIP(hipEventElapsedTime(&ms, a, b));
-    t.push_back(ms);
+    t[with_kernel].push_back(ms);
   }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
-  std::sort(t.begin(), t.end());
-  return t[REPS / 2];
+  for (auto &v : t) std::sort(v.begin(), v.end());
+  empty_ms = t[0][REPS / 2];
+  noop_ms = t[1][REPS / 2];
 }
 
 void prof_resolve(Handle &h) {
@@ -922,7 +927,7 @@ int pse_profile(pse_handle *hd, int enable) {
     }
     P.pending.clear();
     P.used = 0;
-    const int rc = guarded(hd, [&] { P.bracket_ms = bracket_overhead(hd->h); });
+    const int rc = guarded(hd, [&] { bracket_overhead(hd->h, P.bracket_ms, P.noop_ms); });
     if (rc != PSE_OK) return rc;
   }
   P.on = enable != 0;
@@ -938,6 +943,7 @@ int pse_profile_read(pse_handle *hd, pse_kernel_stat *out, int max, int *count) 
     out[c++] = pse_kernel_stat{kPkNames[k], P.launches[k], P.ms[k], P.bytes[k]};
   }
   if (c < max) out[c++] = pse_kernel_stat{"bracket", 1, P.bracket_ms, 0.0};
+  if (c < max) out[c++] = pse_kernel_stat{"bracket_noop", 1, P.noop_ms, 0.0};
   *count = c;
   return PSE_OK;
 }

@@ -107,11 +107,12 @@ struct Profiler {
   int64_t launches[PK_COUNT] = {};
   double ms[PK_COUNT] = {};
   double bytes[PK_COUNT] = {};
-  // event time of a bracket around an empty one-thread kernel (median of a
-  // few, taken when profiling starts): the timestamps and the dispatch
-  // latency a bracket adds to the kernels inside it; subtracted once per
-  // bracket
+  // event time of an empty bracket (two records back to back; median of a
+  // few, taken when profiling starts): the time the two timestamps add to
+  // the kernels between them, subtracted once per bracket
   double bracket_ms = 0.0;
+  // the same around an empty one-thread kernel (reported only)
+  double noop_ms = 0.0;
 };
 
 struct Handle {
