@@ -598,6 +598,21 @@ kspace_fused_kernel(const cplx<T> *__restrict__ in, CompSet cin, cplx<T> *__rest
   for (int e = 0; e < E; ++e)
 #pragma unroll
     for (int m = 0; m < 3; ++m) rho[e][m] = C{(T)0, (T)0};
+  // radial factors of this thread's modes, read from the table once for all
+  // components: j0 (x), f1 (y) and the projection's scale (z)
+  T tj0[E], tf1[E], tsc[E];
+#pragma unroll
+  for (int b = 0; b < E / RL; ++b)
+#pragma unroll
+    for (int r = 0; r < RL; ++r) {
+      const int e = b * RL + r;
+      const int iz = reg_pos<N, E, RL>(t, b, r);
+      const int kz = kidx(iz, N);
+      const auto tb = ktab[ix * ix + ky * ky + kz * kz];
+      tj0[e] = DG ? (T)0 : (T)tb.x;
+      tf1[e] = (T)tb.y;
+      tsc[e] = (T)tb.z;
+    }
   // the next component's z-line is loaded while the current one is
   // transformed (the barriers of the exchanges wait on LDS traffic only)
   C v[E], vn[E];
@@ -623,10 +638,8 @@ kspace_fused_kernel(const cplx<T> *__restrict__ in, CompSet cin, cplx<T> *__rest
       for (int r = 0; r < RL; ++r) {
         const int iz = reg_pos<N, E, RL>(t, b, r);
         if (zero_mode(ix, iy, iz, N)) continue;
-        const int kz = kidx(iz, N);
-        const auto tb = ktab[ix * ix + ky * ky + kz * kz];
         if constexpr (DG) {
-          const T f = (T)-3 * (T)tb.y;
+          const T f = (T)-3 * tf1[b * RL + r];
           const C vv = v[b * RL + r];
 #pragma unroll
           for (int m = 0; m < 3; ++m)
@@ -635,8 +648,8 @@ kspace_fused_kernel(const cplx<T> *__restrict__ in, CompSet cin, cplx<T> *__rest
               rho[b * RL + r][m].y += f * vv.y;
             }
         } else {
-          const T kv[3] = {tp * ix, tp * ky, tp * kz};
-          add_P<C, T>(c, v[b * RL + r], kv, tb.x, tb.y, rho[b * RL + r]);
+          const T kv[3] = {tp * ix, tp * ky, tp * kidx(iz, N)};
+          add_P<C, T>(c, v[b * RL + r], kv, tj0[b * RL + r], tf1[b * RL + r], rho[b * RL + r]);
         }
       }
   }
@@ -654,7 +667,7 @@ kspace_fused_kernel(const cplx<T> *__restrict__ in, CompSet cin, cplx<T> *__rest
         for (int m = 0; m < 3; ++m) rho[e][m] = C{(T)0, (T)0};
         continue;
       }
-      const T scale = ktab[n2].z;
+      const T scale = tsc[e];
       const T kv[3] = {(T)ix, (T)ky, (T)kz};
       const T inv = (T)1 / (T)n2;
       T krx = 0, kry = 0;
@@ -681,17 +694,15 @@ kspace_fused_kernel(const cplx<T> *__restrict__ in, CompSet cin, cplx<T> *__rest
           v[e] = C{(T)0, (T)0};
           continue;
         }
-        const int kz = kidx(iz, N);
-        const auto tb = ktab[ix * ix + ky * ky + kz * kz];
         if constexpr (DG) {
-          const T f = (T)3 * (T)tb.y;
+          const T f = (T)3 * tf1[e];
           v[e] = C{(T)0, (T)0};
 #pragma unroll
           for (int m = 0; m < 3; ++m)
             if (m == c) v[e] = C{f * rho[e][m].x, f * rho[e][m].y};
         } else {
-          const T kv[3] = {tp * ix, tp * ky, tp * kz};
-          v[e] = apply_Pdag<C, T>(c, rho[e], kv, tb.x, tb.y);
+          const T kv[3] = {tp * ix, tp * ky, tp * kidx(iz, N)};
+          v[e] = apply_Pdag<C, T>(c, rho[e], kv, tj0[e], tf1[e]);
         }
       }
     reg_fft_inverse<T, N, E>(v, t, lds, TL, line, tw);
