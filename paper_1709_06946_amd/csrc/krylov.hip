@@ -27,38 +27,38 @@ __global__ void axpby_kernel(double a, const double *x, double b, double *y, siz
   if (i < n) y[i] = a * x[i] + b * y[i];
 }
 
+// Sum over a 256-thread block: within each wave by shuffles, then the four
+// wave sums in a fixed order (valid in thread 0).
+__device__ __forceinline__ double block_sum256(double v, double *s4) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  if ((threadIdx.x & 63) == 0) s4[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return (s4[0] + s4[1]) + (s4[2] + s4[3]);
+}
+
 // partial[j * nb + blk] = sum over the block's share of V_j . w
 __global__ void __launch_bounds__(256)
 multi_dot_partial(const double *__restrict__ V, size_t ldv, const double *__restrict__ w,
                   size_t n, double *__restrict__ partial) {
-  __shared__ double s[256];
+  __shared__ double s[4];
   const int j = blockIdx.y;
   const double *v = V + (size_t)j * ldv;
   double acc = 0.0;
   for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
     acc += v[i] * w[i];
-  s[threadIdx.x] = acc;
-  __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
-    if (threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) partial[(size_t)j * gridDim.x + blockIdx.x] = s[0];
+  acc = block_sum256(acc, s);
+  if (threadIdx.x == 0) partial[(size_t)j * gridDim.x + blockIdx.x] = acc;
 }
 
 __global__ void __launch_bounds__(256)
 reduce_partial(const double *__restrict__ partial, int nb, double *__restrict__ out) {
-  __shared__ double s[256];
+  __shared__ double s[4];
   const int j = blockIdx.x;
   double acc = 0.0;
   for (int b = threadIdx.x; b < nb; b += 256) acc += partial[(size_t)j * nb + b];
-  s[threadIdx.x] = acc;
-  __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
-    if (threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) out[j] = s[0];
+  acc = block_sum256(acc, s);
+  if (threadIdx.x == 0) out[j] = acc;
 }
 
 // w -= sum_j coef_j V_j

@@ -264,6 +264,48 @@ __global__ void scan_add_kernel(int *__restrict__ out, const int *__restrict__ s
     if (i + j < n) out[i + j] += add;
 }
 
+// Exclusive scan of at most 1024 x SCAN1_PER ints in one workgroup: thread
+// t takes a contiguous chunk, the chunk totals are scanned within each wave
+// (shuffles) and across the 16 waves (LDS), and every thread then writes its
+// chunk's prefixes; out[n] = total.  One launch instead of three.
+constexpr int SCAN1_PER = 16;
+
+__global__ void __launch_bounds__(1024)
+scan_single_kernel(const int *__restrict__ in, int *__restrict__ out, int n) {
+  __shared__ int wsum[16];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int per = (n + 1023) / 1024;
+  const int lo = t * per, hi = min(lo + per, n);
+  int sum = 0;
+  for (int i = lo; i < hi; ++i) sum += in[i];
+  int incl = sum;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int u = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += u;
+  }
+  if (lane == 63) wsum[wv] = incl;
+  __syncthreads();
+  if (wv == 0) {
+    const int w = lane < 16 ? wsum[lane] : 0;
+    int wi = w;
+#pragma unroll
+    for (int off = 1; off < 16; off <<= 1) {
+      const int u = __shfl_up(wi, off, 64);
+      if (lane >= off) wi += u;
+    }
+    if (lane < 16) wsum[lane] = wi - w;
+  }
+  __syncthreads();
+  int run = wsum[wv] + incl - sum;
+  for (int i = lo; i < hi; ++i) {
+    const int x = in[i];
+    out[i] = run;
+    run += x;
+  }
+  if (t == 1023) out[n] = run;
+}
+
 __global__ void cell_scatter_kernel(const int *__restrict__ cell_of,
                                     const int *__restrict__ slot,
                                     const int *__restrict__ start, int64_t n,
@@ -296,6 +338,11 @@ cell_order_kernel(const int *__restrict__ start, const int *__restrict__ scat, i
 // out[0..n] = exclusive prefix sums of in[0..n) (out[n] = total); tmp holds
 // n/1024 + 8 ints.
 void exclusive_scan(Handle &h, const int *in, int *out, int *tmp, int n) {
+  if (n <= 1024 * SCAN1_PER) {
+    hipLaunchKernelGGL(scan_single_kernel, dim3(1), dim3(1024), 0, h.stream, in, out, n);
+    PSE_LAUNCH_CHECK();
+    return;
+  }
   const int sb = (n + 1023) / 1024;
   hipLaunchKernelGGL(scan_block_kernel, dim3(sb), dim3(256), 0, h.stream, in, out, tmp, n);
   PSE_LAUNCH_CHECK();
@@ -312,16 +359,7 @@ static void build_bins(Handle &h, const double *xw, Bins &b) {
   hipLaunchKernelGGL(cell_assign_kernel, dim3(nblocks(h.n, 256)), dim3(256), 0,
                      h.stream, xw, h.n, nc, nc / h.p.box, b.of, b.slot, b.count);
   PSE_LAUNCH_CHECK();
-  const int nb = (ncells + 1023) / 1024;
-  hipLaunchKernelGGL(scan_block_kernel, dim3(nb), dim3(256), 0, h.stream, b.count,
-                     b.start, b.scan_tmp, ncells);
-  PSE_LAUNCH_CHECK();
-  hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(256), 0, h.stream, b.scan_tmp, nb,
-                     b.start + ncells);
-  PSE_LAUNCH_CHECK();
-  hipLaunchKernelGGL(scan_add_kernel, dim3(nb), dim3(256), 0, h.stream, b.start,
-                     b.scan_tmp, ncells);
-  PSE_LAUNCH_CHECK();
+  exclusive_scan(h, b.count, b.start, b.scan_tmp, ncells);
   hipLaunchKernelGGL(cell_scatter_kernel, dim3(nblocks(h.n, 256)), dim3(256), 0,
                      h.stream, b.of, b.slot, b.start, h.n, b.scat);
   PSE_LAUNCH_CHECK();
