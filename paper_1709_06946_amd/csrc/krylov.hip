@@ -211,9 +211,14 @@ int check_finite(Handle &h, const double *v, size_t n) {
 
 // Eigen-decomposition of the symmetric tridiagonal matrix (diag d, off-diag
 // e) by the implicit QL iteration with Wilkinson-type shifts; z accumulates
-// the eigenvectors (column k belongs to eigenvalue d[k]).  m <= ldz.
+// the eigenvectors (column k belongs to eigenvalue d[k]).  m <= ldz.  Run by
+// one wavefront: every lane computes the scalar recurrences alike (each lane
+// reads back only its own writes of d and e, which are the same in all
+// lanes), and each plane rotation is applied to the rows of z in parallel,
+// row k by lane k mod 64 (a lane touches only its own rows).
 __device__ void tridiag_ql(double *d, double *e, double *z, int m, int ldz) {
-  for (int i = 0; i < m; ++i)
+  const int lane = threadIdx.x, nt = blockDim.x;
+  for (int i = lane; i < m; i += nt)
     for (int j = 0; j < m; ++j) z[i * ldz + j] = (i == j) ? 1.0 : 0.0;
   if (m == 1) return;
   e[m - 1] = 0.0;
@@ -246,10 +251,10 @@ __device__ void tridiag_ql(double *d, double *e, double *z, int m, int ldz) {
         p = s * r;
         d[i + 1] = g + p;
         g = c * r - b;
-        for (int k = 0; k < m; ++k) {
-          f = z[k * ldz + i + 1];
-          z[k * ldz + i + 1] = s * z[k * ldz + i] + c * f;
-          z[k * ldz + i] = c * z[k * ldz + i] - s * f;
+        for (int k = lane; k < m; k += nt) {
+          const double zf = z[k * ldz + i + 1];
+          z[k * ldz + i + 1] = s * z[k * ldz + i] + c * zf;
+          z[k * ldz + i] = c * z[k * ldz + i] - s * zf;
         }
       }
       if (r == 0.0 && i >= l) continue;
@@ -262,37 +267,48 @@ __device__ void tridiag_ql(double *d, double *e, double *z, int m, int ldz) {
 
 // coef = bnorm * f(T) e_1 with f = sqrt, T = tridiag(alpha, beta) of size m;
 // also the relative change against the previous coefficient vector
-// (zero-padded), written to out_change.
-__global__ void lanczos_sqrt_kernel(const double *alpha, const double *beta, int m,
-                                    double bnorm, double *work, int ldz, double *coef,
-                                    double *coef_prev, double *out_change,
-                                    double *chg_hist) {
-  // the eigenproblem runs on one thread; its arrays live in LDS when they fit
-  // (dynamic shared memory sized by the host), else in the global work area
+// (zero-padded), written to out_change.  One wavefront (64 threads): inputs
+// loaded in parallel, the eigenproblem by tridiag_ql, coefficient i by lane
+// i mod 64, the change summed in index order by lane 0.
+__global__ void __launch_bounds__(64)
+lanczos_sqrt_kernel(const double *alpha, const double *beta, int m, double bnorm,
+                    double *work, int ldz, double *coef, double *coef_prev,
+                    double *out_change, double *chg_hist) {
+  // LDS: the new and previous coefficients (2m), then d, e and z when they
+  // fit (ldz == m; the host sizes the dynamic shared memory), else those
+  // live in the global work area
   extern __shared__ double lds_work[];
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  const bool in_lds = ldz == m;
-  double *base = in_lds ? lds_work : work;
+  if (blockIdx.x != 0) return;
+  const int lane = threadIdx.x, nt = blockDim.x;
+  double *cbuf = lds_work, *pbuf = lds_work + m;
+  double *base = ldz == m ? lds_work + 2 * m : work;
   double *d = base, *e = base + ldz, *z = base + 2 * ldz;
-  for (int i = 0; i < m; ++i) {
+  for (int i = lane; i < m; i += nt) {
     d[i] = alpha[i];
     e[i] = i + 1 < m ? beta[i] : 0.0;
+    pbuf[i] = i < m - 1 ? coef_prev[i] : 0.0;
   }
+  __syncthreads();
   tridiag_ql(d, e, z, m, ldz);
-  double num = 0.0, den = 0.0;
-  for (int i = 0; i < m; ++i) {
+  __syncthreads();
+  for (int i = lane; i < m; i += nt) {
     double acc = 0.0;
     for (int k = 0; k < m; ++k) {
       const double lam = d[k] > 0.0 ? sqrt(d[k]) : 0.0;
       acc += z[i * ldz + k] * lam * z[0 * ldz + k];
     }
-    const double c = bnorm * acc;
-    const double prev = i < m - 1 ? coef_prev[i] : 0.0;
+    cbuf[i] = bnorm * acc;
+    coef[i] = cbuf[i];
+  }
+  __syncthreads();
+  if (lane != 0) return;
+  double num = 0.0, den = 0.0;
+  for (int i = 0; i < m; ++i) {
+    const double c = cbuf[i], prev = pbuf[i];
     num += (c - prev) * (c - prev);
     den += c * c;
-    coef[i] = c;
+    coef_prev[i] = c;
   }
-  for (int i = 0; i < m; ++i) coef_prev[i] = coef[i];
   out_change[0] = den > 0.0 ? sqrt(num / den) : 0.0;
   chg_hist[m - 1] = out_change[0];
 }
@@ -460,10 +476,12 @@ KrylovResult lanczos_sqrt(Handle &h, const Op &A, const double *b, size_t n, dou
   PSE_HIP(hipMemsetAsync(chg_hist, 0, (M + 1) * sizeof(double), h.stream));
   vscale_dev(h, V, b, bn, true, n);
   auto sqrt_coef = [&](int mm) {
-    // LDS holds d, e and the mm^2 eigenvectors when they fit in 48 KiB
-    const size_t lds = (size_t)(2 * mm + mm * mm) * sizeof(double);
+    // LDS holds the two coefficient vectors, and d, e and the mm^2
+    // eigenvectors when they fit in 48 KiB
+    const size_t coefs = (size_t)2 * mm * sizeof(double);
+    const size_t lds = coefs + (size_t)(2 * mm + mm * mm) * sizeof(double);
     const bool fits = lds <= 49152;
-    hipLaunchKernelGGL(lanczos_sqrt_kernel, dim3(1), dim3(64), fits ? lds : 0, h.stream, alpha,
+    hipLaunchKernelGGL(lanczos_sqrt_kernel, dim3(1), dim3(64), fits ? lds : coefs, h.stream, alpha,
                        beta, mm, bnorm, work, fits ? mm : ldz, coef, coef_prev, change,
                        chg_hist);
     PSE_LAUNCH_CHECK();
