@@ -323,41 +323,58 @@ __global__ void backsub_kernel(const double *H, int ldh, int k, const double *g,
   }
 }
 
-// Hessenberg column j entries 0..j from h1 + h2 (two Gram-Schmidt passes),
-// entry j+1 = sqrt(norm2).  Also sets g[0] = beta when j == 0 is requested.
 // GMRES column j from the two Gram-Schmidt passes: H[i][j] = h1[i] + h2[i]
 // (i <= j); h2[j+1] holds w.w after the first pass, so the norm of the
 // twice-orthogonalised w is sqrt(w.w - |h2|^2) (V orthonormal).  Then the
 // previous Givens rotations are applied to the column, the new one is
 // formed and g updated; vnorm = H[j+1][j], resid = |g_{j+1}|.
-__global__ void hess_givens_kernel(double *H, int ldh, int j, const double *h1,
-                                   const double *h2, double *cs, double *sn, double *g,
-                                   double *vnorm, double *resid, double *vn_hist,
-                                   double *res_hist) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  double *col = H + (size_t)j * ldh;
+// One wavefront: the column, its squared norm and the previous rotations
+// are loaded in parallel into LDS (3j + 2 doubles, sized by the host), then
+// lane 0 applies the rotations.
+__global__ void __launch_bounds__(64)
+hess_givens_kernel(double *__restrict__ H, int ldh, int j, const double *__restrict__ h1,
+                   const double *__restrict__ h2, double *__restrict__ cs,
+                   double *__restrict__ sn, double *__restrict__ g, double *__restrict__ vnorm,
+                   double *__restrict__ resid, double *__restrict__ vn_hist,
+                   double *__restrict__ res_hist) {
+  extern __shared__ double sm[];
+  if (blockIdx.x != 0) return;
+  double *cl = sm, *cs_l = sm + (j + 2), *sn_l = cs_l + j;
+  const int lane = threadIdx.x, nt = blockDim.x;
   double p2 = 0.0;
-  for (int i = 0; i <= j; ++i) {
-    col[i] = h1[i] + h2[i];
-    p2 += h2[i] * h2[i];
+  for (int i = lane; i <= j; i += nt) {
+    const double b2 = h2[i];
+    cl[i] = h1[i] + b2;
+    p2 += b2 * b2;
   }
+  for (int i = lane; i < j; i += nt) {
+    cs_l[i] = cs[i];
+    sn_l[i] = sn[i];
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) p2 += __shfl_xor(p2, off, 64);
+  __syncthreads();
+  if (lane != 0) return;
+  double *col = H + (size_t)j * ldh;
   const double nn = sqrt(fmax(h2[j + 1] - p2, 0.0));
-  col[j + 1] = nn;
+  cl[j + 1] = nn;
   vnorm[0] = nn;
   for (int i = 0; i < j; ++i) {
-    const double t = cs[i] * col[i] + sn[i] * col[i + 1];
-    col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
-    col[i] = t;
+    const double t = cs_l[i] * cl[i] + sn_l[i] * cl[i + 1];
+    cl[i + 1] = -sn_l[i] * cl[i] + cs_l[i] * cl[i + 1];
+    cl[i] = t;
   }
-  const double a = col[j], b = col[j + 1];
+  const double a = cl[j], b = cl[j + 1];
   const double r = hypot(a, b);
   const double c = r > 0 ? a / r : 1.0, s = r > 0 ? b / r : 0.0;
   cs[j] = c;
   sn[j] = s;
+  for (int i = 0; i < j; ++i) col[i] = cl[i];
   col[j] = r;
   col[j + 1] = 0.0;
-  g[j + 1] = -s * g[j];
-  g[j] = c * g[j];
+  const double gj = g[j];
+  g[j + 1] = -s * gj;
+  g[j] = c * gj;
   resid[0] = fabs(g[j + 1]);
   vn_hist[j] = nn;
   res_hist[j] = resid[0];
@@ -595,7 +612,8 @@ KrylovResult gmres(Handle &h, const Op &A, const double *b, size_t n, double *x,
       double *w = V + (size_t)(j + 1) * n;
       A(V + (size_t)j * n, w);
       cgs2_pass(h, V, n, j + 1, w, h1, h2);
-      hipLaunchKernelGGL(hess_givens_kernel, dim3(1), dim3(1), 0, h.stream, H, ldh, j, h1, h2,
+      hipLaunchKernelGGL(hess_givens_kernel, dim3(1), dim3(64),
+                         (size_t)(3 * j + 2) * sizeof(double), h.stream, H, ldh, j, h1, h2,
                          cs, sn, g, vnorm, resid, vn_hist, res_hist);
       PSE_LAUNCH_CHECK();
       sub_scale(h, w, V, n, j + 1, h2, vnorm);
