@@ -417,14 +417,15 @@ static void host_read(Handle &h, const double *dev, double *host, int n) {
     if (!std::isfinite(host[i])) throw Error{PSE_ERR_NONFINITE, "non-finite Krylov scalar"};
 }
 
-// Reads n values from each of two device arrays with one synchronisation.
-static void host_read2(Handle &h, const double *a, double *ha, const double *b, double *hb,
-                       int n) {
-  PSE_HIP(hipMemcpyAsync(ha, a, n * sizeof(double), hipMemcpyDeviceToHost, h.stream));
-  PSE_HIP(hipMemcpyAsync(hb, b, n * sizeof(double), hipMemcpyDeviceToHost, h.stream));
+// Reads the first n values of two device histories that lie stride doubles
+// apart (a and a + stride) into ha and ha + stride, with one copy and one
+// synchronisation.
+static void host_read2(Handle &h, const double *a, double *ha, int stride, int n) {
+  PSE_HIP(hipMemcpyAsync(ha, a, (size_t)(stride + n) * sizeof(double), hipMemcpyDeviceToHost,
+                         h.stream));
   PSE_HIP(hipStreamSynchronize(h.stream));
   for (int i = 0; i < n; ++i)
-    if (!std::isfinite(ha[i]) || !std::isfinite(hb[i]))
+    if (!std::isfinite(ha[i]) || !std::isfinite(ha[stride + i]))
       throw Error{PSE_ERR_NONFINITE, "non-finite Krylov scalar"};
 }
 
@@ -520,7 +521,7 @@ KrylovResult lanczos_sqrt(Handle &h, const Op &A, const double *b, size_t n, dou
     m = j + 1;
     res.iters = m;
     if (m < check_from && m < M) continue;
-    host_read2(h, vn_hist, hist.data(), chg_hist, hist.data() + (M + 1), j + 1);
+    host_read2(h, vn_hist, hist.data(), M + 1, j + 1);  // vn_hist, then chg_hist
     const double *vh = hist.data(), *ch = vh + (M + 1);
     int brk = -1;
     for (int i = 0; i <= j; ++i)
@@ -620,7 +621,7 @@ KrylovResult gmres(Handle &h, const Op &A, const double *b, size_t n, double *x,
       ++total;
       k = j + 1;
       if (k < check_from && j + 1 < R && total < maxit) continue;
-      host_read2(h, vn_hist, hist.data(), res_hist, hist.data() + (R + 1), j + 1);
+      host_read2(h, vn_hist, hist.data(), R + 1, j + 1);  // vn_hist, then res_hist
       const double *vh = hist.data(), *rh = vh + (R + 1);
       // first column at which the residual met tol or the space was exhausted;
       // later columns (and Givens entries) are not used by the update
