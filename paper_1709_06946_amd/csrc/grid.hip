@@ -339,6 +339,37 @@ spread_deriv_kernel(const double *__restrict__ q, Layout lq, CompSet cs, GridGeo
 
 // --------------------------------------------------------- interpolation --
 
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)b, l);
+  const long long hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double((hi << 32) | lo);
+}
+
+// Support 8 (512 stencil points, 8 per lane): lane l covers the points
+// (a, b) = (l % 8, l / 8) at every z index c, its point it being c = it.
+// The Gaussian factorises, so a lane takes one exponential for its x-y
+// factor and one for the z factor of c = l % 8; the z factor of point it is
+// read from lane it.  Fills the grid offsets and exp(-kcoef |d|^2) of the
+// lane's eight points, and their offsets d along z (x and y are dx, dy).
+__device__ __forceinline__ void stencil8(int lane, double px, double py, double pz, int ix0,
+                                         int iy0, int iz0, const GridGeom &g, size_t gi[8],
+                                         double e[8], double dz[8], double &dx, double &dy) {
+  const int a = lane & 7, b = lane >> 3;
+  dx = (ix0 + a) * g.h - px;
+  dy = (iy0 + b) * g.h - py;
+  const double exy = exp(-g.kcoef * (dx * dx + dy * dy));
+  const double dzl = (iz0 + a) * g.h - pz;
+  const double ezl = exp(-g.kcoef * dzl * dzl);
+  const size_t gxy = (size_t)wrapi(iy0 + b, g.ng) * g.ng + wrapi(ix0 + a, g.ng);
+#pragma unroll
+  for (int it = 0; it < 8; ++it) {
+    dz[it] = (iz0 + it) * g.h - pz;
+    e[it] = exy * readlane_d(ezl, it);
+    gi[it] = (size_t)wrapi(iz0 + it, g.ng) * g.ng * g.ng + gxy;
+  }
+}
+
 // One wavefront per particle (particles in cell order, each XCD taking a
 // contiguous range of them so that neighbouring stencils share its L2);
 // lane s covers stencil points s, s + 64, ...
@@ -368,18 +399,30 @@ interp_kernel(const double *__restrict__ x, const T *__restrict__ grids,
   if constexpr (MAXIT > 0) {
     size_t gi[MAXIT];
     T w[MAXIT];
+    bool done = false;
+    if constexpr (MAXIT == 8) {
+      if (P == 8) {
+        double e[8], dz[8], dx, dy;
+        stencil8(lane, px, py, pz, ix0, iy0, iz0, g, gi, e, dz, dx, dy);
 #pragma unroll
-    for (int it = 0; it < MAXIT; ++it) {
-      const int s = lane + 64 * it;
-      const int a = s % P, b = (s / P) % P, c = s / (P * P);
-      const double dx = (ix0 + a) * g.h - px;
-      const double dy = (iy0 + b) * g.h - py;
-      const double dz = (iz0 + c) * g.h - pz;
-      const bool in = s < P3;
-      w[it] = in ? (T)(kn3 * exp(-g.kcoef * (dx * dx + dy * dy + dz * dz))) : (T)0;
-      gi[it] = in ? ((size_t)wrapi(iz0 + c, g.ng) * g.ng + wrapi(iy0 + b, g.ng)) * g.ng
-                        + wrapi(ix0 + a, g.ng)
-                  : 0;
+        for (int it = 0; it < 8; ++it) w[it] = (T)(kn3 * e[it]);
+        done = true;
+      }
+    }
+    if (!done) {
+#pragma unroll
+      for (int it = 0; it < MAXIT; ++it) {
+        const int s = lane + 64 * it;
+        const int a = s % P, b = (s / P) % P, c = s / (P * P);
+        const double dx = (ix0 + a) * g.h - px;
+        const double dy = (iy0 + b) * g.h - py;
+        const double dz = (iz0 + c) * g.h - pz;
+        const bool in = s < P3;
+        w[it] = in ? (T)(kn3 * exp(-g.kcoef * (dx * dx + dy * dy + dz * dz))) : (T)0;
+        gi[it] = in ? ((size_t)wrapi(iz0 + c, g.ng) * g.ng + wrapi(iy0 + b, g.ng)) * g.ng
+                          + wrapi(ix0 + a, g.ng)
+                    : 0;
+      }
     }
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
@@ -971,22 +1014,39 @@ interp_deriv_kernel(const double *__restrict__ x, const T *__restrict__ grids, s
   for (int k = 0; k < 6; ++k) acc[k] = (T)0;
   size_t gi[MAXIT];
   T gw[MAXIT][3];
+  bool done = false;
+  if constexpr (MAXIT == 8) {
+    if (P == 8) {
+      double e[8], dz[8], dx, dy;
+      stencil8(lane, px, py, pz, ix0, iy0, iz0, g, gi, e, dz, dx, dy);
 #pragma unroll
-  for (int it = 0; it < MAXIT; ++it) {
-    const int s = lane + 64 * it;
-    const int a = s % P, b = (s / P) % P, c = s / (P * P);
-    const double dx = (ix0 + a) * g.h - px;
-    const double dy = (iy0 + b) * g.h - py;
-    const double dz = (iz0 + c) * g.h - pz;
-    const bool in = s < P3;
-    const double f = in ? -2.0 * g.kcoef * kn3 * exp(-g.kcoef * (dx * dx + dy * dy + dz * dz))
-                        : 0.0;
-    gw[it][0] = (T)(f * dx);
-    gw[it][1] = (T)(f * dy);
-    gw[it][2] = (T)(f * dz);
-    gi[it] = in ? ((size_t)wrapi(iz0 + c, g.ng) * g.ng + wrapi(iy0 + b, g.ng)) * g.ng
-                      + wrapi(ix0 + a, g.ng)
-                : 0;
+      for (int it = 0; it < 8; ++it) {
+        const double f = -2.0 * g.kcoef * kn3 * e[it];
+        gw[it][0] = (T)(f * dx);
+        gw[it][1] = (T)(f * dy);
+        gw[it][2] = (T)(f * dz[it]);
+      }
+      done = true;
+    }
+  }
+  if (!done) {
+#pragma unroll
+    for (int it = 0; it < MAXIT; ++it) {
+      const int s = lane + 64 * it;
+      const int a = s % P, b = (s / P) % P, c = s / (P * P);
+      const double dx = (ix0 + a) * g.h - px;
+      const double dy = (iy0 + b) * g.h - py;
+      const double dz = (iz0 + c) * g.h - pz;
+      const bool in = s < P3;
+      const double f = in ? -2.0 * g.kcoef * kn3 * exp(-g.kcoef * (dx * dx + dy * dy + dz * dz))
+                          : 0.0;
+      gw[it][0] = (T)(f * dx);
+      gw[it][1] = (T)(f * dy);
+      gw[it][2] = (T)(f * dz);
+      gi[it] = in ? ((size_t)wrapi(iz0 + c, g.ng) * g.ng + wrapi(iy0 + b, g.ng)) * g.ng
+                        + wrapi(ix0 + a, g.ng)
+                  : 0;
+    }
   }
   T v[3][MAXIT];
 #pragma unroll
