@@ -346,6 +346,23 @@ __device__ __forceinline__ double readlane_d(double v, int l) {
   return __longlong_as_double((hi << 32) | lo);
 }
 
+// Any support: lane l holds the one-dimensional factors exp(-kcoef d^2) at
+// offset l along x, y and z (meaningful for l < P); stencil point (a, b, c)
+// takes the product of the three, fetched from lanes a, b and c.  Every lane
+// of the wavefront must call it and the shuffles (all lanes active).
+__device__ __forceinline__ void factors1d(int lane, double px, double py, double pz, int ix0,
+                                          int iy0, int iz0, const GridGeom &g, double f[3]) {
+  const double dx = (ix0 + lane) * g.h - px, dy = (iy0 + lane) * g.h - py;
+  const double dz = (iz0 + lane) * g.h - pz;
+  f[0] = exp(-g.kcoef * dx * dx);
+  f[1] = exp(-g.kcoef * dy * dy);
+  f[2] = exp(-g.kcoef * dz * dz);
+}
+
+__device__ __forceinline__ double gauss_at(const double f[3], int a, int b, int c) {
+  return __shfl(f[0], a & 63, 64) * __shfl(f[1], b & 63, 64) * __shfl(f[2], c & 63, 64);
+}
+
 // Support 8 (512 stencil points, 8 per lane): lane l covers the points
 // (a, b) = (l % 8, l / 8) at every z index c, its point it being c = it.
 // The Gaussian factorises, so a lane takes one exponential for its x-y
@@ -410,15 +427,15 @@ interp_kernel(const double *__restrict__ x, const T *__restrict__ grids,
       }
     }
     if (!done) {
+      double f[3];
+      factors1d(lane, px, py, pz, ix0, iy0, iz0, g, f);
 #pragma unroll
       for (int it = 0; it < MAXIT; ++it) {
         const int s = lane + 64 * it;
         const int a = s % P, b = (s / P) % P, c = s / (P * P);
-        const double dx = (ix0 + a) * g.h - px;
-        const double dy = (iy0 + b) * g.h - py;
-        const double dz = (iz0 + c) * g.h - pz;
         const bool in = s < P3;
-        w[it] = in ? (T)(kn3 * exp(-g.kcoef * (dx * dx + dy * dy + dz * dz))) : (T)0;
+        const double e = gauss_at(f, a, b, c);
+        w[it] = in ? (T)(kn3 * e) : (T)0;
         gi[it] = in ? ((size_t)wrapi(iz0 + c, g.ng) * g.ng + wrapi(iy0 + b, g.ng)) * g.ng
                           + wrapi(ix0 + a, g.ng)
                     : 0;
@@ -1030,6 +1047,8 @@ interp_deriv_kernel(const double *__restrict__ x, const T *__restrict__ grids, s
     }
   }
   if (!done) {
+    double f1[3];
+    factors1d(lane, px, py, pz, ix0, iy0, iz0, g, f1);
 #pragma unroll
     for (int it = 0; it < MAXIT; ++it) {
       const int s = lane + 64 * it;
@@ -1038,8 +1057,8 @@ interp_deriv_kernel(const double *__restrict__ x, const T *__restrict__ grids, s
       const double dy = (iy0 + b) * g.h - py;
       const double dz = (iz0 + c) * g.h - pz;
       const bool in = s < P3;
-      const double f = in ? -2.0 * g.kcoef * kn3 * exp(-g.kcoef * (dx * dx + dy * dy + dz * dz))
-                          : 0.0;
+      const double e = gauss_at(f1, a, b, c);
+      const double f = in ? -2.0 * g.kcoef * kn3 * e : 0.0;
       gw[it][0] = (T)(f * dx);
       gw[it][1] = (T)(f * dy);
       gw[it][2] = (T)(f * dz);
