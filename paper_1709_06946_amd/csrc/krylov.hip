@@ -11,6 +11,7 @@
 namespace pse {
 
 constexpr int RED_BLOCKS = 1024;   // partial-sum blocks of a reduction
+constexpr int MAX_DOTS = 128;      // dot products of one fused subtraction pass
 
 __global__ void zero_kernel_d(double *v, size_t n) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -59,6 +60,37 @@ reduce_partial(const double *__restrict__ partial, int nb, double *__restrict__ 
   for (int b = threadIdx.x; b < nb; b += 256) acc += partial[(size_t)j * nb + b];
   acc = block_sum256(acc, s);
   if (threadIdx.x == 0) out[j] = acc;
+}
+
+// The second Gram-Schmidt pass's subtraction fused with the dot products
+// that follow it: w -= sum_{j<m} coef_j V_j, then partial[j nb + blk] =
+// V_j . w for j <= m over the block's share (V_m is w itself, so the last
+// entry is w . w).  Each thread updates and then reads back only its own
+// elements, in the grid-stride order of multi_dot_partial, so the sums are
+// those of a separate subtraction and multi_dot_partial bit for bit.
+__global__ void __launch_bounds__(256)
+sub_dot_partial(double *w, const double *V, size_t ldv, int m, const double *__restrict__ coef,
+                size_t n, double *__restrict__ partial) {
+  __shared__ double s[4][MAX_DOTS];
+  const int nb = gridDim.x, lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const size_t i0 = (size_t)blockIdx.x * 256 + threadIdx.x, step = (size_t)nb * 256;
+  for (size_t i = i0; i < n; i += step) {
+    double acc = 0.0;
+    for (int j = 0; j < m; ++j) acc += coef[j] * V[(size_t)j * ldv + i];
+    w[i] -= acc;
+  }
+#pragma unroll 4
+  for (int j = 0; j <= m; ++j) {
+    const double *v = V + (size_t)j * ldv;
+    double acc = 0.0;
+    for (size_t i = i0; i < n; i += step) acc += v[i] * w[i];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (lane == 0) s[wv][j] = acc;
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j <= m; j += 256)
+    partial[(size_t)j * nb + blockIdx.x] = (s[0][j] + s[1][j]) + (s[2][j] + s[3][j]);
 }
 
 // w -= sum_j coef_j V_j
@@ -440,8 +472,21 @@ static void norm2_dev(Handle &h, const double *v, size_t n, double *dev_norm2) {
 static void cgs2_pass(Handle &h, const double *V, size_t n, int m, double *w, double *h1,
                       double *h2) {
   multi_dot(h, V, n, m, w, n, h1);
-  vsub_multi(h, w, V, n, m, h1, n);
-  multi_dot(h, V, n, m + 1, w, n, h2);
+  if (m + 1 > MAX_DOTS || w != V + (size_t)m * n) {
+    vsub_multi(h, w, V, n, m, h1, n);
+    multi_dot(h, V, n, m + 1, w, n, h2);
+    return;
+  }
+  // w = V_m: the subtraction and the second pass's dot products in one launch
+  int nb = (int)std::min<size_t>(RED_BLOCKS, (n + 255) / 256);
+  if (nb < 1) nb = 1;
+  if ((size_t)nb * (m + 1) > h.dots_len) throw Error{PSE_ERR_INVALID, "reduction scratch too small"};
+  ProfScope ps(h, PK_KRYLOV, (double)(2 * m + 3) * n * 8);
+  hipLaunchKernelGGL(sub_dot_partial, dim3(nb), dim3(256), 0, h.stream, w, V, n, m, h1, n,
+                     h.dots);
+  PSE_LAUNCH_CHECK();
+  hipLaunchKernelGGL(reduce_partial, dim3(m + 1), dim3(256), 0, h.stream, h.dots, nb, h2);
+  PSE_LAUNCH_CHECK();
 }
 
 static void sub_scale(Handle &h, double *w, const double *V, size_t n, int m,
