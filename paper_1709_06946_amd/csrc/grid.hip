@@ -658,21 +658,35 @@ kspace_fused_kernel(const cplx<T> *__restrict__ in, CompSet cin, cplx<T> *__rest
   for (int e = 0; e < E; ++e)
 #pragma unroll
     for (int m = 0; m < 3; ++m) rho[e][m] = C{(T)0, (T)0};
-  // radial factors of this thread's modes, read from the table once for all
-  // components: j0 (x), f1 (y) and the projection's scale (z)
-  T tj0[E], tf1[E], tsc[E];
+  // radial factors of this thread's modes: j0 (x), f1 (y) and the
+  // projection's scale (z).  With four modes per thread they are read from
+  // the table once for all components; with six the registers they would
+  // hold cost more than the repeated (cached) table reads.
+  constexpr bool HOIST = E <= 4;
+  const auto entry = [&](int e) {
+    const int iz = reg_pos<N, E, RL>(t, e / RL, e % RL);
+    const int kz = kidx(iz, N);
+    return ktab[ix * ix + ky * ky + kz * kz];
+  };
+  T tj0[HOIST ? E : 1], tf1[HOIST ? E : 1], tsc[HOIST ? E : 1];
+  if constexpr (HOIST) {
 #pragma unroll
-  for (int b = 0; b < E / RL; ++b)
-#pragma unroll
-    for (int r = 0; r < RL; ++r) {
-      const int e = b * RL + r;
-      const int iz = reg_pos<N, E, RL>(t, b, r);
-      const int kz = kidx(iz, N);
-      const auto tb = ktab[ix * ix + ky * ky + kz * kz];
+    for (int e = 0; e < E; ++e) {
+      const auto tb = entry(e);
       tj0[e] = DG ? (T)0 : (T)tb.x;
       tf1[e] = (T)tb.y;
       tsc[e] = (T)tb.z;
     }
+  }
+  const auto j0_at = [&](int e) -> T {
+    if constexpr (HOIST) return tj0[e]; else return (T)entry(e).x;
+  };
+  const auto f1_at = [&](int e) -> T {
+    if constexpr (HOIST) return tf1[e]; else return (T)entry(e).y;
+  };
+  const auto sc_at = [&](int e) -> T {
+    if constexpr (HOIST) return tsc[e]; else return (T)entry(e).z;
+  };
   // the next component's z-line is loaded while the current one is
   // transformed (the barriers of the exchanges wait on LDS traffic only)
   C v[E], vn[E];
@@ -699,7 +713,7 @@ kspace_fused_kernel(const cplx<T> *__restrict__ in, CompSet cin, cplx<T> *__rest
         const int iz = reg_pos<N, E, RL>(t, b, r);
         if (zero_mode(ix, iy, iz, N)) continue;
         if constexpr (DG) {
-          const T f = (T)-3 * tf1[b * RL + r];
+          const T f = (T)-3 * f1_at(b * RL + r);
           const C vv = v[b * RL + r];
 #pragma unroll
           for (int m = 0; m < 3; ++m)
@@ -709,7 +723,7 @@ kspace_fused_kernel(const cplx<T> *__restrict__ in, CompSet cin, cplx<T> *__rest
             }
         } else {
           const T kv[3] = {tp * ix, tp * ky, tp * kidx(iz, N)};
-          add_P<C, T>(c, v[b * RL + r], kv, tj0[b * RL + r], tf1[b * RL + r], rho[b * RL + r]);
+          add_P<C, T>(c, v[b * RL + r], kv, j0_at(b * RL + r), f1_at(b * RL + r), rho[b * RL + r]);
         }
       }
   }
@@ -727,7 +741,7 @@ kspace_fused_kernel(const cplx<T> *__restrict__ in, CompSet cin, cplx<T> *__rest
         for (int m = 0; m < 3; ++m) rho[e][m] = C{(T)0, (T)0};
         continue;
       }
-      const T scale = tsc[e];
+      const T scale = sc_at(e);
       const T kv[3] = {(T)ix, (T)ky, (T)kz};
       const T inv = (T)1 / (T)n2;
       T krx = 0, kry = 0;
@@ -755,14 +769,14 @@ kspace_fused_kernel(const cplx<T> *__restrict__ in, CompSet cin, cplx<T> *__rest
           continue;
         }
         if constexpr (DG) {
-          const T f = (T)3 * tf1[e];
+          const T f = (T)3 * f1_at(e);
           v[e] = C{(T)0, (T)0};
 #pragma unroll
           for (int m = 0; m < 3; ++m)
             if (m == c) v[e] = C{f * rho[e][m].x, f * rho[e][m].y};
         } else {
           const T kv[3] = {tp * ix, tp * ky, tp * kidx(iz, N)};
-          v[e] = apply_Pdag<C, T>(c, rho[e], kv, tj0[e], tf1[e]);
+          v[e] = apply_Pdag<C, T>(c, rho[e], kv, j0_at(e), f1_at(e));
         }
       }
     reg_fft_inverse<T, N, E>(v, t, lds, TL, line, tw);
