@@ -318,13 +318,17 @@ spread_deriv_kernel(const double *__restrict__ q, Layout lq, CompSet cs, GridGeo
       const T *wj = wg + j * 6 * S, *gj = wj + 3 * S, *sj = st6 + j * 6;
       const T gxwy = gj[lx] * wj[S + ly], wxgy = wj[lx] * gj[S + ly], wxwy = wj[lx] * wj[S + ly];
       const T sxx = sj[0], syy = sj[1], szz = sj[2], sxy = sj[3], sxz = sj[4], syz = sj[5];
+      // D_i = (S_ix g_x w_y + S_iy w_x g_y) w_z + S_iz w_x w_y g_z: the two
+      // brackets are constant along the thread's z-column
+      const T ax = sxx * gxwy + sxy * wxgy, ay = sxy * gxwy + syy * wxgy;
+      const T az = sxz * gxwy + syz * wxgy;
+      const T bx = sxz * wxwy, by = syz * wxwy, bz = szz * wxwy;
 #pragma unroll
       for (int z = 0; z < ZPT; ++z) {
         const T wz = wj[2 * S + z0 + z], gz = gj[2 * S + z0 + z];
-        const T a = gxwy * wz, b = wxgy * wz, c = wxwy * gz;
-        acc[z][0] += sxx * a + sxy * b + sxz * c;
-        acc[z][1] += sxy * a + syy * b + syz * c;
-        acc[z][2] += sxz * a + syz * b + szz * c;
+        acc[z][0] += ax * wz + bx * gz;
+        acc[z][1] += ay * wz + by * gz;
+        acc[z][2] += az * wz + bz * gz;
       }
     }
   }
