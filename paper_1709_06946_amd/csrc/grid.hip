@@ -1047,24 +1047,45 @@ interp_deriv_kernel(const double *__restrict__ x, const T *__restrict__ grids, s
   T acc[6];
 #pragma unroll
   for (int k = 0; k < 6; ++k) acc[k] = (T)0;
-  size_t gi[MAXIT];
-  T gw[MAXIT][3];
   bool done = false;
   if constexpr (MAXIT == 8) {
     if (P == 8) {
+      // the lane's points share x and y: with dK/dx_i = c d_i e (c = -2
+      // kcoef knorm^3, e the Gaussian), the column sums s_k = sum v_k e and
+      // z_k = sum v_k e dz give every T_ij
+      size_t gi[8];
       double e[8], dz[8], dx, dy;
       stencil8(lane, px, py, pz, ix0, iy0, iz0, g, gi, e, dz, dx, dy);
+      T v[3][8];
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int it = 0; it < 8; ++it) v[k][it] = grids[(size_t)k * ngrid + gi[it]];
+      T sk[3] = {(T)0, (T)0, (T)0}, zk[3] = {(T)0, (T)0, (T)0};
 #pragma unroll
       for (int it = 0; it < 8; ++it) {
-        const double f = -2.0 * g.kcoef * kn3 * e[it];
-        gw[it][0] = (T)(f * dx);
-        gw[it][1] = (T)(f * dy);
-        gw[it][2] = (T)(f * dz[it]);
+        const T et = (T)e[it], dzt = (T)dz[it];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          const T ve = v[k][it] * et;
+          sk[k] += ve;
+          zk[k] += ve * dzt;
+        }
       }
+      const double c = -2.0 * g.kcoef * kn3;
+      const T c0 = (T)c, cx = (T)(c * dx), cy = (T)(c * dy);
+      acc[0] = cx * sk[0];
+      acc[1] = cy * sk[1];
+      acc[2] = c0 * zk[2];
+      acc[3] = cy * sk[0] + cx * sk[1];
+      acc[4] = c0 * zk[0] + cx * sk[2];
+      acc[5] = c0 * zk[1] + cy * sk[2];
       done = true;
     }
   }
   if (!done) {
+    size_t gi[MAXIT];
+    T gw[MAXIT][3];
     double f1[3];
     factors1d(lane, px, py, pz, ix0, iy0, iz0, g, f1);
 #pragma unroll
@@ -1084,20 +1105,20 @@ interp_deriv_kernel(const double *__restrict__ x, const T *__restrict__ grids, s
                         + wrapi(ix0 + a, g.ng)
                   : 0;
     }
-  }
-  T v[3][MAXIT];
+    T v[3][MAXIT];
 #pragma unroll
-  for (int k = 0; k < 3; ++k)
+    for (int k = 0; k < 3; ++k)
 #pragma unroll
-    for (int it = 0; it < MAXIT; ++it) v[k][it] = grids[(size_t)k * ngrid + gi[it]];
+      for (int it = 0; it < MAXIT; ++it) v[k][it] = grids[(size_t)k * ngrid + gi[it]];
 #pragma unroll
-  for (int it = 0; it < MAXIT; ++it) {
-    acc[0] += v[0][it] * gw[it][0];
-    acc[1] += v[1][it] * gw[it][1];
-    acc[2] += v[2][it] * gw[it][2];
-    acc[3] += v[0][it] * gw[it][1] + v[1][it] * gw[it][0];
-    acc[4] += v[0][it] * gw[it][2] + v[2][it] * gw[it][0];
-    acc[5] += v[1][it] * gw[it][2] + v[2][it] * gw[it][1];
+    for (int it = 0; it < MAXIT; ++it) {
+      acc[0] += v[0][it] * gw[it][0];
+      acc[1] += v[1][it] * gw[it][1];
+      acc[2] += v[2][it] * gw[it][2];
+      acc[3] += v[0][it] * gw[it][1] + v[1][it] * gw[it][0];
+      acc[4] += v[0][it] * gw[it][2] + v[2][it] * gw[it][0];
+      acc[5] += v[1][it] * gw[it][2] + v[2][it] * gw[it][1];
+    }
   }
 #pragma unroll
   for (int k = 0; k < 6; ++k) {
