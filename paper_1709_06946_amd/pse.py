@@ -189,15 +189,20 @@ def footprint_bytes(params):
     return b.value
 
 
-def _ptr(t, shape=None, name='tensor'):
-    """Raw device pointer of a contiguous float64 CUDA/HIP tensor (or None)."""
+def _ptr(t, shape=None, name='tensor', dtype='float64'):
+    """Raw device pointer of a contiguous device tensor of the given dtype
+    ('float64' or 'complex128'), or None.  The kernels read the memory with
+    that element type, so any other dtype is refused."""
     if t is None:
         return None
     import torch
-    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f'{name} must be a torch tensor')
+    want = getattr(torch, dtype)
+    if t.dtype != want:
+        raise TypeError(f'{name} must be {dtype}, got {t.dtype}')
+    if not t.is_cuda:
         raise TypeError(f'{name} must be a device tensor')
-    if t.dtype not in (torch.float64, torch.complex128):
-        raise TypeError(f'{name} must be float64 or complex128')
     if not t.is_contiguous():
         raise ValueError(f'{name} must be contiguous')
     if shape is not None and tuple(t.shape) != tuple(shape):
@@ -257,7 +262,7 @@ class PSE:
         st = pse_stats()
         rc = self._check(lib().pse_brownian_sample(
             self._h, _ptr(x, (n, 3), 'x'), _ptr(psi_real, (n, 11), 'psi_real'),
-            _ptr(psi_wave, (3, g, g, g // 2 + 1), 'psi_wave'), seed, counter,
+            _ptr(psi_wave, (3, g, g, g // 2 + 1), 'psi_wave', 'complex128'), seed, counter,
             _ptr(out_real, (n, 11), 'out_real'), _ptr(out_wave, (n, 11), 'out_wave'),
             ctypes.byref(st)), 'pse_brownian_sample')
         return rc, st.as_dict()
@@ -267,7 +272,7 @@ class PSE:
         n, g = self.n, self.derived.grid
         _sync()
         io = pse_step_io(_ptr(psi_real, (n, 11), 'psi_real'),
-                         _ptr(psi_wave, (3, g, g, g // 2 + 1), 'psi_wave'),
+                         _ptr(psi_wave, (3, g, g, g // 2 + 1), 'psi_wave', 'complex128'),
                          _ptr(slip, (n, 11), 'slip'), _ptr(stresslet, (n, 5), 'stresslet'),
                          _ptr(velocity, (n, 3), 'velocity'))
         st = pse_stats()
@@ -290,7 +295,7 @@ class PSE:
         n, g = self.n, self.derived.grid
         _sync()
         io = pse_step_io(_ptr(psi_real, (n, 3), 'psi_real'),
-                         _ptr(psi_wave, (3, g, g, g // 2 + 1), 'psi_wave'),
+                         _ptr(psi_wave, (3, g, g, g // 2 + 1), 'psi_wave', 'complex128'),
                          _ptr(slip, (n, 3), 'slip'), None, _ptr(velocity, (n, 3), 'velocity'))
         st = pse_stats()
         rc = self._check(lib().pse_rpy_step(
@@ -314,7 +319,7 @@ class PSE:
         g = self.derived.grid
         _sync()
         nc = data.shape[0]
-        return self._check(lib().pse_fft3d(self._h, _ptr(data, (nc, g, g, g), 'data'), nc,
+        return self._check(lib().pse_fft3d(self._h, _ptr(data, (nc, g, g, g), 'data', 'complex128'), nc,
                                            direction), 'pse_fft3d')
 
     def spread(self, x, q, grids):

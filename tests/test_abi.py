@@ -185,3 +185,22 @@ def test_server_error_without_server_is_empty(pse):
     unknown request (no device needed)."""
     lib = pse.load_library()
     assert lib.pse_server_error(None, 1) == b''
+
+
+def test_binding_refuses_wrong_element_types(pse):
+    """The kernels read each argument with one element type: float64 particle
+    arrays, complex128 wave noise and FFT data.  Any other dtype is refused
+    before a pointer is formed (a float64 wave noise of the complex shape
+    would be read past its end)."""
+    import torch
+    g = 8
+    with pytest.raises(TypeError, match='complex128'):
+        pse._ptr(torch.zeros((3, g, g, g // 2 + 1), dtype=torch.float64), (3, g, g, g // 2 + 1),
+                 'psi_wave', 'complex128')
+    with pytest.raises(TypeError, match='float64'):
+        pse._ptr(torch.zeros((4, 3), dtype=torch.float32), (4, 3), 'x')
+    with pytest.raises(TypeError, match='float64'):
+        pse._ptr(torch.zeros((4, 11), dtype=torch.complex128), (4, 11), 'in')
+    # the right dtype on the host is still refused: device memory only
+    with pytest.raises(TypeError, match='device'):
+        pse._ptr(torch.zeros((4, 3), dtype=torch.float64), (4, 3), 'x')
