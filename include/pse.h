@@ -247,6 +247,17 @@ int pse_rpy_step(pse_handle *h, double *x, const double *F, double dt, uint64_t 
  * sum f exp(-i k.x); +1: sum f exp(+i k.x).  1 <= ncomp <= 6. */
 int pse_fft3d(pse_handle *h, double *data, int ncomp, int direction);
 
+/* In-place real 3D FFT of ncomp grids with the transforms the mobility
+ * product and the wave sampler run (Eq. WSops2), in the handle's precision
+ * (mixed handles convert to float and back).  data holds ncomp blocks of
+ * Ng^3 doubles.  direction -1: each block is a real grid g[z][y][x] (x
+ * fastest) and is overwritten by its half spectrum
+ * G[kz][ky][kx] = sum g exp(-i k.x) for kx < Ng/2, complex (re, im)
+ * interleaved, the kx = Ng/2 column not stored; direction +1: the inverse,
+ * g = sum_k G exp(+i k.x) (unnormalized) over the stored half spectrum and
+ * its conjugates, the kx = Ng/2 column taken as zero.  1 <= ncomp <= 11. */
+int pse_rfft3d(pse_handle *h, double *data, int ncomp, int direction);
+
 /* Gaussian spreading of ncomp components of q (double[N][ncomp]) onto
  * ncomp real grids out[ncomp][Ng][Ng][Ng]: out_c(x_n) = sum_b K(x_n - x_b)
  * q_bc with K(r) = (2 xi^2 / (pi eta_s))^(3/2) exp(-2 xi^2 r^2 / eta_s)

@@ -35,27 +35,35 @@ def principal_sqrt_apply(M, v):
     return Q @ (np.sqrt(lam) * (Q.T @ v))
 
 
-def grid_half_space(Ng):
+def grid_half_space(Ng, nmax=None):
     """Canonical half-space wave numbers of an Ng^3 grid, Nyquist excluded.
 
-    Returns (kappa (K, 3) ints as (kx, ky, kz), array indices (K, 3) as
-    (iz, iy, ix))."""
+    nmax: if given, only wave numbers with |kappa| <= nmax (an optional
+    truncation: the caller knows the terms beyond carry no weight or no
+    noise).  Returns (kappa (K, 3) ints as (kx, ky, kz), array indices
+    (K, 3) as (iz, iy, ix))."""
     h = Ng // 2
-    g = np.arange(-h + 1, h)
+    lim = h - 1 if nmax is None else min(h - 1, int(np.floor(nmax)))
+    g = np.arange(-lim, lim + 1)
     kx, ky, kz = np.meshgrid(g, g, g, indexing='ij')
     kap = np.stack([kx.ravel(), ky.ravel(), kz.ravel()], -1)
     keep = ((kap[:, 0] > 0) | ((kap[:, 0] == 0) & (kap[:, 1] > 0))
             | ((kap[:, 0] == 0) & (kap[:, 1] == 0) & (kap[:, 2] > 0)))
+    if nmax is not None:
+        keep &= (kap**2).sum(1) <= nmax * nmax
     kap = kap[keep]
     idx = np.stack([kap[:, 2] % Ng, kap[:, 1] % Ng, kap[:, 0]], -1)
     return kap, idx
 
 
-def wave_sample(x, psi, L, Ng, xi, a=1.0, eta=1.0, chunk=4096):
-    """M_w^(1/2) psi over the Ng^3 grid's wave vectors; returns (N, 11)."""
+def wave_sample(x, psi, L, Ng, xi, a=1.0, eta=1.0, chunk=4096, kmax=None):
+    """M_w^(1/2) psi over the Ng^3 grid's wave vectors; returns (N, 11).
+
+    kmax: optional truncation of the sum to |k| <= kmax (for large grids:
+    beyond kmax = 2 xi sqrt(50) the amplitude sqrt(H) is below e^-25)."""
     x = np.asarray(x, np.float64)
     V = L**3
-    kap, idx = grid_half_space(Ng)
+    kap, idx = grid_half_space(Ng, None if kmax is None else kmax * L / (2 * np.pi))
     kvec = 2 * np.pi / L * kap
     ps = psi[:, idx[:, 0], idx[:, 1], idx[:, 2]].T           # (K, 3)
     out = np.zeros((x.shape[0], 11))

@@ -867,6 +867,30 @@ int pse_fft3d(pse_handle *hd, double *data, int ncomp, int direction) {
   });
 }
 
+int pse_rfft3d(pse_handle *hd, double *data, int ncomp, int direction) {
+  if (!hd) return PSE_ERR_INVALID;
+  if (!data || ncomp < 1 || ncomp > NC || (direction != 1 && direction != -1)) {
+    hd->h.err = "pse_rfft3d: bad arguments";
+    return PSE_ERR_INVALID;
+  }
+  return guarded(hd, [&] {
+    Handle &h = hd->h;
+    const size_t cnt = (size_t)ncomp * h.ngrid;   // reals = 2 x the half-spectrum complex
+    if (h.mixed) {
+      float *g = reinterpret_cast<float *>(h.g32.gin);
+      from_double<float>(h, data, cnt, g);
+      rfft3d<float>(h, g, h.g32.twiddle, ncomp, direction);
+      to_double<float>(h, g, cnt, data);
+    } else {
+      double *g = reinterpret_cast<double *>(h.g64.gin);
+      from_double<double>(h, data, cnt, g);
+      rfft3d<double>(h, g, h.g64.twiddle, ncomp, direction);
+      to_double<double>(h, g, cnt, data);
+    }
+    PSE_HIP(hipStreamSynchronize(h.stream));
+  });
+}
+
 int pse_spread(pse_handle *hd, const double *x, const double *q, int ncomp, double *out) {
   if (!hd) return PSE_ERR_INVALID;
   if (!x || !q || !out || ncomp < 1 || ncomp > NC) {

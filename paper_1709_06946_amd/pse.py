@@ -93,7 +93,8 @@ class pse_server_info(ctypes.Structure):
 
 EXPORTS = ('pse_derive', 'pse_footprint_bytes', 'pse_create', 'pse_destroy',
            'pse_get_derived', 'pse_mobility_apply', 'pse_brownian_sample',
-           'pse_constrained_step', 'pse_rpy_apply', 'pse_rpy_step', 'pse_fft3d', 'pse_spread', 'pse_interpolate',
+           'pse_constrained_step', 'pse_rpy_apply', 'pse_rpy_step', 'pse_fft3d', 'pse_rfft3d',
+           'pse_spread', 'pse_interpolate',
            'pse_profile', 'pse_profile_read', 'pse_server_create', 'pse_server_submit',
            'pse_server_wait', 'pse_server_result', 'pse_server_release', 'pse_server_stats',
            'pse_server_destroy', 'pse_server_error', 'pse_last_error')
@@ -127,6 +128,7 @@ def load_library(path=LIB_PATH):
     lib.pse_rpy_step.argtypes = [V, V, V, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64,
                                  P(pse_step_io), P(pse_stats)]
     lib.pse_fft3d.argtypes = [V, V, I, I]
+    lib.pse_rfft3d.argtypes = [V, V, I, I]
     lib.pse_spread.argtypes = [V, V, V, I, V]
     lib.pse_interpolate.argtypes = [V, V, V, I, V]
     lib.pse_profile.argtypes = [V, I]
@@ -321,6 +323,15 @@ class PSE:
         nc = data.shape[0]
         return self._check(lib().pse_fft3d(self._h, _ptr(data, (nc, g, g, g), 'data', 'complex128'), nc,
                                            direction), 'pse_fft3d')
+
+    def rfft3d(self, data, direction):
+        """In place: real grids (nc, g, g, g) float64 <-> half spectra stored in
+        the same memory (view as complex (nc, g, g, g // 2))."""
+        g = self.derived.grid
+        _sync()
+        nc = data.shape[0]
+        return self._check(lib().pse_rfft3d(self._h, _ptr(data, (nc, g, g, g), 'data'), nc,
+                                            direction), 'pse_rfft3d')
 
     def spread(self, x, q, grids):
         n, g = self.n, self.derived.grid

@@ -111,3 +111,34 @@ def test_spread_handles_positions_outside_box():
     shift = L * np.random.default_rng(2).integers(-3, 4, size=(100, 3))
     h.spread(dev(x + shift), dev(q), g2)
     assert np.abs(host(g1) - host(g2)).max() < 1e-12 * np.abs(host(g1)).max()
+
+
+@pytest.mark.parametrize('precision', [0, 1])
+@pytest.mark.parametrize('grid', [32, 96, 128, 192, 256, 384])
+@pytest.mark.parametrize('direction', [-1, 1])
+def test_rfft3d_matches_numpy(grid, direction, precision):
+    """The real transforms of the product and the sampler (plane kernel up to
+    128, x pass + line passes above; half spectra with the kx = Ng/2 column
+    not stored) against numpy's rfftn / irfftn."""
+    import torch
+    nc = 2
+    h = _handle(16, 5.0 * grid / 8, grid, precision=precision)
+    rng = np.random.default_rng(grid + 7 * (direction > 0))
+    a = rng.normal(size=(nc, grid, grid, grid))
+    spec = np.fft.rfftn(a, axes=(1, 2, 3))
+    spec[..., grid // 2] = 0.0
+    if direction < 0:
+        src = a
+        ref = spec[..., :grid // 2]
+    else:
+        src = np.ascontiguousarray(spec[..., :grid // 2]).view(np.float64)
+        ref = np.fft.irfftn(spec, s=(grid, grid, grid), axes=(1, 2, 3)) * grid**3
+    t = dev(np.ascontiguousarray(src).reshape(nc, grid, grid, grid))
+    h.rfft3d(t, direction)
+    out = host(t)
+    if direction < 0:
+        out = out.view(np.complex128).reshape(nc, grid, grid, grid // 2)
+    err = np.abs(out - ref).max() / np.abs(ref).max()
+    print(grid, direction, precision, err)
+    assert err < (1e-12 if precision == 0 else 5e-6), err
+    h.close()

@@ -441,3 +441,25 @@ def test_rpy_real_sampler_is_principal_root_of_real_uf_block():
     assert np.allclose(R, R.T, atol=1e-12)
     assert np.linalg.eigvalsh(R).min() > -1e-12
     assert np.allclose(R @ R, Mr, atol=1e-12 * np.abs(Mr).max())
+
+
+def test_wave_sampler_truncation_drops_only_negligible_modes():
+    """The optional |k| <= kmax truncation of the wave sampler (used on large
+    grids) equals the sum over every grid mode once kmax covers the grid, and
+    differs by no more than the weight of the dropped modes otherwise."""
+    L, Ng, xi = 6.0, 32, 0.9
+    x = np.array([[1.0, 2.0, 3.0], [2.5, 2.0, 3.5], [5.0, 0.2, 1.1]])
+    rng = np.random.default_rng(12)
+    psi = (rng.normal(size=(3, Ng, Ng, Ng // 2 + 1))
+           + 1j * rng.normal(size=(3, Ng, Ng, Ng // 2 + 1))) * np.sqrt(0.5)
+    full = brownian.wave_sample(x, psi, L, Ng, xi)
+    cover = brownian.wave_sample(x, psi, L, Ng, xi, kmax=2 * np.pi / L * Ng)
+    assert np.abs(cover - full).max() <= 1e-14 * np.abs(full).max()
+    kap_all, _ = brownian.grid_half_space(Ng)
+    kap_cut, _ = brownian.grid_half_space(Ng, 5.0)
+    assert len(kap_cut) < len(kap_all)
+    assert set(map(tuple, kap_cut)) <= set(map(tuple, kap_all))
+    kmax = 2 * xi * np.sqrt(50.0)
+    assert kmax < 2 * np.pi / L * (Ng // 2 - 1)       # the cut drops modes
+    cut = brownian.wave_sample(x, psi, L, Ng, xi, kmax=kmax)
+    assert np.abs(cut - full).max() <= 1e-9 * np.abs(full).max()
