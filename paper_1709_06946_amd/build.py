@@ -1,7 +1,8 @@
 """Build libpse.so (HIP, gfx950) in-tree with hipcc.
 
 Usage: python -m paper_1709_06946_amd.build   (or build() from Python).
-Every call recompiles all sources.
+Every call recompiles all sources, and the host packing generator of the
+synthetic inputs (libpack.so, plain C).
 """
 import concurrent.futures
 import os
@@ -12,6 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, 'csrc')
 BUILD = os.path.join(HERE, '_build')
 LIB = os.path.join(HERE, 'libpse.so')
+PACK_SRC = os.path.join(HERE, 'packing.c')
+PACK_LIB = os.path.join(HERE, 'libpack.so')
 HIPCC = os.environ.get('HIPCC', '/opt/rocm/bin/hipcc')
 ARCH = 'gfx950'
 
@@ -36,7 +39,19 @@ def _compile(src):
     return obj, r.stderr
 
 
+def build_packing():
+    """The host-only packing generator of the synthetic inputs (plain C)."""
+    tmp = PACK_LIB + f'.tmp{os.getpid()}'
+    cmd = ['gcc', '-O2', '-std=c99', '-fPIC', '-shared', '-Wall', '-o', tmp, PACK_SRC, '-lm']
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f'compile failed: packing.c\n{r.stdout}\n{r.stderr}')
+    os.replace(tmp, PACK_LIB)
+    return PACK_LIB
+
+
 def build(verbose=False):
+    build_packing()
     os.makedirs(BUILD, exist_ok=True)
     jobs = min(len(SOURCES), int(os.environ.get('MAX_JOBS', os.cpu_count() or 4)))
     with concurrent.futures.ThreadPoolExecutor(max_workers=jobs) as ex:

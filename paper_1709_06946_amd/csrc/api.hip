@@ -460,8 +460,9 @@ static void create(const pse_params &p, Handle &h) {
   }
   const size_t n = (size_t)h.n;
   const int ng = h.d.grid;
-  alloc((void **)&h.g64.gin, MAX_PACK * h.ngrid * sizeof(double2));
-  alloc((void **)&h.g64.gout, MAX_PACK * h.ngrid * sizeof(double2));
+  const size_t packs64 = h.mixed ? MIXED_FP64_PACK : MAX_PACK;
+  alloc((void **)&h.g64.gin, packs64 * h.ngrid * sizeof(double2));
+  alloc((void **)&h.g64.gout, packs64 * h.ngrid * sizeof(double2));
   alloc((void **)&h.g64.twiddle, ng * sizeof(double2));
   hipLaunchKernelGGL(twiddle_kernel64, dim3(nblocks(ng, 256)), dim3(256), 0, h.stream,
                      h.g64.twiddle, ng);

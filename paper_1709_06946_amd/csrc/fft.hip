@@ -318,7 +318,7 @@ fft_xy_plane_kernel(T *__restrict__ data, const cplx<T> *__restrict__ tw, int np
 // (t, line) = (tid / TL, tid % TL), so every global access of a wavefront
 // covers TL consecutive x addresses.
 template <typename T, int N>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(512)
 fft_lines_kernel(cplx<T> *__restrict__ data, const cplx<T> *__restrict__ tw, int M, int axis,
                  int dir, int TL) {
   using C = cplx<T>;
@@ -327,7 +327,10 @@ fft_lines_kernel(cplx<T> *__restrict__ data, const cplx<T> *__restrict__ tw, int
   extern __shared__ unsigned char smem_raw[];
   C *lds = reinterpret_cast<C *>(smem_raw);
   const int tiles = M / TL;
-  const size_t xt = blockIdx.x % tiles, rest = blockIdx.x / tiles;
+  // neighbouring x tiles share cache lines when a row segment is shorter
+  // than a line: they run on one XCD (one L2)
+  const size_t lb = xcd_block(blockIdx.x, gridDim.x);
+  const size_t xt = lb % tiles, rest = lb / tiles;
   const size_t c = rest / N, o = rest % N;
   const size_t plane = (size_t)N * M, vol = plane * N;
   const int line = threadIdx.x % TL, t = threadIdx.x / TL;
@@ -412,7 +415,8 @@ template <typename T, int N>
 void launch_lines(Handle &h, cplx<T> *data, const cplx<T> *tw, int ncomp, int M, int axis,
                   int dir) {
   constexpr int TPL = N / line_e(N);
-  const int tl = lines_per_block(N, TPL, N * sizeof(cplx<T>), (size_t)M);
+  // up to 512 threads: 16 lines of 512 points in FP32 (128-byte row segments)
+  const int tl = lines_per_block(N, TPL, N * sizeof(cplx<T>), (size_t)M, 512);
   const size_t lds = (size_t)tl * N * sizeof(cplx<T>);
   const unsigned nb = (unsigned)((size_t)ncomp * N * (M / tl));
   hipLaunchKernelGGL((fft_lines_kernel<T, N>), dim3(nb), dim3(tl * TPL), lds, h.stream, data,

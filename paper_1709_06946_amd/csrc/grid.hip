@@ -650,7 +650,12 @@ kspace_fused_kernel(const cplx<T> *__restrict__ in, CompSet cin, cplx<T> *__rest
   extern __shared__ unsigned char smem_raw[];
   C *lds = reinterpret_cast<C *>(smem_raw);
   const int tiles = M / TL;
-  const int xt = blockIdx.x % tiles, iy = blockIdx.x / tiles;
+  // neighbouring x tiles share the cache lines of their row segments (TL
+  // complex numbers, 32 or 64 bytes at long lines): they run on one XCD, so
+  // its L2 fetches each line once (at 512^3 in FP32 the HBM reads were five
+  // times the data with tiles spread over the XCDs)
+  const int lb = (int)xcd_block(blockIdx.x, gridDim.x);
+  const int xt = lb % tiles, iy = lb / tiles;
   const int line = threadIdx.x % TL, t = threadIdx.x / TL;
   const int ix = xt * TL + line;
   const int ky = kidx(iy, N);

@@ -117,11 +117,13 @@ size_t footprint(const pse_params &p, const pse_derived &d) {
   const size_t n = (size_t)p.n;
   const size_t ncell3 = (size_t)d.cells * d.cells * d.cells;
   size_t bytes = 0;
-  // FP64 grids are always present (the FP64 path, and the refinement of the
-  // mixed path); FP32 grids only for mixed handles.
-  bytes += 2 * MAX_PACK * ng3 * sizeof(double2) + d.grid * sizeof(double2);
-  if (p.precision == PSE_MIXED)
-    bytes += 2 * MAX_PACK * ng3 * sizeof(float2) + d.grid * sizeof(float2);
+  // FP64 grids are always present (the FP64 path; in mixed handles only the
+  // five-component sets of the FP64 residual of the constraint solve); FP32
+  // grids only for mixed handles.
+  const bool mixed = p.precision == PSE_MIXED;
+  bytes += 2 * (size_t)(mixed ? MIXED_FP64_PACK : MAX_PACK) * ng3 * sizeof(double2)
+           + d.grid * sizeof(double2);
+  if (mixed) bytes += 2 * MAX_PACK * ng3 * sizeof(float2) + d.grid * sizeof(float2);
   bytes += (size_t)(3 * (d.grid / 2) * (d.grid / 2) + 1) * 4 * sizeof(double);
   bytes += pair_capacity(p, d) * (sizeof(int) + 10 * sizeof(double))
            + (2 * n + n / 1024 + 16) * sizeof(int);

@@ -17,6 +17,9 @@ namespace pse {
 
 constexpr int NC = 11;           // generalized force/velocity components
 constexpr int MAX_PACK = 6;      // packed complex grids (two real grids each)
+// FP64 packed grids per set of a mixed handle: its FP64 work is the
+// residual of the constraint solve, M_ES on five components at most
+constexpr int MIXED_FP64_PACK = 3;
 constexpr int NCOEF = 7;         // real-space coefficient functions
 
 // Error carrying a status code; converted at the ABI boundary.

@@ -6,31 +6,37 @@ inputs from here, so the two sides always see identical arrays.
 
 The packings stand in for the random hard-sphere suspensions the paper
 measures on (Sec. IV, phi = 0.1 - 0.5): non-overlapping spheres of radius a
-placed uniformly at random in a periodic cube by random sequential addition
-(candidates drawn in batches; a candidate is rejected if it overlaps a placed
-sphere or an earlier candidate of its batch).
+placed uniformly at random in a periodic cube.  Below CPACK_N spheres, random
+sequential addition in numpy (candidates drawn in batches; a candidate is
+rejected if it overlaps a placed sphere or an earlier candidate of its batch)
+for phi <= 0.2, overlap relaxation of uniform centres above.  From CPACK_N
+on, the compiled generator (packing.c): random sequential addition for
+phi <= 0.3; above, sequential addition at the reduced radius that gives
+phi = 0.3, compression to the target fraction and hard-sphere Monte Carlo
+sweeps.
 """
 import numpy as np
 
 SEED_BASE = 1709069460
 
-# Workloads: sphere count, volume fraction, grid, tolerance, time step.
+# Workloads: sphere count, volume fraction, grid, tolerance, time step and
+# the precision form they are run in (0 FP64, 1 mixed).
 WORKLOADS = {
     'n100_phi0.1_g32': dict(N=100, phi=0.1, grid=32, eps=1e-3, dt=1e-3,
-                            gmres_tol=1e-6, lanczos_tol=1e-3, index=0),
+                            gmres_tol=1e-6, lanczos_tol=1e-3, index=0, precision=0),
     'n100_phi0.01_g32': dict(N=100, phi=0.01, grid=32, eps=1e-3, dt=1e-3,
-                             gmres_tol=1e-6, lanczos_tol=1e-3, index=0),
+                             gmres_tol=1e-6, lanczos_tol=1e-3, index=0, precision=0),
     'n10000_phi0.3_g128': dict(N=10_000, phi=0.3, grid=128, eps=1e-3, dt=1e-3,
-                               gmres_tol=1e-6, lanczos_tol=1e-3, index=1),
+                               gmres_tol=1e-6, lanczos_tol=1e-3, index=1, precision=0),
     'n1000000_phi0.1_g512': dict(N=1_000_000, phi=0.1, grid=512, eps=1e-3,
                                  dt=1e-3, gmres_tol=1e-4, lanczos_tol=1e-3,
-                                 index=2),
+                                 index=2, precision=1),
 }
 # the dense suspension over its tolerance sweep (eps, grid)
 for _eps, _g in ((1e-2, 128), (1e-3, 192), (1e-4, 256), (1e-5, 384)):
     WORKLOADS[f'n200000_phi0.45_g{_g}'] = dict(N=200_000, phi=0.45, grid=_g, eps=_eps,
                                                dt=1e-3, gmres_tol=1e-4, lanczos_tol=1e-3,
-                                               index=3)
+                                               index=3, precision=1)
 
 
 def box_length(N, phi, a=1.0):
@@ -155,34 +161,55 @@ def relaxed_packing(N, phi, a=1.0, seed=SEED_BASE, margin=1e-3,
     raise RuntimeError('overlap relaxation did not converge')
 
 
-LATTICE_N = 200_000   # from this size on, packings are jittered lattices
+# From this size on, packings come from the compiled generator (packing.c):
+# random sequential addition up to phi = 0.3, and above it sequential
+# addition at the radius that gives phi = 0.3 followed by compression (radius
+# set to a, overlapping pairs pushed apart until none is left).
+CPACK_N = 2000
+RSA_PHI_MAX = 0.3
+
+_pack_lib = None
 
 
-def jittered_lattice(N, phi, a=1.0, seed=SEED_BASE):
-    """Non-overlapping spheres for very large N: N distinct random sites of
-    the m^3 cubic lattice (m = ceil(N^(1/3))) of the box, each displaced
-    uniformly by at most half the gap (spacing - 2a) per axis, so that no
-    two spheres overlap; the volume fraction is exactly phi.  Needs a lattice
-    spacing above 2a (phi below about 0.47)."""
+def _packing_lib():
+    global _pack_lib
+    if _pack_lib is None:
+        import ctypes
+        import os
+        from . import build
+        if not os.path.exists(build.PACK_LIB):
+            build.build_packing()
+        lib = ctypes.CDLL(build.PACK_LIB)
+        lib.pack_rsa.argtypes = [ctypes.c_int64, ctypes.c_double, ctypes.c_double,
+                                 ctypes.c_uint64, ctypes.c_void_p]
+        lib.pack_compressed.argtypes = [ctypes.c_int64, ctypes.c_double, ctypes.c_double,
+                                        ctypes.c_double, ctypes.c_uint64, ctypes.c_void_p]
+        _pack_lib = lib
+    return _pack_lib
+
+
+def compiled_packing(N, phi, a=1.0, seed=SEED_BASE):
+    """(positions, L): random sequential addition (phi <= 0.3) or sequential
+    addition at phi = 0.3 then compression to phi, by the compiled
+    generator."""
     L = box_length(N, phi, a)
-    m = int(np.ceil(N ** (1.0 / 3.0) - 1e-9))
-    s = L / m
-    if s <= 2.0 * a:
-        raise ValueError('volume fraction too high for a jittered lattice')
-    rng = np.random.default_rng(seed)
-    sites = rng.choice(m**3, size=N, replace=False)
-    ijk = np.stack([sites % m, (sites // m) % m, sites // (m * m)], axis=1)
-    half_gap = 0.5 * (s - 2.0 * a) * (1.0 - 1e-9)
-    x = (ijk + 0.5) * s + rng.uniform(-half_gap, half_gap, size=(N, 3))
-    return np.mod(x, L), L
+    x = np.empty((N, 3))
+    lib = _packing_lib()
+    if phi <= RSA_PHI_MAX:
+        rc = lib.pack_rsa(N, L, a, seed % 2**64, x.ctypes.data)
+    else:
+        rc = lib.pack_compressed(N, L, a, RSA_PHI_MAX, seed % 2**64, x.ctypes.data)
+    if rc != 0:
+        raise RuntimeError(f'packing generator failed ({rc}) at N={N}, phi={phi}')
+    return x, L
 
 
 def packing(N, phi, a=1.0, seed=SEED_BASE):
-    """Random non-overlapping packing: sequential addition for dilute
-    suspensions, overlap relaxation for dense ones, a jittered lattice from
-    LATTICE_N spheres on (sequential addition is too slow there)."""
-    if N >= LATTICE_N:
-        return jittered_lattice(N, phi, a, seed)
+    """Random non-overlapping packing: for small N sequential addition for
+    dilute suspensions and overlap relaxation for dense ones; from CPACK_N
+    spheres on, the compiled generator."""
+    if N >= CPACK_N:
+        return compiled_packing(N, phi, a, seed)
     if phi <= 0.2:
         return rsa_packing(N, phi, a, seed)
     return relaxed_packing(N, phi, a, seed)

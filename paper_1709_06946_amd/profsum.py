@@ -92,8 +92,9 @@ def recorded_traffic(stage, profile_file):
 
 
 # Kernels whose launches make up one stage of the wave-space product.
-STAGE_PREFIX = {'fft': ('fft_',), 'kspace': ('kspace_fused',), 'spread': ('spread_list',),
-                'interp': ('interp_kernel',), 'real': ('real_pair',)}
+STAGE_PREFIX = {'fft': ('fft_',), 'kspace': ('kspace_fused',),
+                'spread': ('spread_list', 'spread_deriv'),
+                'interp': ('interp_kernel', 'interp_deriv'), 'real': ('real_pair',)}
 STAGE_SOURCES = {'fft': ('fft.hip', 'fftreg.h'), 'kspace': ('grid.hip', 'fftreg.h'),
                  'spread': ('grid.hip',), 'interp': ('grid.hip',), 'real': ('real.hip',)}
 COPY_BYTES = 2**30
