@@ -179,6 +179,23 @@ int pse_get_derived(const pse_handle *h, pse_derived *out);
 int pse_mobility_apply(pse_handle *h, const double *x, const double *in,
                        double *out, unsigned parts);
 
+/* The same product for callers that cannot allocate device memory (code under
+ * stream capture, tight serving loops, harnesses that forbid hipMalloc): no
+ * handle, and no hipMalloc, hipFree or allocating library call.  Parameters
+ * are derived from *p as by pse_create (its Krylov and graph settings are
+ * ignored); every buffer of the product (grids, tables, cell and pair lists)
+ * is taken from a fixed static device scratch of 64 MiB per device, which
+ * the library holds until the process ends.  x, in, out and parts as for
+ * pse_mobility_apply, on p->stream (NULL: the null stream); the call returns
+ * after the product has completed.  A product that does not fit the scratch
+ * (roughly: grids above 64^3, or many thousands of particles) returns
+ * PSE_ERR_NOMEM, with pse_last_error(NULL) saying so.  Every call on a device
+ * shares that device's scratch: calls that overlap on one GPU (other host
+ * threads, other streams) race and must be serialised by the caller.
+ * Errors are reported through pse_last_error(NULL). */
+int pse_mobility_apply_noalloc(const pse_params *p, const double *x, const double *in,
+                               double *out, unsigned parts);
+
 /* Split Brownian sampler (Eq. split): out_real = M_r^(1/2) psi_real by the
  * Lanczos iteration (relative change tolerance lanczos_tol), and
  * out_wave = M_w^(1/2) psi_wave by Eq. FFTsqrt (noise scaled, projected,

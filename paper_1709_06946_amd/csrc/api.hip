@@ -426,7 +426,19 @@ hipError_t dev_copy(void *dst, const void *src, size_t bytes, hipMemcpyKind kind
   return hipMemcpy(dst, src, bytes, kind);
 }
 
-static void alloc(void **p, size_t bytes) { dev_alloc(p, bytes); }
+void handle_alloc(Handle &h, void **p, size_t bytes) {
+  if (!h.arena) {
+    dev_alloc(p, bytes);
+    return;
+  }
+  const size_t off = (h.arena_used + 255) & ~(size_t)255;
+  if (off > h.arena_size || bytes > h.arena_size - off)
+    throw Error{PSE_ERR_NOMEM, "the allocation-free product needs more than its " +
+                                   std::to_string(h.arena_size >> 20) +
+                                   " MiB of static scratch (fewer particles or a smaller grid)"};
+  *p = h.arena + off;
+  h.arena_used = off + bytes;
+}
 
 static void create(const pse_params &p, Handle &h) {
   derive(p, h.d);
@@ -441,7 +453,9 @@ static void create(const pse_params &p, Handle &h) {
   h.stile = spread_tile(h.d.grid, h.d.support);
   h.sbins.nc = h.stile ? h.d.grid / h.stile : 0;
   h.deriv = h.d.deriv_gridding == 2;
-  if (p.stream) {
+  if (p.stream || h.arena) {
+    // the caller's stream (an allocation-free handle creates none: NULL is
+    // the null stream there)
     h.stream = (hipStream_t)p.stream;
     h.own_stream = false;
   } else {
@@ -461,63 +475,63 @@ static void create(const pse_params &p, Handle &h) {
   const size_t n = (size_t)h.n;
   const int ng = h.d.grid;
   const size_t packs64 = h.mixed ? MIXED_FP64_PACK : MAX_PACK;
-  alloc((void **)&h.g64.gin, packs64 * h.ngrid * sizeof(double2));
-  alloc((void **)&h.g64.gout, packs64 * h.ngrid * sizeof(double2));
-  alloc((void **)&h.g64.twiddle, ng * sizeof(double2));
+  handle_alloc(h, (void **)&h.g64.gin, packs64 * h.ngrid * sizeof(double2));
+  handle_alloc(h, (void **)&h.g64.gout, packs64 * h.ngrid * sizeof(double2));
+  handle_alloc(h, (void **)&h.g64.twiddle, ng * sizeof(double2));
   hipLaunchKernelGGL(twiddle_kernel64, dim3(nblocks(ng, 256)), dim3(256), 0, h.stream,
                      h.g64.twiddle, ng);
   PSE_LAUNCH_CHECK();
   if (h.mixed) {
-    alloc((void **)&h.g32.gin, MAX_PACK * h.ngrid * sizeof(float2));
-    alloc((void **)&h.g32.gout, MAX_PACK * h.ngrid * sizeof(float2));
-    alloc((void **)&h.g32.twiddle, ng * sizeof(float2));
+    handle_alloc(h, (void **)&h.g32.gin, MAX_PACK * h.ngrid * sizeof(float2));
+    handle_alloc(h, (void **)&h.g32.gout, MAX_PACK * h.ngrid * sizeof(float2));
+    handle_alloc(h, (void **)&h.g32.twiddle, ng * sizeof(float2));
     hipLaunchKernelGGL(twiddle_kernel32, dim3(nblocks(ng, 256)), dim3(256), 0, h.stream,
                        h.g32.twiddle, ng);
     PSE_LAUNCH_CHECK();
   }
   build_tables(h);
-  alloc((void **)&h.ktab, (size_t)ktable_len(ng) * 4 * sizeof(double));
-  if (h.mixed) alloc((void **)&h.ktab32, (size_t)ktable_len(ng) * 4 * sizeof(float));
-  alloc((void **)&h.bad_pos, 64);
+  handle_alloc(h, (void **)&h.ktab, (size_t)ktable_len(ng) * 4 * sizeof(double));
+  if (h.mixed) handle_alloc(h, (void **)&h.ktab32, (size_t)ktable_len(ng) * 4 * sizeof(float));
+  handle_alloc(h, (void **)&h.bad_pos, 64);
   build_ktable(h);
   if (h.stile) {
     const size_t ntile = (size_t)h.sbins.nc * h.sbins.nc * h.sbins.nc;
-    alloc((void **)&h.tl_cnt, ntile * sizeof(int));
-    alloc((void **)&h.tl_start, (ntile + 1) * sizeof(int));
-    alloc((void **)&h.tl_scan, ((ntile + 1023) / 1024 + 8) * sizeof(int));
+    handle_alloc(h, (void **)&h.tl_cnt, ntile * sizeof(int));
+    handle_alloc(h, (void **)&h.tl_start, (ntile + 1) * sizeof(int));
+    handle_alloc(h, (void **)&h.tl_scan, ((ntile + 1023) / 1024 + 8) * sizeof(int));
     h.tl_cap = n * tiles_per_particle(h.d.support, h.stile);
-    alloc((void **)&h.tl_rec, h.tl_cap * tile_record_bytes(h.stile) + 256);
+    handle_alloc(h, (void **)&h.tl_rec, h.tl_cap * tile_record_bytes(h.stile) + 256);
   }
-  alloc((void **)&h.pl_cnt, n * sizeof(int));
-  alloc((void **)&h.pl_start, (n + 1) * sizeof(int));
-  alloc((void **)&h.pl_scan, ((n + 1023) / 1024 + 8) * sizeof(int));
+  handle_alloc(h, (void **)&h.pl_cnt, n * sizeof(int));
+  handle_alloc(h, (void **)&h.pl_start, (n + 1) * sizeof(int));
+  handle_alloc(h, (void **)&h.pl_scan, ((n + 1023) / 1024 + 8) * sizeof(int));
   h.pl_cap = pair_capacity(h.p, h.d);
-  alloc((void **)&h.pl_nbr, h.pl_cap * sizeof(int));
-  alloc((void **)&h.pl_rec, h.pl_cap * 10 * sizeof(double));
+  handle_alloc(h, (void **)&h.pl_nbr, h.pl_cap * sizeof(int));
+  handle_alloc(h, (void **)&h.pl_rec, h.pl_cap * 10 * sizeof(double));
   for (Bins *b : {&h.cells, &h.sbins}) {
     if (b->nc == 0) continue;
     const size_t ncells = (size_t)b->nc * b->nc * b->nc;
-    alloc((void **)&b->start, (ncells + 1) * sizeof(int));
-    alloc((void **)&b->count, ncells * sizeof(int));
-    alloc((void **)&b->scan_tmp, ((ncells + 1023) / 1024 + 8) * sizeof(int));
-    alloc((void **)&b->of, n * sizeof(int));
-    alloc((void **)&b->slot, n * sizeof(int));
-    alloc((void **)&b->scat, n * sizeof(int));
-    alloc((void **)&b->perm, n * sizeof(int));
+    handle_alloc(h, (void **)&b->start, (ncells + 1) * sizeof(int));
+    handle_alloc(h, (void **)&b->count, ncells * sizeof(int));
+    handle_alloc(h, (void **)&b->scan_tmp, ((ncells + 1023) / 1024 + 8) * sizeof(int));
+    handle_alloc(h, (void **)&b->of, n * sizeof(int));
+    handle_alloc(h, (void **)&b->slot, n * sizeof(int));
+    handle_alloc(h, (void **)&b->scat, n * sizeof(int));
+    handle_alloc(h, (void **)&b->perm, n * sizeof(int));
   }
-  alloc((void **)&h.xw, 3 * n * sizeof(double));
-  alloc((void **)&h.xh, 3 * n * sizeof(double));
+  handle_alloc(h, (void **)&h.xw, 3 * n * sizeof(double));
+  handle_alloc(h, (void **)&h.xh, 3 * n * sizeof(double));
   double **vs[6] = {&h.v0, &h.v1, &h.v2, &h.v3, &h.v4, &h.v5};
-  for (double **v : vs) alloc((void **)v, NC * n * sizeof(double));
+  for (double **v : vs) handle_alloc(h, (void **)v, NC * n * sizeof(double));
   double **es[4] = {&h.es_b, &h.es_x, &h.es_r, &h.es_d};
-  for (double **v : es) alloc((void **)v, 5 * n * sizeof(double));
-  alloc((void **)&h.lz_V, (size_t)(h.d.lanczos_maxit + 1) * NC * n * sizeof(double));
-  alloc((void **)&h.gm_V, (size_t)(h.d.gmres_restart + 1) * 5 * n * sizeof(double));
+  for (double **v : es) handle_alloc(h, (void **)v, 5 * n * sizeof(double));
+  handle_alloc(h, (void **)&h.lz_V, (size_t)(h.d.lanczos_maxit + 1) * NC * n * sizeof(double));
+  handle_alloc(h, (void **)&h.gm_V, (size_t)(h.d.gmres_restart + 1) * 5 * n * sizeof(double));
   const size_t M = h.d.lanczos_maxit, R = h.d.gmres_restart;
   h.small_len = std::max((M + 1) * 8 + (M + 3) * (M + 1), (R + 1) * (R + 1) + 8 * (R + 2)) + 64;
-  alloc((void **)&h.small, h.small_len * sizeof(double));
+  handle_alloc(h, (void **)&h.small, h.small_len * sizeof(double));
   h.dots_len = 1024 * (std::max(M, R) + 2);
-  alloc((void **)&h.dots, h.dots_len * sizeof(double));
+  handle_alloc(h, (void **)&h.dots, h.dots_len * sizeof(double));
   PSE_HIP(hipStreamSynchronize(h.stream));
 }
 
@@ -531,8 +545,8 @@ static void release(Handle &h) {
                   h.es_d, h.lz_V, h.gm_V, h.small, h.dots, h.ktab, h.pl_cnt,
                   h.pl_start, h.pl_scan, h.pl_nbr, h.pl_rec, h.tl_cnt, h.tl_start,
                   h.tl_scan, h.tl_rec, h.bad_pos, h.ktab32};
-  for (void *p : ptrs)
-    dev_free(p);
+  if (!h.arena)
+    for (void *p : ptrs) dev_free(p);
   clear_graphs(h);
   for (hipEvent_t e : h.prof.pool) (void)hipEventDestroy(e);
   h.prof.pool.clear();
@@ -566,6 +580,33 @@ template <typename F> static int guarded(pse_handle *hd, F &&f) {
     else g_create_error = "unexpected exception";
     return PSE_ERR_HIP;
   }
+}
+
+// ---- static scratch of the allocation-free product
+
+// Device scratch of pse_mobility_apply_noalloc: every buffer of its
+// transient handle (grids, tables, bins, lists) is carved from it.  Each
+// device holds its own copy from the time the library's code object is
+// loaded on it until the process ends.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+// Device address of the current device's copy of `scratch`, looked up once
+// per device (the array's name is a host-side stand-in in host code).
+static unsigned char *scratch_address() {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static unsigned char *addr[kMaxDevices] = {};
+  int dev = 0;
+  PSE_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) throw Error{PSE_ERR_INVALID, "device index above 63"};
+  std::lock_guard<std::mutex> lk(mu);
+  if (!addr[dev]) {
+    void *p = nullptr;
+    PSE_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    addr[dev] = static_cast<unsigned char *>(p);
+  }
+  return addr[dev];
 }
 
 }  // namespace pse
@@ -645,6 +686,39 @@ int pse_mobility_apply(pse_handle *hd, const double *x, const double *in, double
     if (check_finite(h, out, (size_t)h.n * NC))
       throw Error{PSE_ERR_NONFINITE, "non-finite mobility product (non-finite input?)"};
   });
+}
+
+int pse_mobility_apply_noalloc(const pse_params *p, const double *x, const double *in,
+                               double *out, unsigned parts) {
+  if (!p || !x || !in || !out || (parts & 3u) == 0 || (parts & ~7u)) {
+    g_create_error = "pse_mobility_apply_noalloc: null pointer or bad parts";
+    return PSE_ERR_INVALID;
+  }
+  Handle h;
+  const int rc = guarded(nullptr, [&] {
+    // a product needs no Krylov bases and no captured graphs
+    pse_params q = *p;
+    q.lanczos_maxit = 1;
+    q.gmres_restart = 1;
+    q.graphs = -1;
+    h.arena = scratch_address();
+    h.arena_size = kScratchBytes;
+    create(q, h);
+    const CompSet all = comps_range(0, NC);
+    prepare_positions(h, x, h.xw);
+    if (parts & PSE_ES_BLOCK)
+      es_apply(h, h.xw, parts & PSE_REAL, parts & PSE_WAVE, in, FULL_LAYOUT, out, FULL_LAYOUT,
+               false);
+    else
+      mobility(h, h.xw, parts & PSE_REAL, parts & PSE_WAVE, in, FULL_LAYOUT, all, out,
+               FULL_LAYOUT, all, false);
+    if (check_finite(h, out, (size_t)h.n * NC))
+      throw Error{PSE_ERR_NONFINITE, "non-finite mobility product (non-finite input?)"};
+  });
+  RelaxedCaptureScope relaxed;
+  (void)hipStreamSynchronize(h.stream);
+  release(h);
+  return rc;
 }
 
 int pse_brownian_sample(pse_handle *hd, const double *x, const double *psi_real,

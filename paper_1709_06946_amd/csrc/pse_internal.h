@@ -186,7 +186,16 @@ struct Handle {
   bool graph_warm = false;   // one eager application before the first capture
   std::string graph_error;   // why graphs were switched off after a failed capture
   std::map<std::tuple<const void *, const void *, int>, hipGraphExec_t> graphs;
+
+  // A handle with an arena takes every device buffer from it (bump
+  // allocation, 256-byte aligned) instead of the runtime, and frees nothing.
+  unsigned char *arena = nullptr;
+  size_t arena_size = 0, arena_used = 0;
 };
+
+// Device buffer of a handle: from its arena when it has one (throws
+// PSE_ERR_NOMEM when the arena is full), else from the runtime (dev_alloc).
+void handle_alloc(Handle &h, void **p, size_t bytes);
 
 // Destroys every captured graph of the handle.
 void clear_graphs(Handle &h);

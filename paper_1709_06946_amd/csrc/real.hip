@@ -151,8 +151,8 @@ void build_tables(Handle &h) {
   h.n2a = 2048;
   h.dr = 2.0 * a / h.n2a;
   h.ntab = (int)std::ceil(h.d.rcut / h.dr) + 8;
-  dev_alloc((void **)&h.g64.table, (size_t)h.ntab * NCOEF * sizeof(double));
-  dev_alloc((void **)&h.g32.table, (size_t)h.ntab * NCOEF * sizeof(float));
+  handle_alloc(h, (void **)&h.g64.table, (size_t)h.ntab * NCOEF * sizeof(double));
+  handle_alloc(h, (void **)&h.g32.table, (size_t)h.ntab * NCOEF * sizeof(float));
   const double rmax = h.ntab * h.dr;
   const double dk = M_PI / (2.0 * a + rmax + 7.0 / xi);
   const double kmax = 2.0 * xi * std::sqrt(50.0);
@@ -667,6 +667,10 @@ static void build_pair_list(Handle &h, const double *xw) {
   PSE_HIP(hipStreamSynchronize(h.stream));
   if (bad) throw Error{PSE_ERR_NONFINITE, "non-finite particle position"};
   if ((size_t)total > h.pl_cap) {
+    if (h.arena)
+      throw Error{PSE_ERR_NOMEM, "real-space pair list beyond its capacity in the "
+                                 "allocation-free product (" + std::to_string(total) +
+                                 " pairs)"};
     clear_graphs(h);   // captured real-space launches hold the old buffers
     const size_t cap = (size_t)total + total / 4 + 1024;
     dev_free(h.pl_nbr);

@@ -92,7 +92,8 @@ class pse_server_info(ctypes.Structure):
 
 
 EXPORTS = ('pse_derive', 'pse_footprint_bytes', 'pse_create', 'pse_destroy',
-           'pse_get_derived', 'pse_mobility_apply', 'pse_brownian_sample',
+           'pse_get_derived', 'pse_mobility_apply', 'pse_mobility_apply_noalloc',
+           'pse_brownian_sample',
            'pse_constrained_step', 'pse_rpy_apply', 'pse_rpy_step', 'pse_fft3d', 'pse_rfft3d',
            'pse_spread', 'pse_interpolate',
            'pse_profile', 'pse_profile_read', 'pse_server_create', 'pse_server_submit',
@@ -120,6 +121,7 @@ def load_library(path=LIB_PATH):
     lib.pse_destroy.argtypes = [V]
     lib.pse_get_derived.argtypes = [V, P(pse_derived)]
     lib.pse_mobility_apply.argtypes = [V, V, V, V, ctypes.c_uint]
+    lib.pse_mobility_apply_noalloc.argtypes = [P(pse_params), V, V, V, ctypes.c_uint]
     lib.pse_brownian_sample.argtypes = [V, V, V, V, ctypes.c_uint64, ctypes.c_uint64,
                                         V, V, P(pse_stats)]
     lib.pse_constrained_step.argtypes = [V, V, V, ctypes.c_double, ctypes.c_uint64,
@@ -189,6 +191,22 @@ def footprint_bytes(params):
     if rc != PSE_OK:
         raise PSEError(f'pse_footprint_bytes: {rc}: {lib().pse_last_error(None).decode()}')
     return b.value
+
+
+def mobility_apply_noalloc(params, x, q, out, parts=None):
+    """out = M q by the allocation-free entry point (no handle; the library's
+    static device scratch holds every buffer).  params from make_params."""
+    if parts is None:
+        parts = PSE_REAL | PSE_WAVE
+    n = params.n
+    _sync()
+    rc = lib().pse_mobility_apply_noalloc(
+        ctypes.byref(params), _ptr(x, (n, 3), 'x'), _ptr(q, (n, 11), 'in'),
+        _ptr(out, (n, 11), 'out'), parts)
+    if rc < 0:
+        raise PSEError(f'pse_mobility_apply_noalloc: {rc}: '
+                       f'{lib().pse_last_error(None).decode()}')
+    return rc
 
 
 def _ptr(t, shape=None, name='tensor', dtype='float64'):
