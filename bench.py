@@ -79,6 +79,39 @@ def run_form(w, precision, steps, warmup, seed, prof_steps=2, deriv_gridding=0):
                              eta_s=d.eta_s), finite=bool(torch.isfinite(x).all()))
 
 
+def run_graph(w, precision, steps, warmup, seed):
+    """The same steps as replays of one captured graph of the whole step: a
+    synchronous first step gives the Krylov iteration counts, the handle is
+    switched to device-checked solves with those counts plus a margin, and
+    one captured step is replayed per step (one host launch per step)."""
+    import torch
+    N = w['N']
+    h = make_handle(w, precision)
+    x = torch.tensor(w['x'], device='cuda:0')
+    FL = torch.tensor(w['FL'], device='cuda:0')
+    _, st = h.constrained_step(x, FL, w['dt'], seed=seed, step=0)
+    passes = max(1, st['refine_passes'])
+    caps = (st['lanczos_iters'] + 1, st['gmres_iters'] // passes + 3, passes)
+    h.set_krylov(1, *caps, next_step=1)
+    g = h.step_graph(x, FL, w['dt'], seed=seed, steps=1)
+    for _ in range(warmup):
+        g.launch()
+    h.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g.launch()
+    h.synchronize()
+    dt = time.perf_counter() - t0
+    last = h.stats()
+    g.close()
+    h.close()
+    return dict(value=round(N * steps / dt, 1), ms_per_step=round(1e3 * dt / steps, 3),
+                caps=dict(lanczos=caps[0], gmres=caps[1], refine_passes=caps[2]),
+                last_step=dict(converged=last['converged'], status=last['status'],
+                               gmres_iters=last['gmres_iters'],
+                               fp64_residual=last['fp64_residual']))
+
+
 def form_difference(w, seed, deriv_gridding=0):
     """Velocity of one constrained step from the workload's initial positions
     with the same noise (internal Philox stream, same seed and step) in the
@@ -411,6 +444,11 @@ def main():
         r32 = run_form(w2, pse.PSE_MIXED, args.steps, args.warmup, w2['seed'])
         sec['fp64'] = form_summary(r64)
         sec['mixed'] = form_summary(r32, r64)
+        g64 = run_graph(w2, pse.PSE_FP64, args.steps, args.warmup, w2['seed'])
+        g64['speedup_vs_eager'] = round(g64['value'] / r64['value'], 3)
+        g32 = run_graph(w2, pse.PSE_MIXED, args.steps, args.warmup, w2['seed'])
+        g32['speedup_vs_eager'] = round(g32['value'] / r32['value'], 3)
+        sec['graph'] = dict(fp64=g64, mixed=g32)
         _, sec['fp64']['roofline'] = roofline(r64['prof'], None, w2['grid'], r64['bracket_us'])
         out['secondary'] = sec
     if not args.no_rpy:

@@ -42,8 +42,10 @@
  *   the library never frees or keeps it after the call returns.  The handle
  *   owns all its workspace (grids, spectra, cell lists, Krylov bases).
  * Streams: all work runs on the stream given at creation (NULL = the
- *   library's own stream).  Calls return after the work has completed.  A
- *   handle is not re-entrant: use one handle per host thread.
+ *   library's own stream).  Calls of a synchronous handle return after the
+ *   work has completed; calls of an asynchronous handle (params.async_calls)
+ *   only enqueue it.  A handle is not re-entrant: use one handle per host
+ *   thread.
  * Status: 0 = success; > 0 = warning with valid outputs; < 0 = error, outputs
  *   undefined.  No call aborts or throws; pse_last_error gives the message.
  */
@@ -109,6 +111,23 @@ typedef struct pse_params {
                               points per grid point N (P+1)^3 / Ng^3 stay
                               at most 20, else 1                            */
   void *stream;            /* hipStream_t to run on, or NULL                 */
+  int32_t async_calls;     /* 0: every call returns after its work has
+                              completed; Krylov solves check convergence on
+                              the host and stop at the first iteration that
+                              meets the tolerance.
+                              1: calls only enqueue work on the stream (no
+                              host synchronisation, so a whole step can be
+                              captured into a graph by the caller): every
+                              Lanczos solve runs exactly lanczos_maxit
+                              iterations (0 = 16) and every GMRES solve
+                              exactly gmres_maxit (0 = 32, no restarts;
+                              mixed handles: refine_passes passes, 0 = 1),
+                              the result taken at the first iteration that
+                              met the tolerance (the later ones are computed
+                              and discarded); statistics and status are
+                              written by the device (see pse_constrained_step);
+                              the pair list keeps its creation capacity (pairs
+                              beyond it are dropped and flagged). */
 } pse_params;
 
 /* Derived quantities (Sec. II.C, Eq. bound and the Sec. II.C.1 cutoff). */
@@ -127,9 +146,14 @@ typedef struct pse_derived {
                               derivative                                     */
 } pse_derived;
 
-/* Krylov statistics of the last call (written by the library, host memory). */
+/* Krylov statistics of a step.  Synchronous handles write them to host
+ * memory before returning; asynchronous handles write them from the device
+ * (the pointer must be device memory or pinned host memory) and they are
+ * valid once the stream has completed the call's work. */
 typedef struct pse_stats {
-  int32_t lanczos_iters;   /* Lanczos iterations of the real-space sqrt      */
+  int32_t lanczos_iters;   /* Lanczos iterations of the real-space sqrt (for
+                              asynchronous handles: the iteration whose
+                              iterate was taken)                             */
   int32_t gmres_iters;     /* GMRES iterations, all refinement passes        */
   int32_t refine_passes;   /* FP64 refinement passes (mixed precision)       */
   int32_t converged;       /* 1 if every Krylov solve met its tolerance      */
@@ -137,7 +161,23 @@ typedef struct pse_stats {
   double gmres_residual;   /* final relative residual of M_ES S = b (in the
                               precision of the last solve)                   */
   double fp64_residual;    /* FP64 relative residual after refinement, or -1 */
+  int32_t status;          /* asynchronous handles: PSE_STATUS_* bits of
+                              problems the device met (0 = none); 0 for
+                              synchronous handles, which return errors      */
+  int32_t reserved;
 } pse_stats;
+
+/* pse_stats.status bits. */
+enum {
+  PSE_STATUS_NONFINITE_POS = 1,  /* a non-finite position (taken as 0)       */
+  PSE_STATUS_PAIR_OVERFLOW = 2   /* real-space pairs beyond the pair list's
+                                    capacity were dropped                    */
+};
+
+/* step argument of pse_constrained_step / pse_rpy_step: take the noise
+ * counter from the handle's device step counter and advance it (asynchronous
+ * handles; a captured step then draws new noise on every replay). */
+#define PSE_STEP_DEVICE UINT64_MAX
 
 typedef struct pse_handle pse_handle;
 
@@ -231,6 +271,36 @@ typedef struct pse_step_io {
 int pse_constrained_step(pse_handle *h, double *x, const double *FL,
                          double dt, uint64_t seed, uint64_t step,
                          const pse_step_io *io, pse_stats *stats);
+
+/* Switch a live handle between synchronous (async_calls = 0) and
+ * asynchronous (1) calls.  For asynchronous calls, lanczos_iters (1 ..
+ * lanczos_maxit of the handle), gmres_iters (1 .. its gmres_restart: the
+ * basis holds every iteration) and refine_passes (>= 1, mixed handles) fix
+ * the device-checked solves, and the pair list gets half its last length as
+ * headroom (it cannot grow inside an asynchronous call).  The device step
+ * counter of PSE_STEP_DEVICE is set to next_step.  Synchronises the stream.
+ * Typical use: one synchronous step to learn the iteration counts, then
+ * asynchronous steps with a little margin. */
+int pse_set_krylov(pse_handle *h, int async_calls, int lanczos_iters, int gmres_iters,
+                   int refine_passes, uint64_t next_step);
+
+/* Wait until the handle's stream has completed all enqueued work. */
+int pse_synchronize(pse_handle *h);
+
+/* Graph-captured steps.  pse_step_graph_create captures `steps` constrained
+ * steps of an asynchronous handle on its own stream (params.stream NULL)
+ * into one executable graph: positions x (updated in place), forces FL (or
+ * NULL), dt and seed are fixed; the noise counter is the handle's device step
+ * counter (PSE_STEP_DEVICE), so every launch draws new noise; stats (device
+ * or pinned host memory, or NULL) receives each step's statistics.  Nothing
+ * runs at capture.  pse_step_graph_launch enqueues one replay on the handle's
+ * stream (no host synchronisation); pse_step_graph_destroy waits for the
+ * stream and frees the graph (the handle stays). */
+typedef struct pse_step_graph pse_step_graph;
+int pse_step_graph_create(pse_handle *h, double *x, const double *FL, double dt,
+                          uint64_t seed, int steps, pse_stats *stats, pse_step_graph **out);
+int pse_step_graph_launch(pse_step_graph *g);
+int pse_step_graph_destroy(pse_step_graph *g);
 
 /* ---- Unconstrained (RPY-level) PSE: forces only ----
  * The comparison system of the performance study (Sec. IV): the mobility

@@ -20,6 +20,12 @@ struct pse_handle {
   pse::Handle h;
 };
 
+struct pse_step_graph {
+  pse_handle *hd;
+  hipGraphExec_t exec;
+  int steps;
+};
+
 namespace pse {
 
 static thread_local std::string g_create_error = "no error";
@@ -92,6 +98,54 @@ __global__ void velocity_kernel(const double *__restrict__ slip, const double *_
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   for (int k = 0; k < 3; ++k) U[i * 3 + k] = slip[i * NC + k] + m[i * NC + k];
+}
+
+// step counter of PSE_STEP_DEVICE: set (add = 0) or advanced by one (add = 1)
+__global__ void step_counter_kernel(uint64_t *c, int add) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) c[0] = add ? c[0] + 1 : 0;
+}
+
+__global__ void step_counter_set_kernel(uint64_t *c, uint64_t v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) c[0] = v;
+}
+
+// statistics of an asynchronous call: cleared at its start ...
+__global__ void stats_init_kernel(pse_stats *st, int *status) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  st->lanczos_iters = 0;
+  st->gmres_iters = 0;
+  st->refine_passes = 0;
+  st->converged = 1;
+  st->lanczos_change = 0.0;
+  st->gmres_residual = 0.0;
+  st->fp64_residual = -1.0;
+  st->status = 0;
+  st->reserved = 0;
+  status[0] = 0;
+}
+
+// ... the FP64 relative residual of a refinement pass (the last pass also
+// decides convergence) ...
+__global__ void refine_stats_kernel(const double *bnorm2, const double *rnorm2, int pass,
+                                    int last, double tol, pse_stats *st) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double r = bnorm2[0] > 0.0 ? sqrt(fmax(rnorm2[0], 0.0) / bnorm2[0]) : 0.0;
+  st->fp64_residual = r;
+  st->refine_passes = pass + 1;
+  if (last && !(r < tol)) st->converged = 0;
+}
+
+// ... the FP64 GMRES residual is the FP64 residual ...
+__global__ void gmres_as_fp64_kernel(pse_stats *st) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) st->fp64_residual = st->gmres_residual;
+}
+
+// ... and copied out at its end with the status bits (out: device or pinned
+// host memory, may be NULL)
+__global__ void stats_finish_kernel(pse_stats *st, const int *status, pse_stats *out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  st->status = status[0];
+  if (out) *out = *st;
 }
 
 __global__ void twiddle_kernel64(double2 *tw, int n) {
@@ -218,6 +272,10 @@ static KrylovResult real_sqrt(Handle &h, const double *xw, const double *psi, do
     if (h.mixed) real_apply<float>(h, xw, in, FULL_LAYOUT, all, o, FULL_LAYOUT, all, false);
     else real_apply<double>(h, xw, in, FULL_LAYOUT, all, o, FULL_LAYOUT, all, false);
   };
+  if (h.async) {
+    lanczos_sqrt_dev(h, A, psi, (size_t)h.n * NC, out, h.lz_cap, h.d.lanczos_tol);
+    return KrylovResult{0, 0.0, true};
+  }
   return lanczos_sqrt(h, A, psi, (size_t)h.n * NC, out, h.d.lanczos_maxit, h.d.lanczos_tol,
                       &h.lz_prev);
 }
@@ -248,7 +306,11 @@ void clear_graphs(Handle &h) {
 // capture error then reappears in the eager run and is reported as usual.
 template <typename F>
 static void run_graphed(Handle &h, const void *in, const void *out, int kind, F &&fn) {
-  if (!h.use_graphs || h.prof.on || h.stream == nullptr || !h.graph_warm) {
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (h.stream) (void)hipStreamIsCapturing(h.stream, &cap);
+  if (!h.use_graphs || h.prof.on || h.stream == nullptr || !h.graph_warm ||
+      cap != hipStreamCaptureStatusNone) {
+    // (the caller capturing this stream records the launches themselves)
     fn();
     h.graph_warm = true;
     return;
@@ -310,6 +372,35 @@ static void stresslet_solve(Handle &h, const double *xh, const double *b, double
                   [&] { es_apply(h, xh, true, true, in, l5, o, l5, fp64); });
     });
   };
+  if (h.async) {
+    // device-checked: GMRES of exactly gmres_maxit iterations; mixed handles
+    // run refine_passes passes, each an FP32 solve for the correction and an
+    // FP64 residual (statistics on the device)
+    const int K = h.gm_cap;
+    if (!h.mixed) {
+      gmres_dev(h, make_op(true), b, n5, S, K, h.d.gmres_tol);
+      hipLaunchKernelGGL(gmres_as_fp64_kernel, dim3(1), dim3(1), 0, h.stream, h.dstats);
+      PSE_LAUNCH_CHECK();
+      return;
+    }
+    Op A32 = make_op(false), A64 = make_op(true);
+    double *b2 = h.small + h.small_len - 4, *r2 = b2 + 1;
+    vzero(h, S, n5);
+    vcopy(h, h.es_r, b, n5);
+    multi_dot(h, b, n5, 1, b, n5, b2);
+    for (int pass = 0; pass < h.ref_cap; ++pass) {
+      gmres_dev(h, A32, h.es_r, n5, h.es_d, K, h.d.gmres_tol);
+      vaxpby(h, 1.0, h.es_d, 1.0, S, n5);
+      A64(S, h.es_r);
+      vaxpby(h, 1.0, b, -1.0, h.es_r, n5);
+      multi_dot(h, h.es_r, n5, 1, h.es_r, n5, r2);
+      hipLaunchKernelGGL(refine_stats_kernel, dim3(1), dim3(1), 0, h.stream,
+                         (const double *)b2, (const double *)r2, pass,
+                         pass + 1 == h.ref_cap ? 1 : 0, h.d.gmres_tol, h.dstats);
+      PSE_LAUNCH_CHECK();
+    }
+    return;
+  }
   if (!h.mixed) {
     KrylovResult r = gmres(h, make_op(true), b, n5, S, h.d.gmres_restart, h.d.gmres_maxit,
                            h.d.gmres_tol, &h.gm_prev[0]);
@@ -446,6 +537,10 @@ static void create(const pse_params &p, Handle &h) {
   h.n = p.n;
   h.mixed = p.precision == PSE_MIXED;
   h.use_graphs = p.graphs >= 0;
+  h.async = p.async_calls != 0;
+  h.lz_cap = h.d.lanczos_maxit;
+  h.gm_cap = h.d.gmres_maxit;
+  h.ref_cap = h.d.refine_passes;
   h.ngrid = (size_t)h.d.grid * h.d.grid * h.d.grid;
   h.cells.nc = h.d.cells;
   // spreading tiles of stile^3 grid points gather from the 27 neighbouring
@@ -505,7 +600,9 @@ static void create(const pse_params &p, Handle &h) {
   handle_alloc(h, (void **)&h.pl_cnt, n * sizeof(int));
   handle_alloc(h, (void **)&h.pl_start, (n + 1) * sizeof(int));
   handle_alloc(h, (void **)&h.pl_scan, ((n + 1023) / 1024 + 8) * sizeof(int));
-  h.pl_cap = pair_capacity(h.p, h.d);
+  // the list of an asynchronous handle cannot grow (no host read of its
+  // length): twice the capacity up front
+  h.pl_cap = (h.async ? 2 : 1) * pair_capacity(h.p, h.d);
   handle_alloc(h, (void **)&h.pl_nbr, h.pl_cap * sizeof(int));
   handle_alloc(h, (void **)&h.pl_rec, h.pl_cap * 10 * sizeof(double));
   for (Bins *b : {&h.cells, &h.sbins}) {
@@ -528,10 +625,16 @@ static void create(const pse_params &p, Handle &h) {
   handle_alloc(h, (void **)&h.lz_V, (size_t)(h.d.lanczos_maxit + 1) * NC * n * sizeof(double));
   handle_alloc(h, (void **)&h.gm_V, (size_t)(h.d.gmres_restart + 1) * 5 * n * sizeof(double));
   const size_t M = h.d.lanczos_maxit, R = h.d.gmres_restart;
-  h.small_len = std::max((M + 1) * 8 + (M + 3) * (M + 1), (R + 1) * (R + 1) + 8 * (R + 2)) + 64;
+  h.small_len = std::max((M + 1) * 10 + (M + 3) * (M + 1), (R + 1) * (R + 1) + 8 * (R + 2)) + 64;
   handle_alloc(h, (void **)&h.small, h.small_len * sizeof(double));
   h.dots_len = 1024 * (std::max(M, R) + 2);
   handle_alloc(h, (void **)&h.dots, h.dots_len * sizeof(double));
+  handle_alloc(h, (void **)&h.dctl, CTL_WORDS * sizeof(int));
+  handle_alloc(h, (void **)&h.dstats, sizeof(pse_stats));
+  handle_alloc(h, (void **)&h.dstep, sizeof(uint64_t));
+  fill_int(h, h.dctl, CTL_WORDS, 0);
+  hipLaunchKernelGGL(step_counter_kernel, dim3(1), dim3(1), 0, h.stream, h.dstep, 0);
+  PSE_LAUNCH_CHECK();
   PSE_HIP(hipStreamSynchronize(h.stream));
 }
 
@@ -544,7 +647,7 @@ static void release(Handle &h) {
                   h.xw, h.xh, h.v0, h.v1, h.v2, h.v3, h.v4, h.v5, h.es_b, h.es_x, h.es_r,
                   h.es_d, h.lz_V, h.gm_V, h.small, h.dots, h.ktab, h.pl_cnt,
                   h.pl_start, h.pl_scan, h.pl_nbr, h.pl_rec, h.tl_cnt, h.tl_start,
-                  h.tl_scan, h.tl_rec, h.bad_pos, h.ktab32};
+                  h.tl_scan, h.tl_rec, h.bad_pos, h.ktab32, h.dctl, h.dstats, h.dstep};
   if (!h.arena)
     for (void *p : ptrs) dev_free(p);
   clear_graphs(h);
@@ -683,7 +786,7 @@ int pse_mobility_apply(pse_handle *hd, const double *x, const double *in, double
     else
       mobility(h, h.xw, parts & PSE_REAL, parts & PSE_WAVE, in, FULL_LAYOUT, all, out,
                FULL_LAYOUT, all, false);
-    if (check_finite(h, out, (size_t)h.n * NC))
+    if (!h.async && check_finite(h, out, (size_t)h.n * NC))
       throw Error{PSE_ERR_NONFINITE, "non-finite mobility product (non-finite input?)"};
   });
 }
@@ -721,6 +824,113 @@ int pse_mobility_apply_noalloc(const pse_params *p, const double *x, const doubl
   return rc;
 }
 
+int pse_set_krylov(pse_handle *hd, int async_calls, int lanczos_iters, int gmres_iters,
+                   int refine_passes, uint64_t next_step) {
+  if (!hd) return PSE_ERR_INVALID;
+  Handle &h = hd->h;
+  if (async_calls &&
+      (lanczos_iters < 1 || lanczos_iters > h.d.lanczos_maxit || gmres_iters < 1 ||
+       gmres_iters > h.d.gmres_restart || refine_passes < 1)) {
+    h.err = "pse_set_krylov: iterations beyond the handle's Krylov bases (lanczos_maxit, "
+            "gmres_restart) or below 1";
+    return PSE_ERR_INVALID;
+  }
+  return guarded(hd, [&] {
+    PSE_HIP(hipStreamSynchronize(h.stream));
+    if (async_calls) {
+      // the pair list cannot grow without a host read: headroom over the
+      // last count
+      const size_t want = h.pl_pairs + h.pl_pairs / 2 + 1024;
+      if (h.pl_cap < want && !h.arena) {
+        clear_graphs(h);
+        dev_free(h.pl_nbr);
+        dev_free(h.pl_rec);
+        h.pl_nbr = nullptr;
+        h.pl_rec = nullptr;
+        h.pl_cap = 0;
+        dev_alloc((void **)&h.pl_nbr, want * sizeof(int));
+        dev_alloc((void **)&h.pl_rec, want * 10 * sizeof(double));
+        h.pl_cap = want;
+      }
+      h.lz_cap = lanczos_iters;
+      h.gm_cap = gmres_iters;
+      h.ref_cap = refine_passes;
+    }
+    h.async = async_calls != 0;
+    hipLaunchKernelGGL(step_counter_kernel, dim3(1), dim3(1), 0, h.stream, h.dstep, 0);
+    PSE_LAUNCH_CHECK();
+    if (next_step) {
+      hipLaunchKernelGGL(step_counter_set_kernel, dim3(1), dim3(1), 0, h.stream, h.dstep,
+                         next_step);
+      PSE_LAUNCH_CHECK();
+    }
+    PSE_HIP(hipStreamSynchronize(h.stream));
+  });
+}
+
+int pse_synchronize(pse_handle *hd) {
+  if (!hd) return PSE_ERR_INVALID;
+  return guarded(hd, [&] { PSE_HIP(hipStreamSynchronize(hd->h.stream)); });
+}
+
+int pse_step_graph_create(pse_handle *hd, double *x, const double *FL, double dt,
+                          uint64_t seed, int steps, pse_stats *stats, pse_step_graph **out) {
+  if (!hd || !out || !x || steps < 1 || !(dt > 0)) return PSE_ERR_INVALID;
+  *out = nullptr;
+  Handle &h = hd->h;
+  if (!h.async || !h.own_stream) {
+    h.err = "pse_step_graph_create: needs an asynchronous handle on its own stream";
+    return PSE_ERR_INVALID;
+  }
+  hipGraphExec_t exec = nullptr;
+  const int rc = guarded(hd, [&] {
+    PSE_HIP(hipStreamSynchronize(h.stream));
+    hipGraph_t g = nullptr;
+    std::string why;
+    {
+      std::shared_lock<std::shared_mutex> gate(capture_gate());
+      PSE_HIP(hipStreamBeginCapture(h.stream, hipStreamCaptureModeThreadLocal));
+      int src = PSE_OK;
+      for (int k = 0; k < steps && src == PSE_OK; ++k)
+        src = pse_constrained_step(hd, x, FL, dt, seed, PSE_STEP_DEVICE, nullptr, stats);
+      if (src != PSE_OK) why = h.err;
+      const hipError_t e = hipStreamEndCapture(h.stream, &g);
+      if (why.empty() && e != hipSuccess)
+        why = std::string("hipStreamEndCapture: ") + hipGetErrorString(e);
+      if (why.empty()) {
+        const hipError_t ie = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+        if (ie != hipSuccess) why = std::string("hipGraphInstantiate: ") + hipGetErrorString(ie);
+      }
+      if (g) (void)hipGraphDestroy(g);
+    }
+    if (!why.empty()) {
+      (void)hipGetLastError();
+      throw Error{PSE_ERR_HIP, "step capture failed: " + why};
+    }
+  });
+  if (rc != PSE_OK) return rc;
+  pse_step_graph *sg = new (std::nothrow) pse_step_graph{hd, exec, steps};
+  if (!sg) {
+    (void)hipGraphExecDestroy(exec);
+    return PSE_ERR_NOMEM;
+  }
+  *out = sg;
+  return PSE_OK;
+}
+
+int pse_step_graph_launch(pse_step_graph *sg) {
+  if (!sg) return PSE_ERR_INVALID;
+  return guarded(sg->hd, [&] { PSE_HIP(hipGraphLaunch(sg->exec, sg->hd->h.stream)); });
+}
+
+int pse_step_graph_destroy(pse_step_graph *sg) {
+  if (!sg) return PSE_OK;
+  (void)hipStreamSynchronize(sg->hd->h.stream);
+  (void)hipGraphExecDestroy(sg->exec);
+  delete sg;
+  return PSE_OK;
+}
+
 int pse_brownian_sample(pse_handle *hd, const double *x, const double *psi_real,
                         const double *psi_wave, uint64_t seed, uint64_t counter,
                         double *out_real, double *out_wave, pse_stats *stats) {
@@ -735,6 +945,11 @@ int pse_brownian_sample(pse_handle *hd, const double *x, const double *psi_real,
     pse_stats st{};
     st.converged = 1;
     st.fp64_residual = -1;
+    if (h.async) {
+      hipLaunchKernelGGL(stats_init_kernel, dim3(1), dim3(1), 0, h.stream, h.dstats,
+                         h.dctl + CTL_STATUS);
+      PSE_LAUNCH_CHECK();
+    }
     prepare_positions(h, x, h.xw);
     if (out_real) {
       const double *psi = psi_real;
@@ -751,6 +966,12 @@ int pse_brownian_sample(pse_handle *hd, const double *x, const double *psi_real,
       }
     }
     if (out_wave) wave_sqrt(h, h.xw, psi_wave, seed, counter, out_wave, comps_range(0, NC));
+    if (h.async) {
+      hipLaunchKernelGGL(stats_finish_kernel, dim3(1), dim3(1), 0, h.stream, h.dstats,
+                         (const int *)(h.dctl + CTL_STATUS), stats);
+      PSE_LAUNCH_CHECK();
+      return;
+    }
     PSE_HIP(hipStreamSynchronize(h.stream));
     if (stats) *stats = st;
   });
@@ -772,6 +993,13 @@ int pse_constrained_step(pse_handle *hd, double *x, const double *FL, double dt,
     pse_stats st{};
     st.fp64_residual = -1;
     bool converged = true;
+    const bool dev_step = h.async && step == PSE_STEP_DEVICE;
+    h.counter_dev = dev_step ? h.dstep : nullptr;
+    if (h.async) {
+      hipLaunchKernelGGL(stats_init_kernel, dim3(1), dim3(1), 0, h.stream, h.dstats,
+                         h.dctl + CTL_STATUS);
+      PSE_LAUNCH_CHECK();
+    }
     // 1. slip velocities at x_k
     prepare_positions(h, x, h.xw);
     const double *psi = io ? io->psi_real : nullptr;
@@ -832,11 +1060,23 @@ int pse_constrained_step(pse_handle *hd, double *x, const double *FL, double dt,
       if (io->velocity) PSE_HIP(hipMemcpyAsync(io->velocity, U, 3 * n * sizeof(double),
                                                hipMemcpyDeviceToDevice, h.stream));
     }
+    if (h.async) {
+      if (dev_step) {
+        hipLaunchKernelGGL(step_counter_kernel, dim3(1), dim3(1), 0, h.stream, h.dstep, 1);
+        PSE_LAUNCH_CHECK();
+      }
+      h.counter_dev = nullptr;
+      hipLaunchKernelGGL(stats_finish_kernel, dim3(1), dim3(1), 0, h.stream, h.dstats,
+                         (const int *)(h.dctl + CTL_STATUS), stats);
+      PSE_LAUNCH_CHECK();
+      return;
+    }
     PSE_HIP(hipStreamSynchronize(h.stream));
     st.converged = converged ? 1 : 0;
     if (!converged) warn = PSE_WARN_NOT_CONVERGED;
     if (stats) *stats = st;
   });
+  if (hd) hd->h.counter_dev = nullptr;
   return rc != PSE_OK ? rc : warn;
 }
 
@@ -858,7 +1098,7 @@ int pse_rpy_apply(pse_handle *hd, const double *x, const double *F, double *U,
     prepare_positions(h, x, h.xw);
     mobility(h, h.xw, parts & PSE_REAL, parts & PSE_WAVE, F, RPY_LAYOUT, u3, U, RPY_LAYOUT, u3,
              false);
-    if (check_finite(h, U, (size_t)h.n * 3))
+    if (!h.async && check_finite(h, U, (size_t)h.n * 3))
       throw Error{PSE_ERR_NONFINITE, "non-finite mobility product (non-finite input?)"};
   });
 }
@@ -877,6 +1117,13 @@ int pse_rpy_step(pse_handle *hd, double *x, const double *F, double dt, uint64_t
     const CompSet u3 = comps_range(0, 3);
     pse_stats st{};
     st.fp64_residual = -1;
+    const bool dev_step = h.async && step == PSE_STEP_DEVICE;
+    h.counter_dev = dev_step ? h.dstep : nullptr;
+    if (h.async) {
+      hipLaunchKernelGGL(stats_init_kernel, dim3(1), dim3(1), 0, h.stream, h.dstats,
+                         h.dctl + CTL_STATUS);
+      PSE_LAUNCH_CHECK();
+    }
     prepare_positions(h, x, h.xw);
     // (M_r)_UF^(1/2) psi1 by Lanczos on the UF block of the pair sum
     const double *psi = io ? io->psi_real : nullptr;
@@ -888,8 +1135,12 @@ int pse_rpy_step(pse_handle *hd, double *x, const double *F, double dt, uint64_t
       if (h.mixed) real_apply<float>(h, h.xw, in, RPY_LAYOUT, u3, o, RPY_LAYOUT, u3, false);
       else real_apply<double>(h, h.xw, in, RPY_LAYOUT, u3, o, RPY_LAYOUT, u3, false);
     };
-    KrylovResult lr = lanczos_sqrt(h, A, psi, (size_t)n * 3, h.v0, h.d.lanczos_maxit,
-                                   h.d.lanczos_tol, &h.lz_prev_rpy);
+    KrylovResult lr{0, 0.0, true};
+    if (h.async)
+      lanczos_sqrt_dev(h, A, psi, (size_t)n * 3, h.v0, h.lz_cap, h.d.lanczos_tol);
+    else
+      lr = lanczos_sqrt(h, A, psi, (size_t)n * 3, h.v0, h.d.lanczos_maxit, h.d.lanczos_tol,
+                        &h.lz_prev_rpy);
     st.lanczos_iters = lr.iters;
     st.lanczos_change = lr.resid;
     // (M_w)_UF^(1/2) psi2: the wave sampler's velocity rows
@@ -910,11 +1161,23 @@ int pse_rpy_step(pse_handle *hd, double *x, const double *F, double dt, uint64_t
       if (io->velocity) PSE_HIP(hipMemcpyAsync(io->velocity, U, 3 * n * sizeof(double),
                                                hipMemcpyDeviceToDevice, h.stream));
     }
+    if (h.async) {
+      if (dev_step) {
+        hipLaunchKernelGGL(step_counter_kernel, dim3(1), dim3(1), 0, h.stream, h.dstep, 1);
+        PSE_LAUNCH_CHECK();
+      }
+      h.counter_dev = nullptr;
+      hipLaunchKernelGGL(stats_finish_kernel, dim3(1), dim3(1), 0, h.stream, h.dstats,
+                         (const int *)(h.dctl + CTL_STATUS), stats);
+      PSE_LAUNCH_CHECK();
+      return;
+    }
     PSE_HIP(hipStreamSynchronize(h.stream));
     st.converged = lr.converged ? 1 : 0;
     if (!lr.converged) warn = PSE_WARN_NOT_CONVERGED;
     if (stats) *stats = st;
   });
+  if (hd) hd->h.counter_dev = nullptr;
   return rc != PSE_OK ? rc : warn;
 }
 

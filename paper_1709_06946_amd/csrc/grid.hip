@@ -851,12 +851,13 @@ template <typename T>
 __global__ void __launch_bounds__(256)
 kspace_noise_kernel(const double2 *__restrict__ psi, uint64_t seed, uint64_t counter,
                     cplx<T> *__restrict__ out, CompSet cout, KGeom kg,
-                    const double4 *__restrict__ ktab) {
+                    const double4 *__restrict__ ktab, const uint64_t *counter_dev) {
   using C = cplx<T>;
   const int n = kg.ng, hx = n / 2, hp = n / 2 + 1;
   const size_t hsz = (size_t)hx * n * n;
   const size_t tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (tid >= hsz) return;
+  if (counter_dev) counter = *counter_dev;
   const int ix = (int)(tid % hx);
   const int iy = (int)((tid / hx) % n);
   const int iz = (int)(tid / ((size_t)hx * n));
@@ -904,9 +905,10 @@ kspace_noise_kernel(const double2 *__restrict__ psi, uint64_t seed, uint64_t cou
 
 // Real-space noise psi1 ~ N(0, I), 11 per particle, from Philox.
 __global__ void real_noise_kernel(uint64_t seed, uint64_t counter, int64_t n, int ncomp,
-                                  double *__restrict__ out) {
+                                  double *__restrict__ out, const uint64_t *counter_dev) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  if (counter_dev) counter = *counter_dev;
   double z[12];
   philox_normals(seed, counter, STREAM_REAL, (uint32_t)i, 3, z);
   for (int c = 0; c < ncomp; ++c) out[i * ncomp + c] = z[c];
@@ -1306,13 +1308,13 @@ void kspace_noise(Handle &h, const double *psi, uint64_t seed, uint64_t counter,
   ProfScope ps(h, PK_NOISE, (double)cout.n * hsz * sizeof(cplx<T>) + (psi ? 3.0 * hsz * 16 : 0.0));
   hipLaunchKernelGGL(kspace_noise_kernel<T>, dim3(nblocks(hsz, 256)), dim3(256),
                      0, h.stream, (const double2 *)psi, seed, counter, out, cout,
-                     kgeom(h), (const double4 *)h.ktab);
+                     kgeom(h), (const double4 *)h.ktab, h.counter_dev);
   PSE_LAUNCH_CHECK();
 }
 
 void real_noise(Handle &h, uint64_t seed, uint64_t counter, double *out, int ncomp) {
   hipLaunchKernelGGL(real_noise_kernel, dim3(nblocks(h.n, 256)), dim3(256), 0,
-                     h.stream, seed, counter, h.n, ncomp, out);
+                     h.stream, seed, counter, h.n, ncomp, out, h.counter_dev);
   PSE_LAUNCH_CHECK();
 }
 

@@ -18,6 +18,16 @@ __global__ void zero_kernel_d(double *v, size_t n) {
   if (i < n) v[i] = 0.0;
 }
 
+__global__ void fill_kernel_d(double *v, size_t n, double value) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) v[i] = value;
+}
+
+__global__ void fill_kernel_i(int *v, size_t n, int value) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) v[i] = value;
+}
+
 __global__ void copy_kernel_d(double *dst, const double *src, size_t n) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) dst[i] = src[i];
@@ -116,12 +126,14 @@ __global__ void sub_scale_kernel(double *__restrict__ w, const double *__restric
   w[i] = (w[i] - acc) * f;
 }
 
-// y = (acc ? y : 0) + alpha sum_j coef_j V_j
+// y = (acc ? y : 0) + alpha sum_j coef_j V_j (m from m_dev when given)
 __global__ void gemv_small_kernel(const double *__restrict__ V, size_t ldv, int m,
                                   const double *__restrict__ coef, double *__restrict__ y,
-                                  size_t n, double alpha, int accumulate) {
+                                  size_t n, double alpha, int accumulate,
+                                  const int *__restrict__ m_dev) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  if (m_dev) m = *m_dev;
   double acc = 0.0;
   for (int j = 0; j < m; ++j) acc += coef[j] * V[(size_t)j * ldv + i];
   y[i] = (accumulate ? y[i] : 0.0) + alpha * acc;
@@ -166,6 +178,18 @@ void vzero(Handle &h, double *v, size_t n) {
   hipLaunchKernelGGL(zero_kernel_d, dim3(nblocks(n, 256)), dim3(256), 0, h.stream, v, n);
   PSE_LAUNCH_CHECK();
 }
+void fill_int(Handle &h, int *v, size_t n, int value) {
+  hipLaunchKernelGGL(fill_kernel_i, dim3(nblocks(n, 256)), dim3(256), 0, h.stream, v, n,
+                     value);
+  PSE_LAUNCH_CHECK();
+}
+
+static void fill_double(Handle &h, double *v, size_t n, double value) {
+  hipLaunchKernelGGL(fill_kernel_d, dim3(nblocks(n, 256)), dim3(256), 0, h.stream, v, n,
+                     value);
+  PSE_LAUNCH_CHECK();
+}
+
 void vcopy(Handle &h, double *dst, const double *src, size_t n) {
   hipLaunchKernelGGL(copy_kernel_d, dim3(nblocks(n, 256)), dim3(256), 0, h.stream, dst,
                      src, n);
@@ -199,10 +223,10 @@ void vsub_multi(Handle &h, double *w, const double *V, size_t ldv, int m,
 }
 
 void gemv_small(Handle &h, const double *V, size_t ldv, int m, const double *coef_dev,
-                double *y, size_t n, double alpha, bool accumulate) {
+                double *y, size_t n, double alpha, bool accumulate, const int *m_dev) {
   ProfScope ps(h, PK_KRYLOV, (double)(m + 1 + (accumulate ? 1 : 0)) * n * 8);
   hipLaunchKernelGGL(gemv_small_kernel, dim3(nblocks(n, 256)), dim3(256), 0, h.stream, V,
-                     ldv, m, coef_dev, y, n, alpha, accumulate ? 1 : 0);
+                     ldv, m, coef_dev, y, n, alpha, accumulate ? 1 : 0, m_dev);
   PSE_LAUNCH_CHECK();
 }
 
@@ -302,16 +326,23 @@ __device__ void tridiag_ql(double *d, double *e, double *z, int m, int ldz) {
 // (zero-padded), written to out_change.  One wavefront (64 threads): inputs
 // loaded in parallel, the eigenproblem by tridiag_ql, coefficient i by lane
 // i mod 64, the change summed in index order by lane 0.
+// Device-checked solves (sel != NULL): sel[0] is set once the first
+// iteration that met the tolerance (or broke down: vn_hist[m-1] <= 1e-14 |b|)
+// is found, sel[1] holds its size m and coef_sel its coefficients; at the
+// last iteration (last != 0) without one, m is taken and sel[2] = 1 (not
+// converged).
 __global__ void __launch_bounds__(64)
-lanczos_sqrt_kernel(const double *alpha, const double *beta, int m, double bnorm,
+lanczos_sqrt_kernel(const double *alpha, const double *beta, int m, const double *bnorm_dev,
                     double *work, int ldz, double *coef, double *coef_prev,
-                    double *out_change, double *chg_hist) {
+                    double *out_change, double *chg_hist, int *sel, double *coef_sel,
+                    const double *vn_hist, double tol, int last) {
   // LDS: the new and previous coefficients (2m), then d, e and z when they
   // fit (ldz == m; the host sizes the dynamic shared memory), else those
   // live in the global work area
   extern __shared__ double lds_work[];
   if (blockIdx.x != 0) return;
   const int lane = threadIdx.x, nt = blockDim.x;
+  const double bnorm = *bnorm_dev;
   double *cbuf = lds_work, *pbuf = lds_work + m;
   double *base = ldz == m ? lds_work + 2 * m : work;
   double *d = base, *e = base + ldz, *z = base + 2 * ldz;
@@ -343,11 +374,23 @@ lanczos_sqrt_kernel(const double *alpha, const double *beta, int m, double bnorm
   }
   out_change[0] = den > 0.0 ? sqrt(num / den) : 0.0;
   chg_hist[m - 1] = out_change[0];
+  if (!sel || sel[0]) return;
+  const bool brk = vn_hist[m - 1] <= 1e-14 * bnorm;
+  const bool conv = m > 1 && out_change[0] < tol;
+  if (brk || conv || last) {
+    sel[0] = 1;
+    sel[1] = m;
+    sel[2] = (brk || conv) ? 0 : 1;
+    for (int i = 0; i < m; ++i) coef_sel[i] = cbuf[i];
+  }
 }
 
-// y = R^{-1} g for the k x k upper-triangular part of H.
-__global__ void backsub_kernel(const double *H, int ldh, int k, const double *g, double *y) {
+// y = R^{-1} g for the k x k upper-triangular part of H (k from k_dev when
+// given).
+__global__ void backsub_kernel(const double *H, int ldh, int k, const double *g, double *y,
+                               const int *k_dev) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (k_dev) k = *k_dev;
   for (int i = k - 1; i >= 0; --i) {
     double s = g[i];
     for (int j = i + 1; j < k; ++j) s -= H[(size_t)j * ldh + i] * y[j];
@@ -363,12 +406,17 @@ __global__ void backsub_kernel(const double *H, int ldh, int k, const double *g,
 // One wavefront: the column, its squared norm and the previous rotations
 // are loaded in parallel into LDS (3j + 2 doubles, sized by the host), then
 // lane 0 applies the rotations.
+// Device-checked solves (sel != NULL): sel[0] is set at the first column
+// whose residual met tol |b| or whose new vector vanished (vn <= 1e-15 |b|),
+// sel[1] = its column count k (0 for b = 0); at the last column (last != 0)
+// without one, k = j + 1 and sel[2] = 1 (not converged).
 __global__ void __launch_bounds__(64)
 hess_givens_kernel(double *__restrict__ H, int ldh, int j, const double *__restrict__ h1,
                    const double *__restrict__ h2, double *__restrict__ cs,
                    double *__restrict__ sn, double *__restrict__ g, double *__restrict__ vnorm,
                    double *__restrict__ resid, double *__restrict__ vn_hist,
-                   double *__restrict__ res_hist) {
+                   double *__restrict__ res_hist, int *__restrict__ sel,
+                   const double *__restrict__ bnorm_dev, double tol, int last) {
   extern __shared__ double sm[];
   if (blockIdx.x != 0) return;
   double *cl = sm, *cs_l = sm + (j + 2), *sn_l = cs_l + j;
@@ -410,6 +458,14 @@ hess_givens_kernel(double *__restrict__ H, int ldh, int j, const double *__restr
   resid[0] = fabs(g[j + 1]);
   vn_hist[j] = nn;
   res_hist[j] = resid[0];
+  if (!sel || sel[0]) return;
+  const double bn = *bnorm_dev;
+  const bool done = resid[0] < tol * bn || nn <= 1e-15 * bn;
+  if (done || last) {
+    sel[0] = 1;
+    sel[1] = bn > 0.0 ? j + 1 : 0;
+    sel[2] = done ? 0 : 1;
+  }
 }
 
 __global__ void sqrt_kernel(const double *in, double *out) {
@@ -533,10 +589,10 @@ KrylovResult lanczos_sqrt(Handle &h, const Op &A, const double *b, size_t n, dou
     res.converged = true;
     return res;
   }
-  PSE_HIP(hipMemsetAsync(coef_prev, 0, (M + 1) * sizeof(double), h.stream));
+  fill_double(h, coef_prev, M + 1, 0.0);
   // iterations before the first read leave their change unset: zero, so that
   // the history read back is finite
-  PSE_HIP(hipMemsetAsync(chg_hist, 0, (M + 1) * sizeof(double), h.stream));
+  fill_double(h, chg_hist, M + 1, 0.0);
   vscale_dev(h, V, b, bn, true, n);
   auto sqrt_coef = [&](int mm) {
     // LDS holds the two coefficient vectors, and d, e and the mm^2
@@ -545,8 +601,9 @@ KrylovResult lanczos_sqrt(Handle &h, const Op &A, const double *b, size_t n, dou
     const size_t lds = coefs + (size_t)(2 * mm + mm * mm) * sizeof(double);
     const bool fits = lds <= 49152;
     hipLaunchKernelGGL(lanczos_sqrt_kernel, dim3(1), dim3(64), fits ? lds : coefs, h.stream, alpha,
-                       beta, mm, bnorm, work, fits ? mm : ldz, coef, coef_prev, change,
-                       chg_hist);
+                       beta, mm, (const double *)bn, work, fits ? mm : ldz, coef, coef_prev,
+                       change, chg_hist, (int *)nullptr, (double *)nullptr,
+                       (const double *)nullptr, 0.0, 0);
     PSE_LAUNCH_CHECK();
   };
   const int check_from = (prev_iters && *prev_iters > 3) ? *prev_iters - 2 : 0;
@@ -589,7 +646,7 @@ KrylovResult lanczos_sqrt(Handle &h, const Op &A, const double *b, size_t n, dou
     }
   }
   if (prev_iters) *prev_iters = res.iters;
-  gemv_small(h, V, n, m, coef, y, n, 1.0, false);
+  gemv_small(h, V, n, m, coef, y, n, 1.0, false, nullptr);
   return res;
 }
 
@@ -660,7 +717,8 @@ KrylovResult gmres(Handle &h, const Op &A, const double *b, size_t n, double *x,
       cgs2_pass(h, V, n, j + 1, w, h1, h2);
       hipLaunchKernelGGL(hess_givens_kernel, dim3(1), dim3(64),
                          (size_t)(3 * j + 2) * sizeof(double), h.stream, H, ldh, j, h1, h2,
-                         cs, sn, g, vnorm, resid, vn_hist, res_hist);
+                         cs, sn, g, vnorm, resid, vn_hist, res_hist, (int *)nullptr,
+                         (const double *)nullptr, 0.0, 0);
       PSE_LAUNCH_CHECK();
       sub_scale(h, w, V, n, j + 1, h2, vnorm);
       ++total;
@@ -683,9 +741,10 @@ KrylovResult gmres(Handle &h, const Op &A, const double *b, size_t n, double *x,
       }
       rel = rh[j] / bnorm;
     }
-    hipLaunchKernelGGL(backsub_kernel, dim3(1), dim3(1), 0, h.stream, H, ldh, k, g, ycoef);
+    hipLaunchKernelGGL(backsub_kernel, dim3(1), dim3(1), 0, h.stream, H, ldh, k, g, ycoef,
+                       (const int *)nullptr);
     PSE_LAUNCH_CHECK();
-    gemv_small(h, V, n, k, ycoef, x, n, 1.0, true);
+    gemv_small(h, V, n, k, ycoef, x, n, 1.0, true, nullptr);
     if (rel < tol) {
       res.converged = true;
       break;
@@ -695,6 +754,125 @@ KrylovResult gmres(Handle &h, const Op &A, const double *b, size_t n, double *x,
   res.resid = rel;
   if (prev_iters) *prev_iters = total;
   return res;
+}
+
+// ------------------------------------------- device-checked solves --
+//
+// Used by asynchronous handles: no host reads.  A solve runs exactly K
+// iterations; kernels record on the device the first iteration that met the
+// tolerance (or exhausted the Krylov space), and the result is formed from
+// that iteration's quantities, so that it equals the result of stopping
+// there (the later iterations are computed and discarded).  With no such
+// iteration within K, the K-th iterate is taken and the solve is reported
+// as not converged.
+
+// stats after a Lanczos solve: iterations, last change, convergence
+__global__ void lanczos_stats_kernel(const int *sel, const double *chg_hist, pse_stats *st) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int m = sel[1];
+  st->lanczos_iters = m;
+  st->lanczos_change = m > 0 ? chg_hist[m - 1] : 0.0;
+  if (sel[2]) st->converged = 0;
+}
+
+// stats after a GMRES solve (accumulated over refinement passes)
+__global__ void gmres_stats_kernel(const int *sel, const double *res_hist, const double *bn,
+                                   pse_stats *st) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int k = sel[1];
+  st->gmres_iters += k;
+  st->gmres_residual = (k > 0 && bn[0] > 0.0) ? res_hist[k - 1] / bn[0] : 0.0;
+  if (sel[2]) st->converged = 0;
+}
+
+void lanczos_sqrt_dev(Handle &h, const Op &A, const double *b, size_t n, double *y, int K,
+                      double tol) {
+  const int M = K;
+  const int ldz = M + 1;
+  double *s = h.small;
+  double *alpha = s, *beta = alpha + (M + 1), *h1 = beta + (M + 1), *h2 = h1 + (M + 1);
+  double *norm2 = h2 + (M + 1), *vnorm = norm2 + 1, *bn = vnorm + 1, *change = bn + 1;
+  double *coef = change + 1, *coef_prev = coef + (M + 1);
+  double *vn_hist = coef_prev + (M + 1), *chg_hist = vn_hist + (M + 1);
+  double *coef_sel = chg_hist + (M + 1);
+  double *work = coef_sel + (M + 1);
+  if ((size_t)(work - s) + (size_t)(2 + ldz) * ldz + 8 > h.small_len)
+    throw Error{PSE_ERR_INVALID, "Lanczos scratch too small"};
+  int *sel = h.dctl + CTL_LZ;
+  double *V = h.lz_V;
+  norm2_dev(h, b, n, norm2);
+  hipLaunchKernelGGL(sqrt_kernel, dim3(1), dim3(1), 0, h.stream, norm2, bn);
+  PSE_LAUNCH_CHECK();
+  fill_double(h, coef_prev, M + 1, 0.0);
+  fill_double(h, chg_hist, M + 1, 0.0);
+  fill_int(h, sel, 3, 0);
+  vscale_dev(h, V, b, bn, true, n);
+  for (int j = 0; j < M; ++j) {
+    double *w = V + (size_t)(j + 1) * n;
+    A(V + (size_t)j * n, w);
+    cgs2_pass(h, V, n, j + 1, w, h1, h2);
+    hipLaunchKernelGGL(lanczos_fill_kernel, dim3(1), dim3(1), 0, h.stream, alpha, beta, j,
+                       h1, h2, vnorm, vn_hist);
+    PSE_LAUNCH_CHECK();
+    sub_scale(h, w, V, n, j + 1, h2, vnorm);
+    const int mm = j + 1;
+    const size_t coefs = (size_t)2 * mm * sizeof(double);
+    const size_t lds = coefs + (size_t)(2 * mm + mm * mm) * sizeof(double);
+    const bool fits = lds <= 49152;
+    hipLaunchKernelGGL(lanczos_sqrt_kernel, dim3(1), dim3(64), fits ? lds : coefs, h.stream,
+                       alpha, beta, mm, (const double *)bn, work, fits ? mm : ldz, coef,
+                       coef_prev, change, chg_hist, sel, coef_sel, (const double *)vn_hist,
+                       tol, j + 1 == M ? 1 : 0);
+    PSE_LAUNCH_CHECK();
+  }
+  gemv_small(h, V, n, M, coef_sel, y, n, 1.0, false, sel + 1);
+  hipLaunchKernelGGL(lanczos_stats_kernel, dim3(1), dim3(1), 0, h.stream, (const int *)sel,
+                     (const double *)chg_hist, h.dstats);
+  PSE_LAUNCH_CHECK();
+}
+
+void gmres_dev(Handle &h, const Op &A, const double *b, size_t n, double *x, int K,
+               double tol) {
+  const int R = K;
+  const int ldh = R + 1;
+  double *s = h.small;
+  double *H = s, *cs = H + (size_t)ldh * R, *sn = cs + (R + 1), *g = sn + (R + 1);
+  double *h1 = g + (R + 1), *h2 = h1 + (R + 1), *norm2 = h2 + (R + 1);
+  double *vnorm = norm2 + 1, *bn = vnorm + 1, *resid = bn + 1, *ycoef = resid + 1;
+  double *vn_hist = ycoef + (R + 1), *res_hist = vn_hist + (R + 1);
+  if ((size_t)(res_hist - s) + R + 8 > h.small_len)
+    throw Error{PSE_ERR_INVALID, "GMRES scratch too small"};
+  if ((size_t)R > (size_t)h.d.gmres_restart)
+    throw Error{PSE_ERR_INVALID, "GMRES basis smaller than its iteration count"};
+  int *sel = h.dctl + CTL_GM;
+  double *V = h.gm_V;
+  vzero(h, x, n);
+  norm2_dev(h, b, n, norm2);
+  hipLaunchKernelGGL(sqrt_kernel, dim3(1), dim3(1), 0, h.stream, norm2, bn);
+  PSE_LAUNCH_CHECK();
+  fill_int(h, sel, 3, 0);
+  vscale_dev(h, V, b, bn, true, n);
+  hipLaunchKernelGGL(set_g0_kernel, dim3(1), dim3(1), 0, h.stream, g, R + 1,
+                     (const double *)bn);
+  PSE_LAUNCH_CHECK();
+  for (int j = 0; j < R; ++j) {
+    double *w = V + (size_t)(j + 1) * n;
+    A(V + (size_t)j * n, w);
+    cgs2_pass(h, V, n, j + 1, w, h1, h2);
+    hipLaunchKernelGGL(hess_givens_kernel, dim3(1), dim3(64),
+                       (size_t)(3 * j + 2) * sizeof(double), h.stream, H, ldh, j, h1, h2, cs,
+                       sn, g, vnorm, resid, vn_hist, res_hist, sel, (const double *)bn, tol,
+                       j + 1 == R ? 1 : 0);
+    PSE_LAUNCH_CHECK();
+    sub_scale(h, w, V, n, j + 1, h2, vnorm);
+  }
+  hipLaunchKernelGGL(backsub_kernel, dim3(1), dim3(1), 0, h.stream, H, ldh, R, g, ycoef,
+                     (const int *)(sel + 1));
+  PSE_LAUNCH_CHECK();
+  gemv_small(h, V, n, R, ycoef, x, n, 1.0, true, sel + 1);
+  hipLaunchKernelGGL(gmres_stats_kernel, dim3(1), dim3(1), 0, h.stream, (const int *)sel,
+                     (const double *)res_hist, (const double *)bn, h.dstats);
+  PSE_LAUNCH_CHECK();
 }
 
 }  // namespace pse

@@ -102,12 +102,21 @@ void derive(const pse_params &p, pse_derived &d) {
   d.cells = (int)std::floor(L / d.rcut);
   if (d.cells < 3) fail("fewer than 3 cells per side");
   if (d.cells > 1024) d.cells = 1024;
-  d.lanczos_maxit = p.lanczos_maxit > 0 ? p.lanczos_maxit : 100;
   d.lanczos_tol = p.lanczos_tol > 0 ? p.lanczos_tol : 1e-3;
-  d.gmres_restart = p.gmres_restart > 0 ? p.gmres_restart : 30;
-  d.gmres_maxit = p.gmres_maxit > 0 ? p.gmres_maxit : 200;
   d.gmres_tol = p.gmres_tol > 0 ? p.gmres_tol : 1e-6;
-  d.refine_passes = p.refine_passes > 0 ? p.refine_passes : 3;
+  if (p.async_calls) {
+    // device-checked solves run exactly maxit iterations: modest defaults,
+    // and GMRES without restarts (its basis holds every iteration)
+    d.lanczos_maxit = p.lanczos_maxit > 0 ? p.lanczos_maxit : 16;
+    d.gmres_maxit = p.gmres_maxit > 0 ? p.gmres_maxit : 32;
+    d.gmres_restart = d.gmres_maxit;
+    d.refine_passes = p.refine_passes > 0 ? p.refine_passes : 1;
+  } else {
+    d.lanczos_maxit = p.lanczos_maxit > 0 ? p.lanczos_maxit : 100;
+    d.gmres_restart = p.gmres_restart > 0 ? p.gmres_restart : 30;
+    d.gmres_maxit = p.gmres_maxit > 0 ? p.gmres_maxit : 200;
+    d.refine_passes = p.refine_passes > 0 ? p.refine_passes : 3;
+  }
   if (d.lanczos_maxit > 500 || d.gmres_restart > 200)
     fail("Krylov basis limits too large");
 }
@@ -125,7 +134,7 @@ size_t footprint(const pse_params &p, const pse_derived &d) {
            + d.grid * sizeof(double2);
   if (mixed) bytes += 2 * MAX_PACK * ng3 * sizeof(float2) + d.grid * sizeof(float2);
   bytes += (size_t)(3 * (d.grid / 2) * (d.grid / 2) + 1) * 4 * sizeof(double);
-  bytes += pair_capacity(p, d) * (sizeof(int) + 10 * sizeof(double))
+  bytes += (p.async_calls ? 2 : 1) * pair_capacity(p, d) * (sizeof(int) + 10 * sizeof(double))
            + (2 * n + n / 1024 + 16) * sizeof(int);
   const size_t ntab = (size_t)(2048.0 * d.rcut / (2 * p.radius)) + 16;
   bytes += ntab * NCOEF * (sizeof(double) + sizeof(float));
@@ -144,7 +153,7 @@ size_t footprint(const pse_params &p, const pse_derived &d) {
   bytes += (size_t)(d.lanczos_maxit + 1) * NC * n * sizeof(double);
   bytes += (size_t)(d.gmres_restart + 1) * 5 * n * sizeof(double);
   const size_t small = 4 * (size_t)(d.gmres_restart + 2) * (d.gmres_restart + 2)
-                       + 8 * (size_t)(d.lanczos_maxit + 2) * (d.lanczos_maxit + 2) + 64;
+                       + 10 * (size_t)(d.lanczos_maxit + 2) * (d.lanczos_maxit + 2) + 64;
   bytes += small * sizeof(double);
   bytes += (size_t)4096 * (std::max(d.lanczos_maxit, d.gmres_restart) + 2) * sizeof(double);
   return bytes;

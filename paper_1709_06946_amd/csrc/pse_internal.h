@@ -187,11 +187,28 @@ struct Handle {
   std::string graph_error;   // why graphs were switched off after a failed capture
   std::map<std::tuple<const void *, const void *, int>, hipGraphExec_t> graphs;
 
+  // Asynchronous handles (params.async_calls): Krylov solves checked on the
+  // device, no host synchronisation inside a call.  dctl: device control
+  // words (CTL_*), dstats: the step statistics kept on the device, dstep:
+  // the device step counter used for step = PSE_STEP_DEVICE, counter_dev:
+  // that counter while a call uses it (else NULL).
+  bool async = false;
+  int lz_cap = 0, gm_cap = 0, ref_cap = 0;   // iterations / passes of those solves
+  int *dctl = nullptr;
+  pse_stats *dstats = nullptr;
+  uint64_t *dstep = nullptr;
+  const uint64_t *counter_dev = nullptr;
+
   // A handle with an arena takes every device buffer from it (bump
   // allocation, 256-byte aligned) instead of the runtime, and frees nothing.
   unsigned char *arena = nullptr;
   size_t arena_size = 0, arena_used = 0;
 };
+
+// Device control words of a handle (ints at h.dctl): Lanczos and GMRES
+// selection state (found, count, not converged), the status bits
+// (PSE_STATUS_*) of asynchronous calls.
+enum { CTL_LZ = 0, CTL_GM = 4, CTL_STATUS = 8, CTL_WORDS = 16 };
 
 // Device buffer of a handle: from its arena when it has one (throws
 // PSE_ERR_NOMEM when the arena is full), else from the runtime (dev_alloc).
@@ -386,6 +403,7 @@ void wrap_positions(Handle &h, const double *x, double *xw);
 
 // ---- krylov.hip / blas
 void vzero(Handle &h, double *v, size_t n);
+void fill_int(Handle &h, int *v, size_t n, int value);   // kernel, not a memset node
 void vcopy(Handle &h, double *dst, const double *src, size_t n);
 void vaxpby(Handle &h, double a, const double *x, double b, double *y, size_t n);
 void multi_dot(Handle &h, const double *V, size_t ldv, int m, const double *w,
@@ -394,7 +412,7 @@ void vsub_multi(Handle &h, double *w, const double *V, size_t ldv, int m,
                 const double *coef_dev, size_t n);
 void gemv_small(Handle &h, const double *V, size_t ldv, int m,
                 const double *coef_dev, double *y, size_t n, double alpha,
-                bool accumulate);
+                bool accumulate, const int *m_dev = nullptr);
 void vscale_dev(Handle &h, double *dst, const double *src, const double *s_dev,
                 bool invert, size_t n);
 void gather_comps(Handle &h, const double *src, int sstride, const CompSet &cs,
@@ -416,6 +434,13 @@ KrylovResult lanczos_sqrt(Handle &h, const Op &A, const double *b, size_t n,
                           double *y, int maxit, double tol, int *prev_iters);
 KrylovResult gmres(Handle &h, const Op &A, const double *b, size_t n, double *x,
                    int restart, int maxit, double tol, int *prev_iters);
+// Device-checked forms for asynchronous handles: exactly K iterations, the
+// result taken at the first one that met tol (no restarts); iteration
+// counts, residuals and convergence go to h.dstats.
+void lanczos_sqrt_dev(Handle &h, const Op &A, const double *b, size_t n, double *y, int K,
+                      double tol);
+void gmres_dev(Handle &h, const Op &A, const double *b, size_t n, double *x, int K,
+               double tol);
 
 // ---- grid.hip (noise)
 // N x ncomp standard normals (the first ncomp of each particle's Philox

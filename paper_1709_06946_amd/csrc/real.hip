@@ -168,12 +168,14 @@ void build_tables(Handle &h) {
 // Non-finite coordinates raise *bad and are replaced by 0, so that every
 // later kernel stays in bounds until the host reports the error.
 __global__ void wrap_kernel(const double *__restrict__ x, double *__restrict__ xw,
-                            int64_t n3, double L, int *__restrict__ bad) {
+                            int64_t n3, double L, int *__restrict__ bad,
+                            int *__restrict__ status) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n3) return;
   double v = x[i];
   if (!isfinite(v)) {
     *bad = 1;
+    atomicOr(status, (int)PSE_STATUS_NONFINITE_POS);
     v = 0.0;
   }
   v -= L * floor(v / L);
@@ -183,9 +185,11 @@ __global__ void wrap_kernel(const double *__restrict__ x, double *__restrict__ x
 }
 
 void wrap_positions(Handle &h, const double *x, double *xw) {
-  PSE_HIP(hipMemsetAsync(h.bad_pos, 0, sizeof(int), h.stream));
+  // the flag is cleared by a kernel, not a memset node, so that the launches
+  // can be captured into graphs
+  fill_int(h, h.bad_pos, 1, 0);
   hipLaunchKernelGGL(wrap_kernel, dim3(nblocks(3 * h.n, 256)), dim3(256), 0,
-                     h.stream, x, xw, 3 * h.n, h.p.box, h.bad_pos);
+                     h.stream, x, xw, 3 * h.n, h.p.box, h.bad_pos, h.dctl + CTL_STATUS);
   PSE_LAUNCH_CHECK();
 }
 
@@ -355,7 +359,7 @@ void exclusive_scan(Handle &h, const int *in, int *out, int *tmp, int n) {
 static void build_bins(Handle &h, const double *xw, Bins &b) {
   const int nc = b.nc;
   const int ncells = nc * nc * nc;
-  PSE_HIP(hipMemsetAsync(b.count, 0, ncells * sizeof(int), h.stream));
+  fill_int(h, b.count, ncells, 0);
   hipLaunchKernelGGL(cell_assign_kernel, dim3(nblocks(h.n, 256)), dim3(256), 0,
                      h.stream, xw, h.n, nc, nc / h.p.box, b.of, b.slot, b.count);
   PSE_LAUNCH_CHECK();
@@ -495,6 +499,8 @@ struct PairArgs {
   double L, rcut2;
   double inv_dr;
   int n2a, ntab;
+  int64_t cap;     // pair-list capacity: entries at or beyond it are not written
+  int *status;     // PSE_STATUS_PAIR_OVERFLOW is or-ed in when one is dropped
 };
 
 constexpr int PAIR_REC = 10;   // co[7], e[3]
@@ -546,8 +552,12 @@ pair_list_kernel(const double *__restrict__ xw, const int *__restrict__ perm,
       count += ok ? 1 : 0;
     } else {
       const unsigned long long m = __ballot(ok);
+      const int slot = pos + __popcll(m & ((1ull << lane) - 1ull));
+      if (ok && slot >= pa.cap) {
+        atomicOr(pa.status, (int)PSE_STATUS_PAIR_OVERFLOW);
+        ok = false;
+      }
       if (ok) {
-        const int slot = pos + __popcll(m & ((1ull << lane) - 1ull));
         nbr[slot] = j;
         const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
         double co[NCOEF];
@@ -575,6 +585,7 @@ struct RealArgs {
   int out_mask;   // 1: U, 2: Omega, 4: E
   int accumulate;
   Layout lin, lout;
+  int64_t cap;    // pair-list capacity (entries beyond it were never written)
 };
 
 // M_r applied from the pair list: the self block (r = 0: only the isotropic
@@ -601,7 +612,7 @@ real_pair_kernel(const double *__restrict__ in, double *__restrict__ out,
     load_moments<T>(in + (size_t)i * ra.lin.stride, ra.lin.off, ra.in_mask, F, C);
     pair_action<T>(co, e0, F, C, useF, useC, U, D);
   }
-  const int s1 = start[t + 1];
+  const int s1 = (int)min((int64_t)start[t + 1], ra.cap);
   for (int s = start[t] + lane; s < s1; s += GROUP) {
     const int j = nbr[s];
     const double *r = rec + (size_t)s * PAIR_REC;
@@ -653,6 +664,8 @@ static void build_pair_list(Handle &h, const double *xw) {
   pa.inv_dr = 1.0 / h.dr;
   pa.n2a = h.n2a;
   pa.ntab = h.ntab;
+  pa.cap = (int64_t)h.pl_cap;
+  pa.status = h.dctl + CTL_STATUS;
   const unsigned nb = nblocks((size_t)h.n * 64, 256);
   hipLaunchKernelGGL((pair_list_kernel<false>), dim3(nb), dim3(256), 0, h.stream, xw,
                      h.cells.perm, h.cells.start, h.cells.of, pa, h.pl_cnt, nullptr, nullptr,
@@ -660,6 +673,17 @@ static void build_pair_list(Handle &h, const double *xw) {
   PSE_LAUNCH_CHECK();
   const int n = (int)h.n;
   exclusive_scan(h, h.pl_cnt, h.pl_start, h.pl_scan, n);
+  if (h.async) {
+    // no host read: the list keeps its capacity, pairs beyond it are dropped
+    // and flagged in the device status (non-finite positions are flagged by
+    // the wrap kernel)
+    h.pl_pairs = h.pl_cap;
+    hipLaunchKernelGGL((pair_list_kernel<true>), dim3(nb), dim3(256), 0, h.stream, xw,
+                       h.cells.perm, h.cells.start, h.cells.of, pa, nullptr, h.pl_start,
+                       h.g64.table, h.pl_nbr, h.pl_rec);
+    PSE_LAUNCH_CHECK();
+    return;
+  }
   int total = 0, bad = 0;
   PSE_HIP(hipMemcpyAsync(&total, h.pl_start + n, sizeof(int), hipMemcpyDeviceToHost,
                          h.stream));
@@ -681,6 +705,7 @@ static void build_pair_list(Handle &h, const double *xw) {
     dev_alloc((void **)&h.pl_nbr, cap * sizeof(int));
     dev_alloc((void **)&h.pl_rec, cap * PAIR_REC * sizeof(double));
     h.pl_cap = cap;
+    pa.cap = (int64_t)cap;
   }
   h.pl_pairs = (size_t)total;
   hipLaunchKernelGGL((pair_list_kernel<true>), dim3(nb), dim3(256), 0, h.stream, xw,
@@ -723,6 +748,7 @@ void real_apply(Handle &h, const double *xw, const double *in, Layout lin, const
   ra.in_mask = mask_of(cin, true);
   ra.out_mask = mask_of(cout, false);
   ra.accumulate = accumulate ? 1 : 0;
+  ra.cap = (int64_t)h.pl_cap;
   const T *tab;
   if constexpr (sizeof(T) == 8) tab = h.g64.table; else tab = h.g32.table;
   ProfScope ps(h, PK_REAL, (double)h.pl_pairs * (PAIR_REC * 8 + 4 + NC * 8) +

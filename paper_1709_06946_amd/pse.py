@@ -13,6 +13,8 @@ LIB_PATH = os.path.join(HERE, 'libpse.so')
 PSE_OK, PSE_WARN_NOT_CONVERGED = 0, 1
 PSE_FP64, PSE_MIXED = 0, 1
 PSE_REAL, PSE_WAVE, PSE_ES_BLOCK = 1, 2, 4
+PSE_STATUS_NONFINITE_POS, PSE_STATUS_PAIR_OVERFLOW = 1, 2
+PSE_STEP_DEVICE = 2**64 - 1
 
 
 class pse_params(ctypes.Structure):
@@ -25,7 +27,8 @@ class pse_params(ctypes.Structure):
                 ('lanczos_tol', ctypes.c_double), ('gmres_restart', ctypes.c_int32),
                 ('gmres_maxit', ctypes.c_int32), ('gmres_tol', ctypes.c_double),
                 ('refine_passes', ctypes.c_int32), ('graphs', ctypes.c_int32),
-                ('deriv_gridding', ctypes.c_int32), ('stream', ctypes.c_void_p)]
+                ('deriv_gridding', ctypes.c_int32), ('stream', ctypes.c_void_p),
+                ('async_calls', ctypes.c_int32)]
 
 
 class pse_derived(ctypes.Structure):
@@ -43,7 +46,8 @@ class pse_stats(ctypes.Structure):
     _fields_ = [('lanczos_iters', ctypes.c_int32), ('gmres_iters', ctypes.c_int32),
                 ('refine_passes', ctypes.c_int32), ('converged', ctypes.c_int32),
                 ('lanczos_change', ctypes.c_double), ('gmres_residual', ctypes.c_double),
-                ('fp64_residual', ctypes.c_double)]
+                ('fp64_residual', ctypes.c_double), ('status', ctypes.c_int32),
+                ('reserved', ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -98,7 +102,9 @@ EXPORTS = ('pse_derive', 'pse_footprint_bytes', 'pse_create', 'pse_destroy',
            'pse_spread', 'pse_interpolate',
            'pse_profile', 'pse_profile_read', 'pse_server_create', 'pse_server_submit',
            'pse_server_wait', 'pse_server_result', 'pse_server_release', 'pse_server_stats',
-           'pse_server_destroy', 'pse_server_error', 'pse_last_error')
+           'pse_server_destroy', 'pse_server_error', 'pse_last_error', 'pse_set_krylov',
+           'pse_synchronize', 'pse_step_graph_create', 'pse_step_graph_launch',
+           'pse_step_graph_destroy')
 
 
 def load_library(path=LIB_PATH):
@@ -122,13 +128,14 @@ def load_library(path=LIB_PATH):
     lib.pse_get_derived.argtypes = [V, P(pse_derived)]
     lib.pse_mobility_apply.argtypes = [V, V, V, V, ctypes.c_uint]
     lib.pse_mobility_apply_noalloc.argtypes = [P(pse_params), V, V, V, ctypes.c_uint]
+    # (statistics: host memory, or device-writable memory for asynchronous handles)
     lib.pse_brownian_sample.argtypes = [V, V, V, V, ctypes.c_uint64, ctypes.c_uint64,
-                                        V, V, P(pse_stats)]
+                                        V, V, V]
     lib.pse_constrained_step.argtypes = [V, V, V, ctypes.c_double, ctypes.c_uint64,
-                                         ctypes.c_uint64, P(pse_step_io), P(pse_stats)]
+                                         ctypes.c_uint64, P(pse_step_io), V]
     lib.pse_rpy_apply.argtypes = [V, V, V, V, ctypes.c_uint]
     lib.pse_rpy_step.argtypes = [V, V, V, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64,
-                                 P(pse_step_io), P(pse_stats)]
+                                 P(pse_step_io), V]
     lib.pse_fft3d.argtypes = [V, V, I, I]
     lib.pse_rfft3d.argtypes = [V, V, I, I]
     lib.pse_spread.argtypes = [V, V, V, I, V]
@@ -144,6 +151,12 @@ def load_library(path=LIB_PATH):
     lib.pse_server_destroy.argtypes = [V]
     lib.pse_server_error.argtypes = [V, ctypes.c_int64]
     lib.pse_server_error.restype = ctypes.c_char_p
+    lib.pse_set_krylov.argtypes = [V, I, I, I, I, ctypes.c_uint64]
+    lib.pse_synchronize.argtypes = [V]
+    lib.pse_step_graph_create.argtypes = [V, V, V, ctypes.c_double, ctypes.c_uint64, I, V,
+                                          P(V)]
+    lib.pse_step_graph_launch.argtypes = [V]
+    lib.pse_step_graph_destroy.argtypes = [V]
     lib.pse_last_error.argtypes = [V]
     lib.pse_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
@@ -169,12 +182,13 @@ class PSEError(RuntimeError):
 def make_params(n, box, *, radius=1.0, viscosity=1.0, kT=1.0, tol=1e-3, grid=0,
                 support=0, xi=0.0, rcut=0.0, precision=PSE_FP64, lanczos_maxit=0,
                 lanczos_tol=0.0, gmres_restart=0, gmres_maxit=0, gmres_tol=0.0,
-                refine_passes=0, graphs=0, deriv_gridding=0, stream=None):
+                refine_passes=0, graphs=0, deriv_gridding=0, stream=None, async_calls=0):
     return pse_params(int(n), float(box), float(radius), float(viscosity), float(kT),
                       float(tol), int(grid), int(support), float(xi), float(rcut),
                       int(precision), int(lanczos_maxit), float(lanczos_tol),
                       int(gmres_restart), int(gmres_maxit), float(gmres_tol),
-                      int(refine_passes), int(graphs), int(deriv_gridding), stream)
+                      int(refine_passes), int(graphs), int(deriv_gridding), stream,
+                      int(async_calls))
 
 
 def derive(params):
@@ -238,11 +252,22 @@ def _sync():
 
 
 class PSE:
-    """One library handle (one particle count, box and parameter set)."""
+    """One library handle (one particle count, box and parameter set).
+
+    async_calls=1 makes an asynchronous handle: calls only enqueue work on
+    the handle's stream (pass stream=<torch.cuda.Stream>.cuda_stream to order
+    it with torch's work on that stream), so they can be captured into a
+    graph; step statistics go to a pinned host buffer, read by stats()."""
 
     def __init__(self, n, box, **kw):
         self.params = make_params(n, box, **kw)
         self.n = int(n)
+        self.async_calls = bool(kw.get('async_calls', 0))
+        self._stats_buf = None
+        if self.async_calls:
+            import torch
+            self._stats_buf = torch.zeros(ctypes.sizeof(pse_stats), dtype=torch.uint8,
+                                          pin_memory=True)
         h = ctypes.c_void_p()
         rc = lib().pse_create(ctypes.byref(self.params), ctypes.byref(h))
         if rc != PSE_OK:
@@ -278,28 +303,69 @@ class PSE:
     def brownian_sample(self, x, psi_real=None, psi_wave=None, seed=0, counter=0,
                         out_real=None, out_wave=None):
         n, g = self.n, self.derived.grid
-        _sync()
-        st = pse_stats()
+        if not self.async_calls:
+            _sync()
+        arg, st = self._stats_arg()
         rc = self._check(lib().pse_brownian_sample(
             self._h, _ptr(x, (n, 3), 'x'), _ptr(psi_real, (n, 11), 'psi_real'),
             _ptr(psi_wave, (3, g, g, g // 2 + 1), 'psi_wave', 'complex128'), seed, counter,
             _ptr(out_real, (n, 11), 'out_real'), _ptr(out_wave, (n, 11), 'out_wave'),
-            ctypes.byref(st)), 'pse_brownian_sample')
-        return rc, st.as_dict()
+            arg), 'pse_brownian_sample')
+        return rc, (st.as_dict() if st is not None else None)
+
+    def _stats_arg(self):
+        """(argument, host struct): a host struct for synchronous handles, the
+        pinned buffer for asynchronous ones (written by the device)."""
+        if self.async_calls:
+            return ctypes.c_void_p(self._stats_buf.data_ptr()), None
+        st = pse_stats()
+        return ctypes.cast(ctypes.pointer(st), ctypes.c_void_p), st
+
+    def stats(self):
+        """Statistics of the last asynchronous call, once the device has
+        finished it (synchronises the device)."""
+        import torch
+        torch.cuda.synchronize()
+        return pse_stats.from_buffer_copy(bytes(self._stats_buf.numpy())).as_dict()
 
     def constrained_step(self, x, FL=None, dt=1e-3, seed=0, step=0, psi_real=None,
                          psi_wave=None, slip=None, stresslet=None, velocity=None):
+        """One step; returns (status, stats) -- stats None for asynchronous
+        handles (see stats())."""
         n, g = self.n, self.derived.grid
-        _sync()
+        if not self.async_calls:
+            _sync()
         io = pse_step_io(_ptr(psi_real, (n, 11), 'psi_real'),
                          _ptr(psi_wave, (3, g, g, g // 2 + 1), 'psi_wave', 'complex128'),
                          _ptr(slip, (n, 11), 'slip'), _ptr(stresslet, (n, 5), 'stresslet'),
                          _ptr(velocity, (n, 3), 'velocity'))
-        st = pse_stats()
+        arg, st = self._stats_arg()
         rc = self._check(lib().pse_constrained_step(
             self._h, _ptr(x, (n, 3), 'x'), _ptr(FL, (n, 6), 'FL'), float(dt), seed, step,
-            ctypes.byref(io), ctypes.byref(st)), 'pse_constrained_step')
-        return rc, st.as_dict()
+            ctypes.byref(io), arg), 'pse_constrained_step')
+        return rc, (st.as_dict() if st is not None else None)
+
+    def set_krylov(self, async_calls, lanczos_iters=1, gmres_iters=1, refine_passes=1,
+                   next_step=0):
+        """Switch the live handle between synchronous and asynchronous calls
+        (pse_set_krylov); an asynchronous handle's statistics go to a pinned
+        buffer read by stats()."""
+        if async_calls and self._stats_buf is None:
+            import torch
+            self._stats_buf = torch.zeros(ctypes.sizeof(pse_stats), dtype=torch.uint8,
+                                          pin_memory=True)
+        self._check(lib().pse_set_krylov(self._h, int(async_calls), int(lanczos_iters),
+                                         int(gmres_iters), int(refine_passes),
+                                         int(next_step)), 'pse_set_krylov')
+        self.async_calls = bool(async_calls)
+
+    def synchronize(self):
+        self._check(lib().pse_synchronize(self._h), 'pse_synchronize')
+
+    def step_graph(self, x, FL=None, dt=1e-3, seed=0, steps=1):
+        """StepGraph of `steps` captured constrained steps (asynchronous
+        handle on its own stream; x updated in place by every launch)."""
+        return StepGraph(self, x, FL, dt, seed, steps)
 
     def rpy_apply(self, x, F, out, parts=PSE_REAL | PSE_WAVE):
         """out = M_UF F (the RPY-level product; F, out of shape (N, 3))."""
@@ -313,15 +379,16 @@ class PSE:
                  slip=None, velocity=None):
         """One unconstrained RPY-level Euler-Maruyama step (x updated in place)."""
         n, g = self.n, self.derived.grid
-        _sync()
+        if not self.async_calls:
+            _sync()
         io = pse_step_io(_ptr(psi_real, (n, 3), 'psi_real'),
                          _ptr(psi_wave, (3, g, g, g // 2 + 1), 'psi_wave', 'complex128'),
                          _ptr(slip, (n, 3), 'slip'), None, _ptr(velocity, (n, 3), 'velocity'))
-        st = pse_stats()
+        arg, st = self._stats_arg()
         rc = self._check(lib().pse_rpy_step(
             self._h, _ptr(x, (n, 3), 'x'), _ptr(F, (n, 3), 'F'), float(dt), seed, step,
-            ctypes.byref(io), ctypes.byref(st)), 'pse_rpy_step')
-        return rc, st.as_dict()
+            ctypes.byref(io), arg), 'pse_rpy_step')
+        return rc, (st.as_dict() if st is not None else None)
 
     def profile(self, enable):
         return self._check(lib().pse_profile(self._h, int(bool(enable))), 'pse_profile')
@@ -368,6 +435,37 @@ class PSE:
                                                  _ptr(grids, (nc, g, g, g), 'grids'), nc,
                                                  _ptr(out, (n, nc), 'out')),
                            'pse_interpolate')
+
+
+class StepGraph:
+    """Graph-captured constrained steps of an asynchronous handle
+    (pse_step_graph_*): launch() enqueues one replay on the handle's stream."""
+
+    def __init__(self, handle, x, FL, dt, seed, steps):
+        n = handle.n
+        _sync()
+        self.handle = handle
+        self._keep = (x, FL)
+        g = ctypes.c_void_p()
+        handle._check(lib().pse_step_graph_create(
+            handle._h, _ptr(x, (n, 3), 'x'), _ptr(FL, (n, 6), 'FL'), float(dt), seed,
+            int(steps), ctypes.c_void_p(handle._stats_buf.data_ptr()), ctypes.byref(g)),
+            'pse_step_graph_create')
+        self._g = g
+
+    def launch(self):
+        self.handle._check(lib().pse_step_graph_launch(self._g), 'pse_step_graph_launch')
+
+    def close(self):
+        if getattr(self, '_g', None):
+            lib().pse_step_graph_destroy(self._g)
+            self._g = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class PSEServer:

@@ -1,6 +1,8 @@
 """Served form: requests of different N and volume fraction admitted by
-device footprint onto one GPU, running concurrently.  Each request's result
-is the same alone and in the mix."""
+device footprint onto one GPU, running concurrently (after a synchronous
+first step, each request's steps are replays of one captured graph of the
+whole step).  Each request's result is the same alone and in the mix, bit
+for bit: nothing in a request's work depends on the others."""
 import numpy as np
 import pytest
 
@@ -20,10 +22,10 @@ def _requests():
     return out
 
 
-def _run(server, reqs, steps=4):
+def _run(server, reqs, precision, steps=4):
     from paper_1709_06946_amd import pse
     ids = [server.submit(x, L, FL=FL, steps=steps, seed=seed, grid=pse.grid_for(L),
-                         gmres_tol=1e-10, lanczos_tol=1e-8)
+                         gmres_tol=1e-6, lanczos_tol=1e-3, precision=precision)
            for x, L, FL, seed in reqs]
     res = []
     for rid in ids:
@@ -33,18 +35,19 @@ def _run(server, reqs, steps=4):
     return res
 
 
-def test_alone_equals_mix_and_budget_respected():
+@pytest.mark.parametrize('precision', [0, 1])
+def test_alone_equals_mix_and_budget_respected(precision):
     from paper_1709_06946_amd import pse
     reqs = _requests()
     alone = []
     s1 = pse.PSEServer(max_active=1)
     for r in reqs:
-        alone.append(_run(s1, [r])[0])
+        alone.append(_run(s1, [r], precision)[0])
     s1.close()
     sizes = sorted(i[0]['bytes'] for i in alone)
     budget = sizes[-1] + sizes[-2] + sizes[0]          # at most ~3 at once
     s2 = pse.PSEServer(budget_bytes=budget, max_active=4)
-    mix = _run(s2, reqs)
+    mix = _run(s2, reqs, precision)
     st = s2.stats()
     s2.close()
     assert st['completed'] == len(reqs) and st['failed'] == 0
@@ -58,7 +61,7 @@ def test_alone_equals_mix_and_budget_respected():
         dm -= L * np.rint(dm / L)
         err = np.abs(da - dm).max() / np.abs(da).max()
         print(len(x0), 'alone vs mix', err, 'latency ms', np.round(lm, 2))
-        assert err < 1e-6
+        assert np.array_equal(xa, xm), err
         assert len(lm) == 4 and np.all(lm > 0)
     # requests overlapped in time on the device
     spans = sorted((i['t_admit'], i['t_done']) for i, _, _ in mix)
