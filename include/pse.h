@@ -128,6 +128,16 @@ typedef struct pse_params {
                               written by the device (see pse_constrained_step);
                               the pair list keeps its creation capacity (pairs
                               beyond it are dropped and flagged). */
+  double deform[9];        /* volume-preserving deformation A of the periodic
+                              lattice (Sec. II.C.2), row-major; all zero =
+                              the cube.  The lattice vectors are the columns
+                              of L A (Lees-Edwards shear: A = [[1, gamma, 0],
+                              [0, 1, 0], [0, 0, 1]]; planar extension:
+                              diag(e, 1/e, 1)); det A must be 1.  The FFT
+                              grid is the deformed lattice's, the Gaussian
+                              support grows with lambda_max, the largest
+                              eigenvalue of A^T A (Eq. bound), and the
+                              constraint operator grids its five moments. */
 } pse_params;
 
 /* Derived quantities (Sec. II.C, Eq. bound and the Sec. II.C.1 cutoff). */
@@ -144,6 +154,7 @@ typedef struct pse_derived {
   double lanczos_tol, gmres_tol;
   int32_t deriv_gridding;  /* gridding of M_ES in effect: 1 moments, 2
                               derivative                                     */
+  double lambda_max;       /* largest eigenvalue of A^T A (1 for the cube)   */
 } pse_derived;
 
 /* Krylov statistics of a step.  Synchronous handles write them to host
@@ -192,8 +203,14 @@ typedef struct pse_handle pse_handle;
  * With these rules every block of the mobility product and of the wave-space
  * square root is within eps of the exact sums at eps = 1e-3 (checked against
  * the oracle).
+ * Deformed lattices (params.deform): P = ceil(lambda_max (2/pi) ln(40/eps))
+ * (Eq. bound: both error terms decay as exp(-pi P / (2 lambda_max)) at
+ * m = sqrt(pi P), which needs lambda_max times the support for the same
+ * error), xi divided by sqrt(lambda_max) (the shortest Nyquist wave vector of
+ * the deformed reciprocal lattice is that much shorter), cells of the
+ * real-space list from the cell's thinnest width.
  * Returns PSE_ERR_INVALID for inconsistent parameters (eta_s >= 1,
- * rcut > L/3, unsupported Ng, ...). */
+ * rcut > L/3, unsupported Ng, det A != 1, ...). */
 int pse_derive(const pse_params *p, pse_derived *out);
 
 /* Device bytes a handle with these parameters would allocate (host only). */

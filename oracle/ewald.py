@@ -2,8 +2,12 @@
 
 Test infrastructure only.
 
-Cubic periodic box of side L, V = L^3.  All matrices are 11N x 11N in the
-stored coordinates of conventions.py, particle-major (row 11*alpha + c).
+Periodic box of side L, V = L^3, optionally deformed (Sec. II.C.2): with a
+volume-preserving deformation A (det A = 1), the lattice vectors are the
+columns of L A, the reciprocal vectors k = (2 pi / L) A^-T n (n integer) and
+the real-space images x + L A n.  A = None is the cube.  All matrices are
+11N x 11N in the stored coordinates of conventions.py, particle-major (row
+11*alpha + c).
 
 * Wave space (Eqs. MUFw-MDCw, WSops): for every reciprocal lattice vector
   k = 2 pi n / L, n != 0,
@@ -31,6 +35,32 @@ R_TAIL = 6.5          # real sum truncated at r - 2a = R_TAIL / xi
 
 
 # ----------------------------------------------------------------- k-space --
+
+def _deformation(A):
+    """(A, A^-1) with det A = 1 checked; identity for None."""
+    if A is None:
+        return np.eye(3), np.eye(3)
+    A = np.asarray(A, np.float64)
+    if abs(np.linalg.det(A) - 1.0) > 1e-12:
+        raise ValueError('the lattice deformation must preserve volume (det A = 1)')
+    return A, np.linalg.inv(A)
+
+
+def wave_vectors(L, kmax, A=None):
+    """Half-space reciprocal vectors k = (2 pi / L) A^-T n, n != 0, |k| <= kmax
+    (n in the half space of half_space_lattice), as rows (K, 3)."""
+    if A is None:
+        return 2 * np.pi / L * half_space_lattice(L, kmax)
+    A, Ai = _deformation(A)
+    # |n| = |A^T k| L / 2 pi <= |A^T| kmax L / 2 pi
+    nmax = int(np.floor(np.linalg.norm(A, 2) * kmax * L / (2 * np.pi))) + 1
+    g = np.arange(-nmax, nmax + 1)
+    n = np.stack(np.meshgrid(g, g, g, indexing='ij'), -1).reshape(-1, 3)
+    keep = ((n[:, 0] > 0) | ((n[:, 0] == 0) & (n[:, 1] > 0))
+            | ((n[:, 0] == 0) & (n[:, 1] == 0) & (n[:, 2] > 0)))
+    k = 2 * np.pi / L * (n[keep] @ Ai)        # rows: (A^-T n)^T = n^T A^-1
+    return k[(k**2).sum(1) <= kmax**2]
+
 
 def half_space_lattice(L, kmax):
     """Integer vectors n != 0 with |2 pi n / L| <= kmax in one half space
@@ -65,15 +95,15 @@ def wave_weight(kvec, xi, eta):
     return pf.hasimoto_H(np.sqrt(k2), xi) / (eta * k2)
 
 
-def wave_dense(x, L, xi, a=1.0, eta=1.0, kvec=None, chunk=2048):
+def wave_dense(x, L, xi, a=1.0, eta=1.0, kvec=None, chunk=2048, A=None):
     """Dense M_w (11N x 11N).  kvec: optional explicit half-space k set
-    (default: every lattice vector up to the truncation)."""
+    (default: every lattice vector of the (deformed) lattice up to the
+    truncation)."""
     x = np.asarray(x, np.float64)
     N = x.shape[0]
     V = L**3
     if kvec is None:
-        n = half_space_lattice(L, 2 * xi * np.sqrt(U_MAX))
-        kvec = 2 * np.pi / L * n
+        kvec = wave_vectors(L, 2 * xi * np.sqrt(U_MAX), A)
     M = np.zeros((11 * N, 11 * N))
     for s0 in range(0, kvec.shape[0], chunk):
         kv = kvec[s0:s0 + chunk]
@@ -89,14 +119,13 @@ def wave_dense(x, L, xi, a=1.0, eta=1.0, kvec=None, chunk=2048):
     return M
 
 
-def wave_apply(x, q, L, xi, a=1.0, eta=1.0, kvec=None, chunk=4096):
+def wave_apply(x, q, L, xi, a=1.0, eta=1.0, kvec=None, chunk=4096, A=None):
     """Matrix-free M_w q for q of shape (N, 11) (direct k-sum)."""
     x = np.asarray(x, np.float64)
     q = np.asarray(q, np.float64)
     V = L**3
     if kvec is None:
-        n = half_space_lattice(L, 2 * xi * np.sqrt(U_MAX))
-        kvec = 2 * np.pi / L * n
+        kvec = wave_vectors(L, 2 * xi * np.sqrt(U_MAX), A)
     out = np.zeros_like(q)
     for s0 in range(0, kvec.shape[0], chunk):
         kv = kvec[s0:s0 + chunk]
@@ -112,17 +141,41 @@ def wave_apply(x, q, L, xi, a=1.0, eta=1.0, kvec=None, chunk=4096):
 
 # -------------------------------------------------------------- real space --
 
-def image_pairs(x, L, rcut):
-    """All (alpha, beta, separation) with |x_a - x_b + L n| < rcut over the
+def image_shifts(L, rcut, A=None):
+    """Lattice vectors L A n (rows) covering every image within rcut of a
+    separation already reduced to the cell around the origin."""
+    if A is None:
+        nimg = int(np.ceil(rcut / L)) + 1
+        g = np.arange(-nimg, nimg + 1)
+        return L * np.stack(np.meshgrid(g, g, g, indexing='ij'), -1).reshape(-1, 3)
+    A, Ai = _deformation(A)
+    # the cell's thinnest width is L / max_i |row i of A^-1|
+    width = L / np.sqrt((Ai**2).sum(1)).max()
+    nimg = int(np.ceil(rcut / width)) + 1
+    g = np.arange(-nimg, nimg + 1)
+    n = np.stack(np.meshgrid(g, g, g, indexing='ij'), -1).reshape(-1, 3)
+    return L * n @ A.T
+
+
+def reduce_image(d, L, A=None):
+    """Separations (rows) reduced to the lattice cell around the origin: the
+    lattice coordinates s = A^-1 d / L taken in [-1/2, 1/2)."""
+    if A is None:
+        return d - L * np.rint(d / L)
+    A, Ai = _deformation(A)
+    s = d @ Ai.T / L
+    s -= np.rint(s)
+    return L * s @ A.T
+
+
+def image_pairs(x, L, rcut, A=None):
+    """All (alpha, beta, separation) with |x_a - x_b + L A n| < rcut over the
     periodic lattice, alpha <= beta, including alpha == beta (n = 0 too)."""
     x = np.asarray(x, np.float64)
     N = x.shape[0]
-    nimg = int(np.ceil(rcut / L)) + 1
-    g = np.arange(-nimg, nimg + 1)
-    shifts = L * np.stack(np.meshgrid(g, g, g, indexing='ij'), -1).reshape(-1, 3)
+    shifts = image_shifts(L, rcut, A)
     ia, ib = np.triu_indices(N)
-    d = x[ia] - x[ib]
-    d -= L * np.rint(d / L)
+    d = reduce_image(x[ia] - x[ib], L, A)
     out_a, out_b, out_r = [], [], []
     for sh in shifts:
         rr = d + sh
@@ -158,13 +211,13 @@ def real_cutoff(xi, a):
     return 2.0 * a + R_TAIL / xi
 
 
-def real_dense(x, L, xi, a=1.0, eta=1.0, rcut=None):
+def real_dense(x, L, xi, a=1.0, eta=1.0, rcut=None, A=None):
     """Dense M_r (11N x 11N) by lattice image sum (Eq. pairsums)."""
     x = np.asarray(x, np.float64)
     N = x.shape[0]
     if rcut is None:
         rcut = real_cutoff(xi, a)
-    ia, ib, rv = image_pairs(x, L, rcut)
+    ia, ib, rv = image_pairs(x, L, rcut, A)
     B = pair_blocks(rv, xi, a, eta, 'real')
     M = np.zeros((N, 11, N, 11))
     for p in range(ia.size):
@@ -176,13 +229,13 @@ def real_dense(x, L, xi, a=1.0, eta=1.0, rcut=None):
     return M.reshape(11 * N, 11 * N)
 
 
-def real_apply(x, q, L, xi, a=1.0, eta=1.0, rcut=None):
+def real_apply(x, q, L, xi, a=1.0, eta=1.0, rcut=None, A=None):
     """Matrix-free M_r q for q of shape (N, 11)."""
     x = np.asarray(x, np.float64)
     q = np.asarray(q, np.float64)
     if rcut is None:
         rcut = real_cutoff(xi, a)
-    ia, ib, rv = image_pairs(x, L, rcut)
+    ia, ib, rv = image_pairs(x, L, rcut, A)
     B = pair_blocks(rv, xi, a, eta, 'real')
     out = np.zeros_like(q)
     np.add.at(out, ia, np.einsum('pij,pj->pi', B, q[ib]))
@@ -217,6 +270,6 @@ def real_apply_rows(x, q, L, xi, rows, a=1.0, eta=1.0, rcut=None):
     return out
 
 
-def grand_dense(x, L, xi, a=1.0, eta=1.0):
+def grand_dense(x, L, xi, a=1.0, eta=1.0, A=None):
     """Full grand mobility M = M_w + M_r (independent of xi)."""
-    return wave_dense(x, L, xi, a, eta) + real_dense(x, L, xi, a, eta)
+    return wave_dense(x, L, xi, a, eta, A=A) + real_dense(x, L, xi, a, eta, A=A)

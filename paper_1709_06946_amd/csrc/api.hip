@@ -36,19 +36,34 @@ template <> GridSet<float> &grids<float>(Handle &h) { return h.g32; }
 
 // ------------------------------------------------------- small kernels --
 
-// x_half = wrap(x + c * slip_U)
+// out = wrap(x + c v) for wrapped positions x and velocities v (rows of
+// stride vstride).  Deformed lattices: x in lattice coordinates, the step
+// c A^-1 v taken there and wrapped; out in lattice coordinates (cartesian =
+// 0, the library's mid-point) or mapped back by A (cartesian = 1, the
+// caller's positions).
 __global__ void advance_kernel(const double *__restrict__ x, const double *__restrict__ v,
                                int vstride, double c, int64_t n, double L,
-                               double *__restrict__ out) {
+                               double *__restrict__ out, Deform df, int cartesian) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  for (int d = 0; d < 3; ++d) {
-    double y = x[3 * i + d] + c * v[i * vstride + d];
-    y -= L * floor(y / L);
-    if (y >= L) y -= L;
-    if (y < 0) y = 0;
-    out[3 * i + d] = y;
+  double dv[3] = {v[i * vstride], v[i * vstride + 1], v[i * vstride + 2]};
+  if (df.on) {
+    const double e[3] = {dv[0], dv[1], dv[2]};
+    for (int r = 0; r < 3; ++r)
+      dv[r] = df.Ai[3 * r] * e[0] + df.Ai[3 * r + 1] * e[1] + df.Ai[3 * r + 2] * e[2];
   }
+  double y[3];
+  for (int d = 0; d < 3; ++d) {
+    double t = x[3 * i + d] + c * dv[d];
+    t -= L * floor(t / L);
+    if (t >= L) t -= L;
+    if (t < 0) t = 0;
+    y[d] = t;
+  }
+  for (int d = 0; d < 3; ++d)
+    out[3 * i + d] = (df.on && cartesian)
+                         ? df.A[3 * d] * y[0] + df.A[3 * d + 1] * y[1] + df.A[3 * d + 2] * y[2]
+                         : y[d];
 }
 
 // slip = c (y1 + y2) on U and E components, Omega from y1 alone is not
@@ -182,6 +197,16 @@ static void wave_apply(Handle &h, const double *xw, const double *in, Layout lin
                        bool accumulate) {
   GridSet<T> &G = grids<T>(h);
   T *gin = reinterpret_cast<T *>(G.gin), *gout = reinterpret_cast<T *>(G.gout);
+  if (h.def.on) {
+    // deformed lattice: full 3D transforms around a k-space kernel that
+    // forms each mode's wave vector and radial factors itself
+    spread<T>(h, xw, in, lin, cin, gin);
+    rfft3d<T>(h, gin, G.twiddle, cin.n, -1);
+    kspace_deformed<T>(h, G.gin, cin, G.gout, cout);
+    rfft3d<T>(h, gout, G.twiddle, cout.n, +1);
+    interpolate<T>(h, xw, gout, cout, out, lout, accumulate, 1.0);
+    return;
+  }
   spread<T>(h, xw, in, lin, cin, gin);
   rfft_xy<T>(h, gin, G.twiddle, cin.n, -1);
   kspace_fused<T>(h, G.gin, cin, G.gout, cout, G.twiddle);
@@ -538,6 +563,7 @@ static void create(const pse_params &p, Handle &h) {
   h.mixed = p.precision == PSE_MIXED;
   h.use_graphs = p.graphs >= 0;
   h.async = p.async_calls != 0;
+  deformation(p, h.def);
   h.lz_cap = h.d.lanczos_maxit;
   h.gm_cap = h.d.gmres_maxit;
   h.ref_cap = h.d.refine_passes;
@@ -545,7 +571,9 @@ static void create(const pse_params &p, Handle &h) {
   h.cells.nc = h.d.cells;
   // spreading tiles of stile^3 grid points gather from the 27 neighbouring
   // tiles, so a stencil (P points) must not reach beyond one tile.
-  h.stile = spread_tile(h.d.grid, h.d.support);
+  // (deformed lattices spread with atomics: the Gaussian does not factorise
+  // over the lattice axes, which the tile records rely on)
+  h.stile = h.def.on ? 0 : spread_tile(h.d.grid, h.d.support);
   h.sbins.nc = h.stile ? h.d.grid / h.stile : 0;
   h.deriv = h.d.deriv_gridding == 2;
   if (p.stream || h.arena) {
@@ -1022,7 +1050,7 @@ int pse_constrained_step(pse_handle *hd, double *x, const double *FL, double dt,
     PSE_LAUNCH_CHECK();
     // 2. mid-point
     hipLaunchKernelGGL(advance_kernel, dim3(nblocks(n, 256)), dim3(256), 0, h.stream, h.xw,
-                       slip, NC, 0.5 * dt, n, h.p.box, h.xh);
+                       slip, NC, 0.5 * dt, n, h.p.box, h.xh, h.def, 0);
     PSE_LAUNCH_CHECK();
     build_cells(h, h.xh);
     // 3. constraint at the mid-point: M_ES S = -E^B - M_EF F^P
@@ -1050,7 +1078,7 @@ int pse_constrained_step(pse_handle *hd, double *x, const double *FL, double dt,
     PSE_LAUNCH_CHECK();
     // 4. x_{k+1} = x_k + dt U
     hipLaunchKernelGGL(advance_kernel, dim3(nblocks(n, 256)), dim3(256), 0, h.stream, h.xw,
-                       U, 3, dt, n, h.p.box, x);
+                       U, 3, dt, n, h.p.box, x, h.def, 1);
     PSE_LAUNCH_CHECK();
     if (io) {
       if (io->slip) PSE_HIP(hipMemcpyAsync(io->slip, slip, NC * n * sizeof(double),
@@ -1153,7 +1181,7 @@ int pse_rpy_step(pse_handle *hd, double *x, const double *F, double dt, uint64_t
                        std::sqrt(2.0 * h.p.kT / dt), 3 * n, slip, U);
     PSE_LAUNCH_CHECK();
     hipLaunchKernelGGL(advance_kernel, dim3(nblocks(n, 256)), dim3(256), 0, h.stream, h.xw,
-                       U, 3, dt, n, h.p.box, x);
+                       U, 3, dt, n, h.p.box, x, h.def, 1);
     PSE_LAUNCH_CHECK();
     if (io) {
       if (io->slip) PSE_HIP(hipMemcpyAsync(io->slip, slip, 3 * n * sizeof(double),

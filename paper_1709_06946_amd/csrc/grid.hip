@@ -62,7 +62,8 @@ spread_kernel(const double *__restrict__ x, const double *__restrict__ q,
     const double dx = (ix0 + a) * g.h - px;
     const double dy = (iy0 + b) * g.h - py;
     const double dz = (iz0 + c) * g.h - pz;
-    const T w = (T)(kn3 * exp(-g.kcoef * (dx * dx + dy * dy + dz * dz)));
+    const double r2 = g.def ? qform(g.G, dx, dy, dz) : dx * dx + dy * dy + dz * dz;
+    const T w = (T)(kn3 * exp(-g.kcoef * r2));
     const size_t gi = ((size_t)wrapi(iz0 + c, g.ng) * g.ng + wrapi(iy0 + b, g.ng)) * g.ng
                       + wrapi(ix0 + a, g.ng);
 #pragma unroll
@@ -462,7 +463,8 @@ interp_kernel(const double *__restrict__ x, const T *__restrict__ grids,
       const double dx = (ix0 + a) * g.h - px;
       const double dy = (iy0 + b) * g.h - py;
       const double dz = (iz0 + c) * g.h - pz;
-      const T w = (T)(kn3 * exp(-g.kcoef * (dx * dx + dy * dy + dz * dz)));
+      const double r2 = g.def ? qform(g.G, dx, dy, dz) : dx * dx + dy * dy + dz * dz;
+      const T w = (T)(kn3 * exp(-g.kcoef * r2));
       const size_t gi = ((size_t)wrapi(iz0 + c, g.ng) * g.ng + wrapi(iy0 + b, g.ng)) * g.ng
                         + wrapi(ix0 + a, g.ng);
 #pragma unroll
@@ -524,7 +526,16 @@ struct KGeom {
   double one_m_etas;  // 1 - eta_s
   double pref_m;      // mobility: h^6 / (V eta)
   double pref_n;      // noise: h^3 / sqrt(V eta)
+  int def;            // deformed lattice: k = (2 pi / L) A^-T n
+  double Ai[9];       // A^-1 (row-major)
 };
+
+// Wave vector of the integer index (i, j, l): (2 pi / L) A^-T (i, j, l).
+__device__ __forceinline__ void deformed_k(const KGeom &kg, int i, int j, int l, double *kv) {
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+    kv[r] = kg.twopi_L * (kg.Ai[r] * i + kg.Ai[3 + r] * j + kg.Ai[6 + r] * l);
+}
 
 // Every stored wave vector is k = (2 pi / L) (i, j, l) with integers, so all
 // radial factors depend on |k|^2 only through the integer n2 = i^2 + j^2 + l^2
@@ -533,6 +544,18 @@ struct KGeom {
 //   w = h^3/sqrt(V eta) sqrt(1 + u) e^{-(1 - eta_s) u / 2} / k,  u = k^2 / 4 xi^2
 // (the mobility scaling of Eq. WSops2 with both Gaussian factors divided out,
 // and the amplitude of Eq. FFTsqrt).  Entry 0 (k = 0) is zero.
+// Radial factors of one wave number k^2 (the entries of the |k|^2 table):
+// j0(ka), f1(ka), the mobility scale and the noise amplitude.
+__device__ __forceinline__ double4 radial_factors(const KGeom &kg, double k2) {
+  const double k = sqrt(k2);
+  double j0, f1;
+  shape_factors(k * kg.a, j0, f1);
+  const double u = k2 * kg.inv4xi2;
+  const double mob = kg.pref_m * (1.0 + u) * exp(-kg.one_m_etas * u) / k2;
+  const double amp = kg.pref_n * sqrt(1.0 + u) * exp(-0.5 * kg.one_m_etas * u) / k;
+  return double4{j0, f1, mob, amp};
+}
+
 __global__ void __launch_bounds__(256)
 ktable_kernel(KGeom kg, int len, double4 *__restrict__ tab) {
   const int n2 = blockIdx.x * blockDim.x + threadIdx.x;
@@ -882,11 +905,26 @@ kspace_noise_kernel(const double2 *__restrict__ psi, uint64_t seed, uint64_t cou
   if (!canon)
     for (int m = 0; m < 3; ++m) ps[m].y = -ps[m].y;
   const int ky = kidx(iy, n), kz = kidx(iz, n);
-  const int n2 = ix * ix + ky * ky + kz * kz;
-  const double4 tb = ktab[n2];
-  const double kv[3] = {kg.twopi_L * ix, kg.twopi_L * ky, kg.twopi_L * kz};
-  const double iv[3] = {(double)ix, (double)ky, (double)kz};
-  const double inv = 1.0 / (double)n2;
+  double kv[3], iv[3], inv;
+  double4 tb;
+  if (kg.def) {
+    // deformed lattice: the projection and the radial factors of the true k
+    deformed_k(kg, ix, ky, kz, kv);
+    const double k2 = kv[0] * kv[0] + kv[1] * kv[1] + kv[2] * kv[2];
+    tb = radial_factors(kg, k2);
+    for (int m = 0; m < 3; ++m) iv[m] = kv[m];
+    inv = 1.0 / k2;
+  } else {
+    const int n2 = ix * ix + ky * ky + kz * kz;
+    tb = ktab[n2];
+    kv[0] = kg.twopi_L * ix;
+    kv[1] = kg.twopi_L * ky;
+    kv[2] = kg.twopi_L * kz;
+    iv[0] = (double)ix;
+    iv[1] = (double)ky;
+    iv[2] = (double)kz;
+    inv = 1.0 / (double)n2;
+  }
   double2 kr{0, 0};
   for (int m = 0; m < 3; ++m) {
     kr.x += iv[m] * ps[m].x;
@@ -899,6 +937,51 @@ kspace_noise_kernel(const double2 *__restrict__ psi, uint64_t seed, uint64_t cou
   }
   for (int q = 0; q < cout.n; ++q) {
     const double2 w = apply_Pdag<double2, double>(cout.idx[q], uu, kv, tb.x, tb.y);
+    out[q * hsz + tid] = C{(T)w.x, (T)w.y};
+  }
+}
+
+// k-space kernel of a deformed lattice on full 3D half spectra (x, y and z
+// transformed): per stored mode, rho = sum_c P_c(k) G_c, u = scale
+// (I - k^k^) rho, W_q = P_q^+ u, with k = (2 pi / L) A^-T n and the radial
+// factors of that k (no |k|^2 table: k^2 is no longer an integer multiple
+// of (2 pi / L)^2).  One thread per mode; in and out may be the same.
+template <typename T>
+__global__ void __launch_bounds__(256)
+kspace_deformed_kernel(const cplx<T> *__restrict__ in, CompSet cin, cplx<T> *__restrict__ out,
+                       CompSet cout, KGeom kg) {
+  using C = cplx<T>;
+  const int n = kg.ng, hx = n / 2;
+  const size_t hsz = (size_t)hx * n * n;
+  const size_t tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= hsz) return;
+  const int ix = (int)(tid % hx);
+  const int iy = (int)((tid / hx) % n);
+  const int iz = (int)(tid / ((size_t)hx * n));
+  if (zero_mode(ix, iy, iz, n)) {
+    for (int q = 0; q < cout.n; ++q) out[q * hsz + tid] = C{(T)0, (T)0};
+    return;
+  }
+  double kv[3];
+  deformed_k(kg, ix, kidx(iy, n), kidx(iz, n), kv);
+  const double k2 = kv[0] * kv[0] + kv[1] * kv[1] + kv[2] * kv[2];
+  const double4 tb = radial_factors(kg, k2);
+  double2 rho[3] = {{0, 0}, {0, 0}, {0, 0}};
+  for (int p = 0; p < cin.n; ++p) {
+    const C g = in[p * hsz + tid];
+    add_P<double2, double>(cin.idx[p], double2{(double)g.x, (double)g.y}, kv, tb.x, tb.y, rho);
+  }
+  double2 kr{0, 0};
+  for (int m = 0; m < 3; ++m) {
+    kr.x += kv[m] * rho[m].x;
+    kr.y += kv[m] * rho[m].y;
+  }
+  for (int m = 0; m < 3; ++m) {
+    rho[m].x = tb.z * (rho[m].x - kv[m] * kr.x / k2);
+    rho[m].y = tb.z * (rho[m].y - kv[m] * kr.y / k2);
+  }
+  for (int q = 0; q < cout.n; ++q) {
+    const double2 w = apply_Pdag<double2, double>(cout.idx[q], rho, kv, tb.x, tb.y);
     out[q * hsz + tid] = C{(T)w.x, (T)w.y};
   }
 }
@@ -945,6 +1028,8 @@ static GridGeom geom(const Handle &h) {
   const double xi2 = h.d.xi * h.d.xi;
   g.kcoef = 2.0 * xi2 / h.d.eta_s;
   g.knorm = sqrt(2.0 * xi2 / (M_PI * h.d.eta_s));
+  g.def = h.def.on;
+  for (int i = 0; i < 6; ++i) g.G[i] = h.def.G[i];
   return g;
 }
 
@@ -959,6 +1044,8 @@ static KGeom kgeom(const Handle &h) {
   const double h3 = h.d.h * h.d.h * h.d.h;
   k.pref_n = h3 / sqrt(V * h.p.viscosity);
   k.pref_m = h3 * h3 / (V * h.p.viscosity);
+  k.def = h.def.on;
+  for (int i = 0; i < 9; ++i) k.Ai[i] = h.def.Ai[i];
   return k;
 }
 
@@ -1191,7 +1278,10 @@ void interpolate(Handle &h, const double *x, const T *grids, const CompSet &cs, 
   const int P3 = g.P * g.P * g.P;
   const dim3 grid(nblocks(h.n, 4)), block(256);
   const int *order = (const int *)h.cells.perm;
-  if (P3 <= 128)
+  if (g.def)   // the Gaussian does not factorise over the lattice axes
+    hipLaunchKernelGGL((interp_kernel<T, 0>), grid, block, 0, h.stream, x, grids, h.ngrid, cs, g,
+                       order, h.n, out, lo, acc, scale);
+  else if (P3 <= 128)
     hipLaunchKernelGGL((interp_kernel<T, 2>), grid, block, 0, h.stream, x, grids, h.ngrid, cs, g,
                        order, h.n, out, lo, acc, scale);
   else if (P3 <= 256)
@@ -1302,6 +1392,16 @@ void kspace_fused(Handle &h, const cplx<T> *in, const CompSet &cin, cplx<T> *out
 }
 
 template <typename T>
+void kspace_deformed(Handle &h, const cplx<T> *in, const CompSet &cin, cplx<T> *out,
+                     const CompSet &cout) {
+  const size_t hsz = h.ngrid / 2;
+  ProfScope ps(h, PK_KSPACE, (double)(cin.n + cout.n) * hsz * sizeof(cplx<T>));
+  hipLaunchKernelGGL(kspace_deformed_kernel<T>, dim3(nblocks(hsz, 256)), dim3(256), 0,
+                     h.stream, in, cin, out, cout, kgeom(h));
+  PSE_LAUNCH_CHECK();
+}
+
+template <typename T>
 void kspace_noise(Handle &h, const double *psi, uint64_t seed, uint64_t counter,
                   cplx<T> *out, const CompSet &cout) {
   const size_t hsz = h.ngrid / 2;
@@ -1342,6 +1442,8 @@ template <typename T> void to_double(Handle &h, const T *src, size_t n, double *
                           const CompSet &, T *);                                 \
   template void interpolate<T>(Handle &, const double *, const T *,              \
                                const CompSet &, double *, Layout, bool, double); \
+  template void kspace_deformed<T>(Handle &, const cplx<T> *, const CompSet &,   \
+                                   cplx<T> *, const CompSet &);                  \
   template void kspace_noise<T>(Handle &, const double *, uint64_t, uint64_t,    \
                                 cplx<T> *, const CompSet &);                     \
   template void kspace_fused<T>(Handle &, const cplx<T> *, const CompSet &,      \

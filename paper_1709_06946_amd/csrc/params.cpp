@@ -44,6 +44,83 @@ static int next_supported(int n) {
 
 static void fail(const char *msg) { throw Error{PSE_ERR_INVALID, msg}; }
 
+// All zero (unset) or the identity: the cube.
+static bool lattice_deformed(const pse_params &p) {
+  bool any = false, ident = true;
+  for (int i = 0; i < 9; ++i) {
+    if (p.deform[i] != 0.0) any = true;
+    if (p.deform[i] != ((i % 4 == 0) ? 1.0 : 0.0)) ident = false;
+  }
+  return any && !ident;
+}
+
+// Largest eigenvalue of the symmetric 3x3 matrix S (cyclic Jacobi rotations).
+static double sym3_lambda_max(double S[3][3]) {
+  for (int sweep = 0; sweep < 50; ++sweep) {
+    double off = 0.0;
+    for (int p = 0; p < 3; ++p)
+      for (int q = p + 1; q < 3; ++q) off += S[p][q] * S[p][q];
+    if (off < 1e-30) break;
+    for (int p = 0; p < 3; ++p)
+      for (int q = p + 1; q < 3; ++q) {
+        if (S[p][q] == 0.0) continue;
+        const double th = 0.5 * (S[q][q] - S[p][p]) / S[p][q];
+        const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+        for (int k = 0; k < 3; ++k) {
+          const double a = S[k][p], b = S[k][q];
+          S[k][p] = c * a - s * b;
+          S[k][q] = s * a + c * b;
+        }
+        for (int k = 0; k < 3; ++k) {
+          const double a = S[p][k], b = S[q][k];
+          S[p][k] = c * a - s * b;
+          S[q][k] = s * a + c * b;
+        }
+      }
+  }
+  return std::max(S[0][0], std::max(S[1][1], S[2][2]));
+}
+
+void deformation(const pse_params &p, Deform &df) {
+  df = Deform{};
+  df.on = lattice_deformed(p) ? 1 : 0;
+  double A[9];
+  for (int i = 0; i < 9; ++i) A[i] = df.on ? p.deform[i] : ((i % 4 == 0) ? 1.0 : 0.0);
+  const double det = A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
+                     A[2] * (A[3] * A[7] - A[4] * A[6]);
+  if (!(std::fabs(det - 1.0) < 1e-9)) fail("the lattice deformation must have det A = 1");
+  // inverse (det = 1: the adjugate)
+  double Ai[9] = {A[4] * A[8] - A[5] * A[7], A[2] * A[7] - A[1] * A[8], A[1] * A[5] - A[2] * A[4],
+                  A[5] * A[6] - A[3] * A[8], A[0] * A[8] - A[2] * A[6], A[2] * A[3] - A[0] * A[5],
+                  A[3] * A[7] - A[4] * A[6], A[1] * A[6] - A[0] * A[7], A[0] * A[4] - A[1] * A[3]};
+  for (int i = 0; i < 9; ++i) {
+    df.A[i] = A[i];
+    df.Ai[i] = Ai[i] / det;
+  }
+  double S[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double v = 0.0;
+      for (int k = 0; k < 3; ++k) v += A[3 * k + i] * A[3 * k + j];
+      S[i][j] = v;
+    }
+  df.G[0] = S[0][0];
+  df.G[1] = S[1][1];
+  df.G[2] = S[2][2];
+  df.G[3] = S[0][1];
+  df.G[4] = S[0][2];
+  df.G[5] = S[1][2];
+  df.lambda_max = df.on ? sym3_lambda_max(S) : 1.0;
+  // thinnest width of the cell, in units of L: 1 / max_i |row i of A^-1|
+  double rmax = 0.0;
+  for (int i = 0; i < 3; ++i)
+    rmax = std::max(rmax, std::sqrt(df.Ai[3 * i] * df.Ai[3 * i] +
+                                    df.Ai[3 * i + 1] * df.Ai[3 * i + 1] +
+                                    df.Ai[3 * i + 2] * df.Ai[3 * i + 2]));
+  df.width = 1.0 / rmax;
+}
+
 void derive(const pse_params &p, pse_derived &d) {
   if (p.n <= 0) fail("n must be positive");
   if (!(p.radius > 0)) fail("radius must be positive");
@@ -55,8 +132,13 @@ void derive(const pse_params &p, pse_derived &d) {
     fail("precision must be PSE_FP64 or PSE_MIXED");
   const double L = p.box, a = p.radius, eps = p.tol;
   const double lg = std::sqrt(std::log(1.0 / eps));
-  const double un = std::sqrt(std::log(1.0 / eps) + 9.0);   // sqrt(u_N)
+  Deform df;
+  deformation(p, df);
+  // deformed lattices: the shortest Nyquist wave vector is sqrt(lambda_max)
+  // times shorter, so xi is that much smaller for the same damping there
+  const double un = std::sqrt(std::log(1.0 / eps) + 9.0) * std::sqrt(df.lambda_max);
   d = pse_derived{};
+  d.lambda_max = df.lambda_max;
   if (p.grid > 0) {
     if (!grid_supported(p.grid)) fail("grid must be 2^j or 3*2^j in [8, 1024]");
     d.grid = p.grid;
@@ -71,7 +153,7 @@ void derive(const pse_params &p, pse_derived &d) {
   if (p.deriv_gridding < 0 || p.deriv_gridding > 2) fail("deriv_gridding must be 0, 1 or 2");
   const double eps_q = eps / 20.0;
   d.support = p.support > 0 ? p.support
-                            : (int)std::ceil(2.0 / M_PI * std::log(2.0 / eps_q));
+                            : (int)std::ceil(df.lambda_max * 2.0 / M_PI * std::log(2.0 / eps_q));
   // Derivative gridding of M_ES: the gradient of the truncated Gaussian
   // carries about ten times the Gaussian's quadrature error at equal support
   // (each further point divides both by about 3.5), so with an automatic
@@ -83,7 +165,7 @@ void derive(const pse_params &p, pse_derived &d) {
   // stay below about 20 (measured: faster at 2.4, 3.8, 12 and 14.5, slower
   // at 33).
   d.deriv_gridding = 1;
-  if (p.deriv_gridding != 1) {   // 0 (default) or 2
+  if (p.deriv_gridding != 1 && !df.on) {   // 0 (default) or 2; cube only
     const int pd = p.support > 0 ? d.support : d.support + 1;
     const double dens = (double)p.n * pd * pd * pd / ((double)d.grid * d.grid * d.grid);
     if (pd <= 10 && spread_tile(d.grid, pd) != 0 && (p.deriv_gridding == 2 || dens <= 20.0)) {
@@ -98,8 +180,9 @@ void derive(const pse_params &p, pse_derived &d) {
   d.eta_s = std::pow(d.h * d.support * d.xi / d.m, 2);
   if (!(d.eta_s < 1.0)) fail("eta_s = (h P xi / m)^2 must be < 1: refine the grid or lower xi");
   d.rcut = p.rcut > 0 ? p.rcut : 2.0 * a + lg / d.xi;
-  if (d.rcut > L / 3.0) fail("rcut exceeds L/3: raise xi or use a larger box");
-  d.cells = (int)std::floor(L / d.rcut);
+  if (d.rcut > df.width * L / 3.0)
+    fail("rcut exceeds a third of the cell's thinnest width: raise xi or use a larger box");
+  d.cells = (int)std::floor(df.width * L / d.rcut);
   if (d.cells < 3) fail("fewer than 3 cells per side");
   if (d.cells > 1024) d.cells = 1024;
   d.lanczos_tol = p.lanczos_tol > 0 ? p.lanczos_tol : 1e-3;

@@ -61,6 +61,24 @@ struct CompSet {
   int idx[NC];    // component indices into the 11-vector
 };
 
+// Deformation of the periodic lattice: lattice vectors are the columns of
+// L A (row-major A, det 1), Ai = A^-1, G = A^T A as (xx, yy, zz, xy, xz, yz).
+// Deformed handles keep positions in lattice coordinates A^-1 x, wrapped into
+// [0, L)^3, so that bins, stencils and grids are those of the cube; only
+// distances are mapped back by A.
+struct Deform {
+  int on;
+  double A[9], Ai[9], G[6];
+  double lambda_max;
+  double width;    // thinnest width of the cell over L
+};
+
+// Squared length of A d for lattice-coordinate offsets d.
+__host__ __device__ inline double qform(const double *G, double dx, double dy, double dz) {
+  return G[0] * dx * dx + G[1] * dy * dy + G[2] * dz * dz +
+         2.0 * (G[3] * dx * dy + G[4] * dx * dz + G[5] * dy * dz);
+}
+
 // Geometry and quadrature constants passed by value to kernels.
 struct GridGeom {
   int ng;          // grid points per side
@@ -68,6 +86,8 @@ struct GridGeom {
   double L, h;     // box, spacing
   double kcoef;    // Gaussian: K1d(d) = knorm exp(-kcoef d^2)
   double knorm;
+  int def;         // deformed lattice: distances |A d|^2 = qform(G, d)
+  double G[6];
 };
 
 // Device workspace of one precision.
@@ -199,6 +219,8 @@ struct Handle {
   uint64_t *dstep = nullptr;
   const uint64_t *counter_dev = nullptr;
 
+  Deform def{};              // lattice deformation (def.on = 0: the cube)
+
   // A handle with an arena takes every device buffer from it (bump
   // allocation, 256-byte aligned) instead of the runtime, and frees nothing.
   unsigned char *arena = nullptr;
@@ -270,6 +292,7 @@ void prof_resolve(Handle &h);
 
 // ---- params.cpp
 void derive(const pse_params &p, pse_derived &d);
+void deformation(const pse_params &p, Deform &df);   // throws when det A != 1
 size_t footprint(const pse_params &p, const pse_derived &d);
 
 // ---- fft.hip
@@ -309,6 +332,11 @@ void spread_deriv(Handle &h, const double *q, Layout lq, const CompSet &cs, T *g
 template <typename T>
 void interp_deriv(Handle &h, const double *x, const T *grids, const CompSet &cs, double *out,
                   Layout lo, bool accumulate, double scale);
+// k-space kernel of a deformed lattice on full half spectra (all three
+// axes transformed)
+template <typename T>
+void kspace_deformed(Handle &h, const cplx<T> *in, const CompSet &cin, cplx<T> *out,
+                     const CompSet &cout);
 template <typename T> void zero_grids(Handle &h, T *g, int ncomp);
 void build_tile_lists(Handle &h, const double *xw);
 size_t tile_record_bytes(int S);                  // one (tile, particle) record

@@ -167,6 +167,17 @@ void build_tables(Handle &h) {
 
 // Non-finite coordinates raise *bad and are replaced by 0, so that every
 // later kernel stays in bounds until the host reports the error.
+// Positions of a deformed lattice to lattice coordinates A^-1 x (then
+// wrapped like the cube's).
+__global__ void lattice_coords_kernel(const double *__restrict__ x, double *__restrict__ xl,
+                                      int64_t n, Deform df) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double p[3] = {x[3 * i], x[3 * i + 1], x[3 * i + 2]};
+  for (int r = 0; r < 3; ++r)
+    xl[3 * i + r] = df.Ai[3 * r] * p[0] + df.Ai[3 * r + 1] * p[1] + df.Ai[3 * r + 2] * p[2];
+}
+
 __global__ void wrap_kernel(const double *__restrict__ x, double *__restrict__ xw,
                             int64_t n3, double L, int *__restrict__ bad,
                             int *__restrict__ status) {
@@ -188,6 +199,13 @@ void wrap_positions(Handle &h, const double *x, double *xw) {
   // the flag is cleared by a kernel, not a memset node, so that the launches
   // can be captured into graphs
   fill_int(h, h.bad_pos, 1, 0);
+  if (h.def.on) {
+    // lattice coordinates first, then wrapped in place like the cube's
+    hipLaunchKernelGGL(lattice_coords_kernel, dim3(nblocks(h.n, 256)), dim3(256), 0,
+                       h.stream, x, xw, h.n, h.def);
+    PSE_LAUNCH_CHECK();
+    x = xw;
+  }
   hipLaunchKernelGGL(wrap_kernel, dim3(nblocks(3 * h.n, 256)), dim3(256), 0,
                      h.stream, x, xw, 3 * h.n, h.p.box, h.bad_pos, h.dctl + CTL_STATUS);
   PSE_LAUNCH_CHECK();
@@ -501,6 +519,8 @@ struct PairArgs {
   int n2a, ntab;
   int64_t cap;     // pair-list capacity: entries at or beyond it are not written
   int *status;     // PSE_STATUS_PAIR_OVERFLOW is or-ed in when one is dropped
+  int def;         // deformed lattice: positions are lattice coordinates and
+  double A[9];     // separations are mapped back by A
 };
 
 constexpr int PAIR_REC = 10;   // co[7], e[3]
@@ -514,6 +534,13 @@ __device__ __forceinline__ bool near_pair(const double *__restrict__ xw, double 
   const double hL = 0.5 * pa.L;
 #pragma unroll
   for (int k = 0; k < 3; ++k) d[k] += d[k] > hL ? -pa.L : (d[k] < -hL ? pa.L : 0.0);
+  if (pa.def) {
+    // lattice offsets to the Cartesian separation (the cutoff is at most a
+    // third of the cell's thinnest width, so the image is the nearest one)
+    const double e[3] = {d[0], d[1], d[2]};
+#pragma unroll
+    for (int r = 0; r < 3; ++r) d[r] = pa.A[3 * r] * e[0] + pa.A[3 * r + 1] * e[1] + pa.A[3 * r + 2] * e[2];
+  }
   return d[0] * d[0] + d[1] * d[1] + d[2] * d[2] < pa.rcut2;
 }
 
@@ -666,6 +693,8 @@ static void build_pair_list(Handle &h, const double *xw) {
   pa.ntab = h.ntab;
   pa.cap = (int64_t)h.pl_cap;
   pa.status = h.dctl + CTL_STATUS;
+  pa.def = h.def.on;
+  for (int i = 0; i < 9; ++i) pa.A[i] = h.def.A[i];
   const unsigned nb = nblocks((size_t)h.n * 64, 256);
   hipLaunchKernelGGL((pair_list_kernel<false>), dim3(nb), dim3(256), 0, h.stream, xw,
                      h.cells.perm, h.cells.start, h.cells.of, pa, h.pl_cnt, nullptr, nullptr,

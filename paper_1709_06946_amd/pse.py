@@ -28,7 +28,7 @@ class pse_params(ctypes.Structure):
                 ('gmres_maxit', ctypes.c_int32), ('gmres_tol', ctypes.c_double),
                 ('refine_passes', ctypes.c_int32), ('graphs', ctypes.c_int32),
                 ('deriv_gridding', ctypes.c_int32), ('stream', ctypes.c_void_p),
-                ('async_calls', ctypes.c_int32)]
+                ('async_calls', ctypes.c_int32), ('deform', ctypes.c_double * 9)]
 
 
 class pse_derived(ctypes.Structure):
@@ -39,7 +39,7 @@ class pse_derived(ctypes.Structure):
                 ('lanczos_maxit', ctypes.c_int32), ('gmres_restart', ctypes.c_int32),
                 ('gmres_maxit', ctypes.c_int32), ('refine_passes', ctypes.c_int32),
                 ('lanczos_tol', ctypes.c_double), ('gmres_tol', ctypes.c_double),
-                ('deriv_gridding', ctypes.c_int32)]
+                ('deriv_gridding', ctypes.c_int32), ('lambda_max', ctypes.c_double)]
 
 
 class pse_stats(ctypes.Structure):
@@ -182,13 +182,18 @@ class PSEError(RuntimeError):
 def make_params(n, box, *, radius=1.0, viscosity=1.0, kT=1.0, tol=1e-3, grid=0,
                 support=0, xi=0.0, rcut=0.0, precision=PSE_FP64, lanczos_maxit=0,
                 lanczos_tol=0.0, gmres_restart=0, gmres_maxit=0, gmres_tol=0.0,
-                refine_passes=0, graphs=0, deriv_gridding=0, stream=None, async_calls=0):
+                refine_passes=0, graphs=0, deriv_gridding=0, stream=None, async_calls=0,
+                deform=None):
+    """deform: 3x3 volume-preserving lattice deformation A (lattice vectors
+    are the columns of box * A), or None for the cube."""
+    dv = (ctypes.c_double * 9)(*([0.0] * 9 if deform is None else
+                                 [float(v) for row in deform for v in row]))
     return pse_params(int(n), float(box), float(radius), float(viscosity), float(kT),
                       float(tol), int(grid), int(support), float(xi), float(rcut),
                       int(precision), int(lanczos_maxit), float(lanczos_tol),
                       int(gmres_restart), int(gmres_maxit), float(gmres_tol),
                       int(refine_passes), int(graphs), int(deriv_gridding), stream,
-                      int(async_calls))
+                      int(async_calls), dv)
 
 
 def derive(params):
