@@ -10,7 +10,8 @@
 // captured graph of the whole step (one host launch per step).  Several
 // admitted requests execute at once, so their kernels overlap on the
 // device; requests arriving meanwhile are admitted as slots and memory free
-// up.  Each step's completion time is recorded for latency percentiles.
+// up.  Requests with large grids (kHeavyGrid) run alone.  Each step's
+// completion time is recorded for latency percentiles.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -34,12 +35,20 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 
+// A request whose grid has this many points per side or more keeps the whole
+// device busy in every stage (at 256^3 a line pass alone has 2^15 and more
+// workgroups): overlapping it with others only shares the same bandwidth
+// and caches, so it runs alone; smaller requests, whose launches leave most
+// of the device idle, run several at a time.
+constexpr int kHeavyGrid = 256;
+
 struct Req {
   int64_t id;
   pse_request r;
   std::vector<double> x0, fl, x_out;
   std::vector<double> lat_ms;     // per-step latency
   size_t bytes = 0;
+  bool heavy = false;             // grid of kHeavyGrid^3 points or more
   int status = 0;                 // 0 queued, 1 running, 2 done, <0 failed
   int rc = 0;
   std::string err;
@@ -58,6 +67,7 @@ struct pse_server {
   std::map<int64_t, std::shared_ptr<Req>> all;
   size_t used = 0;
   int active = 0;
+  bool heavy_active = false;          // a heavy request is running (alone)
   bool stopping = false;
   int64_t next_id = 1;
   int device = 0;
@@ -208,13 +218,18 @@ void worker(pse_server *s) {
       s->cv_admit.wait(lk, [&] {
         if (s->stopping && s->queue.empty()) return true;
         if (s->queue.empty()) return false;
-        return s->used + s->queue.front()->bytes <= s->budget || s->active == 0;
+        if (s->active == 0) return true;
+        // FIFO: a heavy request at the head waits for an idle device, and
+        // nothing joins a heavy request that is running
+        if (s->heavy_active || s->queue.front()->heavy) return false;
+        return s->used + s->queue.front()->bytes <= s->budget;
       });
       if (s->queue.empty()) return;   // stopping
       q = s->queue.front();
       s->queue.pop_front();
       s->used += q->bytes;
       s->active += 1;
+      if (q->heavy) s->heavy_active = true;
       s->peak_used = std::max(s->peak_used, s->used);
       s->peak_active = std::max(s->peak_active, s->active);
       q->status = 1;
@@ -225,6 +240,7 @@ void worker(pse_server *s) {
       std::lock_guard<std::mutex> lk(s->mu);
       s->used -= q->bytes;
       s->active -= 1;
+      if (q->heavy) s->heavy_active = false;
       q->t_done = s->now();
       q->status = q->rc < 0 ? q->rc : 2;
       if (q->rc < 0) {
@@ -280,7 +296,10 @@ int pse_server_submit(pse_server *s, const pse_request *r, int64_t *id) {
   p.gmres_tol = r->gmres_tol;
   p.lanczos_tol = r->lanczos_tol;
   size_t bytes = 0;
-  const int rc = pse_footprint_bytes(&p, &bytes);
+  int rc = pse_footprint_bytes(&p, &bytes);
+  if (rc != PSE_OK) return rc;
+  pse_derived d{};
+  rc = pse_derive(&p, &d);
   if (rc != PSE_OK) return rc;
   bytes += (size_t)r->n * 9 * sizeof(double);   // request positions and forces
   if (bytes > s->budget) return PSE_ERR_NOMEM;
@@ -291,6 +310,7 @@ int pse_server_submit(pse_server *s, const pse_request *r, int64_t *id) {
   q->r.x0 = nullptr;
   q->r.FL = r->FL ? q->fl.data() : nullptr;
   q->bytes = bytes;
+  q->heavy = d.grid >= kHeavyGrid;
   {
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->stopping) return PSE_ERR_INVALID;
