@@ -271,10 +271,10 @@ def served(n_req, steps, max_active, n_max, rate_frac, seed, workers=8):
     """Served form: a Poisson stream of independent simulations with N
     log-uniform in [1e3, n_max] and phi uniform in [0.05, 0.45], each `steps`
     mixed-precision constrained steps at eps = 1e-3, admitted by device
-    footprint and run concurrently.  The same requests are first run one at a
-    time (no overlap, no waiting): that run's throughput is the capacity, and
-    the Poisson arrival rate is rate_frac times the capacity in requests per
-    second.  Inputs are generated before either run."""
+    footprint and run concurrently.  The same requests are run one at a time
+    and all submitted at once (no arrival gaps) with and without overlap: the
+    overlapped run's rate is the capacity, and the Poisson arrival rate of the
+    latency run is rate_frac times it.  Inputs are generated before any run."""
     import concurrent.futures
 
     import numpy as np
@@ -330,7 +330,8 @@ def served(n_req, steps, max_active, n_max, rate_frac, seed, workers=8):
                             precision=pse.PSE_MIXED))
         srv.close()
     serial = run(1, np.zeros(n_req))
-    capacity = n_req / serial['wall_s']
+    saturated = run(max_active, np.zeros(n_req))
+    capacity = n_req / saturated['wall_s']
     rate = rate_frac * capacity
     conc = run(max_active, gaps01 / rate)
     return dict(requests=n_req, steps_per_request=steps, n_range=[1000, n_max],
@@ -339,7 +340,7 @@ def served(n_req, steps, max_active, n_max, rate_frac, seed, workers=8):
                 arrival_rate_frac_of_capacity=rate_frac,
                 total_particles=int(sum(r['n'] for r in reqs)),
                 input_generation_s=round(t_inputs, 1),
-                concurrent=conc, one_at_a_time=serial)
+                concurrent=conc, concurrent_all_at_once=saturated, one_at_a_time=serial)
 
 
 def copy_calibration(mib=1024, reps=3):

@@ -644,6 +644,11 @@ static void create(const pse_params &p, Handle &h) {
     handle_alloc(h, (void **)&b->scat, n * sizeof(int));
     handle_alloc(h, (void **)&b->perm, n * sizeof(int));
   }
+  // block-order traversal of the real-space cells (interpolation order)
+  handle_alloc(h, (void **)&h.cells.trav, n * sizeof(int));
+  handle_alloc(h, (void **)&h.cells.bcount, (size_t)h.cells.nc * h.cells.nc * h.cells.nc * sizeof(int));
+  handle_alloc(h, (void **)&h.cells.bstart,
+               ((size_t)h.cells.nc * h.cells.nc * h.cells.nc + 1) * sizeof(int));
   handle_alloc(h, (void **)&h.xw, 3 * n * sizeof(double));
   handle_alloc(h, (void **)&h.xh, 3 * n * sizeof(double));
   double **vs[6] = {&h.v0, &h.v1, &h.v2, &h.v3, &h.v4, &h.v5};
@@ -671,7 +676,7 @@ static void release(Handle &h) {
                   h.g32.twiddle, h.g32.table, h.cells.start, h.cells.count,
                   h.cells.scan_tmp, h.cells.of, h.cells.slot, h.cells.scat, h.cells.perm,
                   h.sbins.start, h.sbins.count, h.sbins.scan_tmp, h.sbins.of, h.sbins.slot,
-                  h.sbins.scat, h.sbins.perm,
+                  h.sbins.scat, h.sbins.perm, h.cells.trav, h.cells.bcount, h.cells.bstart,
                   h.xw, h.xh, h.v0, h.v1, h.v2, h.v3, h.v4, h.v5, h.es_b, h.es_x, h.es_r,
                   h.es_d, h.lz_V, h.gm_V, h.small, h.dots, h.ktab, h.pl_cnt,
                   h.pl_start, h.pl_scan, h.pl_nbr, h.pl_rec, h.tl_cnt, h.tl_start,

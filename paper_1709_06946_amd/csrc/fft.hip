@@ -18,8 +18,7 @@ namespace pse {
 
 // Contiguous-line LDS layout of the x steps: one pad element after every PAD
 // positions, PAD = the first radix of the direction (see padpos), and a line
-// stride of N + N/PAD + 1 elements.
-constexpr int xstride(int n, int pad) { return n + n / pad + 1; }
+// stride of xstride(N, PAD) elements.
 template <int N, int E> constexpr int xstride_max() {
   return xstride(N, Shape<N, E>::first(false)) > xstride(N, Shape<N, E>::first(true))
              ? xstride(N, Shape<N, E>::first(false))

@@ -108,7 +108,15 @@ struct Bins {
   int *scat = nullptr;       // N: particles by bin, in arrival order
   int *perm = nullptr;       // N: particles ordered by bin, by index within a bin
   int *scan_tmp = nullptr;   // block sums of the scan
+  // the same particles with the bins visited block by block (BIN_BLOCK^3
+  // bins per block, blocks in lexicographic order), for the gathers whose
+  // neighbouring particles share grid data (interpolation): a contiguous
+  // range of it covers a compact region of the box
+  int *trav = nullptr;       // N
+  int *bcount = nullptr;     // nc^3: bin counts in block order
+  int *bstart = nullptr;     // nc^3 + 1: their exclusive sums
 };
+constexpr int BIN_BLOCK = 4;
 
 // Kernel classes timed by the optional profiler.
 enum ProfKind {

@@ -357,6 +357,41 @@ cell_order_kernel(const int *__restrict__ start, const int *__restrict__ scat, i
   }
 }
 
+// Bin b of an nc^3 lattice (x fastest) at its position in block order:
+// blocks of BIN_BLOCK^3 bins in lexicographic order, bins lexicographic
+// within a block (partial blocks at the far faces).
+__device__ __forceinline__ int block_order_pos(int b, int nc) {
+  const int bx = b % nc, by = (b / nc) % nc, bz = b / (nc * nc);
+  const int B = BIN_BLOCK, nb = (nc + B - 1) / B;
+  const int Bx = bx / B, By = by / B, Bz = bz / B;
+  // bins before this block: full slabs and rows of blocks, with the widths
+  // of the partial blocks at the far faces
+  const auto w = [&](int blk) { return blk + 1 < nb ? B : nc - B * (nb - 1); };
+  const int wx = w(Bx), wy = w(By);
+  const int before = Bz * B * nc * nc + By * B * nc * w(Bz) + Bx * B * wy * w(Bz);
+  const int lx = bx - Bx * B, ly = by - By * B, lz = bz - Bz * B;
+  return before + (lz * wy + ly) * wx + lx;
+}
+
+// counts permuted into block order
+__global__ void block_count_kernel(const int *__restrict__ count, int nc,
+                                   int *__restrict__ bcount) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nc * nc * nc) return;
+  bcount[block_order_pos(b, nc)] = count[b];
+}
+
+// trav: each bin's members (in perm order) at the bin's block-order offset
+__global__ void block_trav_kernel(const int *__restrict__ start, const int *__restrict__ perm,
+                                  const int *__restrict__ bstart, int nc,
+                                  int *__restrict__ trav) {
+  const int b = blockIdx.x * 4 + threadIdx.x / 64;
+  const int lane = threadIdx.x % 64;
+  if (b >= nc * nc * nc) return;
+  const int lo = start[b], k = start[b + 1] - lo, dst = bstart[block_order_pos(b, nc)];
+  for (int p = lane; p < k; p += 64) trav[dst + p] = perm[lo + p];
+}
+
 // out[0..n] = exclusive prefix sums of in[0..n) (out[n] = total); tmp holds
 // n/1024 + 8 ints.
 void exclusive_scan(Handle &h, const int *in, int *out, int *tmp, int n) {
@@ -388,6 +423,15 @@ static void build_bins(Handle &h, const double *xw, Bins &b) {
   hipLaunchKernelGGL(cell_order_kernel, dim3((unsigned)((ncells + 3) / 4)), dim3(256), 0,
                      h.stream, b.start, b.scat, ncells, b.perm);
   PSE_LAUNCH_CHECK();
+  if (b.trav) {
+    hipLaunchKernelGGL(block_count_kernel, dim3(nblocks(ncells, 256)), dim3(256), 0, h.stream,
+                       b.count, nc, b.bcount);
+    PSE_LAUNCH_CHECK();
+    exclusive_scan(h, b.bcount, b.bstart, b.scan_tmp, ncells);
+    hipLaunchKernelGGL(block_trav_kernel, dim3((unsigned)((ncells + 3) / 4)), dim3(256), 0,
+                       h.stream, b.start, b.perm, b.bstart, nc, b.trav);
+    PSE_LAUNCH_CHECK();
+  }
 }
 
 // ------------------------------------------------------------ pair sum --
