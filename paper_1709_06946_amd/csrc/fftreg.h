@@ -266,19 +266,11 @@ constexpr int xstride(int n, int pad) { return n + n / pad + 1; }
 // Exchange through LDS after a pass of radix R (span Ns) into the input
 // layout of a pass of radix R2.  Element at position pos lives at
 // lds[padpos(pos) * ps + off].
-// WAVE: the line belongs to one wavefront (TPL = 64), whose LDS operations
-// are carried out in order, so the exchange needs no workgroup barrier, only
-// a barrier to the compiler's reordering.
-template <bool WAVE> __device__ __forceinline__ void exchange_barrier() {
-  if constexpr (WAVE) __builtin_amdgcn_wave_barrier();
-  else __syncthreads();
-}
-
-template <typename T, int N, int E, int R, int Ns, int R2, int PADP, bool WAVE = false>
+template <typename T, int N, int E, int R, int Ns, int R2, int PADP>
 __device__ __forceinline__ void reg_exchange(cplx<T> (&v)[E], int t, cplx<T> *lds, int ps,
                                              int off) {
   constexpr int TPL = N / E;
-  exchange_barrier<WAVE>();
+  __syncthreads();
 #pragma unroll
   for (int b = 0; b < E / R; ++b) {
     const int j = t + b * TPL;
@@ -286,7 +278,7 @@ __device__ __forceinline__ void reg_exchange(cplx<T> (&v)[E], int t, cplx<T> *ld
 #pragma unroll
     for (int r = 0; r < R; ++r) lds[padpos<PADP>(base + r * Ns) * ps + off] = v[b * R + r];
   }
-  exchange_barrier<WAVE>();
+  __syncthreads();
 #pragma unroll
   for (int b = 0; b < E / R2; ++b)
 #pragma unroll
@@ -294,7 +286,7 @@ __device__ __forceinline__ void reg_exchange(cplx<T> (&v)[E], int t, cplx<T> *ld
       v[b * R2 + r] = lds[padpos<PADP>(reg_pos<N, E, R2>(t, b, r)) * ps + off];
 }
 
-template <typename T, int N, int E, bool REV, int P, int Ns, int PADP, bool WAVE = false>
+template <typename T, int N, int E, bool REV, int P, int Ns, int PADP>
 __device__ __forceinline__ void reg_run(cplx<T> (&v)[E], int t, cplx<T> *lds, int ps, int off,
                                         const cplx<T> *__restrict__ tw, int dir) {
   using S = Shape<N, E>;
@@ -302,23 +294,23 @@ __device__ __forceinline__ void reg_run(cplx<T> (&v)[E], int t, cplx<T> *lds, in
   reg_pass<T, N, E, R, Ns>(v, t, tw, dir);
   if constexpr (P + 1 < S::NP) {
     constexpr int R2 = S::radix(P + 1, REV);
-    reg_exchange<T, N, E, R, Ns, R2, PADP, WAVE>(v, t, lds, ps, off);
-    reg_run<T, N, E, REV, P + 1, Ns * R, PADP, WAVE>(v, t, lds, ps, off, tw, dir);
+    reg_exchange<T, N, E, R, Ns, R2, PADP>(v, t, lds, ps, off);
+    reg_run<T, N, E, REV, P + 1, Ns * R, PADP>(v, t, lds, ps, off, tw, dir);
   }
 }
 
 // Forward transform (exp(-2 pi i k n / N)) with the passes in factor order.
-template <typename T, int N, int E, int PADP = 0, bool WAVE = false>
+template <typename T, int N, int E, int PADP = 0>
 __device__ __forceinline__ void reg_fft_forward(cplx<T> (&v)[E], int t, cplx<T> *lds, int ps,
                                                 int off, const cplx<T> *__restrict__ tw) {
-  reg_run<T, N, E, false, 0, 1, PADP, WAVE>(v, t, lds, ps, off, tw, -1);
+  reg_run<T, N, E, false, 0, 1, PADP>(v, t, lds, ps, off, tw, -1);
 }
 
 // Inverse (unnormalised, exp(+2 pi i k n / N)) with the passes reversed.
-template <typename T, int N, int E, int PADP = 0, bool WAVE = false>
+template <typename T, int N, int E, int PADP = 0>
 __device__ __forceinline__ void reg_fft_inverse(cplx<T> (&v)[E], int t, cplx<T> *lds, int ps,
                                                 int off, const cplx<T> *__restrict__ tw) {
-  reg_run<T, N, E, true, 0, 1, PADP, WAVE>(v, t, lds, ps, off, tw, +1);
+  reg_run<T, N, E, true, 0, 1, PADP>(v, t, lds, ps, off, tw, +1);
 }
 
 // Element counts per thread: line passes and the fused k-space kernel (which

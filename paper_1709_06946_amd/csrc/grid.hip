@@ -820,150 +820,81 @@ kspace_fused_kernel(const cplx<T> *__restrict__ in, CompSet cin, cplx<T> *__rest
   }
 }
 
-// The same fused z/k-space/z computation for long power-of-two lines, one
-// wavefront per z-line (E = N/64 modes per lane): a workgroup of TL waves
-// owns TL neighbouring kx columns at one ky.  Each component's TL lines are
-// staged through LDS with loads and stores that cover TL consecutive x
-// addresses per z row, and every wave transforms its own line in its own LDS
-// region, whose exchanges need no workgroup barrier (a wavefront's LDS
-// operations are carried out in order).  Four workgroup barriers per
-// component instead of two per radix pass.
-template <typename T, int N, bool DG>
+// Derivative gridding on long lines with all three grids in registers: a
+// workgroup owns TL neighbouring kx columns at one ky (row segments of up to
+// 128 bytes), and the TPL threads of a line hold E modes of each of the
+// three grids D^.  Every load is issued before the first transform; the
+// three forward z transforms run one after the other through one LDS area;
+// each mode is then folded with its three components at hand,
+// out = -9 f1^2 scale (I - k^k^) D^; and the three inverse transforms
+// follow.  No accumulator and no prefetch copy: 3 E complex numbers per
+// thread, so E can be as large as the line passes' (fewer exchanges).
+template <typename T, int N, int E>
 __global__ void __launch_bounds__(512)
-kspace_wave_kernel(const cplx<T> *__restrict__ in, CompSet cin, cplx<T> *__restrict__ out,
-                   CompSet cout, KGeom kg, const typename TabT<T>::type *__restrict__ ktab,
-                   const cplx<T> *__restrict__ tw, int TL) {
+kspace_dg3_kernel(const cplx<T> *__restrict__ in, cplx<T> *__restrict__ out, KGeom kg,
+                  const typename TabT<T>::type *__restrict__ ktab,
+                  const cplx<T> *__restrict__ tw, int TL) {
   using C = cplx<T>;
-  constexpr int E = N / 64, M = N / 2;
+  constexpr int M = N / 2;
   using S = Shape<N, E>;
   constexpr int R0 = S::first(false), RL = S::last(false);
-  constexpr int PF = S::first(false), PI = S::first(true);   // pads of the two directions
-  constexpr int LS = xstride(N, PF) > xstride(N, PI) ? xstride(N, PF) : xstride(N, PI);
   extern __shared__ unsigned char smem_raw[];
   C *lds = reinterpret_cast<C *>(smem_raw);
   const int tiles = M / TL;
   const int lb = (int)xcd_block(blockIdx.x, gridDim.x);
   const int xt = lb % tiles, iy = lb / tiles;
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, nthr = blockDim.x;
-  const int ix = xt * TL + w;
+  const int line = threadIdx.x % TL, t = threadIdx.x / TL;
+  const int ix = xt * TL + line;
   const int ky = kidx(iy, N);
   const size_t hsz = (size_t)M * N * N, plane = (size_t)N * M;
-  const size_t base = (size_t)iy * M + (size_t)xt * TL;
-  C *line = lds + w * LS;
-  const T tp = (T)kg.twopi_L;
-  const auto entry = [&](int e) {
-    const int iz = reg_pos<N, E, RL>(lane, e / RL, e % RL);
-    const int kz = kidx(iz, N);
-    return ktab[ix * ix + ky * ky + kz * kz];
-  };
-  C rho[E][3];
+  const size_t base = (size_t)iy * M + ix;
+  C v[3][E];
 #pragma unroll
-  for (int e = 0; e < E; ++e)
-#pragma unroll
-    for (int m = 0; m < 3; ++m) rho[e][m] = C{(T)0, (T)0};
-  C v[E];
-  for (int p = 0; p < cin.n; ++p) {
-    // stage component p of the TL lines (padded for the forward passes)
-    const C *src = in + (size_t)p * hsz + base;
-    for (int idx = threadIdx.x; idx < N * TL; idx += nthr) {
-      const int ln = idx % TL, z = idx / TL;
-      lds[ln * LS + padpos<PF>(z)] = src[(size_t)z * plane + ln];
-    }
-    __syncthreads();
+  for (int m = 0; m < 3; ++m)
 #pragma unroll
     for (int b = 0; b < E / R0; ++b)
 #pragma unroll
       for (int r = 0; r < R0; ++r)
-        v[b * R0 + r] = line[padpos<PF>(reg_pos<N, E, R0>(lane, b, r))];
-    reg_fft_forward<T, N, E, PF, true>(v, lane, line, 1, 0, tw);
-    const int c = cin.idx[p];
+        v[m][b * R0 + r] = in[m * hsz + base + reg_pos<N, E, R0>(t, b, r) * plane];
 #pragma unroll
-    for (int b = 0; b < E / RL; ++b)
-#pragma unroll
-      for (int r = 0; r < RL; ++r) {
-        const int e = b * RL + r;
-        const int iz = reg_pos<N, E, RL>(lane, b, r);
-        if (zero_mode(ix, iy, iz, N)) continue;
-        if constexpr (DG) {
-#pragma unroll
-          for (int m = 0; m < 3; ++m)
-            if (m == c) rho[e][m] = v[e];
-        } else {
-          const auto tb = entry(e);
-          const T kv[3] = {tp * ix, tp * ky, tp * kidx(iz, N)};
-          add_P<C, T>(c, v[e], kv, (T)tb.x, (T)tb.y, rho[e]);
-        }
-      }
-    __syncthreads();   // the staging area is free for the next component
-  }
-  // u = scale (I - k^k^) rho; derivative gridding folds its factors into one
-  // number per mode: out = -9 f1^2 scale (I - k^k^) D^
+  for (int m = 0; m < 3; ++m) reg_fft_forward<T, N, E>(v[m], t, lds, TL, line, tw);
 #pragma unroll
   for (int b = 0; b < E / RL; ++b)
 #pragma unroll
     for (int r = 0; r < RL; ++r) {
       const int e = b * RL + r;
-      const int iz = reg_pos<N, E, RL>(lane, b, r);
-      const int kz = kidx(iz, N);
+      const int iz = reg_pos<N, E, RL>(t, b, r);
       if (zero_mode(ix, iy, iz, N)) {
 #pragma unroll
-        for (int m = 0; m < 3; ++m) rho[e][m] = C{(T)0, (T)0};
+        for (int m = 0; m < 3; ++m) v[m][e] = C{(T)0, (T)0};
         continue;
       }
-      const auto tb = entry(e);
-      const T scale = DG ? (T)(-9.0 * (double)tb.y * (double)tb.y * (double)tb.z) : (T)tb.z;
+      const int kz = kidx(iz, N);
+      const int n2 = ix * ix + ky * ky + kz * kz;
+      const auto tb = ktab[n2];
+      const T s = (T)-9 * (T)tb.y * (T)tb.y * (T)tb.z;
       const T kv[3] = {(T)ix, (T)ky, (T)kz};
-      const T inv = (T)1 / (T)(ix * ix + ky * ky + kz * kz);
+      const T inv = (T)1 / (T)n2;
       T krx = 0, kry = 0;
 #pragma unroll
       for (int m = 0; m < 3; ++m) {
-        krx += kv[m] * rho[e][m].x;
-        kry += kv[m] * rho[e][m].y;
+        krx += kv[m] * v[m][e].x;
+        kry += kv[m] * v[m][e].y;
       }
 #pragma unroll
       for (int m = 0; m < 3; ++m) {
-        rho[e][m].x = scale * (rho[e][m].x - kv[m] * krx * inv);
-        rho[e][m].y = scale * (rho[e][m].y - kv[m] * kry * inv);
+        v[m][e].x = s * (v[m][e].x - kv[m] * krx * inv);
+        v[m][e].y = s * (v[m][e].y - kv[m] * kry * inv);
       }
     }
-  for (int q = 0; q < cout.n; ++q) {
-    const int c = cout.idx[q];
 #pragma unroll
-    for (int b = 0; b < E / RL; ++b)
-#pragma unroll
-      for (int r = 0; r < RL; ++r) {
-        const int e = b * RL + r;
-        const int iz = reg_pos<N, E, RL>(lane, b, r);
-        if (zero_mode(ix, iy, iz, N)) {
-          v[e] = C{(T)0, (T)0};
-          continue;
-        }
-        if constexpr (DG) {
-          v[e] = C{(T)0, (T)0};
-#pragma unroll
-          for (int m = 0; m < 3; ++m)
-            if (m == c) v[e] = rho[e][m];
-        } else {
-          const auto tb = entry(e);
-          const T kv[3] = {tp * ix, tp * ky, tp * kidx(iz, N)};
-          v[e] = apply_Pdag<C, T>(c, rho[e], kv, (T)tb.x, (T)tb.y);
-        }
-      }
-    reg_fft_inverse<T, N, E, PI, true>(v, lane, line, 1, 0, tw);
-    // the inverse ends in the forward input layout: positions of pass 0
-    __builtin_amdgcn_wave_barrier();
+  for (int m = 0; m < 3; ++m) {
+    reg_fft_inverse<T, N, E>(v[m], t, lds, TL, line, tw);
 #pragma unroll
     for (int b = 0; b < E / R0; ++b)
 #pragma unroll
       for (int r = 0; r < R0; ++r)
-        line[padpos<PI>(reg_pos<N, E, R0>(lane, b, r))] = v[b * R0 + r];
-    __syncthreads();
-    C *dst = out + (size_t)q * hsz + base;
-    for (int idx = threadIdx.x; idx < N * TL; idx += nthr) {
-      const int ln = idx % TL, z = idx / TL;
-      dst[(size_t)z * plane + ln] = lds[ln * LS + padpos<PI>(z)];
-    }
-    __syncthreads();
+        out[m * hsz + base + reg_pos<N, E, R0>(t, b, r) * plane] = v[m][b * R0 + r];
   }
 }
 
@@ -1503,36 +1434,29 @@ void interp_deriv(Handle &h, const double *x, const T *grids, const CompSet &cs,
 
 namespace {
 
-// Lines per workgroup of the wavefront-per-line kernel: 4 (64-byte FP64
-// row segments; measured as fast as 8 at 512^3 and half the LDS).
-template <typename T, int N> int wave_lines() {
-  using S = Shape<N, N / 64>;
-  constexpr int LS = xstride(N, S::first(false)) > xstride(N, S::first(true))
-                         ? xstride(N, S::first(false)) : xstride(N, S::first(true));
-  int tl = 4;
-  while (tl > 1 && (size_t)tl * LS * sizeof(cplx<T>) > 65536) tl /= 2;
-  return tl;
-}
-
 template <typename T, int N>
 void launch_fused(Handle &h, const cplx<T> *in, const CompSet &cin, cplx<T> *out,
                   const CompSet &cout, const cplx<T> *tw, bool dg) {
   using Tab = typename TabT<T>::type;
   const Tab *tab = sizeof(T) == 8 ? (const Tab *)h.ktab : (const Tab *)h.ktab32;
-  // FP64 derivative gridding at 512: one wavefront per line (measured 3.82
-  // -> 3.09 ms per launch at 512^3; the FP32 and moment launches are faster
-  // in the register-resident form below, which prefetches the next
-  // component's line while transforming the current one)
-  if constexpr (N == 512 && sizeof(T) == 8) {
+  // derivative gridding at 512: all three grids in registers, 128-byte row
+  // segments (measured 1.63 -> 1.32 ms per FP32 launch at 512^3, and 3.10 ->
+  // 2.65 ms in FP64, against the accumulating form below; at 256 the FP32
+  // form spills)
+  if constexpr (N == 512) {
     if (dg) {
-      using S = Shape<N, N / 64>;
-      constexpr int LS = xstride(N, S::first(false)) > xstride(N, S::first(true))
-                             ? xstride(N, S::first(false)) : xstride(N, S::first(true));
-      const int tl = wave_lines<T, N>();
-      const size_t lds = (size_t)tl * LS * sizeof(cplx<T>);
+      if (cin.n != 3 || cout.n != 3 || cin.idx[0] != 0 || cin.idx[1] != 1 || cin.idx[2] != 2 ||
+          cout.idx[0] != 0 || cout.idx[1] != 1 || cout.idx[2] != 2)
+        throw Error{PSE_ERR_INVALID, "derivative-gridded k-space takes grids 0, 1, 2"};
+      // the line passes' element count in FP32, half of it in FP64
+      constexpr int E = sizeof(T) == 4 ? line_e(N) : line_e(N) / 2;
+      constexpr int TPL = N / E;
+      int tl = (int)(128 / sizeof(cplx<T>));
+      while (tl > 1 && (tl * TPL > 512 || (size_t)tl * N * sizeof(cplx<T>) > 65536)) tl /= 2;
+      const size_t lds = (size_t)tl * N * sizeof(cplx<T>);
       const unsigned nb = (unsigned)(N * (N / 2 / tl));
-      hipLaunchKernelGGL((kspace_wave_kernel<T, N, true>), dim3(nb), dim3(64 * tl), lds,
-                         h.stream, in, cin, out, cout, kgeom(h), tab, tw, tl);
+      hipLaunchKernelGGL((kspace_dg3_kernel<T, N, E>), dim3(nb), dim3(tl * TPL), lds, h.stream,
+                         in, out, kgeom(h), tab, tw, tl);
       PSE_LAUNCH_CHECK();
       return;
     }
