@@ -98,15 +98,22 @@ typedef struct pse_params {
   int32_t graphs;          /* 0: replay each constraint-operator application
                               from a captured hipGraph (captured on first use
                               per input/output pair); -1: launch eagerly     */
-  int32_t deriv_gridding;  /* wave-space part of the constraint operator
-                              M_ES: 1 = the five stresslet moments gridded
-                              and transformed each way; 2 = three grids each
-                              way (stresslets spread with the Gaussian's
-                              gradient, strain interpolated with it), with
-                              one more support point when support = 0 (the
-                              gradient's quadrature error is about ten times
-                              the Gaussian's at equal support); falls back
-                              to 1 when that support exceeds 10;
+  int32_t deriv_gridding;  /* gridding of the wave-space products (Sec. II
+                              in couplets C and velocity gradients D):
+                              1 = every force, torque and stresslet
+                              component gridded as its own moment and
+                              transformed (up to eleven grids each way);
+                              2 = forces and velocities on three moment
+                              grids each, couplets (torques and stresslets
+                              together) spread with the Gaussian's gradient
+                              onto three grids and rotation and strain
+                              interpolated with it from three more: at most
+                              six grids each way, three each way for M_ES.
+                              The gradient weights are corrected per
+                              particle so that their discrete sum is zero
+                              and their first moment exact, and the support
+                              takes one more point when support = 0; falls
+                              back to 1 when that support exceeds 10.
                               0 = library default: 2 while the stencil
                               points per grid point N (P+1)^3 / Ng^3 stay
                               at most 20, else 1                            */
@@ -152,8 +159,7 @@ typedef struct pse_derived {
   int32_t cells;           /* cells per side of the real-space cell list     */
   int32_t lanczos_maxit, gmres_restart, gmres_maxit, refine_passes;
   double lanczos_tol, gmres_tol;
-  int32_t deriv_gridding;  /* gridding of M_ES in effect: 1 moments, 2
-                              derivative                                     */
+  int32_t deriv_gridding;  /* gridding in effect: 1 moments, 2 derivative */
   double lambda_max;       /* largest eigenvalue of A^T A (1 for the cube)   */
 } pse_derived;
 

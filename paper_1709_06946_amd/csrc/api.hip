@@ -214,6 +214,60 @@ static void wave_apply(Handle &h, const double *xw, const double *in, Layout lin
   interpolate<T>(h, xw, gout, cout, out, lout, accumulate, 1.0);
 }
 
+// Derivative gridding of a wave-space product (handles that use it): the
+// forces go onto three grids as their moments, the couplets (torques and
+// stresslets) onto three grids with the Gaussian's gradient; the velocity
+// comes from three grids by plain interpolation, rotation and strain from
+// the gradient of three more -- at most six grids each way instead of eleven.
+// It applies when the product involves a couplet on either side and every
+// input group (forces, torques, stresslets) is complete or absent.
+struct DGPlan {
+  bool ok = false, hf = false, hL = false, hS = false, hu = false, hv = false;
+  CompSet gin{}, gout{};   // grid codes (see kspace_fused)
+};
+
+static DGPlan dg_plan(const Handle &h, const CompSet &cin, const CompSet &cout) {
+  DGPlan d;
+  if (!h.deriv || h.def.on) return d;
+  int cnt[3] = {0, 0, 0}, last = -1;
+  for (int k = 0; k < cin.n; ++k) {
+    const int c = cin.idx[k];
+    if (c <= last) return d;
+    last = c;
+    ++cnt[c < 3 ? 0 : (c < 6 ? 1 : 2)];
+  }
+  if ((cnt[0] && cnt[0] != 3) || (cnt[1] && cnt[1] != 3) || (cnt[2] && cnt[2] != 5)) return d;
+  d.hf = cnt[0] > 0;
+  d.hL = cnt[1] > 0;
+  d.hS = cnt[2] > 0;
+  for (int k = 0; k < cout.n; ++k) (cout.idx[k] < 3 ? d.hu : d.hv) = true;
+  if (!(d.hL || d.hS || d.hv)) return d;   // forces to velocities: the moment product
+  // velocities alone are interpolated from their grids in order
+  if (!d.hv && !(cout.n == 3 && cout.idx[0] == 0 && cout.idx[1] == 1 && cout.idx[2] == 2))
+    return d;
+  if (d.hf) for (int k = 0; k < 3; ++k) d.gin.idx[d.gin.n++] = k;
+  if (d.hL || d.hS) for (int k = 3; k < 6; ++k) d.gin.idx[d.gin.n++] = k;
+  if (d.hu) for (int k = 0; k < 3; ++k) d.gout.idx[d.gout.n++] = k;
+  if (d.hv) for (int k = 3; k < 6; ++k) d.gout.idx[d.gout.n++] = k;
+  d.ok = d.gin.n > 0;
+  return d;
+}
+
+template <typename T>
+static void wave_apply_dg(Handle &h, const DGPlan &d, const double *xw, const double *in,
+                          Layout lin, const CompSet &cin, double *out, Layout lout,
+                          const CompSet &cout, bool accumulate) {
+  GridSet<T> &G = grids<T>(h);
+  T *gin = reinterpret_cast<T *>(G.gin), *gout = reinterpret_cast<T *>(G.gout);
+  if (d.hL || d.hS) spread_deriv<T>(h, in, lin, cin, d.hf, d.hL, d.hS, gin);
+  else spread<T>(h, xw, in, lin, cin, gin);   // forces only: their moment grids
+  rfft_xy<T>(h, gin, G.twiddle, d.gin.n, -1);
+  kspace_fused<T>(h, G.gin, d.gin, G.gout, d.gout, G.twiddle, true);
+  rfft_xy<T>(h, gout, G.twiddle, d.gout.n, +1);
+  if (d.hv) interp_deriv<T>(h, xw, gout, d.hu, cout, out, lout, accumulate, 1.0);
+  else interpolate<T>(h, xw, gout, cout, out, lout, accumulate, 1.0);
+}
+
 // out[cout] = M(cin -> cout) in[cin] at wrapped positions xw whose cell list
 // is current; in and out are particle vectors in layouts lin and lout.  fp64
 // forces the FP64 kernels in a mixed handle.
@@ -228,50 +282,23 @@ static void mobility(Handle &h, const double *xw, bool want_real, bool want_wave
     acc = true;
   }
   if (want_wave) {
-    if (f32) wave_apply<float>(h, xw, in, lin, cin, out, lout, cout, acc);
-    else wave_apply<double>(h, xw, in, lin, cin, out, lout, cout, acc);
+    const DGPlan d = dg_plan(h, cin, cout);
+    if (d.ok) {
+      if (f32) wave_apply_dg<float>(h, d, xw, in, lin, cin, out, lout, cout, acc);
+      else wave_apply_dg<double>(h, d, xw, in, lin, cin, out, lout, cout, acc);
+    } else {
+      if (f32) wave_apply<float>(h, xw, in, lin, cin, out, lout, cout, acc);
+      else wave_apply<double>(h, xw, in, lin, cin, out, lout, cout, acc);
+    }
   }
-}
-
-// Wave-space part of M_ES with derivative gridding: the stresslets spread
-// with the Gaussian's gradient onto three grids, the derivative k-space
-// factors, and the strain interpolated with the gradient (three grids each
-// way instead of five).
-template <typename T>
-static void wave_apply_dg(Handle &h, const double *xw, const double *in, Layout lin,
-                          const CompSet &cin, double *out, Layout lout, const CompSet &cout,
-                          bool accumulate) {
-  GridSet<T> &G = grids<T>(h);
-  T *gin = reinterpret_cast<T *>(G.gin), *gout = reinterpret_cast<T *>(G.gout);
-  const CompSet c3 = comps_range(0, 3);
-  spread_deriv<T>(h, in, lin, cin, gin);
-  rfft_xy<T>(h, gin, G.twiddle, 3, -1);
-  kspace_fused<T>(h, G.gin, c3, G.gout, c3, G.twiddle, true);
-  rfft_xy<T>(h, gout, G.twiddle, 3, +1);
-  interp_deriv<T>(h, xw, gout, cout, out, lout, accumulate, 1.0);
 }
 
 // out[E] = M_ES in[S] (layouts lin, lout), the operator of the stresslet
-// constraint: derivative gridding for the wave part when the handle uses
-// it, else the moment product.
+// constraint (derivative gridding for the wave part when the handle uses it).
 static void es_apply(Handle &h, const double *xw, bool want_real, bool want_wave,
                      const double *in, Layout lin, double *out, Layout lout, bool fp64) {
   const CompSet es = comps_range(6, 11);
-  if (!h.deriv) {
-    mobility(h, xw, want_real, want_wave, in, lin, es, out, lout, es, fp64);
-    return;
-  }
-  const bool f32 = h.mixed && !fp64;
-  bool acc = false;
-  if (want_real) {
-    if (f32) real_apply<float>(h, xw, in, lin, es, out, lout, es, false);
-    else real_apply<double>(h, xw, in, lin, es, out, lout, es, false);
-    acc = true;
-  }
-  if (want_wave) {
-    if (f32) wave_apply_dg<float>(h, xw, in, lin, es, out, lout, es, acc);
-    else wave_apply_dg<double>(h, xw, in, lin, es, out, lout, es, acc);
-  }
+  mobility(h, xw, want_real, want_wave, in, lin, es, out, lout, es, fp64);
 }
 
 template <typename T>
@@ -279,6 +306,14 @@ static void wave_sqrt_t(Handle &h, const double *xw, const double *psi, uint64_t
                         uint64_t counter, double *out, const CompSet &cout, Layout lout) {
   GridSet<T> &G = grids<T>(h);
   T *gout = reinterpret_cast<T *>(G.gout);
+  const DGPlan d = dg_plan(h, CompSet{}, cout);
+  if (d.hv) {
+    // derivative gridding of the rotation and strain outputs
+    kspace_noise<T>(h, psi, seed, counter, G.gout, d.gout, true);
+    rfft3d<T>(h, gout, G.twiddle, d.gout.n, +1);
+    interp_deriv<T>(h, xw, gout, d.hu, cout, out, lout, false, 1.0);
+    return;
+  }
   kspace_noise<T>(h, psi, seed, counter, G.gout, cout);
   rfft3d<T>(h, gout, G.twiddle, cout.n, +1);
   interpolate<T>(h, xw, gout, cout, out, lout, false, 1.0);
@@ -631,8 +666,8 @@ static void create(const pse_params &p, Handle &h) {
   // the list of an asynchronous handle cannot grow (no host read of its
   // length): twice the capacity up front
   h.pl_cap = (h.async ? 2 : 1) * pair_capacity(h.p, h.d);
-  handle_alloc(h, (void **)&h.pl_nbr, h.pl_cap * sizeof(int));
-  handle_alloc(h, (void **)&h.pl_rec, h.pl_cap * 10 * sizeof(double));
+  pair_storage(h, h.pl_cap, true);
+  if (h.deriv) handle_alloc(h, (void **)&h.dg_mu, 6 * n * sizeof(double));
   for (Bins *b : {&h.cells, &h.sbins}) {
     if (b->nc == 0) continue;
     const size_t ncells = (size_t)b->nc * b->nc * b->nc;
@@ -679,8 +714,9 @@ static void release(Handle &h) {
                   h.sbins.scat, h.sbins.perm, h.cells.trav, h.cells.bcount, h.cells.bstart,
                   h.xw, h.xh, h.v0, h.v1, h.v2, h.v3, h.v4, h.v5, h.es_b, h.es_x, h.es_r,
                   h.es_d, h.lz_V, h.gm_V, h.small, h.dots, h.ktab, h.pl_cnt,
-                  h.pl_start, h.pl_scan, h.pl_nbr, h.pl_rec, h.tl_cnt, h.tl_start,
-                  h.tl_scan, h.tl_rec, h.bad_pos, h.ktab32, h.dctl, h.dstats, h.dstep};
+                  h.pl_start, h.pl_scan, h.pl_nbr, h.pl_rec, h.pl_rec32, h.tl_cnt, h.tl_start,
+                  h.tl_scan, h.tl_rec, h.bad_pos, h.ktab32, h.dctl, h.dstats, h.dstep,
+                  h.dg_mu};
   if (!h.arena)
     for (void *p : ptrs) dev_free(p);
   clear_graphs(h);
@@ -876,14 +912,7 @@ int pse_set_krylov(pse_handle *hd, int async_calls, int lanczos_iters, int gmres
       const size_t want = h.pl_pairs + h.pl_pairs / 2 + 1024;
       if (h.pl_cap < want && !h.arena) {
         clear_graphs(h);
-        dev_free(h.pl_nbr);
-        dev_free(h.pl_rec);
-        h.pl_nbr = nullptr;
-        h.pl_rec = nullptr;
-        h.pl_cap = 0;
-        dev_alloc((void **)&h.pl_nbr, want * sizeof(int));
-        dev_alloc((void **)&h.pl_rec, want * 10 * sizeof(double));
-        h.pl_cap = want;
+        pair_storage(h, want, false);
       }
       h.lz_cap = lanczos_iters;
       h.gm_cap = gmres_iters;

@@ -243,26 +243,34 @@ spread_list_kernel(const double *__restrict__ q, Layout lq, CompSet cs, GridGeom
   }
 }
 
-// Derivative gridding of the stresslets (input of the constraint operator):
-// three grids D_i(x_n) = sum_b sum_j S_b,ij dK/dx_j (x_n - x_b), with S_b the
-// symmetric traceless tensor of the particle's five components in the Y_q
-// basis.  Their transform is i k . S^ K^, so the k-space factor of the
-// stresslet column, -3 i f1(ka) Y_q k, becomes -3 f1(ka) on D^ (Eq. WSops
-// with the gradient moved onto the Gaussian).  Tiles, records and staging as
+// Derivative gridding of the couplets: three grids
+// D_i(x_n) = sum_b sum_j C_b,ij dK/dx_j (x_n - x_b), with C_b = S_b + A_b the
+// particle's couplet, S_b the symmetric traceless stresslet of its five
+// components in the Y_q basis and A_b x = (1/2) L_b x x its torque.  Their
+// transform is i C^ k K^, so the k-space factors of the stresslet column,
+// -3 i f1(ka) Y_q k, and of the torque column, (3/2) i f1(ka) k x e_c,
+// become one factor -3 f1(ka) on D^ (Eq. WSops with the gradient moved onto
+// the Gaussian).  With HF the forces are spread as well, onto three grids
+// ahead of the couplet grids: F_i K (x_n - x_b), the moment gridding of F.
+// Input groups (forces 0-2, torques 3-5, stresslets 6-10) are either all in
+// cs or absent (hasL, hasS).  Tiles, records and staging as
 // spread_list_kernel; per candidate the gradient weights along each axis are
 // g_i = -2 kcoef (d0 + i h) w_i, and per point dK/dx = g_x w_y w_z, etc.
-template <typename T, int S, int ZPT>
+template <typename T, int S, int ZPT, bool HF>
 __global__ void __launch_bounds__(S * S * S / ZPT)
-spread_deriv_kernel(const double *__restrict__ q, Layout lq, CompSet cs, GridGeom g, int nb,
-                    const int *__restrict__ tstart, TileRecs rec, T *__restrict__ grids,
-                    size_t ngrid) {
+spread_deriv_kernel(const double *__restrict__ q, Layout lq, CompSet cs, int hasL, int hasS,
+                    GridGeom g, int nb, const int *__restrict__ tstart, TileRecs rec,
+                    const double *__restrict__ mu, T *__restrict__ grids, size_t ngrid) {
   constexpr int NT = S * S * S / ZPT;
   constexpr int RW = 3 * S + 3;
   constexpr int WPT = (GMAXC * RW + NT - 1) / NT;
+  constexpr int NQ = HF ? 12 : 9;      // per candidate: C (9), then F (3)
+  constexpr int NG = HF ? 6 : 3;
   static_assert(GMAXC <= NT, "one candidate per thread in the moment gather");
   __shared__ double raw[GMAXC * RW];
   __shared__ T wg[GMAXC * 6 * S];      // per candidate: w (3 S), then g (3 S)
-  __shared__ T st6[GMAXC * 6];         // per candidate: Sxx Syy Szz Sxy Sxz Syz
+  __shared__ T cq[GMAXC * NQ];
+  __shared__ double cmu[GMAXC * 6];   // per candidate: mu (3), lambda (3)
   const int tile = blockIdx.x;
   const int tc[3] = {tile % nb, (tile / nb) % nb, tile / (nb * nb)};
   const int lo = tstart[tile];
@@ -271,11 +279,13 @@ spread_deriv_kernel(const double *__restrict__ q, Layout lq, CompSet cs, GridGeo
   const int tid = threadIdx.x;
   const int lx = tid % S, ly = (tid / S) % S, z0 = (tid / (S * S)) * ZPT;
   const T r2 = (T)0.70710678118654752440, r6 = (T)0.40824829046386301637;
-  T acc[ZPT][3];
+  // positions of the groups in cs (cs lists them in increasing order)
+  const int kL = HF ? 3 : 0, kS = kL + (hasL ? 3 : 0);
+  T acc[ZPT][NG];
 #pragma unroll
   for (int z = 0; z < ZPT; ++z)
 #pragma unroll
-    for (int k = 0; k < 3; ++k) acc[z][k] = (T)0;
+    for (int k = 0; k < NG; ++k) acc[z][k] = (T)0;
   for (int c0 = 0; c0 < total; c0 += GMAXC) {
     const int nchunk = min(GMAXC, total - c0);
     const int nw = nchunk * RW;
@@ -289,17 +299,30 @@ spread_deriv_kernel(const double *__restrict__ q, Layout lq, CompSet cs, GridGeo
       wv[i] = t < nw ? wsrc[t] : 0.0;
     }
     if (tid < nchunk) {
-      T sq[5];
+      const double *qp = q + (size_t)pj * lq.stride - lq.off;
+      T sq[5] = {(T)0, (T)0, (T)0, (T)0, (T)0}, lh[3] = {(T)0, (T)0, (T)0};
+      if (hasS)
 #pragma unroll
-      for (int k = 0; k < 5; ++k)
-        sq[k] = (T)q[(size_t)pj * lq.stride + cs.idx[k] - lq.off];
-      T *o = st6 + tid * 6;
-      o[0] = r2 * sq[3] + r6 * sq[4];
-      o[1] = -r2 * sq[3] + r6 * sq[4];
-      o[2] = (T)-2 * r6 * sq[4];
-      o[3] = r2 * sq[0];
-      o[4] = r2 * sq[1];
-      o[5] = r2 * sq[2];
+        for (int k = 0; k < 5; ++k) sq[k] = (T)qp[cs.idx[kS + k]];
+      if (hasL)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) lh[k] = (T)0.5 * (T)qp[cs.idx[kL + k]];
+      const T sxy = r2 * sq[0], sxz = r2 * sq[1], syz = r2 * sq[2];
+      T *o = cq + tid * NQ;
+      o[0] = r2 * sq[3] + r6 * sq[4];          // Cxx
+      o[1] = sxy - lh[2];                      // Cxy
+      o[2] = sxz + lh[1];                      // Cxz
+      o[3] = sxy + lh[2];                      // Cyx
+      o[4] = -r2 * sq[3] + r6 * sq[4];         // Cyy
+      o[5] = syz - lh[0];                      // Cyz
+      o[6] = sxz - lh[1];                      // Czx
+      o[7] = syz + lh[0];                      // Czy
+      o[8] = (T)-2 * r6 * sq[4];               // Czz
+      if constexpr (HF)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) o[9 + k] = (T)qp[cs.idx[k]];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) cmu[tid * 6 + k] = mu[6 * (size_t)pj + k];
     }
 #pragma unroll
     for (int i = 0; i < WPT; ++i) {
@@ -312,24 +335,32 @@ spread_deriv_kernel(const double *__restrict__ q, Layout lq, CompSet cs, GridGeo
       const double w = raw[j * RW + r];
       const double dx = raw[j * RW + 3 * S + d] + i * g.h;
       wg[j * 6 * S + r] = (T)w;
-      wg[j * 6 * S + 3 * S + r] = (T)(-2.0 * g.kcoef * dx * w);
+      wg[j * 6 * S + 3 * S + r] =
+          (T)(cmu[j * 6 + 3 + d] * (-2.0 * g.kcoef * dx - cmu[j * 6 + d]) * w);
     }
     __syncthreads();
     for (int j = 0; j < nchunk; ++j) {
-      const T *wj = wg + j * 6 * S, *gj = wj + 3 * S, *sj = st6 + j * 6;
+      const T *wj = wg + j * 6 * S, *gj = wj + 3 * S, *cj = cq + j * NQ;
       const T gxwy = gj[lx] * wj[S + ly], wxgy = wj[lx] * gj[S + ly], wxwy = wj[lx] * wj[S + ly];
-      const T sxx = sj[0], syy = sj[1], szz = sj[2], sxy = sj[3], sxz = sj[4], syz = sj[5];
-      // D_i = (S_ix g_x w_y + S_iy w_x g_y) w_z + S_iz w_x w_y g_z: the two
+      // D_i = (C_ix g_x w_y + C_iy w_x g_y) w_z + C_iz w_x w_y g_z: the two
       // brackets are constant along the thread's z-column
-      const T ax = sxx * gxwy + sxy * wxgy, ay = sxy * gxwy + syy * wxgy;
-      const T az = sxz * gxwy + syz * wxgy;
-      const T bx = sxz * wxwy, by = syz * wxwy, bz = szz * wxwy;
+      T a[3], b[3], f[3];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        a[i] = cj[3 * i] * gxwy + cj[3 * i + 1] * wxgy;
+        b[i] = cj[3 * i + 2] * wxwy;
+      }
+      if constexpr (HF)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) f[i] = cj[9 + i] * wxwy;
 #pragma unroll
       for (int z = 0; z < ZPT; ++z) {
         const T wz = wj[2 * S + z0 + z], gz = gj[2 * S + z0 + z];
-        acc[z][0] += ax * wz + bx * gz;
-        acc[z][1] += ay * wz + by * gz;
-        acc[z][2] += az * wz + bz * gz;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          if constexpr (HF) acc[z][i] += f[i] * wz;
+          acc[z][NG - 3 + i] += a[i] * wz + b[i] * gz;
+        }
       }
     }
   }
@@ -338,7 +369,7 @@ spread_deriv_kernel(const double *__restrict__ q, Layout lq, CompSet cs, GridGeo
     const size_t gi = ((size_t)(tc[2] * S + z0 + z) * ng + tc[1] * S + ly) * ng
                       + tc[0] * S + lx;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) grids[(size_t)k * ngrid + gi] = acc[z][k];
+    for (int k = 0; k < NG; ++k) grids[(size_t)k * ngrid + gi] = acc[z][k];
   }
 }
 
@@ -657,10 +688,11 @@ __device__ __forceinline__ bool zero_mode(int ix, int iy, int iz, int n) {
 // in the same registers -- the inverse transform runs the passes in reverse
 // order, so its input layout is the forward output layout -- transformed back
 // along z and stored.  One read of the inputs and one write of the outputs.
-// DG (derivative gridding of the constraint operator): the inputs are the
-// three grids D^ of the stresslets spread with the Gaussian's gradient, so
-// rho = -3 f1(ka) D^, and the outputs are the three grids v^ = 3 f1(ka) u^
-// whose gradient the interpolation takes.
+// DG (derivative gridding): the components are grid codes, 0-2 the force
+// grids F^ (factor j0(ka)) and 3-5 the couplet grids D^ spread with the
+// Gaussian's gradient (factor -3 f1(ka)) on input, so rho = j0 F^ - 3 f1 D^;
+// on output 0-2 the velocity grids j0(ka) u^ and 3-5 the grids
+// v^ = 3 f1(ka) u^ whose gradient the interpolation takes.
 template <typename T, int N, bool DG>
 __global__ void __launch_bounds__(512)
 kspace_fused_kernel(const cplx<T> *__restrict__ in, CompSet cin, cplx<T> *__restrict__ out,
@@ -705,7 +737,7 @@ kspace_fused_kernel(const cplx<T> *__restrict__ in, CompSet cin, cplx<T> *__rest
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const auto tb = entry(e);
-      tj0[e] = DG ? (T)0 : (T)tb.x;
+      tj0[e] = (T)tb.x;
       tf1[e] = (T)tb.y;
       tsc[e] = (T)tb.z;
     }
@@ -745,11 +777,11 @@ kspace_fused_kernel(const cplx<T> *__restrict__ in, CompSet cin, cplx<T> *__rest
         const int iz = reg_pos<N, E, RL>(t, b, r);
         if (zero_mode(ix, iy, iz, N)) continue;
         if constexpr (DG) {
-          const T f = (T)-3 * f1_at(b * RL + r);
+          const T f = c < 3 ? j0_at(b * RL + r) : (T)-3 * f1_at(b * RL + r);
           const C vv = v[b * RL + r];
 #pragma unroll
           for (int m = 0; m < 3; ++m)
-            if (m == c) {
+            if (m == c % 3) {
               rho[b * RL + r][m].x += f * vv.x;
               rho[b * RL + r][m].y += f * vv.y;
             }
@@ -801,11 +833,11 @@ kspace_fused_kernel(const cplx<T> *__restrict__ in, CompSet cin, cplx<T> *__rest
           continue;
         }
         if constexpr (DG) {
-          const T f = (T)3 * f1_at(e);
+          const T f = c < 3 ? j0_at(e) : (T)3 * f1_at(e);
           v[e] = C{(T)0, (T)0};
 #pragma unroll
           for (int m = 0; m < 3; ++m)
-            if (m == c) v[e] = C{f * rho[e][m].x, f * rho[e][m].y};
+            if (m == c % 3) v[e] = C{f * rho[e][m].x, f * rho[e][m].y};
         } else {
           const T kv[3] = {tp * ix, tp * ky, tp * kidx(iz, N)};
           v[e] = apply_Pdag<C, T>(c, rho[e], kv, j0_at(e), f1_at(e));
@@ -823,7 +855,7 @@ kspace_fused_kernel(const cplx<T> *__restrict__ in, CompSet cin, cplx<T> *__rest
 // Derivative gridding on long lines with all three grids in registers: a
 // workgroup owns TL neighbouring kx columns at one ky (row segments of up to
 // 128 bytes), and the TPL threads of a line hold E modes of each of the
-// three grids D^.  Every load is issued before the first transform; the
+// three couplet grids D^.  Every load is issued before the first transform; the
 // three forward z transforms run one after the other through one LDS area;
 // each mode is then folded with its three components at hand,
 // out = -9 f1^2 scale (I - k^k^) D^; and the three inverse transforms
@@ -951,7 +983,7 @@ enum : uint32_t { STREAM_REAL = 1, STREAM_WAVE = 2 };
 template <typename T>
 __global__ void __launch_bounds__(256)
 kspace_noise_kernel(const double2 *__restrict__ psi, uint64_t seed, uint64_t counter,
-                    cplx<T> *__restrict__ out, CompSet cout, KGeom kg,
+                    cplx<T> *__restrict__ out, CompSet cout, int dg, KGeom kg,
                     const double4 *__restrict__ ktab, const uint64_t *counter_dev) {
   using C = cplx<T>;
   const int n = kg.ng, hx = n / 2, hp = n / 2 + 1;
@@ -1014,7 +1046,15 @@ kspace_noise_kernel(const double2 *__restrict__ psi, uint64_t seed, uint64_t cou
     uu[m].y = tb.w * (ps[m].y - iv[m] * kr.y * inv);
   }
   for (int q = 0; q < cout.n; ++q) {
-    const double2 w = apply_Pdag<double2, double>(cout.idx[q], uu, kv, tb.x, tb.y);
+    const int c = cout.idx[q];
+    double2 w;
+    if (dg) {
+      // grid codes of derivative gridding: j0(ka) u^ (0-2), 3 f1(ka) u^ (3-5)
+      const double f = c < 3 ? tb.x : 3.0 * tb.y;
+      w = double2{f * uu[c % 3].x, f * uu[c % 3].y};
+    } else {
+      w = apply_Pdag<double2, double>(c, uu, kv, tb.x, tb.y);
+    }
     out[q * hsz + tid] = C{(T)w.x, (T)w.y};
   }
 }
@@ -1179,6 +1219,51 @@ void build_tile_lists(Handle &h, const double *xw) {
   PSE_LAUNCH_CHECK();
 }
 
+// Moment correction of the gradient weights of derivative gridding.  On the
+// grid the gradient of the truncated Gaussian does not have the moments of
+// the continuous one: along axis d its one-dimensional weights
+// g_i = dK1/dx (x_i - x) sum to mu_d times the Gaussian's, sum_i g_i =
+// mu_d sum_i w_i, with mu_d a small number that depends on the particle's
+// offset from the grid, and their first moment sum_i d_i g_i (d_i = x_i - x)
+// differs from -sum_i w_i, its continuous value.  A spread couplet then
+// leaves a spurious monopole in the smallest wave numbers, where the Stokes
+// kernel amplifies it, and the interpolated gradient of a smooth field picks
+// up the field itself.  Spreading and interpolation take instead
+// lambda_d (g_i - mu_d w_i), still separable, whose discrete sum is zero and
+// whose first moment is -sum_i w_i: the gradient of a constant field is
+// zero and that of a linear field exact, relative to the Gaussian's own
+// normalisation.  mu and lambda (three each per particle) are formed once
+// per position update.
+__global__ void __launch_bounds__(256)
+dg_mu_kernel(const double *__restrict__ x, int64_t n, GridGeom g, double *__restrict__ mu) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 3 * n) return;
+  const double xc = x[t];
+  const int i0 = stencil_start(xc, g.h, g.P);
+  double s0 = 0.0, s1 = 0.0, sd = 0.0, sd1 = 0.0;
+  for (int i = 0; i < g.P; ++i) {
+    const double d = (i0 + i) * g.h - xc;
+    const double w = exp(-g.kcoef * d * d);
+    const double gi = -2.0 * g.kcoef * d * w;
+    s0 += w;
+    s1 += gi;
+    sd += d * w;
+    sd1 += d * gi;
+  }
+  const double m = s1 / s0;
+  // sum_i d_i (g_i - m w_i) = sd1 - m sd
+  const int64_t p = t / 3, ax = t % 3;
+  mu[6 * p + ax] = m;
+  mu[6 * p + 3 + ax] = -s0 / (sd1 - m * sd);
+}
+
+void build_dg_mu(Handle &h, const double *xw) {
+  if (!h.deriv) return;
+  hipLaunchKernelGGL(dg_mu_kernel, dim3(nblocks(3 * (size_t)h.n, 256)), dim3(256), 0, h.stream,
+                     xw, h.n, geom(h), h.dg_mu);
+  PSE_LAUNCH_CHECK();
+}
+
 size_t tile_record_bytes(int S) { return sizeof(int) + (3 * (size_t)S + 3) * sizeof(double); }
 
 namespace {
@@ -1193,18 +1278,23 @@ template <typename F> void with_ncm(int n, F f) {
 
 }  // namespace
 
-// Strain from derivative gridding (output of the constraint operator): with
-// v = the three velocity grids of the k-space factor 3 f1(ka) u^, the strain
-// is e_q = -Y_q : sum_n v(x_n) (x) grad K(x_n - x_p) (the interpolation of
-// Y_q : grad v with the gradient moved onto the Gaussian).  One wavefront per
-// particle as interp_kernel; per stencil point the gradient weight is
-// -2 kcoef d K(d), d = x_n - x_p; the sums T_ij = v_i dK/dx_j enter only
-// through their symmetric traceless part.
-template <typename T, int MAXIT>
+// Rotation and strain from derivative gridding: with v = the three velocity
+// grids of the k-space factor 3 f1(ka) u^, and the sums
+// G_ij = sum_n v_i(x_n) dK/dx_j (x_n - x_p) = -(d v_i / d x_j)(x_p) (the
+// interpolation of grad v with the gradient moved onto the Gaussian), the
+// strain is e_q = Y_q : grad v and the rotation curl v / 2 (the adjoints of
+// the stresslet and torque columns).  With HU the three grids of j0(ka) u^
+// come first and give the velocity by plain interpolation.  One wavefront
+// per particle as interp_kernel; per stencil point the gradient weight is
+// lambda (-2 kcoef d - mu) K(d), d = x_n - x_p, with the moment corrections
+// mu, lambda of the particle (see dg_mu_kernel).  cs: the output components (velocity 0-2
+// with HU, rotation 3-5, strain 6-10), any subset.
+template <typename T, int MAXIT, bool HU>
 __global__ void __launch_bounds__(256)
 interp_deriv_kernel(const double *__restrict__ x, const T *__restrict__ grids, size_t ngrid,
-                    CompSet cs, GridGeom g, const int *__restrict__ order, int64_t n,
-                    double *__restrict__ out, Layout lo, int accumulate, double scale) {
+                    CompSet cs, int rot, GridGeom g, const int *__restrict__ order, int64_t n,
+                    const double *__restrict__ mu, double *__restrict__ out, Layout lo,
+                    int accumulate, double scale) {
   const int lane = threadIdx.x & 63;
   const int64_t t = (int64_t)xcd_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
   if (t >= n) return;
@@ -1215,49 +1305,63 @@ interp_deriv_kernel(const double *__restrict__ x, const T *__restrict__ grids, s
   const int iy0 = stencil_start(py, g.h, P);
   const int iz0 = stencil_start(pz, g.h, P);
   const double kn3 = g.knorm * g.knorm * g.knorm;
-  // Txx, Tyy, Tzz, Txy + Tyx, Txz + Tzx, Tyz + Tzy
-  T acc[6];
+  const double mx = mu[6 * p], my = mu[6 * p + 1], mz = mu[6 * p + 2];
+  const double lx = mu[6 * p + 3], ly = mu[6 * p + 4], lz = mu[6 * p + 5];
+  const T *vg = grids + (HU ? 3 * ngrid : 0);
+  // G (row-major, 9) and the velocity (3)
+  T acc[12];
 #pragma unroll
-  for (int k = 0; k < 6; ++k) acc[k] = (T)0;
+  for (int k = 0; k < 12; ++k) acc[k] = (T)0;
   bool done = false;
   if constexpr (MAXIT == 8) {
     if (P == 8) {
       // the lane's points share x and y: with dK/dx_i = c d_i e (c = -2
       // kcoef knorm^3, e the Gaussian), the column sums s_k = sum v_k e and
-      // z_k = sum v_k e dz give every T_ij
+      // z_k = sum v_k e dz give every G_ij
       size_t gi[8];
       double e[8], dz[8], dx, dy;
       stencil8(lane, px, py, pz, ix0, iy0, iz0, g, gi, e, dz, dx, dy);
-      T v[3][8];
+      T v[3][8], u[HU ? 3 : 1][8];
 #pragma unroll
       for (int k = 0; k < 3; ++k)
 #pragma unroll
-        for (int it = 0; it < 8; ++it) v[k][it] = grids[(size_t)k * ngrid + gi[it]];
-      T sk[3] = {(T)0, (T)0, (T)0}, zk[3] = {(T)0, (T)0, (T)0};
+        for (int it = 0; it < 8; ++it) v[k][it] = vg[(size_t)k * ngrid + gi[it]];
+      if constexpr (HU)
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+          for (int it = 0; it < 8; ++it) u[k][it] = grids[(size_t)k * ngrid + gi[it]];
+      // moment correction: lambda_i (dK/dx_i - mu_i K) = lambda_i c (d_i - mu_i / (-2 kcoef)) e
+      T sk[3] = {(T)0, (T)0, (T)0}, zk[3] = {(T)0, (T)0, (T)0}, uk[3] = {(T)0, (T)0, (T)0};
+      const double sh = 1.0 / (-2.0 * g.kcoef);
+      dx -= mx * sh;
+      dy -= my * sh;
 #pragma unroll
       for (int it = 0; it < 8; ++it) {
-        const T et = (T)e[it], dzt = (T)dz[it];
+        const T et = (T)e[it], dzt = (T)(dz[it] - mz * sh);
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
           const T ve = v[k][it] * et;
           sk[k] += ve;
           zk[k] += ve * dzt;
+          if constexpr (HU) uk[k] += u[k][it] * et;
         }
       }
       const double c = -2.0 * g.kcoef * kn3;
-      const T c0 = (T)c, cx = (T)(c * dx), cy = (T)(c * dy);
-      acc[0] = cx * sk[0];
-      acc[1] = cy * sk[1];
-      acc[2] = c0 * zk[2];
-      acc[3] = cy * sk[0] + cx * sk[1];
-      acc[4] = c0 * zk[0] + cx * sk[2];
-      acc[5] = c0 * zk[1] + cy * sk[2];
+      const T c0 = (T)(c * lz), cx = (T)(c * lx * dx), cy = (T)(c * ly * dy);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        acc[3 * k] = cx * sk[k];
+        acc[3 * k + 1] = cy * sk[k];
+        acc[3 * k + 2] = c0 * zk[k];
+        if constexpr (HU) acc[9 + k] = (T)kn3 * uk[k];
+      }
       done = true;
     }
   }
   if (!done) {
     size_t gi[MAXIT];
-    T gw[MAXIT][3];
+    T gw[MAXIT][3], w0[MAXIT];
     double f1[3];
     factors1d(lane, px, py, pz, ix0, iy0, iz0, g, f1);
 #pragma unroll
@@ -1269,10 +1373,11 @@ interp_deriv_kernel(const double *__restrict__ x, const T *__restrict__ grids, s
       const double dz = (iz0 + c) * g.h - pz;
       const bool in = s < P3;
       const double e = gauss_at(f1, a, b, c);
-      const double f = in ? -2.0 * g.kcoef * kn3 * e : 0.0;
-      gw[it][0] = (T)(f * dx);
-      gw[it][1] = (T)(f * dy);
-      gw[it][2] = (T)(f * dz);
+      const double f = in ? kn3 * e : 0.0;
+      gw[it][0] = (T)(f * lx * (-2.0 * g.kcoef * dx - mx));
+      gw[it][1] = (T)(f * ly * (-2.0 * g.kcoef * dy - my));
+      gw[it][2] = (T)(f * lz * (-2.0 * g.kcoef * dz - mz));
+      w0[it] = (T)f;
       gi[it] = in ? ((size_t)wrapi(iz0 + c, g.ng) * g.ng + wrapi(iy0 + b, g.ng)) * g.ng
                         + wrapi(ix0 + a, g.ng)
                   : 0;
@@ -1281,32 +1386,60 @@ interp_deriv_kernel(const double *__restrict__ x, const T *__restrict__ grids, s
 #pragma unroll
     for (int k = 0; k < 3; ++k)
 #pragma unroll
-      for (int it = 0; it < MAXIT; ++it) v[k][it] = grids[(size_t)k * ngrid + gi[it]];
+      for (int it = 0; it < MAXIT; ++it) v[k][it] = vg[(size_t)k * ngrid + gi[it]];
 #pragma unroll
-    for (int it = 0; it < MAXIT; ++it) {
-      acc[0] += v[0][it] * gw[it][0];
-      acc[1] += v[1][it] * gw[it][1];
-      acc[2] += v[2][it] * gw[it][2];
-      acc[3] += v[0][it] * gw[it][1] + v[1][it] * gw[it][0];
-      acc[4] += v[0][it] * gw[it][2] + v[2][it] * gw[it][0];
-      acc[5] += v[1][it] * gw[it][2] + v[2][it] * gw[it][1];
+    for (int it = 0; it < MAXIT; ++it)
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) acc[3 * k + j] += v[k][it] * gw[it][j];
+    if constexpr (HU) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        T u[MAXIT];
+#pragma unroll
+        for (int it = 0; it < MAXIT; ++it) u[it] = grids[(size_t)k * ngrid + gi[it]];
+#pragma unroll
+        for (int it = 0; it < MAXIT; ++it) acc[9 + k] += w0[it] * u[it];
+      }
     }
   }
+  // wavefront sums: the symmetric part always, the antisymmetric part for a
+  // rotation, the velocity with HU
+  T r[12];
+  r[0] = acc[0];                 // Gxx
+  r[1] = acc[4];                 // Gyy
+  r[2] = acc[8];                 // Gzz
+  r[3] = acc[1] + acc[3];        // Gxy + Gyx
+  r[4] = acc[2] + acc[6];        // Gxz + Gzx
+  r[5] = acc[5] + acc[7];        // Gyz + Gzy
+  r[6] = acc[7] - acc[5];        // Gzy - Gyz
+  r[7] = acc[2] - acc[6];        // Gxz - Gzx
+  r[8] = acc[3] - acc[1];        // Gyx - Gxy
+  r[9] = acc[9];
+  r[10] = acc[10];
+  r[11] = acc[11];
+  const int nr = HU ? 12 : (rot ? 9 : 6);
 #pragma unroll
-  for (int k = 0; k < 6; ++k) {
-    T w = acc[k];
-    for (int off = 32; off > 0; off >>= 1) w += __shfl_xor(w, off, 64);
-    acc[k] = w;
+  for (int k = 0; k < 12; ++k) {
+    if (k < nr) {
+      T w = r[k];
+      for (int off = 32; off > 0; off >>= 1) w += __shfl_xor(w, off, 64);
+      r[k] = w;
+    }
   }
   if (lane == 0) {
     const double r2 = 0.70710678118654752440, r6 = 0.40824829046386301637;
-    const double txx = acc[0], tyy = acc[1], tzz = acc[2];
-    const double e[5] = {-r2 * (double)acc[3], -r2 * (double)acc[4], -r2 * (double)acc[5],
-                         -r2 * (txx - tyy), -r6 * (txx + tyy - 2.0 * tzz)};
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
-      double *o = out + p * lo.stride + cs.idx[k] - lo.off;
-      const double val = scale * e[k];
+    for (int k = 0; k < cs.n; ++k) {
+      const int c = cs.idx[k];
+      double val;
+      if (c < 3) val = (double)r[9 + c];
+      else if (c < 6) val = -0.5 * (double)r[3 + c];   // rotation: -(G_ji - G_ij) / 2
+      else if (c < 9) val = -r2 * (double)r[c - 3];
+      else if (c == 9) val = -r2 * ((double)r[0] - (double)r[1]);
+      else val = -r6 * ((double)r[0] + (double)r[1] - 2.0 * (double)r[2]);
+      double *o = out + p * lo.stride + c - lo.off;
+      val *= scale;
       *o = accumulate ? *o + val : val;
     }
   }
@@ -1384,51 +1517,64 @@ void interpolate(Handle &h, const double *x, const T *grids, const CompSet &cs, 
 // stresslet components cs (five, in the Y_q basis) of q in layout lq spread
 // onto three grids with the Gaussian's gradient.
 template <typename T>
-void spread_deriv(Handle &h, const double *q, Layout lq, const CompSet &cs, T *grids) {
-  if (!h.stile || cs.n != 5) throw Error{PSE_ERR_INVALID, "derivative gridding unavailable"};
+void spread_deriv(Handle &h, const double *q, Layout lq, const CompSet &cs, bool hf, bool hasL,
+                  bool hasS, T *grids) {
+  if (!h.stile) throw Error{PSE_ERR_INVALID, "derivative gridding unavailable"};
   const GridGeom g = geom(h);
-  ProfScope ps(h, PK_SPREAD, 3.0 * h.ngrid * sizeof(T) + (double)h.n * (3 + 5) * 8);
+  const int ng = hf ? 6 : 3;
+  ProfScope ps(h, PK_SPREAD, (double)ng * h.ngrid * sizeof(T) + (double)h.n * (3 + cs.n) * 8);
   const int nb = h.sbins.nc;
   const unsigned tiles = (unsigned)nb * nb * nb;
   const TileRecs rec = tile_recs(h);
   const int *ts = (const int *)h.tl_start;
-  if (h.stile == 4)
-    hipLaunchKernelGGL((spread_deriv_kernel<T, 4, 1>), dim3(tiles), dim3(64), 0, h.stream, q,
-                       lq, cs, g, nb, ts, rec, grids, h.ngrid);
-  else if (h.stile == 8)
-    hipLaunchKernelGGL((spread_deriv_kernel<T, 8, 4>), dim3(tiles), dim3(128), 0, h.stream, q,
-                       lq, cs, g, nb, ts, rec, grids, h.ngrid);
-  else
+  const int L = hasL ? 1 : 0, S3 = hasS ? 1 : 0;
+  if (h.stile == 4) {
+    if (hf)
+      hipLaunchKernelGGL((spread_deriv_kernel<T, 4, 1, true>), dim3(tiles), dim3(64), 0,
+                         h.stream, q, lq, cs, L, S3, g, nb, ts, rec, h.dg_mu, grids, h.ngrid);
+    else
+      hipLaunchKernelGGL((spread_deriv_kernel<T, 4, 1, false>), dim3(tiles), dim3(64), 0,
+                         h.stream, q, lq, cs, L, S3, g, nb, ts, rec, h.dg_mu, grids, h.ngrid);
+  } else if (h.stile == 8) {
+    if (hf)
+      hipLaunchKernelGGL((spread_deriv_kernel<T, 8, 4, true>), dim3(tiles), dim3(128), 0,
+                         h.stream, q, lq, cs, L, S3, g, nb, ts, rec, h.dg_mu, grids, h.ngrid);
+    else
+      hipLaunchKernelGGL((spread_deriv_kernel<T, 8, 4, false>), dim3(tiles), dim3(128), 0,
+                         h.stream, q, lq, cs, L, S3, g, nb, ts, rec, h.dg_mu, grids, h.ngrid);
+  } else {
     throw Error{PSE_ERR_INVALID, "unsupported spreading tile"};
+  }
   PSE_LAUNCH_CHECK();
 }
 
-// The strain components cs (five) of out in layout lo from the three
-// velocity grids of derivative gridding (see interp_deriv_kernel).
+// Velocity (with hu), rotation and strain components cs of out in layout lo
+// from the grids of derivative gridding (see interp_deriv_kernel).
 template <typename T>
-void interp_deriv(Handle &h, const double *x, const T *grids, const CompSet &cs, double *out,
-                  Layout lo, bool accumulate, double scale) {
-  if (cs.n != 5) throw Error{PSE_ERR_INVALID, "derivative gridding unavailable"};
+void interp_deriv(Handle &h, const double *x, const T *grids, bool hu, const CompSet &cs,
+                  double *out, Layout lo, bool accumulate, double scale) {
   const GridGeom g = geom(h);
   const int acc = accumulate ? 1 : 0;
-  ProfScope ps(h, PK_INTERP, 3.0 * h.ngrid * sizeof(T) + (double)h.n * (3 + 5) * 8);
+  int rot = 0;
+  for (int k = 0; k < cs.n; ++k) rot |= cs.idx[k] >= 3 && cs.idx[k] < 6;
+  ProfScope ps(h, PK_INTERP, (hu ? 6.0 : 3.0) * h.ngrid * sizeof(T) + (double)h.n * (3 + cs.n) * 8);
   const int P3 = g.P * g.P * g.P;
   const dim3 grid(nblocks(h.n, 4)), block(256);
   const int *order = (const int *)h.cells.trav;
-  if (P3 <= 256)
-    hipLaunchKernelGGL((interp_deriv_kernel<T, 4>), grid, block, 0, h.stream, x, grids,
-                       h.ngrid, cs, g, order, h.n, out, lo, acc, scale);
-  else if (P3 <= 384)
-    hipLaunchKernelGGL((interp_deriv_kernel<T, 6>), grid, block, 0, h.stream, x, grids,
-                       h.ngrid, cs, g, order, h.n, out, lo, acc, scale);
-  else if (P3 <= 512)
-    hipLaunchKernelGGL((interp_deriv_kernel<T, 8>), grid, block, 0, h.stream, x, grids,
-                       h.ngrid, cs, g, order, h.n, out, lo, acc, scale);
-  else if (P3 <= 1024)
-    hipLaunchKernelGGL((interp_deriv_kernel<T, 16>), grid, block, 0, h.stream, x, grids,
-                       h.ngrid, cs, g, order, h.n, out, lo, acc, scale);
-  else
-    throw Error{PSE_ERR_INVALID, "derivative gridding supports P <= 10"};
+  const auto launch = [&](auto maxit) {
+    constexpr int MI = decltype(maxit)::value;
+    if (hu)
+      hipLaunchKernelGGL((interp_deriv_kernel<T, MI, true>), grid, block, 0, h.stream, x, grids,
+                         h.ngrid, cs, rot, g, order, h.n, h.dg_mu, out, lo, acc, scale);
+    else
+      hipLaunchKernelGGL((interp_deriv_kernel<T, MI, false>), grid, block, 0, h.stream, x, grids,
+                         h.ngrid, cs, rot, g, order, h.n, h.dg_mu, out, lo, acc, scale);
+  };
+  if (P3 <= 256) launch(std::integral_constant<int, 4>());
+  else if (P3 <= 384) launch(std::integral_constant<int, 6>());
+  else if (P3 <= 512) launch(std::integral_constant<int, 8>());
+  else if (P3 <= 1024) launch(std::integral_constant<int, 16>());
+  else throw Error{PSE_ERR_INVALID, "derivative gridding supports P <= 10"};
   PSE_LAUNCH_CHECK();
 }
 
@@ -1439,15 +1585,16 @@ void launch_fused(Handle &h, const cplx<T> *in, const CompSet &cin, cplx<T> *out
                   const CompSet &cout, const cplx<T> *tw, bool dg) {
   using Tab = typename TabT<T>::type;
   const Tab *tab = sizeof(T) == 8 ? (const Tab *)h.ktab : (const Tab *)h.ktab32;
-  // derivative gridding at 512: all three grids in registers, 128-byte row
+  // the constraint operator's derivative gridding at 512 (couplet grids
+  // each way): all three grids in registers, 128-byte row
   // segments (measured 1.63 -> 1.32 ms per FP32 launch at 512^3, and 3.10 ->
   // 2.65 ms in FP64, against the accumulating form below; at 256 the FP32
   // form spills)
+  const auto couplet3 = [](const CompSet &c) {
+    return c.n == 3 && c.idx[0] == 3 && c.idx[1] == 4 && c.idx[2] == 5;
+  };
   if constexpr (N == 512) {
-    if (dg) {
-      if (cin.n != 3 || cout.n != 3 || cin.idx[0] != 0 || cin.idx[1] != 1 || cin.idx[2] != 2 ||
-          cout.idx[0] != 0 || cout.idx[1] != 1 || cout.idx[2] != 2)
-        throw Error{PSE_ERR_INVALID, "derivative-gridded k-space takes grids 0, 1, 2"};
+    if (dg && couplet3(cin) && couplet3(cout)) {
       // the line passes' element count in FP32, half of it in FP64
       constexpr int E = sizeof(T) == 4 ? line_e(N) : line_e(N) / 2;
       constexpr int TPL = N / E;
@@ -1503,11 +1650,11 @@ void kspace_deformed(Handle &h, const cplx<T> *in, const CompSet &cin, cplx<T> *
 
 template <typename T>
 void kspace_noise(Handle &h, const double *psi, uint64_t seed, uint64_t counter,
-                  cplx<T> *out, const CompSet &cout) {
+                  cplx<T> *out, const CompSet &cout, bool dg) {
   const size_t hsz = h.ngrid / 2;
   ProfScope ps(h, PK_NOISE, (double)cout.n * hsz * sizeof(cplx<T>) + (psi ? 3.0 * hsz * 16 : 0.0));
   hipLaunchKernelGGL(kspace_noise_kernel<T>, dim3(nblocks(hsz, 256)), dim3(256),
-                     0, h.stream, (const double2 *)psi, seed, counter, out, cout,
+                     0, h.stream, (const double2 *)psi, seed, counter, out, cout, dg ? 1 : 0,
                      kgeom(h), (const double4 *)h.ktab, h.counter_dev);
   PSE_LAUNCH_CHECK();
 }
@@ -1545,13 +1692,13 @@ template <typename T> void to_double(Handle &h, const T *src, size_t n, double *
   template void kspace_deformed<T>(Handle &, const cplx<T> *, const CompSet &,   \
                                    cplx<T> *, const CompSet &);                  \
   template void kspace_noise<T>(Handle &, const double *, uint64_t, uint64_t,    \
-                                cplx<T> *, const CompSet &);                     \
+                                cplx<T> *, const CompSet &, bool);               \
   template void kspace_fused<T>(Handle &, const cplx<T> *, const CompSet &,      \
                                 cplx<T> *, const CompSet &, const cplx<T> *,     \
                                 bool);                                           \
   template void spread_deriv<T>(Handle &, const double *, Layout, const CompSet &, \
-                                T *);                                            \
-  template void interp_deriv<T>(Handle &, const double *, const T *,             \
+                                bool, bool, bool, T *);                          \
+  template void interp_deriv<T>(Handle &, const double *, const T *, bool,       \
                                 const CompSet &, double *, Layout, bool, double); \
   template void zero_grids<T>(Handle &, T *, int);                               \
   template void from_double<T>(Handle &, const double *, size_t, T *);           \

@@ -154,16 +154,18 @@ void derive(const pse_params &p, pse_derived &d) {
   const double eps_q = eps / 20.0;
   d.support = p.support > 0 ? p.support
                             : (int)std::ceil(df.lambda_max * 2.0 / M_PI * std::log(2.0 / eps_q));
-  // Derivative gridding of M_ES: the gradient of the truncated Gaussian
-  // carries about ten times the Gaussian's quadrature error at equal support
-  // (each further point divides both by about 3.5), so with an automatic
-  // support it takes one more point; it needs the spreading tiles and at
-  // most 10 points, else the moment gridding is used.
+  // Derivative gridding: the gradient of the truncated Gaussian carries a
+  // larger quadrature error than the Gaussian at equal support (each further
+  // point divides both by about 3.5), so with an automatic support it takes
+  // one more point (with the moment-corrected gradient weights the couplings
+  // then measure 0.5 to 1.5 times the moment gridding's errors at eps =
+  // 1e-3); it needs the spreading tiles and at most 10 points, else the
+  // moment gridding is used.
   // By default it is used where it pays: it moves two fifths of the grid
-  // traffic of M_ES but spreads and interpolates over (P+1)^3 points, so it
-  // is faster while the stencil points per grid point, N (P+1)^3 / Ng^3,
-  // stay below about 20 (measured: faster at 2.4, 3.8, 12 and 14.5, slower
-  // at 33).
+  // traffic of M_ES and about half of that of the whole product but spreads
+  // and interpolates over (P+1)^3 points, so it is faster while the stencil
+  // points per grid point, N (P+1)^3 / Ng^3, stay below about 20 (measured
+  // on M_ES: faster at 2.4, 3.8, 12 and 14.5, slower at 33).
   d.deriv_gridding = 1;
   if (p.deriv_gridding != 1 && !df.on) {   // 0 (default) or 2; cube only
     const int pd = p.support > 0 ? d.support : d.support + 1;
@@ -217,7 +219,7 @@ size_t footprint(const pse_params &p, const pse_derived &d) {
            + d.grid * sizeof(double2);
   if (mixed) bytes += 2 * MAX_PACK * ng3 * sizeof(float2) + d.grid * sizeof(float2);
   bytes += (size_t)(3 * (d.grid / 2) * (d.grid / 2) + 1) * 4 * sizeof(double);
-  bytes += (p.async_calls ? 2 : 1) * pair_capacity(p, d) * (sizeof(int) + 10 * sizeof(double))
+  bytes += (p.async_calls ? 2 : 1) * pair_capacity(p, d) * pair_entry_bytes(mixed)
            + (2 * n + n / 1024 + 16) * sizeof(int);
   const size_t ntab = (size_t)(2048.0 * d.rcut / (2 * p.radius)) + 16;
   bytes += ntab * NCOEF * (sizeof(double) + sizeof(float));
@@ -233,6 +235,7 @@ size_t footprint(const pse_params &p, const pse_derived &d) {
   bytes += (2 * (ncell3 + tiles3) + 4 + (ncell3 + tiles3) / 1024 + 16) * sizeof(int)
            + 8 * n * sizeof(int);
   bytes += (2 * 3 * n + 6 * NC * n) * sizeof(double);
+  if (d.deriv_gridding == 2) bytes += 6 * n * sizeof(double);
   bytes += (size_t)(d.lanczos_maxit + 1) * NC * n * sizeof(double);
   bytes += (size_t)(d.gmres_restart + 1) * 5 * n * sizeof(double);
   const size_t small = 4 * (size_t)(d.gmres_restart + 2) * (d.gmres_restart + 2)

@@ -182,10 +182,13 @@ struct Handle {
   double *ktab = nullptr;    // per-|k|^2 radial factors (4 doubles per entry)
   float *ktab32 = nullptr;   // the same rounded to float (mixed handles)
   int *bad_pos = nullptr;    // set by the wrap kernel on a non-finite coordinate
+  double *dg_mu = nullptr;   // derivative gridding: moment corrections, 6 per particle
   // real-space pair list (CSR in cell order): start[N+1], neighbour index and
-  // 10 doubles of pair data per entry; counts and scan scratch
+  // 10 doubles of pair data per entry (mixed handles: also the same 10 as
+  // floats, read by the FP32 pair sum); counts and scan scratch
   int *pl_cnt = nullptr, *pl_start = nullptr, *pl_scan = nullptr, *pl_nbr = nullptr;
   double *pl_rec = nullptr;
+  float *pl_rec32 = nullptr;
   size_t pl_cap = 0, pl_pairs = 0;
   // spreading-tile candidate lists (CSR over tiles): one record per (tile,
   // particle) pair, tl_cap records at most
@@ -326,20 +329,27 @@ void spread(Handle &h, const double *x, const double *q, Layout lq, const CompSe
 template <typename T>
 void interpolate(Handle &h, const double *x, const T *grids, const CompSet &cs, double *out,
                  Layout lo, bool accumulate, double scale);
+// dg: outputs are the grid codes of derivative gridding (see kspace_fused)
 template <typename T>
 void kspace_noise(Handle &h, const double *psi, uint64_t seed, uint64_t counter,
-                  cplx<T> *out, const CompSet &cout);
-// z transform + k-space + inverse z transform in one kernel; dg: the
-// derivative-gridding factors (three grids in, three out)
+                  cplx<T> *out, const CompSet &cout, bool dg = false);
+// z transform + k-space + inverse z transform in one kernel; dg: cin and
+// cout are grid codes of derivative gridding, 0-2 force grids (in) or
+// velocity grids j0 u (out), 3-5 couplet grids (in) or 3 f1 u grids (out)
 template <typename T>
 void kspace_fused(Handle &h, const cplx<T> *in, const CompSet &cin, cplx<T> *out,
                   const CompSet &cout, const cplx<T> *tw, bool dg = false);
-// derivative gridding of the constraint operator (three grids each way)
+// derivative gridding: forces (hf: all three in cs, first) onto three grids
+// and couplets (torques with hasL, stresslets with hasS, complete groups in
+// cs, in that order) onto three more; interpolation of velocity (hu) from
+// the first three of six grids and of rotation and strain from the gradient
+// of the other three (any components cs)
 template <typename T>
-void spread_deriv(Handle &h, const double *q, Layout lq, const CompSet &cs, T *grids);
+void spread_deriv(Handle &h, const double *q, Layout lq, const CompSet &cs, bool hf, bool hasL,
+                  bool hasS, T *grids);
 template <typename T>
-void interp_deriv(Handle &h, const double *x, const T *grids, const CompSet &cs, double *out,
-                  Layout lo, bool accumulate, double scale);
+void interp_deriv(Handle &h, const double *x, const T *grids, bool hu, const CompSet &cs,
+                  double *out, Layout lo, bool accumulate, double scale);
 // k-space kernel of a deformed lattice on full half spectra (all three
 // axes transformed)
 template <typename T>
@@ -347,6 +357,8 @@ void kspace_deformed(Handle &h, const cplx<T> *in, const CompSet &cin, cplx<T> *
                      const CompSet &cout);
 template <typename T> void zero_grids(Handle &h, T *g, int ncomp);
 void build_tile_lists(Handle &h, const double *xw);
+// moment corrections of the gradient weights (derivative-gridding handles)
+void build_dg_mu(Handle &h, const double *xw);
 size_t tile_record_bytes(int S);                  // one (tile, particle) record
 int ktable_len(int grid);                         // entries of the |k|^2 table
 void build_ktable(Handle &h);
@@ -355,6 +367,14 @@ template <typename T> void to_double(Handle &h, const T *src, size_t n, double *
 
 // Initial capacity of the real-space pair list: twice the pair count of a
 // uniform suspension (neighbours within rcut), plus slack.
+// Pair-list storage for cap entries (neighbour indices, FP64 records and,
+// in mixed handles, FP32 records): at creation from the handle's workspace,
+// later replacing the previous storage.
+void pair_storage(Handle &h, size_t cap, bool at_create);
+// bytes of one pair-list entry
+inline size_t pair_entry_bytes(bool mixed) {
+  return sizeof(int) + 10 * sizeof(double) + (mixed ? 10 * sizeof(float) : 0);
+}
 inline size_t pair_capacity(const pse_params &p, const pse_derived &d) {
   const double dens = (double)p.n / (p.box * p.box * p.box);
   const double nb = 4.18879020478639098 * d.rcut * d.rcut * d.rcut * dens;

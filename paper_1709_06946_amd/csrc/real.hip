@@ -597,7 +597,7 @@ pair_list_kernel(const double *__restrict__ xw, const int *__restrict__ perm,
                  const int *__restrict__ cell_start, const int *__restrict__ cell_of,
                  PairArgs pa, int *__restrict__ cnt, const int *__restrict__ start,
                  const double *__restrict__ tab, int *__restrict__ nbr,
-                 double *__restrict__ rec) {
+                 double *__restrict__ rec, float *__restrict__ rec32) {
   const int64_t t = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
   const int lane = threadIdx.x % 64;
   if (t >= pa.n) return;
@@ -633,12 +633,20 @@ pair_list_kernel(const double *__restrict__ xw, const int *__restrict__ perm,
         const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
         double co[NCOEF];
         lookup<double>(tab, r, pa.inv_dr, pa.n2a, pa.ntab, co);
-        double *o = rec + (size_t)slot * PAIR_REC;
+        double o[PAIR_REC];
 #pragma unroll
         for (int k = 0; k < NCOEF; ++k) o[k] = co[k];
         const double inv = r > 0 ? 1.0 / r : 0.0;
 #pragma unroll
         for (int k = 0; k < 3; ++k) o[NCOEF + k] = d[k] * inv;
+        double *od = rec + (size_t)slot * PAIR_REC;
+#pragma unroll
+        for (int k = 0; k < PAIR_REC; ++k) od[k] = o[k];
+        if (rec32) {
+          float *of = rec32 + (size_t)slot * PAIR_REC;
+#pragma unroll
+          for (int k = 0; k < PAIR_REC; ++k) of[k] = (float)o[k];
+        }
       }
       pos += __popcll(m);
     }
@@ -665,7 +673,7 @@ template <typename T>
 __global__ void __launch_bounds__(256)
 real_pair_kernel(const double *__restrict__ in, double *__restrict__ out,
                  const int *__restrict__ perm, const int *__restrict__ start,
-                 const int *__restrict__ nbr, const double *__restrict__ rec,
+                 const int *__restrict__ nbr, const T *__restrict__ rec,
                  const T *__restrict__ tab, RealArgs ra) {
   const int64_t t =
       ((int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x) / GROUP;
@@ -686,12 +694,12 @@ real_pair_kernel(const double *__restrict__ in, double *__restrict__ out,
   const int s1 = (int)min((int64_t)start[t + 1], ra.cap);
   for (int s = start[t] + lane; s < s1; s += GROUP) {
     const int j = nbr[s];
-    const double *r = rec + (size_t)s * PAIR_REC;
+    const T *r = rec + (size_t)s * PAIR_REC;
     T co[NCOEF], e[3];
 #pragma unroll
-    for (int k = 0; k < NCOEF; ++k) co[k] = (T)r[k];
+    for (int k = 0; k < NCOEF; ++k) co[k] = r[k];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) e[k] = (T)r[NCOEF + k];
+    for (int k = 0; k < 3; ++k) e[k] = r[NCOEF + k];
     load_moments<T>(in + (size_t)j * ra.lin.stride, ra.lin.off, ra.in_mask, F, C);
     pair_action<T>(co, e, F, C, useF, useC, U, D);
   }
@@ -742,7 +750,7 @@ static void build_pair_list(Handle &h, const double *xw) {
   const unsigned nb = nblocks((size_t)h.n * 64, 256);
   hipLaunchKernelGGL((pair_list_kernel<false>), dim3(nb), dim3(256), 0, h.stream, xw,
                      h.cells.perm, h.cells.start, h.cells.of, pa, h.pl_cnt, nullptr, nullptr,
-                     nullptr, nullptr);
+                     nullptr, nullptr, nullptr);
   PSE_LAUNCH_CHECK();
   const int n = (int)h.n;
   exclusive_scan(h, h.pl_cnt, h.pl_start, h.pl_scan, n);
@@ -753,7 +761,7 @@ static void build_pair_list(Handle &h, const double *xw) {
     h.pl_pairs = h.pl_cap;
     hipLaunchKernelGGL((pair_list_kernel<true>), dim3(nb), dim3(256), 0, h.stream, xw,
                        h.cells.perm, h.cells.start, h.cells.of, pa, nullptr, h.pl_start,
-                       h.g64.table, h.pl_nbr, h.pl_rec);
+                       h.g64.table, h.pl_nbr, h.pl_rec, h.pl_rec32);
     PSE_LAUNCH_CHECK();
     return;
   }
@@ -770,21 +778,35 @@ static void build_pair_list(Handle &h, const double *xw) {
                                  " pairs)"};
     clear_graphs(h);   // captured real-space launches hold the old buffers
     const size_t cap = (size_t)total + total / 4 + 1024;
-    dev_free(h.pl_nbr);
-    dev_free(h.pl_rec);
-    h.pl_nbr = nullptr;
-    h.pl_rec = nullptr;
-    h.pl_cap = 0;
-    dev_alloc((void **)&h.pl_nbr, cap * sizeof(int));
-    dev_alloc((void **)&h.pl_rec, cap * PAIR_REC * sizeof(double));
-    h.pl_cap = cap;
+    pair_storage(h, cap, false);
     pa.cap = (int64_t)cap;
   }
   h.pl_pairs = (size_t)total;
   hipLaunchKernelGGL((pair_list_kernel<true>), dim3(nb), dim3(256), 0, h.stream, xw,
                      h.cells.perm, h.cells.start, h.cells.of, pa, nullptr, h.pl_start,
-                     h.g64.table, h.pl_nbr, h.pl_rec);
+                     h.g64.table, h.pl_nbr, h.pl_rec, h.pl_rec32);
   PSE_LAUNCH_CHECK();
+}
+
+void pair_storage(Handle &h, size_t cap, bool at_create) {
+  if (at_create) {
+    handle_alloc(h, (void **)&h.pl_nbr, cap * sizeof(int));
+    handle_alloc(h, (void **)&h.pl_rec, cap * PAIR_REC * sizeof(double));
+    if (h.mixed) handle_alloc(h, (void **)&h.pl_rec32, cap * PAIR_REC * sizeof(float));
+    h.pl_cap = cap;
+    return;
+  }
+  dev_free(h.pl_nbr);
+  dev_free(h.pl_rec);
+  dev_free(h.pl_rec32);
+  h.pl_nbr = nullptr;
+  h.pl_rec = nullptr;
+  h.pl_rec32 = nullptr;
+  h.pl_cap = 0;
+  dev_alloc((void **)&h.pl_nbr, cap * sizeof(int));
+  dev_alloc((void **)&h.pl_rec, cap * PAIR_REC * sizeof(double));
+  if (h.mixed) dev_alloc((void **)&h.pl_rec32, cap * PAIR_REC * sizeof(float));
+  h.pl_cap = cap;
 }
 
 // Cell list, spreading bins and pair list for wrapped positions xw.
@@ -796,6 +818,7 @@ void build_cells(Handle &h, const double *xw) {
   if (h.stile) {
     build_bins(h, xw, h.sbins);
     build_tile_lists(h, xw);
+    build_dg_mu(h, xw);
   }
   build_pair_list(h, xw);
 }
@@ -822,12 +845,19 @@ void real_apply(Handle &h, const double *xw, const double *in, Layout lin, const
   ra.out_mask = mask_of(cout, false);
   ra.accumulate = accumulate ? 1 : 0;
   ra.cap = (int64_t)h.pl_cap;
-  const T *tab;
-  if constexpr (sizeof(T) == 8) tab = h.g64.table; else tab = h.g32.table;
-  ProfScope ps(h, PK_REAL, (double)h.pl_pairs * (PAIR_REC * 8 + 4 + NC * 8) +
+  const T *tab, *rec;
+  if constexpr (sizeof(T) == 8) {
+    tab = h.g64.table;
+    rec = h.pl_rec;
+  } else {
+    tab = h.g32.table;
+    rec = h.pl_rec32;
+  }
+  if (!rec) throw Error{PSE_ERR_INVALID, "no pair records of this precision"};
+  ProfScope ps(h, PK_REAL, (double)h.pl_pairs * (PAIR_REC * sizeof(T) + 4 + NC * 8) +
                                (double)h.n * (NC * 8 * 2 + 8));
   hipLaunchKernelGGL(real_pair_kernel<T>, dim3(nblocks((size_t)h.n * GROUP, 256)), dim3(256), 0,
-                     h.stream, in, out, h.cells.perm, h.pl_start, h.pl_nbr, h.pl_rec, tab, ra);
+                     h.stream, in, out, h.cells.perm, h.pl_start, h.pl_nbr, rec, tab, ra);
   PSE_LAUNCH_CHECK();
 }
 

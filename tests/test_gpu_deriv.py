@@ -1,8 +1,9 @@
-"""Derivative gridding of the constraint operator M_ES (the stresslets
-spread with the Gaussian's gradient onto three grids, the strain
-interpolated with it, three grids each way instead of five) against the
-FP64 oracle's Ewald sums: the stresslet-strain block over the tolerance
-sweep eps in {1e-2 ... 1e-5}, its wave-space part alone in both precisions,
+"""Derivative gridding (the couplets -- stresslets and torques -- spread
+with the Gaussian's gradient onto three grids, rotation and strain
+interpolated with it; forces and velocities on their moment grids) against
+the FP64 oracle's Ewald sums: the constraint operator M_ES over the
+tolerance sweep eps in {1e-2 ... 1e-5}, its wave-space part alone in both
+precisions, the whole 11 x 11 product over the sweep and per input group,
 agreement with moment gridding, and the constrained step with the same
 noise.  The bar is the method tolerance eps of each configuration."""
 import math
@@ -111,3 +112,69 @@ def test_step_with_derivative_gridding_same_noise(phi):
     print(f'phi={phi} derivative gridding step', errs, st)
     assert rc == 0 and st['converged'] == 1
     assert max(errs.values()) < 1e-3, errs
+
+
+# Derivative gridding of every wave-space product: forces on their moment
+# grids, torques and stresslets together on the gradient grids, velocity
+# interpolated plainly, rotation and strain from the gradient.
+
+def _full(h, x, q, parts):
+    import torch
+    out = torch.zeros((h.n, 11), dtype=torch.float64, device='cuda:0')
+    h.mobility_apply(dev(x), dev(q), out, parts)
+    return host(out)
+
+
+@pytest.mark.parametrize('eps', [1e-2, 1e-3, 1e-4])
+def test_full_product_within_tolerance(eps):
+    from gpu_common import block_errors, particle_errors
+    from paper_1709_06946_amd import pse
+    x, L = packing(100, 0.1, inputs.SEED_BASE + 31)
+    h = pse.PSE(100, L, tol=eps, xi=_min_xi(L, eps), deriv_gridding=2)
+    d = h.derived
+    assert d.deriv_gridding == 2
+    q = np.random.default_rng(32).normal(size=(100, 11))
+    ref = ewald.real_apply(x, q, L, d.xi) + ewald.wave_apply(x, q, L, d.xi)
+    y = _full(h, x, q, pse.PSE_REAL | pse.PSE_WAVE)
+    be, pe = block_errors(y, ref), particle_errors(y, ref)
+    print(f'eps={eps:g} grid={d.grid} P={d.support}', be, pe)
+    assert max(be.values()) < eps, be
+    assert max(pe.values()) < 4 * eps, pe
+
+
+@pytest.mark.parametrize('group', ['F', 'L', 'S'])
+@pytest.mark.parametrize('precision', [0, 1])
+def test_wave_blocks_of_each_input_group(group, precision):
+    """Each input group alone (forces, torques, stresslets) against the
+    oracle's wave sums, every output block: a wrong sign or factor in one
+    coupling (a torque column, a rotation row) shows in its own block."""
+    from gpu_common import block_errors
+    from paper_1709_06946_amd import pse
+    x, L = packing(100, 0.1, inputs.SEED_BASE + 33)
+    h = pse.PSE(100, L, grid=32, tol=1e-3, precision=precision, deriv_gridding=2)
+    assert h.derived.deriv_gridding == 2
+    cols = {'F': slice(0, 3), 'L': slice(3, 6), 'S': slice(6, 11)}[group]
+    q = np.zeros((100, 11))
+    q[:, cols] = np.random.default_rng(34).normal(size=(100, cols.stop - cols.start))
+    ref = ewald.wave_apply(x, q, L, h.derived.xi)
+    be = block_errors(_full(h, x, q, pse.PSE_WAVE), ref)
+    print(f'group={group} precision={precision}', be)
+    assert max(be.values()) < 2e-3, be
+
+
+def test_derivative_and_moment_gridding_agree_on_the_full_product():
+    """The two quadratures of the whole product converge to the same sums:
+    at eps = 1e-4 they agree to within twice the tolerance, block by block."""
+    from gpu_common import block_errors
+    from paper_1709_06946_amd import pse
+    x, L = packing(100, 0.1, inputs.SEED_BASE + 35)
+    eps = 1e-4
+    q = np.random.default_rng(36).normal(size=(100, 11))
+    out = {}
+    for mode in (1, 2):
+        h = pse.PSE(100, L, tol=eps, xi=_min_xi(L, eps), deriv_gridding=mode)
+        assert h.derived.deriv_gridding == mode
+        out[mode] = _full(h, x, q, pse.PSE_WAVE)
+    be = block_errors(out[2], out[1])
+    print('derivative vs moment gridding, full product', be)
+    assert max(be.values()) < 2e-4, be
