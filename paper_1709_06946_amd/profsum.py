@@ -92,7 +92,7 @@ def recorded_traffic(stage, profile_file):
 
 
 # Kernels whose launches make up one stage of the wave-space product.
-STAGE_PREFIX = {'fft': ('fft_',), 'kspace': ('kspace_fused',),
+STAGE_PREFIX = {'fft': ('fft_',), 'kspace': ('kspace_fused', 'kspace_dg3'),
                 'spread': ('spread_list', 'spread_deriv'),
                 'interp': ('interp_kernel', 'interp_deriv'), 'real': ('real_pair',)}
 STAGE_SOURCES = {'fft': ('fft.hip', 'fftreg.h'), 'kspace': ('grid.hip', 'fftreg.h'),
