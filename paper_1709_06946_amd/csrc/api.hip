@@ -714,7 +714,7 @@ static void release(Handle &h) {
                   h.sbins.scat, h.sbins.perm, h.cells.trav, h.cells.bcount, h.cells.bstart,
                   h.xw, h.xh, h.v0, h.v1, h.v2, h.v3, h.v4, h.v5, h.es_b, h.es_x, h.es_r,
                   h.es_d, h.lz_V, h.gm_V, h.small, h.dots, h.ktab, h.pl_cnt,
-                  h.pl_start, h.pl_scan, h.pl_nbr, h.pl_rec, h.pl_rec32, h.tl_cnt, h.tl_start,
+                  h.pl_start, h.pl_scan, h.pl_nbr, h.pl_rec64, h.pl_rec32, h.tl_cnt, h.tl_start,
                   h.tl_scan, h.tl_rec, h.bad_pos, h.ktab32, h.dctl, h.dstats, h.dstep,
                   h.dg_mu};
   if (!h.arena)

@@ -85,13 +85,25 @@ fft_x_c2r_kernel(T *__restrict__ data, const cplx<T> *__restrict__ tw, int TL) {
   extern __shared__ unsigned char smem_raw[];
   C *lds = reinterpret_cast<C *>(smem_raw);
   constexpr int PAD = S::first(true), LS = xstride(N, PAD);
-  for (int w = threadIdx.x; w < TL * H; w += blockDim.x) {
-    const int ln = w / H, k = w % H;
+  // the workgroup is TL lines of TPL threads, so every thread takes H / TPL
+  // of the TL * H input pairs: all its loads are issued before the first
+  // LDS store
+  constexpr int IT = H / TPL;
+  static_assert(IT * TPL == H, "pairs per thread");
+  C a[IT], bb[IT];
+#pragma unroll
+  for (int i = 0; i < IT; ++i) {
+    const int w = threadIdx.x + i * blockDim.x, ln = w / H, k = w % H;
     const C *in = reinterpret_cast<const C *>(data + 2 * ((size_t)blockIdx.x * TL + ln) * N);
-    const C a = in[k], bb = in[H + k];
+    a[i] = in[k];
+    bb[i] = in[H + k];
+  }
+#pragma unroll
+  for (int i = 0; i < IT; ++i) {
+    const int w = threadIdx.x + i * blockDim.x, ln = w / H, k = w % H;
     C *Z = lds + ln * LS;
-    Z[padpos<PAD>(k)] = C{a.x - bb.y, a.y + bb.x};
-    if (k > 0) Z[padpos<PAD>(N - k)] = C{a.x + bb.y, bb.x - a.y};
+    Z[padpos<PAD>(k)] = C{a[i].x - bb[i].y, a[i].y + bb[i].x};
+    if (k > 0) Z[padpos<PAD>(N - k)] = C{a[i].x + bb[i].y, bb[i].x - a[i].y};
     else Z[padpos<PAD>(H)] = C{(T)0, (T)0};
   }
   __syncthreads();

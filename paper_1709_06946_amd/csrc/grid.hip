@@ -403,23 +403,31 @@ __device__ __forceinline__ double gauss_at(const double f[3], int a, int b, int 
 // (a, b) = (l % 8, l / 8) at every z index c, its point it being c = it.
 // The Gaussian factorises, so a lane takes one exponential for its x-y
 // factor and one for the z factor of c = l % 8; the z factor of point it is
-// read from lane it.  Fills the grid offsets and exp(-kcoef |d|^2) of the
-// lane's eight points, and their offsets d along z (x and y are dx, dy).
+// read from lane it.  Fills the grid offsets (within one grid: below 2^31
+// for every supported length) and exp(-kcoef |d|^2) of the lane's eight
+// points, and their offsets d along z (x and y are dx, dy); the weights and
+// z offsets in the kernel's type T (FP32 kernels keep half the registers).
+__device__ __forceinline__ float readlane_t(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double readlane_t(double v, int l) { return readlane_d(v, l); }
+
+template <typename T>
 __device__ __forceinline__ void stencil8(int lane, double px, double py, double pz, int ix0,
-                                         int iy0, int iz0, const GridGeom &g, size_t gi[8],
-                                         double e[8], double dz[8], double &dx, double &dy) {
+                                         int iy0, int iz0, const GridGeom &g, uint32_t gi[8],
+                                         T e[8], T dz[8], double &dx, double &dy) {
   const int a = lane & 7, b = lane >> 3;
   dx = (ix0 + a) * g.h - px;
   dy = (iy0 + b) * g.h - py;
-  const double exy = exp(-g.kcoef * (dx * dx + dy * dy));
+  const T exy = (T)exp(-g.kcoef * (dx * dx + dy * dy));
   const double dzl = (iz0 + a) * g.h - pz;
-  const double ezl = exp(-g.kcoef * dzl * dzl);
-  const size_t gxy = (size_t)wrapi(iy0 + b, g.ng) * g.ng + wrapi(ix0 + a, g.ng);
+  const T ezl = (T)exp(-g.kcoef * dzl * dzl);
+  const uint32_t gxy = (uint32_t)wrapi(iy0 + b, g.ng) * g.ng + wrapi(ix0 + a, g.ng);
 #pragma unroll
   for (int it = 0; it < 8; ++it) {
-    dz[it] = (iz0 + it) * g.h - pz;
-    e[it] = exy * readlane_d(ezl, it);
-    gi[it] = (size_t)wrapi(iz0 + it, g.ng) * g.ng * g.ng + gxy;
+    dz[it] = (T)((iz0 + it) * g.h - pz);
+    e[it] = exy * readlane_t(ezl, it);
+    gi[it] = (uint32_t)wrapi(iz0 + it, g.ng) * g.ng * g.ng + gxy;
   }
 }
 
@@ -450,15 +458,16 @@ interp_kernel(const double *__restrict__ x, const T *__restrict__ grids,
   for (int k = 0; k < NC; ++k) acc[k] = (T)0;
   const double kn3 = g.knorm * g.knorm * g.knorm;
   if constexpr (MAXIT > 0) {
-    size_t gi[MAXIT];
+    uint32_t gi[MAXIT];
     T w[MAXIT];
     bool done = false;
     if constexpr (MAXIT == 8) {
       if (P == 8) {
-        double e[8], dz[8], dx, dy;
-        stencil8(lane, px, py, pz, ix0, iy0, iz0, g, gi, e, dz, dx, dy);
+        T e[8], dz[8];
+        double dx, dy;
+        stencil8<T>(lane, px, py, pz, ix0, iy0, iz0, g, gi, e, dz, dx, dy);
 #pragma unroll
-        for (int it = 0; it < 8; ++it) w[it] = (T)(kn3 * e[it]);
+        for (int it = 0; it < 8; ++it) w[it] = (T)kn3 * e[it];
         done = true;
       }
     }
@@ -472,7 +481,7 @@ interp_kernel(const double *__restrict__ x, const T *__restrict__ grids,
         const bool in = s < P3;
         const double e = gauss_at(f, a, b, c);
         w[it] = in ? (T)(kn3 * e) : (T)0;
-        gi[it] = in ? ((size_t)wrapi(iz0 + c, g.ng) * g.ng + wrapi(iy0 + b, g.ng)) * g.ng
+        gi[it] = in ? ((uint32_t)wrapi(iz0 + c, g.ng) * g.ng + wrapi(iy0 + b, g.ng)) * g.ng
                           + wrapi(ix0 + a, g.ng)
                     : 0;
       }
@@ -1318,9 +1327,10 @@ interp_deriv_kernel(const double *__restrict__ x, const T *__restrict__ grids, s
       // the lane's points share x and y: with dK/dx_i = c d_i e (c = -2
       // kcoef knorm^3, e the Gaussian), the column sums s_k = sum v_k e and
       // z_k = sum v_k e dz give every G_ij
-      size_t gi[8];
-      double e[8], dz[8], dx, dy;
-      stencil8(lane, px, py, pz, ix0, iy0, iz0, g, gi, e, dz, dx, dy);
+      uint32_t gi[8];
+      T e[8], dz[8];
+      double dx, dy;
+      stencil8<T>(lane, px, py, pz, ix0, iy0, iz0, g, gi, e, dz, dx, dy);
       T v[3][8], u[HU ? 3 : 1][8];
 #pragma unroll
       for (int k = 0; k < 3; ++k)
@@ -1336,9 +1346,10 @@ interp_deriv_kernel(const double *__restrict__ x, const T *__restrict__ grids, s
       const double sh = 1.0 / (-2.0 * g.kcoef);
       dx -= mx * sh;
       dy -= my * sh;
+      const T mzs = (T)(mz * sh);
 #pragma unroll
       for (int it = 0; it < 8; ++it) {
-        const T et = (T)e[it], dzt = (T)(dz[it] - mz * sh);
+        const T et = e[it], dzt = dz[it] - mzs;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
           const T ve = v[k][it] * et;
@@ -1360,7 +1371,7 @@ interp_deriv_kernel(const double *__restrict__ x, const T *__restrict__ grids, s
     }
   }
   if (!done) {
-    size_t gi[MAXIT];
+    uint32_t gi[MAXIT];
     T gw[MAXIT][3], w0[MAXIT];
     double f1[3];
     factors1d(lane, px, py, pz, ix0, iy0, iz0, g, f1);
@@ -1378,7 +1389,7 @@ interp_deriv_kernel(const double *__restrict__ x, const T *__restrict__ grids, s
       gw[it][1] = (T)(f * ly * (-2.0 * g.kcoef * dy - my));
       gw[it][2] = (T)(f * lz * (-2.0 * g.kcoef * dz - mz));
       w0[it] = (T)f;
-      gi[it] = in ? ((size_t)wrapi(iz0 + c, g.ng) * g.ng + wrapi(iy0 + b, g.ng)) * g.ng
+      gi[it] = in ? ((uint32_t)wrapi(iz0 + c, g.ng) * g.ng + wrapi(iy0 + b, g.ng)) * g.ng
                         + wrapi(ix0 + a, g.ng)
                   : 0;
     }

@@ -184,10 +184,10 @@ struct Handle {
   int *bad_pos = nullptr;    // set by the wrap kernel on a non-finite coordinate
   double *dg_mu = nullptr;   // derivative gridding: moment corrections, 6 per particle
   // real-space pair list (CSR in cell order): start[N+1], neighbour index and
-  // 10 doubles of pair data per entry (mixed handles: also the same 10 as
-  // floats, read by the FP32 pair sum); counts and scan scratch
+  // 10 numbers of pair data per entry (doubles in FP64 handles, floats in
+  // mixed ones); counts and scan scratch
   int *pl_cnt = nullptr, *pl_start = nullptr, *pl_scan = nullptr, *pl_nbr = nullptr;
-  double *pl_rec = nullptr;
+  double *pl_rec64 = nullptr;
   float *pl_rec32 = nullptr;
   size_t pl_cap = 0, pl_pairs = 0;
   // spreading-tile candidate lists (CSR over tiles): one record per (tile,
@@ -367,13 +367,12 @@ template <typename T> void to_double(Handle &h, const T *src, size_t n, double *
 
 // Initial capacity of the real-space pair list: twice the pair count of a
 // uniform suspension (neighbours within rcut), plus slack.
-// Pair-list storage for cap entries (neighbour indices, FP64 records and,
-// in mixed handles, FP32 records): at creation from the handle's workspace,
-// later replacing the previous storage.
+// Pair-list storage for cap entries (neighbour indices and pair data): at
+// creation from the handle's workspace, later replacing the previous storage.
 void pair_storage(Handle &h, size_t cap, bool at_create);
 // bytes of one pair-list entry
 inline size_t pair_entry_bytes(bool mixed) {
-  return sizeof(int) + 10 * sizeof(double) + (mixed ? 10 * sizeof(float) : 0);
+  return sizeof(int) + 10 * (mixed ? sizeof(float) : sizeof(double));
 }
 inline size_t pair_capacity(const pse_params &p, const pse_derived &d) {
   const double dens = (double)p.n / (p.box * p.box * p.box);

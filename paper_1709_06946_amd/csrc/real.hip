@@ -549,11 +549,17 @@ __device__ __forceinline__ T group_sum(T v) {
 
 // ------------------------------------------------------------ pair list --
 // The positions stay fixed over all the operator applications of a Krylov
-// solve, so the neighbours within rcut and their pair data (the seven
-// interpolated radial coefficients and the unit vector) are found once per
-// position update and stored as a CSR list in cell order: row t holds the
-// neighbours of particle perm[t].  Rows are filled in a fixed order
-// (cells, then candidates, ranked with a ballot inside the group).
+// solve, so the neighbours within rcut are found once per position update
+// and stored as a CSR list in cell order: row t holds the neighbours of
+// particle perm[t].  Rows are filled in a fixed order (cells, then
+// candidates, ranked with a ballot inside the group).  Each entry holds the
+// neighbour index and the pair's data -- the seven interpolated radial
+// coefficients and the unit vector -- in the precision of the handle's own
+// pair sums (FP64 handles: doubles; mixed handles: floats, read by their
+// FP32 sums).  A sum in the other precision (the FP64 residual of a mixed
+// handle, once per step) forms the data from the positions itself.
+
+constexpr int PAIR_REC = 10;   // co[7], e[3]
 
 struct PairArgs {
   int64_t n;
@@ -567,24 +573,30 @@ struct PairArgs {
   double A[9];     // separations are mapped back by A
 };
 
-constexpr int PAIR_REC = 10;   // co[7], e[3]
-
-__device__ __forceinline__ bool near_pair(const double *__restrict__ xw, double xi0, double xi1,
-                                          double xi2, int j, const PairArgs &pa, double *d) {
+// Separation x_i - x_j of wrapped positions: nearest image, and on a
+// deformed lattice mapped from lattice offsets to Cartesian ones (the cutoff
+// is at most a third of the cell's thinnest width, so the image is the
+// nearest one).
+__device__ __forceinline__ void separation(const double *__restrict__ xw, double xi0, double xi1,
+                                           double xi2, int j, double L, int def, const double *A,
+                                           double *d) {
   d[0] = xi0 - xw[3 * j];
   d[1] = xi1 - xw[3 * j + 1];
   d[2] = xi2 - xw[3 * j + 2];
   // positions are wrapped into [0, L): one image shift per axis suffices
-  const double hL = 0.5 * pa.L;
+  const double hL = 0.5 * L;
 #pragma unroll
-  for (int k = 0; k < 3; ++k) d[k] += d[k] > hL ? -pa.L : (d[k] < -hL ? pa.L : 0.0);
-  if (pa.def) {
-    // lattice offsets to the Cartesian separation (the cutoff is at most a
-    // third of the cell's thinnest width, so the image is the nearest one)
+  for (int k = 0; k < 3; ++k) d[k] += d[k] > hL ? -L : (d[k] < -hL ? L : 0.0);
+  if (def) {
     const double e[3] = {d[0], d[1], d[2]};
 #pragma unroll
-    for (int r = 0; r < 3; ++r) d[r] = pa.A[3 * r] * e[0] + pa.A[3 * r + 1] * e[1] + pa.A[3 * r + 2] * e[2];
+    for (int r = 0; r < 3; ++r) d[r] = A[3 * r] * e[0] + A[3 * r + 1] * e[1] + A[3 * r + 2] * e[2];
   }
+}
+
+__device__ __forceinline__ bool near_pair(const double *__restrict__ xw, double xi0, double xi1,
+                                          double xi2, int j, const PairArgs &pa, double *d) {
+  separation(xw, xi0, xi1, xi2, j, pa.L, pa.def, pa.A, d);
   return d[0] * d[0] + d[1] * d[1] + d[2] * d[2] < pa.rcut2;
 }
 
@@ -597,7 +609,7 @@ pair_list_kernel(const double *__restrict__ xw, const int *__restrict__ perm,
                  const int *__restrict__ cell_start, const int *__restrict__ cell_of,
                  PairArgs pa, int *__restrict__ cnt, const int *__restrict__ start,
                  const double *__restrict__ tab, int *__restrict__ nbr,
-                 double *__restrict__ rec, float *__restrict__ rec32) {
+                 double *__restrict__ rec64, float *__restrict__ rec32) {
   const int64_t t = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
   const int lane = threadIdx.x % 64;
   if (t >= pa.n) return;
@@ -630,22 +642,22 @@ pair_list_kernel(const double *__restrict__ xw, const int *__restrict__ perm,
       }
       if (ok) {
         nbr[slot] = j;
-        const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-        double co[NCOEF];
-        lookup<double>(tab, r, pa.inv_dr, pa.n2a, pa.ntab, co);
-        double o[PAIR_REC];
+        if (rec64 || rec32) {
+          const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+          double o[PAIR_REC];
+          lookup<double>(tab, r, pa.inv_dr, pa.n2a, pa.ntab, o);
+          const double inv = r > 0 ? 1.0 / r : 0.0;
 #pragma unroll
-        for (int k = 0; k < NCOEF; ++k) o[k] = co[k];
-        const double inv = r > 0 ? 1.0 / r : 0.0;
+          for (int k = 0; k < 3; ++k) o[NCOEF + k] = d[k] * inv;
+          if (rec64) {
+            double *od = rec64 + (size_t)slot * PAIR_REC;
 #pragma unroll
-        for (int k = 0; k < 3; ++k) o[NCOEF + k] = d[k] * inv;
-        double *od = rec + (size_t)slot * PAIR_REC;
+            for (int k = 0; k < PAIR_REC; ++k) od[k] = o[k];
+          } else {
+            float *of = rec32 + (size_t)slot * PAIR_REC;
 #pragma unroll
-        for (int k = 0; k < PAIR_REC; ++k) od[k] = o[k];
-        if (rec32) {
-          float *of = rec32 + (size_t)slot * PAIR_REC;
-#pragma unroll
-          for (int k = 0; k < PAIR_REC; ++k) of[k] = (float)o[k];
+            for (int k = 0; k < PAIR_REC; ++k) of[k] = (float)o[k];
+          }
         }
       }
       pos += __popcll(m);
@@ -665,16 +677,21 @@ struct RealArgs {
   int accumulate;
   Layout lin, lout;
   int64_t cap;    // pair-list capacity (entries beyond it were never written)
+  double L;       // box; deformed lattice: separations mapped by A
+  int def;
+  double A[9];
+  double inv_dr;  // radial table: spacing, rows of the near part, rows
+  int n2a, ntab;
 };
 
 // M_r applied from the pair list: the self block (r = 0: only the isotropic
 // coefficients, table row 0) plus one pair block per stored neighbour.
 template <typename T>
 __global__ void __launch_bounds__(256)
-real_pair_kernel(const double *__restrict__ in, double *__restrict__ out,
-                 const int *__restrict__ perm, const int *__restrict__ start,
-                 const int *__restrict__ nbr, const T *__restrict__ rec,
-                 const T *__restrict__ tab, RealArgs ra) {
+real_pair_kernel(const double *__restrict__ xw, const double *__restrict__ in,
+                 double *__restrict__ out, const int *__restrict__ perm,
+                 const int *__restrict__ start, const int *__restrict__ nbr,
+                 const T *__restrict__ rec, const T *__restrict__ tab, RealArgs ra) {
   const int64_t t =
       ((int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x) / GROUP;
   const int lane = threadIdx.x % GROUP;
@@ -692,14 +709,25 @@ real_pair_kernel(const double *__restrict__ in, double *__restrict__ out,
     pair_action<T>(co, e0, F, C, useF, useC, U, D);
   }
   const int s1 = (int)min((int64_t)start[t + 1], ra.cap);
+  const double xi0 = xw[3 * i], xi1 = xw[3 * i + 1], xi2 = xw[3 * i + 2];
   for (int s = start[t] + lane; s < s1; s += GROUP) {
     const int j = nbr[s];
-    const T *r = rec + (size_t)s * PAIR_REC;
     T co[NCOEF], e[3];
+    if (rec) {
+      const T *r = rec + (size_t)s * PAIR_REC;
 #pragma unroll
-    for (int k = 0; k < NCOEF; ++k) co[k] = r[k];
+      for (int k = 0; k < NCOEF; ++k) co[k] = r[k];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) e[k] = r[NCOEF + k];
+      for (int k = 0; k < 3; ++k) e[k] = r[NCOEF + k];
+    } else {
+      double d[3];
+      separation(xw, xi0, xi1, xi2, j, ra.L, ra.def, ra.A, d);
+      const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+      const double inv = r > 0 ? 1.0 / r : 0.0;
+      lookup<T>(tab, (T)r, (T)ra.inv_dr, ra.n2a, ra.ntab, co);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) e[k] = (T)(d[k] * inv);
+    }
     load_moments<T>(in + (size_t)j * ra.lin.stride, ra.lin.off, ra.in_mask, F, C);
     pair_action<T>(co, e, F, C, useF, useC, U, D);
   }
@@ -761,7 +789,7 @@ static void build_pair_list(Handle &h, const double *xw) {
     h.pl_pairs = h.pl_cap;
     hipLaunchKernelGGL((pair_list_kernel<true>), dim3(nb), dim3(256), 0, h.stream, xw,
                        h.cells.perm, h.cells.start, h.cells.of, pa, nullptr, h.pl_start,
-                       h.g64.table, h.pl_nbr, h.pl_rec, h.pl_rec32);
+                       h.g64.table, h.pl_nbr, h.pl_rec64, h.pl_rec32);
     PSE_LAUNCH_CHECK();
     return;
   }
@@ -784,28 +812,27 @@ static void build_pair_list(Handle &h, const double *xw) {
   h.pl_pairs = (size_t)total;
   hipLaunchKernelGGL((pair_list_kernel<true>), dim3(nb), dim3(256), 0, h.stream, xw,
                      h.cells.perm, h.cells.start, h.cells.of, pa, nullptr, h.pl_start,
-                     h.g64.table, h.pl_nbr, h.pl_rec, h.pl_rec32);
+                     h.g64.table, h.pl_nbr, h.pl_rec64, h.pl_rec32);
   PSE_LAUNCH_CHECK();
 }
 
 void pair_storage(Handle &h, size_t cap, bool at_create) {
-  if (at_create) {
-    handle_alloc(h, (void **)&h.pl_nbr, cap * sizeof(int));
-    handle_alloc(h, (void **)&h.pl_rec, cap * PAIR_REC * sizeof(double));
-    if (h.mixed) handle_alloc(h, (void **)&h.pl_rec32, cap * PAIR_REC * sizeof(float));
-    h.pl_cap = cap;
-    return;
+  if (!at_create) {
+    dev_free(h.pl_nbr);
+    dev_free(h.pl_rec64);
+    dev_free(h.pl_rec32);
+    h.pl_nbr = nullptr;
+    h.pl_rec64 = nullptr;
+    h.pl_rec32 = nullptr;
+    h.pl_cap = 0;
   }
-  dev_free(h.pl_nbr);
-  dev_free(h.pl_rec);
-  dev_free(h.pl_rec32);
-  h.pl_nbr = nullptr;
-  h.pl_rec = nullptr;
-  h.pl_rec32 = nullptr;
-  h.pl_cap = 0;
-  dev_alloc((void **)&h.pl_nbr, cap * sizeof(int));
-  dev_alloc((void **)&h.pl_rec, cap * PAIR_REC * sizeof(double));
-  if (h.mixed) dev_alloc((void **)&h.pl_rec32, cap * PAIR_REC * sizeof(float));
+  const auto alloc = [&](void **ptr, size_t bytes) {
+    if (at_create) handle_alloc(h, ptr, bytes);
+    else dev_alloc(ptr, bytes);
+  };
+  alloc((void **)&h.pl_nbr, cap * sizeof(int));
+  if (h.mixed) alloc((void **)&h.pl_rec32, cap * PAIR_REC * sizeof(float));
+  else alloc((void **)&h.pl_rec64, cap * PAIR_REC * sizeof(double));
   h.pl_cap = cap;
 }
 
@@ -836,7 +863,6 @@ static int mask_of(const CompSet &cs, bool input) {
 template <typename T>
 void real_apply(Handle &h, const double *xw, const double *in, Layout lin, const CompSet &cin,
                 double *out, Layout lout, const CompSet &cout, bool accumulate) {
-  (void)xw;
   RealArgs ra;
   ra.n = h.n;
   ra.lin = lin;
@@ -845,19 +871,24 @@ void real_apply(Handle &h, const double *xw, const double *in, Layout lin, const
   ra.out_mask = mask_of(cout, false);
   ra.accumulate = accumulate ? 1 : 0;
   ra.cap = (int64_t)h.pl_cap;
+  ra.L = h.p.box;
+  ra.def = h.def.on;
+  for (int k = 0; k < 9; ++k) ra.A[k] = h.def.A[k];
+  ra.inv_dr = 1.0 / h.dr;
+  ra.n2a = h.n2a;
+  ra.ntab = h.ntab;
   const T *tab, *rec;
   if constexpr (sizeof(T) == 8) {
     tab = h.g64.table;
-    rec = h.pl_rec;
+    rec = h.pl_rec64;
   } else {
     tab = h.g32.table;
     rec = h.pl_rec32;
   }
-  if (!rec) throw Error{PSE_ERR_INVALID, "no pair records of this precision"};
-  ProfScope ps(h, PK_REAL, (double)h.pl_pairs * (PAIR_REC * sizeof(T) + 4 + NC * 8) +
-                               (double)h.n * (NC * 8 * 2 + 8));
+  ProfScope ps(h, PK_REAL, (double)h.pl_pairs * (4.0 + (rec ? PAIR_REC * sizeof(T) : 0)) +
+                               (double)h.n * (NC * 8 * 2 + 8 + 24));
   hipLaunchKernelGGL(real_pair_kernel<T>, dim3(nblocks((size_t)h.n * GROUP, 256)), dim3(256), 0,
-                     h.stream, in, out, h.cells.perm, h.pl_start, h.pl_nbr, rec, tab, ra);
+                     h.stream, xw, in, out, h.cells.perm, h.pl_start, h.pl_nbr, rec, tab, ra);
   PSE_LAUNCH_CHECK();
 }
 
