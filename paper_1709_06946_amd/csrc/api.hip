@@ -421,16 +421,46 @@ static void run_graphed(Handle &h, const void *in, const void *out, int kind, F 
 // Solve M_ES S = b at xh (cell list current).  Mixed handles run FP32 GMRES
 // inside FP64 residual refinement: r = b - M_ES^(64) S, correction from the
 // FP32 operator, until the FP64 relative residual meets gmres_tol.
+// Right preconditioner of the constraint solve: out = P v with
+// P = (1 + d/a0)/a0 - M_r,ES / a0^2, the first-order Neumann approximation of
+// the inverse of M_ES's real-space part around its diagonal (d: the
+// real-space self term, a0: the whole operator's; the neighbours' near-field
+// coupling is what the approximation removes).  GMRES solves M_ES P y = b and
+// S = P y, so its residual is the residual of M_ES S = b itself.  One
+// real-space pair sum per application, in the precision of the operator.
+static void es_precond(Handle &h, const double *xh, const double *v, double *out, bool fp64) {
+  const size_t n5 = (size_t)h.n * 5;
+  const Layout l5{5, 6};
+  const CompSet es = comps_range(6, 11);
+  if (h.mixed && !fp64) real_apply<float>(h, xh, v, l5, es, out, l5, es, false);
+  else real_apply<double>(h, xh, v, l5, es, out, l5, es, false);
+  const double a0 = h.es_self_total;
+  vaxpby(h, (1.0 + h.es_self_real / a0) / a0, v, -1.0 / (a0 * a0), out, n5);
+}
+
 static void stresslet_solve(Handle &h, const double *xh, const double *b, double *S,
                             pse_stats &st, bool &converged) {
   const size_t n5 = (size_t)h.n * 5;
   // the operator reads and writes the 5-component vectors directly
   const Layout l5{5, 6};
-  auto make_op = [&, l5](bool fp64) {
-    return Op([&, fp64, l5](const double *in, double *o) {
-      run_graphed(h, in, o, fp64 ? 1 : 2,
-                  [&] { es_apply(h, xh, true, true, in, l5, o, l5, fp64); });
+  // the preconditioned operator M_ES P (graph kinds 3 and 4) and M_ES itself
+  // (1 and 2, for the FP64 residual)
+  auto make_op = [&, l5](bool fp64, bool precond) {
+    return Op([&, fp64, precond, l5](const double *in, double *o) {
+      run_graphed(h, in, o, (fp64 ? 1 : 2) + (precond ? 2 : 0), [&] {
+        const double *x = in;
+        if (precond) {
+          es_precond(h, xh, in, h.es_p, fp64);
+          x = h.es_p;
+        }
+        es_apply(h, xh, true, true, x, l5, o, l5, fp64);
+      });
     });
+  };
+  // S = P y in place (y in v, tmp a scratch vector)
+  auto unprecondition = [&](double *v) {
+    es_precond(h, xh, v, h.es_p, !h.mixed);
+    vcopy(h, v, h.es_p, n5);
   };
   if (h.async) {
     // device-checked: GMRES of exactly gmres_maxit iterations; mixed handles
@@ -438,18 +468,20 @@ static void stresslet_solve(Handle &h, const double *xh, const double *b, double
     // FP64 residual (statistics on the device)
     const int K = h.gm_cap;
     if (!h.mixed) {
-      gmres_dev(h, make_op(true), b, n5, S, K, h.d.gmres_tol);
+      gmres_dev(h, make_op(true, true), b, n5, S, K, h.d.gmres_tol);
+      unprecondition(S);
       hipLaunchKernelGGL(gmres_as_fp64_kernel, dim3(1), dim3(1), 0, h.stream, h.dstats);
       PSE_LAUNCH_CHECK();
       return;
     }
-    Op A32 = make_op(false), A64 = make_op(true);
+    Op A32 = make_op(false, true), A64 = make_op(true, false);
     double *b2 = h.small + h.small_len - 4, *r2 = b2 + 1;
     vzero(h, S, n5);
     vcopy(h, h.es_r, b, n5);
     multi_dot(h, b, n5, 1, b, n5, b2);
     for (int pass = 0; pass < h.ref_cap; ++pass) {
       gmres_dev(h, A32, h.es_r, n5, h.es_d, K, h.d.gmres_tol);
+      unprecondition(h.es_d);
       vaxpby(h, 1.0, h.es_d, 1.0, S, n5);
       A64(S, h.es_r);
       vaxpby(h, 1.0, b, -1.0, h.es_r, n5);
@@ -462,15 +494,16 @@ static void stresslet_solve(Handle &h, const double *xh, const double *b, double
     return;
   }
   if (!h.mixed) {
-    KrylovResult r = gmres(h, make_op(true), b, n5, S, h.d.gmres_restart, h.d.gmres_maxit,
-                           h.d.gmres_tol, &h.gm_prev[0]);
+    KrylovResult r = gmres(h, make_op(true, true), b, n5, S, h.d.gmres_restart,
+                           h.d.gmres_maxit, h.d.gmres_tol, &h.gm_prev[0]);
+    unprecondition(S);
     st.gmres_iters += r.iters;
     st.gmres_residual = r.resid;
     st.fp64_residual = r.resid;
     converged = converged && r.converged;
     return;
   }
-  Op A32 = make_op(false), A64 = make_op(true);
+  Op A32 = make_op(false, true), A64 = make_op(true, false);
   vzero(h, S, n5);
   vcopy(h, h.es_r, b, n5);
   double bnorm2 = 0.0;
@@ -492,6 +525,7 @@ static void stresslet_solve(Handle &h, const double *xh, const double *b, double
     st.gmres_iters += r.iters;
     st.gmres_residual = r.resid;
     st.refine_passes = pass + 1;
+    unprecondition(h.es_d);
     vaxpby(h, 1.0, h.es_d, 1.0, S, n5);
     A64(S, h.es_r);
     vaxpby(h, 1.0, b, -1.0, h.es_r, n5);
@@ -688,7 +722,7 @@ static void create(const pse_params &p, Handle &h) {
   handle_alloc(h, (void **)&h.xh, 3 * n * sizeof(double));
   double **vs[6] = {&h.v0, &h.v1, &h.v2, &h.v3, &h.v4, &h.v5};
   for (double **v : vs) handle_alloc(h, (void **)v, NC * n * sizeof(double));
-  double **es[4] = {&h.es_b, &h.es_x, &h.es_r, &h.es_d};
+  double **es[5] = {&h.es_b, &h.es_x, &h.es_r, &h.es_d, &h.es_p};
   for (double **v : es) handle_alloc(h, (void **)v, 5 * n * sizeof(double));
   handle_alloc(h, (void **)&h.lz_V, (size_t)(h.d.lanczos_maxit + 1) * NC * n * sizeof(double));
   handle_alloc(h, (void **)&h.gm_V, (size_t)(h.d.gmres_restart + 1) * 5 * n * sizeof(double));
@@ -703,7 +737,15 @@ static void create(const pse_params &p, Handle &h) {
   fill_int(h, h.dctl, CTL_WORDS, 0);
   hipLaunchKernelGGL(step_counter_kernel, dim3(1), dim3(1), 0, h.stream, h.dstep, 0);
   PSE_LAUNCH_CHECK();
+  // self terms of M_ES for the constraint solve's preconditioner: the
+  // real-space part from the coefficient table's r = 0 row (the pair block at
+  // zero separation acting on a stresslet gives 9 (3 d2 + d3) S), the whole
+  // operator's from the isolated sphere, 3 / (20 pi eta a^3)
+  double co0[NCOEF];
+  PSE_HIP(hipMemcpyAsync(co0, h.g64.table, sizeof(co0), hipMemcpyDeviceToHost, h.stream));
   PSE_HIP(hipStreamSynchronize(h.stream));
+  h.es_self_real = 9.0 * (3.0 * co0[4] + co0[5]);
+  h.es_self_total = 3.0 / (20.0 * M_PI * h.p.viscosity * std::pow(h.p.radius, 3));
 }
 
 static void release(Handle &h) {
@@ -713,7 +755,7 @@ static void release(Handle &h) {
                   h.sbins.start, h.sbins.count, h.sbins.scan_tmp, h.sbins.of, h.sbins.slot,
                   h.sbins.scat, h.sbins.perm, h.cells.trav, h.cells.bcount, h.cells.bstart,
                   h.xw, h.xh, h.v0, h.v1, h.v2, h.v3, h.v4, h.v5, h.es_b, h.es_x, h.es_r,
-                  h.es_d, h.lz_V, h.gm_V, h.small, h.dots, h.ktab, h.pl_cnt,
+                  h.es_d, h.es_p, h.lz_V, h.gm_V, h.small, h.dots, h.ktab, h.pl_cnt,
                   h.pl_start, h.pl_scan, h.pl_nbr, h.pl_rec64, h.pl_rec32, h.tl_cnt, h.tl_start,
                   h.tl_scan, h.tl_rec, h.bad_pos, h.ktab32, h.dctl, h.dstats, h.dstep,
                   h.dg_mu};

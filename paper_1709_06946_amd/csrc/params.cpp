@@ -234,7 +234,7 @@ size_t footprint(const pse_params &p, const pse_derived &d) {
   }
   bytes += (2 * (ncell3 + tiles3) + 4 + (ncell3 + tiles3) / 1024 + 16) * sizeof(int)
            + 8 * n * sizeof(int);
-  bytes += (2 * 3 * n + 6 * NC * n) * sizeof(double);
+  bytes += (2 * 3 * n + 6 * NC * n + 5 * 5 * n) * sizeof(double);
   if (d.deriv_gridding == 2) bytes += 6 * n * sizeof(double);
   bytes += (size_t)(d.lanczos_maxit + 1) * NC * n * sizeof(double);
   bytes += (size_t)(d.gmres_restart + 1) * 5 * n * sizeof(double);

@@ -178,6 +178,9 @@ struct Handle {
   double *v0 = nullptr, *v1 = nullptr, *v2 = nullptr, *v3 = nullptr;
   double *v4 = nullptr, *v5 = nullptr;
   double *es_b = nullptr, *es_x = nullptr, *es_r = nullptr, *es_d = nullptr;  // N x 5
+  double *es_p = nullptr;    // N x 5: the preconditioned vector of the constraint solve
+  // self terms of M_ES (real-space part, whole operator) for its preconditioner
+  double es_self_real = 0.0, es_self_total = 0.0;
 
   double *ktab = nullptr;    // per-|k|^2 radial factors (4 doubles per entry)
   float *ktab32 = nullptr;   // the same rounded to float (mixed handles)
