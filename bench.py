@@ -343,6 +343,27 @@ def served(n_req, steps, max_active, n_max, rate_frac, seed, workers=8):
                 concurrent=conc, concurrent_all_at_once=saturated, one_at_a_time=serial)
 
 
+def copy_rate_gbs(mib=1024, reps=20):
+    """Read + write rate of a plain 1 GiB device copy (torch copy_, events on
+    the current stream): the streaming rate HBM gives a kernel that reads and
+    writes every byte once, beside the published peak."""
+    import torch
+    a = torch.ones(mib * 2**20 // 4, dtype=torch.float32, device='cuda:0')
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2.0 * mib * 2**20 / (ms * 1e-3) / 1e9
+
+
 def copy_calibration(mib=1024, reps=3):
     """A plain device copy of known size, for scaling HBM byte counters
     (FETCH_SIZE / WRITE_SIZE under rocprofv3 --pmc): each copy reads and
@@ -413,6 +434,9 @@ def main():
     traffic_file = os.path.join(ROOT, 'profiles',
                                 f'hbm_traffic_{args.workload}_{FORM_NAME[prec]}.md')
     dom, roof = roofline(head['prof'], traffic_file, w['grid'], head['bracket_us'])
+    # context for the HBM fraction: what a plain device copy reaches here
+    roof['copy_GBs'] = round(copy_rate_gbs(), 1)
+    roof['frac_of_copy'] = round(roof['achieved'] / roof['copy_GBs'], 4)
     out = dict(
         metric=METRIC, value=round(head['value'], 1), unit='particle-steps/s', n_gpus=1,
         steps=args.steps, warmup=args.warmup, ms_per_step=round(head['ms_per_step'], 3),
