@@ -972,12 +972,28 @@ __device__ __forceinline__ void normals4(u4 r, double *z) {
   z[0] = ra * ca; z[1] = ra * sa; z[2] = rb * cb; z[3] = rb * sb;
 }
 
+// The same in FP32 (the wave noise of mixed-precision handles, whose grids
+// are FP32): u in (0, 1] from the same 32-bit words.
+__device__ __forceinline__ void normals4f(u4 r, double *z) {
+  const float s = 2.3283064365386963e-10f;  // 2^-32
+  const float u1 = ((float)r.x + 0.5f) * s, u2 = ((float)r.y + 0.5f) * s;
+  const float u3 = ((float)r.z + 0.5f) * s, u4v = ((float)r.w + 0.5f) * s;
+  const float ra = sqrtf(-2.0f * logf(u1)), rb = sqrtf(-2.0f * logf(u3));
+  float sa, ca, sb, cb;
+  sincospif(2.0f * u2, &sa, &ca);
+  sincospif(2.0f * u4v, &sb, &cb);
+  z[0] = ra * ca; z[1] = ra * sa; z[2] = rb * cb; z[3] = rb * sb;
+}
+
+template <bool F32 = false>
 __device__ __forceinline__ void philox_normals(uint64_t seed, uint64_t counter,
                                                uint32_t stream, uint32_t index,
                                                int nblk, double *z) {
   for (int b = 0; b < nblk; ++b) {
     u4 c{index, stream * 16u + (uint32_t)b, (uint32_t)counter, (uint32_t)(counter >> 32)};
-    normals4(philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32)), z + 4 * b);
+    const u4 r = philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+    if constexpr (F32) normals4f(r, z + 4 * b);
+    else normals4(r, z + 4 * b);
   }
 }
 
@@ -1017,7 +1033,7 @@ kspace_noise_kernel(const double2 *__restrict__ psi, uint64_t seed, uint64_t cou
     for (int m = 0; m < 3; ++m) ps[m] = psi[m * psz + cidx];
   } else {
     double z[8];
-    philox_normals(seed, counter, STREAM_WAVE, (uint32_t)cidx, 2, z);
+    philox_normals<sizeof(T) == 4>(seed, counter, STREAM_WAVE, (uint32_t)cidx, 2, z);
     const double s = 0.70710678118654752440;
     for (int m = 0; m < 3; ++m) ps[m] = double2{s * z[2 * m], s * z[2 * m + 1]};
   }
