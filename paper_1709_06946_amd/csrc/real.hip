@@ -463,25 +463,28 @@ __device__ __forceinline__ void lookup(const T *__restrict__ tab, T r, T inv_dr,
 }
 
 // Acting with the pair block M(r) on (F, C) of the partner; adds to U and D.
-template <typename T>
+// UF, UC: forces, couplets present; OU, OD: velocity, gradient wanted (the
+// coefficients a, b serve F -> U; c1, c2 serve F -> D and C -> U; d2, d3, d4
+// serve C -> D; only those of the selected couplings are read).
+template <typename T, bool UF, bool UC, bool OU, bool OD>
 __device__ __forceinline__ void pair_action(const T *co, const T *e, const T *F,
-                                            const T (*C)[3], bool useF, bool useC,
-                                            T *U, T (*D)[3]) {
+                                                const T (*C)[3], T *U, T (*D)[3]) {
   const T a = co[0], b = co[1], c1 = co[2], c2 = co[3];
   const T d2 = co[4], d3 = co[5], d4 = co[6];
   const T c14 = c1 + (T)4 * c2;
-  if (useF) {
+  if constexpr (UF) {
     const T eF = e[0] * F[0] + e[1] * F[1] + e[2] * F[2];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-      U[i] += a * F[i] + b * e[i] * eF;
+      if constexpr (OU) U[i] += a * F[i] + b * e[i] * eF;
+      if constexpr (OD)
 #pragma unroll
-      for (int j = 0; j < 3; ++j)
-        D[i][j] += (T)3 * (c1 * e[i] * e[j] * eF + c2 * ((i == j ? eF : (T)0) + F[j] * e[i])
-                           - c14 * F[i] * e[j]);
+        for (int j = 0; j < 3; ++j)
+          D[i][j] += (T)3 * (c1 * e[i] * e[j] * eF + c2 * ((i == j ? eF : (T)0) + F[j] * e[i])
+                             - c14 * F[i] * e[j]);
     }
   }
-  if (useC) {
+  if constexpr (UC) {
     T Ce[3], CTe[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
@@ -492,15 +495,16 @@ __device__ __forceinline__ void pair_action(const T *co, const T *e, const T *F,
     const T k7 = (T)7 * d3 + d4, k5 = (T)5 * d2 + d3;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-      U[i] += (T)(-3) * (c1 * e[i] * eCe + c2 * CTe[i] - c14 * Ce[i]);
+      if constexpr (OU) U[i] += (T)(-3) * (c1 * e[i] * eCe + c2 * CTe[i] - c14 * Ce[i]);
+      if constexpr (OD)
 #pragma unroll
-      for (int j = 0; j < 3; ++j) {
-        const T s = d4 * e[i] * e[j] * eCe
-                    + d3 * ((i == j ? eCe : (T)0) + e[j] * Ce[i] + e[j] * CTe[i]
-                            + e[i] * Ce[j] + e[i] * CTe[j])
-                    + d2 * (C[i][j] + C[j][i]) - k7 * e[j] * Ce[i] - k5 * C[i][j];
-        D[i][j] += (T)(-9) * s;
-      }
+        for (int j = 0; j < 3; ++j) {
+          const T s = d4 * e[i] * e[j] * eCe
+                      + d3 * ((i == j ? eCe : (T)0) + e[j] * Ce[i] + e[j] * CTe[i]
+                              + e[i] * Ce[j] + e[i] * CTe[j])
+                      + d2 * (C[i][j] + C[j][i]) - k7 * e[j] * Ce[i] - k5 * C[i][j];
+          D[i][j] += (T)(-9) * s;
+        }
     }
   }
 }
@@ -649,14 +653,13 @@ pair_list_kernel(const double *__restrict__ xw, const int *__restrict__ perm,
           const double inv = r > 0 ? 1.0 / r : 0.0;
 #pragma unroll
           for (int k = 0; k < 3; ++k) o[NCOEF + k] = d[k] * inv;
+          // field-major: field k of entry s at rec[k * cap + s]
           if (rec64) {
-            double *od = rec64 + (size_t)slot * PAIR_REC;
 #pragma unroll
-            for (int k = 0; k < PAIR_REC; ++k) od[k] = o[k];
+            for (int k = 0; k < PAIR_REC; ++k) rec64[(size_t)k * pa.cap + slot] = o[k];
           } else {
-            float *of = rec32 + (size_t)slot * PAIR_REC;
 #pragma unroll
-            for (int k = 0; k < PAIR_REC; ++k) of[k] = (float)o[k];
+            for (int k = 0; k < PAIR_REC; ++k) rec32[(size_t)k * pa.cap + slot] = (float)o[k];
           }
         }
       }
@@ -686,7 +689,10 @@ struct RealArgs {
 
 // M_r applied from the pair list: the self block (r = 0: only the isotropic
 // coefficients, table row 0) plus one pair block per stored neighbour.
-template <typename T>
+// UF, UC: forces / couplets among the inputs; OU, OD: velocity / gradient
+// outputs (from ra's masks); a stored entry's fields are read only when one
+// of the selected couplings uses them.
+template <typename T, bool UF, bool UC, bool OU, bool OD>
 __global__ void __launch_bounds__(256)
 real_pair_kernel(const double *__restrict__ xw, const double *__restrict__ in,
                  double *__restrict__ out, const int *__restrict__ perm,
@@ -697,7 +703,6 @@ real_pair_kernel(const double *__restrict__ xw, const double *__restrict__ in,
   const int lane = threadIdx.x % GROUP;
   if (t >= ra.n) return;
   const int i = perm[t];
-  const bool useF = ra.in_mask & 1, useC = (ra.in_mask & 6) != 0;
   T U[3] = {0, 0, 0};
   T D[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
   T F[3], C[3][3];
@@ -706,19 +711,31 @@ real_pair_kernel(const double *__restrict__ xw, const double *__restrict__ in,
     for (int j = 0; j < NCOEF; ++j) co[j] = tab[j];
     const T e0[3] = {0, 0, 0};
     load_moments<T>(in + (size_t)i * ra.lin.stride, ra.lin.off, ra.in_mask, F, C);
-    pair_action<T>(co, e0, F, C, useF, useC, U, D);
+    pair_action<T, UF, UC, OU, OD>(co, e0, F, C, U, D);
   }
+  constexpr bool NEED_AB = UF && OU, NEED_C12 = (UF && OD) || (UC && OU), NEED_D = UC && OD;
   const int s1 = (int)min((int64_t)start[t + 1], ra.cap);
   const double xi0 = xw[3 * i], xi1 = xw[3 * i + 1], xi2 = xw[3 * i + 2];
+  const size_t cap = (size_t)ra.cap;
   for (int s = start[t] + lane; s < s1; s += GROUP) {
     const int j = nbr[s];
-    T co[NCOEF], e[3];
+    T co[NCOEF] = {}, e[3];
     if (rec) {
-      const T *r = rec + (size_t)s * PAIR_REC;
+      if constexpr (NEED_AB) {
+        co[0] = rec[s];
+        co[1] = rec[cap + s];
+      }
+      if constexpr (NEED_C12) {
+        co[2] = rec[2 * cap + s];
+        co[3] = rec[3 * cap + s];
+      }
+      if constexpr (NEED_D) {
+        co[4] = rec[4 * cap + s];
+        co[5] = rec[5 * cap + s];
+        co[6] = rec[6 * cap + s];
+      }
 #pragma unroll
-      for (int k = 0; k < NCOEF; ++k) co[k] = r[k];
-#pragma unroll
-      for (int k = 0; k < 3; ++k) e[k] = r[NCOEF + k];
+      for (int k = 0; k < 3; ++k) e[k] = rec[(NCOEF + k) * cap + s];
     } else {
       double d[3];
       separation(xw, xi0, xi1, xi2, j, ra.L, ra.def, ra.A, d);
@@ -729,14 +746,16 @@ real_pair_kernel(const double *__restrict__ xw, const double *__restrict__ in,
       for (int k = 0; k < 3; ++k) e[k] = (T)(d[k] * inv);
     }
     load_moments<T>(in + (size_t)j * ra.lin.stride, ra.lin.off, ra.in_mask, F, C);
-    pair_action<T>(co, e, F, C, useF, useC, U, D);
+    pair_action<T, UF, UC, OU, OD>(co, e, F, C, U, D);
   }
+  if constexpr (OU)
 #pragma unroll
-  for (int k = 0; k < 3; ++k) U[k] = group_sum(U[k]);
+    for (int k = 0; k < 3; ++k) U[k] = group_sum(U[k]);
+  if constexpr (OD)
 #pragma unroll
-  for (int a = 0; a < 3; ++a)
+    for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int b = 0; b < 3; ++b) D[a][b] = group_sum(D[a][b]);
+      for (int b = 0; b < 3; ++b) D[a][b] = group_sum(D[a][b]);
   if (lane != 0) return;
   // component c of the output at out[row + c - off]
   const size_t row = (size_t)i * ra.lout.stride;
@@ -887,8 +906,30 @@ void real_apply(Handle &h, const double *xw, const double *in, Layout lin, const
   }
   ProfScope ps(h, PK_REAL, (double)h.pl_pairs * (4.0 + (rec ? PAIR_REC * sizeof(T) : 0)) +
                                (double)h.n * (NC * 8 * 2 + 8 + 24));
-  hipLaunchKernelGGL(real_pair_kernel<T>, dim3(nblocks((size_t)h.n * GROUP, 256)), dim3(256), 0,
-                     h.stream, xw, in, out, h.cells.perm, h.pl_start, h.pl_nbr, rec, tab, ra);
+  const bool uf = ra.in_mask & 1, uc = (ra.in_mask & 6) != 0;
+  const bool ou = ra.out_mask & 1, od = (ra.out_mask & 6) != 0;
+  const dim3 grid(nblocks((size_t)h.n * GROUP, 256)), block(256);
+  const auto launch = [&](auto UF, auto UC, auto OU, auto OD) {
+    hipLaunchKernelGGL((real_pair_kernel<T, decltype(UF)::value, decltype(UC)::value,
+                                         decltype(OU)::value, decltype(OD)::value>),
+                       grid, block, 0, h.stream, xw, in, out, h.cells.perm, h.pl_start,
+                       h.pl_nbr, rec, tab, ra);
+  };
+  using Y = std::true_type;
+  using N = std::false_type;
+  if (uf && uc) {
+    if (ou && od) launch(Y(), Y(), Y(), Y());
+    else if (ou) launch(Y(), Y(), Y(), N());
+    else launch(Y(), Y(), N(), Y());
+  } else if (uf) {
+    if (ou && od) launch(Y(), N(), Y(), Y());
+    else if (ou) launch(Y(), N(), Y(), N());
+    else launch(Y(), N(), N(), Y());
+  } else {
+    if (ou && od) launch(N(), Y(), Y(), Y());
+    else if (ou) launch(N(), Y(), Y(), N());
+    else launch(N(), Y(), N(), Y());
+  }
   PSE_LAUNCH_CHECK();
 }
 
