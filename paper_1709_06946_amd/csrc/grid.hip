@@ -142,6 +142,9 @@ tile_list_kernel(const double *__restrict__ x, GridGeom g, int S, int nb,
             a += a < 0 ? ng : 0;
             double wi = 0.0;
             if (a < P) {
+              // (reading these from a per-particle array formed once per
+              // position update measured slower: 2.5 against 1.4 ms at
+              // N = 10^6, 512^3 -- scattered loads, one particle per lane)
               const double dx = (st[d] + a) * g.h - xd;
               wi = g.knorm * exp(-g.kcoef * dx * dx);
               d0 = dx - i * g.h;

@@ -647,19 +647,21 @@ pair_list_kernel(const double *__restrict__ xw, const int *__restrict__ perm,
       if (ok) {
         nbr[slot] = j;
         if (rec64 || rec32) {
+          // field-major: field k of entry s at rec[k * cap + s]; the unit
+          // vector now, the distance in field 0 for pair_coef_kernel (the
+          // table interpolation runs there on every lane, not on the few
+          // lanes of a candidate batch that found a neighbour)
           const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-          double o[PAIR_REC];
-          lookup<double>(tab, r, pa.inv_dr, pa.n2a, pa.ntab, o);
           const double inv = r > 0 ? 1.0 / r : 0.0;
-#pragma unroll
-          for (int k = 0; k < 3; ++k) o[NCOEF + k] = d[k] * inv;
-          // field-major: field k of entry s at rec[k * cap + s]
+          const size_t cap = (size_t)pa.cap;
           if (rec64) {
+            rec64[slot] = r;
 #pragma unroll
-            for (int k = 0; k < PAIR_REC; ++k) rec64[(size_t)k * pa.cap + slot] = o[k];
+            for (int k = 0; k < 3; ++k) rec64[(NCOEF + k) * cap + slot] = d[k] * inv;
           } else {
+            rec32[slot] = (float)r;
 #pragma unroll
-            for (int k = 0; k < PAIR_REC; ++k) rec32[(size_t)k * pa.cap + slot] = (float)o[k];
+            for (int k = 0; k < 3; ++k) rec32[(NCOEF + k) * cap + slot] = (float)(d[k] * inv);
           }
         }
       }
@@ -671,6 +673,23 @@ pair_list_kernel(const double *__restrict__ xw, const int *__restrict__ perm,
     for (int off = 32; off > 0; off >>= 1) count += __shfl_xor(count, off, 64);
     if (lane == 0) cnt[t] = count;
   }
+}
+
+// The seven radial coefficients of every stored pair, interpolated from the
+// table at the distance the fill left in field 0 (entries up to the list's
+// length, read on the device, and its capacity).
+// In the records' precision, from the table of that precision.
+template <typename R>
+__global__ void __launch_bounds__(256)
+pair_coef_kernel(R *__restrict__ rec, const int *__restrict__ total, int64_t cap,
+                 const R *__restrict__ tab, double inv_dr, int n2a, int ntab) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t len = min((int64_t)total[0], cap);
+  if (s >= len) return;
+  R co[NCOEF];
+  lookup<R>(tab, rec[s], (R)inv_dr, n2a, ntab, co);
+#pragma unroll
+  for (int k = 0; k < NCOEF; ++k) rec[(size_t)k * cap + s] = co[k];
 }
 
 struct RealArgs {
@@ -779,6 +798,24 @@ real_pair_kernel(const double *__restrict__ xw, const double *__restrict__ in,
   }
 }
 
+// Second half of the pair-list fill: the coefficients of the stored pairs
+// (grid over pl_pairs: the count in synchronous handles, the capacity in
+// asynchronous ones, whose kernel reads the count on the device).
+static void pair_coefficients(Handle &h) {
+  if (h.pl_pairs == 0 || (!h.pl_rec64 && !h.pl_rec32)) return;
+  const dim3 grid(nblocks(h.pl_pairs, 256)), block(256);
+  const int *total = h.pl_start + h.n;
+  if (h.pl_rec64)
+    hipLaunchKernelGGL(pair_coef_kernel<double>, grid, block, 0, h.stream, h.pl_rec64, total,
+                       (int64_t)h.pl_cap, (const double *)h.g64.table, 1.0 / h.dr, h.n2a,
+                       h.ntab);
+  else
+    hipLaunchKernelGGL(pair_coef_kernel<float>, grid, block, 0, h.stream, h.pl_rec32, total,
+                       (int64_t)h.pl_cap, (const float *)h.g32.table, 1.0 / h.dr, h.n2a,
+                       h.ntab);
+  PSE_LAUNCH_CHECK();
+}
+
 // Builds the pair list for the current cell list; grows its storage when
 // the count exceeds the capacity (one host read of the total per update).
 static void build_pair_list(Handle &h, const double *xw) {
@@ -810,6 +847,7 @@ static void build_pair_list(Handle &h, const double *xw) {
                        h.cells.perm, h.cells.start, h.cells.of, pa, nullptr, h.pl_start,
                        h.g64.table, h.pl_nbr, h.pl_rec64, h.pl_rec32);
     PSE_LAUNCH_CHECK();
+    pair_coefficients(h);
     return;
   }
   int total = 0, bad = 0;
@@ -833,6 +871,7 @@ static void build_pair_list(Handle &h, const double *xw) {
                      h.cells.perm, h.cells.start, h.cells.of, pa, nullptr, h.pl_start,
                      h.g64.table, h.pl_nbr, h.pl_rec64, h.pl_rec32);
   PSE_LAUNCH_CHECK();
+  pair_coefficients(h);
 }
 
 void pair_storage(Handle &h, size_t cap, bool at_create) {
