@@ -131,28 +131,14 @@ tile_list_kernel(const double *__restrict__ x, GridGeom g, int S, int nb,
     } else {
       const unsigned long long m = __ballot(ok);
       if (ok) {
+        // the record's particle and, in its offset slots, the tile's first
+        // grid index along each axis; tile_weights_kernel forms the weights
+        // (on every lane, not on the lanes of a candidate batch that met the
+        // tile)
         const int e = pos + __popcll(m & ((1ull << lane) - 1ull));
         rec.p[e] = p;
         double *w = rec.w + (size_t)e * (3 * S + 3);
-        for (int d = 0; d < 3; ++d) {
-          const double xd = x[3 * p + d];
-          double d0 = 0.0;
-          for (int i = 0; i < S; ++i) {
-            int a = (tc[d] * S + i - st[d]) % ng;
-            a += a < 0 ? ng : 0;
-            double wi = 0.0;
-            if (a < P) {
-              // (reading these from a per-particle array formed once per
-              // position update measured slower: 2.5 against 1.4 ms at
-              // N = 10^6, 512^3 -- scattered loads, one particle per lane)
-              const double dx = (st[d] + a) * g.h - xd;
-              wi = g.knorm * exp(-g.kcoef * dx * dx);
-              d0 = dx - i * g.h;
-            }
-            w[d * S + i] = wi;
-          }
-          w[3 * S + d] = d0;
-        }
+        for (int d = 0; d < 3; ++d) w[3 * S + d] = (double)(tc[d] * S);
       }
       pos += __popcll(m);
     }
@@ -162,6 +148,39 @@ tile_list_kernel(const double *__restrict__ x, GridGeom g, int S, int nb,
     for (int off = 32; off > 0; off >>= 1) count += __shfl_xor(count, off, 64);
     if (lane == 0) cnt[tile] = count;
   }
+}
+
+// Second half of the tile-list fill, one thread per (record, axis): the S
+// one-dimensional weights of the record's particle at the tile's grid
+// positions along the axis (zero outside its stencil) and the offset d0 of
+// the first stencil point inside the tile from that position.
+__global__ void __launch_bounds__(256)
+tile_weights_kernel(const double *__restrict__ x, GridGeom g, int S,
+                    const int *__restrict__ total, int64_t cap, TileRecs rec) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t len = min((int64_t)total[0], cap);
+  if (t >= 3 * len) return;
+  const int64_t e = t / 3;
+  const int d = (int)(t % 3);
+  const int P = g.P, ng = g.ng;
+  const int p = rec.p[e];
+  double *w = rec.w + (size_t)e * (3 * S + 3);
+  const int t0 = (int)w[3 * S + d];
+  const double xd = x[3 * p + d];
+  const int st = stencil_start(xd, g.h, P);
+  double d0 = 0.0;
+  for (int i = 0; i < S; ++i) {
+    int a = (t0 + i - st) % ng;
+    a += a < 0 ? ng : 0;
+    double wi = 0.0;
+    if (a < P) {
+      const double dx = (st + a) * g.h - xd;
+      wi = g.knorm * exp(-g.kcoef * dx * dx);
+      d0 = dx - i * g.h;
+    }
+    w[d * S + i] = wi;
+  }
+  w[3 * S + d] = d0;
 }
 
 // Gather form of the spreading sum: one workgroup per tile of S^3 grid
@@ -1244,6 +1263,11 @@ void build_tile_lists(Handle &h, const double *xw) {
   hipLaunchKernelGGL((tile_list_kernel<true>), dim3(blocks), dim3(256), 0, h.stream, xw, g,
                      h.stile, nb, (const int *)h.sbins.start, (const int *)h.sbins.perm, nullptr,
                      (const int *)h.tl_start, tile_recs(h));
+  PSE_LAUNCH_CHECK();
+  // grid over the capacity; the kernel reads the list's length on the device
+  hipLaunchKernelGGL(tile_weights_kernel, dim3(nblocks(3 * h.tl_cap, 256)), dim3(256), 0,
+                     h.stream, xw, g, h.stile, (const int *)h.tl_start + ntile,
+                     (int64_t)h.tl_cap, tile_recs(h));
   PSE_LAUNCH_CHECK();
 }
 
