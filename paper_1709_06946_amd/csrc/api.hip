@@ -709,6 +709,7 @@ static void create(const pse_params &p, Handle &h) {
   h.pl_cap = (h.async ? 2 : 1) * pair_capacity(h.p, h.d);
   pair_storage(h, h.pl_cap, true);
   if (h.deriv) handle_alloc(h, (void **)&h.dg_mu, 6 * n * sizeof(double));
+  handle_alloc(h, (void **)&h.mpack, 12 * n * sizeof(double));
   for (Bins *b : {&h.cells, &h.sbins}) {
     if (b->nc == 0) continue;
     const size_t ncells = (size_t)b->nc * b->nc * b->nc;
@@ -765,7 +766,7 @@ static void release(Handle &h) {
                   h.es_d, h.es_p, h.lz_V, h.gm_V, h.small, h.dots, h.ktab, h.pl_cnt,
                   h.pl_start, h.pl_scan, h.pl_nbr, h.pl_rec64, h.pl_rec32, h.tl_cnt, h.tl_start,
                   h.tl_scan, h.tl_rec, h.bad_pos, h.ktab32, h.dctl, h.dstats, h.dstep,
-                  h.dg_mu};
+                  h.dg_mu, h.mpack};
   if (!h.arena)
     for (void *p : ptrs) dev_free(p);
   clear_graphs(h);

@@ -236,6 +236,7 @@ size_t footprint(const pse_params &p, const pse_derived &d) {
            + 8 * n * sizeof(int);
   bytes += (2 * 3 * n + 6 * NC * n + 5 * 5 * n) * sizeof(double);
   if (d.deriv_gridding == 2) bytes += 6 * n * sizeof(double);
+  bytes += 12 * n * sizeof(double);   // packed moments of the pair sums
   bytes += (size_t)(d.lanczos_maxit + 1) * NC * n * sizeof(double);
   bytes += (size_t)(d.gmres_restart + 1) * 5 * n * sizeof(double);
   const size_t small = 4 * (size_t)(d.gmres_restart + 2) * (d.gmres_restart + 2)

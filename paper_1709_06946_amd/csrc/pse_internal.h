@@ -186,6 +186,7 @@ struct Handle {
   float *ktab32 = nullptr;   // the same rounded to float (mixed handles)
   int *bad_pos = nullptr;    // set by the wrap kernel on a non-finite coordinate
   double *dg_mu = nullptr;   // derivative gridding: moment corrections, 6 per particle
+  void *mpack = nullptr;     // pair sums: moments packed 12 per particle (FP64 size)
   // real-space pair list (CSR in cell order): start[N+1], neighbour index and
   // 10 numbers of pair data per entry (doubles in FP64 handles, floats in
   // mixed ones); counts and scan scratch

@@ -509,28 +509,55 @@ __device__ __forceinline__ void pair_action(const T *co, const T *e, const T *F,
   }
 }
 
-// Moments of one particle; v points at its vector in layout lo (component c
-// at v[c - lo.off]), only the components selected by mask are read.
+// The moments of the particles packed for the pair sums: 12 numbers per
+// particle in the sum's precision, (F, L, s1..s5, 0), components absent
+// from the input mask zero, so that a neighbour's moments take three
+// 16-byte loads (FP32) or six (FP64) instead of one load per component.
 template <typename T>
-__device__ __forceinline__ void load_moments(const double *__restrict__ v0, int off, int mask,
-                                             T *F, T (*C)[3]) {
-  auto v = [&](int c) { return v0[c - off]; };
+__global__ void __launch_bounds__(256)
+pack_moments_kernel(const double *__restrict__ in, Layout lin, int mask, int64_t n,
+                    T *__restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * 12) return;
+  const int64_t p = t / 12;
+  const int c = (int)(t % 12);
+  const int grp = c < 3 ? 1 : (c < 6 ? 2 : 4);
+  out[t] = (c < NC && (mask & grp)) ? (T)in[p * lin.stride + c - lin.off] : (T)0;
+}
+
+template <typename T>
+__device__ __forceinline__ void load_packed(const T *__restrict__ m, int mask, T *F,
+                                            T (*C)[3]) {
+  T v[12];
+  if constexpr (sizeof(T) == 4) {
+    const float4 *m4 = reinterpret_cast<const float4 *>(m);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const float4 a = m4[k];
+      v[4 * k] = a.x; v[4 * k + 1] = a.y; v[4 * k + 2] = a.z; v[4 * k + 3] = a.w;
+    }
+  } else {
+    const double2 *m2 = reinterpret_cast<const double2 *>(m);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const double2 a = m2[k];
+      v[2 * k] = a.x; v[2 * k + 1] = a.y;
+    }
+  }
   const T r2 = (T)0.70710678118654752440, r6 = (T)0.40824829046386301637;
   for (int i = 0; i < 3; ++i) {
-    F[i] = (T)0;
+    F[i] = v[i];
     for (int j = 0; j < 3; ++j) C[i][j] = (T)0;
   }
-  if (mask & 1)
-    for (int i = 0; i < 3; ++i) F[i] = (T)v(i);
   if (mask & 2) {
     // C^A_mn = -1/2 eps_mnk L_k
-    const T Lx = (T)v(3), Ly = (T)v(4), Lz = (T)v(5);
+    const T Lx = v[3], Ly = v[4], Lz = v[5];
     C[0][1] -= (T)0.5 * Lz; C[1][0] += (T)0.5 * Lz;
     C[0][2] += (T)0.5 * Ly; C[2][0] -= (T)0.5 * Ly;
     C[1][2] -= (T)0.5 * Lx; C[2][1] += (T)0.5 * Lx;
   }
   if (mask & 4) {
-    const T s1 = (T)v(6), s2 = (T)v(7), s3 = (T)v(8), s4 = (T)v(9), s5 = (T)v(10);
+    const T s1 = v[6], s2 = v[7], s3 = v[8], s4 = v[9], s5 = v[10];
     C[0][1] += r2 * s1; C[1][0] += r2 * s1;
     C[0][2] += r2 * s2; C[2][0] += r2 * s2;
     C[1][2] += r2 * s3; C[2][1] += r2 * s3;
@@ -713,7 +740,7 @@ struct RealArgs {
 // of the selected couplings uses them.
 template <typename T, bool UF, bool UC, bool OU, bool OD>
 __global__ void __launch_bounds__(256)
-real_pair_kernel(const double *__restrict__ xw, const double *__restrict__ in,
+real_pair_kernel(const double *__restrict__ xw, const T *__restrict__ in,
                  double *__restrict__ out, const int *__restrict__ perm,
                  const int *__restrict__ start, const int *__restrict__ nbr,
                  const T *__restrict__ rec, const T *__restrict__ tab, RealArgs ra) {
@@ -729,7 +756,7 @@ real_pair_kernel(const double *__restrict__ xw, const double *__restrict__ in,
     T co[NCOEF];
     for (int j = 0; j < NCOEF; ++j) co[j] = tab[j];
     const T e0[3] = {0, 0, 0};
-    load_moments<T>(in + (size_t)i * ra.lin.stride, ra.lin.off, ra.in_mask, F, C);
+    load_packed<T>(in + (size_t)i * 12, ra.in_mask, F, C);
     pair_action<T, UF, UC, OU, OD>(co, e0, F, C, U, D);
   }
   constexpr bool NEED_AB = UF && OU, NEED_C12 = (UF && OD) || (UC && OU), NEED_D = UC && OD;
@@ -764,7 +791,7 @@ real_pair_kernel(const double *__restrict__ xw, const double *__restrict__ in,
 #pragma unroll
       for (int k = 0; k < 3; ++k) e[k] = (T)(d[k] * inv);
     }
-    load_moments<T>(in + (size_t)j * ra.lin.stride, ra.lin.off, ra.in_mask, F, C);
+    load_packed<T>(in + (size_t)j * 12, ra.in_mask, F, C);
     pair_action<T, UF, UC, OU, OD>(co, e, F, C, U, D);
   }
   if constexpr (OU)
@@ -947,12 +974,16 @@ void real_apply(Handle &h, const double *xw, const double *in, Layout lin, const
                                (double)h.n * (NC * 8 * 2 + 8 + 24));
   const bool uf = ra.in_mask & 1, uc = (ra.in_mask & 6) != 0;
   const bool ou = ra.out_mask & 1, od = (ra.out_mask & 6) != 0;
+  T *mp = reinterpret_cast<T *>(h.mpack);
+  hipLaunchKernelGGL(pack_moments_kernel<T>, dim3(nblocks((size_t)h.n * 12, 256)), dim3(256),
+                     0, h.stream, in, lin, ra.in_mask, h.n, mp);
+  PSE_LAUNCH_CHECK();
   const dim3 grid(nblocks((size_t)h.n * GROUP, 256)), block(256);
   const auto launch = [&](auto UF, auto UC, auto OU, auto OD) {
     hipLaunchKernelGGL((real_pair_kernel<T, decltype(UF)::value, decltype(UC)::value,
                                          decltype(OU)::value, decltype(OD)::value>),
-                       grid, block, 0, h.stream, xw, in, out, h.cells.perm, h.pl_start,
-                       h.pl_nbr, rec, tab, ra);
+                       grid, block, 0, h.stream, xw, (const T *)mp, out, h.cells.perm,
+                       h.pl_start, h.pl_nbr, rec, tab, ra);
   };
   using Y = std::true_type;
   using N = std::false_type;
