@@ -10,7 +10,8 @@
 // captured graph of the whole step (one host launch per step).  Several
 // admitted requests execute at once, so their kernels overlap on the
 // device; requests arriving meanwhile are admitted as slots and memory free
-// up.  Requests with large grids (kHeavyGrid) run alone.  Each step's
+// up.  At most one request with a large grid (kHeavyGrid) runs at a time;
+// small ones run beside it.  Each step's
 // completion time is recorded for latency percentiles.
 #include <hip/hip_runtime.h>
 
@@ -219,9 +220,10 @@ void worker(pse_server *s) {
         if (s->stopping && s->queue.empty()) return true;
         if (s->queue.empty()) return false;
         if (s->active == 0) return true;
-        // FIFO: a heavy request at the head waits for an idle device, and
-        // nothing joins a heavy request that is running
-        if (s->heavy_active || s->queue.front()->heavy) return false;
+        // FIFO; one heavy request at a time (two would only share the
+        // same HBM), and small requests join whatever runs, within the
+        // budget and the limit on requests in flight
+        if (s->queue.front()->heavy && s->heavy_active) return false;
         return s->used + s->queue.front()->bytes <= s->budget;
       });
       if (s->queue.empty()) return;   // stopping
