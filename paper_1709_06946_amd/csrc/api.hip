@@ -316,8 +316,12 @@ static void wave_sqrt_t(Handle &h, const double *xw, const double *psi, uint64_t
   const DGPlan d = dg_plan(h, CompSet{}, cout);
   if (d.hv) {
     // derivative gridding of the rotation and strain outputs
-    kspace_noise<T>(h, psi, seed, counter, G.gout, d.gout, true);
-    rfft3d<T>(h, gout, G.twiddle, d.gout.n, +1);
+    if (kspace_noise_z<T>(h, psi, seed, counter, G.gout, d.gout, G.twiddle)) {
+      rfft_xy<T>(h, gout, G.twiddle, d.gout.n, +1);
+    } else {
+      kspace_noise<T>(h, psi, seed, counter, G.gout, d.gout, true);
+      rfft3d<T>(h, gout, G.twiddle, d.gout.n, +1);
+    }
     interp_deriv<T>(h, xw, gout, d.hu, cout, out, lout, false, 1.0);
     return;
   }

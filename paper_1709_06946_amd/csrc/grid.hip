@@ -1021,6 +1021,61 @@ __device__ __forceinline__ void philox_normals(uint64_t seed, uint64_t counter,
 
 enum : uint32_t { STREAM_REAL = 1, STREAM_WAVE = 2 };
 
+// u(k) of the wave noise at stored mode (ix, iy, iz) (not a zeroed mode) and
+// its radial factors tb and wave vector kv (see kspace_noise_kernel).
+template <bool F32>
+__device__ __forceinline__ void noise_mode(const double2 *__restrict__ psi, uint64_t seed,
+                                           uint64_t counter, const KGeom &kg,
+                                           const double4 *__restrict__ ktab, int ix, int iy,
+                                           int iz, double2 uu[3], double4 &tb, double kv[3]) {
+  const int n = kg.ng, hx = n / 2, hp = n / 2 + 1;
+  // canonical member: kx > 0; or kx = 0 and ky in (0, n/2); or kx = ky = 0, kz in (0, n/2)
+  const bool canon = ix > 0 || (iy > 0 && iy < hx) || (iy == 0 && iz < hx);
+  const int cy = canon ? iy : (n - iy) % n, cz = canon ? iz : (n - iz) % n;
+  const size_t cidx = ((size_t)cz * n + cy) * hp + ix;   // index in the noise layout
+  double2 ps[3];
+  if (psi) {
+    const size_t psz = (size_t)n * n * hp;
+    for (int m = 0; m < 3; ++m) ps[m] = psi[m * psz + cidx];
+  } else {
+    double z[8];
+    philox_normals<F32>(seed, counter, STREAM_WAVE, (uint32_t)cidx, 2, z);
+    const double s = 0.70710678118654752440;
+    for (int m = 0; m < 3; ++m) ps[m] = double2{s * z[2 * m], s * z[2 * m + 1]};
+  }
+  if (!canon)
+    for (int m = 0; m < 3; ++m) ps[m].y = -ps[m].y;
+  const int ky = kidx(iy, n), kz = kidx(iz, n);
+  double iv[3], inv;
+  if (kg.def) {
+    // deformed lattice: the projection and the radial factors of the true k
+    deformed_k(kg, ix, ky, kz, kv);
+    const double k2 = kv[0] * kv[0] + kv[1] * kv[1] + kv[2] * kv[2];
+    tb = radial_factors(kg, k2);
+    for (int m = 0; m < 3; ++m) iv[m] = kv[m];
+    inv = 1.0 / k2;
+  } else {
+    const int n2 = ix * ix + ky * ky + kz * kz;
+    tb = ktab[n2];
+    kv[0] = kg.twopi_L * ix;
+    kv[1] = kg.twopi_L * ky;
+    kv[2] = kg.twopi_L * kz;
+    iv[0] = (double)ix;
+    iv[1] = (double)ky;
+    iv[2] = (double)kz;
+    inv = 1.0 / (double)n2;
+  }
+  double2 kr{0, 0};
+  for (int m = 0; m < 3; ++m) {
+    kr.x += iv[m] * ps[m].x;
+    kr.y += iv[m] * ps[m].y;
+  }
+  for (int m = 0; m < 3; ++m) {
+    uu[m].x = tb.w * (ps[m].x - iv[m] * kr.x * inv);
+    uu[m].y = tb.w * (ps[m].y - iv[m] * kr.y * inv);
+  }
+}
+
 // Wave-space square root (Eq. FFTsqrt): for each stored mode k,
 //   u(k) = h^3 / sqrt(V eta) sqrt(1 + k^2/4xi^2) exp(-(1 - eta_s) k^2/8xi^2) / k
 //          (I - kk) psi(k),   W_c(k) = P_c^+(k) u(k),
@@ -1045,53 +1100,10 @@ kspace_noise_kernel(const double2 *__restrict__ psi, uint64_t seed, uint64_t cou
     for (int q = 0; q < cout.n; ++q) out[q * hsz + tid] = C{(T)0, (T)0};
     return;
   }
-  // canonical member: kx > 0; or kx = 0 and ky in (0, n/2); or kx = ky = 0, kz in (0, n/2)
-  const bool canon = ix > 0 || (iy > 0 && iy < hx) || (iy == 0 && iz < hx);
-  const int cy = canon ? iy : (n - iy) % n, cz = canon ? iz : (n - iz) % n;
-  const size_t cidx = ((size_t)cz * n + cy) * hp + ix;   // index in the noise layout
-  double2 ps[3];
-  if (psi) {
-    const size_t psz = (size_t)n * n * hp;
-    for (int m = 0; m < 3; ++m) ps[m] = psi[m * psz + cidx];
-  } else {
-    double z[8];
-    philox_normals<sizeof(T) == 4>(seed, counter, STREAM_WAVE, (uint32_t)cidx, 2, z);
-    const double s = 0.70710678118654752440;
-    for (int m = 0; m < 3; ++m) ps[m] = double2{s * z[2 * m], s * z[2 * m + 1]};
-  }
-  if (!canon)
-    for (int m = 0; m < 3; ++m) ps[m].y = -ps[m].y;
-  const int ky = kidx(iy, n), kz = kidx(iz, n);
-  double kv[3], iv[3], inv;
-  double4 tb;
-  if (kg.def) {
-    // deformed lattice: the projection and the radial factors of the true k
-    deformed_k(kg, ix, ky, kz, kv);
-    const double k2 = kv[0] * kv[0] + kv[1] * kv[1] + kv[2] * kv[2];
-    tb = radial_factors(kg, k2);
-    for (int m = 0; m < 3; ++m) iv[m] = kv[m];
-    inv = 1.0 / k2;
-  } else {
-    const int n2 = ix * ix + ky * ky + kz * kz;
-    tb = ktab[n2];
-    kv[0] = kg.twopi_L * ix;
-    kv[1] = kg.twopi_L * ky;
-    kv[2] = kg.twopi_L * kz;
-    iv[0] = (double)ix;
-    iv[1] = (double)ky;
-    iv[2] = (double)kz;
-    inv = 1.0 / (double)n2;
-  }
-  double2 kr{0, 0};
-  for (int m = 0; m < 3; ++m) {
-    kr.x += iv[m] * ps[m].x;
-    kr.y += iv[m] * ps[m].y;
-  }
   double2 uu[3];
-  for (int m = 0; m < 3; ++m) {
-    uu[m].x = tb.w * (ps[m].x - iv[m] * kr.x * inv);
-    uu[m].y = tb.w * (ps[m].y - iv[m] * kr.y * inv);
-  }
+  double4 tb;
+  double kv[3];
+  noise_mode<sizeof(T) == 4>(psi, seed, counter, kg, ktab, ix, iy, iz, uu, tb, kv);
   for (int q = 0; q < cout.n; ++q) {
     const int c = cout.idx[q];
     double2 w;
@@ -1103,6 +1115,76 @@ kspace_noise_kernel(const double2 *__restrict__ psi, uint64_t seed, uint64_t cou
       w = apply_Pdag<double2, double>(c, uu, kv, tb.x, tb.y);
     }
     out[q * hsz + tid] = C{(T)w.x, (T)w.y};
+  }
+}
+
+
+// The wave noise of derivative gridding with the inverse z transform fused
+// (cubic lattice, long lines): a workgroup owns TL neighbouring kx columns
+// at one ky as the k-space kernels do; each thread forms u(k) of its E modes
+// (noise_mode), keeps them with the factors j0(ka) and 3 f1(ka), and for
+// every output grid code (0-2: j0 u^, 3-5: 3 f1 u^) transforms the line back
+// along z and stores it -- the grids the y and x passes take next, without
+// the round trip through HBM of a separate noise kernel and z pass.
+template <typename T, int N, int E>
+__global__ void __launch_bounds__(512)
+kspace_noise_z_kernel(const double2 *__restrict__ psi, uint64_t seed, uint64_t counter,
+                      cplx<T> *__restrict__ out, CompSet cout, KGeom kg,
+                      const double4 *__restrict__ ktab, const cplx<T> *__restrict__ tw, int TL,
+                      const uint64_t *counter_dev) {
+  using C = cplx<T>;
+  constexpr int M = N / 2;
+  using S = Shape<N, E>;
+  constexpr int R0 = S::first(false), RL = S::last(false);
+  extern __shared__ unsigned char smem_raw[];
+  C *lds = reinterpret_cast<C *>(smem_raw);
+  if (counter_dev) counter = *counter_dev;
+  const int tiles = M / TL;
+  const int lb = (int)xcd_block(blockIdx.x, gridDim.x);
+  const int xt = lb % tiles, iy = lb / tiles;
+  const int line = threadIdx.x % TL, t = threadIdx.x / TL;
+  const int ix = xt * TL + line;
+  const size_t hsz = (size_t)M * N * N, plane = (size_t)N * M;
+  const size_t base = (size_t)iy * M + ix;
+  C u[3][E];
+  T fj[E], ff[E];
+#pragma unroll
+  for (int b = 0; b < E / RL; ++b)
+#pragma unroll
+    for (int r = 0; r < RL; ++r) {
+      const int e = b * RL + r;
+      const int iz = reg_pos<N, E, RL>(t, b, r);
+      if (zero_mode(ix, iy, iz, N)) {
+#pragma unroll
+        for (int m = 0; m < 3; ++m) u[m][e] = C{(T)0, (T)0};
+        fj[e] = ff[e] = (T)0;
+        continue;
+      }
+      double2 uu[3];
+      double4 tb;
+      double kv[3];
+      noise_mode<sizeof(T) == 4>(psi, seed, counter, kg, ktab, ix, iy, iz, uu, tb, kv);
+#pragma unroll
+      for (int m = 0; m < 3; ++m) u[m][e] = C{(T)uu[m].x, (T)uu[m].y};
+      fj[e] = (T)tb.x;
+      ff[e] = (T)(3.0 * tb.y);
+    }
+  for (int q = 0; q < cout.n; ++q) {
+    const int c = cout.idx[q];
+    C v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const T f = c < 3 ? fj[e] : ff[e];
+#pragma unroll
+      for (int m = 0; m < 3; ++m)
+        if (m == c % 3) v[e] = C{f * u[m][e].x, f * u[m][e].y};
+    }
+    reg_fft_inverse<T, N, E>(v, t, lds, TL, line, tw);
+    C *dst = out + (size_t)q * hsz + base;
+#pragma unroll
+    for (int b = 0; b < E / R0; ++b)
+#pragma unroll
+      for (int r = 0; r < R0; ++r) dst[reg_pos<N, E, R0>(t, b, r) * plane] = v[b * R0 + r];
   }
 }
 
@@ -1703,6 +1785,24 @@ void kspace_deformed(Handle &h, const cplx<T> *in, const CompSet &cin, cplx<T> *
 }
 
 template <typename T>
+bool kspace_noise_z(Handle &h, const double *psi, uint64_t seed, uint64_t counter,
+                    cplx<T> *out, const CompSet &cout, const cplx<T> *tw) {
+  // long power-of-two lines of a cubic lattice (measured at 512)
+  if (h.def.on || h.d.grid != 512) return false;
+  constexpr int N = 512, E = 8, TPL = N / E;
+  const int tl = 512 / TPL;
+  const size_t hsz = h.ngrid / 2;
+  ProfScope ps(h, PK_NOISE, (double)cout.n * hsz * sizeof(cplx<T>) + (psi ? 3.0 * hsz * 16 : 0.0));
+  const size_t lds = (size_t)tl * N * sizeof(cplx<T>);
+  const unsigned nb = (unsigned)(N * (N / 2 / tl));
+  hipLaunchKernelGGL((kspace_noise_z_kernel<T, N, E>), dim3(nb), dim3(tl * TPL), lds,
+                     h.stream, (const double2 *)psi, seed, counter, out, cout, kgeom(h),
+                     (const double4 *)h.ktab, tw, tl, h.counter_dev);
+  PSE_LAUNCH_CHECK();
+  return true;
+}
+
+template <typename T>
 void kspace_noise(Handle &h, const double *psi, uint64_t seed, uint64_t counter,
                   cplx<T> *out, const CompSet &cout, bool dg) {
   const size_t hsz = h.ngrid / 2;
@@ -1747,6 +1847,8 @@ template <typename T> void to_double(Handle &h, const T *src, size_t n, double *
                                    cplx<T> *, const CompSet &);                  \
   template void kspace_noise<T>(Handle &, const double *, uint64_t, uint64_t,    \
                                 cplx<T> *, const CompSet &, bool);               \
+  template bool kspace_noise_z<T>(Handle &, const double *, uint64_t, uint64_t,  \
+                                  cplx<T> *, const CompSet &, const cplx<T> *);  \
   template void kspace_fused<T>(Handle &, const cplx<T> *, const CompSet &,      \
                                 cplx<T> *, const CompSet &, const cplx<T> *,     \
                                 bool);                                           \

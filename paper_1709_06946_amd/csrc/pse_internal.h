@@ -337,6 +337,11 @@ void interpolate(Handle &h, const double *x, const T *grids, const CompSet &cs, 
 template <typename T>
 void kspace_noise(Handle &h, const double *psi, uint64_t seed, uint64_t counter,
                   cplx<T> *out, const CompSet &cout, bool dg = false);
+// the same for derivative-gridding codes, with the inverse z transform
+// fused; false (nothing launched) where that form is not built
+template <typename T>
+bool kspace_noise_z(Handle &h, const double *psi, uint64_t seed, uint64_t counter,
+                    cplx<T> *out, const CompSet &cout, const cplx<T> *tw);
 // z transform + k-space + inverse z transform in one kernel; dg: cin and
 // cout are grid codes of derivative gridding, 0-2 force grids (in) or
 // velocity grids j0 u (out), 3-5 couplet grids (in) or 3 f1 u grids (out)
