@@ -724,6 +724,25 @@ __device__ __forceinline__ bool zero_mode(int ix, int iy, int iz, int n) {
 // Gaussian's gradient (factor -3 f1(ka)) on input, so rho = j0 F^ - 3 f1 D^;
 // on output 0-2 the velocity grids j0(ka) u^ and 3-5 the grids
 // v^ = 3 f1(ka) u^ whose gradient the interpolation takes.
+// The twiddle table in LDS behind a kernel's exchange area (TL lines of N
+// elements): the transforms then read their twiddles with LDS loads.  Read
+// from global memory inside a transform, each twiddle's first use waits on
+// the in-order vector-memory counter, that is for every grid load and store
+// issued before it, so no transform overlaps the grid traffic in flight.  A
+// thread takes its entry before the grid loads (tw_fetch) and stores it
+// after issuing them (tw_store); a transform's first pass uses no twiddles,
+// so the first exchange's barrier orders these stores before any read.
+template <typename C, int N>
+__device__ __forceinline__ C tw_fetch(const C *__restrict__ tw) {
+  return threadIdx.x < N ? tw[threadIdx.x] : C{};
+}
+
+template <typename C, int N>
+__device__ __forceinline__ void tw_store(C *twl, C first, const C *__restrict__ tw) {
+  if (threadIdx.x < N) twl[threadIdx.x] = first;
+  for (int i = (int)(threadIdx.x + blockDim.x); i < N; i += blockDim.x) twl[i] = tw[i];
+}
+
 template <typename T, int N, bool DG>
 __global__ void __launch_bounds__(512)
 kspace_fused_kernel(const cplx<T> *__restrict__ in, CompSet cin, cplx<T> *__restrict__ out,
@@ -784,11 +803,14 @@ kspace_fused_kernel(const cplx<T> *__restrict__ in, CompSet cin, cplx<T> *__rest
   };
   // the next component's z-line is loaded while the current one is
   // transformed (the barriers of the exchanges wait on LDS traffic only)
+  const C tw0 = tw_fetch<C, N>(tw);
   C v[E], vn[E];
 #pragma unroll
   for (int b = 0; b < E / R0; ++b)
 #pragma unroll
     for (int r = 0; r < R0; ++r) vn[b * R0 + r] = in[base + reg_pos<N, E, R0>(t, b, r) * plane];
+  C *twl = lds + (size_t)TL * N;
+  tw_store<C, N>(twl, tw0, tw);
   for (int p = 0; p < cin.n; ++p) {
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e] = vn[e];
@@ -799,7 +821,7 @@ kspace_fused_kernel(const cplx<T> *__restrict__ in, CompSet cin, cplx<T> *__rest
 #pragma unroll
         for (int r = 0; r < R0; ++r) vn[b * R0 + r] = src[reg_pos<N, E, R0>(t, b, r) * plane];
     }
-    reg_fft_forward<T, N, E>(v, t, lds, TL, line, tw);
+    reg_fft_forward<T, N, E>(v, t, lds, TL, line, twl);
     const int c = cin.idx[p];
 #pragma unroll
     for (int b = 0; b < E / RL; ++b)
@@ -874,7 +896,7 @@ kspace_fused_kernel(const cplx<T> *__restrict__ in, CompSet cin, cplx<T> *__rest
           v[e] = apply_Pdag<C, T>(c, rho[e], kv, j0_at(e), f1_at(e));
         }
       }
-    reg_fft_inverse<T, N, E>(v, t, lds, TL, line, tw);
+    reg_fft_inverse<T, N, E>(v, t, lds, TL, line, twl);
     C *dst = out + (size_t)q * hsz + base;
 #pragma unroll
     for (int b = 0; b < E / R0; ++b)
@@ -911,6 +933,7 @@ kspace_dg3_kernel(const cplx<T> *__restrict__ in, cplx<T> *__restrict__ out, KGe
   const int ky = kidx(iy, N);
   const size_t hsz = (size_t)M * N * N, plane = (size_t)N * M;
   const size_t base = (size_t)iy * M + ix;
+  const C tw0 = tw_fetch<C, N>(tw);
   C v[3][E];
 #pragma unroll
   for (int m = 0; m < 3; ++m)
@@ -919,14 +942,29 @@ kspace_dg3_kernel(const cplx<T> *__restrict__ in, cplx<T> *__restrict__ out, KGe
 #pragma unroll
       for (int r = 0; r < R0; ++r)
         v[m][b * R0 + r] = in[m * hsz + base + reg_pos<N, E, R0>(t, b, r) * plane];
+  C *twl = lds + (size_t)TL * N;
+  tw_store<C, N>(twl, tw0, tw);
 #pragma unroll
-  for (int m = 0; m < 3; ++m) reg_fft_forward<T, N, E>(v[m], t, lds, TL, line, tw);
+  for (int m = 0; m < 3; ++m) reg_fft_forward<T, N, E>(v[m], t, lds, TL, line, twl);
+  // the table entries of the thread's modes are loaded in groups of KG
+  // before their first use (every mode's |k|^2 is inside the table, the
+  // zeroed modes' included) instead of one round trip per mode
+  constexpr int KG = sizeof(T) == 8 ? 2 : (E < 8 ? E : 8);
 #pragma unroll
-  for (int b = 0; b < E / RL; ++b)
+  for (int g0 = 0; g0 < E; g0 += KG) {
+    T ty[KG], tz[KG];
 #pragma unroll
-    for (int r = 0; r < RL; ++r) {
-      const int e = b * RL + r;
-      const int iz = reg_pos<N, E, RL>(t, b, r);
+    for (int i = 0; i < KG; ++i) {
+      const int e = g0 + i;
+      const int kz = kidx(reg_pos<N, E, RL>(t, e / RL, e % RL), N);
+      const auto &tb = ktab[ix * ix + ky * ky + kz * kz];
+      ty[i] = (T)tb.y;
+      tz[i] = (T)tb.z;
+    }
+#pragma unroll
+    for (int i = 0; i < KG; ++i) {
+      const int e = g0 + i;
+      const int iz = reg_pos<N, E, RL>(t, e / RL, e % RL);
       if (zero_mode(ix, iy, iz, N)) {
 #pragma unroll
         for (int m = 0; m < 3; ++m) v[m][e] = C{(T)0, (T)0};
@@ -934,8 +972,7 @@ kspace_dg3_kernel(const cplx<T> *__restrict__ in, cplx<T> *__restrict__ out, KGe
       }
       const int kz = kidx(iz, N);
       const int n2 = ix * ix + ky * ky + kz * kz;
-      const auto tb = ktab[n2];
-      const T s = (T)-9 * (T)tb.y * (T)tb.y * (T)tb.z;
+      const T s = (T)-9 * ty[i] * ty[i] * tz[i];
       const T kv[3] = {(T)ix, (T)ky, (T)kz};
       const T inv = (T)1 / (T)n2;
       T krx = 0, kry = 0;
@@ -950,9 +987,10 @@ kspace_dg3_kernel(const cplx<T> *__restrict__ in, cplx<T> *__restrict__ out, KGe
         v[m][e].y = s * (v[m][e].y - kv[m] * kry * inv);
       }
     }
+  }
 #pragma unroll
   for (int m = 0; m < 3; ++m) {
-    reg_fft_inverse<T, N, E>(v[m], t, lds, TL, line, tw);
+    reg_fft_inverse<T, N, E>(v[m], t, lds, TL, line, twl);
 #pragma unroll
     for (int b = 0; b < E / R0; ++b)
 #pragma unroll
@@ -1146,6 +1184,8 @@ kspace_noise_z_kernel(const double2 *__restrict__ psi, uint64_t seed, uint64_t c
   const int ix = xt * TL + line;
   const size_t hsz = (size_t)M * N * N, plane = (size_t)N * M;
   const size_t base = (size_t)iy * M + ix;
+  C *twl = lds + (size_t)TL * N;
+  tw_store<C, N>(twl, tw_fetch<C, N>(tw), tw);
   C u[3][E];
   T fj[E], ff[E];
 #pragma unroll
@@ -1179,7 +1219,7 @@ kspace_noise_z_kernel(const double2 *__restrict__ psi, uint64_t seed, uint64_t c
       for (int m = 0; m < 3; ++m)
         if (m == c % 3) v[e] = C{f * u[m][e].x, f * u[m][e].y};
     }
-    reg_fft_inverse<T, N, E>(v, t, lds, TL, line, tw);
+    reg_fft_inverse<T, N, E>(v, t, lds, TL, line, twl);
     C *dst = out + (size_t)q * hsz + base;
 #pragma unroll
     for (int b = 0; b < E / R0; ++b)
@@ -1735,8 +1775,10 @@ void launch_fused(Handle &h, const cplx<T> *in, const CompSet &cin, cplx<T> *out
       constexpr int E = sizeof(T) == 4 ? line_e(N) : line_e(N) / 2;
       constexpr int TPL = N / E;
       int tl = (int)(128 / sizeof(cplx<T>));
-      while (tl > 1 && (tl * TPL > 512 || (size_t)tl * N * sizeof(cplx<T>) > 65536)) tl /= 2;
-      const size_t lds = (size_t)tl * N * sizeof(cplx<T>);
+      // exchange area of tl lines and the twiddle table
+      const auto lds_of = [](int l) { return (size_t)(l + 1) * N * sizeof(cplx<T>); };
+      while (tl > 1 && (tl * TPL > 512 || lds_of(tl) > (size_t)h.max_lds)) tl /= 2;
+      const size_t lds = lds_of(tl);
       const unsigned nb = (unsigned)(N * (N / 2 / tl));
       hipLaunchKernelGGL((kspace_dg3_kernel<T, N, E>), dim3(nb), dim3(tl * TPL), lds, h.stream,
                          in, out, kgeom(h), tab, tw, tl);
@@ -1748,7 +1790,10 @@ void launch_fused(Handle &h, const cplx<T> *in, const CompSet &cin, cplx<T> *out
   // at least four z-lines (64-byte row segments) per workgroup on long lines
   const int tl = lines_per_block(N, TPL, N * sizeof(cplx<T>), (size_t)N / 2,
                                  TPL >= 128 ? 512 : 256);
-  const size_t lds = (size_t)tl * N * sizeof(cplx<T>);
+  // exchange area and the twiddle table
+  const size_t lds = (size_t)(tl + 1) * N * sizeof(cplx<T>);
+  if (lds > (size_t)h.max_lds)
+    throw Error{PSE_ERR_HIP, "k-space kernel: LDS beyond the device's per-workgroup limit"};
   const unsigned nb = (unsigned)(N * (N / 2 / tl));
   if (dg)
     hipLaunchKernelGGL((kspace_fused_kernel<T, N, true>), dim3(nb), dim3(tl * TPL), lds,
@@ -1793,7 +1838,9 @@ bool kspace_noise_z(Handle &h, const double *psi, uint64_t seed, uint64_t counte
   const int tl = 512 / TPL;
   const size_t hsz = h.ngrid / 2;
   ProfScope ps(h, PK_NOISE, (double)cout.n * hsz * sizeof(cplx<T>) + (psi ? 3.0 * hsz * 16 : 0.0));
-  const size_t lds = (size_t)tl * N * sizeof(cplx<T>);
+  // exchange area and the twiddle table
+  const size_t lds = (size_t)(tl + 1) * N * sizeof(cplx<T>);
+  if (lds > (size_t)h.max_lds) return false;
   const unsigned nb = (unsigned)(N * (N / 2 / tl));
   hipLaunchKernelGGL((kspace_noise_z_kernel<T, N, E>), dim3(nb), dim3(tl * TPL), lds,
                      h.stream, (const double2 *)psi, seed, counter, out, cout, kgeom(h),
