@@ -1066,7 +1066,9 @@ int pse_brownian_sample(pse_handle *hd, const double *x, const double *psi_real,
                          h.dctl + CTL_STATUS);
       PSE_LAUNCH_CHECK();
     }
-    prepare_positions(h, x, h.xw);
+    // pair sums and interpolation only: no spreading tile lists
+    wrap_positions(h, x, h.xw);
+    build_cells(h, h.xw, false);
     if (out_real) {
       const double *psi = psi_real;
       if (!psi) {
@@ -1116,8 +1118,11 @@ int pse_constrained_step(pse_handle *hd, double *x, const double *FL, double dt,
                          h.dctl + CTL_STATUS);
       PSE_LAUNCH_CHECK();
     }
-    // 1. slip velocities at x_k
-    prepare_positions(h, x, h.xw);
+    // 1. slip velocities at x_k: pair sums and the wave noise's
+    // interpolation only (every spreading of the step runs at the mid-point),
+    // so no spreading tile lists here
+    wrap_positions(h, x, h.xw);
+    build_cells(h, h.xw, false);
     const double *psi = io ? io->psi_real : nullptr;
     if (!psi) {
       real_noise(h, seed, step, h.v2);

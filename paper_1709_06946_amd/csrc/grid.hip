@@ -1626,6 +1626,8 @@ void spread(Handle &h, const double *x, const double *q, Layout lq, const CompSe
             T *grids) {
   const GridGeom g = geom(h);
   if (h.stile) {
+    if (!h.tiles_current)
+      throw Error{PSE_ERR_INVALID, "spreading tile lists not built for these positions"};
     ProfScope ps(h, PK_SPREAD, (double)cs.n * h.ngrid * sizeof(T) + (double)h.n * (3 + cs.n) * 8);
     const int nb = h.sbins.nc;
     const unsigned tiles = (unsigned)nb * nb * nb;
@@ -1696,6 +1698,8 @@ template <typename T>
 void spread_deriv(Handle &h, const double *q, Layout lq, const CompSet &cs, bool hf, bool hasL,
                   bool hasS, T *grids) {
   if (!h.stile) throw Error{PSE_ERR_INVALID, "derivative gridding unavailable"};
+  if (!h.tiles_current)
+    throw Error{PSE_ERR_INVALID, "spreading tile lists not built for these positions"};
   const GridGeom g = geom(h);
   const int ng = hf ? 6 : 3;
   ProfScope ps(h, PK_SPREAD, (double)ng * h.ngrid * sizeof(T) + (double)h.n * (3 + cs.n) * 8);

@@ -169,6 +169,7 @@ struct Handle {
   Bins cells;
   Bins sbins;
   int stile;                 // grid points per spreading tile side (0: atomics)
+  bool tiles_current = false; // tile lists built at the last cell build's positions
   int max_lds = 65536;       // dynamic LDS a workgroup may use on this device
   int num_cu = 256;          // compute units of the device
 
@@ -458,7 +459,10 @@ __device__ __forceinline__ int nbr27_slot(int idx, int first, int pre) {
 // ---- real.hip
 void build_tables(Handle &h);
 void exclusive_scan(Handle &h, const int *in, int *out, int *tmp, int n);
-void build_cells(Handle &h, const double *xw);   // both bin lists
+// Cell list and pair list for wrapped positions xw, the spreading bins and
+// tile lists too unless spreading is false (positions where only pair sums
+// and interpolation run).
+void build_cells(Handle &h, const double *xw, bool spreading = true);
 template <typename T>
 void real_apply(Handle &h, const double *x, const double *in, Layout lin,
                 const CompSet &cin, double *out, Layout lout, const CompSet &cout,

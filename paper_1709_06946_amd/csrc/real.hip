@@ -922,16 +922,18 @@ void pair_storage(Handle &h, size_t cap, bool at_create) {
 }
 
 // Cell list, spreading bins and pair list for wrapped positions xw.
-void build_cells(Handle &h, const double *xw) {
+void build_cells(Handle &h, const double *xw, bool spreading) {
+  const bool tiles = h.stile && spreading;
   const double nc3 = (double)h.cells.nc * h.cells.nc * h.cells.nc
-                     + (h.stile ? (double)h.sbins.nc * h.sbins.nc * h.sbins.nc : 0.0);
-  ProfScope ps(h, PK_CELLS, (double)h.n * (24 + 16) * (h.stile ? 2 : 1) + 12.0 * nc3);
+                     + (tiles ? (double)h.sbins.nc * h.sbins.nc * h.sbins.nc : 0.0);
+  ProfScope ps(h, PK_CELLS, (double)h.n * (24 + 16) * (tiles ? 2 : 1) + 12.0 * nc3);
   build_bins(h, xw, h.cells);
-  if (h.stile) {
+  if (tiles) {
     build_bins(h, xw, h.sbins);
     build_tile_lists(h, xw);
-    build_dg_mu(h, xw);
   }
+  if (h.stile) build_dg_mu(h, xw);
+  h.tiles_current = tiles;
   build_pair_list(h, xw);
 }
 
