@@ -695,6 +695,10 @@ static void create(const pse_params &p, Handle &h) {
   build_tables(h);
   handle_alloc(h, (void **)&h.ktab, (size_t)ktable_len(ng) * 4 * sizeof(double));
   if (h.mixed) handle_alloc(h, (void **)&h.ktab32, (size_t)ktable_len(ng) * 4 * sizeof(float));
+  if (h.deriv) {
+    handle_alloc(h, (void **)&h.kdg, (size_t)ktable_len(ng) * sizeof(double));
+    if (h.mixed) handle_alloc(h, (void **)&h.kdg32, (size_t)ktable_len(ng) * sizeof(float));
+  }
   handle_alloc(h, (void **)&h.bad_pos, 64);
   build_ktable(h);
   if (h.stile) {
@@ -770,7 +774,7 @@ static void release(Handle &h) {
                   h.es_d, h.es_p, h.lz_V, h.gm_V, h.small, h.dots, h.ktab, h.pl_cnt,
                   h.pl_start, h.pl_scan, h.pl_nbr, h.pl_rec64, h.pl_rec32, h.tl_cnt, h.tl_start,
                   h.tl_scan, h.tl_rec, h.bad_pos, h.ktab32, h.dctl, h.dstats, h.dstep,
-                  h.dg_mu, h.mpack};
+                  h.dg_mu, h.mpack, h.kdg, h.kdg32};
   if (!h.arena)
     for (void *p : ptrs) dev_free(p);
   clear_graphs(h);

@@ -917,8 +917,7 @@ kspace_fused_kernel(const cplx<T> *__restrict__ in, CompSet cin, cplx<T> *__rest
 template <typename T, int N, int E>
 __global__ void __launch_bounds__(512)
 kspace_dg3_kernel(const cplx<T> *__restrict__ in, cplx<T> *__restrict__ out, KGeom kg,
-                  const typename TabT<T>::type *__restrict__ ktab,
-                  const cplx<T> *__restrict__ tw, int TL) {
+                  const T *__restrict__ kdg, const cplx<T> *__restrict__ tw, int TL) {
   using C = cplx<T>;
   constexpr int M = N / 2;
   using S = Shape<N, E>;
@@ -946,20 +945,18 @@ kspace_dg3_kernel(const cplx<T> *__restrict__ in, cplx<T> *__restrict__ out, KGe
   tw_store<C, N>(twl, tw0, tw);
 #pragma unroll
   for (int m = 0; m < 3; ++m) reg_fft_forward<T, N, E>(v[m], t, lds, TL, line, twl);
-  // the table entries of the thread's modes are loaded in groups of KG
-  // before their first use (every mode's |k|^2 is inside the table, the
-  // zeroed modes' included) instead of one round trip per mode
+  // the factors of the thread's modes are loaded in groups of KG before
+  // their first use (every mode's |k|^2 is inside the table, the zeroed
+  // modes' included) instead of one round trip per mode
   constexpr int KG = sizeof(T) == 8 ? 2 : (E < 8 ? E : 8);
 #pragma unroll
   for (int g0 = 0; g0 < E; g0 += KG) {
-    T ty[KG], tz[KG];
+    T sk[KG];
 #pragma unroll
     for (int i = 0; i < KG; ++i) {
       const int e = g0 + i;
       const int kz = kidx(reg_pos<N, E, RL>(t, e / RL, e % RL), N);
-      const auto &tb = ktab[ix * ix + ky * ky + kz * kz];
-      ty[i] = (T)tb.y;
-      tz[i] = (T)tb.z;
+      sk[i] = kdg[ix * ix + ky * ky + kz * kz];
     }
 #pragma unroll
     for (int i = 0; i < KG; ++i) {
@@ -972,7 +969,7 @@ kspace_dg3_kernel(const cplx<T> *__restrict__ in, cplx<T> *__restrict__ out, KGe
       }
       const int kz = kidx(iz, N);
       const int n2 = ix * ix + ky * ky + kz * kz;
-      const T s = (T)-9 * ty[i] * ty[i] * tz[i];
+      const T s = sk[i];
       const T kv[3] = {(T)ix, (T)ky, (T)kz};
       const T inv = (T)1 / (T)n2;
       T krx = 0, kry = 0;
@@ -1344,6 +1341,20 @@ ktable_to_float_kernel(const double4 *__restrict__ src, int len, float4 *__restr
   if (i < len) dst[i] = float4{(float)src[i].x, (float)src[i].y, (float)src[i].z, (float)src[i].w};
 }
 
+// The constraint operator's k-space factor of derivative gridding,
+// -9 f1(ka)^2 times the mobility factor, one number per |k|^2 (the fold of
+// kspace_dg3_kernel reads only this; a quarter of the four-factor entry).
+__global__ void __launch_bounds__(256)
+kdg_table_kernel(const double4 *__restrict__ tab, int len, double *__restrict__ d,
+                 float *__restrict__ f) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= len) return;
+  const double4 t = tab[i];
+  const double v = -9.0 * t.y * t.y * t.z;
+  d[i] = v;
+  if (f) f[i] = (float)v;
+}
+
 void build_ktable(Handle &h) {
   const int len = ktable_len(h.d.grid);
   hipLaunchKernelGGL(ktable_kernel, dim3(nblocks(len, 256)), dim3(256), 0, h.stream, kgeom(h),
@@ -1352,6 +1363,11 @@ void build_ktable(Handle &h) {
   if (h.ktab32) {
     hipLaunchKernelGGL(ktable_to_float_kernel, dim3(nblocks(len, 256)), dim3(256), 0, h.stream,
                        (const double4 *)h.ktab, len, (float4 *)h.ktab32);
+    PSE_LAUNCH_CHECK();
+  }
+  if (h.kdg) {
+    hipLaunchKernelGGL(kdg_table_kernel, dim3(nblocks(len, 256)), dim3(256), 0, h.stream,
+                       (const double4 *)h.ktab, len, h.kdg, h.kdg32);
     PSE_LAUNCH_CHECK();
   }
 }
@@ -1784,8 +1800,10 @@ void launch_fused(Handle &h, const cplx<T> *in, const CompSet &cin, cplx<T> *out
       while (tl > 1 && (tl * TPL > 512 || lds_of(tl) > (size_t)h.max_lds)) tl /= 2;
       const size_t lds = lds_of(tl);
       const unsigned nb = (unsigned)(N * (N / 2 / tl));
+      const T *kdg = sizeof(T) == 8 ? (const T *)h.kdg : (const T *)h.kdg32;
+      if (!kdg) throw Error{PSE_ERR_INVALID, "k-space factor of derivative gridding missing"};
       hipLaunchKernelGGL((kspace_dg3_kernel<T, N, E>), dim3(nb), dim3(tl * TPL), lds, h.stream,
-                         in, out, kgeom(h), tab, tw, tl);
+                         in, out, kgeom(h), kdg, tw, tl);
       PSE_LAUNCH_CHECK();
       return;
     }

@@ -218,7 +218,11 @@ size_t footprint(const pse_params &p, const pse_derived &d) {
   bytes += 2 * (size_t)(mixed ? MIXED_FP64_PACK : MAX_PACK) * ng3 * sizeof(double2)
            + d.grid * sizeof(double2);
   if (mixed) bytes += 2 * MAX_PACK * ng3 * sizeof(float2) + d.grid * sizeof(float2);
-  bytes += (size_t)(3 * (d.grid / 2) * (d.grid / 2) + 1) * 4 * sizeof(double);
+  // the per-|k|^2 tables: four radial factors (FP64, and FP32 in mixed
+  // handles), and with derivative gridding the constraint operator's factor
+  const size_t nk = (size_t)(3 * (d.grid / 2) * (d.grid / 2) + 1);
+  bytes += nk * 4 * (sizeof(double) + (mixed ? sizeof(float) : 0));
+  if (d.deriv_gridding == 2) bytes += nk * (sizeof(double) + (mixed ? sizeof(float) : 0));
   bytes += (p.async_calls ? 2 : 1) * pair_capacity(p, d) * pair_entry_bytes(mixed)
            + (2 * n + n / 1024 + 16) * sizeof(int);
   const size_t ntab = (size_t)(2048.0 * d.rcut / (2 * p.radius)) + 16;

@@ -185,6 +185,8 @@ struct Handle {
 
   double *ktab = nullptr;    // per-|k|^2 radial factors (4 doubles per entry)
   float *ktab32 = nullptr;   // the same rounded to float (mixed handles)
+  double *kdg = nullptr;     // derivative gridding: the constraint operator's k-space
+  float *kdg32 = nullptr;    // factor -9 f1^2 mob per |k|^2 (FP64; FP32 in mixed handles)
   int *bad_pos = nullptr;    // set by the wrap kernel on a non-finite coordinate
   double *dg_mu = nullptr;   // derivative gridding: moment corrections, 6 per particle
   void *mpack = nullptr;     // pair sums: moments packed 12 per particle (FP64 size)
