@@ -192,6 +192,11 @@ fft_xy_plane_kernel(T *__restrict__ data, const cplx<T> *__restrict__ tw, int np
   using S = Shape<N, E>;
   extern __shared__ unsigned char smem_raw[];
   C *lds = reinterpret_cast<C *>(smem_raw);
+  // the plane's LDS (the padded x layout or the [y][kx] layout), then the
+  // twiddle table
+  constexpr int LSX = xstride_max<N, E>(), AREA = H * LSX > N * H ? H * LSX : N * H;
+  C *twl = lds + AREA;
+  const C tw0 = tw_fetch<C, N>(tw);
   const int tid = threadIdx.x;
   const int xl = tid / TPL, xt = tid % TPL;          // x steps: pair xl, thread xt
   const int yl = tid % H, yt = tid / H;              // y steps: column yl, thread yt
@@ -215,6 +220,7 @@ fft_xy_plane_kernel(T *__restrict__ data, const cplx<T> *__restrict__ tw, int np
           vn[b * R0 + r] = C{pr[(2 * xl) * N + pos], pr[(2 * xl + 1) * N + pos]};
         }
     }
+    tw_store<C, N>(twl, tw0, tw);
     for (; pl < nplanes; pl += step) {
       // the thread coordinates are made opaque in each iteration so that the
       // transforms' twiddle loads stay inside the loop instead of holding
@@ -233,7 +239,7 @@ fft_xy_plane_kernel(T *__restrict__ data, const cplx<T> *__restrict__ tw, int np
             vn[b * R0 + r] = C{pr[(2 * xl) * N + pos], pr[(2 * xl + 1) * N + pos]};
           }
       }
-      reg_fft_forward<T, N, E, PAD>(v, xt_, lds, 1, xoff, tw);
+      reg_fft_forward<T, N, E, PAD>(v, xt_, lds, 1, xoff, twl);
       __syncthreads();
 #pragma unroll
       for (int b = 0; b < E / RL; ++b)
@@ -262,7 +268,7 @@ fft_xy_plane_kernel(T *__restrict__ data, const cplx<T> *__restrict__ tw, int np
       for (int b = 0; b < E / R0; ++b)
 #pragma unroll
         for (int r = 0; r < R0; ++r) v[b * R0 + r] = lds[reg_pos<N, E, R0>(yt_, b, r) * H + yl];
-      reg_fft_forward<T, N, E>(v, yt_, lds, H, yl, tw);
+      reg_fft_forward<T, N, E>(v, yt_, lds, H, yl, twl);
       C *spec = reinterpret_cast<C *>(data + (size_t)pl * N * N);
 #pragma unroll
       for (int b = 0; b < E / RL; ++b)
@@ -279,7 +285,8 @@ fft_xy_plane_kernel(T *__restrict__ data, const cplx<T> *__restrict__ tw, int np
     for (int b = 0; b < E / R0; ++b)
 #pragma unroll
       for (int r = 0; r < R0; ++r) v[b * R0 + r] = sp[reg_pos<N, E, R0>(yt, b, r) * H + yl];
-    reg_fft_inverse<T, N, E>(v, yt, lds, H, yl, tw);
+    tw_store<C, N>(twl, tw0, tw);
+    reg_fft_inverse<T, N, E>(v, yt, lds, H, yl, twl);
     __syncthreads();
 #pragma unroll
     for (int b = 0; b < E / RL; ++b)
@@ -309,7 +316,7 @@ fft_xy_plane_kernel(T *__restrict__ data, const cplx<T> *__restrict__ tw, int np
 #pragma unroll
       for (int r = 0; r < R0; ++r)
         v[b * R0 + r] = lds[xoff + padpos<PAD>(reg_pos<N, E, R0>(xt, b, r))];
-    reg_fft_inverse<T, N, E, PAD>(v, xt, lds, 1, xoff, tw);
+    reg_fft_inverse<T, N, E, PAD>(v, xt, lds, 1, xoff, twl);
     T *pr = data + (size_t)pl * N * N;
 #pragma unroll
     for (int b = 0; b < E / RL; ++b)
@@ -435,15 +442,16 @@ void launch_lines(Handle &h, cplx<T> *data, const cplx<T> *tw, int ncomp, int M,
   PSE_LAUNCH_CHECK();
 }
 
-// Plane kernel: N/2 * TPL threads and max(H * LS, N * H) complex of LDS
-// (the padded x layout and the [y][kx] layout), when these fit (returns
-// false otherwise).
+// Plane kernel: N/2 * TPL threads and max(H * LS, N * H) + N complex of LDS
+// (the padded x layout and the [y][kx] layout, then the twiddles), when these
+// fit (returns false otherwise).
 template <typename T, int N>
 bool launch_xy_plane(Handle &h, T *grids, const cplx<T> *tw, int ncomp, int dir) {
   constexpr int TPL = N / plane_e(N), H = N / 2;
   constexpr int threads = H * TPL;
   constexpr int LS = xstride_max<N, plane_e(N)>();
-  const size_t lds = (size_t)(H * LS > N * H ? H * LS : N * H) * sizeof(cplx<T>);
+  // the plane's layouts and the twiddle table
+  const size_t lds = (size_t)((H * LS > N * H ? H * LS : N * H) + N) * sizeof(cplx<T>);
   if (threads > 512 || threads < 64 || lds > (size_t)h.max_lds) return false;
   static std::once_flag once[2];
   hipError_t attr = hipSuccess;

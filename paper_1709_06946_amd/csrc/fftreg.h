@@ -313,6 +313,25 @@ __device__ __forceinline__ void reg_fft_inverse(cplx<T> (&v)[E], int t, cplx<T> 
   reg_run<T, N, E, true, 0, 1, PADP>(v, t, lds, ps, off, tw, +1);
 }
 
+// The twiddle table in LDS behind a kernel's exchange area: the transforms
+// then read their twiddles with LDS loads.  Read from global memory inside a
+// transform, each twiddle's first use waits on the in-order vector-memory
+// counter, that is for every grid load and store issued before it, so no
+// transform overlaps the grid traffic in flight.  A thread takes its entry
+// before the grid loads (tw_fetch) and stores it after issuing them
+// (tw_store); a transform's first pass uses no twiddles, so the first
+// exchange's barrier orders these stores before any read.
+template <typename C, int N>
+__device__ __forceinline__ C tw_fetch(const C *__restrict__ tw) {
+  return threadIdx.x < N ? tw[threadIdx.x] : C{};
+}
+
+template <typename C, int N>
+__device__ __forceinline__ void tw_store(C *twl, C first, const C *__restrict__ tw) {
+  if (threadIdx.x < N) twl[threadIdx.x] = first;
+  for (int i = (int)(threadIdx.x + blockDim.x); i < N; i += blockDim.x) twl[i] = tw[i];
+}
+
 // Element counts per thread: line passes and the fused k-space kernel (which
 // also keeps three complex numbers per element in registers, so it takes few
 // elements: 4 for powers of two, 6 (radices 6, 3, 2) for 3 * 2^k lengths).

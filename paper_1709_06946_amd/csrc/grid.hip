@@ -724,25 +724,6 @@ __device__ __forceinline__ bool zero_mode(int ix, int iy, int iz, int n) {
 // Gaussian's gradient (factor -3 f1(ka)) on input, so rho = j0 F^ - 3 f1 D^;
 // on output 0-2 the velocity grids j0(ka) u^ and 3-5 the grids
 // v^ = 3 f1(ka) u^ whose gradient the interpolation takes.
-// The twiddle table in LDS behind a kernel's exchange area (TL lines of N
-// elements): the transforms then read their twiddles with LDS loads.  Read
-// from global memory inside a transform, each twiddle's first use waits on
-// the in-order vector-memory counter, that is for every grid load and store
-// issued before it, so no transform overlaps the grid traffic in flight.  A
-// thread takes its entry before the grid loads (tw_fetch) and stores it
-// after issuing them (tw_store); a transform's first pass uses no twiddles,
-// so the first exchange's barrier orders these stores before any read.
-template <typename C, int N>
-__device__ __forceinline__ C tw_fetch(const C *__restrict__ tw) {
-  return threadIdx.x < N ? tw[threadIdx.x] : C{};
-}
-
-template <typename C, int N>
-__device__ __forceinline__ void tw_store(C *twl, C first, const C *__restrict__ tw) {
-  if (threadIdx.x < N) twl[threadIdx.x] = first;
-  for (int i = (int)(threadIdx.x + blockDim.x); i < N; i += blockDim.x) twl[i] = tw[i];
-}
-
 template <typename T, int N, bool DG>
 __global__ void __launch_bounds__(512)
 kspace_fused_kernel(const cplx<T> *__restrict__ in, CompSet cin, cplx<T> *__restrict__ out,
