@@ -773,15 +773,12 @@ kspace_fused_kernel(const cplx<T> *__restrict__ in, CompSet cin, cplx<T> *__rest
       tsc[e] = (T)tb.z;
     }
   }
-  const auto j0_at = [&](int e) -> T {
-    if constexpr (HOIST) return tj0[e]; else return (T)entry(e).x;
-  };
-  const auto f1_at = [&](int e) -> T {
-    if constexpr (HOIST) return tf1[e]; else return (T)entry(e).y;
-  };
-  const auto sc_at = [&](int e) -> T {
-    if constexpr (HOIST) return tsc[e]; else return (T)entry(e).z;
-  };
+  // Without hoisting, FP32 kernels up to 384 points (BATCH) load the factors
+  // where nothing else is in flight that their use would wait for (the
+  // vector-memory counter is in order): in each input step before the next
+  // component's prefetch, and for the fold and the output steps once, before
+  // the first store; the others (registers) read them at each use.
+  constexpr bool BATCH = !HOIST && sizeof(T) == 4 && N <= 384;
   // the next component's z-line is loaded while the current one is
   // transformed (the barriers of the exchanges wait on LDS traffic only)
   const C tw0 = tw_fetch<C, N>(tw);
@@ -795,6 +792,25 @@ kspace_fused_kernel(const cplx<T> *__restrict__ in, CompSet cin, cplx<T> *__rest
   for (int p = 0; p < cin.n; ++p) {
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e] = vn[e];
+    T pj0[BATCH ? E : 1], pf1[BATCH ? E : 1];
+    if constexpr (BATCH) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const auto tb = entry(e);
+        pj0[e] = (T)tb.x;
+        pf1[e] = (T)tb.y;
+      }
+    }
+    const auto j0_at = [&](int e) -> T {
+      if constexpr (HOIST) return tj0[e];
+      else if constexpr (BATCH) return pj0[e];
+      else return (T)entry(e).x;
+    };
+    const auto f1_at = [&](int e) -> T {
+      if constexpr (HOIST) return tf1[e];
+      else if constexpr (BATCH) return pf1[e];
+      else return (T)entry(e).y;
+    };
     if (p + 1 < cin.n) {
       const C *src = in + (size_t)(p + 1) * hsz + base;
 #pragma unroll
@@ -825,6 +841,31 @@ kspace_fused_kernel(const cplx<T> *__restrict__ in, CompSet cin, cplx<T> *__rest
         }
       }
   }
+  T oj0[BATCH ? E : 1], of1[BATCH ? E : 1], osc[BATCH ? E : 1];
+  if constexpr (BATCH) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const auto tb = entry(e);
+      oj0[e] = (T)tb.x;
+      of1[e] = (T)tb.y;
+      osc[e] = (T)tb.z;
+    }
+  }
+  const auto j0_at = [&](int e) -> T {
+    if constexpr (HOIST) return tj0[e];
+    else if constexpr (BATCH) return oj0[e];
+    else return (T)entry(e).x;
+  };
+  const auto f1_at = [&](int e) -> T {
+    if constexpr (HOIST) return tf1[e];
+    else if constexpr (BATCH) return of1[e];
+    else return (T)entry(e).y;
+  };
+  const auto sc_at = [&](int e) -> T {
+    if constexpr (HOIST) return tsc[e];
+    else if constexpr (BATCH) return osc[e];
+    else return (T)entry(e).z;
+  };
   // u = scale (I - k^k^) rho
 #pragma unroll
   for (int b = 0; b < E / RL; ++b)
