@@ -474,7 +474,10 @@ def main():
         g32 = run_graph(w2, pse.PSE_MIXED, args.steps, args.warmup, w2['seed'])
         g32['speedup_vs_eager'] = round(g32['value'] / r32['value'], 3)
         sec['graph'] = dict(fp64=g64, mixed=g32)
-        _, sec['fp64']['roofline'] = roofline(r64['prof'], None, w2['grid'], r64['bracket_us'])
+        traffic2 = os.path.join(ROOT, 'profiles',
+                                f'hbm_traffic_{args.secondary}_{FORM_NAME[0]}.md')
+        _, sec['fp64']['roofline'] = roofline(r64['prof'], traffic2, w2['grid'],
+                                              r64['bracket_us'])
         out['secondary'] = sec
     if not args.no_rpy:
         r = run_rpy(w, prec, args.steps, args.warmup, seed)
