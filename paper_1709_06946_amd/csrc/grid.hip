@@ -150,37 +150,52 @@ tile_list_kernel(const double *__restrict__ x, GridGeom g, int S, int nb,
   }
 }
 
-// Second half of the tile-list fill, one thread per (record, axis): the S
-// one-dimensional weights of the record's particle at the tile's grid
-// positions along the axis (zero outside its stencil) and the offset d0 of
-// the first stencil point inside the tile from that position.
-__global__ void __launch_bounds__(256)
+// Second half of the tile-list fill: for every record, the S
+// one-dimensional weights of its particle at the tile's grid positions along
+// each axis (zero outside its stencil) and the offset d0 of the first
+// stencil point inside the tile from that position.  A workgroup takes
+// TW_RECS records, one thread per (record, axis), forms their 3 S + 3
+// numbers in LDS and writes them back as one contiguous block, so the stores
+// are coalesced (written in place, each record's numbers stride 3 S + 3
+// apart across the threads).
+constexpr int TW_RECS = 64;
+
+__global__ void __launch_bounds__(3 * TW_RECS)
 tile_weights_kernel(const double *__restrict__ x, GridGeom g, int S,
                     const int *__restrict__ total, int64_t cap, TileRecs rec) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  extern __shared__ double tw_block[];   // TW_RECS records of 3 S + 3
+  const int RW = 3 * S + 3;
   const int64_t len = min((int64_t)total[0], cap);
-  if (t >= 3 * len) return;
-  const int64_t e = t / 3;
-  const int d = (int)(t % 3);
-  const int P = g.P, ng = g.ng;
-  const int p = rec.p[e];
-  double *w = rec.w + (size_t)e * (3 * S + 3);
-  const int t0 = (int)w[3 * S + d];
-  const double xd = x[3 * p + d];
-  const int st = stencil_start(xd, g.h, P);
-  double d0 = 0.0;
-  for (int i = 0; i < S; ++i) {
-    int a = (t0 + i - st) % ng;
-    a += a < 0 ? ng : 0;
-    double wi = 0.0;
-    if (a < P) {
-      const double dx = (st + a) * g.h - xd;
-      wi = g.knorm * exp(-g.kcoef * dx * dx);
-      d0 = dx - i * g.h;
+  const int64_t e0 = (int64_t)blockIdx.x * TW_RECS;
+  if (e0 >= len) return;
+  const int nrec = (int)min((int64_t)TW_RECS, len - e0);
+  const int tid = threadIdx.x;
+  const int j = tid / 3, d = tid % 3;
+  if (j < nrec) {
+    const int64_t e = e0 + j;
+    const int P = g.P, ng = g.ng;
+    const int p = rec.p[e];
+    // the tile's first grid index along the axis, left by the list fill
+    const int t0 = (int)rec.w[(size_t)e * RW + 3 * S + d];
+    const double xd = x[3 * p + d];
+    const int st = stencil_start(xd, g.h, P);
+    double d0 = 0.0;
+    for (int i = 0; i < S; ++i) {
+      int a = (t0 + i - st) % ng;
+      a += a < 0 ? ng : 0;
+      double wi = 0.0;
+      if (a < P) {
+        const double dx = (st + a) * g.h - xd;
+        wi = g.knorm * exp(-g.kcoef * dx * dx);
+        d0 = dx - i * g.h;
+      }
+      tw_block[j * RW + d * S + i] = wi;
     }
-    w[d * S + i] = wi;
+    tw_block[j * RW + 3 * S + d] = d0;
   }
-  w[3 * S + d] = d0;
+  __syncthreads();
+  double *dst = rec.w + (size_t)e0 * RW;
+  for (int k = tid; k < nrec * RW; k += blockDim.x) dst[k] = tw_block[k];
 }
 
 // Gather form of the spreading sum: one workgroup per tile of S^3 grid
@@ -1425,9 +1440,10 @@ void build_tile_lists(Handle &h, const double *xw) {
                      (const int *)h.tl_start, tile_recs(h));
   PSE_LAUNCH_CHECK();
   // grid over the capacity; the kernel reads the list's length on the device
-  hipLaunchKernelGGL(tile_weights_kernel, dim3(nblocks(3 * h.tl_cap, 256)), dim3(256), 0,
-                     h.stream, xw, g, h.stile, (const int *)h.tl_start + ntile,
-                     (int64_t)h.tl_cap, tile_recs(h));
+  hipLaunchKernelGGL(tile_weights_kernel, dim3(nblocks(h.tl_cap, TW_RECS)), dim3(3 * TW_RECS),
+                     (size_t)TW_RECS * (3 * h.stile + 3) * sizeof(double), h.stream, xw, g,
+                     h.stile, (const int *)h.tl_start + ntile, (int64_t)h.tl_cap,
+                     tile_recs(h));
   PSE_LAUNCH_CHECK();
 }
 
