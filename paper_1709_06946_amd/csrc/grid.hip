@@ -131,14 +131,12 @@ tile_list_kernel(const double *__restrict__ x, GridGeom g, int S, int nb,
     } else {
       const unsigned long long m = __ballot(ok);
       if (ok) {
-        // the record's particle and, in its offset slots, the tile's first
-        // grid index along each axis; tile_weights_kernel forms the weights
-        // (on every lane, not on the lanes of a candidate batch that met the
-        // tile)
+        // the record's particle and, in its first offset slot, the tile's
+        // index; tile_weights_kernel forms the weights and offsets (on every
+        // lane, not on the lanes of a candidate batch that met the tile)
         const int e = pos + __popcll(m & ((1ull << lane) - 1ull));
         rec.p[e] = p;
-        double *w = rec.w + (size_t)e * (3 * S + 3);
-        for (int d = 0; d < 3; ++d) w[3 * S + d] = (double)(tc[d] * S);
+        rec.w[(size_t)e * (3 * S + 3) + 3 * S] = (double)tile;
       }
       pos += __popcll(m);
     }
@@ -161,7 +159,7 @@ tile_list_kernel(const double *__restrict__ x, GridGeom g, int S, int nb,
 constexpr int TW_RECS = 64;
 
 __global__ void __launch_bounds__(3 * TW_RECS)
-tile_weights_kernel(const double *__restrict__ x, GridGeom g, int S,
+tile_weights_kernel(const double *__restrict__ x, GridGeom g, int S, int nb,
                     const int *__restrict__ total, int64_t cap, TileRecs rec) {
   extern __shared__ double tw_block[];   // TW_RECS records of 3 S + 3
   const int RW = 3 * S + 3;
@@ -175,8 +173,10 @@ tile_weights_kernel(const double *__restrict__ x, GridGeom g, int S,
     const int64_t e = e0 + j;
     const int P = g.P, ng = g.ng;
     const int p = rec.p[e];
-    // the tile's first grid index along the axis, left by the list fill
-    const int t0 = (int)rec.w[(size_t)e * RW + 3 * S + d];
+    // the tile's first grid index along the axis, from the tile index the
+    // list fill left in the record
+    const int tile = (int)rec.w[(size_t)e * RW + 3 * S];
+    const int t0 = (d == 0 ? tile % nb : (d == 1 ? (tile / nb) % nb : tile / (nb * nb))) * S;
     const double xd = x[3 * p + d];
     const int st = stencil_start(xd, g.h, P);
     double d0 = 0.0;
@@ -1442,7 +1442,7 @@ void build_tile_lists(Handle &h, const double *xw) {
   // grid over the capacity; the kernel reads the list's length on the device
   hipLaunchKernelGGL(tile_weights_kernel, dim3(nblocks(h.tl_cap, TW_RECS)), dim3(3 * TW_RECS),
                      (size_t)TW_RECS * (3 * h.stile + 3) * sizeof(double), h.stream, xw, g,
-                     h.stile, (const int *)h.tl_start + ntile, (int64_t)h.tl_cap,
+                     h.stile, nb, (const int *)h.tl_start + ntile, (int64_t)h.tl_cap,
                      tile_recs(h));
   PSE_LAUNCH_CHECK();
 }
