@@ -420,14 +420,15 @@ __device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nb) {
 
 // Lanes 0..26 of a wavefront take the 27 bins around (cx, cy, cz) of a
 // periodic nc^3 lattice (bin offsets in x fastest) and load their first slot
-// and length; an inclusive scan over the wavefront gives each bin's offset
-// `pre` in the concatenated candidate sequence of length `total`.
+// and length (none for a lane whose skip is set); an inclusive scan over the
+// wavefront gives each bin's offset `pre` in the concatenated candidate
+// sequence of length `total`.
 __device__ __forceinline__ void nbr27_setup(int lane, int cx, int cy, int cz, int nc,
                                             const int *__restrict__ start, int &first,
-                                            int &pre, int &total) {
+                                            int &pre, int &total, bool skip = false) {
   int len = 0;
   first = 0;
-  if (lane < 27) {
+  if (lane < 27 && !skip) {
     const int bx = (cx + lane % 3 - 1 + nc) % nc;
     const int by = (cy + (lane / 3) % 3 - 1 + nc) % nc;
     const int bz = (cz + lane / 9 - 1 + nc) % nc;

@@ -596,6 +596,7 @@ struct PairArgs {
   int64_t n;
   int nc;
   double L, rcut2;
+  double inv_cs, cs2;   // cells per unit length, squared cell side
   double inv_dr;
   int n2a, ntab;
   int64_t cap;     // pair-list capacity: entries at or beyond it are not written
@@ -648,8 +649,25 @@ pair_list_kernel(const double *__restrict__ xw, const int *__restrict__ perm,
   const double xi0 = xw[3 * i], xi1 = xw[3 * i + 1], xi2 = xw[3 * i + 2];
   const int nc = pa.nc;
   const int ci = cell_of[i];
+  const int cc[3] = {ci % nc, (ci / nc) % nc, ci / (nc * nc)};
+  // a neighbouring cell whose gap to the particle exceeds the cutoff holds no
+  // neighbour: it is skipped (the list is the same; on a deformed lattice,
+  // where cell units are not lengths, every cell is searched)
+  bool skip = false;
+  if (!pa.def && lane < 27) {
+    const int off[3] = {lane % 3 - 1, (lane / 3) % 3 - 1, lane / 9 - 1};
+    const double xi[3] = {xi0, xi1, xi2};
+    double g2 = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const double u = xi[d] * pa.inv_cs - cc[d];   // position in the cell, cell units
+      const double gap = off[d] > 0 ? 1.0 - u : (off[d] < 0 ? u : 0.0);
+      if (gap > 0.0) g2 += gap * gap;
+    }
+    skip = g2 * pa.cs2 > pa.rcut2 * (1.0 + 1e-9);
+  }
   int first, pre, total;
-  nbr27_setup(lane, ci % nc, (ci / nc) % nc, ci / (nc * nc), nc, cell_start, first, pre, total);
+  nbr27_setup(lane, cc[0], cc[1], cc[2], nc, cell_start, first, pre, total, skip);
   int pos = FILL ? start[t] : 0;
   int count = 0;
   for (int base = 0; base < total; base += 64) {
@@ -851,6 +869,9 @@ static void build_pair_list(Handle &h, const double *xw) {
   pa.nc = h.cells.nc;
   pa.L = h.p.box;
   pa.rcut2 = h.d.rcut * h.d.rcut;
+  // the cell assignment's own scale (cell = floor(x nc / L))
+  pa.inv_cs = pa.nc / h.p.box;
+  pa.cs2 = (h.p.box / pa.nc) * (h.p.box / pa.nc);
   pa.inv_dr = 1.0 / h.dr;
   pa.n2a = h.n2a;
   pa.ntab = h.ntab;
