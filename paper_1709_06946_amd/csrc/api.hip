@@ -256,20 +256,30 @@ static DGPlan dg_plan(const Handle &h, const CompSet &cin, const CompSet &cout) 
 template <typename T>
 static void wave_apply_dg(Handle &h, const DGPlan &d, const double *xw, const double *in,
                           Layout lin, const CompSet &cin, double *out, Layout lout,
-                          const CompSet &cout, bool accumulate) {
+                          const CompSet &cout, bool accumulate, bool reuse_forces) {
   GridSet<T> &G = grids<T>(h);
   T *gin = reinterpret_cast<T *>(G.gin), *gout = reinterpret_cast<T *>(G.gout);
-  if (d.hf) spread<T>(h, xw, in, lin, comps_range(0, 3), gin);   // forces: moment grids
-  if (d.hL || d.hS) {
+  // the forces' three moment grids live in slots 0-2 and the couplets' in
+  // slots 3-5, also without forces, so a product without forces leaves the
+  // slots 0-2 of an earlier one as they were: with reuse_forces the forces'
+  // x-y transformed grids there (same positions, same forces, same
+  // precision, nothing since writing those slots) serve again
+  T *gc = gin + 3 * h.ngrid;
+  const bool hc = d.hL || d.hS;
+  if (d.hf && !reuse_forces)
+    spread<T>(h, xw, in, lin, comps_range(0, 3), gin);   // forces: moment grids
+  if (hc) {
     // couplets onto the next three grids (measured faster than spreading
     // forces and couplets in one launch: 1.4 + 1.4 against 3.9 ms at 512^3)
     CompSet cc{};
     for (int k = 0; k < cin.n; ++k)
       if (cin.idx[k] >= 3) cc.idx[cc.n++] = cin.idx[k];
-    spread_deriv<T>(h, in, lin, cc, false, d.hL, d.hS, gin + (d.hf ? 3 * h.ngrid : 0));
+    spread_deriv<T>(h, in, lin, cc, false, d.hL, d.hS, gc);
   }
-  rfft_xy<T>(h, gin, G.twiddle, d.gin.n, -1);
-  kspace_fused<T>(h, G.gin, d.gin, G.gout, d.gout, G.twiddle, true);
+  if (d.hf && !reuse_forces) rfft_xy<T>(h, gin, G.twiddle, d.gin.n, -1);
+  else if (hc) rfft_xy<T>(h, gc, G.twiddle, 3, -1);
+  const cplx<T> *gk = d.hf ? G.gin : G.gin + 3 * (h.ngrid / 2);
+  kspace_fused<T>(h, gk, d.gin, G.gout, d.gout, G.twiddle, true);
   rfft_xy<T>(h, gout, G.twiddle, d.gout.n, +1);
   if (d.hv) interp_deriv<T>(h, xw, gout, d.hu, cout, out, lout, accumulate, 1.0);
   else interpolate<T>(h, xw, gout, cout, out, lout, accumulate, 1.0);
@@ -280,7 +290,7 @@ static void wave_apply_dg(Handle &h, const DGPlan &d, const double *xw, const do
 // forces the FP64 kernels in a mixed handle.
 static void mobility(Handle &h, const double *xw, bool want_real, bool want_wave,
                      const double *in, Layout lin, const CompSet &cin, double *out,
-                     Layout lout, const CompSet &cout, bool fp64) {
+                     Layout lout, const CompSet &cout, bool fp64, bool reuse_forces = false) {
   const bool f32 = h.mixed && !fp64;
   bool acc = false;
   if (want_real) {
@@ -291,8 +301,8 @@ static void mobility(Handle &h, const double *xw, bool want_real, bool want_wave
   if (want_wave) {
     const DGPlan d = dg_plan(h, cin, cout);
     if (d.ok) {
-      if (f32) wave_apply_dg<float>(h, d, xw, in, lin, cin, out, lout, cout, acc);
-      else wave_apply_dg<double>(h, d, xw, in, lin, cin, out, lout, cout, acc);
+      if (f32) wave_apply_dg<float>(h, d, xw, in, lin, cin, out, lout, cout, acc, reuse_forces);
+      else wave_apply_dg<double>(h, d, xw, in, lin, cin, out, lout, cout, acc, reuse_forces);
     } else {
       if (f32) wave_apply<float>(h, xw, in, lin, cin, out, lout, cout, acc);
       else wave_apply<double>(h, xw, in, lin, cin, out, lout, cout, acc);
@@ -1167,8 +1177,12 @@ int pse_constrained_step(pse_handle *hd, double *x, const double *FL, double dt,
                        (const double *)h.es_x, n, h.v4);
     PSE_LAUNCH_CHECK();
     const CompSet u3 = comps_range(0, 3);
+    // the right-hand side's product left the forces' transformed grids in the
+    // first input slots (same positions, same forces; the constraint solve in
+    // between spreads couplets only), so the final product spreads and
+    // transforms the couplets alone
     mobility(h, h.xh, true, true, h.v4, FULL_LAYOUT, FL ? comps_range(0, 11) : es, h.v5,
-             FULL_LAYOUT, u3, false);
+             FULL_LAYOUT, u3, false, FL != nullptr);
     double *U = h.v2;   // N x 3
     hipLaunchKernelGGL(velocity_kernel, dim3(nblocks(n, 256)), dim3(256), 0, h.stream, slip,
                        h.v5, n, U);
