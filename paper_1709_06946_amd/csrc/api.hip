@@ -194,7 +194,7 @@ __global__ void f2d_kernel(const float2 *src, double2 *dst, size_t n) {
 template <typename T>
 static void wave_apply(Handle &h, const double *xw, const double *in, Layout lin,
                        const CompSet &cin, double *out, Layout lout, const CompSet &cout,
-                       bool accumulate) {
+                       bool accumulate, bool reuse_ft) {
   GridSet<T> &G = grids<T>(h);
   T *gin = reinterpret_cast<T *>(G.gin), *gout = reinterpret_cast<T *>(G.gout);
   if (h.def.on) {
@@ -207,9 +207,26 @@ static void wave_apply(Handle &h, const double *xw, const double *in, Layout lin
     interpolate<T>(h, xw, gout, cout, out, lout, accumulate, 1.0);
     return;
   }
-  spread<T>(h, xw, in, lin, cin, gin);
-  rfft_xy<T>(h, gin, G.twiddle, cin.n, -1);
-  kspace_fused<T>(h, G.gin, cin, G.gout, cout, G.twiddle);
+  // Where the set holds a grid per component, a contiguous run of input
+  // components takes the slots of their codes (forces and torques 0-5,
+  // stresslets 6-10), so a product without forces and torques leaves their
+  // slots as they were; with reuse_ft (same positions, same forces and
+  // torques, nothing written to those slots since) the x-y transformed
+  // grids of an earlier product there serve again, and only the stresslets
+  // are spread and transformed.
+  const int slots = (sizeof(T) == 8 && h.mixed) ? 2 * MIXED_FP64_PACK : 2 * MAX_PACK;
+  bool run = cin.n > 0;
+  for (int k = 1; k < cin.n; ++k) run = run && cin.idx[k] == cin.idx[0] + k;
+  const int s0 = (slots >= NC && run) ? cin.idx[0] : 0;
+  if (reuse_ft && s0 == 0 && slots >= NC && run && cin.n == NC) {
+    const CompSet st = comps_range(6, NC);
+    spread<T>(h, xw, in, lin, st, gin + 6 * h.ngrid);
+    rfft_xy<T>(h, gin + 6 * h.ngrid, G.twiddle, st.n, -1);
+  } else {
+    spread<T>(h, xw, in, lin, cin, gin + (size_t)s0 * h.ngrid);
+    rfft_xy<T>(h, gin + (size_t)s0 * h.ngrid, G.twiddle, cin.n, -1);
+  }
+  kspace_fused<T>(h, G.gin + (size_t)s0 * (h.ngrid / 2), cin, G.gout, cout, G.twiddle);
   rfft_xy<T>(h, gout, G.twiddle, cout.n, +1);
   interpolate<T>(h, xw, gout, cout, out, lout, accumulate, 1.0);
 }
@@ -304,8 +321,8 @@ static void mobility(Handle &h, const double *xw, bool want_real, bool want_wave
       if (f32) wave_apply_dg<float>(h, d, xw, in, lin, cin, out, lout, cout, acc, reuse_forces);
       else wave_apply_dg<double>(h, d, xw, in, lin, cin, out, lout, cout, acc, reuse_forces);
     } else {
-      if (f32) wave_apply<float>(h, xw, in, lin, cin, out, lout, cout, acc);
-      else wave_apply<double>(h, xw, in, lin, cin, out, lout, cout, acc);
+      if (f32) wave_apply<float>(h, xw, in, lin, cin, out, lout, cout, acc, reuse_forces);
+      else wave_apply<double>(h, xw, in, lin, cin, out, lout, cout, acc, reuse_forces);
     }
   }
 }
@@ -1177,10 +1194,10 @@ int pse_constrained_step(pse_handle *hd, double *x, const double *FL, double dt,
                        (const double *)h.es_x, n, h.v4);
     PSE_LAUNCH_CHECK();
     const CompSet u3 = comps_range(0, 3);
-    // the right-hand side's product left the forces' transformed grids in the
-    // first input slots (same positions, same forces; the constraint solve in
-    // between spreads couplets only), so the final product spreads and
-    // transforms the couplets alone
+    // the right-hand side's product left the forces' (with moment gridding
+    // also the torques') transformed grids in the first input slots (same
+    // positions, same forces and torques; the constraint solve in between
+    // uses other slots), so the final product spreads and transforms the rest
     mobility(h, h.xh, true, true, h.v4, FULL_LAYOUT, FL ? comps_range(0, 11) : es, h.v5,
              FULL_LAYOUT, u3, false, FL != nullptr);
     double *U = h.v2;   // N x 3
