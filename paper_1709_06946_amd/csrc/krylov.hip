@@ -103,6 +103,54 @@ sub_dot_partial(double *w, const double *V, size_t ldv, int m, const double *__r
     partial[(size_t)j * nb + blockIdx.x] = (s[0][j] + s[1][j]) + (s[2][j] + s[3][j]);
 }
 
+// The same in one pass over the elements when m + 1 <= SDF: a thread loads
+// V_0..V_{m-1} at each of its elements once, subtracts, stores w and adds
+// the products into the m + 1 sums from the loaded values, so each vector
+// is read once instead of twice.  The per-thread order of every sum and the
+// reduction are those of sub_dot_partial, so the results agree bit for bit.
+constexpr int SDF = 8;
+
+__global__ void __launch_bounds__(256)
+sub_dot_partial1(double *w, const double *V, size_t ldv, int m, const double *__restrict__ coef,
+                 size_t n, double *__restrict__ partial) {
+  __shared__ double s[4][SDF];
+  const int nb = gridDim.x, lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const size_t i0 = (size_t)blockIdx.x * 256 + threadIdx.x, step = (size_t)nb * 256;
+  double cf[SDF - 1], acc[SDF];
+#pragma unroll
+  for (int j = 0; j < SDF - 1; ++j) cf[j] = j < m ? coef[j] : 0.0;
+#pragma unroll
+  for (int j = 0; j < SDF; ++j) acc[j] = 0.0;
+  for (size_t i = i0; i < n; i += step) {
+    double v[SDF - 1];
+#pragma unroll
+    for (int j = 0; j < SDF - 1; ++j) v[j] = j < m ? V[(size_t)j * ldv + i] : 0.0;
+    double a = 0.0;
+#pragma unroll
+    for (int j = 0; j < SDF - 1; ++j)
+      if (j < m) a += cf[j] * v[j];
+    const double wn = w[i] - a;
+    w[i] = wn;
+#pragma unroll
+    for (int j = 0; j < SDF - 1; ++j)
+      if (j < m) acc[j] += v[j] * wn;
+#pragma unroll
+    for (int j = 0; j < SDF; ++j)
+      if (j == m) acc[j] += wn * wn;
+  }
+#pragma unroll
+  for (int j = 0; j < SDF; ++j) {
+    if (j > m) break;
+    double a = acc[j];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
+    if (lane == 0) s[wv][j] = a;
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j <= m; j += 256)
+    partial[(size_t)j * nb + blockIdx.x] = (s[0][j] + s[1][j]) + (s[2][j] + s[3][j]);
+}
+
 // w -= sum_j coef_j V_j
 __global__ void sub_multi_kernel(double *__restrict__ w, const double *__restrict__ V,
                                  size_t ldv, int m, const double *__restrict__ coef,
@@ -537,9 +585,15 @@ static void cgs2_pass(Handle &h, const double *V, size_t n, int m, double *w, do
   int nb = (int)std::min<size_t>(RED_BLOCKS, (n + 255) / 256);
   if (nb < 1) nb = 1;
   if ((size_t)nb * (m + 1) > h.dots_len) throw Error{PSE_ERR_INVALID, "reduction scratch too small"};
-  ProfScope ps(h, PK_KRYLOV, (double)(2 * m + 3) * n * 8);
-  hipLaunchKernelGGL(sub_dot_partial, dim3(nb), dim3(256), 0, h.stream, w, V, n, m, h1, n,
-                     h.dots);
+  // one pass reads V_0..V_{m-1} and w and writes w; the two-loop form reads
+  // them twice
+  ProfScope ps(h, PK_KRYLOV, (double)(m + 1 <= SDF ? m + 2 : 2 * m + 3) * n * 8);
+  if (m + 1 <= SDF)
+    hipLaunchKernelGGL(sub_dot_partial1, dim3(nb), dim3(256), 0, h.stream, w, V, n, m, h1, n,
+                       h.dots);
+  else
+    hipLaunchKernelGGL(sub_dot_partial, dim3(nb), dim3(256), 0, h.stream, w, V, n, m, h1, n,
+                       h.dots);
   PSE_LAUNCH_CHECK();
   hipLaunchKernelGGL(reduce_partial, dim3(m + 1), dim3(256), 0, h.stream, h.dots, nb, h2);
   PSE_LAUNCH_CHECK();
